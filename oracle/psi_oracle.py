@@ -1,0 +1,248 @@
+"""Plain FP64 CPU oracle for the ψ-score (Arhachoui et al., ASONAM 2022).
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import, call or
+link this module: only the test-suite, the package's smoke check and the
+benchmark's CPU-baseline leg use it.  It shares no code with the HIP library.
+
+Notation (Sec. II): (i, j) ∈ E means user i follows user j; L(j) is the set of
+leaders of j; λ_n, μ_n are the posting and re-posting rates of user n.
+
+Functions and the passages they follow:
+
+* ``clean_edges``       — the graph is unweighted with no self-loops (Sec. II):
+                          self-loops and repeated edges are dropped.
+* ``operator``          — the matrices A, B and vectors c, d of the matrix form
+                          (Sec. II, the definitions under eqs. (newsfeed)/(wall);
+                          c and d are the diagonals of C and D, Sec. III-A).
+* ``psi_by_definition`` — ψ_i = (1/N) Σ_n q_i^(n) (eq. psiscore) with p_i from
+                          the newsfeed balance equations (4)–(5) and q_i from the
+                          wall balance equations (2)–(3): N separate N-size
+                          linear solves (LAPACK via numpy), one per origin.
+* ``power_nf``          — Algorithm 1 (Power-NF) for one origin.
+* ``psi_closed_form``   — eq. (ultimsol) with the series summed exactly: one
+                          solve of (I − Aᵀ) s = c, then ψ = (Bᵀ s + d) / N.
+* ``power_psi``         — Algorithm 2 (Power-ψ), FP64, in the paper's order.
+* ``pagerank_power``    — the PageRank power method, eq. (pagerank_power).
+* ``fixed_point_residual``, ``b_norm``, ``kappa`` — the L1 fixed-point residual
+                          of eq. (power_psi) and the norms used by the bound of
+                          eq. (psi_diff).
+
+Readings where the paper is silent:
+
+* users with no leaders have an empty newsfeed: their rows of A and B are zero
+  (the sums in the definitions of A and B are empty) and p^(j) = 0;
+* ‖·‖ is the L1 norm (the paper's stated implementation choice, Sec. III-C);
+  ‖B‖ is the norm induced by L1 on row vectors, i.e. the largest row sum;
+* the default stopping test is ‖s_t − s_{t−1}‖₁ ≤ ε (eq. condition, the
+  "s-tolerance" of Sec. V); ``tol_mode="bnorm"`` multiplies the gap by ‖B‖ as
+  Algorithm 2 prints it, ``"rel_l1"`` divides it by ‖s_t‖₁;
+* ψ is formed from the final s (the last line of Algorithm 2).
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+
+__all__ = [
+    "clean_edges", "operator", "psi_by_definition", "power_nf", "psi_closed_form",
+    "power_psi", "pagerank_power", "transition_matrix", "fixed_point_residual",
+    "b_norm", "kappa", "rel_l1", "rel_l2",
+]
+
+
+def clean_edges(n, follower, leader):
+    """Drop self-loops and repeated edges (Sec. II: unweighted, no self-loops).
+
+    Returns (follower, leader, n_self_loops, n_duplicates) with the surviving
+    edges sorted by (follower, leader).
+    """
+    f = np.asarray(follower, dtype=np.int64)
+    l = np.asarray(leader, dtype=np.int64)
+    if f.shape != l.shape:
+        raise ValueError("follower and leader differ in length")
+    if f.size and (f.min() < 0 or l.min() < 0 or f.max() >= n or l.max() >= n):
+        raise ValueError("edge endpoint out of range")
+    loops = f == l
+    f, l = f[~loops], l[~loops]
+    key = np.unique(f * n + l)
+    n_dup = f.size - key.size
+    return key // n, key % n, int(loops.sum()), int(n_dup)
+
+
+def operator(n, follower, leader, lam, mu):
+    """A, B (scipy CSR, row j = follower, column i = leader), c, d.
+
+    a_ji = μ_i / Σ_{ℓ∈L(j)}(λ_ℓ+μ_ℓ) and b_ji = λ_i / Σ_{ℓ∈L(j)}(λ_ℓ+μ_ℓ) when
+    i ∈ L(j), else 0;  c_i = μ_i/(λ_i+μ_i), d_i = λ_i/(λ_i+μ_i).
+    """
+    lam = np.asarray(lam, dtype=np.float64)
+    mu = np.asarray(mu, dtype=np.float64)
+    f, l, _, _ = clean_edges(n, follower, leader)
+    den = np.zeros(n)
+    np.add.at(den, f, lam[l] + mu[l])
+    a_val = mu[l] / den[f]
+    b_val = lam[l] / den[f]
+    A = sp.csr_matrix((a_val, (f, l)), shape=(n, n))
+    B = sp.csr_matrix((b_val, (f, l)), shape=(n, n))
+    c = mu / (lam + mu)
+    d = lam / (lam + mu)
+    return A, B, c, d
+
+
+def psi_by_definition(n, follower, leader, lam, mu):
+    """ψ from its definition: N separate N-size solves (eqs. (2)–(5), psiscore).
+
+    For every origin i the newsfeed shares p_i solve, for every user j,
+        Σ_{k∈L(j)}(λ_k+μ_k) p_i^(j) − Σ_{k∈L(j)} μ_k p_i^(k) = λ_i 1{i∈L(j)}
+    (eqs. (4)–(5); a user with no leaders has p_i^(j) = 0), then the wall
+    shares are
+        (λ_j+μ_j) q_i^(j) = μ_j p_i^(j)            for j ≠ i   (eq. 2)
+        (λ_i+μ_i) q_i^(i) = λ_i + μ_i p_i^(i)                   (eq. 3)
+    and ψ_i = (1/N) Σ_n q_i^(n).  Dense; meant for N of a few hundred.
+    Returns (psi, P, Q) with p_i and q_i as column i of P and Q.
+    """
+    lam = np.asarray(lam, dtype=np.float64)
+    mu = np.asarray(mu, dtype=np.float64)
+    f, l, _, _ = clean_edges(n, follower, leader)
+    leads = np.zeros((n, n), dtype=bool)  # leads[j, k]: k ∈ L(j)
+    leads[f, l] = True
+    M = np.zeros((n, n))
+    for j in range(n):
+        ks = np.nonzero(leads[j])[0]
+        if ks.size == 0:
+            M[j, j] = 1.0  # empty newsfeed: p^(j) = 0
+            continue
+        M[j, j] += np.sum(lam[ks] + mu[ks])
+        M[j, ks] -= mu[ks]
+    P = np.zeros((n, n))
+    Q = np.zeros((n, n))
+    for i in range(n):
+        rhs = np.where(leads[:, i], lam[i], 0.0)
+        p = np.linalg.solve(M, rhs)
+        q = mu * p / (lam + mu)
+        q[i] = (lam[i] + mu[i] * p[i]) / (lam[i] + mu[i])
+        P[:, i] = p
+        Q[:, i] = q
+    psi = Q.sum(axis=0) / n
+    return psi, P, Q
+
+
+def power_nf(A, b_i, tol, max_iter=100_000):
+    """Algorithm 1 (Power-NF): p ← b_i; repeat p ← A p + b_i until ‖Δp‖₁ ≤ ε."""
+    p = np.array(b_i, dtype=np.float64)
+    t = 0
+    gap = 1.0
+    while gap > tol:
+        if t >= max_iter:
+            raise RuntimeError("Power-NF did not converge")
+        p_old = p
+        p = A @ p_old + b_i
+        gap = np.abs(p - p_old).sum()
+        t += 1
+    return p, t
+
+
+def psi_closed_form(A, B, c, d):
+    """Eq. (ultimsol) with Σ_t cᵀAᵗ = cᵀ(I−A)⁻¹: solve (I − Aᵀ) s = c."""
+    n = A.shape[0]
+    I = sp.identity(n, format="csc")
+    s = sp.linalg.spsolve((I - A.T).tocsc(), c)
+    psi = (B.T @ s + d) / n
+    return psi, s
+
+
+def b_norm(B):
+    """‖B‖ induced by L1 on row vectors: the largest row sum."""
+    rs = np.asarray(abs(B).sum(axis=1)).ravel()
+    return float(rs.max()) if rs.size else 0.0
+
+
+def kappa(A):
+    """Largest row sum of A: the contraction factor of s ↦ Aᵀs + c in L1."""
+    rs = np.asarray(abs(A).sum(axis=1)).ravel()
+    return float(rs.max()) if rs.size else 0.0
+
+
+def power_psi(A, B, c, d, tol, tol_mode="abs_l1", max_iter=100_000, s0=None,
+              record=False, steps=None):
+    """Algorithm 2 (Power-ψ) in FP64, steps in the paper's order.
+
+        s ← c (or a given start);  B_norm ← ‖B‖;  t ← 0;  gap ← 1
+        while gap > ε:  s_old ← s;  sᵀ ← s_oldᵀA + cᵀ;  gap ← ‖s_old − s‖₁
+                        (× B_norm for tol_mode "bnorm", ÷ ‖s‖₁ for "rel_l1");
+                        t ← t + 1
+        ψᵀ ← (sᵀB + dᵀ) / N
+
+    Returns a dict with psi, s, iterations t, the final gap and (optionally)
+    every gap.  ``steps`` runs exactly that many iterations whatever the gap
+    (used to inspect ψ_t at a fixed t).
+    """
+    if not tol > 0:
+        raise ValueError("tolerance must be positive")
+    n = A.shape[0]
+    AT = A.T.tocsr()
+    BT = B.T.tocsr()
+    s = np.array(c if s0 is None else s0, dtype=np.float64)
+    bnorm = b_norm(B)
+    t = 0
+    gap = 1.0
+    gaps = []
+    while (gap > tol) if steps is None else (t < steps):
+        if t >= max_iter:
+            raise RuntimeError("Power-psi did not converge")
+        s_old = s
+        s = AT @ s_old + c
+        gap = np.abs(s_old - s).sum()
+        if tol_mode == "bnorm":
+            gap *= bnorm
+        elif tol_mode == "rel_l1":
+            gap /= np.abs(s).sum()
+        elif tol_mode != "abs_l1":
+            raise ValueError(f"unknown tol_mode {tol_mode!r}")
+        t += 1
+        if record:
+            gaps.append(gap)
+    psi = (BT @ s + d) / n
+    return dict(psi=psi, s=s, iterations=t, gap=gap, gaps=gaps, bnorm=bnorm)
+
+
+def transition_matrix(n, follower, leader):
+    """W = D_out⁻¹ L with L_ji = 1 iff j follows i (Sec. III-D); rows of users
+    who follow nobody are zero."""
+    f, l, _, _ = clean_edges(n, follower, leader)
+    deg = np.bincount(f, minlength=n).astype(np.float64)
+    return sp.csr_matrix((1.0 / deg[f], (f, l)), shape=(n, n))
+
+
+def pagerank_power(W, alpha, tol, max_iter=100_000):
+    """Eq. (pagerank_power): π_t = α π_{t−1} W + (1−α)/N 1, from π_0 = 1/N,
+    stopped on the π-tolerance ‖π_t − π_{t−1}‖₁ ≤ ε (Sec. V)."""
+    n = W.shape[0]
+    WT = W.T.tocsr()
+    pi = np.full(n, 1.0 / n)
+    t = 0
+    gap = 1.0
+    while gap > tol:
+        if t >= max_iter:
+            raise RuntimeError("PageRank power method did not converge")
+        old = pi
+        pi = alpha * (WT @ old) + (1.0 - alpha) / n
+        gap = np.abs(pi - old).sum()
+        t += 1
+    return pi, t
+
+
+def fixed_point_residual(A, c, s):
+    """‖Aᵀs + c − s‖₁: how far s is from the fixed point of eq. (power_psi)."""
+    return float(np.abs(A.T @ s + c - s).sum())
+
+
+def rel_l1(ref, x):
+    ref = np.asarray(ref, dtype=np.float64)
+    return float(np.abs(np.asarray(x) - ref).sum() / np.abs(ref).sum())
+
+
+def rel_l2(ref, x):
+    """The paper's error measure, eq. (error)."""
+    ref = np.asarray(ref, dtype=np.float64)
+    return float(np.linalg.norm(np.asarray(x) - ref) / np.linalg.norm(ref))
