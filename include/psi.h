@@ -1,0 +1,208 @@
+/*
+ * psi.h — C ABI of the MI355X (gfx950) Power-ψ library.
+ *
+ * The library computes the ψ-score of Arhachoui, Bautista, Danisch and
+ * Giovanidis ("A Fast Algorithm for Ranking Users by their Influence in Online
+ * Social Platforms", ASONAM 2022): given a directed follower graph and, per
+ * user n, a posting rate λ_n and a re-posting rate μ_n (Sec. II), it solves the
+ * single N-size system of eq. (ultimsol) by the power iteration of
+ * Algorithm 2 (eq. power_psi) and returns ψ = (sᵀB + dᵀ)/N.
+ *
+ * Conventions shared by every entry point
+ *   - Edge k is (follower[k], leader[k]): user follower[k] follows user
+ *     leader[k] ((i, j) ∈ E means i follows j, Sec. II).  User ids are
+ *     0 .. n_users-1.
+ *   - Every function returns a psi_status; on failure psi_last_error() gives
+ *     a message (thread-local, valid until the next call on that thread).
+ *     No C++ exception crosses the ABI.
+ *   - Device pointers are HIP device memory on the current device.  The
+ *     library never allocates device memory: the caller passes workspaces
+ *     whose sizes the *_workspace_size queries return.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Work is
+ *     stream-ordered.  psi_build_operator and the solves block the calling
+ *     host thread until their result is known, because when to stop depends
+ *     on the data; psi_step and psi_final only enqueue.
+ *   - One operator may not be used by two calls at the same time: the solve
+ *     state lives in the operator's workspace.
+ *   - Limits: n_users < 2^30, n_users + n_edges < 2^31 - 4096.
+ */
+#ifndef PSI_H
+#define PSI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum psi_status {
+    PSI_OK = 0,
+    PSI_EINVAL = 1,      /* bad argument or input (message says which)        */
+    PSI_ENOTCONV = 2,    /* max_iter reached before the gap fell to tol       */
+    PSI_ESTAGNATED = 3,  /* the gap stopped decreasing above tol              */
+    PSI_ENUMERIC = 4,    /* NaN or Inf in the iteration                        */
+    PSI_EDEVICE = 5,     /* a HIP runtime call failed                          */
+    PSI_ENOSPACE = 6     /* a workspace is smaller than the size query said    */
+} psi_status;
+
+/* ---- operator build flags ------------------------------------------------ */
+#define PSI_INPUT_HOST       0x1u  /* follower/leader/lambda/mu are host pointers   */
+#define PSI_STRICT           0x2u  /* self-loops or repeated edges are an error     */
+#define PSI_WEIGHTED_FP64    0x4u  /* also store a_ji per edge in FP64 (weighted form) */
+#define PSI_FOLLOWER_MAJOR   0x8u  /* also keep CSR(A) (rows = followers)           */
+
+/* ---- tolerance modes (how the gap of eq. eps_t is compared with tol) ------ */
+#define PSI_TOL_ABS_L1  0  /* ‖s_t − s_{t−1}‖₁ ≤ tol   (eq. condition)            */
+#define PSI_TOL_BNORM   1  /* ‖B‖·‖s_t − s_{t−1}‖₁ ≤ tol   (Algorithm 2 as printed) */
+#define PSI_TOL_REL_L1  2  /* ‖s_t − s_{t−1}‖₁ / ‖s_t‖₁ ≤ tol                     */
+
+/* ---- arithmetic of a solve ----------------------------------------------- */
+#define PSI_PREC_FP64           0  /* FP64, factored operator (μ_i·Σ_j s_j/den_j)   */
+#define PSI_PREC_FP64_WEIGHTED  1  /* FP64, per-edge a_ji (needs PSI_WEIGHTED_FP64) */
+#define PSI_PREC_MIXED          2  /* FP32 correction solves + FP64 residual       */
+#define PSI_PREC_FP32           3  /* FP32 iterate only (no refinement)            */
+
+/* ---- solve flags ---------------------------------------------------------- */
+#define PSI_NO_FALLBACK     0x1u  /* use s0 even if its residual is worse than c's */
+
+typedef struct psi_operator psi_operator;
+
+typedef struct psi_operator_stats {
+    int64_t n_users;
+    int64_t n_edges_in;      /* edges passed to the build                   */
+    int64_t n_edges;         /* edges kept (M) after clean-up               */
+    int64_t n_self_loops;    /* dropped self-loops                          */
+    int64_t n_duplicates;    /* dropped repeated edges                      */
+    int64_t n_no_leaders;    /* users with an empty newsfeed (zero rows)    */
+    int64_t max_followers;   /* longest row of the pull operator            */
+    int32_t n_graphs;
+    int32_t flags;
+    double b_norm;           /* ‖B‖ = max_j Σ_i b_ji (L1-induced, row vectors) */
+    double kappa;            /* max_j Σ_i a_ji (< 1): contraction factor       */
+} psi_operator_stats;
+
+typedef struct psi_params {
+    double tol;          /* ε > 0                                              */
+    int32_t tol_mode;    /* PSI_TOL_*                                          */
+    int32_t max_iter;    /* cap on Power-ψ iterations (A-products), > 0        */
+    int32_t precision;   /* PSI_PREC_*                                         */
+    int32_t check_every; /* host checks the gap every k steps; 0 = adaptive    */
+    uint32_t flags;      /* PSI_NO_FALLBACK                                    */
+    int32_t tile_items;  /* merge-path items per tile; 0 = library default     */
+    double inner_tol;    /* PSI_PREC_MIXED: relative tol of each FP32 solve; 0 = default */
+} psi_params;
+
+typedef struct psi_info {
+    int32_t status;           /* same value as the return code              */
+    int32_t iterations;       /* Power-ψ steps t (FP64 A-products for MIXED) */
+    int32_t spmv_passes;      /* all operator passes incl. the final Bᵀs one  */
+    int32_t fp32_passes;      /* FP32 correction passes (MIXED / FP32)        */
+    int32_t refinements;      /* FP64 residual evaluations (MIXED)            */
+    int32_t used_s0;          /* 1 if the given s0 was used, 0 if c was       */
+    double final_gap;         /* last gap in the tol_mode's units            */
+    double final_l1_step;     /* last ‖s_t − s_{t−1}‖₁                        */
+    double b_norm;
+    double kappa;
+    double err_bound_s;       /* κ/(1−κ)·‖s_t − s_{t−1}‖₁ ≥ ‖s − s_t‖₁        */
+    double psi_gap_bound;     /* ‖s_t − s_{t−1}‖₁·‖B‖/N ≥ ‖ψ_t − ψ_{t−1}‖₁    */
+    double device_ms;         /* time from first to last kernel of the solve  */
+} psi_info;
+
+/* Library version string. */
+const char* psi_version(void);
+
+/* Message for the last failure on this thread ("" if none). */
+const char* psi_last_error(void);
+
+/* Sizes of the two device workspaces an operator build needs.
+ *   persistent: holds the operator and its solve state for the operator's
+ *               lifetime;
+ *   scratch:    used only during psi_build_operator, free afterwards.
+ * n_edges counts the raw edges, before self-loops and repeats are dropped. */
+psi_status psi_operator_workspace_size(int64_t n_users, int64_t n_edges, int32_t n_graphs,
+                                       uint32_t flags, size_t* persistent_bytes,
+                                       size_t* scratch_bytes);
+
+/* Build the Power-ψ operator (Sec. II, the definitions of A, b_i, C and d_i;
+ * c and d are the diagonals of C and D, Sec. III-A) on the device:
+ *   - drops self-loops and repeated edges (the graph is unweighted and has no
+ *     self-loops, Sec. II), or fails with PSI_STRICT;
+ *   - den_j = Σ_{ℓ∈L(j)} (λ_ℓ + μ_ℓ); a user with no leaders gets an empty
+ *     (zero) row of A and B;
+ *   - c_i = μ_i/(λ_i+μ_i), d_i = λ_i/(λ_i+μ_i);
+ *   - the pull operator CSR(Aᵀ): row i lists the followers of i, ascending;
+ *   - ‖B‖ and κ (largest row sums of B and A).
+ * follower, leader: int32 [n_edges]; lambda, mu: FP64 [n_users]; host
+ * pointers with PSI_INPUT_HOST, device pointers otherwise; not retained.
+ * λ_i must be finite and > 0, μ_i finite and ≥ 0 (else PSI_EINVAL).
+ * n_graphs > 1 stacks independent graphs block-diagonally: node_offsets
+ * (host, int64 [n_graphs+1], 0 = first, n_users = last) gives each graph's
+ * users and no edge may join two graphs.  n_graphs = 1 ignores node_offsets.
+ * persistent/scratch: device buffers of at least the queried sizes.
+ * *op receives a host handle (freed by psi_operator_destroy, which does not
+ * free the workspaces).  Blocks until the build is done. */
+psi_status psi_build_operator(int64_t n_users, int64_t n_edges, const int32_t* follower,
+                              const int32_t* leader, const double* lambda, const double* mu,
+                              int32_t n_graphs, const int64_t* node_offsets, uint32_t flags,
+                              void* persistent, size_t persistent_bytes, void* scratch,
+                              size_t scratch_bytes, void* stream, psi_operator** op);
+
+psi_status psi_operator_destroy(psi_operator* op);
+
+psi_status psi_operator_get_stats(const psi_operator* op, psi_operator_stats* out);
+
+/* Device views of the built operator (read-only, valid while the persistent
+ * workspace lives): row_ptr int32 [N+1] and col int32 [M] of CSR(Aᵀ); c, d,
+ * inv_den (1/den_j, 0 for a user with no leaders) FP64 [N]. Any out pointer
+ * may be NULL. */
+psi_status psi_operator_views(const psi_operator* op, const int32_t** row_ptr,
+                              const int32_t** col, const double** c, const double** d,
+                              const double** inv_den);
+
+/* Fill *p with the library defaults (tol 1e-8, PSI_TOL_ABS_L1, max_iter 10000,
+ * PSI_PREC_FP64, adaptive checks). */
+psi_status psi_params_default(psi_params* p);
+
+/* Solve for ψ by Algorithm 2: s ← s0 (or c); repeat s ← Aᵀs + c until the gap
+ * (tol_mode) is ≤ tol; then ψ = (Bᵀs + d)/N from the final s.
+ *   s0:      device FP64 [N] start, or NULL for c.  Unless PSI_NO_FALLBACK,
+ *            s0 is replaced by c when its residual ‖Aᵀs0 + c − s0‖₁ exceeds
+ *            that of c (info->used_s0 says which was used);
+ *   psi_out: device FP64 [N];
+ *   s_out:   device FP64 [N] final s, or NULL;
+ *   info:    host, may be NULL.
+ * Returns PSI_ENOTCONV / PSI_ESTAGNATED / PSI_ENUMERIC with ψ of the last
+ * iterate written. */
+psi_status psi_solve(psi_operator* op, const psi_params* prm, const double* s0,
+                     double* psi_out, double* s_out, psi_info* info, void* stream);
+
+/* One Power-ψ step (eq. power_psi), enqueued only:
+ *   s_out = Aᵀ s_in + c,  *gap_out (device FP64 scalar, may be NULL)
+ *   = ‖s_out − s_in‖₁.  precision PSI_PREC_FP64 or PSI_PREC_FP64_WEIGHTED.
+ * s_in, s_out: device FP64 [N], distinct. */
+psi_status psi_step(psi_operator* op, int32_t precision, const double* s_in, double* s_out,
+                    double* gap_out, int32_t tile_items, void* stream);
+
+/* The last line of Algorithm 2, enqueued only: psi_out = (Bᵀ s + d)/N.
+ * s, psi_out: device FP64 [N]. */
+psi_status psi_final(psi_operator* op, const double* s, double* psi_out, void* stream);
+
+/* ---- operator pass kinds (for timing and tuning) -------------------------- */
+#define PSI_PASS_STEP64     0  /* FP64 factored step: s' = c + μ⊙Σ_{j∈F(i)} s_j/den_j */
+#define PSI_PASS_STEP64_W   1  /* FP64 weighted step: s' = c + Σ_j a_ji s_j           */
+#define PSI_PASS_FINAL64    2  /* ψ = (λ⊙Σ_{j∈F(i)} s_j/den_j + d)/N                 */
+#define PSI_PASS_STEP32     3  /* FP32 correction step: e' = r + μ⊙Σ e_j/den_j        */
+
+/* Time `reps` back-to-back launches of one operator pass (the kernel a solve
+ * runs in its loop), between two hipEvents recorded on `stream`, after one
+ * untimed launch.  Writes the mean duration of one launch in milliseconds to
+ * *mean_ms (host).  Overwrites the operator's solve state.  Blocks until done. */
+psi_status psi_pass_time(psi_operator* op, int32_t pass_kind, int32_t reps, int32_t tile_items,
+                         double* mean_ms, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PSI_H */

@@ -1,0 +1,225 @@
+"""Python face of the Power-ψ library: the C-ABI calls under the same names.
+
+PyTorch supplies device memory (workspaces and result tensors are torch
+tensors) and the stream; every step of the computation runs in the HIP
+kernels of libpsi.so.  Nothing here computes ψ.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _ffi
+from ._ffi import (PSI_FOLLOWER_MAJOR, PSI_INPUT_HOST, PSI_NO_FALLBACK, PSI_PREC_FP32,  # noqa: F401
+                   PSI_PREC_FP64, PSI_PREC_FP64_WEIGHTED, PSI_PREC_MIXED, PSI_STRICT,
+                   PSI_TOL_ABS_L1, PSI_TOL_BNORM, PSI_TOL_REL_L1, PSI_WEIGHTED_FP64)
+
+PRECISIONS = {"fp64": PSI_PREC_FP64, "fp64_weighted": PSI_PREC_FP64_WEIGHTED,
+              "mixed": PSI_PREC_MIXED, "fp32": PSI_PREC_FP32}
+TOL_MODES = {"abs_l1": PSI_TOL_ABS_L1, "bnorm": PSI_TOL_BNORM, "rel_l1": PSI_TOL_REL_L1}
+
+
+class PsiError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{_ffi.STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+def load():
+    return _ffi.load()
+
+
+def _check(status: int):
+    if status != _ffi.PSI_OK:
+        raise PsiError(status, _ffi.load().psi_last_error().decode())
+
+
+def _stream_handle(stream) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _ptr(t) -> int | None:
+    return None if t is None else int(t.data_ptr())
+
+
+def version() -> str:
+    return _ffi.load().psi_version().decode()
+
+
+def workspace_size(n_users: int, n_edges: int, n_graphs: int = 1, flags: int = 0) -> tuple[int, int]:
+    lib = _ffi.load()
+    p, s = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(lib.psi_operator_workspace_size(n_users, n_edges, n_graphs, flags, ctypes.byref(p),
+                                           ctypes.byref(s)))
+    return p.value, s.value
+
+
+class Operator:
+    """A built Power-ψ operator (psi_build_operator) and its device workspace.
+
+    follower/leader/lam/mu are numpy arrays (passed as host memory) or CUDA
+    torch tensors (int32 / float64).  Edge k means follower[k] follows
+    leader[k].
+    """
+
+    def __init__(self, n_users, follower, leader, lam, mu, node_offsets=None, flags: int = 0,
+                 stream=None, device=None):
+        lib = _ffi.load()
+        self._lib = lib
+        self.device = torch.device(device) if device is not None else torch.device(
+            "cuda", torch.cuda.current_device())
+        host = isinstance(follower, np.ndarray)
+        keep = []
+        if host:
+            f = np.ascontiguousarray(follower, dtype=np.int32)
+            l = np.ascontiguousarray(leader, dtype=np.int32)
+            la = np.ascontiguousarray(lam, dtype=np.float64)
+            m_ = np.ascontiguousarray(mu, dtype=np.float64)
+            keep = [f, l, la, m_]
+            ptrs = [a.ctypes.data for a in keep]
+            flags |= PSI_INPUT_HOST
+            n_edges = int(f.shape[0])
+        else:
+            f = follower.to(self.device, torch.int32).contiguous()
+            l = leader.to(self.device, torch.int32).contiguous()
+            la = lam.to(self.device, torch.float64).contiguous()
+            m_ = mu.to(self.device, torch.float64).contiguous()
+            keep = [f, l, la, m_]
+            ptrs = [a.data_ptr() for a in keep]
+            n_edges = int(f.shape[0])
+        n_graphs = 1
+        offs_ptr = None
+        if node_offsets is not None:
+            offs = np.ascontiguousarray(node_offsets, dtype=np.int64)
+            n_graphs = int(offs.shape[0] - 1)
+            keep.append(offs)
+            offs_ptr = offs.ctypes.data
+            self.node_offsets = offs.copy()
+        else:
+            self.node_offsets = np.array([0, n_users], dtype=np.int64)
+        self.n = int(n_users)
+        self.n_graphs = n_graphs
+        self.flags = flags
+        pbytes, sbytes = workspace_size(self.n, n_edges, n_graphs, flags)
+        self.workspace = torch.empty(pbytes, dtype=torch.uint8, device=self.device)
+        scratch = torch.empty(sbytes, dtype=torch.uint8, device=self.device)
+        handle = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            st = _stream_handle(stream)
+            _check(lib.psi_build_operator(self.n, n_edges, ptrs[0], ptrs[1], ptrs[2], ptrs[3],
+                                          n_graphs, offs_ptr, flags, self.workspace.data_ptr(),
+                                          pbytes, scratch.data_ptr(), sbytes, st,
+                                          ctypes.byref(handle)))
+        del scratch
+        self._h = handle
+
+    # ------------------------------------------------------------------ queries
+    @property
+    def handle(self):
+        return self._h
+
+    def stats(self) -> dict:
+        s = _ffi.OperatorStats()
+        _check(self._lib.psi_operator_get_stats(self._h, ctypes.byref(s)))
+        return _ffi.struct_dict(s)
+
+    def views(self) -> dict:
+        """row_ptr, col, c, d, inv_den as tensors aliasing the workspace."""
+        ptrs = [ctypes.c_void_p() for _ in range(5)]
+        _check(self._lib.psi_operator_views(self._h, *[ctypes.byref(p) for p in ptrs]))
+        st = self.stats()
+        base = self.workspace.data_ptr()
+        out = {}
+        for name, p, dt, cnt in (("row_ptr", ptrs[0], torch.int32, self.n + 1),
+                                 ("col", ptrs[1], torch.int32, st["n_edges"]),
+                                 ("c", ptrs[2], torch.float64, self.n),
+                                 ("d", ptrs[3], torch.float64, self.n),
+                                 ("inv_den", ptrs[4], torch.float64, self.n)):
+            off = p.value - base
+            nbytes = cnt * torch.tensor([], dtype=dt).element_size()
+            out[name] = self.workspace[off:off + nbytes].view(dt)
+        return out
+
+    # ------------------------------------------------------------------ compute
+    def solve(self, tol: float = 1e-8, tol_mode: str = "abs_l1", max_iter: int = 10000,
+              precision: str = "fp64", s0: torch.Tensor | None = None, check_every: int = 0,
+              tile_items: int = 0, inner_tol: float = 0.0, no_fallback: bool = False,
+              return_s: bool = False, psi_out: torch.Tensor | None = None, stream=None,
+              raise_on_status: bool = False):
+        """psi_solve: ψ (and s) by Algorithm 2; returns (psi, info) or (psi, s, info)."""
+        p = _ffi.Params()
+        _check(self._lib.psi_params_default(ctypes.byref(p)))
+        p.tol = tol
+        p.tol_mode = TOL_MODES[tol_mode] if isinstance(tol_mode, str) else int(tol_mode)
+        p.max_iter = max_iter
+        p.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        p.check_every = check_every
+        p.flags = PSI_NO_FALLBACK if no_fallback else 0
+        p.tile_items = tile_items
+        p.inner_tol = inner_tol
+        psi = psi_out if psi_out is not None else torch.empty(self.n, dtype=torch.float64,
+                                                              device=self.device)
+        s = torch.empty(self.n, dtype=torch.float64, device=self.device) if return_s else None
+        if s0 is not None:
+            s0 = s0.to(self.device, torch.float64).contiguous()
+        info = _ffi.Info()
+        with torch.cuda.device(self.device):
+            st = self._lib.psi_solve(self._h, ctypes.byref(p), _ptr(s0), _ptr(psi), _ptr(s),
+                                     ctypes.byref(info), _stream_handle(stream))
+        d = _ffi.struct_dict(info)
+        d["status_name"] = _ffi.STATUS_NAMES.get(st, str(st))
+        if st in (_ffi.PSI_EINVAL, _ffi.PSI_EDEVICE, _ffi.PSI_ENOSPACE) or (
+                raise_on_status and st != _ffi.PSI_OK):
+            _check(st)
+        return (psi, s, d) if return_s else (psi, d)
+
+    def step(self, s_in: torch.Tensor, precision: str = "fp64", tile_items: int = 0,
+             stream=None):
+        """psi_step: one Power-ψ step s_out = Aᵀ s_in + c and its L1 gap (enqueued)."""
+        s_in = s_in.to(self.device, torch.float64).contiguous()
+        out = torch.empty_like(s_in)
+        gap = torch.empty(1, dtype=torch.float64, device=self.device)
+        with torch.cuda.device(self.device):
+            _check(self._lib.psi_step(self._h, PRECISIONS[precision], s_in.data_ptr(),
+                                      out.data_ptr(), gap.data_ptr(), tile_items,
+                                      _stream_handle(stream)))
+        return out, gap
+
+    def final(self, s: torch.Tensor, stream=None) -> torch.Tensor:
+        """psi_final: ψ = (Bᵀ s + d)/N (enqueued)."""
+        s = s.to(self.device, torch.float64).contiguous()
+        out = torch.empty_like(s)
+        with torch.cuda.device(self.device):
+            _check(self._lib.psi_final(self._h, s.data_ptr(), out.data_ptr(),
+                                       _stream_handle(stream)))
+        return out
+
+    def pass_time(self, kind: str, reps: int = 50, tile_items: int = 0, stream=None) -> float:
+        """psi_pass_time: mean ms of one launch of a pass kind (HIP events on the stream)."""
+        kinds = {"step64": _ffi.PSI_PASS_STEP64, "step64_w": _ffi.PSI_PASS_STEP64_W,
+                 "final64": _ffi.PSI_PASS_FINAL64, "step32": _ffi.PSI_PASS_STEP32}
+        out = ctypes.c_double()
+        with torch.cuda.device(self.device):
+            _check(self._lib.psi_pass_time(self._h, kinds[kind], reps, tile_items,
+                                           ctypes.byref(out), _stream_handle(stream)))
+        return out.value
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.psi_operator_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def build_operator(graph, flags: int = 0, stream=None, device=None) -> Operator:
+    """Operator from a synthetic graph record (host arrays)."""
+    return Operator(graph.n, graph.follower, graph.leader, graph.lam, graph.mu,
+                    node_offsets=graph.node_offsets, flags=flags, stream=stream, device=device)

@@ -1,0 +1,223 @@
+// extern "C" entry points of the Power-ψ library (declared in include/psi.h).
+#include <cstring>
+#include <exception>
+#include <new>
+
+#include "psi_internal.h"
+
+namespace psi {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+void clear_error() { g_last_error.clear(); }
+
+psi_status step(psi_operator* op, int precision, const double* s_in, double* s_out,
+                double* gap_out, int tile_items, hipStream_t st);
+psi_status final_psi(psi_operator* op, const double* s_vec, double* psi_out, hipStream_t st);
+psi_status pass_time(psi_operator* op, int kind, int reps, int tile_items, double* mean_ms,
+                     hipStream_t st);
+
+static psi_status check_device(const psi_operator* op) {
+  int dev = -1;
+  PSI_HIP_CHECK(hipGetDevice(&dev));
+  if (dev != op->device) {
+    set_error("the current device is not the one the operator was built on");
+    return PSI_EINVAL;
+  }
+  return PSI_OK;
+}
+
+}  // namespace psi
+
+using psi::set_error;
+
+#define PSI_GUARD_BEGIN \
+  psi::clear_error();   \
+  try {
+#define PSI_GUARD_END                          \
+  }                                            \
+  catch (const std::bad_alloc&) {              \
+    set_error("host allocation failed");       \
+    return PSI_EDEVICE;                        \
+  }                                            \
+  catch (const std::exception& e) {            \
+    set_error(e.what());                       \
+    return PSI_EDEVICE;                        \
+  }                                            \
+  catch (...) {                                \
+    set_error("unknown C++ exception");        \
+    return PSI_EDEVICE;                        \
+  }
+
+extern "C" {
+
+const char* psi_version(void) { return "psi-mi355x 0.1 (gfx950)"; }
+
+const char* psi_last_error(void) { return psi::g_last_error.c_str(); }
+
+psi_status psi_operator_workspace_size(int64_t n_users, int64_t n_edges, int32_t n_graphs,
+                                       uint32_t flags, size_t* persistent_bytes,
+                                       size_t* scratch_bytes) {
+  PSI_GUARD_BEGIN
+  PSI_REQUIRE(n_users >= 1 && n_users < (int64_t(1) << 30), "n_users must be in [1, 2^30)");
+  PSI_REQUIRE(n_edges >= 0, "n_edges must be >= 0");
+  PSI_REQUIRE(n_users + n_edges < (int64_t(1) << 31) - 4096, "n_users + n_edges too large");
+  PSI_REQUIRE(n_graphs >= 1, "n_graphs must be >= 1");
+  PSI_REQUIRE(persistent_bytes && scratch_bytes, "output pointers must not be NULL");
+  psi::Layout L = psi::compute_layout(n_users, n_edges, n_graphs, flags);
+  *persistent_bytes = L.persistent;
+  *scratch_bytes = L.scratch;
+  return PSI_OK;
+  PSI_GUARD_END
+}
+
+psi_status psi_build_operator(int64_t n_users, int64_t n_edges, const int32_t* follower,
+                              const int32_t* leader, const double* lambda, const double* mu,
+                              int32_t n_graphs, const int64_t* node_offsets, uint32_t flags,
+                              void* persistent, size_t persistent_bytes, void* scratch,
+                              size_t scratch_bytes, void* stream, psi_operator** op) {
+  PSI_GUARD_BEGIN
+  PSI_REQUIRE(op, "op must not be NULL");
+  *op = nullptr;
+  PSI_REQUIRE(n_users >= 1 && n_users < (int64_t(1) << 30), "n_users must be in [1, 2^30)");
+  PSI_REQUIRE(n_edges >= 0, "n_edges must be >= 0");
+  PSI_REQUIRE(n_users + n_edges < (int64_t(1) << 31) - 4096, "n_users + n_edges too large");
+  PSI_REQUIRE(n_edges == 0 || (follower && leader), "edge arrays must not be NULL");
+  PSI_REQUIRE(lambda && mu, "lambda and mu must not be NULL");
+  PSI_REQUIRE(n_graphs >= 1, "n_graphs must be >= 1");
+  PSI_REQUIRE(persistent && scratch, "workspaces must not be NULL");
+  if (n_graphs > 1) {
+    PSI_REQUIRE(node_offsets, "node_offsets needed when n_graphs > 1");
+    PSI_REQUIRE(node_offsets[0] == 0 && node_offsets[n_graphs] == n_users,
+                "node_offsets must run from 0 to n_users");
+    for (int g = 0; g < n_graphs; ++g)
+      PSI_REQUIRE(node_offsets[g + 1] > node_offsets[g], "every graph needs at least one user");
+  }
+  psi::Layout L = psi::compute_layout(n_users, n_edges, n_graphs, flags);
+  if (persistent_bytes < L.persistent || scratch_bytes < L.scratch) {
+    set_error("workspace smaller than psi_operator_workspace_size reported");
+    return PSI_ENOSPACE;
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  psi_operator* o = new psi_operator();
+  PSI_HIP_CHECK(hipGetDevice(&o->device));
+  o->n = n_users;
+  o->m_in = n_edges;
+  o->n_graphs = n_graphs;
+  o->flags = flags;
+  if (n_graphs > 1) o->node_offsets.assign(node_offsets, node_offsets + n_graphs + 1);
+  else o->node_offsets = {0, n_users};
+  psi::carve_persistent(o, static_cast<char*>(persistent), n_edges, n_graphs);
+  psi_status s = psi::build_operator(o, follower, leader, lambda, mu, node_offsets,
+                                     static_cast<char*>(scratch), scratch_bytes, st);
+  if (s == PSI_OK) {
+    hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&o->host_ctrl), 2 * sizeof(psi::Ctrl),
+                                 hipHostMallocDefault);
+    if (e != hipSuccess) {
+      set_error(std::string("hipHostMalloc: ") + hipGetErrorString(e));
+      s = PSI_EDEVICE;
+    }
+  }
+  if (s != PSI_OK) {
+    if (o->host_ctrl) (void)hipHostFree(o->host_ctrl);
+    delete o;
+    return s;
+  }
+  *op = o;
+  return PSI_OK;
+  PSI_GUARD_END
+}
+
+psi_status psi_operator_destroy(psi_operator* op) {
+  PSI_GUARD_BEGIN
+  if (!op) return PSI_OK;
+  if (op->host_ctrl) (void)hipHostFree(op->host_ctrl);
+  delete op;
+  return PSI_OK;
+  PSI_GUARD_END
+}
+
+psi_status psi_operator_get_stats(const psi_operator* op, psi_operator_stats* out) {
+  PSI_GUARD_BEGIN
+  PSI_REQUIRE(op && out, "arguments must not be NULL");
+  *out = op->stats;
+  return PSI_OK;
+  PSI_GUARD_END
+}
+
+psi_status psi_operator_views(const psi_operator* op, const int32_t** row_ptr,
+                              const int32_t** col, const double** c, const double** d,
+                              const double** inv_den) {
+  PSI_GUARD_BEGIN
+  PSI_REQUIRE(op, "op must not be NULL");
+  if (row_ptr) *row_ptr = op->row_ptr;
+  if (col) *col = op->col;
+  if (c) *c = op->c;
+  if (d) *d = op->d;
+  if (inv_den) *inv_den = op->invden;
+  return PSI_OK;
+  PSI_GUARD_END
+}
+
+psi_status psi_params_default(psi_params* p) {
+  PSI_GUARD_BEGIN
+  PSI_REQUIRE(p, "p must not be NULL");
+  std::memset(p, 0, sizeof(*p));
+  p->tol = 1e-8;
+  p->tol_mode = PSI_TOL_ABS_L1;
+  p->max_iter = 10000;
+  p->precision = PSI_PREC_FP64;
+  p->check_every = 0;
+  p->flags = 0;
+  p->tile_items = 0;
+  p->inner_tol = 0.0;
+  return PSI_OK;
+  PSI_GUARD_END
+}
+
+psi_status psi_solve(psi_operator* op, const psi_params* prm, const double* s0,
+                     double* psi_out, double* s_out, psi_info* info, void* stream) {
+  PSI_GUARD_BEGIN
+  PSI_REQUIRE(op, "op must not be NULL");
+  psi_status s = psi::check_device(op);
+  if (s != PSI_OK) return s;
+  return psi::solve(op, prm, s0, psi_out, s_out, info, static_cast<hipStream_t>(stream));
+  PSI_GUARD_END
+}
+
+psi_status psi_step(psi_operator* op, int32_t precision, const double* s_in, double* s_out,
+                    double* gap_out, int32_t tile_items, void* stream) {
+  PSI_GUARD_BEGIN
+  PSI_REQUIRE(op, "op must not be NULL");
+  psi_status s = psi::check_device(op);
+  if (s != PSI_OK) return s;
+  return psi::step(op, precision, s_in, s_out, gap_out, tile_items,
+                   static_cast<hipStream_t>(stream));
+  PSI_GUARD_END
+}
+
+psi_status psi_final(psi_operator* op, const double* s, double* psi_out, void* stream) {
+  PSI_GUARD_BEGIN
+  PSI_REQUIRE(op, "op must not be NULL");
+  PSI_REQUIRE(op->n_graphs == 1, "psi_final: multi-graph operators are finished by psi_solve_batched");
+  psi_status st = psi::check_device(op);
+  if (st != PSI_OK) return st;
+  return psi::final_psi(op, s, psi_out, static_cast<hipStream_t>(stream));
+  PSI_GUARD_END
+}
+
+psi_status psi_pass_time(psi_operator* op, int32_t pass_kind, int32_t reps, int32_t tile_items,
+                         double* mean_ms, void* stream) {
+  PSI_GUARD_BEGIN
+  PSI_REQUIRE(op, "op must not be NULL");
+  PSI_REQUIRE(op->n_graphs == 1, "psi_pass_time needs a single-graph operator");
+  psi_status st = psi::check_device(op);
+  if (st != PSI_OK) return st;
+  return psi::pass_time(op, pass_kind, reps, tile_items, mean_ms, static_cast<hipStream_t>(stream));
+  PSI_GUARD_END
+}
+
+}  // extern "C"

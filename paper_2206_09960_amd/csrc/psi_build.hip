@@ -1,0 +1,686 @@
+// Operator build on the device (Sec. II: the definitions of A, b_i, C, d_i).
+//
+// edges -> drop self-loops -> LSD radix sort of (follower, leader) keys ->
+// drop repeats -> CSR(A) (rows = followers j, cols = leaders L(j)) ->
+// den_j, 1/den_j, row sums of A and B -> sort of the swapped keys ->
+// CSR(Aᵀ) (rows = leaders i, cols = followers j, ascending), the pull
+// operator the Power-ψ pass runs over.
+//
+// Every step is deterministic: the sort is total on (row, col) keys, sums run
+// in ascending column order, and maxima are exact.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "psi_internal.h"
+
+namespace psi {
+
+bool tile_items_supported(int t);
+
+namespace {
+
+constexpr int kSortWaves = 4;
+constexpr int kSortRounds = 16;
+constexpr int kSortTile = kSortWaves * kSortRounds * 64;  // keys per workgroup
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kBlock * kScanItems;
+
+inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+inline int bits_for(int64_t n) {
+  int b = 1;
+  while ((int64_t(1) << b) < n) ++b;
+  return b;
+}
+
+// ------------------------------------------------------------------ scan
+// Exclusive prefix sum of uint32 (results fit in uint32: callers bound the
+// totals by 2^31).  Three kernels: tile totals, scan of the totals, tile scan.
+__global__ __launch_bounds__(kBlock) void k_scan_tile_sums(const uint32_t* in, int64_t n,
+                                                           uint32_t* tile_sums) {
+  __shared__ uint32_t red[kBlock / 64];
+  int64_t base = int64_t(blockIdx.x) * kScanTile;
+  uint32_t acc = 0;
+  for (int i = 0; i < kScanItems; ++i) {
+    int64_t k = base + int64_t(i) * kBlock + threadIdx.x;
+    if (k < n) acc += in[k];
+  }
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t t = 0;
+    for (int w = 0; w < kBlock / 64; ++w) t += red[w];
+    tile_sums[blockIdx.x] = t;
+  }
+}
+
+// Single workgroup: exclusive scan of the tile totals, chunk by chunk.
+__global__ __launch_bounds__(1024) void k_scan_totals(uint32_t* sums, int64_t n_tiles,
+                                                      uint32_t* total_out) {
+  __shared__ uint32_t buf[1024];
+  __shared__ uint32_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int64_t base = 0; base < n_tiles; base += 1024) {
+    int64_t k = base + threadIdx.x;
+    uint32_t v = k < n_tiles ? sums[k] : 0u;
+    buf[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+      uint32_t t = threadIdx.x >= off ? buf[threadIdx.x - off] : 0u;
+      __syncthreads();
+      buf[threadIdx.x] += t;
+      __syncthreads();
+    }
+    uint32_t incl = buf[threadIdx.x];
+    if (k < n_tiles) sums[k] = carry + incl - v;
+    __syncthreads();
+    if (threadIdx.x == 1023) carry += incl;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && total_out) *total_out = carry;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_apply(const uint32_t* in, uint32_t* out,
+                                                       int64_t n, const uint32_t* tile_off) {
+  __shared__ uint32_t part[kBlock];
+  int64_t base = int64_t(blockIdx.x) * kScanTile + int64_t(threadIdx.x) * kScanItems;
+  uint32_t v[kScanItems];
+  uint32_t run = 0;
+  for (int i = 0; i < kScanItems; ++i) {
+    int64_t k = base + i;
+    v[i] = k < n ? in[k] : 0u;
+    run += v[i];
+  }
+  part[threadIdx.x] = run;
+  __syncthreads();
+  for (int off = 1; off < kBlock; off <<= 1) {
+    uint32_t t = threadIdx.x >= off ? part[threadIdx.x - off] : 0u;
+    __syncthreads();
+    part[threadIdx.x] += t;
+    __syncthreads();
+  }
+  uint32_t acc = tile_off[blockIdx.x] + part[threadIdx.x] - run;
+  for (int i = 0; i < kScanItems; ++i) {
+    int64_t k = base + i;
+    if (k < n) out[k] = acc;
+    acc += v[i];
+  }
+}
+
+// ------------------------------------------------------------------ radix sort
+// LSD radix sort of uint64 keys, 8-bit digits.  A workgroup owns kSortTile
+// consecutive keys; wave w takes rounds of 64 consecutive keys, so the order
+// (wave, round, lane) is the input order and the scatter is stable.
+__device__ inline uint64_t lanemask_lt() {
+  return (uint64_t(1) << __lane_id()) - 1;
+}
+
+__global__ __launch_bounds__(kBlock) void k_radix_hist(const uint64_t* keys, int64_t n, int shift,
+                                                       uint32_t* counts, int n_blocks) {
+  __shared__ uint32_t hist[256];
+  hist[threadIdx.x] = 0;
+  __syncthreads();
+  int64_t base = int64_t(blockIdx.x) * kSortTile;
+  for (int i = 0; i < kSortTile / kBlock; ++i) {
+    int64_t k = base + int64_t(i) * kBlock + threadIdx.x;
+    if (k < n) atomicAdd(&hist[(keys[k] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  counts[int64_t(threadIdx.x) * n_blocks + blockIdx.x] = hist[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint64_t* keys_in,
+                                                          uint64_t* keys_out, int64_t n,
+                                                          int shift, const uint32_t* offsets,
+                                                          int n_blocks) {
+  __shared__ uint32_t wave_cnt[kSortWaves][256];
+  __shared__ uint32_t glob[256];
+  const int wave = threadIdx.x >> 6;
+  const int lane = __lane_id();
+  for (int w = 0; w < kSortWaves; ++w) wave_cnt[w][threadIdx.x] = 0;
+  glob[threadIdx.x] = offsets[int64_t(threadIdx.x) * n_blocks + blockIdx.x];
+  __syncthreads();
+  int64_t base = int64_t(blockIdx.x) * kSortTile + int64_t(wave) * (kSortRounds * 64);
+  uint64_t key[kSortRounds];
+  uint32_t pos[kSortRounds];
+  for (int r = 0; r < kSortRounds; ++r) {
+    int64_t k = base + int64_t(r) * 64 + lane;
+    bool valid = k < n;
+    key[r] = valid ? keys_in[k] : 0;
+    uint32_t dig = uint32_t(key[r] >> shift) & 255u;
+    uint64_t peers = __ballot(valid);
+    for (int b = 0; b < 8; ++b) {
+      bool bit = (dig >> b) & 1u;
+      uint64_t m = __ballot(valid && bit);
+      peers &= bit ? m : ~m;
+    }
+    uint32_t rank = __popcll(peers & lanemask_lt());
+    uint32_t before = wave_cnt[wave][dig];
+    pos[r] = before + rank;
+    if (valid && rank == 0) wave_cnt[wave][dig] = before + __popcll(peers);
+    __builtin_amdgcn_wave_barrier();
+  }
+  __syncthreads();
+  {
+    uint32_t run = 0;
+    for (int w = 0; w < kSortWaves; ++w) {
+      uint32_t t = wave_cnt[w][threadIdx.x];
+      wave_cnt[w][threadIdx.x] = run;
+      run += t;
+    }
+  }
+  __syncthreads();
+  for (int r = 0; r < kSortRounds; ++r) {
+    int64_t k = base + int64_t(r) * 64 + lane;
+    if (k < n) {
+      uint32_t dig = uint32_t(key[r] >> shift) & 255u;
+      const uint64_t p = uint64_t(glob[dig]) + wave_cnt[wave][dig] + pos[r];
+      if (p < uint64_t(n)) keys_out[p] = key[r];
+    }
+  }
+}
+
+// ------------------------------------------------------------------ edge kernels
+__global__ void k_check_activity(const double* lam, const double* mu, int64_t n, Ctrl* ctrl) {
+  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double l = lam[i], m = mu[i];
+  if (!(l > 0.0) || !isfinite(l) || !(m >= 0.0) || !isfinite(m))
+    atomicOr(&ctrl->err_flags, kErrActivity);
+}
+
+// key = (row << nb) | col; self-loops become the all-ones sentinel, which
+// sorts after every real key and is dropped by the compaction.
+__global__ void k_pack_keys(const int32_t* follower, const int32_t* leader, int64_t m,
+                            int64_t n, int nb, int follower_major, uint64_t sentinel,
+                            const int64_t* graph_off, int n_graphs, uint64_t* keys,
+                            Ctrl* ctrl) {
+  int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= m) return;
+  int64_t f = follower[k], l = leader[k];
+  if (f < 0 || f >= n || l < 0 || l >= n) {
+    atomicOr(&ctrl->err_flags, kErrIndex);
+    keys[k] = sentinel;
+    return;
+  }
+  if (n_graphs > 1) {
+    // graph of a user: last g with graph_off[g] <= id
+    int lo = 0, hi = n_graphs;
+    while (hi - lo > 1) {
+      int mid = (lo + hi) >> 1;
+      if (graph_off[mid] <= f) lo = mid; else hi = mid;
+    }
+    if (l < graph_off[lo] || l >= graph_off[lo + 1]) atomicOr(&ctrl->err_flags, kErrCrossGraph);
+  }
+  if (f == l) {
+    atomicAdd(&ctrl->n_self_loops, 1ull);
+    keys[k] = sentinel;
+    return;
+  }
+  uint64_t row = uint64_t(follower_major ? f : l);
+  uint64_t cl = uint64_t(follower_major ? l : f);
+  keys[k] = (row << nb) | cl;
+}
+
+__global__ void k_flag_unique(const uint64_t* keys, int64_t m, uint64_t sentinel,
+                              uint32_t* flags) {
+  int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= m) return;
+  uint64_t v = keys[k];
+  flags[k] = (v != sentinel && (k == 0 || keys[k - 1] != v)) ? 1u : 0u;
+}
+
+__global__ void k_compact(const uint64_t* keys, int64_t m, uint64_t sentinel,
+                          const uint32_t* pos, uint64_t* out) {
+  int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= m) return;
+  uint64_t v = keys[k];
+  if (v != sentinel && (k == 0 || keys[k - 1] != v)) out[pos[k]] = v;
+}
+
+__global__ void k_swap_halves(const uint64_t* in, int64_t m, int nb, uint64_t* out) {
+  int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= m) return;
+  uint64_t v = in[k];
+  uint64_t mask = (uint64_t(1) << nb) - 1;
+  out[k] = ((v & mask) << nb) | (v >> nb);
+}
+
+// CSR from row-major sorted distinct keys: col[e] and the row starts.
+__global__ void k_csr_from_keys(const uint64_t* keys, int64_t m, int64_t n, int nb,
+                                int* row_ptr, int* col) {
+  int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= m) return;
+  uint64_t v = keys[e];
+  uint64_t mask = (uint64_t(1) << nb) - 1;
+  int64_t r = int64_t(v >> nb);
+  col[e] = int(v & mask);
+  int64_t r_prev = e == 0 ? -1 : int64_t(keys[e - 1] >> nb);
+  for (int64_t rr = r_prev + 1; rr <= r; ++rr) row_ptr[rr] = int(e);
+  if (e == m - 1)
+    for (int64_t rr = r + 1; rr <= n; ++rr) row_ptr[rr] = int(m);
+}
+
+__global__ void k_fill_u64(uint64_t* p, int64_t n, uint64_t v) {
+  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_fill_int(int* p, int64_t n, int v) {
+  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// Per follower j over CSR(A): den_j = Σ_{ℓ∈L(j)}(λ_ℓ+μ_ℓ) in ascending ℓ,
+// 1/den_j (0 for an empty newsfeed), and the row sums of B and A.
+__global__ void k_den(const int* fm_row_ptr, const int* fm_col, const double* lam,
+                      const double* mu, int64_t n, double* invden, Ctrl* ctrl) {
+  int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  int e0 = fm_row_ptr[j], e1 = fm_row_ptr[j + 1];
+  double den = 0.0, sl = 0.0, sm = 0.0;
+  for (int e = e0; e < e1; ++e) {
+    int k = fm_col[e];
+    double lk = lam[k], mk = mu[k];
+    den += lk + mk;
+    sl += lk;
+    sm += mk;
+  }
+  if (e1 == e0) {
+    invden[j] = 0.0;
+    atomicAdd(&ctrl->n_no_leaders, 1ull);
+    return;
+  }
+  double inv = 1.0 / den;
+  invden[j] = inv;
+  double bj = sl * inv, kj = sm * inv;
+  atomicMax(&ctrl->bnorm_bits, (unsigned long long)__double_as_longlong(bj));
+  atomicMax(&ctrl->kappa_bits, (unsigned long long)__double_as_longlong(kj));
+}
+
+__global__ void k_node_consts(const double* lam, const double* mu, const double* invden,
+                              int64_t n, double* c, double* d, float* mu32, float* invden32,
+                              float* c32) {
+  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double l = lam[i], m = mu[i];
+  double ci = m / (l + m);
+  c[i] = ci;
+  d[i] = l / (l + m);
+  mu32[i] = float(m);
+  invden32[i] = float(invden[i]);
+  c32[i] = float(ci);
+}
+
+__global__ void k_max_row(const int* row_ptr, int64_t n, Ctrl* ctrl) {
+  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  unsigned long long len = (unsigned long long)(row_ptr[i + 1] - row_ptr[i]);
+  if (len) atomicMax(&ctrl->max_row, len);
+}
+
+// a_ji = μ_i / den_j stored per edge of CSR(Aᵀ) row i (weighted form).
+__global__ void k_weights64(const int* row_ptr, const int* col, const double* mu,
+                            const double* invden, int64_t n, double* val) {
+  int64_t row = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+  int lane = threadIdx.x & 63;
+  if (row >= n) return;
+  double mi = mu[row];
+  for (int e = row_ptr[row] + lane; e < row_ptr[row + 1]; e += 64) val[e] = mi * invden[col[e]];
+}
+
+// First row of every merge-path tile: on the path that merges the row ends
+// row_ptr[1..n] with the edge indices 0..m-1, tile b starts at diagonal b*T.
+__global__ void k_schedule(const int* row_ptr, int64_t n, int64_t m, int64_t items,
+                           int64_t n_tiles, int* tile_row) {
+  int64_t b = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (b > n_tiles) return;
+  int64_t diag = std::min(b * items, n + m);
+  int64_t lo = std::max<int64_t>(diag - m, 0), hi = std::min<int64_t>(diag, n);
+  while (lo < hi) {
+    int64_t pivot = (lo + hi) >> 1;
+    if (int64_t(row_ptr[pivot + 1]) <= diag - pivot - 1) lo = pivot + 1; else hi = pivot;
+  }
+  tile_row[b] = int(lo);
+}
+
+inline unsigned grid_for(int64_t n, int block = kBlock) {
+  return unsigned((n + block - 1) / block);
+}
+
+struct Scratch {
+  char* p;
+  size_t left;
+  template <class T>
+  T* take(int64_t count) {
+    size_t bytes = align_up(size_t(std::max<int64_t>(count, 1)) * sizeof(T));
+    if (bytes > left) return nullptr;
+    T* r = reinterpret_cast<T*>(p);
+    p += bytes;
+    left -= bytes;
+    return r;
+  }
+};
+
+struct SortBufs {
+  uint64_t* a;
+  uint64_t* b;
+  uint32_t* counts;   // 256 * n_blocks
+  uint32_t* flags;    // m_raw
+  uint32_t* tile_sums;
+  uint32_t* total;    // 1 value
+};
+
+psi_status scan_u32(const uint32_t* in, uint32_t* out, int64_t n, SortBufs& sb,
+                    hipStream_t st) {
+  if (n <= 0) return PSI_OK;
+  int64_t tiles = (n + kScanTile - 1) / kScanTile;
+  hipLaunchKernelGGL(k_scan_tile_sums, dim3(unsigned(tiles)), dim3(kBlock), 0, st, in, n,
+                     sb.tile_sums);
+  hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(1024), 0, st, sb.tile_sums, tiles, sb.total);
+  hipLaunchKernelGGL(k_scan_apply, dim3(unsigned(tiles)), dim3(kBlock), 0, st, in, out, n,
+                     sb.tile_sums);
+  PSI_HIP_CHECK(hipGetLastError());
+  return PSI_OK;
+}
+
+// Sorts sb.a[0..m) on the low `bits` bits; returns the buffer holding the result.
+psi_status radix_sort(SortBufs& sb, int64_t m, int bits, hipStream_t st, uint64_t** result) {
+  int n_blocks = int((m + kSortTile - 1) / kSortTile);
+  uint64_t* src = sb.a;
+  uint64_t* dst = sb.b;
+  for (int shift = 0; shift < bits; shift += 8) {
+    hipLaunchKernelGGL(k_radix_hist, dim3(n_blocks), dim3(kBlock), 0, st, src, m, shift,
+                       sb.counts, n_blocks);
+    psi_status s = scan_u32(sb.counts, sb.counts, int64_t(256) * n_blocks, sb, st);
+    if (s != PSI_OK) return s;
+    hipLaunchKernelGGL(k_radix_scatter, dim3(n_blocks), dim3(kBlock), 0, st, src, dst, m, shift,
+                       sb.counts, n_blocks);
+    PSI_HIP_CHECK(hipGetLastError());
+    std::swap(src, dst);
+  }
+  *result = src;
+  return PSI_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ layout
+static void layout_persistent(int64_t n, int64_t m_raw, int n_graphs, uint32_t flags,
+                              psi_operator* op, char* base, size_t* total) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char* {
+    char* p = base ? base + off : nullptr;
+    off += align_up(std::max<size_t>(bytes, 1));
+    return p;
+  };
+  int64_t max_tiles = (n + m_raw) / kMinTileItems + 2;
+  char* row_ptr = take(4 * size_t(n + 1));
+  char* col = take(4 * size_t(m_raw));
+  char* fm_row_ptr = nullptr;
+  char* fm_col = nullptr;
+  if (flags & PSI_FOLLOWER_MAJOR) {
+    fm_row_ptr = take(4 * size_t(n + 1));
+    fm_col = take(4 * size_t(m_raw));
+  }
+  char* lam = take(8 * size_t(n));
+  char* mu = take(8 * size_t(n));
+  char* c = take(8 * size_t(n));
+  char* d = take(8 * size_t(n));
+  char* invden = take(8 * size_t(n));
+  char* mu32 = take(4 * size_t(n));
+  char* invden32 = take(4 * size_t(n));
+  char* c32 = take(4 * size_t(n));
+  char* val64 = (flags & PSI_WEIGHTED_FP64) ? take(8 * size_t(m_raw)) : nullptr;
+  char* s_a = take(8 * size_t(n));
+  char* s_b = take(8 * size_t(n));
+  char* z_a = take(8 * size_t(n));
+  char* z_b = take(8 * size_t(n));
+  char* e_a = take(4 * size_t(n));
+  char* e_b = take(4 * size_t(n));
+  char* ze_a = take(4 * size_t(n));
+  char* ze_b = take(4 * size_t(n));
+  char* r32 = take(4 * size_t(n));
+  char* part_open = take(8 * size_t(max_tiles));
+  char* gap_part = take(16 * size_t(kMaxGrid));
+  char* tile_row = take(4 * size_t(max_tiles + 1));
+  char* ctrl = take(2 * sizeof(Ctrl));
+  char* hist = take(8 * size_t(kHistLen));
+  char* scal = take(8 * 8);
+  char* goff = take(8 * size_t(n_graphs + 1));
+  *total = off;
+  if (!op) return;
+  op->row_ptr = (int*)row_ptr;
+  op->col = (int*)col;
+  op->fm_row_ptr = (int*)fm_row_ptr;
+  op->fm_col = (int*)fm_col;
+  op->lam = (double*)lam;
+  op->mu = (double*)mu;
+  op->c = (double*)c;
+  op->d = (double*)d;
+  op->invden = (double*)invden;
+  op->mu32 = (float*)mu32;
+  op->invden32 = (float*)invden32;
+  op->c32 = (float*)c32;
+  op->val64 = (double*)val64;
+  op->s_a = (double*)s_a;
+  op->s_b = (double*)s_b;
+  op->z_a = (double*)z_a;
+  op->z_b = (double*)z_b;
+  op->e_a = (float*)e_a;
+  op->e_b = (float*)e_b;
+  op->ze_a = (float*)ze_a;
+  op->ze_b = (float*)ze_b;
+  op->r32 = (float*)r32;
+  op->part_open = (double*)part_open;
+  op->gap_part = (double*)gap_part;
+  op->tile_row = (int*)tile_row;
+  op->max_tiles = max_tiles;
+  op->ctrl = (Ctrl*)ctrl;
+  op->hist = (double*)hist;
+  op->scal = (double*)scal;
+  op->graph_off = (int64_t*)goff;
+}
+
+static size_t scratch_size(int64_t n, int64_t m_raw) {
+  int64_t sort_blocks = (m_raw + kSortTile - 1) / kSortTile;
+  int64_t scan_len = std::max<int64_t>(m_raw, 256 * sort_blocks);
+  size_t s = 0;
+  s += 2 * align_up(8 * size_t(std::max<int64_t>(m_raw, 1)));        // key buffers
+  s += align_up(4 * size_t(256 * std::max<int64_t>(sort_blocks, 1))); // digit counts
+  s += align_up(4 * size_t(std::max<int64_t>(m_raw, 1)));            // flags / CSR(A) cols
+  s += align_up(4 * size_t((scan_len + kScanTile - 1) / kScanTile + 1));
+  s += align_up(4 * 4);                                               // scan total
+  s += align_up(4 * size_t(n + 1));                                   // CSR(A) rows
+  return s;
+}
+
+Layout compute_layout(int64_t n, int64_t m_raw, int n_graphs, uint32_t flags) {
+  Layout L;
+  layout_persistent(n, m_raw, n_graphs, flags, nullptr, nullptr, &L.persistent);
+  L.scratch = scratch_size(n, m_raw);
+  return L;
+}
+
+void carve_persistent(psi_operator* op, char* base, int64_t m_raw, int n_graphs) {
+  size_t total = 0;
+  layout_persistent(op->n, m_raw, n_graphs, op->flags, op, base, &total);
+}
+
+// ------------------------------------------------------------------ build
+psi_status build_operator(psi_operator* op, const int32_t* follower, const int32_t* leader,
+                          const double* lambda, const double* mu, const int64_t* node_offsets,
+                          char* scratch, size_t scratch_bytes, hipStream_t st) {
+  const int64_t n = op->n;
+  const int64_t m_raw = op->m_in;
+  const bool host_in = (op->flags & PSI_INPUT_HOST) != 0;
+  Scratch sc{scratch, scratch_bytes};
+  SortBufs sb{};
+  sb.a = sc.take<uint64_t>(m_raw);
+  sb.b = sc.take<uint64_t>(m_raw);
+  int64_t sort_blocks = (m_raw + kSortTile - 1) / kSortTile;
+  sb.counts = sc.take<uint32_t>(256 * std::max<int64_t>(sort_blocks, 1));
+  sb.flags = sc.take<uint32_t>(m_raw);
+  int64_t scan_len = std::max<int64_t>(m_raw, 256 * sort_blocks);
+  sb.tile_sums = sc.take<uint32_t>((scan_len + kScanTile - 1) / kScanTile + 1);
+  sb.total = sc.take<uint32_t>(4);
+  int* fm_row_ptr_tmp = sc.take<int>(n + 1);
+  if (!sb.a || !sb.b || !sb.counts || !sb.flags || !sb.tile_sums || !sb.total ||
+      !fm_row_ptr_tmp) {
+    set_error("scratch workspace too small");
+    return PSI_ENOSPACE;
+  }
+
+  PSI_HIP_CHECK(hipMemsetAsync(op->ctrl, 0, 2 * sizeof(Ctrl), st));
+  hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(op->max_tiles)), dim3(kBlock), 0, st,
+                     reinterpret_cast<uint64_t*>(op->part_open), op->max_tiles, kEmptySlot);
+  hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(2 * kMaxGrid)), dim3(kBlock), 0, st,
+                     reinterpret_cast<uint64_t*>(op->gap_part), int64_t(2 * kMaxGrid), kEmptySlot);
+  if (op->n_graphs > 1)
+    PSI_HIP_CHECK(hipMemcpyAsync(op->graph_off, node_offsets, 8 * size_t(op->n_graphs + 1),
+                                 hipMemcpyHostToDevice, st));
+  // activity vectors -> persistent λ, μ
+  hipMemcpyKind kind = host_in ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+  PSI_HIP_CHECK(hipMemcpyAsync(op->lam, lambda, 8 * size_t(n), kind, st));
+  PSI_HIP_CHECK(hipMemcpyAsync(op->mu, mu, 8 * size_t(n), kind, st));
+  hipLaunchKernelGGL(k_check_activity, dim3(grid_for(n)), dim3(kBlock), 0, st, op->lam, op->mu,
+                     n, op->ctrl);
+  // edges (host copies go to the second key buffer, unused until the first scatter)
+  const int32_t* f_dev = follower;
+  const int32_t* l_dev = leader;
+  if (host_in && m_raw > 0) {
+    int32_t* tmp = reinterpret_cast<int32_t*>(sb.b);
+    PSI_HIP_CHECK(hipMemcpyAsync(tmp, follower, 4 * size_t(m_raw), hipMemcpyHostToDevice, st));
+    PSI_HIP_CHECK(hipMemcpyAsync(tmp + m_raw, leader, 4 * size_t(m_raw), hipMemcpyHostToDevice,
+                                 st));
+    f_dev = tmp;
+    l_dev = tmp + m_raw;
+  }
+  const int nb = bits_for(n);
+  const int key_bits = 2 * nb;
+  const uint64_t sentinel = key_bits >= 64 ? ~uint64_t(0) : ((uint64_t(1) << key_bits) - 1);
+
+  int64_t m = 0;
+  uint64_t* sorted = sb.a;
+  if (m_raw > 0) {
+    hipLaunchKernelGGL(k_pack_keys, dim3(grid_for(m_raw)), dim3(kBlock), 0, st, f_dev, l_dev,
+                       m_raw, n, nb, 1, sentinel, op->graph_off, op->n_graphs, sb.a, op->ctrl);
+    PSI_HIP_CHECK(hipGetLastError());
+    psi_status s = radix_sort(sb, m_raw, key_bits, st, &sorted);
+    if (s != PSI_OK) return s;
+    hipLaunchKernelGGL(k_flag_unique, dim3(grid_for(m_raw)), dim3(kBlock), 0, st, sorted, m_raw,
+                       sentinel, sb.flags);
+    s = scan_u32(sb.flags, sb.flags, m_raw, sb, st);
+    if (s != PSI_OK) return s;
+    uint32_t total = 0;
+    PSI_HIP_CHECK(hipMemcpyAsync(&total, sb.total, 4, hipMemcpyDeviceToHost, st));
+    uint64_t* uniq = (sorted == sb.a) ? sb.b : sb.a;
+    hipLaunchKernelGGL(k_compact, dim3(grid_for(m_raw)), dim3(kBlock), 0, st, sorted, m_raw,
+                       sentinel, sb.flags, uniq);
+    PSI_HIP_CHECK(hipStreamSynchronize(st));
+    m = int64_t(total);
+    sorted = uniq;
+  }
+  Ctrl hc{};
+  PSI_HIP_CHECK(hipMemcpyAsync(&hc, op->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+  PSI_HIP_CHECK(hipStreamSynchronize(st));
+  if (hc.err_flags & kErrIndex) { set_error("edge endpoint outside [0, n_users)"); return PSI_EINVAL; }
+  if (hc.err_flags & kErrActivity) {
+    set_error("activity must satisfy lambda > 0 and mu >= 0, both finite");
+    return PSI_EINVAL;
+  }
+  if (hc.err_flags & kErrCrossGraph) { set_error("an edge joins two graphs"); return PSI_EINVAL; }
+  const int64_t n_loops = int64_t(hc.n_self_loops);
+  const int64_t n_dups = m_raw - n_loops - m;
+  if ((op->flags & PSI_STRICT) && (n_loops || n_dups)) {
+    set_error("PSI_STRICT: input has " + std::to_string(n_loops) + " self-loops and " +
+              std::to_string(n_dups) + " repeated edges");
+    return PSI_EINVAL;
+  }
+  op->m = m;
+
+  // CSR(A): rows = followers j, cols = leaders (in the flags region, or persistent)
+  int* fm_row_ptr = op->fm_row_ptr ? op->fm_row_ptr : fm_row_ptr_tmp;
+  int* fm_col = op->fm_col ? op->fm_col : reinterpret_cast<int*>(sb.flags);
+  if (m > 0) {
+    hipLaunchKernelGGL(k_csr_from_keys, dim3(grid_for(m)), dim3(kBlock), 0, st, sorted, m, n, nb,
+                       fm_row_ptr, fm_col);
+  } else {
+    hipLaunchKernelGGL(k_fill_int, dim3(grid_for(n + 1)), dim3(kBlock), 0, st, fm_row_ptr, n + 1,
+                       0);
+  }
+  hipLaunchKernelGGL(k_den, dim3(grid_for(n)), dim3(kBlock), 0, st, fm_row_ptr, fm_col, op->lam,
+                     op->mu, n, op->invden, op->ctrl);
+  hipLaunchKernelGGL(k_node_consts, dim3(grid_for(n)), dim3(kBlock), 0, st, op->lam, op->mu,
+                     op->invden, n, op->c, op->d, op->mu32, op->invden32, op->c32);
+  PSI_HIP_CHECK(hipGetLastError());
+
+  // CSR(Aᵀ): sort the swapped keys
+  if (m > 0) {
+    uint64_t* other = (sorted == sb.a) ? sb.b : sb.a;
+    hipLaunchKernelGGL(k_swap_halves, dim3(grid_for(m)), dim3(kBlock), 0, st, sorted, m, nb,
+                       other);
+    SortBufs sb2 = sb;
+    sb2.a = other;
+    sb2.b = sorted;
+    uint64_t* res = nullptr;
+    psi_status s = radix_sort(sb2, m, key_bits, st, &res);
+    if (s != PSI_OK) return s;
+    hipLaunchKernelGGL(k_csr_from_keys, dim3(grid_for(m)), dim3(kBlock), 0, st, res, m, n, nb,
+                       op->row_ptr, op->col);
+  } else {
+    hipLaunchKernelGGL(k_fill_int, dim3(grid_for(n + 1)), dim3(kBlock), 0, st, op->row_ptr, n + 1,
+                       0);
+  }
+  hipLaunchKernelGGL(k_max_row, dim3(grid_for(n)), dim3(kBlock), 0, st, op->row_ptr, n, op->ctrl);
+  if (op->val64 && m > 0)
+    hipLaunchKernelGGL(k_weights64, dim3(grid_for(n * 64)), dim3(kBlock), 0, st, op->row_ptr,
+                       op->col, op->mu, op->invden, n, op->val64);
+  PSI_HIP_CHECK(hipGetLastError());
+  PSI_HIP_CHECK(hipMemcpyAsync(&hc, op->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+  PSI_HIP_CHECK(hipStreamSynchronize(st));
+
+  double bnorm, kap;
+  std::memcpy(&bnorm, &hc.bnorm_bits, 8);
+  std::memcpy(&kap, &hc.kappa_bits, 8);
+  psi_operator_stats& S = op->stats;
+  S.n_users = n;
+  S.n_edges_in = m_raw;
+  S.n_edges = m;
+  S.n_self_loops = n_loops;
+  S.n_duplicates = n_dups;
+  S.n_no_leaders = int64_t(hc.n_no_leaders);
+  S.max_followers = int64_t(hc.max_row);
+  S.n_graphs = op->n_graphs;
+  S.flags = int32_t(op->flags);
+  S.b_norm = bnorm;
+  S.kappa = kap;
+  op->sched_items = 0;
+  return ensure_schedule(op, kDefaultTileItems, st);
+}
+
+psi_status ensure_schedule(psi_operator* op, int tile_items, hipStream_t st) {
+  if (tile_items <= 0) tile_items = kDefaultTileItems;
+  if (!tile_items_supported(tile_items)) {
+    set_error("tile_items must be one of 1024, 1536, 2048, 3072, 4096");
+    return PSI_EINVAL;
+  }
+  if (op->sched_items == tile_items) return PSI_OK;
+  int64_t total = op->n + op->m;
+  int64_t n_tiles = std::max<int64_t>((total + tile_items - 1) / tile_items, 1);
+  if (n_tiles + 1 > op->max_tiles + 1) {
+    set_error("schedule does not fit the workspace");
+    return PSI_ENOSPACE;
+  }
+  hipLaunchKernelGGL(k_schedule, dim3(grid_for(n_tiles + 1)), dim3(kBlock), 0, st, op->row_ptr,
+                     op->n, op->m, int64_t(tile_items), n_tiles, op->tile_row);
+  PSI_HIP_CHECK(hipGetLastError());
+  op->sched_items = tile_items;
+  op->n_tiles = int(n_tiles);
+  return PSI_OK;
+}
+
+}  // namespace psi

@@ -1,0 +1,173 @@
+// Internal declarations of the Power-ψ HIP library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "psi.h"
+
+namespace psi {
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string& msg);
+void clear_error();
+
+#define PSI_HIP_CHECK(expr)                                                        \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess) {                                                        \
+      psi::set_error(std::string(#expr) + ": " + hipGetErrorString(e_));           \
+      return PSI_EDEVICE;                                                          \
+    }                                                                              \
+  } while (0)
+
+#define PSI_REQUIRE(cond, msg)        \
+  do {                                \
+    if (!(cond)) {                    \
+      psi::set_error(msg);            \
+      return PSI_EINVAL;              \
+    }                                 \
+  } while (0)
+
+// ---------------------------------------------------------------- constants
+constexpr int kBlock = 256;            // threads of every operator-pass workgroup
+constexpr int kMinTileItems = 1024;    // smallest merge-path tile (sizes the schedule)
+constexpr int kDefaultTileItems = 2048;
+constexpr int kHistLen = 1 << 16;      // device gap history entries
+constexpr int kMaxGrid = 8192;         // largest resident grid of a pass kernel
+// Cross-tile slots hold this signalling-NaN pattern while empty.  Every value
+// a tile publishes is the result of floating-point arithmetic, which never
+// produces a signalling NaN, so the pattern cannot collide with data.
+constexpr unsigned long long kEmptySlot = 0x7FF4DEADBEEF0001ull;
+
+// Validation bits raised by the build kernels.
+enum : unsigned {
+  kErrIndex = 1u,      // edge endpoint outside [0, n)
+  kErrActivity = 2u,   // λ not finite/positive or μ not finite/non-negative
+  kErrCrossGraph = 4u, // an edge joins two graphs of a multi-graph operator
+  kErrSlotTimeout = 8u,  // a cross-tile slot was not filled in time (never expected)
+};
+
+// Device-side control block of one operator (one solve at a time).
+struct Ctrl {
+  unsigned int ticket;    // tiles finished in the current pass
+  int done;               // 1 once the gap met tol, max_iter hit or NaN seen
+  int iter;               // steps performed in the current solve
+  int status;             // psi_status decided on the device
+  double gap;             // last gap in tol_mode units
+  double l1;              // last ‖Δ‖₁
+  double snorm;           // last ‖s_new‖₁
+  double tol;
+  int tol_mode;
+  int max_iter;
+  double bnorm;
+  unsigned int err_flags;           // build validation
+  unsigned int pad0;
+  unsigned long long bnorm_bits;    // max over rows (bit pattern of a non-negative double)
+  unsigned long long kappa_bits;
+  unsigned long long n_self_loops;
+  unsigned long long n_unique;
+  unsigned long long n_no_leaders;
+  unsigned long long max_row;
+};
+
+// Arguments of one merge-path operator pass.  The pass gathers x over the
+// follower lists of CSR(Aᵀ) and applies a per-row epilogue.
+struct PassArgs {
+  const int* row_ptr;
+  const int* col;
+  const int* tile_row;  // first row of each tile, [n_tiles + 1]
+  int n_rows;
+  int n_nnz;
+  int n_tiles;
+  int tile_items;
+  const void* x;        // gathered vector (FP64 or FP32)
+  const double* val64;  // per-edge weights (weighted form) or null
+  // epilogue inputs / outputs
+  const double* c;
+  const double* mu;
+  const double* invden;
+  const double* lam;
+  const double* d;
+  const double* s_old;
+  double* s_new;
+  double* z_new;
+  const float* r32;
+  const float* mu32;
+  const float* invden32;
+  const float* e_old;
+  float* e_new;
+  float* ze_new;
+  double inv_n;
+  // cross-tile state
+  double* part_open;   // [n_tiles] a tile's partial of its open last row (slot)
+  double* gap_part;    // [2*grid] (Σ|Δ|, Σ|new|) of each workgroup (slot)
+  Ctrl* ctrl;
+  double* hist;
+  double* gap_out;      // optional plain copy of the gap (psi_step)
+  int count_iter;       // 1: the pass is a Power-ψ step that advances ctrl->iter
+  int respect_done;     // 1: exit at once when ctrl->done is set
+};
+
+enum PassMode : int {
+  kStep64 = 0,      // s_new = c + μ·Σ z_j, z_new = invden·s_new, gap
+  kStep64W = 1,     // s_new = c + Σ a_ji s_j (weighted), gap
+  kFinal64 = 2,     // ψ = (λ·Σ z_j + d)/N
+  kStep32 = 3,      // e_new = r + μ·Σ ze_j, ze_new = invden·e_new, gap (FP32 storage)
+};
+
+}  // namespace psi
+
+struct psi_operator {
+  int device = 0;
+  int64_t n = 0, m_in = 0, m = 0;
+  int n_graphs = 1;
+  uint32_t flags = 0;
+  psi_operator_stats stats{};
+  // persistent device arrays
+  int* row_ptr = nullptr;   // CSR(Aᵀ): rows = leaders, cols = followers
+  int* col = nullptr;
+  int* fm_row_ptr = nullptr;  // CSR(A): rows = followers, cols = leaders (optional)
+  int* fm_col = nullptr;
+  double *lam = nullptr, *mu = nullptr, *c = nullptr, *d = nullptr, *invden = nullptr;
+  float *mu32 = nullptr, *invden32 = nullptr, *c32 = nullptr;
+  double* val64 = nullptr;
+  // solve state
+  double *s_a = nullptr, *s_b = nullptr, *z_a = nullptr, *z_b = nullptr;
+  float *e_a = nullptr, *e_b = nullptr, *ze_a = nullptr, *ze_b = nullptr, *r32 = nullptr;
+  double *part_open = nullptr, *gap_part = nullptr;
+  int* tile_row = nullptr;
+  int64_t max_tiles = 0;
+  int sched_items = 0;   // tile size the schedule in tile_row was built for
+  int n_tiles = 0;
+  psi::Ctrl* ctrl = nullptr;   // [2]: outer solve, inner (FP32 correction) solve
+  psi::Ctrl* host_ctrl = nullptr;  // pinned host mirror
+  double* hist = nullptr;
+  double* scal = nullptr;  // small FP64 device scratch (8 values)
+  int64_t* graph_off = nullptr;  // device copy of node_offsets [n_graphs + 1]
+  std::vector<int64_t> node_offsets;
+};
+
+namespace psi {
+// Workspace layout shared by the size query and the build.
+struct Layout {
+  size_t persistent = 0;
+  size_t scratch = 0;
+};
+Layout compute_layout(int64_t n, int64_t m_raw, int n_graphs, uint32_t flags);
+void carve_persistent(psi_operator* op, char* base, int64_t m_raw, int n_graphs);
+
+psi_status build_operator(psi_operator* op, const int32_t* follower, const int32_t* leader,
+                          const double* lambda, const double* mu, const int64_t* node_offsets,
+                          char* scratch, size_t scratch_bytes, hipStream_t stream);
+
+psi_status ensure_schedule(psi_operator* op, int tile_items, hipStream_t stream);
+psi_status launch_pass(psi_operator* op, PassMode mode, const PassArgs& a, hipStream_t stream);
+PassArgs base_args(psi_operator* op);
+
+psi_status solve(psi_operator* op, const psi_params* prm, const double* s0, double* psi_out,
+                 double* s_out, psi_info* info, hipStream_t stream);
+}  // namespace psi

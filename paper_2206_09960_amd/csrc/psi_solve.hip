@@ -1,0 +1,541 @@
+// Solve drivers: Algorithm 2 (Power-ψ) on the device.
+//
+// The host only enqueues passes and, every few passes, reads a pinned copy of
+// the device control block; the gap test of eq. (condition) is made on the
+// device by the last tile of each pass, and passes enqueued after it exit at
+// once.  The number of passes between host checks is predicted from the
+// observed geometric decay of the gap.
+//
+// PSI_PREC_MIXED refines in FP64 around FP32 correction solves: with
+// r = Aᵀs + c − s computed in FP64 (one FP64 pass, whose L1 norm is also the
+// gap of eq. eps_t), the correction e = Aᵀe + r is iterated in FP32 to a
+// relative tolerance and s ← s + e.  The fixed point of eq. (power_psi) is
+// unchanged; only the arithmetic of the correction is FP32.
+#include <algorithm>
+#include <cmath>
+#include <limits>
+
+#include "psi_internal.h"
+
+namespace psi {
+
+bool tile_items_supported(int t);
+
+namespace {
+
+inline unsigned grid_for(int64_t n) { return static_cast<unsigned>((n + kBlock - 1) / kBlock); }
+
+__global__ void k_init64(const double* s0, const double* c, const double* invden, int64_t n,
+                         double* s, double* z) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double v = s0 ? s0[i] : c[i];
+  s[i] = v;
+  z[i] = invden[i] * v;
+}
+
+__global__ void k_init32(const double* s0, const double* c, const float* invden32, int64_t n,
+                         float* e, float* ze) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float v = static_cast<float>(s0 ? s0[i] : c[i]);
+  e[i] = v;
+  ze[i] = invden32[i] * v;
+}
+
+__global__ void k_ctrl_set(Ctrl* c, double tol, int tol_mode, int max_iter, double bnorm) {
+  c->ticket = 0;
+  c->done = 0;
+  c->iter = 0;
+  c->status = 0;
+  c->gap = 0.0;
+  c->l1 = 0.0;
+  c->snorm = 0.0;
+  c->tol = tol;
+  c->tol_mode = tol_mode;
+  c->max_iter = max_iter;
+  c->bnorm = bnorm;
+}
+
+// Inner (FP32 correction) solve: stop when ‖e_k − e_{k−1}‖₁ ≤ η‖r‖₁.
+__global__ void k_ctrl_inner(const Ctrl* outer, Ctrl* inner, double eta, int max_iter) {
+  inner->ticket = 0;
+  inner->done = 0;
+  inner->iter = 0;
+  inner->status = 0;
+  inner->gap = 0.0;
+  inner->l1 = 0.0;
+  inner->tol = eta * outer->l1;
+  inner->tol_mode = PSI_TOL_ABS_L1;
+  inner->max_iter = max_iter;
+  inner->bnorm = 1.0;
+}
+
+// r = s_new − s_old (the FP64 residual Aᵀs + c − s), rounded to FP32; e_0 = r.
+__global__ void k_prep_inner(const double* s_new, const double* s_old, const float* invden32,
+                             int64_t n, float* r32, float* e, float* ze) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float r = static_cast<float>(s_new[i] - s_old[i]);
+  r32[i] = r;
+  e[i] = r;
+  ze[i] = invden32[i] * r;
+}
+
+__global__ void k_update(double* s, const float* e, const double* invden, int64_t n, double* z) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double v = s[i] + static_cast<double>(e[i]);
+  s[i] = v;
+  z[i] = invden[i] * v;
+}
+
+__global__ void k_e_to_s(const float* e, const double* invden, int64_t n, double* s, double* z) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double v = static_cast<double>(e[i]);
+  s[i] = v;
+  z[i] = invden[i] * v;
+}
+
+__global__ void k_make_z(const double* s, const double* invden, int64_t n, double* z) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) z[i] = invden[i] * s[i];
+}
+
+struct IterResult {
+  int iters = 0;       // passes that ran on the device (ctrl->iter)
+  int status = PSI_OK;
+  double gap = 0.0;
+  double l1 = 0.0;
+  bool stagnated = false;
+};
+
+// Enqueue passes until the device sets done; make(i) gives the arguments of
+// pass i (i counts passes enqueued in this call).
+template <class Make>
+psi_status iterate(psi_operator* op, int ctrl_idx, PassMode mode, Make make, int max_iter,
+                   int check_every, hipStream_t st, IterResult* out) {
+  Ctrl* dctrl = op->ctrl + ctrl_idx;
+  Ctrl* hctrl = op->host_ctrl + ctrl_idx;
+  int enq = 0;
+  int k = check_every > 0 ? check_every : 6;
+  double prev_gap = -1.0;
+  int prev_iter = 0;
+  double best = std::numeric_limits<double>::infinity();
+  int best_iter = 0;
+  while (true) {
+    const int cnt = std::min(k, max_iter - enq);
+    for (int i = 0; i < cnt; ++i) {
+      psi_status s = launch_pass(op, mode, make(enq + i), st);
+      if (s != PSI_OK) return s;
+    }
+    enq += cnt;
+    PSI_HIP_CHECK(hipMemcpyAsync(hctrl, dctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+    PSI_HIP_CHECK(hipStreamSynchronize(st));
+    out->iters = hctrl->iter;
+    out->gap = hctrl->gap;
+    out->l1 = hctrl->l1;
+    out->status = hctrl->status;
+    if (hctrl->done) return PSI_OK;
+    if (enq >= max_iter) {
+      out->status = PSI_ENOTCONV;
+      return PSI_OK;
+    }
+    const double gap = hctrl->gap;
+    const int it = hctrl->iter;
+    if (gap < best * (1.0 - 1e-3)) {
+      best = gap;
+      best_iter = it;
+    } else if (it - best_iter >= 25) {
+      out->status = PSI_ESTAGNATED;
+      out->stagnated = true;
+      return PSI_OK;
+    }
+    if (check_every == 0) {
+      if (prev_gap > 0.0 && gap > 0.0 && gap < prev_gap && it > prev_iter) {
+        const double rate = std::pow(gap / prev_gap, 1.0 / (it - prev_iter));
+        const double need = std::log(hctrl->tol / gap) / std::log(rate);
+        k = static_cast<int>(std::clamp(std::ceil(need), 1.0, 64.0));
+      } else {
+        k = std::min(2 * k, 64);
+      }
+      prev_gap = gap;
+      prev_iter = it;
+    }
+  }
+}
+
+struct Timer {
+  hipEvent_t a = nullptr, b = nullptr;
+  ~Timer() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+};
+
+}  // namespace
+
+psi_status solve(psi_operator* op, const psi_params* prm, const double* s0, double* psi_out,
+                 double* s_out, psi_info* info, hipStream_t st) {
+  PSI_REQUIRE(prm, "params must not be NULL");
+  PSI_REQUIRE(psi_out, "psi_out must not be NULL");
+  PSI_REQUIRE(prm->tol > 0.0 && std::isfinite(prm->tol), "tol must be finite and > 0");
+  PSI_REQUIRE(prm->max_iter > 0, "max_iter must be > 0");
+  PSI_REQUIRE(prm->tol_mode >= PSI_TOL_ABS_L1 && prm->tol_mode <= PSI_TOL_REL_L1,
+              "unknown tol_mode");
+  PSI_REQUIRE(prm->precision >= PSI_PREC_FP64 && prm->precision <= PSI_PREC_FP32,
+              "unknown precision");
+  PSI_REQUIRE(prm->check_every >= 0, "check_every must be >= 0");
+  PSI_REQUIRE(prm->precision != PSI_PREC_FP64_WEIGHTED || op->val64,
+              "PSI_PREC_FP64_WEIGHTED needs an operator built with PSI_WEIGHTED_FP64");
+  PSI_REQUIRE(op->n_graphs == 1, "multi-graph operators are solved by psi_solve_batched");
+  const int tile = prm->tile_items ? prm->tile_items : (op->sched_items ? op->sched_items
+                                                                        : kDefaultTileItems);
+  PSI_REQUIRE(tile_items_supported(tile), "unsupported tile_items");
+  psi_status s = ensure_schedule(op, tile, st);
+  if (s != PSI_OK) return s;
+
+  const int64_t n = op->n;
+  const double bnorm = op->stats.b_norm;
+  const double kap = op->stats.kappa;
+  Timer tm;
+  PSI_HIP_CHECK(hipEventCreate(&tm.a));
+  PSI_HIP_CHECK(hipEventCreate(&tm.b));
+  PSI_HIP_CHECK(hipEventRecord(tm.a, st));
+
+  PassArgs base = base_args(op);
+  psi_info inf{};
+  inf.b_norm = bnorm;
+  inf.kappa = kap;
+  inf.used_s0 = s0 ? 1 : 0;
+
+  // optional start: keep s0 only if its fixed-point residual beats c's
+  if (s0 && !(prm->flags & PSI_NO_FALLBACK)) {
+    for (int which = 0; which < 2; ++which) {
+      hipLaunchKernelGGL(k_init64, dim3(grid_for(n)), dim3(kBlock), 0, st, which ? s0 : nullptr,
+                         op->c, op->invden, n, op->s_a, op->z_a);
+      PassArgs a = base;
+      a.x = op->z_a;
+      a.s_old = op->s_a;
+      a.s_new = op->s_b;
+      a.z_new = op->z_b;
+      a.gap_out = op->scal + which;
+      a.count_iter = 0;
+      a.respect_done = 0;
+      a.ctrl = op->ctrl + 1;
+      s = launch_pass(op, kStep64, a, st);
+      if (s != PSI_OK) return s;
+      inf.spmv_passes += 1;
+    }
+    double r[2];
+    PSI_HIP_CHECK(hipMemcpyAsync(r, op->scal, sizeof(r), hipMemcpyDeviceToHost, st));
+    PSI_HIP_CHECK(hipStreamSynchronize(st));
+    if (!(r[1] <= r[0])) {
+      s0 = nullptr;
+      inf.used_s0 = 0;
+    }
+  }
+
+  double* s_fin = nullptr;
+  double* z_fin = nullptr;
+  int status = PSI_OK;
+  double last_l1 = 0.0;
+  const int prec = prm->precision;
+
+  auto plain64 = [&](double* sa, double* za, double* sb, double* zb, int max_iter,
+                     IterResult* res) -> psi_status {
+    const PassMode mode = prec == PSI_PREC_FP64_WEIGHTED ? kStep64W : kStep64;
+    auto make = [&](int i) {
+      PassArgs a = base;
+      const bool even = (i & 1) == 0;
+      a.x = mode == kStep64W ? static_cast<const void*>(even ? sa : sb)
+                             : static_cast<const void*>(even ? za : zb);
+      a.s_old = even ? sa : sb;
+      a.s_new = even ? sb : sa;
+      a.z_new = even ? zb : za;
+      a.count_iter = 1;
+      a.respect_done = 1;
+      a.ctrl = op->ctrl;
+      return a;
+    };
+    return iterate(op, 0, mode, make, max_iter, prm->check_every, st, res);
+  };
+
+  if (prec == PSI_PREC_FP64 || prec == PSI_PREC_FP64_WEIGHTED) {
+    hipLaunchKernelGGL(k_init64, dim3(grid_for(n)), dim3(kBlock), 0, st, s0, op->c, op->invden,
+                       n, op->s_a, op->z_a);
+    hipLaunchKernelGGL(k_ctrl_set, dim3(1), dim3(1), 0, st, op->ctrl, prm->tol, prm->tol_mode,
+                       prm->max_iter, bnorm);
+    IterResult res;
+    s = plain64(op->s_a, op->z_a, op->s_b, op->z_b, prm->max_iter, &res);
+    if (s != PSI_OK) return s;
+    inf.iterations = res.iters;
+    inf.spmv_passes += res.iters;
+    status = res.status;
+    inf.final_gap = res.gap;
+    last_l1 = res.l1;
+    const bool odd = res.iters & 1;
+    s_fin = odd ? op->s_b : op->s_a;
+    z_fin = odd ? op->z_b : op->z_a;
+    if (prec == PSI_PREC_FP64_WEIGHTED) {
+      hipLaunchKernelGGL(k_make_z, dim3(grid_for(n)), dim3(kBlock), 0, st, s_fin, op->invden, n,
+                         z_fin);
+    }
+  } else if (prec == PSI_PREC_FP32) {
+    hipLaunchKernelGGL(k_init32, dim3(grid_for(n)), dim3(kBlock), 0, st, s0, op->c, op->invden32,
+                       n, op->e_a, op->ze_a);
+    hipLaunchKernelGGL(k_ctrl_set, dim3(1), dim3(1), 0, st, op->ctrl, prm->tol, prm->tol_mode,
+                       prm->max_iter, bnorm);
+    auto make = [&](int i) {
+      PassArgs a = base;
+      const bool even = (i & 1) == 0;
+      a.x = even ? op->ze_a : op->ze_b;
+      a.r32 = op->c32;
+      a.e_old = even ? op->e_a : op->e_b;
+      a.e_new = even ? op->e_b : op->e_a;
+      a.ze_new = even ? op->ze_b : op->ze_a;
+      a.count_iter = 1;
+      a.respect_done = 1;
+      a.ctrl = op->ctrl;
+      return a;
+    };
+    IterResult res;
+    s = iterate(op, 0, kStep32, make, prm->max_iter, prm->check_every, st, &res);
+    if (s != PSI_OK) return s;
+    inf.iterations = res.iters;
+    inf.fp32_passes = res.iters;
+    inf.spmv_passes += res.iters;
+    status = res.status;
+    inf.final_gap = res.gap;
+    last_l1 = res.l1;
+    const float* e_fin = (res.iters & 1) ? op->e_b : op->e_a;
+    hipLaunchKernelGGL(k_e_to_s, dim3(grid_for(n)), dim3(kBlock), 0, st, e_fin, op->invden, n,
+                       op->s_a, op->z_a);
+    s_fin = op->s_a;
+    z_fin = op->z_a;
+  } else {  // PSI_PREC_MIXED
+    const double eta = prm->inner_tol > 0.0 ? prm->inner_tol : 2e-6;
+    double* X = op->s_a;
+    double* zX = op->z_a;
+    double* Y = op->s_b;
+    double* zY = op->z_b;
+    hipLaunchKernelGGL(k_init64, dim3(grid_for(n)), dim3(kBlock), 0, st, s0, op->c, op->invden,
+                       n, X, zX);
+    hipLaunchKernelGGL(k_ctrl_set, dim3(1), dim3(1), 0, st, op->ctrl, prm->tol, prm->tol_mode,
+                       prm->max_iter, bnorm);
+    double prev_gap = std::numeric_limits<double>::infinity();
+    int fp64_passes = 0;
+    bool finished = false;
+    while (!finished) {
+      // FP64 residual pass: Y = Aᵀ X + c, gap = ‖Y − X‖₁ (tol_mode units)
+      PassArgs a = base;
+      a.x = zX;
+      a.s_old = X;
+      a.s_new = Y;
+      a.z_new = zY;
+      a.count_iter = 1;
+      a.respect_done = 0;
+      a.ctrl = op->ctrl;
+      s = launch_pass(op, kStep64, a, st);
+      if (s != PSI_OK) return s;
+      ++fp64_passes;
+      Ctrl* h = op->host_ctrl;
+      PSI_HIP_CHECK(hipMemcpyAsync(h, op->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+      PSI_HIP_CHECK(hipStreamSynchronize(st));
+      inf.final_gap = h->gap;
+      last_l1 = h->l1;
+      s_fin = Y;
+      z_fin = zY;
+      if (h->done) {
+        status = h->status;
+        break;
+      }
+      if (!(h->gap < 0.25 * prev_gap)) {
+        // refinement no longer gains: finish with plain FP64 steps from Y
+        const int before = h->iter;
+        IterResult res;
+        s = plain64(Y, zY, X, zX, prm->max_iter - fp64_passes, &res);
+        if (s != PSI_OK) return s;
+        fp64_passes = res.iters;  // ctrl->iter kept counting from the refinement passes
+        status = res.status;
+        inf.final_gap = res.gap;
+        last_l1 = res.l1;
+        const int extra = res.iters - before;
+        const bool odd = extra & 1;
+        s_fin = odd ? X : Y;
+        z_fin = odd ? zX : zY;
+        break;
+      }
+      prev_gap = h->gap;
+      // FP32 correction solve e = Aᵀe + r
+      hipLaunchKernelGGL(k_prep_inner, dim3(grid_for(n)), dim3(kBlock), 0, st, Y, X,
+                         op->invden32, n, op->r32, op->e_a, op->ze_a);
+      hipLaunchKernelGGL(k_ctrl_inner, dim3(1), dim3(1), 0, st, op->ctrl, op->ctrl + 1, eta,
+                         prm->max_iter);
+      auto make = [&](int i) {
+        PassArgs b = base;
+        const bool even = (i & 1) == 0;
+        b.x = even ? op->ze_a : op->ze_b;
+        b.r32 = op->r32;
+        b.e_old = even ? op->e_a : op->e_b;
+        b.e_new = even ? op->e_b : op->e_a;
+        b.ze_new = even ? op->ze_b : op->ze_a;
+        b.count_iter = 1;
+        b.respect_done = 1;
+        b.ctrl = op->ctrl + 1;
+        return b;
+      };
+      IterResult res;
+      s = iterate(op, 1, kStep32, make, prm->max_iter, prm->check_every, st, &res);
+      if (s != PSI_OK) return s;
+      inf.fp32_passes += res.iters;
+      if (res.status == PSI_ENUMERIC) {
+        status = PSI_ENUMERIC;
+        break;
+      }
+      const float* e_fin = (res.iters & 1) ? op->e_b : op->e_a;
+      hipLaunchKernelGGL(k_update, dim3(grid_for(n)), dim3(kBlock), 0, st, X, e_fin, op->invden,
+                         n, zX);
+      inf.refinements += 1;
+      if (fp64_passes >= prm->max_iter) {
+        status = PSI_ENOTCONV;
+        break;
+      }
+    }
+    inf.iterations = fp64_passes;
+    inf.spmv_passes += fp64_passes + inf.fp32_passes;
+  }
+
+  // ψ = (Bᵀs + d)/N from the final s (the last line of Algorithm 2)
+  {
+    PassArgs a = base;
+    a.x = z_fin;
+    a.s_new = psi_out;
+    a.count_iter = 0;
+    a.respect_done = 0;
+    s = launch_pass(op, kFinal64, a, st);
+    if (s != PSI_OK) return s;
+    inf.spmv_passes += 1;
+  }
+  if (s_out) PSI_HIP_CHECK(hipMemcpyAsync(s_out, s_fin, 8 * size_t(n), hipMemcpyDeviceToDevice, st));
+  PSI_HIP_CHECK(hipEventRecord(tm.b, st));
+  PSI_HIP_CHECK(hipEventSynchronize(tm.b));
+  float ms = 0.f;
+  PSI_HIP_CHECK(hipEventElapsedTime(&ms, tm.a, tm.b));
+  inf.device_ms = ms;
+  inf.final_l1_step = last_l1;
+  inf.err_bound_s = kap < 1.0 ? kap / (1.0 - kap) * last_l1 : std::numeric_limits<double>::infinity();
+  inf.psi_gap_bound = n > 0 ? last_l1 * bnorm / static_cast<double>(n) : 0.0;
+  inf.status = status;
+  if (info) *info = inf;
+  if (status == PSI_ENOTCONV) set_error("max_iter reached before the gap fell to tol");
+  else if (status == PSI_ESTAGNATED) set_error("the gap stopped decreasing above tol");
+  else if (status == PSI_ENUMERIC) set_error("NaN or Inf in the iteration");
+  return static_cast<psi_status>(status);
+}
+
+psi_status step(psi_operator* op, int precision, const double* s_in, double* s_out,
+                double* gap_out, int tile_items, hipStream_t st) {
+  PSI_REQUIRE(s_in && s_out && s_in != s_out, "s_in and s_out must be distinct device arrays");
+  PSI_REQUIRE(precision == PSI_PREC_FP64 || precision == PSI_PREC_FP64_WEIGHTED,
+              "psi_step supports PSI_PREC_FP64 and PSI_PREC_FP64_WEIGHTED");
+  PSI_REQUIRE(precision != PSI_PREC_FP64_WEIGHTED || op->val64,
+              "weighted step needs an operator built with PSI_WEIGHTED_FP64");
+  const int tile = tile_items ? tile_items : (op->sched_items ? op->sched_items : kDefaultTileItems);
+  PSI_REQUIRE(tile_items_supported(tile), "unsupported tile_items");
+  psi_status s = ensure_schedule(op, tile, st);
+  if (s != PSI_OK) return s;
+  PassArgs a = base_args(op);
+  a.s_old = s_in;
+  a.s_new = s_out;
+  a.z_new = op->z_b;
+  a.gap_out = gap_out;
+  a.count_iter = 0;
+  a.respect_done = 0;
+  a.ctrl = op->ctrl + 1;
+  if (precision == PSI_PREC_FP64) {
+    hipLaunchKernelGGL(k_make_z, dim3(grid_for(op->n)), dim3(kBlock), 0, st, s_in, op->invden,
+                       op->n, op->z_a);
+    a.x = op->z_a;
+    return launch_pass(op, kStep64, a, st);
+  }
+  a.x = s_in;
+  return launch_pass(op, kStep64W, a, st);
+}
+
+psi_status final_psi(psi_operator* op, const double* s_vec, double* psi_out, hipStream_t st) {
+  PSI_REQUIRE(s_vec && psi_out, "s and psi_out must not be NULL");
+  psi_status s = ensure_schedule(op, op->sched_items ? op->sched_items : kDefaultTileItems, st);
+  if (s != PSI_OK) return s;
+  hipLaunchKernelGGL(k_make_z, dim3(grid_for(op->n)), dim3(kBlock), 0, st, s_vec, op->invden,
+                     op->n, op->z_a);
+  PassArgs a = base_args(op);
+  a.x = op->z_a;
+  a.s_new = psi_out;
+  return launch_pass(op, kFinal64, a, st);
+}
+
+psi_status pass_time(psi_operator* op, int kind, int reps, int tile_items, double* mean_ms,
+                     hipStream_t st) {
+  PSI_REQUIRE(mean_ms, "mean_ms must not be NULL");
+  PSI_REQUIRE(reps >= 1, "reps must be >= 1");
+  PSI_REQUIRE(kind >= PSI_PASS_STEP64 && kind <= PSI_PASS_STEP32, "unknown pass kind");
+  PSI_REQUIRE(kind != PSI_PASS_STEP64_W || op->val64,
+              "the weighted pass needs an operator built with PSI_WEIGHTED_FP64");
+  const int tile = tile_items ? tile_items : (op->sched_items ? op->sched_items : kDefaultTileItems);
+  PSI_REQUIRE(tile_items_supported(tile), "unsupported tile_items");
+  psi_status s = ensure_schedule(op, tile, st);
+  if (s != PSI_OK) return s;
+  const int64_t n = op->n;
+  hipLaunchKernelGGL(k_init64, dim3(grid_for(n)), dim3(kBlock), 0, st, nullptr, op->c, op->invden,
+                     n, op->s_a, op->z_a);
+  hipLaunchKernelGGL(k_init32, dim3(grid_for(n)), dim3(kBlock), 0, st, nullptr, op->c,
+                     op->invden32, n, op->e_a, op->ze_a);
+  PassArgs base = base_args(op);
+  base.count_iter = 0;
+  base.respect_done = 0;
+  base.ctrl = op->ctrl + 1;
+  base.r32 = op->c32;
+  PassMode mode = kind == PSI_PASS_STEP64 ? kStep64
+                : kind == PSI_PASS_STEP64_W ? kStep64W
+                : kind == PSI_PASS_FINAL64 ? kFinal64 : kStep32;
+  auto make = [&](int i) {
+    PassArgs a = base;
+    const bool even = (i & 1) == 0;
+    if (mode == kStep32) {
+      a.x = even ? op->ze_a : op->ze_b;
+      a.e_old = even ? op->e_a : op->e_b;
+      a.e_new = even ? op->e_b : op->e_a;
+      a.ze_new = even ? op->ze_b : op->ze_a;
+    } else if (mode == kFinal64) {
+      a.x = op->z_a;
+      a.s_new = op->s_b;
+    } else {
+      a.x = mode == kStep64W ? static_cast<const void*>(even ? op->s_a : op->s_b)
+                             : static_cast<const void*>(even ? op->z_a : op->z_b);
+      a.s_old = even ? op->s_a : op->s_b;
+      a.s_new = even ? op->s_b : op->s_a;
+      a.z_new = even ? op->z_b : op->z_a;
+    }
+    return a;
+  };
+  s = launch_pass(op, mode, make(0), st);
+  if (s != PSI_OK) return s;
+  Timer tm;
+  PSI_HIP_CHECK(hipEventCreate(&tm.a));
+  PSI_HIP_CHECK(hipEventCreate(&tm.b));
+  PSI_HIP_CHECK(hipEventRecord(tm.a, st));
+  for (int i = 1; i <= reps; ++i) {
+    s = launch_pass(op, mode, make(i), st);
+    if (s != PSI_OK) return s;
+  }
+  PSI_HIP_CHECK(hipEventRecord(tm.b, st));
+  PSI_HIP_CHECK(hipEventSynchronize(tm.b));
+  float ms = 0.f;
+  PSI_HIP_CHECK(hipEventElapsedTime(&ms, tm.a, tm.b));
+  *mean_ms = static_cast<double>(ms) / reps;
+  return PSI_OK;
+}
+
+}  // namespace psi

@@ -1,0 +1,82 @@
+"""The C-ABI library loads and exports every symbol include/psi.h declares
+(no compute calls: these run without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADERS = [os.path.join(ROOT, "include", h) for h in sorted(os.listdir(os.path.join(ROOT, "include")))
+           if h.endswith(".h")]
+
+
+def declared_functions():
+    names = []
+    for h in HEADERS:
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names += re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(psi_[a-z0-9_]+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2206_09960_amd import _ffi
+    if not os.path.exists(_ffi.LIB_PATH):
+        from paper_2206_09960_amd import build
+        build.build()
+    return _ffi.load()
+
+
+def test_header_declares_entry_points():
+    names = declared_functions()
+    for required in ("psi_build_operator", "psi_solve", "psi_step", "psi_final",
+                     "psi_operator_workspace_size", "psi_last_error"):
+        assert required in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_binding_covers_header(lib):
+    from paper_2206_09960_amd import _ffi
+    bound = {s[0] for s in _ffi.SIGNATURES}
+    assert set(declared_functions()) <= bound
+
+
+def test_host_only_calls(lib):
+    from paper_2206_09960_amd import _ffi
+    assert lib.psi_version().decode().startswith("psi-mi355x")
+    p = _ffi.Params()
+    assert lib.psi_params_default(ctypes.byref(p)) == 0
+    assert p.tol == 1e-8 and p.max_iter == 10000
+    a, b = ctypes.c_size_t(), ctypes.c_size_t()
+    assert lib.psi_operator_workspace_size(1000, 10000, 1, 0, ctypes.byref(a), ctypes.byref(b)) == 0
+    assert a.value > 1000 * 8 and b.value > 10000 * 16
+    assert lib.psi_operator_workspace_size(0, 10, 1, 0, ctypes.byref(a), ctypes.byref(b)) == 1
+    assert b"n_users" in lib.psi_last_error()
+
+
+def test_struct_sizes_match_header():
+    """Compile a tiny C program against the header and compare struct sizes."""
+    import subprocess
+    import tempfile
+    from paper_2206_09960_amd import _ffi
+    src = r'''
+#include <stdio.h>
+#include "psi.h"
+int main(void){printf("%zu %zu %zu\n", sizeof(psi_operator_stats), sizeof(psi_params), sizeof(psi_info));return 0;}
+'''
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "t.c")
+        open(c, "w").write(src)
+        exe = os.path.join(d, "t")
+        r = subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-I", "/opt/rocm/include",
+                            c, "-o", exe], capture_output=True, text=True)
+        assert r.returncode == 0, r.stderr
+        out = subprocess.run([exe], capture_output=True, text=True).stdout.split()
+    assert [int(x) for x in out] == [ctypes.sizeof(_ffi.OperatorStats), ctypes.sizeof(_ffi.Params),
+                                     ctypes.sizeof(_ffi.Info)]

@@ -1,0 +1,326 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Tolerances: FP64 solves match the oracle's Algorithm 2 at the same tolerance
+within 1e-9 relative L1; mixed precision (FP32 corrections + FP64 residual)
+within 1e-9; FP32-only within 1e-6.  Index work (CSR structure, clean-up
+counts) is compared exactly.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def oracle_run(g, tol, tol_mode="abs_l1"):
+    A, B, c, d = oracle.operator(g.n, g.follower, g.leader, g.lam, g.mu)
+    r = oracle.power_psi(A, B, c, d, tol, tol_mode=tol_mode)
+    return A, B, c, d, r
+
+
+def gpu_op(api, g, flags=0):
+    return api.Operator(g.n, g.follower, g.leader, g.lam, g.mu, flags=flags)
+
+
+# ---------------------------------------------------------------- worked example
+def test_two_user_bit_exact(gpu_lib):
+    api = gpu_lib
+    with open(os.path.join(GOLDEN, "two_user.json")) as fh:
+        gd = json.load(fh)
+    f = np.array(gd["follower"], dtype=np.int32)
+    l = np.array(gd["leader"], dtype=np.int32)
+    op = api.Operator(2, f, l, np.array(gd["lambda"]), np.array(gd["mu"]))
+    st = op.stats()
+    assert st["b_norm"] == gd["b_norm"] and st["kappa"] == gd["kappa"]
+    v = op.views()
+    assert v["c"].cpu().tolist() == gd["c"] and v["d"].cpu().tolist() == gd["d"]
+    for t in range(1, len(gd["iterates"])):
+        s_in = torch.tensor(gd["iterates"][t - 1], dtype=torch.float64, device="cuda")
+        s_out, gap = op.step(s_in)
+        torch.cuda.synchronize()
+        assert s_out.cpu().tolist() == gd["iterates"][t]
+        assert gap.item() == gd["gaps"][t - 1]
+    psi, s, info = op.solve(tol=1e-15, return_s=True)
+    np.testing.assert_allclose(psi.cpu().numpy(), gd["psi"], rtol=0, atol=1e-15)
+    np.testing.assert_allclose(s.cpu().numpy(), gd["s_fixed_point"], rtol=0, atol=1e-14)
+    assert info["status"] == 0
+    psi3, info3 = op.solve(tol=0.3)  # three steps, dyadic iterate
+    assert info3["iterations"] == 3
+    s3 = np.array(gd["iterates"][3])
+    B = np.array([[0, 0.25], [0.5, 0]])
+    expect = (s3 @ B + np.array(gd["d"])) / 2
+    assert psi3.cpu().tolist() == expect.tolist()
+
+
+# ---------------------------------------------------------------- operator build
+@pytest.mark.parametrize("case", ["random_small", "chung_lu_20k", "star", "cycle"])
+def test_operator_structure(gpu_lib, case):
+    api = gpu_lib
+    if case == "random_small":
+        g = synth.random_small(150, 0.05, 3, dangling=True, extra_self_loops=7, extra_duplicates=11)
+    elif case == "chung_lu_20k":
+        g = synth.chung_lu(20000, 12, 2.2, 9, sigma=1.5)
+    elif case == "star":
+        g = synth.star(5000, 2)
+    else:
+        g = synth.cycle(777)
+    op = gpu_op(api, g)
+    st = op.stats()
+    f, l, loops, dups = oracle.clean_edges(g.n, g.follower, g.leader)
+    assert st["n_edges"] == f.size and st["n_self_loops"] == loops and st["n_duplicates"] == dups
+    A, B, c, d = oracle.operator(g.n, g.follower, g.leader, g.lam, g.mu)
+    AT = A.T.tocsr()
+    AT.sort_indices()
+    v = op.views()
+    assert np.array_equal(v["row_ptr"].cpu().numpy(), AT.indptr)
+    assert np.array_equal(v["col"].cpu().numpy(), AT.indices)
+    assert np.array_equal(v["c"].cpu().numpy(), c)
+    assert np.array_equal(v["d"].cpu().numpy(), d)
+    den = np.zeros(g.n)
+    np.add.at(den, f, g.lam[l] + g.mu[l])
+    inv = np.where(den > 0, 1.0 / np.where(den > 0, den, 1.0), 0.0)
+    np.testing.assert_allclose(v["inv_den"].cpu().numpy(), inv, rtol=1e-15, atol=0)
+    assert abs(st["b_norm"] - oracle.b_norm(B)) <= 1e-15 * oracle.b_norm(B)
+    assert abs(st["kappa"] - oracle.kappa(A)) <= 1e-15 * oracle.kappa(A)
+    assert st["n_no_leaders"] == int((np.bincount(f, minlength=g.n) == 0).sum())
+    assert st["max_followers"] == int(np.diff(AT.indptr).max())
+
+
+def test_strict_and_invalid_inputs(gpu_lib):
+    api = gpu_lib
+    g = synth.random_small(40, 0.1, 5, extra_self_loops=2)
+    with pytest.raises(api.PsiError, match="PSI_EINVAL"):
+        api.Operator(g.n, g.follower, g.leader, g.lam, g.mu, flags=api.PSI_STRICT)
+    bad = g.leader.copy()
+    bad[3] = g.n
+    with pytest.raises(api.PsiError, match="outside"):
+        api.Operator(g.n, g.follower, bad, g.lam, g.mu)
+    lam = g.lam.copy()
+    lam[7] = 0.0
+    with pytest.raises(api.PsiError, match="activity"):
+        api.Operator(g.n, g.follower, g.leader, lam, g.mu)
+    mu = g.mu.copy()
+    mu[1] = np.nan
+    with pytest.raises(api.PsiError, match="activity"):
+        api.Operator(g.n, g.follower, g.leader, g.lam, mu)
+    op = gpu_op(api, g)
+    with pytest.raises(api.PsiError, match="tol"):
+        op.solve(tol=0.0)
+    with pytest.raises(api.PsiError, match="tile"):
+        op.solve(tile_items=1000)
+
+
+# ---------------------------------------------------------------- one step
+@pytest.mark.parametrize("tile", [1024, 1536, 2048, 3072, 4096])
+def test_step_matches_oracle(gpu_lib, tile):
+    api = gpu_lib
+    g = synth.chung_lu(30000, 15, 2.1, 11, sigma=2.0)
+    op = gpu_op(api, g, flags=api.PSI_WEIGHTED_FP64)
+    A, B, c, d = oracle.operator(g.n, g.follower, g.leader, g.lam, g.mu)
+    s_in = np.random.default_rng(1).uniform(0.5, 3.0, g.n)
+    expect = A.T @ s_in + c
+    for prec in ("fp64", "fp64_weighted"):
+        out, gap = op.step(torch.tensor(s_in, device="cuda"), precision=prec, tile_items=tile)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        np.testing.assert_allclose(got, expect, rtol=1e-13, atol=0)
+        assert abs(gap.item() - np.abs(expect - s_in).sum()) <= 1e-12 * np.abs(expect - s_in).sum()
+    psi = op.final(torch.tensor(s_in, device="cuda")).cpu().numpy()
+    np.testing.assert_allclose(psi, (B.T @ s_in + d) / g.n, rtol=1e-13, atol=0)
+
+
+def test_step_bitwise_repeatable(gpu_lib):
+    api = gpu_lib
+    g = synth.chung_lu(200000, 20, 2.1, 12, sigma=2.0)
+    op = gpu_op(api, g)
+    s_in = torch.rand(g.n, dtype=torch.float64, device="cuda") + 0.5
+    ref, gref = op.step(s_in)
+    for _ in range(5):
+        out, gap = op.step(s_in)
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref) and torch.equal(gap, gref)
+
+
+# ---------------------------------------------------------------- full solves
+SOLVE_CASES = [
+    ("random_dangling", lambda: synth.random_small(200, 0.02, 21, dangling=True), 1e-12),
+    ("random_closed", lambda: synth.random_small(180, 0.03, 22, dangling=False), 1e-12),
+    ("cl_1k", lambda: synth.workload("cl_1k"), 1e-10),
+    ("cl_50k_g2.1", lambda: synth.chung_lu(50000, 20, 2.1, 23, sigma=2.0), 1e-8),
+    ("star_300k", lambda: synth.star(300001, 24), 1e-10),
+    ("uniform_act", lambda: synth.chung_lu(20000, 8, 2.5, 25, activity_kind="uniform"), 1e-9),
+]
+
+
+@pytest.mark.parametrize("name,make,tol", SOLVE_CASES, ids=[c[0] for c in SOLVE_CASES])
+def test_solve_fp64_matches_oracle(gpu_lib, name, make, tol):
+    api = gpu_lib
+    g = make()
+    A, B, c, d, r = oracle_run(g, tol)
+    op = gpu_op(api, g)
+    psi, s, info = op.solve(tol=tol, return_s=True)
+    psi = psi.cpu().numpy()
+    assert info["status"] == 0, info
+    assert abs(info["iterations"] - r["iterations"]) <= 1
+    assert oracle.rel_l1(r["psi"], psi) <= 1e-9
+    assert oracle.rel_l1(r["s"], s.cpu().numpy()) <= 1e-9
+    s_np = s.cpu().numpy()
+    # the CPU's own evaluation of the residual rounds at about eps·Σ|s|
+    assert oracle.fixed_point_residual(A, c, s_np) <= tol * 1.5 + 1e-15 * np.abs(s_np).sum()
+
+
+def test_star_hub_closed_form(gpu_lib):
+    """One 3M-long row: ψ_h = d_h(1 + Σ_{j≠h} c_j)/N, ψ_j = d_j/N."""
+    api = gpu_lib
+    g = synth.star(3_000_001, 26)
+    op = gpu_op(api, g)
+    psi, info = op.solve(tol=1e-10)
+    psi = psi.cpu().numpy()
+    c = g.mu / (g.lam + g.mu)
+    d = g.lam / (g.lam + g.mu)
+    expect = d / g.n
+    expect[0] = d[0] * (1.0 + np.sort(c[1:]).sum()) / g.n
+    np.testing.assert_allclose(psi, expect, rtol=1e-12, atol=0)
+
+
+def test_solve_repeatable_and_tile_independent(gpu_lib):
+    api = gpu_lib
+    g = synth.chung_lu(100000, 20, 2.2, 27, sigma=1.5)
+    op = gpu_op(api, g)
+    ref, info = op.solve(tol=1e-8)
+    for _ in range(3):
+        again, info2 = op.solve(tol=1e-8)
+        assert torch.equal(again, ref) and info2["iterations"] == info["iterations"]
+    for tile in (1024, 3072, 4096):
+        other, _ = op.solve(tol=1e-8, tile_items=tile)
+        assert oracle.rel_l1(ref.cpu().numpy(), other.cpu().numpy()) <= 1e-12
+
+
+@pytest.mark.parametrize("mode", ["bnorm", "rel_l1"])
+def test_tol_modes(gpu_lib, mode):
+    api = gpu_lib
+    g = synth.chung_lu(5000, 10, 2.2, 28, sigma=1.0)
+    tol = 1e-9 if mode == "bnorm" else 1e-13
+    A, B, c, d, r = oracle_run(g, tol, tol_mode=mode)
+    op = gpu_op(api, g)
+    psi, info = op.solve(tol=tol, tol_mode=mode)
+    assert abs(info["iterations"] - r["iterations"]) <= 1
+    assert oracle.rel_l1(r["psi"], psi.cpu().numpy()) <= 1e-9
+
+
+def test_weighted_form(gpu_lib):
+    api = gpu_lib
+    g = synth.chung_lu(40000, 15, 2.2, 29, sigma=1.5)
+    A, B, c, d, r = oracle_run(g, 1e-9)
+    op = gpu_op(api, g, flags=api.PSI_WEIGHTED_FP64)
+    psi, info = op.solve(tol=1e-9, precision="fp64_weighted")
+    assert info["status"] == 0
+    assert oracle.rel_l1(r["psi"], psi.cpu().numpy()) <= 1e-9
+
+
+def test_mixed_and_fp32(gpu_lib):
+    api = gpu_lib
+    g = synth.chung_lu(100000, 20, 2.2, 30, sigma=1.5)
+    A, B, c, d, r = oracle_run(g, 1e-8)
+    op = gpu_op(api, g)
+    psi_m, s_m, info_m = op.solve(tol=1e-8, precision="mixed", return_s=True)
+    assert info_m["status"] == 0, info_m
+    assert info_m["fp32_passes"] > 0 and info_m["refinements"] >= 1
+    assert oracle.rel_l1(r["psi"], psi_m.cpu().numpy()) <= 1e-9
+    s_np = s_m.cpu().numpy()
+    assert oracle.fixed_point_residual(A, c, s_np) <= 1.5e-8 + 1e-15 * np.abs(s_np).sum()
+    psi_f, info_f = op.solve(tol=1e-4, precision="fp32")
+    err = oracle.rel_l1(r["psi"], psi_f.cpu().numpy())
+    assert err <= 1e-6, err
+
+
+def test_edge_cases(gpu_lib):
+    api = gpu_lib
+    # no edges at all: s = c, ψ = d/N
+    n = 7
+    lam = np.linspace(0.5, 2.0, n)
+    mu = np.linspace(1.0, 0.2, n)
+    e = np.zeros(0, dtype=np.int32)
+    op = api.Operator(n, e, e, lam, mu)
+    psi, info = op.solve(tol=1e-12)
+    np.testing.assert_allclose(psi.cpu().numpy(), lam / (lam + mu) / n, rtol=1e-15)
+    # only self-loops and repeats
+    f = np.array([0, 1, 1, 1, 2], dtype=np.int32)
+    l = np.array([0, 2, 2, 2, 2], dtype=np.int32)
+    op = api.Operator(3, f, l, lam[:3], mu[:3])
+    st = op.stats()
+    assert (st["n_edges"], st["n_self_loops"], st["n_duplicates"]) == (1, 2, 2)
+    A, B, c, d = oracle.operator(3, f, l, lam[:3], mu[:3])
+    psi, info = op.solve(tol=1e-14)
+    np.testing.assert_allclose(psi.cpu().numpy(), oracle.psi_closed_form(A, B, c, d)[0],
+                               rtol=1e-14)
+    # μ = 0 for some users is allowed
+    g = synth.chung_lu(3000, 10, 2.2, 31)
+    mu0 = g.mu.copy()
+    mu0[::3] = 0.0
+    g0 = synth.Graph(g.n, g.follower, g.leader, g.lam, mu0)
+    A, B, c, d, r = oracle_run(g0, 1e-10)
+    psi, info = gpu_op(api, g0).solve(tol=1e-10)
+    assert oracle.rel_l1(r["psi"], psi.cpu().numpy()) <= 1e-9
+
+
+def test_termination_statuses(gpu_lib):
+    api = gpu_lib
+    g = synth.chung_lu(20000, 10, 2.2, 32)
+    op = gpu_op(api, g)
+    psi, info = op.solve(tol=1e-12, max_iter=3)
+    assert info["status_name"] == "PSI_ENOTCONV" and info["iterations"] == 3
+    with pytest.raises(api.PsiError, match="ENOTCONV"):
+        op.solve(tol=1e-12, max_iter=2, raise_on_status=True)
+    # the deterministic FP32 map either lands on an exact FP32 fixed point (gap 0)
+    # or stops improving; both keep ψ within the FP32 bound
+    A, B, c, d, r = oracle_run(g, 1e-12)
+    psi, info = op.solve(tol=1e-14, precision="fp32")
+    assert info["status_name"] in ("PSI_OK", "PSI_ESTAGNATED")
+    assert oracle.rel_l1(r["psi"], psi.cpu().numpy()) <= 1e-6
+
+
+def test_warm_start_and_fallback(gpu_lib):
+    api = gpu_lib
+    g = synth.chung_lu(50000, 20, 2.2, 33, sigma=1.5)
+    op = gpu_op(api, g)
+    ref, s_ref, info_cold = op.solve(tol=1e-8, return_s=True)
+    # start from a nearly converged iterate: few iterations, same ψ
+    # (the error contracts geometrically, so the saving is the log of the start's error)
+    for rel, most in ((1e-6, 0.75 * info_cold["iterations"]), (1e-12, 6)):
+        psi, info = op.solve(tol=1e-8, s0=s_ref * (1 + rel))
+        assert info["used_s0"] == 1 and info["iterations"] <= most, (rel, info)
+        assert oracle.rel_l1(ref.cpu().numpy(), psi.cpu().numpy()) <= 1e-9
+    # a garbage start is rejected for c
+    bad = torch.full_like(s_ref, 1e6)
+    psi, info = op.solve(tol=1e-8, s0=bad)
+    assert info["used_s0"] == 0
+    assert oracle.rel_l1(ref.cpu().numpy(), psi.cpu().numpy()) <= 1e-9
+    # unless asked to keep it: still converges to the same fixed point
+    psi, info = op.solve(tol=1e-8, s0=bad, no_fallback=True)
+    assert info["used_s0"] == 1
+    assert oracle.rel_l1(ref.cpu().numpy(), psi.cpu().numpy()) <= 1e-9
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_full_size_1m(gpu_lib, prec):
+    """The measured workload (N = 1,000,000, mean degree 20, γ = 2.2, σ = 1.5,
+    tol 1e-8), element by element against the oracle."""
+    api = gpu_lib
+    g = synth.workload("cl_1m")
+    A, B, c, d, r = oracle_run(g, 1e-8)
+    op = gpu_op(api, g)
+    psi, s, info = op.solve(tol=1e-8, precision=prec, return_s=True)
+    assert info["status"] == 0, info
+    assert oracle.rel_l1(r["psi"], psi.cpu().numpy()) <= 1e-9
+    assert oracle.rel_l2(r["psi"], psi.cpu().numpy()) <= 1e-9
+    s_np = s.cpu().numpy()
+    assert oracle.fixed_point_residual(A, c, s_np) <= 1.5e-8 + 1e-15 * np.abs(s_np).sum()
