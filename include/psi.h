@@ -90,6 +90,8 @@ typedef struct psi_params {
     int32_t check_every; /* host checks the gap every k steps; 0 = adaptive    */
     uint32_t flags;      /* PSI_NO_FALLBACK                                    */
     int32_t tile_items;  /* merge-path items per tile; 0 = library default     */
+    int32_t col_segments;/* 1, 2, 4 or 8 column segments (one per XCD group);   */
+                         /* 0 = chosen from N and the precision                */
     double inner_tol;    /* PSI_PREC_MIXED: relative tol of each FP32 solve; 0 = default */
 } psi_params;
 
@@ -180,9 +182,10 @@ psi_status psi_solve(psi_operator* op, const psi_params* prm, const double* s0,
 /* One Power-ψ step (eq. power_psi), enqueued only:
  *   s_out = Aᵀ s_in + c,  *gap_out (device FP64 scalar, may be NULL)
  *   = ‖s_out − s_in‖₁.  precision PSI_PREC_FP64 or PSI_PREC_FP64_WEIGHTED.
- * s_in, s_out: device FP64 [N], distinct. */
+ * s_in, s_out: device FP64 [N], distinct.  tile_items and col_segments as in
+ * psi_params (0 = default). */
 psi_status psi_step(psi_operator* op, int32_t precision, const double* s_in, double* s_out,
-                    double* gap_out, int32_t tile_items, void* stream);
+                    double* gap_out, int32_t tile_items, int32_t col_segments, void* stream);
 
 /* The last line of Algorithm 2, enqueued only: psi_out = (Bᵀ s + d)/N.
  * s, psi_out: device FP64 [N]. */
@@ -194,12 +197,12 @@ psi_status psi_final(psi_operator* op, const double* s, double* psi_out, void* s
 #define PSI_PASS_FINAL64    2  /* ψ = (λ⊙Σ_{j∈F(i)} s_j/den_j + d)/N                 */
 #define PSI_PASS_STEP32     3  /* FP32 correction step: e' = r + μ⊙Σ e_j/den_j        */
 
-/* Time `reps` back-to-back launches of one operator pass (the kernel a solve
- * runs in its loop), between two hipEvents recorded on `stream`, after one
- * untimed launch.  Writes the mean duration of one launch in milliseconds to
+/* Time `reps` back-to-back launches of one operator pass (the kernels a solve
+ * runs in its loop: with col_segments > 1 the partial pass and the combine),
+ * between two hipEvents recorded on `stream`, after one untimed launch.  Writes the mean duration of one launch in milliseconds to
  * *mean_ms (host).  Overwrites the operator's solve state.  Blocks until done. */
 psi_status psi_pass_time(psi_operator* op, int32_t pass_kind, int32_t reps, int32_t tile_items,
-                         double* mean_ms, void* stream);
+                         int32_t col_segments, double* mean_ms, void* stream);
 
 #ifdef __cplusplus
 }

@@ -37,7 +37,8 @@ class OperatorStats(ctypes.Structure):
 
 class Params(ctypes.Structure):
     _fields_ = [("tol", f64), ("tol_mode", i32), ("max_iter", i32), ("precision", i32),
-                ("check_every", i32), ("flags", u32), ("tile_items", i32), ("inner_tol", f64)]
+                ("check_every", i32), ("flags", u32), ("tile_items", i32), ("col_segments", i32),
+                ("inner_tol", f64)]
 
 
 class Info(ctypes.Structure):
@@ -64,9 +65,9 @@ SIGNATURES = [
                                  ctypes.POINTER(vp), ctypes.POINTER(vp)]),
     ("psi_params_default", i32, [ctypes.POINTER(Params)]),
     ("psi_solve", i32, [vp, ctypes.POINTER(Params), vp, vp, vp, ctypes.POINTER(Info), vp]),
-    ("psi_step", i32, [vp, i32, vp, vp, vp, i32, vp]),
+    ("psi_step", i32, [vp, i32, vp, vp, vp, i32, i32, vp]),
     ("psi_final", i32, [vp, vp, vp, vp]),
-    ("psi_pass_time", i32, [vp, i32, i32, i32, ctypes.POINTER(f64), vp]),
+    ("psi_pass_time", i32, [vp, i32, i32, i32, i32, ctypes.POINTER(f64), vp]),
 ]
 
 _lib = None

@@ -146,7 +146,8 @@ class Operator:
     # ------------------------------------------------------------------ compute
     def solve(self, tol: float = 1e-8, tol_mode: str = "abs_l1", max_iter: int = 10000,
               precision: str = "fp64", s0: torch.Tensor | None = None, check_every: int = 0,
-              tile_items: int = 0, inner_tol: float = 0.0, no_fallback: bool = False,
+              tile_items: int = 0, col_segments: int = 0, inner_tol: float = 0.0,
+              no_fallback: bool = False,
               return_s: bool = False, psi_out: torch.Tensor | None = None, stream=None,
               raise_on_status: bool = False):
         """psi_solve: ψ (and s) by Algorithm 2; returns (psi, info) or (psi, s, info)."""
@@ -159,6 +160,7 @@ class Operator:
         p.check_every = check_every
         p.flags = PSI_NO_FALLBACK if no_fallback else 0
         p.tile_items = tile_items
+        p.col_segments = col_segments
         p.inner_tol = inner_tol
         psi = psi_out if psi_out is not None else torch.empty(self.n, dtype=torch.float64,
                                                               device=self.device)
@@ -177,7 +179,7 @@ class Operator:
         return (psi, s, d) if return_s else (psi, d)
 
     def step(self, s_in: torch.Tensor, precision: str = "fp64", tile_items: int = 0,
-             stream=None):
+             col_segments: int = 0, stream=None):
         """psi_step: one Power-ψ step s_out = Aᵀ s_in + c and its L1 gap (enqueued)."""
         s_in = s_in.to(self.device, torch.float64).contiguous()
         out = torch.empty_like(s_in)
@@ -185,7 +187,7 @@ class Operator:
         with torch.cuda.device(self.device):
             _check(self._lib.psi_step(self._h, PRECISIONS[precision], s_in.data_ptr(),
                                       out.data_ptr(), gap.data_ptr(), tile_items,
-                                      _stream_handle(stream)))
+                                      col_segments, _stream_handle(stream)))
         return out, gap
 
     def final(self, s: torch.Tensor, stream=None) -> torch.Tensor:
@@ -197,13 +199,14 @@ class Operator:
                                        _stream_handle(stream)))
         return out
 
-    def pass_time(self, kind: str, reps: int = 50, tile_items: int = 0, stream=None) -> float:
+    def pass_time(self, kind: str, reps: int = 50, tile_items: int = 0, col_segments: int = 0,
+                  stream=None) -> float:
         """psi_pass_time: mean ms of one launch of a pass kind (HIP events on the stream)."""
         kinds = {"step64": _ffi.PSI_PASS_STEP64, "step64_w": _ffi.PSI_PASS_STEP64_W,
                  "final64": _ffi.PSI_PASS_FINAL64, "step32": _ffi.PSI_PASS_STEP32}
         out = ctypes.c_double()
         with torch.cuda.device(self.device):
-            _check(self._lib.psi_pass_time(self._h, kinds[kind], reps, tile_items,
+            _check(self._lib.psi_pass_time(self._h, kinds[kind], reps, tile_items, col_segments,
                                            ctypes.byref(out), _stream_handle(stream)))
         return out.value
 

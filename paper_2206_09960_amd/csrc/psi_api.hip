@@ -15,10 +15,10 @@ void set_error(const std::string& msg) { g_last_error = msg; }
 void clear_error() { g_last_error.clear(); }
 
 psi_status step(psi_operator* op, int precision, const double* s_in, double* s_out,
-                double* gap_out, int tile_items, hipStream_t st);
+                double* gap_out, int tile_items, int col_segments, hipStream_t st);
 psi_status final_psi(psi_operator* op, const double* s_vec, double* psi_out, hipStream_t st);
-psi_status pass_time(psi_operator* op, int kind, int reps, int tile_items, double* mean_ms,
-                     hipStream_t st);
+psi_status pass_time(psi_operator* op, int kind, int reps, int tile_items, int col_segments,
+                     double* mean_ms, hipStream_t st);
 
 static psi_status check_device(const psi_operator* op) {
   int dev = -1;
@@ -173,6 +173,7 @@ psi_status psi_params_default(psi_params* p) {
   p->check_every = 0;
   p->flags = 0;
   p->tile_items = 0;
+  p->col_segments = 0;
   p->inner_tol = 0.0;
   return PSI_OK;
   PSI_GUARD_END
@@ -189,12 +190,12 @@ psi_status psi_solve(psi_operator* op, const psi_params* prm, const double* s0,
 }
 
 psi_status psi_step(psi_operator* op, int32_t precision, const double* s_in, double* s_out,
-                    double* gap_out, int32_t tile_items, void* stream) {
+                    double* gap_out, int32_t tile_items, int32_t col_segments, void* stream) {
   PSI_GUARD_BEGIN
   PSI_REQUIRE(op, "op must not be NULL");
   psi_status s = psi::check_device(op);
   if (s != PSI_OK) return s;
-  return psi::step(op, precision, s_in, s_out, gap_out, tile_items,
+  return psi::step(op, precision, s_in, s_out, gap_out, tile_items, col_segments,
                    static_cast<hipStream_t>(stream));
   PSI_GUARD_END
 }
@@ -210,13 +211,14 @@ psi_status psi_final(psi_operator* op, const double* s, double* psi_out, void* s
 }
 
 psi_status psi_pass_time(psi_operator* op, int32_t pass_kind, int32_t reps, int32_t tile_items,
-                         double* mean_ms, void* stream) {
+                         int32_t col_segments, double* mean_ms, void* stream) {
   PSI_GUARD_BEGIN
   PSI_REQUIRE(op, "op must not be NULL");
   PSI_REQUIRE(op->n_graphs == 1, "psi_pass_time needs a single-graph operator");
   psi_status st = psi::check_device(op);
   if (st != PSI_OK) return st;
-  return psi::pass_time(op, pass_kind, reps, tile_items, mean_ms, static_cast<hipStream_t>(stream));
+  return psi::pass_time(op, pass_kind, reps, tile_items, col_segments, mean_ms,
+                        static_cast<hipStream_t>(stream));
   PSI_GUARD_END
 }
 

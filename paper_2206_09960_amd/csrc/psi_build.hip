@@ -347,6 +347,44 @@ __global__ void k_schedule(const int* row_ptr, int64_t n, int64_t m, int64_t ite
   tile_row[b] = int(lo);
 }
 
+// Entries of row i of CSR(Aᵀ) that fall in column segment s (columns are
+// ascending within a row, so each segment is a contiguous run): counts.
+__global__ void k_seg_count(const int* row_ptr, const int* col, int64_t n, int S, int64_t seg,
+                            int* seg_row_ptr) {
+  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int lo_e = row_ptr[i];
+  const int end = row_ptr[i + 1];
+  for (int s = 0; s < S; ++s) {
+    // first entry with col >= (s+1)*seg
+    const int64_t bound = (s + 1) * seg;
+    int lo = lo_e, hi = end;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (col[mid] < bound) lo = mid + 1; else hi = mid;
+    }
+    seg_row_ptr[int64_t(s) * (n + 1) + i] = lo - lo_e;
+    lo_e = lo;
+  }
+}
+
+// Copy each row's run of segment s into that segment's CSR (one wave per row).
+__global__ void k_seg_scatter(const int* row_ptr, const int* col, int64_t n, int S, int64_t seg,
+                              const int* seg_row_ptr, const int64_t* seg_off, int* seg_col) {
+  const int64_t row = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (row >= n) return;
+  int e = row_ptr[row];
+  for (int s = 0; s < S; ++s) {
+    const int* rp = seg_row_ptr + int64_t(s) * (n + 1);
+    const int cnt = rp[row + 1] - rp[row];
+    int* dst = seg_col + seg_off[s] + rp[row];
+    for (int k = lane; k < cnt; k += 64) dst[k] = col[e + k];
+    e += cnt;
+  }
+  (void)seg;
+}
+
 inline unsigned grid_for(int64_t n, int block = kBlock) {
   return unsigned((n + block - 1) / block);
 }
@@ -446,11 +484,20 @@ static void layout_persistent(int64_t n, int64_t m_raw, int n_graphs, uint32_t f
   char* r32 = take(4 * size_t(n));
   char* part_open = take(8 * size_t(max_tiles));
   char* gap_part = take(16 * size_t(kMaxGrid));
+  char* gap_grp = take(16 * size_t(kMaxGrid / 64));
+  char* grp_ticket = take(4 * size_t(kMaxGrid / 64));
   char* tile_row = take(4 * size_t(max_tiles + 1));
   char* ctrl = take(2 * sizeof(Ctrl));
   char* hist = take(8 * size_t(kHistLen));
   char* scal = take(8 * 8);
   char* goff = take(8 * size_t(n_graphs + 1));
+  const int64_t max_seg_tiles = (8 * n + m_raw) / kMinTileItems + 16;
+  char* seg_col = take(4 * size_t(m_raw));
+  char* seg_row_ptr = take(4 * size_t(8 * (n + 1)));
+  char* seg_tile_row = take(4 * size_t(max_seg_tiles + 8));
+  char* seg_part_open = take(8 * size_t(max_seg_tiles));
+  char* seg_y = take(8 * size_t(8 * n));
+  char* seg_scan_tmp = take(4 * size_t((n + 1) / 4096 + 8));
   *total = off;
   if (!op) return;
   op->row_ptr = (int*)row_ptr;
@@ -477,12 +524,21 @@ static void layout_persistent(int64_t n, int64_t m_raw, int n_graphs, uint32_t f
   op->r32 = (float*)r32;
   op->part_open = (double*)part_open;
   op->gap_part = (double*)gap_part;
+  op->gap_grp = (double*)gap_grp;
+  op->grp_ticket = (unsigned*)grp_ticket;
   op->tile_row = (int*)tile_row;
   op->max_tiles = max_tiles;
   op->ctrl = (Ctrl*)ctrl;
   op->hist = (double*)hist;
   op->scal = (double*)scal;
   op->graph_off = (int64_t*)goff;
+  op->seg_col = (int*)seg_col;
+  op->seg_row_ptr = (int*)seg_row_ptr;
+  op->seg_tile_row = (int*)seg_tile_row;
+  op->seg_part_open = (double*)seg_part_open;
+  op->seg_y = (double*)seg_y;
+  op->seg_scan_tmp = (uint32_t*)seg_scan_tmp;
+  op->max_seg_tiles = max_seg_tiles;
 }
 
 static size_t scratch_size(int64_t n, int64_t m_raw) {
@@ -539,6 +595,13 @@ psi_status build_operator(psi_operator* op, const int32_t* follower, const int32
                      reinterpret_cast<uint64_t*>(op->part_open), op->max_tiles, kEmptySlot);
   hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(2 * kMaxGrid)), dim3(kBlock), 0, st,
                      reinterpret_cast<uint64_t*>(op->gap_part), int64_t(2 * kMaxGrid), kEmptySlot);
+  hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(2 * kMaxGrid / 64)), dim3(kBlock), 0, st,
+                     reinterpret_cast<uint64_t*>(op->gap_grp), int64_t(2 * kMaxGrid / 64),
+                     kEmptySlot);
+  PSI_HIP_CHECK(hipMemsetAsync(op->grp_ticket, 0, 4 * size_t(kMaxGrid / 64), st));
+  hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(op->max_seg_tiles)), dim3(kBlock), 0, st,
+                     reinterpret_cast<uint64_t*>(op->seg_part_open), op->max_seg_tiles, kEmptySlot);
+  op->seg_S = 0;
   if (op->n_graphs > 1)
     PSI_HIP_CHECK(hipMemcpyAsync(op->graph_off, node_offsets, 8 * size_t(op->n_graphs + 1),
                                  hipMemcpyHostToDevice, st));
@@ -680,6 +743,77 @@ psi_status ensure_schedule(psi_operator* op, int tile_items, hipStream_t st) {
   PSI_HIP_CHECK(hipGetLastError());
   op->sched_items = tile_items;
   op->n_tiles = int(n_tiles);
+  return PSI_OK;
+}
+
+psi_status ensure_segments(psi_operator* op, int S, int tile_items, hipStream_t st) {
+  PSI_REQUIRE(S == 2 || S == 4 || S == 8, "col_segments must be 1, 2, 4 or 8");
+  PSI_REQUIRE(tile_items_supported(tile_items), "unsupported tile_items");
+  PSI_REQUIRE(op->n_graphs == 1, "column segments need a single-graph operator");
+  const int64_t n = op->n;
+  const int64_t seg = (n + S - 1) / S;
+  if (op->seg_S != S) {
+    if (op->m > 0) {
+      hipLaunchKernelGGL(k_seg_count, dim3(grid_for(n)), dim3(kBlock), 0, st, op->row_ptr,
+                         op->col, n, S, seg, op->seg_row_ptr);
+    } else {
+      hipLaunchKernelGGL(k_fill_int, dim3(grid_for(int64_t(S) * (n + 1))), dim3(kBlock), 0, st,
+                         op->seg_row_ptr, int64_t(S) * (n + 1), 0);
+    }
+    // exclusive scan of each segment's counts (entry n receives the total)
+    SortBufs sb{};
+    sb.tile_sums = op->seg_scan_tmp;
+    sb.total = op->seg_scan_tmp + ((n + 1) / 4096 + 4);
+    std::vector<uint32_t> totals(S);
+    for (int s = 0; s < S; ++s) {
+      uint32_t* rp = reinterpret_cast<uint32_t*>(op->seg_row_ptr + int64_t(s) * (n + 1));
+      PSI_HIP_CHECK(hipMemsetAsync(rp + n, 0, 4, st));
+      psi_status r = scan_u32(rp, rp, n + 1, sb, st);
+      if (r != PSI_OK) return r;
+      PSI_HIP_CHECK(hipMemcpyAsync(&totals[s], rp + n, 4, hipMemcpyDeviceToHost, st));
+    }
+    PSI_HIP_CHECK(hipStreamSynchronize(st));
+    std::vector<int64_t> off(S + 1, 0);
+    for (int s = 0; s < S; ++s) off[s + 1] = off[s] + totals[s];
+    if (off[S] != op->m) {
+      set_error("column segmentation lost edges");
+      return PSI_EDEVICE;
+    }
+    int64_t* doff = reinterpret_cast<int64_t*>(op->scal);  // 8 values of scratch
+    PSI_HIP_CHECK(hipMemcpyAsync(doff, off.data(), 8 * size_t(S), hipMemcpyHostToDevice, st));
+    if (op->m > 0)
+      hipLaunchKernelGGL(k_seg_scatter, dim3(grid_for(n * 64)), dim3(kBlock), 0, st, op->row_ptr,
+                         op->col, n, S, seg, op->seg_row_ptr, doff, op->seg_col);
+    PSI_HIP_CHECK(hipGetLastError());
+    PSI_HIP_CHECK(hipStreamSynchronize(st));
+    for (int s = 0; s < S; ++s) {
+      op->seg[s].row_ptr = op->seg_row_ptr + int64_t(s) * (n + 1);
+      op->seg[s].col = op->seg_col + off[s];
+      op->seg[s].n_nnz = static_cast<int>(totals[s]);
+    }
+    op->seg_S = S;
+    op->seg_items = 0;
+  }
+  if (op->seg_items != tile_items) {
+    int64_t tile_off = 0;
+    for (int s = 0; s < S; ++s) {
+      const int64_t total = n + op->seg[s].n_nnz;
+      const int64_t nt = std::max<int64_t>((total + tile_items - 1) / tile_items, 1);
+      if (tile_off + nt + 1 > op->max_seg_tiles + 8) {
+        set_error("segment schedules do not fit the workspace");
+        return PSI_ENOSPACE;
+      }
+      hipLaunchKernelGGL(k_schedule, dim3(grid_for(nt + 1)), dim3(kBlock), 0, st,
+                         op->seg[s].row_ptr, n, int64_t(op->seg[s].n_nnz), int64_t(tile_items), nt,
+                         op->seg_tile_row + tile_off);
+      op->seg[s].tile_row = op->seg_tile_row + tile_off;
+      op->seg[s].part_open = op->seg_part_open + (tile_off - s);
+      op->seg[s].n_tiles = static_cast<int>(nt);
+      tile_off += nt + 1;
+    }
+    PSI_HIP_CHECK(hipGetLastError());
+    op->seg_items = tile_items;
+  }
   return PSI_OK;
 }
 

@@ -37,7 +37,7 @@ constexpr int kBlock = 256;            // threads of every operator-pass workgro
 constexpr int kMinTileItems = 1024;    // smallest merge-path tile (sizes the schedule)
 constexpr int kDefaultTileItems = 2048;
 constexpr int kHistLen = 1 << 16;      // device gap history entries
-constexpr int kMaxGrid = 8192;         // largest resident grid of a pass kernel
+constexpr int kMaxGrid = 4096;         // largest grid of a pass kernel (64 groups of 64)
 // Cross-tile slots hold this signalling-NaN pattern while empty.  Every value
 // a tile publishes is the result of floating-point arithmetic, which never
 // produces a signalling NaN, so the pattern cannot collide with data.
@@ -105,6 +105,8 @@ struct PassArgs {
   // cross-tile state
   double* part_open;   // [n_tiles] a tile's partial of its open last row (slot)
   double* gap_part;    // [2*grid] (Σ|Δ|, Σ|new|) of each workgroup (slot)
+  double* gap_grp;     // [2*ceil(grid/64)] the same per group of 64 workgroups (slot)
+  unsigned* grp_ticket;  // [ceil(grid/64)] arrivals per group (reset by its last)
   Ctrl* ctrl;
   double* hist;
   double* gap_out;      // optional plain copy of the gap (psi_step)
@@ -117,6 +119,24 @@ enum PassMode : int {
   kStep64W = 1,     // s_new = c + Σ a_ji s_j (weighted), gap
   kFinal64 = 2,     // ψ = (λ·Σ z_j + d)/N
   kStep32 = 3,      // e_new = r + μ·Σ ze_j, ze_new = invden·e_new, gap (FP32 storage)
+  kPart64 = 4,      // y_s = Σ_{j∈F(i), j in segment s} x_j, x FP64 (partial pass)
+  kPart32 = 5,      // same with x FP32, y_s stored FP32
+};
+
+// One column segment of CSR(Aᵀ): the followers in [lo, hi) of every row.
+struct SegInfo {
+  const int* row_ptr;   // [n_rows + 1], offsets into col (0-based per segment)
+  const int* col;       // global follower ids
+  const int* tile_row;  // merge-path schedule of this segment [n_tiles + 1]
+  double* part_open;    // cross-tile slots [n_tiles]
+  void* y;              // partial result [n_rows]
+  int n_nnz;
+  int n_tiles;
+};
+
+struct SegArgs {
+  SegInfo seg[8];
+  int S;
 };
 
 }  // namespace psi
@@ -138,7 +158,8 @@ struct psi_operator {
   // solve state
   double *s_a = nullptr, *s_b = nullptr, *z_a = nullptr, *z_b = nullptr;
   float *e_a = nullptr, *e_b = nullptr, *ze_a = nullptr, *ze_b = nullptr, *r32 = nullptr;
-  double *part_open = nullptr, *gap_part = nullptr;
+  double *part_open = nullptr, *gap_part = nullptr, *gap_grp = nullptr;
+  unsigned* grp_ticket = nullptr;
   int* tile_row = nullptr;
   int64_t max_tiles = 0;
   int sched_items = 0;   // tile size the schedule in tile_row was built for
@@ -149,6 +170,17 @@ struct psi_operator {
   double* scal = nullptr;  // small FP64 device scratch (8 values)
   int64_t* graph_off = nullptr;  // device copy of node_offsets [n_graphs + 1]
   std::vector<int64_t> node_offsets;
+  // column-segmented form of CSR(Aᵀ) (built on first use for a given S)
+  int seg_S = 0;            // segments currently built (0 = none)
+  int seg_items = 0;        // tile size of their schedules
+  psi::SegInfo seg[8]{};
+  int* seg_col = nullptr;       // [m]
+  int* seg_row_ptr = nullptr;   // [8 * (n + 1)]
+  int* seg_tile_row = nullptr;  // [max_seg_tiles + 8]
+  double* seg_part_open = nullptr;  // [max_seg_tiles]
+  double* seg_y = nullptr;      // [8 * n]
+  uint32_t* seg_scan_tmp = nullptr;
+  int64_t max_seg_tiles = 0;
 };
 
 namespace psi {
@@ -165,7 +197,11 @@ psi_status build_operator(psi_operator* op, const int32_t* follower, const int32
                           char* scratch, size_t scratch_bytes, hipStream_t stream);
 
 psi_status ensure_schedule(psi_operator* op, int tile_items, hipStream_t stream);
+// Build (or keep) the S-segment form of CSR(Aᵀ) with tiles of tile_items.
+psi_status ensure_segments(psi_operator* op, int S, int tile_items, hipStream_t stream);
+bool tile_items_supported(int t);
 psi_status launch_pass(psi_operator* op, PassMode mode, const PassArgs& a, hipStream_t stream);
+psi_status launch_pass_seg(psi_operator* op, PassMode mode, const PassArgs& a, hipStream_t stream);
 PassArgs base_args(psi_operator* op);
 
 psi_status solve(psi_operator* op, const psi_params* prm, const double* s0, double* psi_out,

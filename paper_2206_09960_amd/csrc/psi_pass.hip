@@ -9,18 +9,26 @@
 // distribution, so the power-law follower counts (hub rows) need no special
 // kernel.  Inside a tile:
 //   1. coalesced, non-temporal reads of the column indices, one gather of x
-//      per edge into LDS (x stays cache-resident);
+//      per edge into LDS;
 //   2. each thread consumes T/256 consecutive path items from LDS;
 //   3. a segmented scan of the per-thread carries finishes rows that span
 //      threads;
 //   4. rows that begin and end in the tile get their epilogue at once.
-// The grid is persistent and co-resident (cooperative launch): workgroups walk
-// the tiles grid-stride.  A row that spans tiles is summed from the tiles'
+// The grid is persistent and sized to be co-resident: workgroups walk the
+// tiles grid-stride.  A row that spans tiles is summed from the tiles'
 // partials, in tile order, by the workgroup that owns the tile where the row
 // ends; partials travel through coherent slots (see take_slot), so no cache
 // flush or floating-point atomic is needed and every pass is bitwise
 // repeatable.  The gap is one partial per workgroup, summed in workgroup order
 // by the last workgroup to finish, which also decides termination.
+//
+// Column-segmented passes (S = 2, 4, 8).  The gather of x is limited by the
+// rate at which the caches serve random lines, and that rate roughly doubles
+// when the gathered range fits one XCD's L2.  Workgroups are dispatched to
+// the 8 XCDs round-robin, so the XCDs with xcd % S == s run the tiles of
+// column segment s (followers in [s·N/S, (s+1)·N/S)) and write a partial
+// y_s; a streaming combine kernel then adds the S partials in segment order
+// and applies the epilogue and the gap.
 #include <algorithm>
 #include <cmath>
 
@@ -36,23 +44,21 @@ __device__ inline void st_agent(double* p, double x) {
                      __HIP_MEMORY_SCOPE_AGENT);
 }
 
-constexpr unsigned long long kEmpty = kEmptySlot;
-
 // Wait (bounded) until a slot is filled, take its value and empty it again.
-// The writer filled it before it announced itself on the counter the caller
-// observed, so the wait is short; the bound only guarantees the kernel ends.
+// The writer fills the slot before the reader can need it (see the kernels),
+// so the wait is short; the bound only guarantees the kernel ends.
 __device__ inline double take_slot(double* p, Ctrl* ctrl) {
   unsigned long long* q = reinterpret_cast<unsigned long long*>(p);
   unsigned long long v = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  for (int spin = 0; v == kEmpty && spin < (1 << 22); ++spin) {
+  for (int spin = 0; v == kEmptySlot && spin < (1 << 22); ++spin) {
     __builtin_amdgcn_s_sleep(1);
     v = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
-  if (v == kEmpty) {
+  if (v == kEmptySlot) {
     atomicOr(&ctrl->err_flags, kErrSlotTimeout);
     return 0.0;
   }
-  __hip_atomic_store(q, kEmpty, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(q, kEmptySlot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   return __longlong_as_double(static_cast<long long>(v));
 }
 
@@ -75,9 +81,21 @@ __device__ inline void block_sum2(double& a, double& b, double* sh) {
   __syncthreads();
 }
 
+// The CSR a group of workgroups walks: the whole of CSR(Aᵀ), or one column
+// segment of it.
+struct TileSrc {
+  const int* row_ptr;
+  const int* col;
+  const int* tile_row;
+  double* part_open;
+  void* y;  // per-row output of a partial pass
+  int n_nnz;
+  int n_tiles;
+};
+
 template <int MODE>
 __device__ inline double gather(const PassArgs& a, int j, int e) {
-  if constexpr (MODE == kStep32) {
+  if constexpr (MODE == kStep32 || MODE == kPart32) {
     return static_cast<double>(static_cast<const float*>(a.x)[j]);
   } else if constexpr (MODE == kStep64W) {
     return static_cast<const double*>(a.x)[j] * __builtin_nontemporal_load(a.val64 + e);
@@ -86,116 +104,200 @@ __device__ inline double gather(const PassArgs& a, int j, int e) {
   }
 }
 
+// Per-user inputs of the epilogue, loaded ahead of the row's sum.
+struct RowIn {
+  double a0, a1, a2, a3;
+};
+
+template <int MODE>
+__device__ inline RowIn load_row(const PassArgs& a, int r) {
+  RowIn in{0.0, 0.0, 0.0, 0.0};
+  if constexpr (MODE == kStep64) {
+    in = {a.c[r], a.mu[r], a.invden[r], a.s_old[r]};
+  } else if constexpr (MODE == kStep64W) {
+    in.a0 = a.c[r];
+    in.a3 = a.s_old[r];
+  } else if constexpr (MODE == kFinal64) {
+    in.a0 = a.lam[r];
+    in.a1 = a.d[r];
+  } else if constexpr (MODE == kStep32) {
+    in = {static_cast<double>(a.r32[r]), static_cast<double>(a.mu32[r]),
+          static_cast<double>(a.invden32[r]), static_cast<double>(a.e_old[r])};
+  }
+  return in;
+}
+
 // Per-user epilogue; g accumulates |new − old|, s accumulates |new|.
 template <int MODE>
-__device__ inline void epilogue(const PassArgs& a, int r, double y, double& g, double& s) {
+__device__ inline void apply_row(const PassArgs& a, void* yout, int r, const RowIn& in, double y,
+                                 double& g, double& s) {
   if constexpr (MODE == kStep64) {
-    const double sn = a.c[r] + a.mu[r] * y;
-    const double so = a.s_old[r];
+    const double sn = in.a0 + in.a1 * y;  // c + μ·y
     a.s_new[r] = sn;
-    a.z_new[r] = a.invden[r] * sn;
-    g += fabs(sn - so);
+    a.z_new[r] = in.a2 * sn;
+    g += fabs(sn - in.a3);
     s += fabs(sn);
   } else if constexpr (MODE == kStep64W) {
-    const double sn = a.c[r] + y;
-    const double so = a.s_old[r];
+    const double sn = in.a0 + y;
     a.s_new[r] = sn;
-    g += fabs(sn - so);
+    g += fabs(sn - in.a3);
     s += fabs(sn);
   } else if constexpr (MODE == kFinal64) {
-    a.s_new[r] = (a.lam[r] * y + a.d[r]) * a.inv_n;
-  } else {
-    const float en = a.r32[r] + a.mu32[r] * static_cast<float>(y);
-    const float eo = a.e_old[r];
+    a.s_new[r] = (in.a0 * y + in.a1) * a.inv_n;
+  } else if constexpr (MODE == kStep32) {
+    const float en = static_cast<float>(in.a0) + static_cast<float>(in.a1) * static_cast<float>(y);
     a.e_new[r] = en;
-    a.ze_new[r] = a.invden32[r] * en;
-    g += fabs(static_cast<double>(en) - static_cast<double>(eo));
+    a.ze_new[r] = static_cast<float>(in.a2) * en;
+    g += fabs(static_cast<double>(en) - in.a3);
     s += fabs(static_cast<double>(en));
+  } else if constexpr (MODE == kPart64) {
+    static_cast<double*>(yout)[r] = y;
+  } else {
+    static_cast<float*>(yout)[r] = static_cast<float>(y);
   }
 }
 
-// Finish a row that spans tiles [bs, be]: its partials from tiles bs..be-1
-// (published by their blocks) plus this tile's head partial, summed in tile
-// order; then its epilogue.  Called by the whole workgroup of the block that
-// owns tile be, so the row's gap term lands in a fixed place of the sum.
-template <int MODE, int T>
-__device__ void finish_row(const PassArgs& a, int r, int be, double head, double* sh, double& g,
-                           double& sn) {
-  const int bs = static_cast<int>((static_cast<long long>(r) + a.row_ptr[r]) / T);
-  double acc = 0.0, dummy = 0.0;
-  for (int q = bs + static_cast<int>(threadIdx.x); q < be; q += kBlock)
-    acc += take_slot(&a.part_open[q], a.ctrl);
-  block_sum2(acc, dummy, sh);
-  if (threadIdx.x == 0) epilogue<MODE>(a, r, acc + head, g, sn);
+template <int MODE>
+__device__ inline void epilogue(const PassArgs& a, void* yout, int r, double y, double& g,
+                                double& s) {
+  apply_row<MODE>(a, yout, r, load_row<MODE>(a, r), y, g, s);
 }
 
-// Persistent pass: a co-resident grid walks the tiles grid-stride.  A tile
-// publishes the partial of its open last row at once; the row that ends in a
-// tile but began earlier is finished one iteration later (its earlier tiles
-// were handed out before this one, so their partials are ready by then).
-template <int IPT, int MODE>
-__global__ __launch_bounds__(kBlock) void k_pass(PassArgs a) {
-  constexpr int T = kBlock * IPT;
-  __shared__ int s_rowend[T];
-  __shared__ double s_val[T];
-  __shared__ double s_rowval[T];
-  __shared__ int s_crow[kBlock];
-  __shared__ double s_cval[kBlock];
-  __shared__ double s_red[8];
-  __shared__ int s_last;
+template <int IPT>
+struct TileLds {
+  int rowend[kBlock * IPT];
+  double val[kBlock * IPT];
+  double rowval[kBlock * IPT];
+  double cval[kBlock];
+  int wkey[2][kBlock / 64];
+  double wval[kBlock / 64];
+  double red[8];
+  int last;
+};
 
-  if (a.respect_done && a.ctrl->done) return;
+// Tile bounds on the merge path.
+struct TileMeta {
+  int tile, r0, r1, e0, e1, rp0, rp1;  // rp0 = row_ptr[r0], rp1 = row_ptr[r1] (r1 < n)
+};
+
+__device__ inline TileMeta tile_meta(const TileSrc& src, int n_rows, long long total, int tile,
+                                     int T) {
+  TileMeta m;
+  m.tile = tile;
+  m.r0 = src.tile_row[tile];
+  m.r1 = src.tile_row[tile + 1];
+  const long long d0 = static_cast<long long>(tile) * T;
+  const long long d1 = d0 + T < total ? d0 + T : total;
+  m.e0 = static_cast<int>(d0 - m.r0);
+  m.e1 = static_cast<int>(d1 - m.r1);
+  m.rp0 = m.r1 > m.r0 ? src.row_ptr[m.r0] : m.e0;
+  m.rp1 = m.r1 < n_rows ? src.row_ptr[m.r1] : m.e1;
+  return m;
+}
+
+// Column indices and row ends of a tile, one coalesced load per item slot;
+// indices past the tile are clamped so every lane loads without a branch.
+template <int IPT>
+__device__ inline void load_tile(const TileSrc& src, const TileMeta& m, int* j, int* re) {
+  const int ne = m.e1 - m.e0, nr = m.r1 - m.r0;
+#pragma unroll
+  for (int i = 0; i < IPT; ++i) {
+    const int k = i * kBlock + static_cast<int>(threadIdx.x);
+    j[i] = ne > 0 ? __builtin_nontemporal_load(src.col + m.e0 + min(k, ne - 1)) : 0;
+    re[i] = nr > 0 ? src.row_ptr[m.r0 + 1 + min(k, nr - 1)] : 0;
+  }
+}
+
+template <int IPT, int MODE>
+__device__ inline void gather_tile(const PassArgs& a, const TileMeta& m, const int* j, double* v) {
+  const int ne = m.e1 - m.e0;
+#pragma unroll
+  for (int i = 0; i < IPT; ++i) {
+    const int k = min(i * kBlock + static_cast<int>(threadIdx.x), ne > 0 ? ne - 1 : 0);
+    v[i] = ne > 0 ? gather<MODE>(a, j[i], m.e0 + k) : 0.0;
+  }
+}
+
+// Walk tiles first, first+stride, ... of src, software-pipelined: while a
+// tile is reduced in LDS, the next tile's indices are in flight, and its
+// gathers are issued before this tile's epilogue.  A tile publishes the
+// partial of its open last row at once; the row that ends in a tile but began
+// earlier is summed from the earlier tiles' partials (in tile order) in the
+// next iteration, when they are ready, by this workgroup.
+template <int IPT, int MODE>
+__device__ void run_tiles(const PassArgs& a, const TileSrc& src, int first, int stride,
+                          TileLds<IPT>& L, double& g, double& sn) {
+  constexpr int T = kBlock * IPT;
   const int tid = threadIdx.x;
-  const long long total = static_cast<long long>(a.n_rows) + a.n_nnz;
-  double g = 0.0, sn = 0.0;
-  int pend_row = -1, pend_tile = 0;  // uniform across the workgroup
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const long long total = static_cast<long long>(a.n_rows) + src.n_nnz;
+  if (first >= src.n_tiles) return;
+
+  TileMeta cur = tile_meta(src, a.n_rows, total, first, T);
+  int j[IPT], re[IPT];
+  double v[IPT];
+  load_tile<IPT>(src, cur, j, re);
+  gather_tile<IPT, MODE>(a, cur, j, v);
+
+  // row that ended in the previous tile but began earlier (uniform)
+  int pend_row = -1, pend_tile = 0;
   double pend_head = 0.0;
 
-  for (int tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
-    const int r0 = a.tile_row[tile];
-    const int r1 = a.tile_row[tile + 1];
-    const long long d0 = static_cast<long long>(tile) * T;
-    const long long d1 = d0 + T < total ? d0 + T : total;
-    const int e0 = static_cast<int>(d0 - r0);
-    const int e1 = static_cast<int>(d1 - r1);
-    const int nr = r1 - r0;
-    const int ne = e1 - e0;
+  for (;;) {
+    const int nr = cur.r1 - cur.r0;
+    const int ne = cur.e1 - cur.e0;
+    const bool head_inc = nr > 0 && cur.rp0 < cur.e0;
+    const bool open = cur.r1 < a.n_rows && cur.e1 > cur.rp1;
 
-    // 1. stage row ends and gathered values
-    for (int k = tid; k < nr; k += kBlock) s_rowend[k] = a.row_ptr[r0 + 1 + k];
-    if (ne > 0) {
-      // indices past the tile are clamped to its last edge, so every lane
-      // issues its loads without a branch and all of them are in flight
-      int j[IPT];
-      double v[IPT];
+    // 1. stage this tile in LDS
 #pragma unroll
-      for (int i = 0; i < IPT; ++i) {
-        const int k = min(i * kBlock + tid, ne - 1);
-        j[i] = __builtin_nontemporal_load(a.col + e0 + k);
-      }
-#pragma unroll
-      for (int i = 0; i < IPT; ++i) {
-        const int k = min(i * kBlock + tid, ne - 1);
-        v[i] = gather<MODE>(a, j[i], e0 + k);
-      }
-#pragma unroll
-      for (int i = 0; i < IPT; ++i) {
-        const int k = i * kBlock + tid;
-        if (k < ne) s_val[k] = v[i];
-      }
+    for (int i = 0; i < IPT; ++i) {
+      const int k = i * kBlock + tid;
+      if (k < ne) L.val[k] = v[i];
+      if (k < nr) L.rowend[k] = re[i];
     }
-    const bool head_inc = nr > 0 && a.row_ptr[r0] < e0;
-    const bool open = r1 < a.n_rows && e1 > a.row_ptr[r1];
+    // 2. early loads: epilogue inputs of this tile's rows, and the partials
+    //    and inputs of the pending row
+    // (a tile holds about T / (mean row length + 1) rows, so two per thread
+    // cover the usual case; rows beyond load at use)
+    constexpr int RPT = IPT < 2 ? IPT : 2;
+    RowIn rin[RPT];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int k = i * kBlock + tid;
+      if (k < nr) rin[i] = load_row<MODE>(a, cur.r0 + k);
+    }
+    RowIn pin{0.0, 0.0, 0.0, 0.0};
+    int pbs = 0, pnq = 0;
+    unsigned long long pslot = kEmptySlot;
+    if (pend_row >= 0) {
+      pbs = static_cast<int>((static_cast<long long>(pend_row) + src.row_ptr[pend_row]) / T);
+      pnq = pend_tile - pbs;
+      if (tid == 0) pin = load_row<MODE>(a, pend_row);
+      if (wave == 0 && lane < pnq && pnq <= 64)
+        pslot = __hip_atomic_load(reinterpret_cast<unsigned long long*>(&src.part_open[pbs + lane]),
+                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    // 3. the next tile's bounds, indices and row ends
+    const int nxt_tile = cur.tile + stride;
+    const bool has_next = nxt_tile < src.n_tiles;
+    TileMeta nxt = cur;
+    int jn[IPT], ren[IPT];
+    if (has_next) {
+      nxt = tile_meta(src, a.n_rows, total, nxt_tile, T);
+      load_tile<IPT>(src, nxt, jn, ren);
+    }
     __syncthreads();
 
-    // 2. this thread's start on the tile's merge path, then its items
+    // 4. this thread's start on the tile's merge path, then its items
     const int len = nr + ne;
     const int diag = tid * IPT < len ? tid * IPT : len;
     int lo = diag - ne > 0 ? diag - ne : 0;
     int hi = diag < nr ? diag : nr;
     while (lo < hi) {
       const int p = (lo + hi) >> 1;
-      if (s_rowend[p] <= e0 + diag - p - 1) lo = p + 1; else hi = p;
+      if (L.rowend[p] <= cur.e0 + diag - p - 1) lo = p + 1; else hi = p;
     }
     const int row_start = lo;
     int row = lo;
@@ -203,122 +305,304 @@ __global__ __launch_bounds__(kBlock) void k_pass(PassArgs a) {
     const int dend = diag + IPT < len ? diag + IPT : len;
     double run = 0.0;
     for (int it = diag; it < dend; ++it) {
-      if (row < nr && s_rowend[row] <= e0 + nz) {
-        s_rowval[row] = run;
+      if (row < nr && L.rowend[row] <= cur.e0 + nz) {
+        L.rowval[row] = run;
         run = 0.0;
         ++row;
       } else {
-        run += s_val[nz];
+        run += L.val[nz];
         ++nz;
       }
     }
-
-    // 3. segmented inclusive scan of the carries (rows are non-decreasing in tid)
-    s_crow[tid] = row;
-    s_cval[tid] = run;
-    __syncthreads();
-    double v = run;
-    for (int off = 1; off < kBlock; off <<= 1) {
-      const double add = (tid >= off && s_crow[tid - off] == row) ? s_cval[tid - off] : 0.0;
-      __syncthreads();
-      v += add;
-      s_cval[tid] = v;
-      __syncthreads();
+    // 5. segmented inclusive scan of the carries (rows non-decreasing in tid):
+    //    within each wave by shuffles, then across the four waves
+    const int up_row = __shfl_up(row, 1, 64);  // carry row of the previous lane
+    double sv = run;
+    for (int off = 1; off < 64; off <<= 1) {
+      const double ov = __shfl_up(sv, off, 64);
+      const int ok = __shfl_up(row, off, 64);
+      if (lane >= off && ok == row) sv += ov;
     }
-    if (row > row_start && tid > 0 && s_crow[tid - 1] == row_start)
-      s_rowval[row_start] += s_cval[tid - 1];
-    __syncthreads();
-
-    // 4. publish the open row's partial, then the epilogue of the rows that
-    //    begin and end here
-    if (tid == 0 && open) st_agent(&a.part_open[tile], s_cval[kBlock - 1]);
-    for (int k = tid; k < nr; k += kBlock) {
-      if (k == 0 && head_inc) continue;
-      epilogue<MODE>(a, r0 + k, s_rowval[k], g, sn);
-    }
-    const double head = s_rowval[0];
-    // 5. the row that ended in the previous tile of this block
-    if (pend_row >= 0) finish_row<MODE, T>(a, pend_row, pend_tile, pend_head, s_red, g, sn);
-    pend_row = head_inc ? r0 : -1;
-    pend_tile = tile;
-    pend_head = head;
-    __syncthreads();  // LDS is refilled by the next tile
-  }
-  if (pend_row >= 0) finish_row<MODE, T>(a, pend_row, pend_tile, pend_head, s_red, g, sn);
-
-  if constexpr (MODE != kFinal64) {
-    // 6. gap: one partial per workgroup, summed in workgroup order by the last
-    block_sum2(g, sn, s_red);
-    if (tid == 0) {
-      st_agent(&a.gap_part[2 * blockIdx.x], g);
-      st_agent(&a.gap_part[2 * blockIdx.x + 1], sn);
-      const unsigned t = atomicAdd(&a.ctrl->ticket, 1u);
-      s_last = t == gridDim.x - 1u;
+    if (lane == 0) L.wkey[0][wave] = row;
+    if (lane == 63) {
+      L.wkey[1][wave] = row;
+      L.wval[wave] = sv;
     }
     __syncthreads();
-    if (!s_last) return;
-    double G = 0.0, S = 0.0;
-    for (int q = tid; q < static_cast<int>(gridDim.x); q += kBlock) {
-      G += take_slot(&a.gap_part[2 * q], a.ctrl);
-      S += take_slot(&a.gap_part[2 * q + 1], a.ctrl);
+    {
+      // carry into this wave's first segment from the waves before it
+      double carry = 0.0;
+      int ck = -1;
+      for (int w = 0; w < wave; ++w) {
+        const int kf = L.wkey[0][w], kl = L.wkey[1][w];
+        const double add = (kf == kl && ck == kf) ? carry : 0.0;
+        carry = L.wval[w] + add;
+        ck = kl;
+      }
+      if (wave > 0 && row == ck) sv += carry;
     }
-    block_sum2(G, S, s_red);
-    if (tid == 0) {
-      Ctrl* c = a.ctrl;
-      c->ticket = 0;
-      if (a.gap_out) *a.gap_out = G;
-      if (a.count_iter) {
-        double gap = G;
-        if (c->tol_mode == PSI_TOL_BNORM) gap = G * c->bnorm;
-        else if (c->tol_mode == PSI_TOL_REL_L1) gap = S > 0.0 ? G / S : G;
-        const int it = c->iter + 1;
-        c->iter = it;
-        c->gap = gap;
-        c->l1 = G;
-        c->snorm = S;
-        if (a.hist && it - 1 < kHistLen) a.hist[it - 1] = gap;
-        if (!isfinite(gap)) {
-          c->done = 1;
-          c->status = PSI_ENUMERIC;
-        } else if (gap <= c->tol) {
-          c->done = 1;
-          c->status = PSI_OK;
-        } else if (it >= c->max_iter) {
-          c->done = 1;
-          c->status = PSI_ENOTCONV;
+    L.cval[tid] = sv;
+    __syncthreads();
+    const int prev_row = lane != 0 ? up_row : (wave > 0 ? L.wkey[1][wave - 1] : -1);
+    if (row > row_start && tid > 0 && prev_row == row_start) L.rowval[row_start] += L.cval[tid - 1];
+    __syncthreads();
+
+    // 6. gathers of the next tile, then this tile's epilogue
+    double vn[IPT];
+    if (has_next) gather_tile<IPT, MODE>(a, nxt, jn, vn);
+    if (tid == 0 && open) st_agent(&src.part_open[cur.tile], L.cval[kBlock - 1]);
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int k = i * kBlock + tid;
+      if (k < nr && !(k == 0 && head_inc))
+        apply_row<MODE>(a, src.y, cur.r0 + k, rin[i], L.rowval[k], g, sn);
+    }
+    for (int k = RPT * kBlock + tid; k < nr; k += kBlock)
+      epilogue<MODE>(a, src.y, cur.r0 + k, L.rowval[k], g, sn);
+    // 7. the pending row: its partials from the earlier tiles, in tile order
+    if (pend_row >= 0) {
+      double acc = 0.0;
+      if (pnq <= 64) {
+        if (wave == 0) {
+          if (lane < pnq) {
+            unsigned long long* q =
+                reinterpret_cast<unsigned long long*>(&src.part_open[pbs + lane]);
+            for (int spin = 0; pslot == kEmptySlot && spin < (1 << 22); ++spin) {
+              __builtin_amdgcn_s_sleep(1);
+              pslot = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            if (pslot == kEmptySlot) atomicOr(&a.ctrl->err_flags, kErrSlotTimeout);
+            else __hip_atomic_store(q, kEmptySlot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            acc = pslot == kEmptySlot ? 0.0 : __longlong_as_double(static_cast<long long>(pslot));
+          }
+          for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
         }
+      } else {
+        for (int q = pbs + tid; q < pend_tile; q += kBlock) acc += take_slot(&src.part_open[q], a.ctrl);
+        double dummy = 0.0;
+        block_sum2(acc, dummy, L.red);
+      }
+      if (tid == 0) apply_row<MODE>(a, src.y, pend_row, pin, acc + pend_head, g, sn);
+    }
+    pend_row = head_inc ? cur.r0 : -1;
+    pend_tile = cur.tile;
+    pend_head = L.rowval[0];
+    __syncthreads();  // LDS is refilled by the next tile
+    if (!has_next) break;
+    cur = nxt;
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) {
+      v[i] = vn[i];
+      re[i] = ren[i];
+    }
+  }
+  if (pend_row >= 0) {
+    double acc = 0.0, dummy = 0.0;
+    const int pbs = static_cast<int>((static_cast<long long>(pend_row) + src.row_ptr[pend_row]) / T);
+    for (int q = pbs + tid; q < pend_tile; q += kBlock) acc += take_slot(&src.part_open[q], a.ctrl);
+    block_sum2(acc, dummy, L.red);
+    if (tid == 0) epilogue<MODE>(a, src.y, pend_row, acc + pend_head, g, sn);
+  }
+}
+
+// Wave 0 takes up to 64 (g, sn) slot pairs at base[0 .. count) in one round
+// trip and sums them in slot order (fixed tree); result in lane 0.
+__device__ inline void take_pairs(double* base, int count, Ctrl* ctrl, double& G, double& S) {
+  const int lane = threadIdx.x & 63;
+  G = 0.0;
+  S = 0.0;
+  if (lane < count) {
+    unsigned long long* q0 = reinterpret_cast<unsigned long long*>(base + 2 * lane);
+    unsigned long long v0 = __hip_atomic_load(q0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned long long v1 = __hip_atomic_load(q0 + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int spin = 0; (v0 == kEmptySlot || v1 == kEmptySlot) && spin < (1 << 22); ++spin) {
+      __builtin_amdgcn_s_sleep(1);
+      v0 = __hip_atomic_load(q0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      v1 = __hip_atomic_load(q0 + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (v0 == kEmptySlot || v1 == kEmptySlot) {
+      atomicOr(&ctrl->err_flags, kErrSlotTimeout);
+    } else {
+      G = __longlong_as_double(static_cast<long long>(v0));
+      S = __longlong_as_double(static_cast<long long>(v1));
+    }
+    __hip_atomic_store(q0, kEmptySlot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(q0 + 1, kEmptySlot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    G += __shfl_down(G, off, 64);
+    S += __shfl_down(S, off, 64);
+  }
+}
+
+// One partial per workgroup (g, sn), reduced in two levels of at most 64 in
+// workgroup order: the last workgroup of each group of 64 sums its group,
+// the last group sums the groups, records the gap and decides termination.
+// Counters are spread over groups, so no single address takes every arrival.
+__device__ void finalize_gap(const PassArgs& a, double g, double sn, double* red, int* s_last) {
+  const int tid = threadIdx.x;
+  block_sum2(g, sn, red);
+  const int grp = blockIdx.x >> 6;
+  const int n_grp = (gridDim.x + 63) >> 6;
+  const int in_grp = min(64, static_cast<int>(gridDim.x) - (grp << 6));
+  if (tid == 0) {
+    st_agent(&a.gap_part[2 * blockIdx.x], g);
+    st_agent(&a.gap_part[2 * blockIdx.x + 1], sn);
+    const unsigned t = atomicAdd(&a.grp_ticket[grp], 1u);
+    *s_last = t == static_cast<unsigned>(in_grp) - 1u;
+  }
+  __syncthreads();
+  if (!*s_last) return;
+  if (tid < 64) {
+    double G, S;
+    take_pairs(a.gap_part + 2 * (grp << 6), in_grp, a.ctrl, G, S);
+    if (tid == 0) {
+      a.grp_ticket[grp] = 0;
+      st_agent(&a.gap_grp[2 * grp], G);
+      st_agent(&a.gap_grp[2 * grp + 1], S);
+      const unsigned t = atomicAdd(&a.ctrl->ticket, 1u);
+      *s_last = t == static_cast<unsigned>(n_grp) - 1u;
+    }
+  }
+  __syncthreads();
+  if (!*s_last || tid >= 64) return;
+  double G, S;
+  take_pairs(a.gap_grp, n_grp, a.ctrl, G, S);
+  if (tid == 0) {
+    Ctrl* c = a.ctrl;
+    c->ticket = 0;
+    if (a.gap_out) *a.gap_out = G;
+    if (a.count_iter) {
+      double gap = G;
+      if (c->tol_mode == PSI_TOL_BNORM) gap = G * c->bnorm;
+      else if (c->tol_mode == PSI_TOL_REL_L1) gap = S > 0.0 ? G / S : G;
+      const int it = c->iter + 1;
+      c->iter = it;
+      c->gap = gap;
+      c->l1 = G;
+      c->snorm = S;
+      if (a.hist && it - 1 < kHistLen) a.hist[it - 1] = gap;
+      if (!isfinite(gap)) {
+        c->done = 1;
+        c->status = PSI_ENUMERIC;
+      } else if (gap <= c->tol) {
+        c->done = 1;
+        c->status = PSI_OK;
+      } else if (it >= c->max_iter) {
+        c->done = 1;
+        c->status = PSI_ENOTCONV;
       }
     }
   }
 }
 
-// Co-resident workgroups for one pass kernel: CUs × workgroups per CU.
+// Fused pass over the whole of CSR(Aᵀ).
 template <int IPT, int MODE>
-int resident_grid() {
-  static int cached = 0;
-  if (cached) return cached;
+__global__ __launch_bounds__(kBlock) void k_pass(PassArgs a) {
+  __shared__ TileLds<IPT> L;
+  if (a.respect_done && a.ctrl->done) return;
+  TileSrc src{a.row_ptr, a.col, a.tile_row, a.part_open, nullptr, a.n_nnz, a.n_tiles};
+  double g = 0.0, sn = 0.0;
+  run_tiles<IPT, MODE>(a, src, blockIdx.x, gridDim.x, L, g, sn);
+  if constexpr (MODE != kFinal64) finalize_gap(a, g, sn, L.red, &L.last);
+}
+
+// Partial pass of one column segment per XCD group: y_s = A_sᵀ x.
+template <int IPT, int MODE>
+__global__ __launch_bounds__(kBlock) void k_pass_seg(PassArgs a, SegArgs sg) {
+  __shared__ TileLds<IPT> L;
+  if (a.respect_done && a.ctrl->done) return;
+  const int xcd = blockIdx.x & 7;
+  const int group = xcd % sg.S;
+  const int per_round = 8 / sg.S;  // workgroups of a group among 8 consecutive ones
+  const int rank = (blockIdx.x >> 3) * per_round + xcd / sg.S;
+  const int size = (gridDim.x >> 3) * per_round;
+  const SegInfo& si = sg.seg[group];
+  TileSrc src{si.row_ptr, si.col, si.tile_row, si.part_open, si.y, si.n_nnz, si.n_tiles};
+  double g = 0.0, sn = 0.0;
+  run_tiles<IPT, MODE>(a, src, rank, size, L, g, sn);
+}
+
+// y_i = Σ_s y_s[i] in segment order, then the epilogue of MODE and the gap.
+template <int MODE, class YT>
+__global__ __launch_bounds__(kBlock) void k_combine(PassArgs a, SegArgs sg) {
+  __shared__ double red[8];
+  __shared__ int last;
+  if (a.respect_done && a.ctrl->done) return;
+  double g = 0.0, sn = 0.0;
+  const YT* y0 = static_cast<const YT*>(sg.seg[0].y);
+  const YT* y1 = static_cast<const YT*>(sg.seg[1].y);
+  const YT* y2 = static_cast<const YT*>(sg.seg[2].y);
+  const YT* y3 = static_cast<const YT*>(sg.seg[3].y);
+  const YT* y4 = static_cast<const YT*>(sg.seg[4].y);
+  const YT* y5 = static_cast<const YT*>(sg.seg[5].y);
+  const YT* y6 = static_cast<const YT*>(sg.seg[6].y);
+  const YT* y7 = static_cast<const YT*>(sg.seg[7].y);
+  const int S = sg.S;
+  constexpr int U = 4;  // rows in flight per thread
+  const int stride = gridDim.x * kBlock;
+  for (int base = blockIdx.x * kBlock + threadIdx.x; base < a.n_rows; base += U * stride) {
+    double y[U];
+    RowIn in[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int r = base + u * stride;
+      y[u] = 0.0;
+      if (r < a.n_rows) {
+        // partials summed in segment order
+        y[u] = static_cast<double>(y0[r]) + static_cast<double>(y1[r]);
+        if (S > 2) y[u] = (y[u] + static_cast<double>(y2[r])) + static_cast<double>(y3[r]);
+        if (S > 4)
+          y[u] = (((y[u] + static_cast<double>(y4[r])) + static_cast<double>(y5[r])) +
+                  static_cast<double>(y6[r])) + static_cast<double>(y7[r]);
+        in[u] = load_row<MODE>(a, r);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int r = base + u * stride;
+      if (r < a.n_rows) apply_row<MODE>(a, nullptr, r, in[u], y[u], g, sn);
+    }
+  }
+  if constexpr (MODE != kFinal64) finalize_gap(a, g, sn, red, &last);
+}
+
+// Co-resident workgroups of a kernel: CUs × workgroups per CU, a multiple of 8.
+template <class K>
+int resident_grid(K kernel) {
   int dev = 0, per_cu = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pass<IPT, MODE>, kBlock, 0) !=
-      hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0) != hipSuccess)
     return 0;
-  cached = std::min(kMaxGrid, std::max(1, per_cu) * cus);
-  return cached;
+  const int g = std::min(kMaxGrid, std::max(1, per_cu) * cus);
+  return std::max(8, g / 8 * 8);
 }
 
 template <int IPT, int MODE>
 psi_status launch_ipt(const PassArgs& a, hipStream_t st) {
-  const int cap = resident_grid<IPT, MODE>();
+  static const int cap = resident_grid(k_pass<IPT, MODE>);
   if (cap <= 0) {
     set_error("could not size the resident grid");
     return PSI_EDEVICE;
   }
+  // the grid never exceeds what fits on the device at once, so on an idle
+  // device every workgroup is resident; the slot waits are bounded in any case
   const int grid = std::min(cap, a.n_tiles);
-  PassArgs copy = a;
-  void* args[] = {&copy};
-  PSI_HIP_CHECK(hipLaunchCooperativeKernel(reinterpret_cast<void*>(k_pass<IPT, MODE>), dim3(grid),
-                                           dim3(kBlock), args, 0, st));
+  hipLaunchKernelGGL((k_pass<IPT, MODE>), dim3(grid), dim3(kBlock), 0, st, a);
+  PSI_HIP_CHECK(hipGetLastError());
+  return PSI_OK;
+}
+
+template <int IPT, int PMODE>
+psi_status launch_seg_ipt(const PassArgs& a, const SegArgs& sg, hipStream_t st) {
+  static const int cap = resident_grid(k_pass_seg<IPT, PMODE>);
+  if (cap <= 0) {
+    set_error("could not size the resident grid");
+    return PSI_EDEVICE;
+  }
+  hipLaunchKernelGGL((k_pass_seg<IPT, PMODE>), dim3(cap), dim3(kBlock), 0, st, a, sg);
+  PSI_HIP_CHECK(hipGetLastError());
   return PSI_OK;
 }
 
@@ -334,6 +618,30 @@ psi_status launch_mode(const PassArgs& a, hipStream_t st) {
       set_error("unsupported tile size " + std::to_string(a.tile_items));
       return PSI_EINVAL;
   }
+}
+
+template <int PMODE>
+psi_status launch_seg_mode(const PassArgs& a, const SegArgs& sg, hipStream_t st) {
+  switch (a.tile_items) {
+    case 1024: return launch_seg_ipt<4, PMODE>(a, sg, st);
+    case 1536: return launch_seg_ipt<6, PMODE>(a, sg, st);
+    case 2048: return launch_seg_ipt<8, PMODE>(a, sg, st);
+    case 3072: return launch_seg_ipt<12, PMODE>(a, sg, st);
+    case 4096: return launch_seg_ipt<16, PMODE>(a, sg, st);
+    default:
+      set_error("unsupported tile size " + std::to_string(a.tile_items));
+      return PSI_EINVAL;
+  }
+}
+
+template <int MODE, class YT>
+psi_status launch_combine(const PassArgs& a, const SegArgs& sg, hipStream_t st) {
+  // about four rows per thread and round; at most 1024 workgroups
+  const int want = static_cast<int>((a.n_rows + 4 * kBlock - 1) / (4 * kBlock));
+  const int grid = std::max(1, std::min(1024, want));
+  hipLaunchKernelGGL((k_combine<MODE, YT>), dim3(grid), dim3(kBlock), 0, st, a, sg);
+  PSI_HIP_CHECK(hipGetLastError());
+  return PSI_OK;
 }
 
 }  // namespace
@@ -362,6 +670,8 @@ PassArgs base_args(psi_operator* op) {
   a.inv_n = op->n > 0 ? 1.0 / static_cast<double>(op->n) : 0.0;
   a.part_open = op->part_open;
   a.gap_part = op->gap_part;
+  a.gap_grp = op->gap_grp;
+  a.grp_ticket = op->grp_ticket;
   a.ctrl = op->ctrl;
   a.hist = op->hist;
   return a;
@@ -374,8 +684,37 @@ psi_status launch_pass(psi_operator* op, PassMode mode, const PassArgs& a, hipSt
     case kStep64W: return launch_mode<kStep64W>(a, st);
     case kFinal64: return launch_mode<kFinal64>(a, st);
     case kStep32: return launch_mode<kStep32>(a, st);
+    default: break;
   }
   set_error("unknown pass mode");
+  return PSI_EINVAL;
+}
+
+// A pass in column-segmented form: partial pass + combine (S = op->seg_S).
+psi_status launch_pass_seg(psi_operator* op, PassMode mode, const PassArgs& a, hipStream_t st) {
+  SegArgs sg{};
+  sg.S = op->seg_S;
+  for (int s = 0; s < sg.S; ++s) sg.seg[s] = op->seg[s];
+  PassArgs b = a;
+  b.tile_items = op->seg_items;
+  psi_status r = PSI_OK;
+  switch (mode) {
+    case kStep64:
+    case kFinal64:
+      for (int s = 0; s < sg.S; ++s) sg.seg[s].y = op->seg_y + size_t(s) * op->n;
+      r = launch_seg_mode<kPart64>(b, sg, st);
+      if (r != PSI_OK) return r;
+      return mode == kStep64 ? launch_combine<kStep64, double>(b, sg, st)
+                             : launch_combine<kFinal64, double>(b, sg, st);
+    case kStep32:
+      for (int s = 0; s < sg.S; ++s)
+        sg.seg[s].y = reinterpret_cast<float*>(op->seg_y) + size_t(s) * op->n;
+      r = launch_seg_mode<kPart32>(b, sg, st);
+      if (r != PSI_OK) return r;
+      return launch_combine<kStep32, float>(b, sg, st);
+    default: break;
+  }
+  set_error("this pass has no column-segmented form");
   return PSI_EINVAL;
 }
 

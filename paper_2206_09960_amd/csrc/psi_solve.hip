@@ -111,10 +111,40 @@ struct IterResult {
   bool stagnated = false;
 };
 
+// Column segments for a gathered vector of `bytes` per user: enough that one
+// segment (the share of an XCD group) stays near half of a 4 MB L2.
+int auto_segments(const psi_operator* op, int bytes) {
+  const double xb = static_cast<double>(op->n) * bytes;
+  if (xb <= 3.0e6) return 1;
+  int S = 2;
+  while (S < 8 && xb / S > 2.5e6) S *= 2;
+  return S;
+}
+
+psi_status resolve_segments(const psi_operator* op, int requested, int bytes, int* S) {
+  PSI_REQUIRE(requested == 0 || requested == 1 || requested == 2 || requested == 4 ||
+                  requested == 8,
+              "col_segments must be 0, 1, 2, 4 or 8");
+  *S = requested ? requested : auto_segments(op, bytes);
+  return PSI_OK;
+}
+
+psi_status prepare(psi_operator* op, int tile, int S, hipStream_t st) {
+  psi_status s = ensure_schedule(op, tile, st);
+  if (s != PSI_OK || S <= 1) return s;
+  return ensure_segments(op, S, tile, st);
+}
+
+// A pass in the column-segmented form when S > 1 (the weighted form has none).
+psi_status run_pass(psi_operator* op, int S, PassMode mode, const PassArgs& a, hipStream_t st) {
+  if (S > 1 && mode != kStep64W) return launch_pass_seg(op, mode, a, st);
+  return launch_pass(op, mode, a, st);
+}
+
 // Enqueue passes until the device sets done; make(i) gives the arguments of
 // pass i (i counts passes enqueued in this call).
 template <class Make>
-psi_status iterate(psi_operator* op, int ctrl_idx, PassMode mode, Make make, int max_iter,
+psi_status iterate(psi_operator* op, int S, int ctrl_idx, PassMode mode, Make make, int max_iter,
                    int check_every, hipStream_t st, IterResult* out) {
   Ctrl* dctrl = op->ctrl + ctrl_idx;
   Ctrl* hctrl = op->host_ctrl + ctrl_idx;
@@ -127,7 +157,7 @@ psi_status iterate(psi_operator* op, int ctrl_idx, PassMode mode, Make make, int
   while (true) {
     const int cnt = std::min(k, max_iter - enq);
     for (int i = 0; i < cnt; ++i) {
-      psi_status s = launch_pass(op, mode, make(enq + i), st);
+      psi_status s = run_pass(op, S, mode, make(enq + i), st);
       if (s != PSI_OK) return s;
     }
     enq += cnt;
@@ -193,7 +223,12 @@ psi_status solve(psi_operator* op, const psi_params* prm, const double* s0, doub
   const int tile = prm->tile_items ? prm->tile_items : (op->sched_items ? op->sched_items
                                                                         : kDefaultTileItems);
   PSI_REQUIRE(tile_items_supported(tile), "unsupported tile_items");
-  psi_status s = ensure_schedule(op, tile, st);
+  int S = 1;
+  psi_status s = resolve_segments(op, prm->col_segments,
+                                  prm->precision == PSI_PREC_FP64 ? 8 : 4, &S);
+  if (s != PSI_OK) return s;
+  if (prm->precision == PSI_PREC_FP64_WEIGHTED) S = 1;
+  s = prepare(op, tile, S, st);
   if (s != PSI_OK) return s;
 
   const int64_t n = op->n;
@@ -224,7 +259,7 @@ psi_status solve(psi_operator* op, const psi_params* prm, const double* s0, doub
       a.count_iter = 0;
       a.respect_done = 0;
       a.ctrl = op->ctrl + 1;
-      s = launch_pass(op, kStep64, a, st);
+      s = run_pass(op, S, kStep64, a, st);
       if (s != PSI_OK) return s;
       inf.spmv_passes += 1;
     }
@@ -259,7 +294,7 @@ psi_status solve(psi_operator* op, const psi_params* prm, const double* s0, doub
       a.ctrl = op->ctrl;
       return a;
     };
-    return iterate(op, 0, mode, make, max_iter, prm->check_every, st, res);
+    return iterate(op, S, 0, mode, make, max_iter, prm->check_every, st, res);
   };
 
   if (prec == PSI_PREC_FP64 || prec == PSI_PREC_FP64_WEIGHTED) {
@@ -301,7 +336,7 @@ psi_status solve(psi_operator* op, const psi_params* prm, const double* s0, doub
       return a;
     };
     IterResult res;
-    s = iterate(op, 0, kStep32, make, prm->max_iter, prm->check_every, st, &res);
+    s = iterate(op, S, 0, kStep32, make, prm->max_iter, prm->check_every, st, &res);
     if (s != PSI_OK) return s;
     inf.iterations = res.iters;
     inf.fp32_passes = res.iters;
@@ -337,7 +372,7 @@ psi_status solve(psi_operator* op, const psi_params* prm, const double* s0, doub
       a.count_iter = 1;
       a.respect_done = 0;
       a.ctrl = op->ctrl;
-      s = launch_pass(op, kStep64, a, st);
+      s = run_pass(op, S, kStep64, a, st);
       if (s != PSI_OK) return s;
       ++fp64_passes;
       Ctrl* h = op->host_ctrl;
@@ -387,7 +422,7 @@ psi_status solve(psi_operator* op, const psi_params* prm, const double* s0, doub
         return b;
       };
       IterResult res;
-      s = iterate(op, 1, kStep32, make, prm->max_iter, prm->check_every, st, &res);
+      s = iterate(op, S, 1, kStep32, make, prm->max_iter, prm->check_every, st, &res);
       if (s != PSI_OK) return s;
       inf.fp32_passes += res.iters;
       if (res.status == PSI_ENUMERIC) {
@@ -414,7 +449,7 @@ psi_status solve(psi_operator* op, const psi_params* prm, const double* s0, doub
     a.s_new = psi_out;
     a.count_iter = 0;
     a.respect_done = 0;
-    s = launch_pass(op, kFinal64, a, st);
+    s = run_pass(op, S, kFinal64, a, st);
     if (s != PSI_OK) return s;
     inf.spmv_passes += 1;
   }
@@ -436,7 +471,7 @@ psi_status solve(psi_operator* op, const psi_params* prm, const double* s0, doub
 }
 
 psi_status step(psi_operator* op, int precision, const double* s_in, double* s_out,
-                double* gap_out, int tile_items, hipStream_t st) {
+                double* gap_out, int tile_items, int col_segments, hipStream_t st) {
   PSI_REQUIRE(s_in && s_out && s_in != s_out, "s_in and s_out must be distinct device arrays");
   PSI_REQUIRE(precision == PSI_PREC_FP64 || precision == PSI_PREC_FP64_WEIGHTED,
               "psi_step supports PSI_PREC_FP64 and PSI_PREC_FP64_WEIGHTED");
@@ -444,7 +479,11 @@ psi_status step(psi_operator* op, int precision, const double* s_in, double* s_o
               "weighted step needs an operator built with PSI_WEIGHTED_FP64");
   const int tile = tile_items ? tile_items : (op->sched_items ? op->sched_items : kDefaultTileItems);
   PSI_REQUIRE(tile_items_supported(tile), "unsupported tile_items");
-  psi_status s = ensure_schedule(op, tile, st);
+  int S = 1;
+  psi_status s = resolve_segments(op, col_segments, 8, &S);
+  if (s != PSI_OK) return s;
+  if (precision == PSI_PREC_FP64_WEIGHTED) S = 1;
+  s = prepare(op, tile, S, st);
   if (s != PSI_OK) return s;
   PassArgs a = base_args(op);
   a.s_old = s_in;
@@ -458,26 +497,27 @@ psi_status step(psi_operator* op, int precision, const double* s_in, double* s_o
     hipLaunchKernelGGL(k_make_z, dim3(grid_for(op->n)), dim3(kBlock), 0, st, s_in, op->invden,
                        op->n, op->z_a);
     a.x = op->z_a;
-    return launch_pass(op, kStep64, a, st);
+    return run_pass(op, S, kStep64, a, st);
   }
   a.x = s_in;
-  return launch_pass(op, kStep64W, a, st);
+  return run_pass(op, 1, kStep64W, a, st);
 }
 
 psi_status final_psi(psi_operator* op, const double* s_vec, double* psi_out, hipStream_t st) {
   PSI_REQUIRE(s_vec && psi_out, "s and psi_out must not be NULL");
-  psi_status s = ensure_schedule(op, op->sched_items ? op->sched_items : kDefaultTileItems, st);
+  const int S = auto_segments(op, 8);
+  psi_status s = prepare(op, op->sched_items ? op->sched_items : kDefaultTileItems, S, st);
   if (s != PSI_OK) return s;
   hipLaunchKernelGGL(k_make_z, dim3(grid_for(op->n)), dim3(kBlock), 0, st, s_vec, op->invden,
                      op->n, op->z_a);
   PassArgs a = base_args(op);
   a.x = op->z_a;
   a.s_new = psi_out;
-  return launch_pass(op, kFinal64, a, st);
+  return run_pass(op, S, kFinal64, a, st);
 }
 
-psi_status pass_time(psi_operator* op, int kind, int reps, int tile_items, double* mean_ms,
-                     hipStream_t st) {
+psi_status pass_time(psi_operator* op, int kind, int reps, int tile_items, int col_segments,
+                     double* mean_ms, hipStream_t st) {
   PSI_REQUIRE(mean_ms, "mean_ms must not be NULL");
   PSI_REQUIRE(reps >= 1, "reps must be >= 1");
   PSI_REQUIRE(kind >= PSI_PASS_STEP64 && kind <= PSI_PASS_STEP32, "unknown pass kind");
@@ -485,7 +525,11 @@ psi_status pass_time(psi_operator* op, int kind, int reps, int tile_items, doubl
               "the weighted pass needs an operator built with PSI_WEIGHTED_FP64");
   const int tile = tile_items ? tile_items : (op->sched_items ? op->sched_items : kDefaultTileItems);
   PSI_REQUIRE(tile_items_supported(tile), "unsupported tile_items");
-  psi_status s = ensure_schedule(op, tile, st);
+  int S = 1;
+  psi_status s = resolve_segments(op, col_segments, kind == PSI_PASS_STEP32 ? 4 : 8, &S);
+  if (s != PSI_OK) return s;
+  if (kind == PSI_PASS_STEP64_W) S = 1;
+  s = prepare(op, tile, S, st);
   if (s != PSI_OK) return s;
   const int64_t n = op->n;
   hipLaunchKernelGGL(k_init64, dim3(grid_for(n)), dim3(kBlock), 0, st, nullptr, op->c, op->invden,
@@ -520,14 +564,14 @@ psi_status pass_time(psi_operator* op, int kind, int reps, int tile_items, doubl
     }
     return a;
   };
-  s = launch_pass(op, mode, make(0), st);
+  s = run_pass(op, S, mode, make(0), st);
   if (s != PSI_OK) return s;
   Timer tm;
   PSI_HIP_CHECK(hipEventCreate(&tm.a));
   PSI_HIP_CHECK(hipEventCreate(&tm.b));
   PSI_HIP_CHECK(hipEventRecord(tm.a, st));
   for (int i = 1; i <= reps; ++i) {
-    s = launch_pass(op, mode, make(i), st);
+    s = run_pass(op, S, mode, make(i), st);
     if (s != PSI_OK) return s;
   }
   PSI_HIP_CHECK(hipEventRecord(tm.b, st));

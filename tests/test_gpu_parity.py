@@ -137,6 +137,39 @@ def test_step_matches_oracle(gpu_lib, tile):
     np.testing.assert_allclose(psi, (B.T @ s_in + d) / g.n, rtol=1e-13, atol=0)
 
 
+@pytest.mark.parametrize("segs", [2, 4, 8])
+@pytest.mark.parametrize("tile", [1024, 2048, 4096])
+def test_segmented_step_matches_oracle(gpu_lib, segs, tile):
+    """Column-segmented pass (per-XCD-group partials + combine) vs the oracle."""
+    api = gpu_lib
+    g = synth.chung_lu(40000, 15, 2.1, 13, sigma=2.0)
+    op = gpu_op(api, g)
+    A, B, c, d = oracle.operator(g.n, g.follower, g.leader, g.lam, g.mu)
+    s_in = np.random.default_rng(2).uniform(0.5, 3.0, g.n)
+    expect = A.T @ s_in + c
+    out, gap = op.step(torch.tensor(s_in, device="cuda"), tile_items=tile, col_segments=segs)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(out.cpu().numpy(), expect, rtol=1e-13, atol=0)
+    assert abs(gap.item() - np.abs(expect - s_in).sum()) <= 1e-12 * np.abs(expect - s_in).sum()
+    for _ in range(3):  # bitwise repeatable
+        again, gap2 = op.step(torch.tensor(s_in, device="cuda"), tile_items=tile, col_segments=segs)
+        torch.cuda.synchronize()
+        assert torch.equal(again, out) and torch.equal(gap2, gap)
+
+
+@pytest.mark.parametrize("prec,tol,bar", [("fp64", 1e-9, 1e-9), ("mixed", 1e-9, 1e-9),
+                                          ("fp32", 1e-5, 1e-6)])
+@pytest.mark.parametrize("segs", [1, 2, 4, 8])
+def test_segmented_solve(gpu_lib, prec, tol, bar, segs):
+    api = gpu_lib
+    g = synth.chung_lu(60000, 20, 2.2, 14, sigma=1.5)
+    A, B, c, d, r = oracle_run(g, tol)
+    op = gpu_op(api, g)
+    psi, info = op.solve(tol=tol, precision=prec, col_segments=segs)
+    assert info["status"] == 0, info
+    assert oracle.rel_l1(r["psi"], psi.cpu().numpy()) <= bar
+
+
 def test_step_bitwise_repeatable(gpu_lib):
     api = gpu_lib
     g = synth.chung_lu(200000, 20, 2.1, 12, sigma=2.0)
