@@ -33,10 +33,14 @@ WORKLOAD = "cl_1m"
 PEAK_HBM_GBS = 8000.0
 
 
-def algorithmic_bytes(kind: str, n: int, m: int) -> int:
-    """Compulsory HBM bytes of one pass (each array touched once)."""
+def algorithmic_bytes(kind: str, n: int, m: int, segs: int = 1) -> int:
+    """Compulsory HBM bytes of one launch (each array touched once)."""
     if kind == "step64":     # col 4M; row_ptr 4, z 8, c 8, mu 8, invden 8, s_old 8, s_new 8, z_new 8
         return 4 * m + 60 * n
+    if kind == "part64":     # col 4M; S row_ptrs 4SN; z 8N; S partials written 8SN
+        return 4 * m + (12 * segs + 8) * n
+    if kind == "part32":     # col 4M; S row_ptrs 4SN; ze 4N; S FP32 partials 4SN
+        return 4 * m + (8 * segs + 4) * n
     if kind == "step64_w":   # col 4M + val 8M; row_ptr 4, s 8, c 8, s_new 8
         return 12 * m + 28 * n
     if kind == "step32":     # col 4M; row_ptr 4, ze 4, r 4, mu 4, invden 4, e_old 4, e_new 4, ze_new 4
@@ -163,15 +167,24 @@ def main() -> int:
     value = passes * m / (ms * 1e-3) / 1e9
 
     # dominant kernel: per-launch time with HIP events on the stream it runs on
-    kind = "step32" if head == "mixed" else "step64"
+    segs = info["col_segments"]
     pass_ms = {k: op.pass_time(k, reps=50) for k in ("step64", "step64_w", "step32", "final64")}
-    alg = algorithmic_bytes(kind, g.n, m)
+    if segs > 1:
+        kind = "part32" if head == "mixed" else "part64"
+        kernel = f"k_pass_seg<{info['tile_items'] // 256}, {5 if head == 'mixed' else 4}>"
+        pass_ms[kind] = op.pass_time(kind, reps=50, col_segments=segs)
+    else:
+        kind = "step32" if head == "mixed" else "step64"
+        kernel = f"k_pass<{info['tile_items'] // 256}, {3 if head == 'mixed' else 0}>"
+    alg = algorithmic_bytes(kind, g.n, m, segs)
     achieved = alg / (pass_ms[kind] * 1e-3) / 1e9
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=PEAK_HBM_GBS, unit="GB/s",
                     frac=round(achieved / PEAK_HBM_GBS, 4),
                     traffic=traffic_from_profile(kind, 1),
-                    kernel=f"k_pass<{kind}>", algorithmic_bytes=alg,
-                    mean_launch_us=round(pass_ms[kind] * 1e3, 2))
+                    kernel=kernel, algorithmic_bytes=alg, col_segments=segs,
+                    mean_launch_us=round(pass_ms[kind] * 1e3, 2),
+                    gathers_per_s=round(m / (pass_ms[kind] * 1e-3) / 1e9, 1),
+                    gather_unit="G random lines/s")
 
     if args.copy_calibration:
         a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
@@ -189,7 +202,8 @@ def main() -> int:
         "config": {"workload": "directed Chung-Lu, N=1,000,000, mean degree 20, exponent 2.2, "
                                "lambda,mu ~ LogNormal(0,1.5), tol 1e-8 (L1 step), int32 CSR",
                    "n_users": g.n, "n_edges": m, "max_followers": st["max_followers"],
-                   "tol": tol, "headline_mode": head, "parallelism": "single GPU"},
+                   "tol": tol, "headline_mode": head, "col_segments": info["col_segments"],
+                   "tile_items": info["tile_items"], "parallelism": "single GPU"},
         "time_to_psi_ms": {p: round(v["ms"], 4) for p, v in modes.items()},
         "passes": {p: v["info"]["spmv_passes"] for p, v in modes.items()},
         "speedup_vs_plain_fp64": round(modes["fp64_weighted"]["ms"] / ms, 3),

@@ -102,6 +102,8 @@ typedef struct psi_info {
     int32_t fp32_passes;      /* FP32 correction passes (MIXED / FP32)        */
     int32_t refinements;      /* FP64 residual evaluations (MIXED)            */
     int32_t used_s0;          /* 1 if the given s0 was used, 0 if c was       */
+    int32_t col_segments;     /* column segments the passes used             */
+    int32_t tile_items;       /* merge-path tile size the passes used        */
     double final_gap;         /* last gap in the tol_mode's units            */
     double final_l1_step;     /* last ‖s_t − s_{t−1}‖₁                        */
     double b_norm;
@@ -196,6 +198,8 @@ psi_status psi_final(psi_operator* op, const double* s, double* psi_out, void* s
 #define PSI_PASS_STEP64_W   1  /* FP64 weighted step: s' = c + Σ_j a_ji s_j           */
 #define PSI_PASS_FINAL64    2  /* ψ = (λ⊙Σ_{j∈F(i)} s_j/den_j + d)/N                 */
 #define PSI_PASS_STEP32     3  /* FP32 correction step: e' = r + μ⊙Σ e_j/den_j        */
+#define PSI_PASS_PART64     4  /* only the per-segment partial kernel of STEP64       */
+#define PSI_PASS_PART32     5  /* only the per-segment partial kernel of STEP32       */
 
 /* Time `reps` back-to-back launches of one operator pass (the kernels a solve
  * runs in its loop: with col_segments > 1 the partial pass and the combine),

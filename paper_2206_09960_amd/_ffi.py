@@ -24,6 +24,7 @@ PSI_PREC_FP64, PSI_PREC_FP64_WEIGHTED, PSI_PREC_MIXED, PSI_PREC_FP32 = 0, 1, 2, 
 PSI_NO_FALLBACK = 0x1
 # pass kinds
 PSI_PASS_STEP64, PSI_PASS_STEP64_W, PSI_PASS_FINAL64, PSI_PASS_STEP32 = 0, 1, 2, 3
+PSI_PASS_PART64, PSI_PASS_PART32 = 4, 5
 
 i32, i64, u32, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_double
 vp, sz = ctypes.c_void_p, ctypes.c_size_t
@@ -43,7 +44,8 @@ class Params(ctypes.Structure):
 
 class Info(ctypes.Structure):
     _fields_ = [("status", i32), ("iterations", i32), ("spmv_passes", i32), ("fp32_passes", i32),
-                ("refinements", i32), ("used_s0", i32), ("final_gap", f64),
+                ("refinements", i32), ("used_s0", i32), ("col_segments", i32),
+                ("tile_items", i32), ("final_gap", f64),
                 ("final_l1_step", f64), ("b_norm", f64), ("kappa", f64), ("err_bound_s", f64),
                 ("psi_gap_bound", f64), ("device_ms", f64)]
 

@@ -203,7 +203,8 @@ class Operator:
                   stream=None) -> float:
         """psi_pass_time: mean ms of one launch of a pass kind (HIP events on the stream)."""
         kinds = {"step64": _ffi.PSI_PASS_STEP64, "step64_w": _ffi.PSI_PASS_STEP64_W,
-                 "final64": _ffi.PSI_PASS_FINAL64, "step32": _ffi.PSI_PASS_STEP32}
+                 "final64": _ffi.PSI_PASS_FINAL64, "step32": _ffi.PSI_PASS_STEP32,
+                 "part64": _ffi.PSI_PASS_PART64, "part32": _ffi.PSI_PASS_PART32}
         out = ctypes.c_double()
         with torch.cuda.device(self.device):
             _check(self._lib.psi_pass_time(self._h, kinds[kind], reps, tile_items, col_segments,

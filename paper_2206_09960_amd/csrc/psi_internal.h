@@ -202,6 +202,8 @@ psi_status ensure_segments(psi_operator* op, int S, int tile_items, hipStream_t 
 bool tile_items_supported(int t);
 psi_status launch_pass(psi_operator* op, PassMode mode, const PassArgs& a, hipStream_t stream);
 psi_status launch_pass_seg(psi_operator* op, PassMode mode, const PassArgs& a, hipStream_t stream);
+// Only the per-segment partial kernel of a segmented kStep64 / kStep32 pass.
+psi_status launch_part_seg(psi_operator* op, PassMode mode, const PassArgs& a, hipStream_t stream);
 PassArgs base_args(psi_operator* op);
 
 psi_status solve(psi_operator* op, const psi_params* prm, const double* s0, double* psi_out,

@@ -718,4 +718,19 @@ psi_status launch_pass_seg(psi_operator* op, PassMode mode, const PassArgs& a, h
   return PSI_EINVAL;
 }
 
+psi_status launch_part_seg(psi_operator* op, PassMode mode, const PassArgs& a, hipStream_t st) {
+  SegArgs sg{};
+  sg.S = op->seg_S;
+  for (int s = 0; s < sg.S; ++s) sg.seg[s] = op->seg[s];
+  PassArgs b = a;
+  b.tile_items = op->seg_items;
+  if (mode == kStep32) {
+    for (int s = 0; s < sg.S; ++s)
+      sg.seg[s].y = reinterpret_cast<float*>(op->seg_y) + size_t(s) * op->n;
+    return launch_seg_mode<kPart32>(b, sg, st);
+  }
+  for (int s = 0; s < sg.S; ++s) sg.seg[s].y = op->seg_y + size_t(s) * op->n;
+  return launch_seg_mode<kPart64>(b, sg, st);
+}
+
 }  // namespace psi

@@ -244,6 +244,8 @@ psi_status solve(psi_operator* op, const psi_params* prm, const double* s0, doub
   inf.b_norm = bnorm;
   inf.kappa = kap;
   inf.used_s0 = s0 ? 1 : 0;
+  inf.col_segments = S;
+  inf.tile_items = tile;
 
   // optional start: keep s0 only if its fixed-point residual beats c's
   if (s0 && !(prm->flags & PSI_NO_FALLBACK)) {
@@ -520,7 +522,10 @@ psi_status pass_time(psi_operator* op, int kind, int reps, int tile_items, int c
                      double* mean_ms, hipStream_t st) {
   PSI_REQUIRE(mean_ms, "mean_ms must not be NULL");
   PSI_REQUIRE(reps >= 1, "reps must be >= 1");
-  PSI_REQUIRE(kind >= PSI_PASS_STEP64 && kind <= PSI_PASS_STEP32, "unknown pass kind");
+  PSI_REQUIRE(kind >= PSI_PASS_STEP64 && kind <= PSI_PASS_PART32, "unknown pass kind");
+  const bool part_only = kind == PSI_PASS_PART64 || kind == PSI_PASS_PART32;
+  if (kind == PSI_PASS_PART64) kind = PSI_PASS_STEP64;
+  if (kind == PSI_PASS_PART32) kind = PSI_PASS_STEP32;
   PSI_REQUIRE(kind != PSI_PASS_STEP64_W || op->val64,
               "the weighted pass needs an operator built with PSI_WEIGHTED_FP64");
   const int tile = tile_items ? tile_items : (op->sched_items ? op->sched_items : kDefaultTileItems);
@@ -529,6 +534,7 @@ psi_status pass_time(psi_operator* op, int kind, int reps, int tile_items, int c
   psi_status s = resolve_segments(op, col_segments, kind == PSI_PASS_STEP32 ? 4 : 8, &S);
   if (s != PSI_OK) return s;
   if (kind == PSI_PASS_STEP64_W) S = 1;
+  PSI_REQUIRE(!part_only || S > 1, "a partial pass needs col_segments > 1");
   s = prepare(op, tile, S, st);
   if (s != PSI_OK) return s;
   const int64_t n = op->n;
@@ -564,14 +570,17 @@ psi_status pass_time(psi_operator* op, int kind, int reps, int tile_items, int c
     }
     return a;
   };
-  s = run_pass(op, S, mode, make(0), st);
+  auto launch = [&](const PassArgs& a) {
+    return part_only ? launch_part_seg(op, mode, a, st) : run_pass(op, S, mode, a, st);
+  };
+  s = launch(make(0));
   if (s != PSI_OK) return s;
   Timer tm;
   PSI_HIP_CHECK(hipEventCreate(&tm.a));
   PSI_HIP_CHECK(hipEventCreate(&tm.b));
   PSI_HIP_CHECK(hipEventRecord(tm.a, st));
   for (int i = 1; i <= reps; ++i) {
-    s = run_pass(op, S, mode, make(i), st);
+    s = launch(make(i));
     if (s != PSI_OK) return s;
   }
   PSI_HIP_CHECK(hipEventRecord(tm.b, st));
