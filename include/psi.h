@@ -50,7 +50,6 @@ typedef enum psi_status {
 #define PSI_INPUT_HOST       0x1u  /* follower/leader/lambda/mu are host pointers   */
 #define PSI_STRICT           0x2u  /* self-loops or repeated edges are an error     */
 #define PSI_WEIGHTED_FP64    0x4u  /* also store a_ji per edge in FP64 (weighted form) */
-#define PSI_FOLLOWER_MAJOR   0x8u  /* also keep CSR(A) (rows = followers)           */
 
 /* ---- tolerance modes (how the gap of eq. eps_t is compared with tol) ------ */
 #define PSI_TOL_ABS_L1  0  /* ‖s_t − s_{t−1}‖₁ ≤ tol   (eq. condition)            */
@@ -192,6 +191,25 @@ psi_status psi_step(psi_operator* op, int32_t precision, const double* s_in, dou
 /* The last line of Algorithm 2, enqueued only: psi_out = (Bᵀ s + d)/N.
  * s, psi_out: device FP64 [N]. */
 psi_status psi_final(psi_operator* op, const double* s, double* psi_out, void* stream);
+
+/* Device workspace (bytes) of psi_solve_batched on this operator. */
+psi_status psi_batched_workspace_size(const psi_operator* op, int32_t n_scenarios, size_t* bytes);
+
+/* Many independent Power-ψ solves in one call.
+ * Scenario mode (n_scenarios = K ≥ 1, lambda and mu given): K activity
+ * scenarios on the operator's graph — scenario k has rates
+ * lambda[i*K + k], mu[i*K + k] (device FP64, user-major [N × K]) and its own
+ * A, B, c, d (Sec. II) — solved together as one multi-vector pass per step
+ * (scenarios in tiles of 64).  Each scenario runs Algorithm 2 to its own
+ * tolerance and is frozen afterwards; psi_out[i*K + k] (device FP64 [N × K])
+ * is its ψ; infos[k] (host, may be NULL) its iteration count and gap.
+ * The operator's own λ, μ are not used.  Only PSI_PREC_FP64 and
+ * PSI_TOL_ABS_L1.  Returns the first non-OK scenario status, if any.
+ * workspace: device, at least psi_batched_workspace_size bytes. */
+psi_status psi_solve_batched(psi_operator* op, const psi_params* prm, int32_t n_scenarios,
+                             const double* lambda, const double* mu, double* psi_out,
+                             psi_info* infos, void* workspace, size_t workspace_bytes,
+                             void* stream);
 
 /* ---- operator pass kinds (for timing and tuning) -------------------------- */
 #define PSI_PASS_STEP64     0  /* FP64 factored step: s' = c + μ⊙Σ_{j∈F(i)} s_j/den_j */

@@ -15,7 +15,6 @@ STATUS_NAMES = {0: "PSI_OK", 1: "PSI_EINVAL", 2: "PSI_ENOTCONV", 3: "PSI_ESTAGNA
 PSI_INPUT_HOST = 0x1
 PSI_STRICT = 0x2
 PSI_WEIGHTED_FP64 = 0x4
-PSI_FOLLOWER_MAJOR = 0x8
 # tolerance modes
 PSI_TOL_ABS_L1, PSI_TOL_BNORM, PSI_TOL_REL_L1 = 0, 1, 2
 # precisions
@@ -70,6 +69,9 @@ SIGNATURES = [
     ("psi_step", i32, [vp, i32, vp, vp, vp, i32, i32, vp]),
     ("psi_final", i32, [vp, vp, vp, vp]),
     ("psi_pass_time", i32, [vp, i32, i32, i32, i32, ctypes.POINTER(f64), vp]),
+    ("psi_batched_workspace_size", i32, [vp, i32, ctypes.POINTER(sz)]),
+    ("psi_solve_batched", i32, [vp, ctypes.POINTER(Params), i32, vp, vp, vp, ctypes.POINTER(Info),
+                                vp, sz, vp]),
 ]
 
 _lib = None

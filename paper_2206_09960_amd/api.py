@@ -12,7 +12,7 @@ import numpy as np
 import torch
 
 from . import _ffi
-from ._ffi import (PSI_FOLLOWER_MAJOR, PSI_INPUT_HOST, PSI_NO_FALLBACK, PSI_PREC_FP32,  # noqa: F401
+from ._ffi import (PSI_INPUT_HOST, PSI_NO_FALLBACK, PSI_PREC_FP32,  # noqa: F401
                    PSI_PREC_FP64, PSI_PREC_FP64_WEIGHTED, PSI_PREC_MIXED, PSI_STRICT,
                    PSI_TOL_ABS_L1, PSI_TOL_BNORM, PSI_TOL_REL_L1, PSI_WEIGHTED_FP64)
 
@@ -210,6 +210,51 @@ class Operator:
             _check(self._lib.psi_pass_time(self._h, kinds[kind], reps, tile_items, col_segments,
                                            ctypes.byref(out), _stream_handle(stream)))
         return out.value
+
+    def _params(self, tol, tol_mode, max_iter, precision, check_every, tile_items=0,
+                col_segments=0, inner_tol=0.0, no_fallback=False):
+        p = _ffi.Params()
+        _check(self._lib.psi_params_default(ctypes.byref(p)))
+        p.tol = tol
+        p.tol_mode = TOL_MODES[tol_mode] if isinstance(tol_mode, str) else int(tol_mode)
+        p.max_iter = max_iter
+        p.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        p.check_every = check_every
+        p.flags = PSI_NO_FALLBACK if no_fallback else 0
+        p.tile_items = tile_items
+        p.col_segments = col_segments
+        p.inner_tol = inner_tol
+        return p
+
+    def solve_batched(self, lam: torch.Tensor, mu: torch.Tensor, tol: float = 1e-8,
+                      max_iter: int = 10000, check_every: int = 0, stream=None,
+                      raise_on_status: bool = False):
+        """psi_solve_batched, scenario mode: lam, mu [N × K] (one column per
+        scenario); returns (psi [N × K], list of K info dicts)."""
+        lam = lam.to(self.device, torch.float64).contiguous()
+        mu = mu.to(self.device, torch.float64).contiguous()
+        if lam.dim() != 2 or lam.shape != mu.shape or lam.shape[0] != self.n:
+            raise ValueError("lam and mu must both be [n_users, n_scenarios]")
+        k = int(lam.shape[1])
+        p = self._params(tol, "abs_l1", max_iter, "fp64", check_every)
+        nbytes = ctypes.c_size_t()
+        _check(self._lib.psi_batched_workspace_size(self._h, k, ctypes.byref(nbytes)))
+        ws = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+        psi = torch.empty((self.n, k), dtype=torch.float64, device=self.device)
+        infos = (_ffi.Info * k)()
+        with torch.cuda.device(self.device):
+            st = self._lib.psi_solve_batched(self._h, ctypes.byref(p), k, lam.data_ptr(),
+                                             mu.data_ptr(), psi.data_ptr(), infos, ws.data_ptr(),
+                                             nbytes.value, _stream_handle(stream))
+        if st in (_ffi.PSI_EINVAL, _ffi.PSI_EDEVICE, _ffi.PSI_ENOSPACE) or (
+                raise_on_status and st != _ffi.PSI_OK):
+            _check(st)
+        out = []
+        for i in range(k):
+            d = _ffi.struct_dict(infos[i])
+            d["status_name"] = _ffi.STATUS_NAMES.get(d["status"], str(d["status"]))
+            out.append(d)
+        return psi, out
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

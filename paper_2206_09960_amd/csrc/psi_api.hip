@@ -222,4 +222,24 @@ psi_status psi_pass_time(psi_operator* op, int32_t pass_kind, int32_t reps, int3
   PSI_GUARD_END
 }
 
+psi_status psi_batched_workspace_size(const psi_operator* op, int32_t n_scenarios, size_t* bytes) {
+  PSI_GUARD_BEGIN
+  PSI_REQUIRE(op, "op must not be NULL");
+  return psi::batched_workspace_size(op, n_scenarios, bytes);
+  PSI_GUARD_END
+}
+
+psi_status psi_solve_batched(psi_operator* op, const psi_params* prm, int32_t n_scenarios,
+                             const double* lambda, const double* mu, double* psi_out,
+                             psi_info* infos, void* workspace, size_t workspace_bytes,
+                             void* stream) {
+  PSI_GUARD_BEGIN
+  PSI_REQUIRE(op, "op must not be NULL");
+  psi_status st = psi::check_device(op);
+  if (st != PSI_OK) return st;
+  return psi::solve_batched(op, prm, n_scenarios, lambda, mu, psi_out, infos, workspace,
+                            workspace_bytes, static_cast<hipStream_t>(stream));
+  PSI_GUARD_END
+}
+
 }  // extern "C"

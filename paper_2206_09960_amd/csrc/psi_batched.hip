@@ -1,0 +1,592 @@
+// Batched Power-ψ: K activity scenarios (λ^k, μ^k) on one follower graph.
+//
+// Every scenario has its own A^k, B^k, c^k, d^k (Sec. II, the definitions of
+// A, b_i, C, d_i), but all share the edge pattern, so one pass is a
+// multi-vector product over CSR(Aᵀ): y_i^k = Σ_{j∈F(i)} s_j^k / den_j^k.  The
+// iterates are stored user-major, [N × Kc] with Kc ≤ 64 scenarios per tile of
+// the batch, so an edge gathers one contiguous Kc-vector and each lane of a
+// wave owns one scenario.  Scenarios are independent solves of Algorithm 2:
+// each has its own gap, stops at its own iteration (and is frozen afterwards)
+// and gets ψ^k from its own final s^k.
+//
+// Work split.  Rows (leaders) with at most kHubEdges followers are packed
+// whole into wave tiles of about kWaveItems merge-path items; a wave sums its
+// rows edge by edge in order.  Longer rows are cut into chunks of kChunkEdges
+// edges; a workgroup reduces each chunk in a fixed order and a finishing
+// kernel adds a row's chunks in chunk order.  Every sum has a fixed order, so
+// batched solves are bitwise repeatable.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "psi_internal.h"
+
+namespace psi {
+
+namespace {
+
+constexpr int kWaveItems = 256;    // merge-path items per wave tile
+constexpr int kHubEdges = 256;     // rows longer than this are chunked
+constexpr int kChunkEdges = 1024;  // edges per hub chunk
+constexpr int kMaxK = 64;          // scenarios per batch tile (one per lane)
+
+inline unsigned grid_for(int64_t n, int block = kBlock) {
+  return static_cast<unsigned>((n + block - 1) / block);
+}
+inline size_t align_up(size_t x) { return (x + 255) / 256 * 256; }
+
+struct BatchCtrl {
+  Ctrl c;          // global: done when every scenario is done
+  int kdone[kMaxK];
+  int kiter[kMaxK];
+  int kstatus[kMaxK];
+  double kgap[kMaxK];
+};
+
+// Workspace of one batch tile (reused for every tile of Kc scenarios).
+struct BatchWs {
+  double *lam, *mu, *c, *d, *invden;
+  double *s_a, *s_b, *z_a, *z_b;
+  int* row_tiles;      // [n_wtiles + 1]
+  int* hub_rows;       // [max_hubs]
+  int* hub_chunk0;     // [max_hubs + 1] first chunk of each hub
+  int* chunk_row;      // [max_chunks]
+  int* chunk_e0;       // [max_chunks]
+  uint32_t* flags;     // [n + 1] scratch for the hub scan
+  uint32_t* scan_tmp;
+  double* chunk_part;  // [max_chunks × Kc]
+  double* gap_blk;     // [kMaxGrid × Kc]
+  double* gap_hub;     // [max_hubs × Kc]
+  BatchCtrl* ctrl;
+  BatchCtrl* host_ctrl;  // not in the workspace
+  int64_t n_wtiles, max_hubs, max_chunks;
+};
+
+size_t batch_layout(int64_t n, int64_t m, BatchWs* w, char* base) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char* {
+    char* p = base ? base + off : nullptr;
+    off += align_up(std::max<size_t>(bytes, 1));
+    return p;
+  };
+  const int64_t n_wtiles = (n + m) / kWaveItems + 2;
+  const int64_t max_hubs = m / (kHubEdges + 1) + 1;
+  const int64_t max_chunks = m / kChunkEdges + max_hubs + 1;
+  const size_t nk = 8 * size_t(n) * kMaxK;
+  BatchWs t{};
+  t.lam = (double*)take(nk);
+  t.mu = (double*)take(nk);
+  t.c = (double*)take(nk);
+  t.d = (double*)take(nk);
+  t.invden = (double*)take(nk);
+  t.s_a = (double*)take(nk);
+  t.s_b = (double*)take(nk);
+  t.z_a = (double*)take(nk);
+  t.z_b = (double*)take(nk);
+  t.row_tiles = (int*)take(4 * size_t(n_wtiles + 1));
+  t.hub_rows = (int*)take(4 * size_t(max_hubs));
+  t.hub_chunk0 = (int*)take(4 * size_t(max_hubs + 1));
+  t.chunk_row = (int*)take(4 * size_t(max_chunks));
+  t.chunk_e0 = (int*)take(4 * size_t(max_chunks));
+  t.flags = (uint32_t*)take(4 * size_t(n + 1));
+  t.scan_tmp = (uint32_t*)take(4 * size_t(scan_tile_count(n + 1) + 8));
+  t.chunk_part = (double*)take(8 * size_t(max_chunks) * kMaxK);
+  t.gap_blk = (double*)take(8 * size_t(kMaxGrid) * kMaxK);
+  t.gap_hub = (double*)take(8 * size_t(max_hubs) * kMaxK);
+  t.ctrl = (BatchCtrl*)take(sizeof(BatchCtrl));
+  t.n_wtiles = n_wtiles;
+  t.max_hubs = max_hubs;
+  t.max_chunks = max_chunks;
+  if (w) *w = t;
+  return off;
+}
+
+// ---------------------------------------------------------------- preparation
+// λ^k, μ^k of this tile, user-major [N × Kc], from the caller's [N × K].
+__global__ void k_bprep_act(const double* lam_in, const double* mu_in, int64_t n, int K, int k0,
+                            int Kc, double* lam, double* mu, Ctrl* ctrl) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= n * Kc) return;
+  const int64_t i = t / Kc;
+  const int k = static_cast<int>(t % Kc);
+  const double l = lam_in[i * K + k0 + k], m = mu_in[i * K + k0 + k];
+  if (!(l > 0.0) || !isfinite(l) || !(m >= 0.0) || !isfinite(m))
+    atomicOr(&ctrl->err_flags, kErrActivity);
+  lam[t] = l;
+  mu[t] = m;
+}
+
+// den_j^k = Σ_{ℓ∈L(j)} (λ_ℓ^k + μ_ℓ^k) in ascending ℓ over CSR(A), one wave
+// per follower j, lane k; then 1/den, c, d of user j.
+__global__ void k_bprep_den(const int* fm_row_ptr, const int* fm_col, const double* lam,
+                            const double* mu, int64_t n, int Kc, double* invden, double* c,
+                            double* d) {
+  const int64_t j = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+  const int k = threadIdx.x & 63;
+  if (j >= n || k >= Kc) return;
+  double den = 0.0;
+  for (int e = fm_row_ptr[j]; e < fm_row_ptr[j + 1]; ++e) {
+    const int64_t l = fm_col[e];
+    den += lam[l * Kc + k] + mu[l * Kc + k];
+  }
+  const int64_t t = j * Kc + k;
+  invden[t] = den > 0.0 ? 1.0 / den : 0.0;
+  const double lj = lam[t], mj = mu[t];
+  c[t] = mj / (lj + mj);
+  d[t] = lj / (lj + mj);
+}
+
+__global__ void k_binit(const double* c, const double* invden, int64_t total, double* s,
+                        double* z) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= total) return;
+  s[t] = c[t];
+  z[t] = invden[t] * c[t];
+}
+
+// Wave tiles that hold whole rows: the merge-path row at diagonal b·items,
+// moved past a row that straddles the diagonal.
+__global__ void k_row_tiles(const int* row_ptr, int64_t n, int64_t m, int64_t items,
+                            int64_t n_tiles, int* row_tiles) {
+  const int64_t b = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (b > n_tiles) return;
+  const int64_t diag = std::min(b * items, n + m);
+  int64_t lo = std::max<int64_t>(diag - m, 0), hi = std::min<int64_t>(diag, n);
+  while (lo < hi) {
+    const int64_t p = (lo + hi) >> 1;
+    if (int64_t(row_ptr[p + 1]) <= diag - p - 1) lo = p + 1; else hi = p;
+  }
+  const int64_t e = diag - lo;
+  int64_t r = lo;
+  if (r < n && e > row_ptr[r]) ++r;
+  row_tiles[b] = static_cast<int>(b == n_tiles ? n : r);
+}
+
+__global__ void k_hub_flags(const int* row_ptr, int64_t n, uint32_t* flags) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i > n) return;
+  flags[i] = (i < n && row_ptr[i + 1] - row_ptr[i] > kHubEdges) ? 1u : 0u;
+}
+
+__global__ void k_hub_list(const int* row_ptr, int64_t n, const uint32_t* pos, int* hub_rows,
+                           uint32_t* nchunks) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int len = row_ptr[i + 1] - row_ptr[i];
+  if (len > kHubEdges) {
+    hub_rows[pos[i]] = static_cast<int>(i);
+    nchunks[pos[i]] = static_cast<uint32_t>((len + kChunkEdges - 1) / kChunkEdges);
+  }
+}
+
+__global__ void k_chunk_table(const int* row_ptr, const int* hub_rows, const uint32_t* chunk0,
+                              int n_hubs, int* chunk_row, int* chunk_e0, int* hub_chunk0) {
+  const int h = blockIdx.x * blockDim.x + threadIdx.x;
+  if (h >= n_hubs) return;
+  const int r = hub_rows[h];
+  const int e0 = row_ptr[r], e1 = row_ptr[r + 1];
+  int c = static_cast<int>(chunk0[h]);
+  hub_chunk0[h] = c;
+  for (int e = e0; e < e1; e += kChunkEdges, ++c) {
+    chunk_row[c] = r;
+    chunk_e0[c] = e;
+  }
+}
+
+// ---------------------------------------------------------------- passes
+struct BArgs {
+  const int* row_ptr;
+  const int* col;
+  int n_rows;
+  int Kc;
+  const int* row_tiles;
+  int n_wtiles;
+  const int* hub_rows;
+  const int* hub_chunk0;
+  int n_hubs;
+  const int* chunk_row;
+  const int* chunk_e0;
+  int n_chunks;
+  const double* z;     // gathered [N × Kc]
+  const double* s_old;
+  double* s_new;
+  double* z_new;
+  const double* c;
+  const double* mu;
+  const double* invden;
+  const double* lam;
+  const double* d;
+  double inv_n;
+  double* psi;         // final: psi[r * psi_ld + psi_col0 + k]
+  int psi_ld;
+  int psi_col0;
+  double* chunk_part;
+  double* gap_blk;
+  double* gap_hub;
+  BatchCtrl* ctrl;
+};
+
+// Epilogue of row r for scenario k; a scenario that has met its tolerance
+// keeps its iterate (and contributes no gap).
+template <bool FINAL>
+__device__ inline void bepi(const BArgs& a, int r, int k, double y, bool frozen, double& gap) {
+  const int64_t t = int64_t(r) * a.Kc + k;
+  if constexpr (FINAL) {
+    a.psi[int64_t(r) * a.psi_ld + a.psi_col0 + k] = (a.lam[t] * y + a.d[t]) * a.inv_n;
+  } else {
+    const double so = a.s_old[t];
+    if (frozen) {
+      a.s_new[t] = so;
+      a.z_new[t] = a.z[t];
+      return;
+    }
+    const double sn = a.c[t] + a.mu[t] * y;
+    a.s_new[t] = sn;
+    a.z_new[t] = a.invden[t] * sn;
+    gap += fabs(sn - so);
+  }
+}
+
+// Rows of at most kHubEdges followers: waves walk the wave tiles grid-stride.
+template <bool FINAL>
+__global__ __launch_bounds__(kBlock) void k_spmm_rows(BArgs a) {
+  __shared__ double red[kBlock / 64][kMaxK];
+  if (!FINAL && a.ctrl->c.done) return;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int k = lane < a.Kc ? lane : a.Kc - 1;  // idle lanes shadow the last scenario
+  const bool frozen = !FINAL && a.ctrl->kdone[k];
+  double gap = 0.0;
+  const int stride = gridDim.x * (kBlock / 64);
+  for (int tile = blockIdx.x * (kBlock / 64) + wave; tile < a.n_wtiles; tile += stride) {
+    const int r0 = a.row_tiles[tile], r1 = a.row_tiles[tile + 1];
+    for (int r = r0; r < r1; ++r) {
+      const int e0 = a.row_ptr[r], e1 = a.row_ptr[r + 1];
+      if (e1 - e0 > kHubEdges) continue;  // finished by the hub kernels
+      double y = 0.0;
+      int e = e0;
+      for (; e + 8 <= e1; e += 8) {
+        int j[8];
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) j[u] = a.col[e + u];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = a.z[int64_t(j[u]) * a.Kc + k];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) y += v[u];
+      }
+      for (; e < e1; ++e) y += a.z[int64_t(a.col[e]) * a.Kc + k];
+      if (lane < a.Kc) bepi<FINAL>(a, r, k, y, frozen, gap);
+    }
+  }
+  if constexpr (!FINAL) {
+    red[wave][lane] = gap;
+    __syncthreads();
+    if (wave == 0 && lane < a.Kc)
+      a.gap_blk[int64_t(blockIdx.x) * a.Kc + lane] =
+          ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+  }
+}
+
+// One workgroup per hub chunk: wave w sums edges e0+w, e0+w+4, ...; the four
+// wave sums are added in wave order.
+__global__ __launch_bounds__(kBlock) void k_spmm_hub_chunk(BArgs a, int final_pass) {
+  __shared__ double red[kBlock / 64][kMaxK];
+  if (!final_pass && a.ctrl->c.done) return;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int k = lane < a.Kc ? lane : a.Kc - 1;
+  const int ch = blockIdx.x;
+  const int r = a.chunk_row[ch];
+  const int e0 = a.chunk_e0[ch];
+  const int e1 = min(e0 + kChunkEdges, a.row_ptr[r + 1]);
+  double y = 0.0;
+  int e = e0 + wave;
+  for (; e + 28 < e1; e += 32) {
+    int j[8];
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) j[u] = a.col[e + 4 * u];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = a.z[int64_t(j[u]) * a.Kc + k];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) y += v[u];
+  }
+  for (; e < e1; e += 4) y += a.z[int64_t(a.col[e]) * a.Kc + k];
+  red[wave][lane] = y;
+  __syncthreads();
+  if (wave == 0 && lane < a.Kc)
+    a.chunk_part[int64_t(ch) * a.Kc + lane] =
+        ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+}
+
+// One wave per hub row: its chunks in chunk order, then the epilogue.
+template <bool FINAL>
+__global__ __launch_bounds__(64) void k_spmm_hub_finish(BArgs a) {
+  if (!FINAL && a.ctrl->c.done) return;
+  const int lane = threadIdx.x;
+  const int h = blockIdx.x;
+  if (lane >= a.Kc) return;
+  const bool frozen = !FINAL && a.ctrl->kdone[lane];
+  const int r = a.hub_rows[h];
+  double y = 0.0;
+  for (int ch = a.hub_chunk0[h]; ch < a.hub_chunk0[h + 1]; ++ch)
+    y += a.chunk_part[int64_t(ch) * a.Kc + lane];
+  double gap = 0.0;
+  bepi<FINAL>(a, r, lane, y, frozen, gap);
+  if constexpr (!FINAL) a.gap_hub[int64_t(h) * a.Kc + lane] = gap;
+}
+
+// Per-scenario gaps in a fixed order (workgroups, then hub rows), tolerance
+// test and freezing; done when every scenario is done.
+__global__ __launch_bounds__(1024) void k_batch_gap(BArgs a, int n_blk) {
+  __shared__ double red[16][kMaxK];
+  __shared__ int n_done;
+  BatchCtrl* bc = a.ctrl;
+  if (bc->c.done) return;  // uniform: read by every thread before any barrier
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;  // 16 waves split the partials
+  double g = 0.0;
+  if (lane < a.Kc) {
+    for (int b = wave; b < n_blk; b += 16) g += a.gap_blk[int64_t(b) * a.Kc + lane];
+    for (int h = wave; h < a.n_hubs; h += 16) g += a.gap_hub[int64_t(h) * a.Kc + lane];
+  }
+  red[wave][lane] = g;
+  if (threadIdx.x == 0) n_done = 0;
+  __syncthreads();
+  if (wave == 0 && lane < a.Kc) {
+    double G = 0.0;
+    for (int w = 0; w < 16; ++w) G += red[w][lane];
+    if (!bc->kdone[lane]) {
+      const int it = bc->kiter[lane] + 1;
+      bc->kiter[lane] = it;
+      bc->kgap[lane] = G;
+      if (!isfinite(G)) {
+        bc->kdone[lane] = 1;
+        bc->kstatus[lane] = PSI_ENUMERIC;
+      } else if (G <= bc->c.tol) {
+        bc->kdone[lane] = 1;
+        bc->kstatus[lane] = PSI_OK;
+      } else if (it >= bc->c.max_iter) {
+        bc->kdone[lane] = 1;
+        bc->kstatus[lane] = PSI_ENOTCONV;
+      }
+    }
+    if (bc->kdone[lane]) atomicAdd(&n_done, 1);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    bc->c.iter += 1;
+    if (n_done == a.Kc) bc->c.done = 1;
+  }
+}
+
+__global__ void k_bctrl_init(BatchCtrl* bc, double tol, int max_iter) {
+  bc->c = Ctrl{};
+  bc->c.tol = tol;
+  bc->c.max_iter = max_iter;
+  for (int k = 0; k < kMaxK; ++k) {
+    bc->kdone[k] = 0;
+    bc->kiter[k] = 0;
+    bc->kstatus[k] = PSI_OK;
+    bc->kgap[k] = 0.0;
+  }
+}
+
+int rows_grid() {
+  static int cap = 0;
+  if (!cap) {
+    int dev = 0, per_cu = 0, cus = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_spmm_rows<false>, kBlock, 0);
+    cap = std::min(kMaxGrid, std::max(1, per_cu) * std::max(1, cus));
+  }
+  return cap;
+}
+
+}  // namespace
+
+psi_status batched_workspace_size(const psi_operator* op, int n_scenarios, size_t* bytes) {
+  PSI_REQUIRE(bytes, "bytes must not be NULL");
+  PSI_REQUIRE(n_scenarios >= 1, "n_scenarios must be >= 1");
+  *bytes = batch_layout(op->n, op->m, nullptr, nullptr);
+  return PSI_OK;
+}
+
+psi_status solve_batched(psi_operator* op, const psi_params* prm, int K, const double* lam_in,
+                         const double* mu_in, double* psi_out, psi_info* infos, void* ws,
+                         size_t ws_bytes, hipStream_t st) {
+  PSI_REQUIRE(prm && psi_out && ws, "params, psi_out and workspace must not be NULL");
+  PSI_REQUIRE(lam_in && mu_in, "lambda and mu must not be NULL in scenario mode");
+  PSI_REQUIRE(K >= 1, "n_scenarios must be >= 1");
+  PSI_REQUIRE(prm->tol > 0.0 && std::isfinite(prm->tol), "tol must be finite and > 0");
+  PSI_REQUIRE(prm->max_iter > 0, "max_iter must be > 0");
+  PSI_REQUIRE(prm->tol_mode == PSI_TOL_ABS_L1, "batched solves use PSI_TOL_ABS_L1");
+  PSI_REQUIRE(prm->precision == PSI_PREC_FP64, "batched solves run in PSI_PREC_FP64");
+  PSI_REQUIRE(op->n_graphs == 1, "scenario batches need a single-graph operator");
+  size_t need = batch_layout(op->n, op->m, nullptr, nullptr);
+  if (ws_bytes < need) {
+    set_error("batched workspace smaller than psi_batched_workspace_size reported");
+    return PSI_ENOSPACE;
+  }
+  BatchWs w{};
+  batch_layout(op->n, op->m, &w, static_cast<char*>(ws));
+  const int64_t n = op->n, m = op->m;
+
+  // hub rows and their chunks (depend only on the pattern)
+  hipLaunchKernelGGL(k_hub_flags, dim3(grid_for(n + 1)), dim3(kBlock), 0, st, op->row_ptr, n,
+                     w.flags);
+  psi_status s = scan_exclusive_u32(w.flags, w.flags, n + 1, w.scan_tmp,
+                                    w.scan_tmp + scan_tile_count(n + 1) + 4, st);
+  if (s != PSI_OK) return s;
+  uint32_t n_hubs = 0;
+  PSI_HIP_CHECK(hipMemcpyAsync(&n_hubs, w.flags + n, 4, hipMemcpyDeviceToHost, st));
+  PSI_HIP_CHECK(hipStreamSynchronize(st));
+  uint32_t* nchunks = reinterpret_cast<uint32_t*>(w.chunk_row);  // counts, then scanned in place
+  uint32_t n_chunks = 0;
+  if (n_hubs > 0) {
+    hipLaunchKernelGGL(k_hub_list, dim3(grid_for(n)), dim3(kBlock), 0, st, op->row_ptr, n,
+                       w.flags, w.hub_rows, nchunks);
+    uint32_t* chunk0 = reinterpret_cast<uint32_t*>(w.chunk_e0);
+    PSI_HIP_CHECK(hipMemsetAsync(nchunks + n_hubs, 0, 4, st));
+    s = scan_exclusive_u32(nchunks, chunk0, int64_t(n_hubs) + 1, w.scan_tmp,
+                           w.scan_tmp + scan_tile_count(n + 1) + 4, st);
+    if (s != PSI_OK) return s;
+    PSI_HIP_CHECK(hipMemcpyAsync(&n_chunks, chunk0 + n_hubs, 4, hipMemcpyDeviceToHost, st));
+    PSI_HIP_CHECK(hipStreamSynchronize(st));
+    // hub_chunk0 = chunk0 (copied), then the chunk table overwrites the scratch
+    PSI_HIP_CHECK(hipMemcpyAsync(w.hub_chunk0, chunk0, 4 * size_t(n_hubs + 1),
+                                 hipMemcpyDeviceToDevice, st));
+    hipLaunchKernelGGL(k_chunk_table, dim3(grid_for(n_hubs)), dim3(kBlock), 0, st, op->row_ptr,
+                       w.hub_rows, reinterpret_cast<const uint32_t*>(w.hub_chunk0), int(n_hubs),
+                       w.chunk_row, w.chunk_e0, w.hub_chunk0);
+  }
+  const int64_t n_wtiles = std::max<int64_t>((n + m + kWaveItems - 1) / kWaveItems, 1);
+  hipLaunchKernelGGL(k_row_tiles, dim3(grid_for(n_wtiles + 1)), dim3(kBlock), 0, st, op->row_ptr,
+                     n, m, int64_t(kWaveItems), n_wtiles, w.row_tiles);
+  PSI_HIP_CHECK(hipGetLastError());
+
+  struct Pinned {
+    BatchCtrl* p = nullptr;
+    ~Pinned() {
+      if (p) (void)hipHostFree(p);
+    }
+  } pinned;
+  PSI_HIP_CHECK(hipHostMalloc(reinterpret_cast<void**>(&pinned.p), sizeof(BatchCtrl),
+                              hipHostMallocDefault));
+  w.host_ctrl = pinned.p;
+  const int grid = std::min(rows_grid(), static_cast<int>(n_wtiles));
+  hipEvent_t ev0, ev1;
+  PSI_HIP_CHECK(hipEventCreate(&ev0));
+  PSI_HIP_CHECK(hipEventCreate(&ev1));
+  PSI_HIP_CHECK(hipEventRecord(ev0, st));
+  int worst = PSI_OK;
+  for (int k0 = 0; k0 < K; k0 += kMaxK) {
+    const int Kc = std::min(kMaxK, K - k0);
+    const int64_t nk = n * Kc;
+    hipLaunchKernelGGL(k_bctrl_init, dim3(1), dim3(1), 0, st, w.ctrl, prm->tol, prm->max_iter);
+    hipLaunchKernelGGL(k_bprep_act, dim3(grid_for(nk)), dim3(kBlock), 0, st, lam_in, mu_in, n, K,
+                       k0, Kc, w.lam, w.mu, &w.ctrl->c);
+    hipLaunchKernelGGL(k_bprep_den, dim3(grid_for(n * 64)), dim3(kBlock), 0, st, op->fm_row_ptr,
+                       op->fm_col, w.lam, w.mu, n, Kc, w.invden, w.c, w.d);
+    hipLaunchKernelGGL(k_binit, dim3(grid_for(nk)), dim3(kBlock), 0, st, w.c, w.invden, nk, w.s_a,
+                       w.z_a);
+    PSI_HIP_CHECK(hipGetLastError());
+    BArgs base{};
+    base.row_ptr = op->row_ptr;
+    base.col = op->col;
+    base.n_rows = static_cast<int>(n);
+    base.Kc = Kc;
+    base.row_tiles = w.row_tiles;
+    base.n_wtiles = static_cast<int>(n_wtiles);
+    base.hub_rows = w.hub_rows;
+    base.hub_chunk0 = w.hub_chunk0;
+    base.n_hubs = static_cast<int>(n_hubs);
+    base.chunk_row = w.chunk_row;
+    base.chunk_e0 = w.chunk_e0;
+    base.n_chunks = static_cast<int>(n_chunks);
+    base.c = w.c;
+    base.mu = w.mu;
+    base.invden = w.invden;
+    base.lam = w.lam;
+    base.d = w.d;
+    base.inv_n = 1.0 / static_cast<double>(n);
+    base.chunk_part = w.chunk_part;
+    base.gap_blk = w.gap_blk;
+    base.gap_hub = w.gap_hub;
+    base.ctrl = w.ctrl;
+    auto pass = [&](int i, bool final_pass) -> psi_status {
+      BArgs a = base;
+      const bool even = (i & 1) == 0;
+      a.z = even ? w.z_a : w.z_b;
+      a.s_old = even ? w.s_a : w.s_b;
+      a.s_new = even ? w.s_b : w.s_a;
+      a.z_new = even ? w.z_b : w.z_a;
+      if (final_pass) {
+        a.psi = psi_out;
+        a.psi_ld = K;
+        a.psi_col0 = k0;
+        hipLaunchKernelGGL(k_spmm_rows<true>, dim3(grid), dim3(kBlock), 0, st, a);
+        if (n_chunks) hipLaunchKernelGGL(k_spmm_hub_chunk, dim3(n_chunks), dim3(kBlock), 0, st, a, 1);
+        if (n_hubs) hipLaunchKernelGGL(k_spmm_hub_finish<true>, dim3(n_hubs), dim3(64), 0, st, a);
+      } else {
+        hipLaunchKernelGGL(k_spmm_rows<false>, dim3(grid), dim3(kBlock), 0, st, a);
+        if (n_chunks) hipLaunchKernelGGL(k_spmm_hub_chunk, dim3(n_chunks), dim3(kBlock), 0, st, a, 0);
+        if (n_hubs) hipLaunchKernelGGL(k_spmm_hub_finish<false>, dim3(n_hubs), dim3(64), 0, st, a);
+        hipLaunchKernelGGL(k_batch_gap, dim3(1), dim3(1024), 0, st, a, grid);
+      }
+      PSI_HIP_CHECK(hipGetLastError());
+      return PSI_OK;
+    };
+    // enqueue blocks of passes; passes after the last scenario converged exit at once
+    int enq = 0, chunk = prm->check_every > 0 ? prm->check_every : 8;
+    BatchCtrl* h = w.host_ctrl;
+    while (true) {
+      const int cnt = std::min(chunk, prm->max_iter - enq);
+      for (int i = 0; i < cnt; ++i) {
+        s = pass(enq + i, false);
+        if (s != PSI_OK) return s;
+      }
+      enq += cnt;
+      PSI_HIP_CHECK(hipMemcpyAsync(h, w.ctrl, sizeof(BatchCtrl), hipMemcpyDeviceToHost, st));
+      PSI_HIP_CHECK(hipStreamSynchronize(st));
+      if (h->c.err_flags & kErrActivity) {
+        set_error("activity must satisfy lambda > 0 and mu >= 0, both finite");
+        return PSI_EINVAL;
+      }
+      if (h->c.done || enq >= prm->max_iter) break;
+      if (prm->check_every == 0) chunk = std::min(2 * chunk, 64);
+    }
+    const int passes = h->c.iter;
+    s = pass(passes, true);
+    if (s != PSI_OK) return s;
+    for (int k = 0; k < Kc; ++k) {
+      int stk = h->kdone[k] ? h->kstatus[k] : PSI_ENOTCONV;
+      if (stk != PSI_OK && worst == PSI_OK) worst = stk;
+      if (infos) {
+        psi_info& inf = infos[k0 + k];
+        inf = psi_info{};
+        inf.status = stk;
+        inf.iterations = h->kiter[k];
+        inf.spmv_passes = h->kiter[k] + 1;
+        inf.final_gap = h->kgap[k];
+        inf.final_l1_step = h->kgap[k];
+        inf.col_segments = 1;
+        inf.tile_items = kWaveItems;
+      }
+    }
+  }
+  PSI_HIP_CHECK(hipEventRecord(ev1, st));
+  PSI_HIP_CHECK(hipEventSynchronize(ev1));
+  float ms = 0.f;
+  PSI_HIP_CHECK(hipEventElapsedTime(&ms, ev0, ev1));
+  (void)hipEventDestroy(ev0);
+  (void)hipEventDestroy(ev1);
+  if (infos)
+    for (int k = 0; k < K; ++k) infos[k].device_ms = ms;
+  if (worst != PSI_OK) set_error("a scenario did not converge (see its info)");
+  return static_cast<psi_status>(worst);
+}
+
+}  // namespace psi

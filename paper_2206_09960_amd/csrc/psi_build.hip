@@ -315,6 +315,20 @@ __global__ void k_node_consts(const double* lam, const double* mu, const double*
   c32[i] = float(ci);
 }
 
+// Graph of every user and 1/N of that graph (block-diagonal operators).
+__global__ void k_graph_rows(const int64_t* graph_off, int n_graphs, int64_t n, int* graph_of,
+                             double* inv_ng) {
+  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int lo = 0, hi = n_graphs;
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (graph_off[mid] <= i) lo = mid; else hi = mid;
+  }
+  graph_of[i] = lo;
+  inv_ng[i] = 1.0 / static_cast<double>(graph_off[lo + 1] - graph_off[lo]);
+}
+
 __global__ void k_max_row(const int* row_ptr, int64_t n, Ctrl* ctrl) {
   int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -458,12 +472,10 @@ static void layout_persistent(int64_t n, int64_t m_raw, int n_graphs, uint32_t f
   int64_t max_tiles = (n + m_raw) / kMinTileItems + 2;
   char* row_ptr = take(4 * size_t(n + 1));
   char* col = take(4 * size_t(m_raw));
-  char* fm_row_ptr = nullptr;
-  char* fm_col = nullptr;
-  if (flags & PSI_FOLLOWER_MAJOR) {
-    fm_row_ptr = take(4 * size_t(n + 1));
-    fm_col = take(4 * size_t(m_raw));
-  }
+  char* fm_row_ptr = take(4 * size_t(n + 1));
+  char* fm_col = take(4 * size_t(m_raw));
+  char* graph_of = n_graphs > 1 ? take(4 * size_t(n)) : nullptr;
+  char* inv_ng = n_graphs > 1 ? take(8 * size_t(n)) : nullptr;
   char* lam = take(8 * size_t(n));
   char* mu = take(8 * size_t(n));
   char* c = take(8 * size_t(n));
@@ -504,6 +516,8 @@ static void layout_persistent(int64_t n, int64_t m_raw, int n_graphs, uint32_t f
   op->col = (int*)col;
   op->fm_row_ptr = (int*)fm_row_ptr;
   op->fm_col = (int*)fm_col;
+  op->graph_of = (int*)graph_of;
+  op->inv_ng = (double*)inv_ng;
   op->lam = (double*)lam;
   op->mu = (double*)mu;
   op->c = (double*)c;
@@ -666,8 +680,9 @@ psi_status build_operator(psi_operator* op, const int32_t* follower, const int32
   op->m = m;
 
   // CSR(A): rows = followers j, cols = leaders (in the flags region, or persistent)
-  int* fm_row_ptr = op->fm_row_ptr ? op->fm_row_ptr : fm_row_ptr_tmp;
-  int* fm_col = op->fm_col ? op->fm_col : reinterpret_cast<int*>(sb.flags);
+  int* fm_row_ptr = op->fm_row_ptr;
+  int* fm_col = op->fm_col;
+  (void)fm_row_ptr_tmp;
   if (m > 0) {
     hipLaunchKernelGGL(k_csr_from_keys, dim3(grid_for(m)), dim3(kBlock), 0, st, sorted, m, n, nb,
                        fm_row_ptr, fm_col);
@@ -699,6 +714,9 @@ psi_status build_operator(psi_operator* op, const int32_t* follower, const int32
                        0);
   }
   hipLaunchKernelGGL(k_max_row, dim3(grid_for(n)), dim3(kBlock), 0, st, op->row_ptr, n, op->ctrl);
+  if (op->n_graphs > 1)
+    hipLaunchKernelGGL(k_graph_rows, dim3(grid_for(n)), dim3(kBlock), 0, st, op->graph_off,
+                       op->n_graphs, n, op->graph_of, op->inv_ng);
   if (op->val64 && m > 0)
     hipLaunchKernelGGL(k_weights64, dim3(grid_for(n * 64)), dim3(kBlock), 0, st, op->row_ptr,
                        op->col, op->mu, op->invden, n, op->val64);
@@ -814,6 +832,24 @@ psi_status ensure_segments(psi_operator* op, int S, int tile_items, hipStream_t 
     PSI_HIP_CHECK(hipGetLastError());
     op->seg_items = tile_items;
   }
+  return PSI_OK;
+}
+
+psi_status scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* tile_sums,
+                              uint32_t* total, hipStream_t st) {
+  SortBufs sb{};
+  sb.tile_sums = tile_sums;
+  sb.total = total;
+  return scan_u32(in, out, n, sb, st);
+}
+
+int64_t scan_tile_count(int64_t n) { return (n + kScanTile - 1) / kScanTile; }
+
+psi_status build_schedule(const int* row_ptr, int64_t n, int64_t m, int items, int64_t n_tiles,
+                          int* tile_row, hipStream_t st) {
+  hipLaunchKernelGGL(k_schedule, dim3(grid_for(n_tiles + 1)), dim3(kBlock), 0, st, row_ptr, n, m,
+                     int64_t(items), n_tiles, tile_row);
+  PSI_HIP_CHECK(hipGetLastError());
   return PSI_OK;
 }
 

@@ -150,8 +150,10 @@ struct psi_operator {
   // persistent device arrays
   int* row_ptr = nullptr;   // CSR(Aᵀ): rows = leaders, cols = followers
   int* col = nullptr;
-  int* fm_row_ptr = nullptr;  // CSR(A): rows = followers, cols = leaders (optional)
+  int* fm_row_ptr = nullptr;  // CSR(A): rows = followers, cols = leaders L(j)
   int* fm_col = nullptr;
+  int* graph_of = nullptr;     // graph of each user (n_graphs > 1)
+  double* inv_ng = nullptr;    // 1/N of each user's graph (n_graphs > 1)
   double *lam = nullptr, *mu = nullptr, *c = nullptr, *d = nullptr, *invden = nullptr;
   float *mu32 = nullptr, *invden32 = nullptr, *c32 = nullptr;
   double* val64 = nullptr;
@@ -208,4 +210,18 @@ PassArgs base_args(psi_operator* op);
 
 psi_status solve(psi_operator* op, const psi_params* prm, const double* s0, double* psi_out,
                  double* s_out, psi_info* info, hipStream_t stream);
+
+// Exclusive prefix sum of n uint32 (in may equal out); tile_sums needs
+// scan_tile_count(n) + 1 entries; *total receives the sum.
+psi_status scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* tile_sums,
+                              uint32_t* total, hipStream_t st);
+int64_t scan_tile_count(int64_t n);
+// Merge-path schedule: first row of each of n_tiles tiles of `items` path items.
+psi_status build_schedule(const int* row_ptr, int64_t n, int64_t m, int items, int64_t n_tiles,
+                          int* tile_row, hipStream_t st);
+
+psi_status batched_workspace_size(const psi_operator* op, int n_scenarios, size_t* bytes);
+psi_status solve_batched(psi_operator* op, const psi_params* prm, int n_scenarios,
+                         const double* lambda, const double* mu, double* psi_out, psi_info* infos,
+                         void* ws, size_t ws_bytes, hipStream_t st);
 }  // namespace psi

@@ -1,0 +1,86 @@
+"""GPU parity of the batched solves against the CPU oracle and single solves.
+
+Scenario mode: K activity scenarios on one graph; column k must match the
+oracle's Algorithm 2 for scenario k (1e-9 relative L1) and the single-graph
+solve of that scenario.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def scenarios(n, k, seed, sigma=1.5):
+    lam = np.empty((n, k))
+    mu = np.empty((n, k))
+    for s in range(k):
+        lam[:, s], mu[:, s] = synth.activity(n, seed, "lognormal", sigma, scenario=s)
+    return lam, mu
+
+
+@pytest.mark.parametrize("n,k,gamma", [(20000, 5, 2.2), (3000, 70, 2.1), (50000, 64, 2.2)])
+def test_scenarios_match_oracle(gpu_lib, n, k, gamma):
+    api = gpu_lib
+    g = synth.chung_lu(n, 15, gamma, 41, sigma=1.5)
+    lam, mu = scenarios(n, k, 42)
+    op = api.Operator(g.n, g.follower, g.leader, g.lam, g.mu)
+    psi, infos = op.solve_batched(torch.tensor(lam), torch.tensor(mu), tol=1e-9)
+    psi = psi.cpu().numpy()
+    for s in sorted({0, 1, k // 2, k - 1}):
+        A, B, c, d = oracle.operator(g.n, g.follower, g.leader, lam[:, s], mu[:, s])
+        r = oracle.power_psi(A, B, c, d, 1e-9)
+        assert infos[s]["status"] == 0
+        assert abs(infos[s]["iterations"] - r["iterations"]) <= 1
+        assert oracle.rel_l1(r["psi"], psi[:, s]) <= 1e-9, s
+
+
+def test_scenarios_equal_single_solves_and_repeat(gpu_lib):
+    api = gpu_lib
+    g = synth.chung_lu(30000, 20, 2.2, 43, sigma=1.0)
+    k = 6
+    lam, mu = scenarios(g.n, k, 44, sigma=2.0)
+    op = api.Operator(g.n, g.follower, g.leader, g.lam, g.mu)
+    psi, infos = op.solve_batched(torch.tensor(lam), torch.tensor(mu), tol=1e-10)
+    again, _ = op.solve_batched(torch.tensor(lam), torch.tensor(mu), tol=1e-10)
+    assert torch.equal(psi, again)
+    for s in range(k):
+        single = api.Operator(g.n, g.follower, g.leader, lam[:, s], mu[:, s])
+        p1, info = single.solve(tol=1e-10)
+        assert abs(info["iterations"] - infos[s]["iterations"]) <= 1
+        assert oracle.rel_l1(p1.cpu().numpy(), psi[:, s].cpu().numpy()) <= 1e-12
+
+
+def test_scenarios_star_hub_closed_form(gpu_lib):
+    """A 200k-follower hub (chunked rows) in every scenario."""
+    api = gpu_lib
+    n = 200_001
+    g = synth.star(n, 45)
+    lam, mu = scenarios(n, 3, 46)
+    op = api.Operator(g.n, g.follower, g.leader, g.lam, g.mu)
+    psi, infos = op.solve_batched(torch.tensor(lam), torch.tensor(mu), tol=1e-11)
+    psi = psi.cpu().numpy()
+    for s in range(3):
+        c = mu[:, s] / (lam[:, s] + mu[:, s])
+        d = lam[:, s] / (lam[:, s] + mu[:, s])
+        expect = d / n
+        expect[0] = d[0] * (1.0 + np.sort(c[1:]).sum()) / n
+        np.testing.assert_allclose(psi[:, s], expect, rtol=1e-12, atol=0)
+
+
+def test_scenarios_invalid_and_statuses(gpu_lib):
+    api = gpu_lib
+    g = synth.chung_lu(5000, 10, 2.2, 47)
+    lam, mu = scenarios(g.n, 4, 48)
+    op = api.Operator(g.n, g.follower, g.leader, g.lam, g.mu)
+    bad = lam.copy()
+    bad[10, 2] = -1.0
+    with pytest.raises(api.PsiError, match="activity"):
+        op.solve_batched(torch.tensor(bad), torch.tensor(mu))
+    psi, infos = op.solve_batched(torch.tensor(lam), torch.tensor(mu), tol=1e-12, max_iter=3)
+    assert all(i["status_name"] == "PSI_ENOTCONV" and i["iterations"] == 3 for i in infos)
+    with pytest.raises(ValueError):
+        op.solve_batched(torch.tensor(lam[:-1]), torch.tensor(mu[:-1]))
