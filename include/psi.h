@@ -203,9 +203,17 @@ psi_status psi_batched_workspace_size(const psi_operator* op, int32_t n_scenario
  * (scenarios in tiles of 64).  Each scenario runs Algorithm 2 to its own
  * tolerance and is frozen afterwards; psi_out[i*K + k] (device FP64 [N × K])
  * is its ψ; infos[k] (host, may be NULL) its iteration count and gap.
- * The operator's own λ, μ are not used.  Only PSI_PREC_FP64 and
- * PSI_TOL_ABS_L1.  Returns the first non-OK scenario status, if any.
- * workspace: device, at least psi_batched_workspace_size bytes. */
+ * The operator's own λ, μ are not used.
+ * Graph mode (operator built with n_graphs = G > 1; n_scenarios = 1, lambda
+ * and mu NULL): the G independent graphs of the block-diagonal operator are
+ * solved together, one pass over all of them per step; each graph has its
+ * own gap (over its users), stops at its own tolerance (and is frozen) and
+ * its ψ uses its own N; psi_out (device [n_users]) holds every graph's ψ at
+ * its users' positions, infos[g] (host, may be NULL) graph g's result.
+ * Both modes: only PSI_PREC_FP64 and PSI_TOL_ABS_L1; returns the first
+ * non-OK scenario/graph status, if any.
+ * workspace: device, at least psi_batched_workspace_size bytes (0 in graph
+ * mode: the operator's own workspace holds the state). */
 psi_status psi_solve_batched(psi_operator* op, const psi_params* prm, int32_t n_scenarios,
                              const double* lambda, const double* mu, double* psi_out,
                              psi_info* infos, void* workspace, size_t workspace_bytes,

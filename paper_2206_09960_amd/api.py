@@ -256,6 +256,29 @@ class Operator:
             out.append(d)
         return psi, out
 
+    def solve_graphs(self, tol: float = 1e-8, max_iter: int = 10000, check_every: int = 0,
+                     tile_items: int = 0, stream=None, raise_on_status: bool = False):
+        """psi_solve_batched, graph mode: every graph of a block-diagonal
+        operator solved to its own tolerance; returns (psi [N], G info dicts)."""
+        if self.n_graphs < 2:
+            raise ValueError("graph mode needs an operator built with node_offsets")
+        p = self._params(tol, "abs_l1", max_iter, "fp64", check_every, tile_items)
+        psi = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        infos = (_ffi.Info * self.n_graphs)()
+        with torch.cuda.device(self.device):
+            st = self._lib.psi_solve_batched(self._h, ctypes.byref(p), 1, None, None,
+                                             psi.data_ptr(), infos, None, 0,
+                                             _stream_handle(stream))
+        if st in (_ffi.PSI_EINVAL, _ffi.PSI_EDEVICE, _ffi.PSI_ENOSPACE) or (
+                raise_on_status and st != _ffi.PSI_OK):
+            _check(st)
+        out = []
+        for i in range(self.n_graphs):
+            d = _ffi.struct_dict(infos[i])
+            d["status_name"] = _ffi.STATUS_NAMES.get(d["status"], str(d["status"]))
+            out.append(d)
+        return psi, out
+
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             self._lib.psi_operator_destroy(self._h)

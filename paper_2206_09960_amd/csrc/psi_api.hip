@@ -90,6 +90,7 @@ psi_status psi_build_operator(int64_t n_users, int64_t n_edges, const int32_t* f
   PSI_REQUIRE(n_graphs >= 1, "n_graphs must be >= 1");
   PSI_REQUIRE(persistent && scratch, "workspaces must not be NULL");
   if (n_graphs > 1) {
+    PSI_REQUIRE(n_graphs < 65536, "at most 65535 graphs");
     PSI_REQUIRE(node_offsets, "node_offsets needed when n_graphs > 1");
     PSI_REQUIRE(node_offsets[0] == 0 && node_offsets[n_graphs] == n_users,
                 "node_offsets must run from 0 to n_users");
@@ -225,6 +226,11 @@ psi_status psi_pass_time(psi_operator* op, int32_t pass_kind, int32_t reps, int3
 psi_status psi_batched_workspace_size(const psi_operator* op, int32_t n_scenarios, size_t* bytes) {
   PSI_GUARD_BEGIN
   PSI_REQUIRE(op, "op must not be NULL");
+  if (op->n_graphs > 1) {
+    PSI_REQUIRE(bytes, "bytes must not be NULL");
+    *bytes = 0;
+    return PSI_OK;
+  }
   return psi::batched_workspace_size(op, n_scenarios, bytes);
   PSI_GUARD_END
 }
@@ -237,6 +243,11 @@ psi_status psi_solve_batched(psi_operator* op, const psi_params* prm, int32_t n_
   PSI_REQUIRE(op, "op must not be NULL");
   psi_status st = psi::check_device(op);
   if (st != PSI_OK) return st;
+  if (op->n_graphs > 1) {
+    PSI_REQUIRE(n_scenarios == 1 && !lambda && !mu,
+                "graph mode: n_scenarios must be 1 and lambda, mu NULL");
+    return psi::solve_graphs(op, prm, psi_out, infos, static_cast<hipStream_t>(stream));
+  }
   return psi::solve_batched(op, prm, n_scenarios, lambda, mu, psi_out, infos, workspace,
                             workspace_bytes, static_cast<hipStream_t>(stream));
   PSI_GUARD_END

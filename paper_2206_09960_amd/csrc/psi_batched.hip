@@ -393,6 +393,76 @@ __global__ void k_bctrl_init(BatchCtrl* bc, double tol, int max_iter) {
   }
 }
 
+// ---------------------------------------------------------------- graphs
+// Per-graph gap of a block-diagonal operator: graph g sums its users' |Δ| in
+// a fixed order, records it, and freezes when it meets the tolerance; the
+// last graph to report sets done when every graph is done.  One counter
+// carries both the arrivals (low 16 bits) and the done graphs (high bits).
+__global__ __launch_bounds__(kBlock) void k_graph_gap(const int64_t* graph_off, int n_graphs,
+                                                      const double* row_delta, Ctrl* ctrl,
+                                                      int* gdone, int* giter, int* gstatus,
+                                                      double* ggap) {
+  __shared__ double red[kBlock / 64];
+  if (ctrl->done) return;
+  const int g = blockIdx.x;
+  const int was_done = gdone[g];
+  double sum = 0.0;
+  if (!was_done)
+    for (int64_t r = graph_off[g] + threadIdx.x; r < graph_off[g + 1]; r += kBlock)
+      sum += row_delta[r];
+  for (int off = 32; off > 0; off >>= 1) sum += __shfl_down(sum, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sum;
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  int done = was_done;
+  if (!was_done) {
+    const double G = (red[0] + red[1]) + (red[2] + red[3]);
+    const int it = giter[g] + 1;
+    giter[g] = it;
+    ggap[g] = G;
+    if (!isfinite(G)) {
+      done = 1;
+      gstatus[g] = PSI_ENUMERIC;
+    } else if (G <= ctrl->tol) {
+      done = 1;
+      gstatus[g] = PSI_OK;
+    } else if (it >= ctrl->max_iter) {
+      done = 1;
+      gstatus[g] = PSI_ENOTCONV;
+    }
+    gdone[g] = done;
+  }
+  const unsigned t = atomicAdd(&ctrl->ticket, 1u + (static_cast<unsigned>(done) << 16));
+  if ((t & 0xFFFFu) == static_cast<unsigned>(n_graphs) - 1u) {
+    const unsigned n_done = (t >> 16) + static_cast<unsigned>(done);
+    ctrl->ticket = 0;
+    ctrl->iter += 1;
+    if (n_done == static_cast<unsigned>(n_graphs)) ctrl->done = 1;
+  }
+}
+
+__global__ void k_graph_init(const double* c, const double* invden, int64_t n, int n_graphs,
+                             double* s, double* z, int* gdone, int* giter, int* gstatus,
+                             double* ggap, Ctrl* ctrl, double tol, int max_iter) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) {
+    s[i] = c[i];
+    z[i] = invden[i] * c[i];
+  }
+  if (i < n_graphs) {
+    gdone[i] = 0;
+    giter[i] = 0;
+    gstatus[i] = PSI_OK;
+    ggap[i] = 0.0;
+  }
+  if (i == 0) {
+    *ctrl = Ctrl{};
+    ctrl->tol = tol;
+    ctrl->max_iter = max_iter;
+    ctrl->bnorm = 1.0;
+  }
+}
+
 int rows_grid() {
   static int cap = 0;
   if (!cap) {
@@ -586,6 +656,106 @@ psi_status solve_batched(psi_operator* op, const psi_params* prm, int K, const d
   if (infos)
     for (int k = 0; k < K; ++k) infos[k].device_ms = ms;
   if (worst != PSI_OK) set_error("a scenario did not converge (see its info)");
+  return static_cast<psi_status>(worst);
+}
+
+psi_status solve_graphs(psi_operator* op, const psi_params* prm, double* psi_out, psi_info* infos,
+                        hipStream_t st) {
+  PSI_REQUIRE(prm && psi_out, "params and psi_out must not be NULL");
+  PSI_REQUIRE(op->n_graphs > 1, "graph mode needs a multi-graph operator");
+  PSI_REQUIRE(prm->tol > 0.0 && std::isfinite(prm->tol), "tol must be finite and > 0");
+  PSI_REQUIRE(prm->max_iter > 0, "max_iter must be > 0");
+  PSI_REQUIRE(prm->tol_mode == PSI_TOL_ABS_L1, "graph batches use PSI_TOL_ABS_L1");
+  PSI_REQUIRE(prm->precision == PSI_PREC_FP64, "graph batches run in PSI_PREC_FP64");
+  const int tile = prm->tile_items ? prm->tile_items : (op->sched_items ? op->sched_items
+                                                                        : kDefaultTileItems);
+  PSI_REQUIRE(tile_items_supported(tile), "unsupported tile_items");
+  psi_status s = ensure_schedule(op, tile, st);
+  if (s != PSI_OK) return s;
+  const int64_t n = op->n;
+  const int G = op->n_graphs;
+  hipEvent_t ev0, ev1;
+  PSI_HIP_CHECK(hipEventCreate(&ev0));
+  PSI_HIP_CHECK(hipEventCreate(&ev1));
+  PSI_HIP_CHECK(hipEventRecord(ev0, st));
+  hipLaunchKernelGGL(k_graph_init, dim3(grid_for(std::max<int64_t>(n, G))), dim3(kBlock), 0, st,
+                     op->c, op->invden, n, G, op->s_a, op->z_a, op->gdone, op->giter, op->gstatus,
+                     op->ggap, op->ctrl, prm->tol, prm->max_iter);
+  PassArgs base = base_args(op);
+  base.count_iter = 0;
+  base.respect_done = 1;
+  auto pass = [&](int i) -> psi_status {
+    PassArgs a = base;
+    const bool even = (i & 1) == 0;
+    a.x = even ? op->z_a : op->z_b;
+    a.s_old = even ? op->s_a : op->s_b;
+    a.s_new = even ? op->s_b : op->s_a;
+    a.z_new = even ? op->z_b : op->z_a;
+    psi_status r = launch_pass(op, kStep64G, a, st);
+    if (r != PSI_OK) return r;
+    hipLaunchKernelGGL(k_graph_gap, dim3(G), dim3(kBlock), 0, st, op->graph_off, G, op->row_delta,
+                       op->ctrl, op->gdone, op->giter, op->gstatus, op->ggap);
+    PSI_HIP_CHECK(hipGetLastError());
+    return PSI_OK;
+  };
+  int enq = 0, chunk = prm->check_every > 0 ? prm->check_every : 8;
+  Ctrl* h = op->host_ctrl;
+  while (true) {
+    const int cnt = std::min(chunk, prm->max_iter - enq);
+    for (int i = 0; i < cnt; ++i) {
+      s = pass(enq + i);
+      if (s != PSI_OK) return s;
+    }
+    enq += cnt;
+    PSI_HIP_CHECK(hipMemcpyAsync(h, op->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+    PSI_HIP_CHECK(hipStreamSynchronize(st));
+    if (h->err_flags & kErrSlotTimeout) {
+      set_error("a cross-tile slot was not filled in time");
+      return PSI_EDEVICE;
+    }
+    if (h->done || enq >= prm->max_iter) break;
+    if (prm->check_every == 0) chunk = std::min(2 * chunk, 64);
+  }
+  const int passes = h->iter;
+  {
+    PassArgs a = base;
+    a.respect_done = 0;
+    a.x = (passes & 1) ? op->z_b : op->z_a;
+    a.s_new = psi_out;
+    s = launch_pass(op, kFinal64G, a, st);
+    if (s != PSI_OK) return s;
+  }
+  std::vector<int> it(G), stv(G);
+  std::vector<double> gap(G);
+  PSI_HIP_CHECK(hipMemcpyAsync(it.data(), op->giter, 4 * size_t(G), hipMemcpyDeviceToHost, st));
+  PSI_HIP_CHECK(hipMemcpyAsync(stv.data(), op->gstatus, 4 * size_t(G), hipMemcpyDeviceToHost, st));
+  PSI_HIP_CHECK(hipMemcpyAsync(gap.data(), op->ggap, 8 * size_t(G), hipMemcpyDeviceToHost, st));
+  std::vector<int> dn(G);
+  PSI_HIP_CHECK(hipMemcpyAsync(dn.data(), op->gdone, 4 * size_t(G), hipMemcpyDeviceToHost, st));
+  PSI_HIP_CHECK(hipEventRecord(ev1, st));
+  PSI_HIP_CHECK(hipEventSynchronize(ev1));
+  float ms = 0.f;
+  PSI_HIP_CHECK(hipEventElapsedTime(&ms, ev0, ev1));
+  (void)hipEventDestroy(ev0);
+  (void)hipEventDestroy(ev1);
+  int worst = PSI_OK;
+  for (int g = 0; g < G; ++g) {
+    const int stg = dn[g] ? stv[g] : PSI_ENOTCONV;
+    if (stg != PSI_OK && worst == PSI_OK) worst = stg;
+    if (infos) {
+      psi_info& inf = infos[g];
+      inf = psi_info{};
+      inf.status = stg;
+      inf.iterations = it[g];
+      inf.spmv_passes = it[g] + 1;
+      inf.final_gap = gap[g];
+      inf.final_l1_step = gap[g];
+      inf.col_segments = 1;
+      inf.tile_items = tile;
+      inf.device_ms = ms;
+    }
+  }
+  if (worst != PSI_OK) set_error("a graph did not converge (see its info)");
   return static_cast<psi_status>(worst);
 }
 

@@ -476,6 +476,11 @@ static void layout_persistent(int64_t n, int64_t m_raw, int n_graphs, uint32_t f
   char* fm_col = take(4 * size_t(m_raw));
   char* graph_of = n_graphs > 1 ? take(4 * size_t(n)) : nullptr;
   char* inv_ng = n_graphs > 1 ? take(8 * size_t(n)) : nullptr;
+  char* row_delta = n_graphs > 1 ? take(8 * size_t(n)) : nullptr;
+  char* gdone = n_graphs > 1 ? take(4 * size_t(n_graphs)) : nullptr;
+  char* giter = n_graphs > 1 ? take(4 * size_t(n_graphs)) : nullptr;
+  char* gstatus = n_graphs > 1 ? take(4 * size_t(n_graphs)) : nullptr;
+  char* ggap = n_graphs > 1 ? take(8 * size_t(n_graphs)) : nullptr;
   char* lam = take(8 * size_t(n));
   char* mu = take(8 * size_t(n));
   char* c = take(8 * size_t(n));
@@ -518,6 +523,11 @@ static void layout_persistent(int64_t n, int64_t m_raw, int n_graphs, uint32_t f
   op->fm_col = (int*)fm_col;
   op->graph_of = (int*)graph_of;
   op->inv_ng = (double*)inv_ng;
+  op->row_delta = (double*)row_delta;
+  op->gdone = (int*)gdone;
+  op->giter = (int*)giter;
+  op->gstatus = (int*)gstatus;
+  op->ggap = (double*)ggap;
   op->lam = (double*)lam;
   op->mu = (double*)mu;
   op->c = (double*)c;

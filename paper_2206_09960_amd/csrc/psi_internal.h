@@ -110,6 +110,10 @@ struct PassArgs {
   Ctrl* ctrl;
   double* hist;
   double* gap_out;      // optional plain copy of the gap (psi_step)
+  const int* graph_of;  // block-diagonal operators: graph of each user
+  const double* inv_ng; //   1/N of each user's graph
+  const int* gdone;     //   graphs that met their tolerance (frozen)
+  double* row_delta;    //   |s_new − s_old| of each user
   int count_iter;       // 1: the pass is a Power-ψ step that advances ctrl->iter
   int respect_done;     // 1: exit at once when ctrl->done is set
 };
@@ -121,6 +125,8 @@ enum PassMode : int {
   kStep32 = 3,      // e_new = r + μ·Σ ze_j, ze_new = invden·e_new, gap (FP32 storage)
   kPart64 = 4,      // y_s = Σ_{j∈F(i), j in segment s} x_j, x FP64 (partial pass)
   kPart32 = 5,      // same with x FP32, y_s stored FP32
+  kStep64G = 6,     // kStep64 on a block-diagonal operator: per-graph freezing, |Δ| per row
+  kFinal64G = 7,    // kFinal64 with 1/N of each user's own graph
 };
 
 // One column segment of CSR(Aᵀ): the followers in [lo, hi) of every row.
@@ -154,6 +160,11 @@ struct psi_operator {
   int* fm_col = nullptr;
   int* graph_of = nullptr;     // graph of each user (n_graphs > 1)
   double* inv_ng = nullptr;    // 1/N of each user's graph (n_graphs > 1)
+  double* row_delta = nullptr; // per-user |Δ| of the last pass (n_graphs > 1)
+  int* gdone = nullptr;        // per-graph state (n_graphs > 1)
+  int* giter = nullptr;
+  int* gstatus = nullptr;
+  double* ggap = nullptr;
   double *lam = nullptr, *mu = nullptr, *c = nullptr, *d = nullptr, *invden = nullptr;
   float *mu32 = nullptr, *invden32 = nullptr, *c32 = nullptr;
   double* val64 = nullptr;
@@ -221,6 +232,8 @@ psi_status build_schedule(const int* row_ptr, int64_t n, int64_t m, int items, i
                           int* tile_row, hipStream_t st);
 
 psi_status batched_workspace_size(const psi_operator* op, int n_scenarios, size_t* bytes);
+psi_status solve_graphs(psi_operator* op, const psi_params* prm, double* psi_out, psi_info* infos,
+                        hipStream_t st);
 psi_status solve_batched(psi_operator* op, const psi_params* prm, int n_scenarios,
                          const double* lambda, const double* mu, double* psi_out, psi_info* infos,
                          void* ws, size_t ws_bytes, hipStream_t st);

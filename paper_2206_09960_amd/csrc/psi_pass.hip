@@ -106,14 +106,29 @@ __device__ inline double gather(const PassArgs& a, int j, int e) {
 
 // Per-user inputs of the epilogue, loaded ahead of the row's sum.
 struct RowIn {
-  double a0, a1, a2, a3;
+  double a0, a1, a2, a3, a4;
+  int frozen;
 };
 
 template <int MODE>
 __device__ inline RowIn load_row(const PassArgs& a, int r) {
-  RowIn in{0.0, 0.0, 0.0, 0.0};
+  RowIn in{0.0, 0.0, 0.0, 0.0, 0.0, 0};
   if constexpr (MODE == kStep64) {
-    in = {a.c[r], a.mu[r], a.invden[r], a.s_old[r]};
+    in.a0 = a.c[r];
+    in.a1 = a.mu[r];
+    in.a2 = a.invden[r];
+    in.a3 = a.s_old[r];
+  } else if constexpr (MODE == kStep64G) {
+    in.a0 = a.c[r];
+    in.a1 = a.mu[r];
+    in.a2 = a.invden[r];
+    in.a3 = a.s_old[r];
+    in.a4 = static_cast<const double*>(a.x)[r];  // z of s_old, kept when frozen
+    in.frozen = a.gdone[a.graph_of[r]];
+  } else if constexpr (MODE == kFinal64G) {
+    in.a0 = a.lam[r];
+    in.a1 = a.d[r];
+    in.a2 = a.inv_ng[r];
   } else if constexpr (MODE == kStep64W) {
     in.a0 = a.c[r];
     in.a3 = a.s_old[r];
@@ -121,8 +136,10 @@ __device__ inline RowIn load_row(const PassArgs& a, int r) {
     in.a0 = a.lam[r];
     in.a1 = a.d[r];
   } else if constexpr (MODE == kStep32) {
-    in = {static_cast<double>(a.r32[r]), static_cast<double>(a.mu32[r]),
-          static_cast<double>(a.invden32[r]), static_cast<double>(a.e_old[r])};
+    in.a0 = static_cast<double>(a.r32[r]);
+    in.a1 = static_cast<double>(a.mu32[r]);
+    in.a2 = static_cast<double>(a.invden32[r]);
+    in.a3 = static_cast<double>(a.e_old[r]);
   }
   return in;
 }
@@ -144,6 +161,22 @@ __device__ inline void apply_row(const PassArgs& a, void* yout, int r, const Row
     s += fabs(sn);
   } else if constexpr (MODE == kFinal64) {
     a.s_new[r] = (in.a0 * y + in.a1) * a.inv_n;
+  } else if constexpr (MODE == kStep64G) {
+    if (in.frozen) {
+      a.s_new[r] = in.a3;
+      a.z_new[r] = in.a4;
+      a.row_delta[r] = 0.0;
+      return;
+    }
+    const double sn = in.a0 + in.a1 * y;
+    a.s_new[r] = sn;
+    a.z_new[r] = in.a2 * sn;
+    const double dlt = fabs(sn - in.a3);
+    a.row_delta[r] = dlt;
+    g += dlt;
+    s += fabs(sn);
+  } else if constexpr (MODE == kFinal64G) {
+    a.s_new[r] = (in.a0 * y + in.a1) * in.a2;
   } else if constexpr (MODE == kStep32) {
     const float en = static_cast<float>(in.a0) + static_cast<float>(in.a1) * static_cast<float>(y);
     a.e_new[r] = en;
@@ -504,7 +537,7 @@ __global__ __launch_bounds__(kBlock) void k_pass(PassArgs a) {
   TileSrc src{a.row_ptr, a.col, a.tile_row, a.part_open, nullptr, a.n_nnz, a.n_tiles};
   double g = 0.0, sn = 0.0;
   run_tiles<IPT, MODE>(a, src, blockIdx.x, gridDim.x, L, g, sn);
-  if constexpr (MODE != kFinal64) finalize_gap(a, g, sn, L.red, &L.last);
+  if constexpr (MODE != kFinal64 && MODE != kFinal64G) finalize_gap(a, g, sn, L.red, &L.last);
 }
 
 // Partial pass of one column segment per XCD group: y_s = A_sᵀ x.
@@ -668,6 +701,10 @@ PassArgs base_args(psi_operator* op) {
   a.mu32 = op->mu32;
   a.invden32 = op->invden32;
   a.inv_n = op->n > 0 ? 1.0 / static_cast<double>(op->n) : 0.0;
+  a.graph_of = op->graph_of;
+  a.inv_ng = op->inv_ng;
+  a.gdone = op->gdone;
+  a.row_delta = op->row_delta;
   a.part_open = op->part_open;
   a.gap_part = op->gap_part;
   a.gap_grp = op->gap_grp;
@@ -684,6 +721,8 @@ psi_status launch_pass(psi_operator* op, PassMode mode, const PassArgs& a, hipSt
     case kStep64W: return launch_mode<kStep64W>(a, st);
     case kFinal64: return launch_mode<kFinal64>(a, st);
     case kStep32: return launch_mode<kStep32>(a, st);
+    case kStep64G: return launch_mode<kStep64G>(a, st);
+    case kFinal64G: return launch_mode<kFinal64G>(a, st);
     default: break;
   }
   set_error("unknown pass mode");

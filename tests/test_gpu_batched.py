@@ -84,3 +84,56 @@ def test_scenarios_invalid_and_statuses(gpu_lib):
     assert all(i["status_name"] == "PSI_ENOTCONV" and i["iterations"] == 3 for i in infos)
     with pytest.raises(ValueError):
         op.solve_batched(torch.tensor(lam[:-1]), torch.tensor(mu[:-1]))
+
+
+# ---------------------------------------------------------------- graph mode
+def subgraph(g, k):
+    lo, hi = int(g.node_offsets[k]), int(g.node_offsets[k + 1])
+    sel = (g.follower >= lo) & (g.follower < hi)
+    return synth.Graph(hi - lo, g.follower[sel] - lo, g.leader[sel] - lo, g.lam[lo:hi], g.mu[lo:hi])
+
+
+@pytest.mark.parametrize("n_graphs,lo,hi", [(7, 500, 3000), (256, 100, 400)])
+def test_graphs_match_oracle_and_lone_solves(gpu_lib, n_graphs, lo, hi):
+    api = gpu_lib
+    g = synth.multi_graph(n_graphs, lo, hi, 8, 2.2, seed=51, sigma=1.5)
+    op = api.Operator(g.n, g.follower, g.leader, g.lam, g.mu, node_offsets=g.node_offsets)
+    psi, infos = op.solve_graphs(tol=1e-10)
+    psi = psi.cpu().numpy()
+    assert len(infos) == n_graphs
+    again, _ = op.solve_graphs(tol=1e-10)
+    assert np.array_equal(again.cpu().numpy(), psi)
+    for k in sorted({0, 1, n_graphs // 2, n_graphs - 1}):
+        sub = subgraph(g, k)
+        A, B, c, d = oracle.operator(sub.n, sub.follower, sub.leader, sub.lam, sub.mu)
+        r = oracle.power_psi(A, B, c, d, 1e-10)
+        part = psi[g.node_offsets[k]:g.node_offsets[k + 1]]
+        assert infos[k]["status"] == 0
+        assert abs(infos[k]["iterations"] - r["iterations"]) <= 1
+        assert oracle.rel_l1(r["psi"], part) <= 1e-9
+        lone = api.Operator(sub.n, sub.follower, sub.leader, sub.lam, sub.mu)
+        p1, i1 = lone.solve(tol=1e-10)
+        assert abs(i1["iterations"] - infos[k]["iterations"]) <= 1
+        assert oracle.rel_l1(p1.cpu().numpy(), part) <= 1e-12
+
+
+def test_graphs_with_an_edgeless_graph(gpu_lib):
+    api = gpu_lib
+    a = synth.chung_lu(2000, 6, 2.2, 52)
+    n_iso = 50
+    b_lam = np.linspace(0.2, 3.0, n_iso)
+    b_mu = np.linspace(1.5, 0.1, n_iso)
+    n = a.n + n_iso
+    offs = np.array([0, a.n, n], dtype=np.int64)
+    op = api.Operator(n, a.follower, a.leader, np.concatenate([a.lam, b_lam]),
+                      np.concatenate([a.mu, b_mu]), node_offsets=offs)
+    psi, infos = op.solve_graphs(tol=1e-11)
+    psi = psi.cpu().numpy()
+    np.testing.assert_allclose(psi[a.n:], b_lam / (b_lam + b_mu) / n_iso, rtol=1e-15)
+    A, B, c, d = oracle.operator(a.n, a.follower, a.leader, a.lam, a.mu)
+    r = oracle.power_psi(A, B, c, d, 1e-11)
+    assert oracle.rel_l1(r["psi"], psi[:a.n]) <= 1e-9
+    bad_f = np.array([0, a.n + 1], dtype=np.int32)  # an edge joining the two graphs
+    bad_l = np.array([1, 3], dtype=np.int32)
+    with pytest.raises(api.PsiError, match="joins two graphs"):
+        api.Operator(n, bad_f, bad_l, np.ones(n), np.ones(n), node_offsets=offs)
