@@ -9,9 +9,11 @@ it:
     x0_i  = [log λ_i, log μ_i, c_i, d_i, log(1+|F(i)|), log(1+|L(i)|),
              log(1+den_i), 1]                                   (8 features)
     h     = ReLU(x0 Win + bin)                                  (64)
-    3 ×:  p   = h Wm                                            (32)
-          m_i = Σ_{j∈F(i)} p_j / den_j                          (the pull
-                pattern of Aᵀ with the row weights 1/den_j of A, without μ)
+    3 ×:  p_j = (h_j Wm) / den_j                                (32, the
+                message of user j, scaled by the column weight 1/den_j
+                that A gives j's leaders, without μ)
+          m_i = Σ_{j∈F(i)} p_j                                  (the pull
+                pattern of Aᵀ)
           h   = ReLU([h | m] Wl + bl)                           (96 → 64)
     out_i = h_i · w_out + b_out;   t̂_i = softplus(out_i)
     loss  = mean over users with c_i > 0 of (t̂_i − t_i)²
@@ -20,7 +22,7 @@ Parameters are one flat FP32 vector in the order Win [8×64], bin [64], then
 per layer Wm [64×32], Wl [96×64], bl [64], then w_out [64], b_out [1].
 
 Everything here is FP64.  With ``bf16_storage=True`` the values the GPU stores in
-bfloat16 (Wm, Wl, and h, p, m after each layer) are rounded the same way
+bfloat16 (Wm, Wl, and h, the scaled message p and m after each layer) are rounded the same way
 (round to nearest even) so GPU and oracle differ only by FP32 summation
 order; the backward pass treats the rounding as the identity, as the GPU does.
 """
@@ -121,8 +123,8 @@ def forward(theta, g, bf16_storage=False):
     for l in range(LAYERS):
         Wm = q(p[f"Wm{l}"])
         W = q(p[f"Wl{l}"])
-        msg = q(h @ Wm)
-        m = q(P @ (invden[:, None] * msg))
+        msg = q(invden[:, None] * (h @ Wm))
+        m = q(P @ msg)
         x = np.concatenate([h, m], axis=1)
         h = q(np.maximum(x @ W + p[f"bl{l}"], 0.0))
         cache[f"msg{l}"] = msg
@@ -168,7 +170,7 @@ def loss_and_grad(theta, g, t, mask, bf16_storage=False):
         dx = dz @ cache[f"Wl{l}"].T
         dh_prev = dx[:, :H]
         dm = dx[:, H:]
-        # m = P (invden ⊙ msg)  ⇒  dmsg = invden ⊙ (Pᵀ dm)
+        # msg = invden ⊙ (h Wm), m = P msg  ⇒  d(h Wm) = invden ⊙ (Pᵀ dm)
         dmsg = invden[:, None] * (P.T @ dm)
         h_prev = cache[f"h{l}"]
         grads[f"Wm{l}"] = h_prev.T @ dmsg
