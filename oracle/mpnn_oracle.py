@@ -6,14 +6,16 @@ point s of eq. (power_psi) (s ≥ c because A and c are non-negative), and the
 solver starts from s0 = c ⊙ exp(t̂).  The network, in the order the GPU runs
 it:
 
-    x0_i  = [log λ_i, log μ_i, c_i, d_i, log(1+|F(i)|), log(1+|L(i)|),
-             log(1+den_i), 1]                                   (8 features)
+    x0_i  = [log λ_i, log(μ_i + 1e-12), c_i, d_i, log(1+|F(i)|),
+             log(1+|L(i)|), log(1+den_i), log(λ_i + μ_i)]       (8 features)
     h     = ReLU(x0 Win + bin)                                  (64)
     3 ×:  p_j = (h_j Wm) / den_j                                (32, the
                 message of user j, scaled by the column weight 1/den_j
                 that A gives j's leaders, without μ)
-          m_i = Σ_{j∈F(i)} p_j                                  (the pull
-                pattern of Aᵀ)
+          m_i = log(1 + ReLU((λ_i + μ_i) Σ_{j∈F(i)} p_j))        (the pull
+                pattern of Aᵀ; the receiver factor and the log make one
+                layer able to express log(s_i/c_i) = log(1 + (λ_i + μ_i)
+                Σ_j s_j/den_j), which the fixed point satisfies exactly)
           h   = ReLU([h | m] Wl + bl)                           (96 → 64)
     out_i = h_i · w_out + b_out;   t̂_i = softplus(out_i)
     loss  = mean over users with c_i > 0 of (t̂_i − t_i)²
@@ -107,8 +109,8 @@ def graph_arrays(n, follower, leader, lam, mu):
     c = mu / (lam + mu)
     d = lam / (lam + mu)
     x0 = np.stack([np.log(lam), np.log(mu + 1e-12), c, d, np.log1p(n_followers),
-                   np.log1p(n_leaders), np.log1p(den), np.ones(n)], axis=1)
-    return dict(P=P, invden=invden, c=c, d=d, x0=x0, n=n)
+                   np.log1p(n_leaders), np.log1p(den), np.log(lam + mu)], axis=1)
+    return dict(P=P, invden=invden, lm=lam + mu, c=c, d=d, x0=x0, n=n)
 
 
 def forward(theta, g, bf16_storage=False):
@@ -124,7 +126,7 @@ def forward(theta, g, bf16_storage=False):
         Wm = q(p[f"Wm{l}"])
         W = q(p[f"Wl{l}"])
         msg = q(invden[:, None] * (h @ Wm))
-        m = q(P @ msg)
+        m = q(np.log1p(np.maximum(g["lm"][:, None] * (P @ msg), 0.0)))
         x = np.concatenate([h, m], axis=1)
         h = q(np.maximum(x @ W + p[f"bl{l}"], 0.0))
         cache[f"msg{l}"] = msg
@@ -169,9 +171,11 @@ def loss_and_grad(theta, g, t, mask, bf16_storage=False):
         grads[f"bl{l}"] = dz.sum(axis=0)
         dx = dz @ cache[f"Wl{l}"].T
         dh_prev = dx[:, :H]
-        dm = dx[:, H:]
-        # msg = invden ⊙ (h Wm), m = P msg  ⇒  d(h Wm) = invden ⊙ (Pᵀ dm)
-        dmsg = invden[:, None] * (P.T @ dm)
+        # m = log1p(a) for a = lm ⊙ (P msg) > 0, else 0: dm/da = exp(−m) where m > 0
+        m = cache[f"m{l}"]
+        da = dx[:, H:] * np.where(m > 0, np.exp(-m), 0.0) * g["lm"][:, None]
+        # msg = invden ⊙ (h Wm), a = lm ⊙ P msg  ⇒  d(h Wm) = invden ⊙ (Pᵀ (da))
+        dmsg = invden[:, None] * (P.T @ da)
         h_prev = cache[f"h{l}"]
         grads[f"Wm{l}"] = h_prev.T @ dmsg
         dh = dh_prev + dmsg @ cache[f"Wm{l}"].T
