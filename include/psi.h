@@ -234,6 +234,82 @@ psi_status psi_solve_batched(psi_operator* op, const psi_params* prm, int32_t n_
 psi_status psi_pass_time(psi_operator* op, int32_t pass_kind, int32_t reps, int32_t tile_items,
                          int32_t col_segments, double* mean_ms, void* stream);
 
+/* ---- learned warm start ---------------------------------------------------
+ * An extension of the method (the paper has none): a small message-passing
+ * network predicts the fixed point s of eq. (power_psi) so that Algorithm 2
+ * starts closer to it.  Since A ≥ 0, s ≥ c (Sec. II), and the network
+ * predicts t̂ ≈ log(s/c) ≥ 0, giving s0 = c ⊙ exp(t̂).  Algorithm 2
+ * converges from any start (the iteration contracts to the unique fixed
+ * point), so a poor prediction costs iterations, never correctness, and
+ * psi_solve keeps c when the residual of s0 is not smaller.
+ *
+ * The network, with F(i) the followers of i and den_j as in Sec. II:
+ *   x0_i = [log λ_i, log(μ_i + 1e-12), c_i, d_i, log(1+|F(i)|),
+ *           log(1+|L(i)|), log(1+den_i), 1]
+ *   h = ReLU(x0 Win + bin)                                          (64)
+ *   3 layers:  p_j = (h_j Wm)/den_j (32),  m_i = Σ_{j∈F(i)} p_j,
+ *              h = ReLU([h | m] Wl + bl)                            (64)
+ *   out = h·w_out + b_out,  t̂ = softplus(out)
+ *   loss = mean over users with c_i > 0 of (t̂_i − log(s_i/c_i))²
+ * Parameters: psi_mpnn_param_count() FP32 values, row-major, in the order
+ * Win [8×64], bin [64], then per layer Wm [64×32], Wl [96×64], bl [64],
+ * then w_out [64], b_out [1].  Wm, Wl and the activations h, p, m are used
+ * in bfloat16 (round to nearest even), products accumulate in FP32.
+ * Forward and backward are bitwise repeatable. */
+typedef struct psi_model psi_model;
+
+/* Number of FP32 parameters (25409). */
+int64_t psi_mpnn_param_count(void);
+
+/* Device bytes a model's state needs (parameters, Adam moments, gradient,
+ * bf16 weight fragments). */
+psi_status psi_model_state_size(size_t* bytes);
+
+/* Creates a model on the current device.  params: n_params FP32 values in
+ * the order above, host memory with PSI_INPUT_HOST in flags, else device
+ * memory; copied.  state: caller-owned device memory of at least
+ * psi_model_state_size bytes, kept by the model until psi_model_destroy
+ * (Adam moments start at zero).  Blocks until the copy is done. */
+psi_status psi_model_create(const float* params, int64_t n_params, uint32_t flags, void* state,
+                            size_t state_bytes, void* stream, psi_model** model);
+psi_status psi_model_destroy(psi_model* model);
+
+/* Copies the current parameters / the last gradient (FP32 [param_count])
+ * to out: host memory (blocks) with PSI_INPUT_HOST in flags, else device
+ * memory (enqueued only). */
+psi_status psi_model_params(const psi_model* model, float* out, uint32_t flags, void* stream);
+psi_status psi_model_grad(const psi_model* model, float* out, uint32_t flags, void* stream);
+
+/* Device workspace (bytes) of psi_mpnn_forward / psi_warmstart
+ * (training = 0) and of psi_mpnn_loss_backward (training = 1) on this
+ * operator: about 0.4 KB and 1.6 KB per user plus 2.2 bytes per edge. */
+psi_status psi_mpnn_workspace_size(const psi_operator* op, int32_t training, size_t* bytes);
+
+/* Forward pass on the operator's graph, enqueued only.  t_hat (device FP32
+ * [N]) and s0 (device FP64 [N], = c ⊙ exp(t̂)) may each be NULL.
+ * Model, operator and the current device must agree. */
+psi_status psi_mpnn_forward(psi_model* model, psi_operator* op, float* t_hat, double* s0,
+                            void* workspace, size_t workspace_bytes, void* stream);
+
+/* The warm start s0_out = c ⊙ exp(t̂) (device FP64 [N]), enqueued only; pass
+ * it to psi_solve as s0. */
+psi_status psi_warmstart(psi_model* model, psi_operator* op, double* s0_out, void* workspace,
+                         size_t workspace_bytes, void* stream);
+
+/* Forward pass, loss against s_target (device FP64 [N], the fixed point
+ * psi_solve returns in s_out) and backward pass; the gradient replaces the
+ * model's stored one (read it with psi_model_grad).  *loss (host, may be
+ * NULL; then the call only enqueues) receives the loss after the call
+ * blocks.  t_hat (device FP32 [N], may be NULL) receives t̂. */
+psi_status psi_mpnn_loss_backward(psi_model* model, psi_operator* op, const double* s_target,
+                                  double* loss, float* t_hat, void* workspace,
+                                  size_t workspace_bytes, void* stream);
+
+/* One Adam step (Kingma & Ba, bias-corrected) on the stored gradient,
+ * enqueued only.  Needs lr > 0, beta1, beta2 in [0, 1), eps > 0. */
+psi_status psi_mpnn_adam_step(psi_model* model, double lr, double beta1, double beta2, double eps,
+                              void* stream);
+
 #ifdef __cplusplus
 }
 #endif

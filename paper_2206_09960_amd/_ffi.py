@@ -72,6 +72,17 @@ SIGNATURES = [
     ("psi_batched_workspace_size", i32, [vp, i32, ctypes.POINTER(sz)]),
     ("psi_solve_batched", i32, [vp, ctypes.POINTER(Params), i32, vp, vp, vp, ctypes.POINTER(Info),
                                 vp, sz, vp]),
+    ("psi_mpnn_param_count", i64, []),
+    ("psi_model_state_size", i32, [ctypes.POINTER(sz)]),
+    ("psi_model_create", i32, [vp, i64, u32, vp, sz, vp, ctypes.POINTER(vp)]),
+    ("psi_model_destroy", i32, [vp]),
+    ("psi_model_params", i32, [vp, vp, u32, vp]),
+    ("psi_model_grad", i32, [vp, vp, u32, vp]),
+    ("psi_mpnn_workspace_size", i32, [vp, i32, ctypes.POINTER(sz)]),
+    ("psi_mpnn_forward", i32, [vp, vp, vp, vp, vp, sz, vp]),
+    ("psi_warmstart", i32, [vp, vp, vp, vp, sz, vp]),
+    ("psi_mpnn_loss_backward", i32, [vp, vp, vp, ctypes.POINTER(f64), vp, vp, sz, vp]),
+    ("psi_mpnn_adam_step", i32, [vp, f64, f64, f64, f64, vp]),
 ]
 
 _lib = None

@@ -295,3 +295,100 @@ def build_operator(graph, flags: int = 0, stream=None, device=None) -> Operator:
     """Operator from a synthetic graph record (host arrays)."""
     return Operator(graph.n, graph.follower, graph.leader, graph.lam, graph.mu,
                     node_offsets=graph.node_offsets, flags=flags, stream=stream, device=device)
+
+
+# ---------------------------------------------------------------------- learned warm start
+def mpnn_param_count() -> int:
+    return int(_ffi.load().psi_mpnn_param_count())
+
+
+class Model:
+    """The warm-start network (psi_model_*): FP32 parameters on the device,
+    Adam state, and the forward / backward / update calls of psi.h.
+
+    params: numpy float32 vector of mpnn_param_count() values (host copy)."""
+
+    def __init__(self, params, device=None, stream=None):
+        lib = _ffi.load()
+        self._lib = lib
+        self.device = torch.device(device) if device is not None else torch.device(
+            "cuda", torch.cuda.current_device())
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.shape != (mpnn_param_count(),):
+            raise ValueError(f"params must have {mpnn_param_count()} values")
+        nbytes = ctypes.c_size_t()
+        _check(lib.psi_model_state_size(ctypes.byref(nbytes)))
+        self.state = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib.psi_model_create(p.ctypes.data, p.size, PSI_INPUT_HOST,
+                                        self.state.data_ptr(), nbytes.value,
+                                        _stream_handle(stream), ctypes.byref(h)))
+        self._h = h
+        self._ws = {}
+
+    def params(self) -> np.ndarray:
+        out = np.empty(mpnn_param_count(), dtype=np.float32)
+        _check(self._lib.psi_model_params(self._h, out.ctypes.data, PSI_INPUT_HOST,
+                                          _stream_handle(None)))
+        return out
+
+    def grad(self) -> np.ndarray:
+        out = np.empty(mpnn_param_count(), dtype=np.float32)
+        _check(self._lib.psi_model_grad(self._h, out.ctypes.data, PSI_INPUT_HOST,
+                                        _stream_handle(None)))
+        return out
+
+    def workspace(self, op: Operator, training: bool) -> torch.Tensor:
+        key = (id(op), bool(training))
+        ws = self._ws.get(key)
+        if ws is None:
+            nb = ctypes.c_size_t()
+            _check(self._lib.psi_mpnn_workspace_size(op.handle, int(training), ctypes.byref(nb)))
+            ws = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+            self._ws = {key: ws}  # one cached workspace at a time
+        return ws
+
+    def forward(self, op: Operator, want_t_hat: bool = True, want_s0: bool = True, stream=None):
+        ws = self.workspace(op, False)
+        t_hat = torch.empty(op.n, dtype=torch.float32, device=self.device) if want_t_hat else None
+        s0 = torch.empty(op.n, dtype=torch.float64, device=self.device) if want_s0 else None
+        _check(self._lib.psi_mpnn_forward(self._h, op.handle, _ptr(t_hat), _ptr(s0),
+                                          ws.data_ptr(), ws.numel(), _stream_handle(stream)))
+        return t_hat, s0
+
+    def warmstart(self, op: Operator, s0_out: torch.Tensor | None = None, stream=None):
+        ws = self.workspace(op, False)
+        s0 = s0_out if s0_out is not None else torch.empty(op.n, dtype=torch.float64,
+                                                           device=self.device)
+        _check(self._lib.psi_warmstart(self._h, op.handle, s0.data_ptr(), ws.data_ptr(),
+                                       ws.numel(), _stream_handle(stream)))
+        return s0
+
+    def loss_backward(self, op: Operator, s_target: torch.Tensor, want_t_hat: bool = False,
+                      stream=None):
+        """Returns (loss, t_hat or None); the gradient stays in the model."""
+        ws = self.workspace(op, True)
+        s_target = s_target.to(self.device, torch.float64).contiguous()
+        t_hat = torch.empty(op.n, dtype=torch.float32, device=self.device) if want_t_hat else None
+        loss = ctypes.c_double()
+        _check(self._lib.psi_mpnn_loss_backward(self._h, op.handle, s_target.data_ptr(),
+                                                ctypes.byref(loss), _ptr(t_hat), ws.data_ptr(),
+                                                ws.numel(), _stream_handle(stream)))
+        return loss.value, t_hat
+
+    def adam_step(self, lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999,
+                  eps: float = 1e-8, stream=None):
+        _check(self._lib.psi_mpnn_adam_step(self._h, lr, beta1, beta2, eps,
+                                            _stream_handle(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.psi_model_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -253,4 +253,80 @@ psi_status psi_solve_batched(psi_operator* op, const psi_params* prm, int32_t n_
   PSI_GUARD_END
 }
 
+/* ---- learned warm start ---------------------------------------------------- */
+int64_t psi_mpnn_param_count(void) { return psi::mpnn_param_count(); }
+
+psi_status psi_model_state_size(size_t* bytes) {
+  PSI_GUARD_BEGIN
+  PSI_REQUIRE(bytes, "bytes must not be NULL");
+  *bytes = psi::model_state_size();
+  return PSI_OK;
+  PSI_GUARD_END
+}
+
+psi_status psi_model_create(const float* params, int64_t n_params, uint32_t flags, void* state,
+                            size_t state_bytes, void* stream, psi_model** model) {
+  PSI_GUARD_BEGIN
+  return psi::model_create(params, n_params, flags, state, state_bytes,
+                           static_cast<hipStream_t>(stream), model);
+  PSI_GUARD_END
+}
+
+psi_status psi_model_destroy(psi_model* model) {
+  PSI_GUARD_BEGIN
+  return psi::model_destroy(model);
+  PSI_GUARD_END
+}
+
+psi_status psi_model_params(const psi_model* model, float* out, uint32_t flags, void* stream) {
+  PSI_GUARD_BEGIN
+  return psi::model_get(model, 0, out, flags, static_cast<hipStream_t>(stream));
+  PSI_GUARD_END
+}
+
+psi_status psi_model_grad(const psi_model* model, float* out, uint32_t flags, void* stream) {
+  PSI_GUARD_BEGIN
+  return psi::model_get(model, 1, out, flags, static_cast<hipStream_t>(stream));
+  PSI_GUARD_END
+}
+
+psi_status psi_mpnn_workspace_size(const psi_operator* op, int32_t training, size_t* bytes) {
+  PSI_GUARD_BEGIN
+  return psi::mpnn_workspace_size(op, training, bytes);
+  PSI_GUARD_END
+}
+
+psi_status psi_mpnn_forward(psi_model* model, psi_operator* op, float* t_hat, double* s0,
+                            void* workspace, size_t workspace_bytes, void* stream) {
+  PSI_GUARD_BEGIN
+  return psi::mpnn_forward(model, op, t_hat, s0, workspace, workspace_bytes,
+                           static_cast<hipStream_t>(stream));
+  PSI_GUARD_END
+}
+
+psi_status psi_warmstart(psi_model* model, psi_operator* op, double* s0_out, void* workspace,
+                         size_t workspace_bytes, void* stream) {
+  PSI_GUARD_BEGIN
+  PSI_REQUIRE(s0_out, "s0_out must not be NULL");
+  return psi::mpnn_forward(model, op, nullptr, s0_out, workspace, workspace_bytes,
+                           static_cast<hipStream_t>(stream));
+  PSI_GUARD_END
+}
+
+psi_status psi_mpnn_loss_backward(psi_model* model, psi_operator* op, const double* s_target,
+                                  double* loss, float* t_hat, void* workspace,
+                                  size_t workspace_bytes, void* stream) {
+  PSI_GUARD_BEGIN
+  return psi::mpnn_loss_backward(model, op, s_target, loss, t_hat, workspace, workspace_bytes,
+                                 static_cast<hipStream_t>(stream));
+  PSI_GUARD_END
+}
+
+psi_status psi_mpnn_adam_step(psi_model* model, double lr, double beta1, double beta2, double eps,
+                              void* stream) {
+  PSI_GUARD_BEGIN
+  return psi::mpnn_adam_step(model, lr, beta1, beta2, eps, static_cast<hipStream_t>(stream));
+  PSI_GUARD_END
+}
+
 }  // extern "C"

@@ -237,4 +237,20 @@ psi_status solve_graphs(psi_operator* op, const psi_params* prm, double* psi_out
 psi_status solve_batched(psi_operator* op, const psi_params* prm, int n_scenarios,
                          const double* lambda, const double* mu, double* psi_out, psi_info* infos,
                          void* ws, size_t ws_bytes, hipStream_t st);
+
+// learned warm start (psi_mpnn.hip)
+int64_t mpnn_param_count();
+size_t model_state_size();
+psi_status model_create(const float* params, int64_t n_params, uint32_t flags, void* state,
+                        size_t state_bytes, hipStream_t st, psi_model** out);
+psi_status model_destroy(psi_model* md);
+psi_status model_get(const psi_model* md, int what, float* out, uint32_t flags, hipStream_t st);
+psi_status mpnn_workspace_size(const psi_operator* op, int training, size_t* bytes);
+psi_status mpnn_forward(psi_model* md, psi_operator* op, float* t_hat, double* s0, void* ws,
+                        size_t ws_bytes, hipStream_t st);
+psi_status mpnn_loss_backward(psi_model* md, psi_operator* op, const double* s_target,
+                              double* loss, float* t_hat, void* ws, size_t ws_bytes,
+                              hipStream_t st);
+psi_status mpnn_adam_step(psi_model* md, double lr, double beta1, double beta2, double eps,
+                          hipStream_t st);
 }  // namespace psi
