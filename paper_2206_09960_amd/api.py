@@ -340,13 +340,14 @@ class Model:
         return out
 
     def workspace(self, op: Operator, training: bool) -> torch.Tensor:
-        key = (id(op), bool(training))
-        ws = self._ws.get(key)
-        if ws is None:
-            nb = ctypes.c_size_t()
-            _check(self._lib.psi_mpnn_workspace_size(op.handle, int(training), ctypes.byref(nb)))
+        """One device workspace, grown to the largest size asked for so far."""
+        nb = ctypes.c_size_t()
+        _check(self._lib.psi_mpnn_workspace_size(op.handle, int(training), ctypes.byref(nb)))
+        ws = self._ws.get("buf")
+        if ws is None or ws.numel() < nb.value:
+            self._ws["buf"] = None
             ws = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
-            self._ws = {key: ws}  # one cached workspace at a time
+            self._ws["buf"] = ws
         return ws
 
     def forward(self, op: Operator, want_t_hat: bool = True, want_s0: bool = True, stream=None):

@@ -515,6 +515,14 @@ static void layout_persistent(int64_t n, int64_t m_raw, int n_graphs, uint32_t f
   char* seg_part_open = take(8 * size_t(max_seg_tiles));
   char* seg_y = take(8 * size_t(8 * n));
   char* seg_scan_tmp = take(4 * size_t((n + 1) / 4096 + 8));
+  const int64_t mp_max_hubs = m_raw / (kMpHubEdges + 1) + 1;
+  const int64_t mp_max_chunks = m_raw / kMpChunkEdges + mp_max_hubs + 1;
+  char* mp[2][3];
+  for (int o = 0; o < 2; ++o) {
+    mp[o][0] = take(4 * size_t(mp_max_hubs));
+    mp[o][1] = take(4 * size_t(mp_max_hubs + 1));
+    mp[o][2] = take(4 * size_t(mp_max_chunks));
+  }
   *total = off;
   if (!op) return;
   op->row_ptr = (int*)row_ptr;
@@ -563,6 +571,14 @@ static void layout_persistent(int64_t n, int64_t m_raw, int n_graphs, uint32_t f
   op->seg_y = (double*)seg_y;
   op->seg_scan_tmp = (uint32_t*)seg_scan_tmp;
   op->max_seg_tiles = max_seg_tiles;
+  op->mp_max_hubs = mp_max_hubs;
+  op->mp_max_chunks = mp_max_chunks;
+  for (int o = 0; o < 2; ++o) {
+    op->mp_hubs[o].hub_rows = (int*)mp[o][0];
+    op->mp_hubs[o].chunk0 = (uint32_t*)mp[o][1];
+    op->mp_hubs[o].chunk_hub = (int*)mp[o][2];
+    op->mp_hubs[o].n_hubs = -1;
+  }
 }
 
 static size_t scratch_size(int64_t n, int64_t m_raw) {

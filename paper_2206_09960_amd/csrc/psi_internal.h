@@ -51,6 +51,18 @@ enum : unsigned {
   kErrSlotTimeout = 8u,  // a cross-tile slot was not filled in time (never expected)
 };
 
+// Message-passing aggregation: rows with more than kMpHubEdges entries are
+// cut into chunks of kMpChunkEdges.
+constexpr int kMpHubEdges = 64;
+constexpr int kMpChunkEdges = 512;
+struct MpHubs {
+  int* hub_rows = nullptr;     // [max_hubs] rows with more than kMpHubEdges entries
+  uint32_t* chunk0 = nullptr;  // [max_hubs + 1] first chunk of each hub
+  int* chunk_hub = nullptr;    // [max_chunks] hub of each chunk
+  int64_t n_hubs = -1;         // -1 until built
+  int64_t n_chunks = 0;
+};
+
 // Device-side control block of one operator (one solve at a time).
 struct Ctrl {
   unsigned int ticket;    // tiles finished in the current pass
@@ -187,6 +199,10 @@ struct psi_operator {
   int seg_S = 0;            // segments currently built (0 = none)
   int seg_items = 0;        // tile size of their schedules
   psi::SegInfo seg[8]{};
+  // hub schedule of the message-passing aggregation, one per orientation
+  // (0: CSR(Aᵀ), 1: CSR(A)); built on first use
+  psi::MpHubs mp_hubs[2]{};
+  int64_t mp_max_hubs = 0, mp_max_chunks = 0;
   int* seg_col = nullptr;       // [m]
   int* seg_row_ptr = nullptr;   // [8 * (n + 1)]
   int* seg_tile_row = nullptr;  // [max_seg_tiles + 8]

@@ -69,9 +69,6 @@ constexpr int kFragsPerLayer = 16;
 constexpr size_t kFragBytes = size_t(kLayers) * kFragsPerLayer * 64 * 16;
 
 // ---------------------------------------------------------------- work split
-constexpr int kGroupItems = 64;   // merge-path items (rows + edges) per 8-lane group tile
-constexpr int kHubEdges = 64;     // rows longer than this are cut into chunks
-constexpr int kChunkEdges = 512;  // edges per hub chunk (one workgroup)
 constexpr int kNodeRows = 64;     // users per workgroup tile of the dense kernels
 constexpr int kMaxNodeGrid = 2048;
 constexpr int kMaxBwGrid = 256;
@@ -125,15 +122,14 @@ __device__ inline void features(const OpView& o, int64_t r, float x[kF0]) {
     return;
   }
   const double lam = o.lam[r], mu = o.mu[r], iv = o.invden[r];
-  const double den = iv > 0.0 ? 1.0 / iv : 0.0;
-  x[0] = float(log(lam));
-  x[1] = float(log(mu + 1e-12));
+  x[0] = logf(float(lam));
+  x[1] = logf(float(mu) + 1e-12f);
   x[2] = float(o.c[r]);
   x[3] = float(o.d[r]);
-  x[4] = float(log1p(double(o.row_ptr[r + 1] - o.row_ptr[r])));
-  x[5] = float(log1p(double(o.fm_row_ptr[r + 1] - o.fm_row_ptr[r])));
-  x[6] = float(log1p(den));
-  x[7] = float(log(lam + mu));
+  x[4] = log1pf(float(o.row_ptr[r + 1] - o.row_ptr[r]));
+  x[5] = log1pf(float(o.fm_row_ptr[r + 1] - o.fm_row_ptr[r]));
+  x[6] = iv > 0.0 ? log1pf(float(1.0 / iv)) : 0.f;
+  x[7] = logf(float(lam + mu));
 }
 
 // ---------------------------------------------------------------- weights
@@ -178,33 +174,14 @@ __global__ void k_mp_adam(float* p, float* m, float* v, const float* g, int n, f
   p[k] -= lr * (mk * c1) / (sqrtf(vk * c2) + eps);
 }
 
-// ---------------------------------------------------------------- schedules
-// Group tiles holding whole rows: the merge-path row at diagonal b·items,
-// moved past a row that straddles the diagonal.
-__global__ void k_mp_row_tiles(const int* row_ptr, int64_t n, int64_t m, int64_t items,
-                               int64_t n_tiles, int* row_tiles) {
-  const int64_t b = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (b > n_tiles) return;
-  const int64_t diag = std::min(b * items, n + m);
-  int64_t lo = std::max<int64_t>(diag - m, 0), hi = std::min<int64_t>(diag, n);
-  while (lo < hi) {
-    const int64_t p = (lo + hi) >> 1;
-    if (int64_t(row_ptr[p + 1]) <= diag - p - 1) lo = p + 1; else hi = p;
-  }
-  int64_t r = lo;
-  if (r < n && diag - lo > row_ptr[r]) ++r;
-  row_tiles[b] = static_cast<int>(b == n_tiles ? n : r);
-}
-
+// ---------------------------------------------------------------- hub schedule
+// Rows with more than kMpHubEdges entries ("hubs") are cut into chunks of
+// kMpChunkEdges; the list of hubs and the chunk → hub table depend only on
+// the operator and are built once per orientation.
 __global__ void k_mp_hub_flags(const int* row_ptr, int64_t n, uint32_t* flags) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i > n) return;
-  flags[i] = (i < n && row_ptr[i + 1] - row_ptr[i] > kHubEdges) ? 1u : 0u;
-}
-
-__global__ void k_mp_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = v;
+  flags[i] = (i < n && row_ptr[i + 1] - row_ptr[i] > kMpHubEdges) ? 1u : 0u;
 }
 
 __global__ void k_mp_hub_list(const int* row_ptr, int64_t n, const uint32_t* pos, int* hub_rows,
@@ -212,17 +189,15 @@ __global__ void k_mp_hub_list(const int* row_ptr, int64_t n, const uint32_t* pos
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int len = row_ptr[i + 1] - row_ptr[i];
-  if (len > kHubEdges) {
+  if (len > kMpHubEdges) {
     hub_rows[pos[i]] = static_cast<int>(i);
-    nchunk[pos[i]] = static_cast<uint32_t>((len + kChunkEdges - 1) / kChunkEdges);
+    nchunk[pos[i]] = static_cast<uint32_t>((len + kMpChunkEdges - 1) / kMpChunkEdges);
   }
 }
 
-// chunk → hub; n_hubs is read from the device (the scan total at flags[n]).
-__global__ void k_mp_chunk_table(const uint32_t* n_hubs_p, const uint32_t* chunk0, int64_t max_hubs,
-                                 int* chunk_hub) {
+__global__ void k_mp_chunk_table(const uint32_t* chunk0, int64_t n_hubs, int* chunk_hub) {
   const int64_t h = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (h >= max_hubs || h >= int64_t(*n_hubs_p)) return;
+  if (h >= n_hubs) return;
   for (uint32_t c = chunk0[h]; c < chunk0[h + 1]; ++c) chunk_hub[c] = static_cast<int>(h);
 }
 
@@ -230,29 +205,23 @@ __global__ void k_mp_chunk_table(const uint32_t* n_hubs_p, const uint32_t* chunk
 // Forward: out_i = bf16(log1p(max((λ_i + μ_i) Σ_{j∈row i} in_j, 0))), in/out
 // bf16 [n × 32].
 // Backward: out_i = invden_i · Σ_{j∈row i} in_j, in/out FP32 [n × 32].
-// Eight lanes carry one 32-vector (4 values each); a wave sums 8 rows at once.
-struct Sched {
+// Eight lanes carry one 32-vector (4 values each).  A row of at most
+// kMpHubEdges entries belongs to one 8-lane group, which loads 16 column
+// indices, then issues the 16 gathers, then adds them in edge order; hub
+// chunks are summed by a workgroup (16 consecutive edges per group, the 32
+// group sums added in group order) and finished per hub in chunk order.
+struct AggArgs {
   const int* row_ptr;
   const int* col;
-  int64_t n, m;
-  int* row_tiles;
-  int64_t n_gtiles;
-  uint32_t* flags;     // [n + 1]: hub flags, then their exclusive scan ([n] = n_hubs)
-  uint32_t* scan_tmp;
-  uint32_t* scan_total;
-  int* hub_rows;       // [max_hubs]
-  uint32_t* chunk0;    // [max_hubs + 1]
-  int* chunk_hub;      // [max_chunks]
-  float* chunk_part;   // [max_chunks × 32]
-  int64_t max_hubs, max_chunks;
-};
-
-struct AggArgs {
-  Sched s;
+  int64_t n;
+  const int* hub_rows;
+  const uint32_t* chunk0;
+  const int* chunk_hub;
+  float* chunk_part;      // [n_chunks × 32]
   const void* in;
   void* out;
-  const double* invden;      // backward: row scale
-  const double *lam, *mu;    // forward: receiver factor λ + μ
+  const double* invden;   // backward: row scale
+  const double *lam, *mu; // forward: receiver factor λ + μ
 };
 
 template <bool BW>
@@ -282,107 +251,76 @@ __device__ inline void agg_store(const AggArgs& a, int64_t r, int q, f32x4_t v) 
   }
 }
 
+// Sum of edges [b, min(b + 16, e1)) into acc, in edge order; b < e1.  Indices
+// past the end repeat the last edge (in bounds, not added), so the 16 loads
+// issue back to back.
 template <bool BW>
-__global__ __launch_bounds__(kBlock) void k_mp_agg_rows(AggArgs a) {
-  const int64_t g = (int64_t(blockIdx.x) * kBlock + threadIdx.x) >> 3;
-  const int q = threadIdx.x & 7;
-  if (g >= a.s.n_gtiles) return;  // whole groups leave; no barriers follow
-  const int r1 = a.s.row_tiles[g + 1];
-  int r = a.s.row_tiles[g];
-  int e1 = r < r1 ? a.s.row_ptr[r] : 0;
-  for (; r < r1; ++r) {
-    const int e0 = e1;
-    e1 = a.s.row_ptr[r + 1];
-    if (e1 - e0 > kHubEdges) continue;  // summed by the hub kernels
-    f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
-    int e = e0;
-    for (; e + 4 <= e1; e += 4) {
-      const int j0 = a.s.col[e], j1 = a.s.col[e + 1], j2 = a.s.col[e + 2], j3 = a.s.col[e + 3];
-      const f32x4_t v0 = agg_load<BW>(a.in, j0, q), v1 = agg_load<BW>(a.in, j1, q);
-      const f32x4_t v2 = agg_load<BW>(a.in, j2, q), v3 = agg_load<BW>(a.in, j3, q);
-      acc += v0;
-      acc += v1;
-      acc += v2;
-      acc += v3;
-    }
-    for (; e < e1; ++e) acc += agg_load<BW>(a.in, a.s.col[e], q);
-    agg_store<BW>(a, r, q, acc);
-  }
+__device__ inline void sum16(const AggArgs& a, int b, int e1, int q, f32x4_t& acc) {
+  int j[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) j[u] = a.col[min(b + u, e1 - 1)];
+  f32x4_t v[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) v[u] = agg_load<BW>(a.in, j[u], q);
+#pragma unroll
+  for (int u = 0; u < 16; ++u)
+    if (b + u < e1) acc += v[u];
 }
 
-// One workgroup per hub chunk (grid-stride): group gi of 32 sums edges
-// e0 + gi, e0 + gi + 32, ...; the 32 group sums are added in group order.
-// A hub of one chunk is finished here, longer hubs by k_mp_agg_hub_finish.
+template <bool BW>
+__global__ __launch_bounds__(kBlock) void k_mp_agg_rows(AggArgs a) {
+  const int64_t r = (int64_t(blockIdx.x) * kBlock + threadIdx.x) >> 3;
+  const int q = threadIdx.x & 7;
+  if (r >= a.n) return;  // whole groups leave; no barriers follow
+  const int e0 = a.row_ptr[r], e1 = a.row_ptr[r + 1];
+  if (e1 - e0 > kMpHubEdges) return;  // a hub: the chunk kernels sum it
+  f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
+  for (int b = e0; b < e1; b += 16) sum16<BW>(a, b, e1, q, acc);
+  agg_store<BW>(a, r, q, acc);
+}
+
+// One workgroup per hub chunk; group gi sums edges e0 + 16 gi .. + 15.
 template <bool BW>
 __global__ __launch_bounds__(kBlock) void k_mp_agg_hubs(AggArgs a) {
   __shared__ float red[32][kMsg + 1];
   const int gi = threadIdx.x >> 3;
   const int q = threadIdx.x & 7;
-  const uint32_t n_hubs = a.s.flags[a.s.n];
-  const int64_t n_chunks = n_hubs ? int64_t(a.s.chunk0[n_hubs]) : 0;
-  for (int64_t ch = blockIdx.x; ch < n_chunks; ch += gridDim.x) {
-    const int h = a.s.chunk_hub[ch];
-    const int r = a.s.hub_rows[h];
-    const int c0 = static_cast<int>(a.s.chunk0[h]), c1 = static_cast<int>(a.s.chunk0[h + 1]);
-    const int e0 = a.s.row_ptr[r] + (static_cast<int>(ch) - c0) * kChunkEdges;
-    const int e1 = min(e0 + kChunkEdges, a.s.row_ptr[r + 1]);
-    f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
-    int e = e0 + gi;
-    for (; e + 96 < e1; e += 128) {
-      const int j0 = a.s.col[e], j1 = a.s.col[e + 32], j2 = a.s.col[e + 64], j3 = a.s.col[e + 96];
-      const f32x4_t v0 = agg_load<BW>(a.in, j0, q), v1 = agg_load<BW>(a.in, j1, q);
-      const f32x4_t v2 = agg_load<BW>(a.in, j2, q), v3 = agg_load<BW>(a.in, j3, q);
-      acc += v0;
-      acc += v1;
-      acc += v2;
-      acc += v3;
-    }
-    for (; e < e1; e += 32) acc += agg_load<BW>(a.in, a.s.col[e], q);
+  const int ch = blockIdx.x;
+  const int h = a.chunk_hub[ch];
+  const int r = a.hub_rows[h];
+  const int e0 = a.row_ptr[r] + (ch - static_cast<int>(a.chunk0[h])) * kMpChunkEdges;
+  const int e1 = min(e0 + kMpChunkEdges, a.row_ptr[r + 1]);
+  f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
+  const int b = e0 + 16 * gi;
+  if (b < e1) sum16<BW>(a, b, e1, q, acc);
 #pragma unroll
-    for (int u = 0; u < 4; ++u) red[gi][4 * q + u] = acc[u];
-    __syncthreads();
-    if (threadIdx.x < kMsg) {
-      float v = 0.f;
-      for (int k = 0; k < 32; ++k) v += red[k][threadIdx.x];
-      red[0][threadIdx.x] = v;  // only this thread reads column threadIdx.x
-    }
-    __syncthreads();
-    if (threadIdx.x < 8) {
-      const int qq = threadIdx.x;
-      const f32x4_t v = {red[0][4 * qq], red[0][4 * qq + 1], red[0][4 * qq + 2], red[0][4 * qq + 3]};
-      if (c1 - c0 == 1) {
-        agg_store<BW>(a, r, qq, v);
-      } else {
-        *reinterpret_cast<f32x4_t*>(a.s.chunk_part + ch * kMsg + 4 * qq) = v;
-      }
-    }
-    __syncthreads();
+  for (int u = 0; u < 4; ++u) red[gi][4 * q + u] = acc[u];
+  __syncthreads();
+  if (threadIdx.x < kMsg) {
+    float v = 0.f;
+    for (int k = 0; k < 32; ++k) v += red[k][threadIdx.x];
+    a.chunk_part[int64_t(ch) * kMsg + threadIdx.x] = v;
   }
 }
 
-// One workgroup per multi-chunk hub: 8 slices of the chunk list, then the
-// slices in order.
+// One workgroup per hub: 8 slices of its chunks, then the slices in order.
 template <bool BW>
 __global__ __launch_bounds__(kBlock) void k_mp_agg_hub_finish(AggArgs a) {
   __shared__ float red[8][kMsg];
   const int f = threadIdx.x & 31;
   const int slice = threadIdx.x >> 5;
-  const int64_t n_hubs = a.s.flags[a.s.n];
-  for (int64_t h = blockIdx.x; h < n_hubs; h += gridDim.x) {
-    const int c0 = static_cast<int>(a.s.chunk0[h]), c1 = static_cast<int>(a.s.chunk0[h + 1]);
-    if (c1 - c0 == 1) continue;  // uniform over the block
-    float v = 0.f;
-    for (int c = c0 + slice; c < c1; c += 8) v += a.s.chunk_part[int64_t(c) * kMsg + f];
-    red[slice][f] = v;
-    __syncthreads();
-    if (threadIdx.x < 8) {
-      const int qq = threadIdx.x;
-      f32x4_t s = {0.f, 0.f, 0.f, 0.f};
-      for (int k = 0; k < 8; ++k)
-        s += f32x4_t{red[k][4 * qq], red[k][4 * qq + 1], red[k][4 * qq + 2], red[k][4 * qq + 3]};
-      agg_store<BW>(a, a.s.hub_rows[h], qq, s);
-    }
-    __syncthreads();
+  const int h = blockIdx.x;
+  const int c0 = static_cast<int>(a.chunk0[h]), c1 = static_cast<int>(a.chunk0[h + 1]);
+  float v = 0.f;
+  for (int c = c0 + slice; c < c1; c += 8) v += a.chunk_part[int64_t(c) * kMsg + f];
+  red[slice][f] = v;
+  __syncthreads();
+  if (threadIdx.x < 8) {
+    const int qq = threadIdx.x;
+    f32x4_t s = {0.f, 0.f, 0.f, 0.f};
+    for (int k = 0; k < 8; ++k)
+      s += f32x4_t{red[k][4 * qq], red[k][4 * qq + 1], red[k][4 * qq + 2], red[k][4 * qq + 3]};
+    agg_store<BW>(a, a.hub_rows[h], qq, s);
   }
 }
 
@@ -505,7 +443,7 @@ __global__ __launch_bounds__(kBlock) void k_mp_node(NodeArgs a) {
         hs[w][4 * grp + q][16 * t + colq] = hb[t][q];
       }
     __syncthreads();
-    {
+    if (KIND < 2 || TRAIN) {  // the last layer's h is kept only for the backward pass
       const int rr = lane >> 2, part = lane & 3;
       const int64_t r = r0 + rr;
       if (r < n) {
@@ -909,7 +847,10 @@ __global__ void k_mp_grad_reduce(const float* part, int grid, float* grad) {
 
 // ---------------------------------------------------------------- workspace
 struct MpWs {
-  Sched fwd, bwd;
+  uint32_t* flags;      // [n + 1] hub flags (schedule build)
+  uint32_t* scan_tmp;
+  uint32_t* scan_total;
+  float* chunk_part;    // [max_chunks × 32]
   unsigned short* h[4];
   unsigned short* m[3];
   unsigned short* msg;
@@ -923,31 +864,6 @@ struct MpWs {
   int node_grid, bw_grid;
 };
 
-size_t sched_layout(int64_t n, int64_t m, Sched* s, char* base, size_t off) {
-  auto take = [&](size_t bytes) -> char* {
-    char* p = base ? base + off : nullptr;
-    off += align_up(std::max<size_t>(bytes, 1));
-    return p;
-  };
-  Sched t{};
-  t.n = n;
-  t.m = m;
-  t.n_gtiles = (n + m) / kGroupItems + 2;
-  t.max_hubs = m / (kHubEdges + 1) + 1;
-  t.max_chunks = m / kChunkEdges + t.max_hubs + 1;
-  t.row_tiles = (int*)take(4 * size_t(t.n_gtiles + 1));
-  t.flags = (uint32_t*)take(4 * size_t(n + 1));
-  const int64_t scan_n = std::max<int64_t>(n + 1, t.max_hubs + 1);
-  t.scan_tmp = (uint32_t*)take(4 * size_t(scan_tile_count(scan_n) + 8));
-  t.scan_total = (uint32_t*)take(16);
-  t.hub_rows = (int*)take(4 * size_t(t.max_hubs));
-  t.chunk0 = (uint32_t*)take(4 * size_t(t.max_hubs + 1));
-  t.chunk_hub = (int*)take(4 * size_t(t.max_chunks));
-  t.chunk_part = (float*)take(4 * size_t(kMsg) * size_t(t.max_chunks));
-  if (s) *s = t;
-  return off;
-}
-
 int node_grid_for(int64_t n) {
   return int(std::min<int64_t>((n + kNodeRows - 1) / kNodeRows, kMaxNodeGrid));
 }
@@ -956,7 +872,7 @@ int bw_grid_for(int64_t n) {
 }
 
 size_t mp_layout(const psi_operator* op, bool training, MpWs* w, char* base) {
-  const int64_t n = op->n, m = op->m;
+  const int64_t n = op->n;
   MpWs t{};
   size_t off = 0;
   auto take = [&](size_t bytes) -> char* {
@@ -964,8 +880,11 @@ size_t mp_layout(const psi_operator* op, bool training, MpWs* w, char* base) {
     off += align_up(std::max<size_t>(bytes, 1));
     return p;
   };
-  off = sched_layout(n, m, &t.fwd, base, off);
-  if (training) off = sched_layout(n, m, &t.bwd, base, off);
+  t.flags = (uint32_t*)take(4 * size_t(n + 1));
+  const int64_t scan_n = std::max<int64_t>(n + 1, op->mp_max_hubs + 1);
+  t.scan_tmp = (uint32_t*)take(4 * size_t(scan_tile_count(scan_n) + 8));
+  t.scan_total = (uint32_t*)take(16);
+  t.chunk_part = (float*)take(4 * size_t(kMsg) * size_t(op->mp_max_chunks));
   const int n_h = training ? 4 : 2;
   for (int k = 0; k < n_h; ++k) t.h[k] = (unsigned short*)take(2 * size_t(n) * kH);
   const int n_m = training ? 3 : 1;
@@ -987,37 +906,53 @@ size_t mp_layout(const psi_operator* op, bool training, MpWs* w, char* base) {
   return off;
 }
 
-psi_status build_sched(Sched& s, const int* row_ptr, const int* col, hipStream_t st) {
-  s.row_ptr = row_ptr;
-  s.col = col;
-  const int64_t n = s.n;
-  hipLaunchKernelGGL(k_mp_row_tiles, dim3(grid_for(s.n_gtiles + 1)), dim3(kBlock), 0, st, row_ptr,
-                     n, s.m, int64_t(kGroupItems), s.n_gtiles, s.row_tiles);
+// The hub schedule of orientation o (0: CSR(Aᵀ), 1: CSR(A)), built on first
+// use and kept in the operator.  Blocks twice to learn the hub and chunk counts.
+psi_status ensure_hubs(psi_operator* op, int o, MpWs& w, hipStream_t st) {
+  MpHubs& hb = op->mp_hubs[o];
+  if (hb.n_hubs >= 0) return PSI_OK;
+  const int* row_ptr = o == 0 ? op->row_ptr : op->fm_row_ptr;
+  const int64_t n = op->n;
   hipLaunchKernelGGL(k_mp_hub_flags, dim3(grid_for(n + 1)), dim3(kBlock), 0, st, row_ptr, n,
-                     s.flags);
-  psi_status r = scan_exclusive_u32(s.flags, s.flags, n + 1, s.scan_tmp, s.scan_total, st);
+                     w.flags);
+  psi_status r = scan_exclusive_u32(w.flags, w.flags, n + 1, w.scan_tmp, w.scan_total, st);
   if (r != PSI_OK) return r;
-  hipLaunchKernelGGL(k_mp_fill_u32, dim3(grid_for(s.max_hubs + 1)), dim3(kBlock), 0, st, s.chunk0,
-                     s.max_hubs + 1, 0u);
-  hipLaunchKernelGGL(k_mp_hub_list, dim3(grid_for(n)), dim3(kBlock), 0, st, row_ptr, n, s.flags,
-                     s.hub_rows, s.chunk0);
-  r = scan_exclusive_u32(s.chunk0, s.chunk0, s.max_hubs + 1, s.scan_tmp, s.scan_total, st);
-  if (r != PSI_OK) return r;
-  hipLaunchKernelGGL(k_mp_chunk_table, dim3(grid_for(s.max_hubs)), dim3(kBlock), 0, st,
-                     s.flags + n, s.chunk0, s.max_hubs, s.chunk_hub);
-  PSI_HIP_CHECK(hipGetLastError());
+  uint32_t n_hubs = 0;
+  PSI_HIP_CHECK(hipMemcpyAsync(&n_hubs, w.flags + n, 4, hipMemcpyDeviceToHost, st));
+  PSI_HIP_CHECK(hipStreamSynchronize(st));
+  PSI_REQUIRE(int64_t(n_hubs) <= op->mp_max_hubs, "internal: hub count exceeds its bound");
+  uint32_t n_chunks = 0;
+  if (n_hubs > 0) {
+    hipLaunchKernelGGL(k_mp_hub_list, dim3(grid_for(n)), dim3(kBlock), 0, st, row_ptr, n,
+                       w.flags, hb.hub_rows, hb.chunk0);
+    PSI_HIP_CHECK(hipMemsetAsync(hb.chunk0 + n_hubs, 0, 4, st));
+    r = scan_exclusive_u32(hb.chunk0, hb.chunk0, int64_t(n_hubs) + 1, w.scan_tmp, w.scan_total,
+                           st);
+    if (r != PSI_OK) return r;
+    PSI_HIP_CHECK(hipMemcpyAsync(&n_chunks, hb.chunk0 + n_hubs, 4, hipMemcpyDeviceToHost, st));
+    PSI_HIP_CHECK(hipStreamSynchronize(st));
+    PSI_REQUIRE(int64_t(n_chunks) <= op->mp_max_chunks, "internal: chunk count exceeds its bound");
+    hipLaunchKernelGGL(k_mp_chunk_table, dim3(grid_for(n_hubs)), dim3(kBlock), 0, st, hb.chunk0,
+                       int64_t(n_hubs), hb.chunk_hub);
+    PSI_HIP_CHECK(hipGetLastError());
+  }
+  hb.n_hubs = n_hubs;
+  hb.n_chunks = n_chunks;
   return PSI_OK;
 }
 
 template <bool BW>
-psi_status aggregate(const Sched& s, const void* in, void* out, const psi_operator* op,
+psi_status aggregate(const psi_operator* op, int o, MpWs& w, const void* in, void* out,
                      hipStream_t st) {
-  AggArgs a{s, in, out, op->invden, op->lam, op->mu};
-  hipLaunchKernelGGL(k_mp_agg_rows<BW>, dim3(grid_for(s.n_gtiles * 8)), dim3(kBlock), 0, st, a);
-  const unsigned hub_grid = unsigned(std::min<int64_t>(s.max_chunks, 4096));
-  hipLaunchKernelGGL(k_mp_agg_hubs<BW>, dim3(hub_grid), dim3(kBlock), 0, st, a);
-  const unsigned fin_grid = unsigned(std::min<int64_t>(s.max_hubs, 1024));
-  hipLaunchKernelGGL(k_mp_agg_hub_finish<BW>, dim3(fin_grid), dim3(kBlock), 0, st, a);
+  const MpHubs& hb = op->mp_hubs[o];
+  AggArgs a{o == 0 ? op->row_ptr : op->fm_row_ptr, o == 0 ? op->col : op->fm_col, op->n,
+            hb.hub_rows, hb.chunk0, hb.chunk_hub, w.chunk_part, in, out, op->invden, op->lam,
+            op->mu};
+  hipLaunchKernelGGL(k_mp_agg_rows<BW>, dim3(grid_for(op->n * 8)), dim3(kBlock), 0, st, a);
+  if (hb.n_hubs > 0) {
+    hipLaunchKernelGGL(k_mp_agg_hubs<BW>, dim3(unsigned(hb.n_chunks)), dim3(kBlock), 0, st, a);
+    hipLaunchKernelGGL(k_mp_agg_hub_finish<BW>, dim3(unsigned(hb.n_hubs)), dim3(kBlock), 0, st, a);
+  }
   PSI_HIP_CHECK(hipGetLastError());
   return PSI_OK;
 }
@@ -1035,7 +970,7 @@ const u32x4_t* frag_wm(const psi_model* md, int l) { return frag_wl(md, l) + 12 
 template <bool TRAIN>
 psi_status forward(psi_model* md, psi_operator* op, MpWs& w, float* t_hat, double* s0,
                    const double* s_target, hipStream_t st) {
-  psi_status r = build_sched(w.fwd, op->row_ptr, op->col, st);
+  psi_status r = ensure_hubs(op, 0, w, st);
   if (r != PSI_OK) return r;
   NodeArgs a{};
   a.o = op_view(op);
@@ -1049,7 +984,7 @@ psi_status forward(psi_model* md, psi_operator* op, MpWs& w, float* t_hat, doubl
   a.frag_wm = frag_wm(md, 0);
   hipLaunchKernelGGL((k_mp_node<0, TRAIN>), grid, block, 0, st, a);
   for (int l = 0; l < kLayers; ++l) {
-    r = aggregate<false>(w.fwd, w.msg, m_at(l), op, st);
+    r = aggregate<false>(op, 0, w, w.msg, m_at(l), st);
     if (r != PSI_OK) return r;
     a.layer = l;
     a.h_in = h_at(l);
@@ -1077,7 +1012,7 @@ psi_status forward(psi_model* md, psi_operator* op, MpWs& w, float* t_hat, doubl
 
 psi_status backward(psi_model* md, psi_operator* op, MpWs& w, const double* s_target,
                     hipStream_t st) {
-  psi_status r = build_sched(w.bwd, op->fm_row_ptr, op->fm_col, st);
+  psi_status r = ensure_hubs(op, 1, w, st);
   if (r != PSI_OK) return r;
   BwArgs b{};
   b.o = op_view(op);
@@ -1098,7 +1033,7 @@ psi_status backward(psi_model* md, psi_operator* op, MpWs& w, const double* s_ta
     b.dhp_out = w.dhp[l & 1];
     if (l == kLayers - 1) hipLaunchKernelGGL(k_mp_bw<0>, grid, block, 0, st, b);
     else hipLaunchKernelGGL(k_mp_bw<1>, grid, block, 0, st, b);
-    r = aggregate<true>(w.bwd, w.dm, w.dmsg, op, st);
+    r = aggregate<true>(op, 1, w, w.dm, w.dmsg, st);
     if (r != PSI_OK) return r;
   }
   b.layer = 0;
