@@ -103,6 +103,35 @@ def chung_lu_edges(n: int, m_target: int, gamma: float, seed: int,
     return follower, leader
 
 
+def chung_lu_edges_torch(n: int, m_target: int, gamma: float, seed: int,
+                         d_max: float | None = None, device="cpu"):
+    """chung_lu_edges drawn with torch on ``device``: the same edges, bit for
+    bit (the N-sized weights and permutation are still computed by NumPy)."""
+    import torch
+    if n < 2:
+        raise ValueError("need at least two users")
+    if d_max is None:
+        d_max = n - 1
+    w = capped_weights(n, float(m_target), gamma, float(d_max))
+    cdf = np.cumsum(w)
+    cdf /= cdf[-1]
+    cdf_t = torch.from_numpy(cdf).to(device)
+    perm_t = torch.from_numpy(permutation(n, seed)).to(device)
+    follower = torch.empty(m_target, dtype=torch.int32, device=device)
+    leader = torch.empty(m_target, dtype=torch.int32, device=device)
+    chunk = 1 << 26
+    for start in range(0, m_target, chunk):
+        cnt = min(chunk, m_target - start)
+        u0 = rng.uniform01_torch(seed, STREAM_LEADER, cnt, start, device)
+        rank = torch.searchsorted(cdf_t, u0, right=True).clamp_(max=n - 1)
+        leader[start:start + cnt] = perm_t[rank]
+        del u0, rank
+        u1 = rng.uniform01_torch(seed, STREAM_FOLLOWER, cnt, start, device)
+        follower[start:start + cnt] = (u1 * n).to(torch.int64).clamp_(max=n - 1).to(torch.int32)
+        del u1
+    return follower, leader
+
+
 def activity(n: int, seed: int, kind: str = "lognormal", sigma: float = 1.0,
              scenario: int = 0) -> tuple[np.ndarray, np.ndarray]:
     if kind == "lognormal":
@@ -226,8 +255,19 @@ WORKLOADS = {
 }
 
 
-def workload(name: str) -> Graph:
+def workload(name: str, device=None) -> Graph:
+    """A named workload.  With ``device`` (a torch device) the edges are drawn
+    there by the torch twin and returned as torch int32 tensors; λ, μ stay
+    NumPy arrays.  Both routes give the same values."""
     w = dict(WORKLOADS[name])
     w.pop("tol", None)
     w.pop("scenarios", None)
-    return chung_lu(**w)
+    if device is None:
+        return chung_lu(**w)
+    n, seed, sigma = w["n"], w["seed"], w.get("sigma", 1.0)
+    m_target = int(round(n * w["mean_degree"]))
+    follower, leader = chung_lu_edges_torch(n, m_target, w["gamma"], seed, w.get("d_max"), device)
+    lam, mu = activity(n, seed, "lognormal", sigma)
+    return Graph(n, follower, leader, lam, mu,
+                 meta=dict(kind="chung_lu", n=n, m_target=m_target, gamma=w["gamma"], seed=seed,
+                           sigma=sigma, d_max=w.get("d_max") or n - 1, activity="lognormal"))

@@ -59,3 +59,34 @@ def standard_normal(seed: int, stream: int, count: int) -> np.ndarray:
     u1 = u[0::2]
     u2 = u[1::2]
     return np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)
+
+
+# ---------------------------------------------------------------- torch twin
+# The same words computed with torch int64 tensors (two's-complement wrapping
+# multiply, logical shifts by masking), on any device; used to draw the edges
+# of the largest graphs where they are consumed.
+def _i64(c: int) -> int:
+    return c - (1 << 64) if c >= (1 << 63) else c
+
+
+def _shr(z, k: int):
+    return (z >> k) & ((1 << (64 - k)) - 1)
+
+
+def mix64_torch(z):
+    z = (z ^ _shr(z, 30)) * _i64(0xBF58476D1CE4E5B9)
+    z = (z ^ _shr(z, 27)) * _i64(0x94D049BB133111EB)
+    return z ^ _shr(z, 31)
+
+
+def words_torch(seed: int, stream: int, start: int, count: int, device="cpu"):
+    import torch
+    key = int(stream_key(seed, stream))
+    idx = torch.arange(start + 1, start + 1 + count, dtype=torch.int64, device=device)
+    return mix64_torch(idx * _i64(0x9E3779B97F4A7C15) + _i64(key))
+
+
+def uniform01_torch(seed: int, stream: int, count: int, start: int = 0, device="cpu"):
+    import torch
+    w = words_torch(seed, stream, start, count, device)
+    return (_shr(w, 11).to(torch.float64) + 0.5) * _TWO_M53

@@ -40,3 +40,16 @@ def test_multi_graph_offsets():
     gid_f = np.searchsorted(g.node_offsets, g.follower, side="right")
     gid_l = np.searchsorted(g.node_offsets, g.leader, side="right")
     assert np.array_equal(gid_f, gid_l)  # no edge crosses graphs
+
+
+def test_torch_twin_draws_the_same_edges():
+    import torch
+    from synth import rng
+    w = rng.words(7, 3, 123_456, 5000)
+    wt = rng.words_torch(7, 3, 123_456, 5000)
+    assert np.array_equal(w.view(np.int64), wt.numpy())
+    assert np.array_equal(rng.uniform01(7, 3, 5000, 99), rng.uniform01_torch(7, 3, 5000, 99).numpy())
+    f, l = synth.chung_lu_edges(5000, 60_000, 2.1, 11, d_max=800)
+    ft, lt = synth.chung_lu_edges_torch(5000, 60_000, 2.1, 11, d_max=800)
+    assert np.array_equal(f, ft.numpy()) and np.array_equal(l, lt.numpy())
+    assert ft.dtype == torch.int32
