@@ -1,17 +1,24 @@
 #!/usr/bin/env python3
 """Power-ψ benchmark on one MI355X.
 
-Workload: directed Chung–Lu follower graph, N = 1,000,000 users, mean degree
-20 (≈20M edges), exponent 2.2, λ, μ ~ LogNormal(0, 1.5), tolerance 1e-8 on
-‖s_t − s_{t−1}‖₁, int32 CSR.  A step is one complete time-to-ψ solve (all
-Power-ψ passes, the fused axpy and gap reductions, and the final ψ pass) on
-the operator already resident in HBM; the one-time operator build is timed
+Default workload (cl_1m): directed Chung–Lu follower graph, N = 1,000,000
+users, mean degree 20 (≈20M edges), exponent 2.2, λ, μ ~ LogNormal(0, 1.5),
+tolerance 1e-8 on ‖s_t − s_{t−1}‖₁, int32 CSR.  A step is one complete
+time-to-ψ solve (all Power-ψ passes, the fused axpy and gap reductions, and
+the final ψ pass; with a warm start also the network's inference) on the
+operator already resident in HBM; the one-time operator build is timed
 separately.
 
 value = edges traversed per second over the whole solve (Σ passes × M / t),
-in GTEPS; ms_per_step = time-to-ψ.  The headline mode is the faster of FP64
-(factored operator) and MIXED (FP32 corrections + FP64 residual); both are
-reported with the plain FP64 weighted-CSR iteration as the comparator.
+in GTEPS; ms_per_step = time-to-ψ.  The headline mode is the fastest of FP64
+(factored operator), MIXED (FP32 corrections + FP64 residual) and the
+learned warm start ahead of the faster of those two; all are reported with
+the plain FP64 weighted-CSR iteration as the comparator.
+
+Other workloads (--workload): cl_10m (N=1e7, 2e8 edges), cl_40m (N=4e7,
+1.4e9 edges, hub rows up to 3e6), cl_4m_k64 (64 activity scenarios on one
+N=4e6, 8e7-edge graph, batched), graphs256 (256 graphs with N in [1e3, 1e5]
+in one batched solve).
 
 Prints one JSON line.  ``--gpus N`` with N > 1 exits: this build runs on one
 GPU.
@@ -29,8 +36,22 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "GTEPS per iteration + time-to-ψ at tol 1e-8 (1 MI355X), vs plain FP64"
-WORKLOAD = "cl_1m"
+DEFAULT_WORKLOAD = "cl_1m"
+SINGLE = ("cl_1m", "cl_10m", "cl_40m")
 PEAK_HBM_GBS = 8000.0
+WEIGHTS = os.path.join(ROOT, "paper_2206_09960_amd", "weights", "warmstart_cl.npy")
+DESCRIPTIONS = {
+    "cl_1m": "directed Chung-Lu, N=1,000,000, mean degree 20, exponent 2.2, "
+             "lambda,mu ~ LogNormal(0,1.5), tol 1e-8 (L1 step), int32 CSR",
+    "cl_10m": "directed Chung-Lu, N=10,000,000, mean degree 20, exponent 2.2, "
+              "lambda,mu ~ LogNormal(0,1.5), tol 1e-8 (L1 step), int32 CSR",
+    "cl_40m": "directed Chung-Lu, N=40,000,000, mean degree 35, exponent 2.1, max followers "
+              "3,000,000, lambda,mu ~ LogNormal(0,2), tol 1e-8 (L1 step), int32 CSR",
+    "cl_4m_k64": "64 activity scenarios (LogNormal(0,1.5), independent streams) on one directed "
+                 "Chung-Lu graph, N=4,000,000, mean degree 20, exponent 2.2, tol 1e-8 per scenario",
+    "graphs256": "256 directed Chung-Lu graphs, N_g uniform in [1,000, 100,000], mean degree 15, "
+                 "exponent 2.2, LogNormal(0,1.5), tol 1e-8 per graph, one block-diagonal operator",
+}
 
 
 def algorithmic_bytes(kind: str, n: int, m: int, segs: int = 1) -> int:
@@ -59,10 +80,10 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(kernel_kind: str, n_launch: int):
+def traffic_from_profile(kernel_kind: str, workload: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
     None when it is missing or was taken on other kernel sources."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{kernel_kind}_{WORKLOAD}.json")
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel_kind}_{workload}.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -74,7 +95,6 @@ def traffic_from_profile(kernel_kind: str, n_launch: int):
 
 def cpu_baseline(g, tol):
     """The oracle (scipy CSR, one thread) on the same workload: full solve."""
-    import numpy as np  # noqa: F401
     import oracle
     t0 = time.perf_counter()
     A, B, c, d = oracle.operator(g.n, g.follower, g.leader, g.lam, g.mu)
@@ -90,97 +110,117 @@ def cpu_baseline(g, tol):
                 seconds=t_solve), r["psi"]
 
 
-def main() -> int:
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run a 1 GiB device copy (reference kernel for HBM counters)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
-              "sharding of this path is a design, not a build", file=sys.stderr)
-        return 2
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
+
+def timed(fn, k, w):
+    import torch
+    for _ in range(w):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = None
+    for _ in range(k):
+        out = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / k, out
+
+
+def generate(name):
+    import synth
+    t0 = time.perf_counter()
+    big = name in ("cl_10m", "cl_40m", "cl_4m_k64", "graphs256")
+    g = synth.workload(name, device="cuda" if big else None)
+    log(f"generated {name}: N={g.n} M_raw={g.m_raw} in {time.perf_counter() - t0:.1f}s")
+    return g
+
+
+def run_single(args, name):
     import numpy as np
     import torch
 
     import synth
     from paper_2206_09960_amd import api
 
-    if not torch.cuda.is_available():
-        print("bench.py needs a GPU", file=sys.stderr)
-        return 2
-    torch.cuda.set_device(0)
-    wl = synth.WORKLOADS[WORKLOAD]
-    tol = wl["tol"]
-    t0 = time.perf_counter()
-    g = synth.workload(WORKLOAD)
-    t_gen = time.perf_counter() - t0
-    print(f"[bench] generated N={g.n} M_raw={g.m_raw} in {t_gen:.1f}s", file=sys.stderr, flush=True)
-
-    # operator build (one-time; inputs copied to HBM first so the build is device-only)
-    f_dev = torch.from_numpy(g.follower).cuda()
-    l_dev = torch.from_numpy(g.leader).cuda()
+    tol = synth.WORKLOADS[name]["tol"]
+    g = generate(name)
+    f_dev = torch.as_tensor(g.follower).cuda()
+    l_dev = torch.as_tensor(g.leader).cuda()
     lam_dev = torch.from_numpy(g.lam).cuda()
     mu_dev = torch.from_numpy(g.mu).cuda()
     torch.cuda.synchronize()
     builds = []
-    for _ in range(2):
+    for _ in range(2 if name == "cl_1m" else 1):
         t0 = time.perf_counter()
         op = api.Operator(g.n, f_dev, l_dev, lam_dev, mu_dev, flags=api.PSI_WEIGHTED_FP64)
         torch.cuda.synchronize()
         builds.append((time.perf_counter() - t0) * 1e3)
+    del f_dev, l_dev
     st = op.stats()
     m = st["n_edges"]
-    print(f"[bench] operator built: M={m} max_row={st['max_followers']} in {builds[-1]:.1f} ms",
-          file=sys.stderr, flush=True)
-
-    def timed_solves(precision, k, w):
-        for _ in range(w):
-            op.solve(tol=tol, precision=precision)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        infos = []
-        psi = None
-        for _ in range(k):
-            psi, info = op.solve(tol=tol, precision=precision)
-            infos.append(info)
-        torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) * 1e3 / k
-        return ms, infos[-1], psi
+    log(f"operator built: M={m} max_row={st['max_followers']} in {builds[-1]:.1f} ms")
 
     modes = {}
     for prec in ("fp64_weighted", "fp64", "mixed"):
-        ms, info, psi = timed_solves(prec, args.steps, args.warmup)
+        ms, (psi, info) = timed(lambda: op.solve(tol=tol, precision=prec), args.steps, args.warmup)
         assert info["status"] == 0, (prec, info)
         modes[prec] = dict(ms=ms, info=info, psi=psi.cpu().numpy())
-        print(f"[bench] {prec}: {ms:.3f} ms/solve, {info['spmv_passes']} passes "
-              f"({info['iterations']} FP64, {info['fp32_passes']} FP32)", file=sys.stderr, flush=True)
+        log(f"{prec}: {ms:.3f} ms/solve, {info['spmv_passes']} passes "
+            f"({info['iterations']} FP64, {info['fp32_passes']} FP32)")
+    base = min(("fp64", "mixed"), key=lambda p: modes[p]["ms"])
 
-    head = min(("fp64", "mixed"), key=lambda p: modes[p]["ms"])
+    warm = None
+    if not args.no_warm and os.path.exists(WEIGHTS):
+        model = api.Model(np.load(WEIGHTS))
+        s0 = model.warmstart(op)
+        ms_inf, _ = timed(lambda: model.warmstart(op, s0_out=s0), args.steps, args.warmup)
+        wname = f"{base}_warm"
+        ms, (psi, info) = timed(lambda: op.solve(tol=tol, precision=base,
+                                                 s0=model.warmstart(op, s0_out=s0)),
+                                args.steps, args.warmup)
+        assert info["status"] == 0, (wname, info)
+        modes[wname] = dict(ms=ms, info=info, psi=psi.cpu().numpy())
+        with open(os.path.splitext(WEIGHTS)[0] + ".json") as fh:
+            rec = json.load(fh)
+        warm = dict(mode=wname, ms_inference=round(ms_inf, 4), ms_total=round(ms, 4),
+                    iterations_warm=info["iterations"],
+                    iterations_cold=modes[base]["info"]["iterations"], used_s0=info["used_s0"],
+                    model=f"3-layer message passing, hidden 64, trained on {rec['n_graphs']} "
+                          f"Chung-Lu graphs of N in [{min(rec['n_users'])}, "
+                          f"{max(rec['n_users'])}] ({rec['steps']} Adam steps)")
+        log(f"{wname}: {ms:.3f} ms/solve incl. {ms_inf:.3f} ms inference, "
+            f"{info['iterations']} iterations (cold {warm['iterations_cold']})")
+
+    head = min((p for p in modes if p != "fp64_weighted"), key=lambda p: modes[p]["ms"])
+    head_prec = head.replace("_warm", "")
     # the timed region of the reported value: K solves of the headline mode
-    ms, info, psi = timed_solves(head, args.steps, args.warmup)
+    if head.endswith("_warm"):
+        ms, (psi, info) = timed(lambda: op.solve(tol=tol, precision=head_prec,
+                                                 s0=model.warmstart(op, s0_out=s0)),
+                                args.steps, args.warmup)
+    else:
+        ms, (psi, info) = timed(lambda: op.solve(tol=tol, precision=head_prec), args.steps,
+                                args.warmup)
     passes = info["spmv_passes"]
     value = passes * m / (ms * 1e-3) / 1e9
 
     # dominant kernel: per-launch time with HIP events on the stream it runs on
     segs = info["col_segments"]
     pass_ms = {k: op.pass_time(k, reps=50) for k in ("step64", "step64_w", "step32", "final64")}
+    mixed = head_prec == "mixed"
     if segs > 1:
-        kind = "part32" if head == "mixed" else "part64"
-        kernel = f"k_pass_seg<{info['tile_items'] // 256}, {5 if head == 'mixed' else 4}>"
+        kind = "part32" if mixed else "part64"
+        kernel = f"k_pass_seg<{info['tile_items'] // 256}, {5 if mixed else 4}>"
         pass_ms[kind] = op.pass_time(kind, reps=50, col_segments=segs)
     else:
-        kind = "step32" if head == "mixed" else "step64"
-        kernel = f"k_pass<{info['tile_items'] // 256}, {3 if head == 'mixed' else 0}>"
+        kind = "step32" if mixed else "step64"
+        kernel = f"k_pass<{info['tile_items'] // 256}, {3 if mixed else 0}>"
     alg = algorithmic_bytes(kind, g.n, m, segs)
     achieved = alg / (pass_ms[kind] * 1e-3) / 1e9
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=PEAK_HBM_GBS, unit="GB/s",
                     frac=round(achieved / PEAK_HBM_GBS, 4),
-                    traffic=traffic_from_profile(kind, 1),
+                    traffic=traffic_from_profile(kind, name),
                     kernel=kernel, algorithmic_bytes=alg, col_segments=segs,
                     mean_launch_us=round(pass_ms[kind] * 1e3, 2),
                     gathers_per_s=round(m / (pass_ms[kind] * 1e-3) / 1e9, 1),
@@ -197,10 +237,9 @@ def main() -> int:
         "metric": METRIC, "value": round(value, 2), "unit": "GTEPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if head == "fp64" else "f32+f64",
+        "dtype": "f32+f64" if mixed else "f64",
         "data": "synthetic",
-        "config": {"workload": "directed Chung-Lu, N=1,000,000, mean degree 20, exponent 2.2, "
-                               "lambda,mu ~ LogNormal(0,1.5), tol 1e-8 (L1 step), int32 CSR",
+        "config": {"workload": DESCRIPTIONS[name], "name": name,
                    "n_users": g.n, "n_edges": m, "max_followers": st["max_followers"],
                    "tol": tol, "headline_mode": head, "col_segments": info["col_segments"],
                    "tile_items": info["tile_items"], "parallelism": "single GPU"},
@@ -210,9 +249,12 @@ def main() -> int:
         "gteps_per_pass": {k: round(m / (v * 1e-3) / 1e9, 1) for k, v in pass_ms.items()},
         "pass_us": {k: round(v * 1e3, 2) for k, v in pass_ms.items()},
         "roofline": roofline,
+        "warm_start": warm,
         "build_ms": round(builds[-1], 2),
+        "mixed_vs_fp64_rel_l1": float(np.abs(modes["mixed"]["psi"] - modes["fp64"]["psi"]).sum()
+                                      / np.abs(modes["fp64"]["psi"]).sum()),
     }
-    if not args.no_cpu_baseline:
+    if name == DEFAULT_WORKLOAD and not args.no_cpu_baseline:
         cb, psi_ref = cpu_baseline(g, tol)
         out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
         out["cpu_baseline"]["value"] = round(cb["value"], 4)
@@ -220,8 +262,108 @@ def main() -> int:
             p: float(np.abs(v["psi"] - psi_ref).sum() / np.abs(psi_ref).sum())
             for p, v in modes.items()}
         out["oracle_seconds"] = round(cb["seconds"], 2)
+    else:
+        out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)
     return 0
+
+
+def run_batched(args, name):
+    """cl_4m_k64 (scenario mode) or graphs256 (graph mode)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2206_09960_amd import api
+
+    tol = synth.WORKLOADS[name]["tol"]
+    g = generate(name)
+    f_dev = torch.as_tensor(g.follower).cuda()
+    l_dev = torch.as_tensor(g.leader).cuda()
+    t0 = time.perf_counter()
+    op = api.Operator(g.n, f_dev, l_dev, torch.from_numpy(g.lam).cuda(),
+                      torch.from_numpy(g.mu).cuda(), node_offsets=g.node_offsets)
+    torch.cuda.synchronize()
+    build_ms = (time.perf_counter() - t0) * 1e3
+    del f_dev, l_dev
+    st = op.stats()
+    m = st["n_edges"]
+    log(f"operator built: M={m} in {build_ms:.1f} ms")
+    if name == "cl_4m_k64":
+        k = synth.WORKLOADS[name]["scenarios"]
+        seed, sigma = synth.WORKLOADS[name]["seed"], synth.WORKLOADS[name]["sigma"]
+        lam = np.empty((g.n, k))
+        mu = np.empty((g.n, k))
+        for s in range(k):
+            lam[:, s], mu[:, s] = synth.activity(g.n, seed, "lognormal", sigma, scenario=s)
+        lam_t, mu_t = torch.from_numpy(lam).cuda(), torch.from_numpy(mu).cuda()
+        del lam, mu
+        ms, (psi, infos) = timed(lambda: op.solve_batched(lam_t, mu_t, tol=tol), args.steps,
+                                 args.warmup)
+        units = k
+        unit_name = "scenarios"
+        # one scenario alone, for the speedup of batching
+        single = api.Operator(g.n, g.follower, g.leader, lam_t[:, 0].contiguous(),
+                              mu_t[:, 0].contiguous())
+        ms1, (_, info1) = timed(lambda: single.solve(tol=tol), max(1, args.steps // 2), 1)
+        ref = dict(single_solve_ms=round(ms1, 3), single_passes=info1["spmv_passes"],
+                   sequential_estimate_ms=round(ms1 * k, 2))
+    else:
+        ms, (psi, infos) = timed(lambda: op.solve_graphs(tol=tol), args.steps, args.warmup)
+        units = len(infos)
+        unit_name = "graphs"
+        ref = None
+    assert all(i["status"] == 0 for i in infos), [i["status_name"] for i in infos][:5]
+    passes = [i["spmv_passes"] for i in infos]
+    if name == "cl_4m_k64":
+        edge_visits = sum(p * m for p in passes)
+    else:
+        # a graph stops at its own tolerance and is frozen: its edges count for its own passes
+        rp = op.views()["row_ptr"].cpu().numpy().astype(np.int64)
+        m_g = rp[g.node_offsets[1:]] - rp[g.node_offsets[:-1]]
+        edge_visits = int(np.dot(m_g, np.asarray(passes, dtype=np.int64)))
+    out = {
+        "metric": f"batched time-to-psi at tol 1e-8 over {units} {unit_name} (1 MI355X)",
+        "value": round(edge_visits / (ms * 1e-3) / 1e9, 2),
+        "unit": "GTEPS (edges x passes summed over the batch)",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": DESCRIPTIONS[name], "name": name, "n_users": g.n, "n_edges": m,
+                   "units": units, "tol": tol, "parallelism": "single GPU"},
+        "passes": {"min": int(min(passes)), "max": int(max(passes)),
+                   "mean": round(float(np.mean(passes)), 2)},
+        "single_scenario_reference": ref,
+        "roofline": None, "cpu_baseline": None, "build_ms": round(build_ms, 2),
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD,
+                    choices=list(SINGLE) + ["cl_4m_k64", "graphs256"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-warm", action="store_true", help="skip the learned warm start mode")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a 1 GiB device copy (reference kernel for HBM counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "sharding of this path is a design, not a build", file=sys.stderr)
+        return 2
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 2
+    torch.cuda.set_device(0)
+    if args.workload in SINGLE:
+        return run_single(args, args.workload)
+    return run_batched(args, args.workload)
 
 
 if __name__ == "__main__":

@@ -161,11 +161,13 @@ def chung_lu(n: int, mean_degree: float, gamma: float, seed: int,
 
 
 def multi_graph(n_graphs: int, n_lo: int, n_hi: int, mean_degree: float, gamma: float,
-                seed: int, sigma: float = 1.0) -> Graph:
+                seed: int, sigma: float = 1.0, device=None) -> Graph:
     """Independent Chung–Lu graphs stacked block-diagonally.
 
     Graph g has N_g uniform in {n_lo..n_hi} (stream 5 of ``seed``) and is drawn
     with seed 1000*seed + g; its users are numbered from node_offsets[g].
+    With ``device`` the edges are drawn there by the torch twin (same values)
+    and returned as torch int32 tensors.
     """
     u = rng.uniform01(seed, STREAM_SIZES, n_graphs)
     sizes = n_lo + np.minimum((u * (n_hi - n_lo + 1)).astype(np.int64), n_hi - n_lo)
@@ -173,12 +175,24 @@ def multi_graph(n_graphs: int, n_lo: int, n_hi: int, mean_degree: float, gamma: 
     offsets[1:] = np.cumsum(sizes)
     fs, ls, lams, mus = [], [], [], []
     for g in range(n_graphs):
-        sub = chung_lu(int(sizes[g]), mean_degree, gamma, 1000 * seed + g, sigma)
-        fs.append(sub.follower + np.int32(offsets[g]))
-        ls.append(sub.leader + np.int32(offsets[g]))
-        lams.append(sub.lam)
-        mus.append(sub.mu)
-    return Graph(int(offsets[-1]), np.concatenate(fs), np.concatenate(ls),
+        n_g, seed_g = int(sizes[g]), 1000 * seed + g
+        if device is None:
+            sub = chung_lu(n_g, mean_degree, gamma, seed_g, sigma)
+            f, l, lam, mu = sub.follower, sub.leader, sub.lam, sub.mu
+        else:
+            f, l = chung_lu_edges_torch(n_g, int(round(n_g * mean_degree)), gamma, seed_g,
+                                        device=device)
+            lam, mu = activity(n_g, seed_g, "lognormal", sigma)
+        fs.append(f + int(offsets[g]))
+        ls.append(l + int(offsets[g]))
+        lams.append(lam)
+        mus.append(mu)
+    if device is None:
+        follower, leader = np.concatenate(fs), np.concatenate(ls)
+    else:
+        import torch
+        follower, leader = torch.cat(fs), torch.cat(ls)
+    return Graph(int(offsets[-1]), follower, leader,
                  np.concatenate(lams), np.concatenate(mus), node_offsets=offsets,
                  meta=dict(kind="multi_graph", n_graphs=n_graphs, n_lo=n_lo, n_hi=n_hi,
                            mean_degree=mean_degree, gamma=gamma, seed=seed, sigma=sigma))
@@ -252,6 +266,8 @@ WORKLOADS = {
     "cl_4m_k64": dict(n=4_000_000, mean_degree=20, gamma=2.2, seed=4, sigma=1.5,
                       scenarios=64, tol=1e-8),
     "cl_10m": dict(n=10_000_000, mean_degree=20, gamma=2.2, seed=5, sigma=1.5, tol=1e-8),
+    "graphs256": dict(kind="multi", n_graphs=256, n_lo=1_000, n_hi=100_000, mean_degree=15,
+                      gamma=2.2, seed=4, sigma=1.5, tol=1e-8),
 }
 
 
@@ -262,6 +278,8 @@ def workload(name: str, device=None) -> Graph:
     w = dict(WORKLOADS[name])
     w.pop("tol", None)
     w.pop("scenarios", None)
+    if w.pop("kind", None) == "multi":
+        return multi_graph(**w, device=device)
     if device is None:
         return chung_lu(**w)
     n, seed, sigma = w["n"], w["seed"], w.get("sigma", 1.0)
