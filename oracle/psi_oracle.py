@@ -26,6 +26,12 @@ Functions and the passages they follow:
 * ``fixed_point_residual``, ``b_norm``, ``kappa`` — the L1 fixed-point residual
                           of eq. (power_psi) and the norms used by the bound of
                           eq. (psi_diff).
+* ``sampled_rows``      — for a few users i only, (Aᵀs)_i and (Bᵀs)_i from the
+                          definitions of A and B (Sec. II) over the raw edge
+                          list, without building the whole operator: the
+                          residual of eq. (power_psi) and the last line of
+                          Algorithm 2 at those users, for graphs too large for
+                          the full oracle.
 
 Readings where the paper is silent:
 
@@ -46,7 +52,7 @@ import scipy.sparse as sp
 __all__ = [
     "clean_edges", "operator", "psi_by_definition", "power_nf", "psi_closed_form",
     "power_psi", "pagerank_power", "transition_matrix", "fixed_point_residual",
-    "b_norm", "kappa", "rel_l1", "rel_l2",
+    "b_norm", "kappa", "rel_l1", "rel_l2", "sampled_rows",
 ]
 
 
@@ -246,3 +252,51 @@ def rel_l2(ref, x):
     """The paper's error measure, eq. (error)."""
     ref = np.asarray(ref, dtype=np.float64)
     return float(np.linalg.norm(np.asarray(x) - ref) / np.linalg.norm(ref))
+
+
+def sampled_rows(n, follower, leader, lam, mu, s, rows, chunk=1 << 26):
+    """Residual of eq. (power_psi) and ψ (last line of Algorithm 2) at `rows`.
+
+    For each sampled user i: F(i) = the distinct followers j ≠ i of i, and for
+    each such j, den_j = Σ over the distinct leaders ℓ ≠ j of j of (λ_ℓ + μ_ℓ)
+    (the definitions of A and B, Sec. II).  With y_i = Σ_{j∈F(i)} s_j / den_j:
+        residual_i = c_i + μ_i y_i − s_i,   psi_i = (d_i + λ_i y_i) / N.
+    The edge arrays are read in chunks, twice; memory stays proportional to
+    the sampled rows and their followers.  Returns (residual, psi) in the
+    order of `rows`.
+    """
+    rows = np.asarray(rows, dtype=np.int64)
+    lam = np.asarray(lam, dtype=np.float64)
+    mu = np.asarray(mu, dtype=np.float64)
+    s = np.asarray(s, dtype=np.float64)
+    m = len(follower)
+    want = np.zeros(n, dtype=bool)
+    want[rows] = True
+    pairs = []  # (leader i, follower j) with i sampled
+    for a in range(0, m, chunk):
+        f = np.asarray(follower[a:a + chunk], dtype=np.int64)
+        l = np.asarray(leader[a:a + chunk], dtype=np.int64)
+        sel = want[l] & (f != l)
+        pairs.append(l[sel] * n + f[sel])
+    key = np.unique(np.concatenate(pairs))
+    row_of, fol = key // n, key % n
+    need = np.zeros(n, dtype=bool)
+    need[fol] = True
+    lead = []  # (follower j, leader ℓ) for the followers j of sampled rows
+    for a in range(0, m, chunk):
+        f = np.asarray(follower[a:a + chunk], dtype=np.int64)
+        l = np.asarray(leader[a:a + chunk], dtype=np.int64)
+        sel = need[f] & (f != l)
+        lead.append(f[sel] * n + l[sel])
+    key2 = np.unique(np.concatenate(lead))
+    j2, l2 = key2 // n, key2 % n
+    den = np.zeros(n)
+    np.add.at(den, j2, lam[l2] + mu[l2])
+    y = np.zeros(n)
+    np.add.at(y, row_of, s[fol] / den[fol])
+    c = mu / (lam + mu)
+    d = lam / (lam + mu)
+    yr = y[rows]
+    residual = c[rows] + mu[rows] * yr - s[rows]
+    psi = (d[rows] + lam[rows] * yr) / n
+    return residual, psi

@@ -256,3 +256,15 @@ def test_pins_reject_planted_mistakes(mutant):
     except RuntimeError:
         return  # diverged: caught
     assert oracle.rel_l1(psi_def, bad) > 1e-6
+
+
+def test_sampled_rows_agree_with_the_full_operator():
+    """The one-by-one row evaluation (raw edges, duplicates and self-loops
+    present) against the full operator's Aᵀs + c − s and (Bᵀs + d)/N."""
+    g = synth.random_small(300, 0.03, 21, extra_self_loops=20, extra_duplicates=40)
+    A, B, c, d = oracle.operator(g.n, g.follower, g.leader, g.lam, g.mu)
+    s = oracle.power_psi(A, B, c, d, 1e-6)["s"] * 1.01  # any vector, not the fixed point
+    rows = np.array([0, 5, 17, 123, 299])
+    res, psi = oracle.sampled_rows(g.n, g.follower, g.leader, g.lam, g.mu, s, rows, chunk=97)
+    np.testing.assert_allclose(res, (A.T @ s + c - s)[rows], rtol=1e-13, atol=1e-15)
+    np.testing.assert_allclose(psi, ((B.T @ s + d) / g.n)[rows], rtol=1e-13, atol=0)
