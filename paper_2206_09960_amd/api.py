@@ -83,10 +83,10 @@ class Operator:
             flags |= PSI_INPUT_HOST
             n_edges = int(f.shape[0])
         else:
-            f = follower.to(self.device, torch.int32).contiguous()
-            l = leader.to(self.device, torch.int32).contiguous()
-            la = lam.to(self.device, torch.float64).contiguous()
-            m_ = mu.to(self.device, torch.float64).contiguous()
+            f = torch.as_tensor(follower).to(self.device, torch.int32).contiguous()
+            l = torch.as_tensor(leader).to(self.device, torch.int32).contiguous()
+            la = torch.as_tensor(lam).to(self.device, torch.float64).contiguous()
+            m_ = torch.as_tensor(mu).to(self.device, torch.float64).contiguous()
             keep = [f, l, la, m_]
             ptrs = [a.data_ptr() for a in keep]
             n_edges = int(f.shape[0])

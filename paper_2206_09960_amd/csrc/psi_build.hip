@@ -210,7 +210,7 @@ __global__ void k_pack_keys(const int32_t* follower, const int32_t* leader, int6
     // graph of a user: last g with graph_off[g] <= id
     int lo = 0, hi = n_graphs;
     while (hi - lo > 1) {
-      int mid = (lo + hi) >> 1;
+      int mid = lo + ((hi - lo) >> 1);
       if (graph_off[mid] <= f) lo = mid; else hi = mid;
     }
     if (l < graph_off[lo] || l >= graph_off[lo + 1]) atomicOr(&ctrl->err_flags, kErrCrossGraph);
@@ -322,7 +322,7 @@ __global__ void k_graph_rows(const int64_t* graph_off, int n_graphs, int64_t n, 
   if (i >= n) return;
   int lo = 0, hi = n_graphs;
   while (hi - lo > 1) {
-    int mid = (lo + hi) >> 1;
+    int mid = lo + ((hi - lo) >> 1);
     if (graph_off[mid] <= i) lo = mid; else hi = mid;
   }
   graph_of[i] = lo;
@@ -374,7 +374,7 @@ __global__ void k_seg_count(const int* row_ptr, const int* col, int64_t n, int S
     const int64_t bound = (s + 1) * seg;
     int lo = lo_e, hi = end;
     while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
+      const int mid = lo + ((hi - lo) >> 1);  // lo + hi can exceed 2^31 past edge 2^30
       if (col[mid] < bound) lo = mid + 1; else hi = mid;
     }
     seg_row_ptr[int64_t(s) * (n + 1) + i] = lo - lo_e;
