@@ -80,15 +80,17 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(kernel_kind: str, workload: str):
+def traffic_from_profile(kernel_kind: str, workload: str, kernel: str, alg: int):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None when it is missing or was taken on other kernel sources."""
+    None when it is missing, was taken on other kernel sources, or on another
+    launch configuration (kernel instance or column segments)."""
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel_kind}_{workload}.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
-    if rec.get("source_hash") != source_hash():
+    if (rec.get("source_hash") != source_hash() or rec.get("kernel") != kernel
+            or rec.get("algorithmic_bytes") != alg):
         return None
     return rec.get("hbm_bytes_per_launch")
 
@@ -161,6 +163,11 @@ def run_single(args, name):
     m = st["n_edges"]
     log(f"operator built: M={m} max_row={st['max_followers']} in {builds[-1]:.1f} ms")
 
+    t0 = time.perf_counter()
+    tuned = {p: op.autotune(p) for p in ("fp64_weighted", "fp64", "mixed")}
+    tune_ms = (time.perf_counter() - t0) * 1e3
+    log(f"autotuned in {tune_ms:.0f} ms: {tuned}")
+
     modes = {}
     for prec in ("fp64_weighted", "fp64", "mixed"):
         ms, (psi, info) = timed(lambda: op.solve(tol=tol, precision=prec), args.steps, args.warmup)
@@ -207,12 +214,16 @@ def run_single(args, name):
 
     # dominant kernel: per-launch time with HIP events on the stream it runs on
     segs = info["col_segments"]
-    pass_ms = {k: op.pass_time(k, reps=50) for k in ("step64", "step64_w", "step32", "final64")}
+    launch = {"step64": tuned["fp64"], "step64_w": tuned["fp64_weighted"], "step32": tuned["mixed"],
+              "final64": tuned["fp64"]}
+    pass_ms = {k: op.pass_time(k, reps=50, tile_items=v["tile_items"],
+                               col_segments=v["col_segments"]) for k, v in launch.items()}
     mixed = head_prec == "mixed"
     if segs > 1:
         kind = "part32" if mixed else "part64"
         kernel = f"k_pass_seg<{info['tile_items'] // 256}, {5 if mixed else 4}>"
-        pass_ms[kind] = op.pass_time(kind, reps=50, col_segments=segs)
+        pass_ms[kind] = op.pass_time(kind, reps=50, tile_items=info["tile_items"],
+                                     col_segments=segs)
     else:
         kind = "step32" if mixed else "step64"
         kernel = f"k_pass<{info['tile_items'] // 256}, {3 if mixed else 0}>"
@@ -220,7 +231,7 @@ def run_single(args, name):
     achieved = alg / (pass_ms[kind] * 1e-3) / 1e9
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=PEAK_HBM_GBS, unit="GB/s",
                     frac=round(achieved / PEAK_HBM_GBS, 4),
-                    traffic=traffic_from_profile(kind, name),
+                    traffic=traffic_from_profile(kind, name, kernel, alg),
                     kernel=kernel, algorithmic_bytes=alg, col_segments=segs,
                     mean_launch_us=round(pass_ms[kind] * 1e3, 2),
                     gathers_per_s=round(m / (pass_ms[kind] * 1e-3) / 1e9, 1),
@@ -251,6 +262,8 @@ def run_single(args, name):
         "roofline": roofline,
         "warm_start": warm,
         "build_ms": round(builds[-1], 2),
+        "autotune_ms": round(tune_ms, 1),
+        "autotuned": {p: {k: v[k] for k in ("tile_items", "col_segments")} for p, v in tuned.items()},
         "mixed_vs_fp64_rel_l1": float(np.abs(modes["mixed"]["psi"] - modes["fp64"]["psi"]).sum()
                                       / np.abs(modes["fp64"]["psi"]).sum()),
     }

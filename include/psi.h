@@ -234,6 +234,20 @@ psi_status psi_solve_batched(psi_operator* op, const psi_params* prm, int32_t n_
 psi_status psi_pass_time(psi_operator* op, int32_t pass_kind, int32_t reps, int32_t tile_items,
                          int32_t col_segments, double* mean_ms, void* stream);
 
+/* Schedule autotuner.  Times `reps` back-to-back launches of the pass that
+ * dominates a solve in `precision` (the FP64 step, the FP64 weighted step, or
+ * the FP32 correction step for PSI_PREC_MIXED / PSI_PREC_FP32; with the
+ * combine kernel when col_segments > 1) for every supported tile_items
+ * (1024, 1536, 2048, 3072, 4096) and col_segments (1, 2, 4, 8; 1 only for
+ * the weighted form), with hipEvents on `stream`, and keeps the fastest in
+ * the operator: later psi_solve calls in that precision whose psi_params
+ * leave tile_items / col_segments at 0 use it.  reps = 0 picks about 20 ms
+ * of passes per candidate (at least 3).  Writes the choice and its mean pass
+ * time (ms) to the host pointers, each of which may be NULL.  Overwrites the
+ * operator's solve state; blocks.  Single-graph operators only. */
+psi_status psi_autotune(psi_operator* op, int32_t precision, int32_t reps, int32_t* tile_items,
+                        int32_t* col_segments, double* best_ms, void* stream);
+
 /* ---- learned warm start ---------------------------------------------------
  * An extension of the method (the paper has none): a small message-passing
  * network predicts the fixed point s of eq. (power_psi) so that Algorithm 2

@@ -211,6 +211,16 @@ class Operator:
                                            ctypes.byref(out), _stream_handle(stream)))
         return out.value
 
+    def autotune(self, precision: str = "fp64", reps: int = 0, stream=None) -> dict:
+        """psi_autotune: the fastest tile_items / col_segments for `precision`,
+        kept in the operator for later solves."""
+        t, sg, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        with torch.cuda.device(self.device):
+            _check(self._lib.psi_autotune(self._h, prec, reps, ctypes.byref(t), ctypes.byref(sg),
+                                          ctypes.byref(ms), _stream_handle(stream)))
+        return dict(tile_items=t.value, col_segments=sg.value, pass_ms=ms.value)
+
     def _params(self, tol, tol_mode, max_iter, precision, check_every, tile_items=0,
                 col_segments=0, inner_tol=0.0, no_fallback=False):
         p = _ffi.Params()

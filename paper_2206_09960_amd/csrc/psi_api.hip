@@ -223,6 +223,22 @@ psi_status psi_pass_time(psi_operator* op, int32_t pass_kind, int32_t reps, int3
   PSI_GUARD_END
 }
 
+psi_status psi_autotune(psi_operator* op, int32_t precision, int32_t reps, int32_t* tile_items,
+                        int32_t* col_segments, double* best_ms, void* stream) {
+  PSI_GUARD_BEGIN
+  PSI_REQUIRE(op, "op must not be NULL");
+  psi_status st = psi::check_device(op);
+  if (st != PSI_OK) return st;
+  int t = 0, sg = 0;
+  st = psi::autotune(op, precision, reps, &t, &sg, best_ms, static_cast<hipStream_t>(stream));
+  if (st == PSI_OK) {
+    if (tile_items) *tile_items = t;
+    if (col_segments) *col_segments = sg;
+  }
+  return st;
+  PSI_GUARD_END
+}
+
 psi_status psi_batched_workspace_size(const psi_operator* op, int32_t n_scenarios, size_t* bytes) {
   PSI_GUARD_BEGIN
   PSI_REQUIRE(op, "op must not be NULL");

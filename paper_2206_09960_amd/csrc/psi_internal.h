@@ -203,6 +203,9 @@ struct psi_operator {
   // (0: CSR(Aᵀ), 1: CSR(A)); built on first use
   psi::MpHubs mp_hubs[2]{};
   int64_t mp_max_hubs = 0, mp_max_chunks = 0;
+  // schedule chosen by psi_autotune, per precision (0 = not tuned)
+  int tuned_tile[4]{};
+  int tuned_S[4]{};
   int* seg_col = nullptr;       // [m]
   int* seg_row_ptr = nullptr;   // [8 * (n + 1)]
   int* seg_tile_row = nullptr;  // [max_seg_tiles + 8]
@@ -237,6 +240,8 @@ PassArgs base_args(psi_operator* op);
 
 psi_status solve(psi_operator* op, const psi_params* prm, const double* s0, double* psi_out,
                  double* s_out, psi_info* info, hipStream_t stream);
+psi_status autotune(psi_operator* op, int precision, int reps, int* tile_items, int* col_segments,
+                    double* best_ms, hipStream_t stream);
 
 // Exclusive prefix sum of n uint32 (in may equal out); tile_sums needs
 // scan_tile_count(n) + 1 entries; *total receives the sum.

@@ -220,12 +220,14 @@ psi_status solve(psi_operator* op, const psi_params* prm, const double* s0, doub
   PSI_REQUIRE(prm->precision != PSI_PREC_FP64_WEIGHTED || op->val64,
               "PSI_PREC_FP64_WEIGHTED needs an operator built with PSI_WEIGHTED_FP64");
   PSI_REQUIRE(op->n_graphs == 1, "multi-graph operators are solved by psi_solve_batched");
-  const int tile = prm->tile_items ? prm->tile_items : (op->sched_items ? op->sched_items
-                                                                        : kDefaultTileItems);
+  const int tuned_tile = op->tuned_tile[prm->precision];
+  const int tile = prm->tile_items ? prm->tile_items
+                 : tuned_tile      ? tuned_tile
+                 : (op->sched_items ? op->sched_items : kDefaultTileItems);
   PSI_REQUIRE(tile_items_supported(tile), "unsupported tile_items");
   int S = 1;
-  psi_status s = resolve_segments(op, prm->col_segments,
-                                  prm->precision == PSI_PREC_FP64 ? 8 : 4, &S);
+  const int want_S = prm->col_segments ? prm->col_segments : op->tuned_S[prm->precision];
+  psi_status s = resolve_segments(op, want_S, prm->precision == PSI_PREC_FP64 ? 8 : 4, &S);
   if (s != PSI_OK) return s;
   if (prm->precision == PSI_PREC_FP64_WEIGHTED) S = 1;
   s = prepare(op, tile, S, st);
@@ -588,6 +590,51 @@ psi_status pass_time(psi_operator* op, int kind, int reps, int tile_items, int c
   float ms = 0.f;
   PSI_HIP_CHECK(hipEventElapsedTime(&ms, tm.a, tm.b));
   *mean_ms = static_cast<double>(ms) / reps;
+  return PSI_OK;
+}
+
+// Times the loop kernels of a solve in `precision` for every supported tile
+// size and column-segment count and keeps the fastest in the operator.
+psi_status autotune(psi_operator* op, int precision, int reps, int* tile_items, int* col_segments,
+                    double* best_ms, hipStream_t st) {
+  PSI_REQUIRE(precision >= PSI_PREC_FP64 && precision <= PSI_PREC_FP32, "unknown precision");
+  PSI_REQUIRE(reps >= 0, "reps must be >= 0");
+  PSI_REQUIRE(op->n_graphs == 1, "psi_autotune needs a single-graph operator");
+  PSI_REQUIRE(precision != PSI_PREC_FP64_WEIGHTED || op->val64,
+              "PSI_PREC_FP64_WEIGHTED needs an operator built with PSI_WEIGHTED_FP64");
+  const int kind = precision == PSI_PREC_FP64 ? PSI_PASS_STEP64
+                 : precision == PSI_PREC_FP64_WEIGHTED ? PSI_PASS_STEP64_W : PSI_PASS_STEP32;
+  static const int kTiles[] = {1024, 1536, 2048, 3072, 4096};
+  static const int kSegs[] = {1, 2, 4, 8};
+  const int n_segs = precision == PSI_PREC_FP64_WEIGHTED ? 1 : 4;
+  double best = 0.0;
+  int best_tile = 0, best_S = 0;
+  for (int si = 0; si < n_segs; ++si) {
+    for (int tile : kTiles) {
+      int r = reps;
+      if (r == 0) {  // about 20 ms of passes per candidate, at least 3
+        double one = 0.0;
+        psi_status s = pass_time(op, kind, 1, tile, kSegs[si], &one, st);
+        if (s != PSI_OK) return s;
+        r = static_cast<int>(std::min(50.0, std::max(3.0, 20.0 / std::max(one, 1e-3))));
+      }
+      double ms = 0.0;
+      psi_status s = pass_time(op, kind, r, tile, kSegs[si], &ms, st);
+      if (s != PSI_OK) return s;
+      if (best_tile == 0 || ms < best) {
+        best = ms;
+        best_tile = tile;
+        best_S = kSegs[si];
+      }
+    }
+  }
+  psi_status s = prepare(op, best_tile, best_S, st);
+  if (s != PSI_OK) return s;
+  op->tuned_tile[precision] = best_tile;
+  op->tuned_S[precision] = best_S;
+  if (tile_items) *tile_items = best_tile;
+  if (col_segments) *col_segments = best_S;
+  if (best_ms) *best_ms = best;
   return PSI_OK;
 }
 

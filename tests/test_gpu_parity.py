@@ -357,3 +357,24 @@ def test_full_size_1m(gpu_lib, prec):
     assert oracle.rel_l2(r["psi"], psi.cpu().numpy()) <= 1e-9
     s_np = s.cpu().numpy()
     assert oracle.fixed_point_residual(A, c, s_np) <= 1.5e-8 + 1e-15 * np.abs(s_np).sum()
+
+
+def test_autotune_picks_a_supported_schedule_that_solves_use(gpu_lib):
+    api = gpu_lib
+    g = synth.chung_lu(200_000, 12, 2.2, 31, sigma=1.5)
+    op = api.Operator(g.n, g.follower, g.leader, g.lam, g.mu)
+    ref, _ = op.solve(tol=1e-10)
+    ref = ref.cpu().numpy()
+    for prec, bar in (("fp64", 1e-12), ("mixed", 1e-9)):
+        t = op.autotune(prec, reps=3)
+        assert t["tile_items"] in (1024, 1536, 2048, 3072, 4096)
+        assert t["col_segments"] in (1, 2, 4, 8) and t["pass_ms"] > 0
+        psi, info = op.solve(tol=1e-10, precision=prec)
+        assert info["status"] == 0
+        assert (info["tile_items"], info["col_segments"]) == (t["tile_items"], t["col_segments"])
+        assert oracle.rel_l1(ref, psi.cpu().numpy()) <= bar
+        # an explicit choice still wins over the tuned one
+        _, info2 = op.solve(tol=1e-10, precision=prec, tile_items=1024, col_segments=1)
+        assert (info2["tile_items"], info2["col_segments"]) == (1024, 1)
+    with pytest.raises(api.PsiError, match="WEIGHTED"):
+        op.autotune("fp64_weighted")
