@@ -378,3 +378,37 @@ def test_autotune_picks_a_supported_schedule_that_solves_use(gpu_lib):
         assert (info2["tile_items"], info2["col_segments"]) == (1024, 1)
     with pytest.raises(api.PsiError, match="WEIGHTED"):
         op.autotune("fp64_weighted")
+
+
+@pytest.mark.parametrize("power_method", [True, False])
+def test_pagerank_mode_matches_the_power_method(gpu_lib, power_method):
+    """Homogeneous activity on the same kernels gives the PageRank vector; with
+    the power method's start and π-tolerance, its iterates and count too."""
+    api = gpu_lib
+    g = synth.chung_lu(30_000, 8, 2.2, 57)  # some users follow nobody: leaking PageRank
+    W = oracle.transition_matrix(g.n, g.follower, g.leader)
+    pi_ref, t_ref = oracle.pagerank_power(W, 0.85, 1e-10)
+    pi, info, _ = api.pagerank(g.n, g.follower, g.leader, alpha=0.85, tol=1e-10,
+                               power_method=power_method)
+    assert info["status"] == 0
+    pi = pi.cpu().numpy()
+    if power_method:
+        # the same stopping step; ψ from s_t is π_{t+1}, one step past the oracle's π_t
+        assert abs(info["iterations"] - t_ref) <= 1
+        assert oracle.rel_l1(pi_ref, pi) <= 1e-9
+    else:
+        exact, _ = oracle.pagerank_power(W, 0.85, 1e-15)
+        assert oracle.rel_l1(exact, pi) <= 1e-8
+
+
+def test_exact_fixed_point_equals_the_closed_form(gpu_lib):
+    """The reference ψ of the experiments (FP64 map run until its step stops
+    shrinking) against eq. (ultimsol) solved exactly by the oracle."""
+    api = gpu_lib
+    g = synth.chung_lu(12_591, 49_743 / 12_591, 2.2, 21, activity_kind="uniform")
+    op = api.Operator(g.n, g.follower, g.leader, g.lam, g.mu)
+    psi, info = op.solve(tol=1e-300, max_iter=2000)
+    assert info["status_name"] in ("PSI_OK", "PSI_ESTAGNATED")
+    A, B, c, d = oracle.operator(g.n, g.follower, g.leader, g.lam, g.mu)
+    exact, _ = oracle.psi_closed_form(A, B, c, d)
+    assert oracle.rel_l1(exact, psi.cpu().numpy()) <= 1e-12
