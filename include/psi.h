@@ -219,6 +219,25 @@ psi_status psi_solve_batched(psi_operator* op, const psi_params* prm, int32_t n_
                              psi_info* infos, void* workspace, size_t workspace_bytes,
                              void* stream);
 
+/* Per-origin newsfeed shares: Algorithm 1 (Power-NF, eq. fixpt_algo) for K
+ * chosen origins at once.  For origin i, p_i solves p_i = A p_i + b_i
+ * (eq. newsfeed: p_i^(j) is the share of user j's newsfeed that comes from
+ * i), iterated from p_i = b_i until ‖p_i(t) − p_i(t−1)‖₁ ≤ tol (the
+ * p-tolerance of Sec. V); each origin stops, and is frozen, on its own.
+ * From it, q_i = C p_i + d_i (eq. wall: q_i^(j) = c_j p_i^(j), plus d_i at
+ * j = i) is the share of j's wall from i, and ψ_i = (1/N) Σ_j q_i^(j)
+ * (eq. psiscore).  This is the by-product Power-ψ skips: the influence of
+ * one user on each other user.
+ * origins: host int32 [K], user ids (repeats allowed).  p_out: device FP64
+ * user-major [N × K] (p_out[j*K + k] = p_{origins[k]}^(j)), may be NULL.
+ * psi_out: device FP64 [K], ψ of each origin.  infos: host [K], may be
+ * NULL.  Only PSI_PREC_FP64 and PSI_TOL_ABS_L1; single-graph operators.
+ * workspace: device, at least psi_batched_workspace_size bytes.  Blocks. */
+psi_status psi_solve_origins(psi_operator* op, const psi_params* prm, int32_t n_origins,
+                             const int32_t* origins, double* p_out, double* psi_out,
+                             psi_info* infos, void* workspace, size_t workspace_bytes,
+                             void* stream);
+
 /* ---- operator pass kinds (for timing and tuning) -------------------------- */
 #define PSI_PASS_STEP64     0  /* FP64 factored step: s' = c + μ⊙Σ_{j∈F(i)} s_j/den_j */
 #define PSI_PASS_STEP64_W   1  /* FP64 weighted step: s' = c + Σ_j a_ji s_j           */

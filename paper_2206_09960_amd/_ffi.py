@@ -72,6 +72,8 @@ SIGNATURES = [
     ("psi_batched_workspace_size", i32, [vp, i32, ctypes.POINTER(sz)]),
     ("psi_solve_batched", i32, [vp, ctypes.POINTER(Params), i32, vp, vp, vp, ctypes.POINTER(Info),
                                 vp, sz, vp]),
+    ("psi_solve_origins", i32, [vp, ctypes.POINTER(Params), i32, vp, vp, vp,
+                                ctypes.POINTER(Info), vp, sz, vp]),
     ("psi_autotune", i32, [vp, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
                            ctypes.POINTER(f64), vp]),
     ("psi_mpnn_param_count", i64, []),

@@ -266,6 +266,37 @@ class Operator:
             out.append(d)
         return psi, out
 
+    def solve_origins(self, origins, tol: float = 1e-8, max_iter: int = 10000,
+                      want_p: bool = True, check_every: int = 0, stream=None,
+                      raise_on_status: bool = False):
+        """psi_solve_origins: Power-NF for the given origin users at once.
+        Returns (psi [K], p [N × K] or None, list of K info dicts); column k
+        of p is the newsfeed share vector p_i of origin i = origins[k]."""
+        org = np.ascontiguousarray(origins, dtype=np.int32)
+        if org.ndim != 1 or org.size == 0:
+            raise ValueError("origins must be a non-empty 1-D array of user ids")
+        k = int(org.size)
+        p = self._params(tol, "abs_l1", max_iter, "fp64", check_every)
+        nbytes = ctypes.c_size_t()
+        _check(self._lib.psi_batched_workspace_size(self._h, k, ctypes.byref(nbytes)))
+        ws = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+        psi = torch.empty(k, dtype=torch.float64, device=self.device)
+        pm = torch.empty((self.n, k), dtype=torch.float64, device=self.device) if want_p else None
+        infos = (_ffi.Info * k)()
+        with torch.cuda.device(self.device):
+            st = self._lib.psi_solve_origins(self._h, ctypes.byref(p), k, org.ctypes.data,
+                                             _ptr(pm), psi.data_ptr(), infos, ws.data_ptr(),
+                                             nbytes.value, _stream_handle(stream))
+        if st in (_ffi.PSI_EINVAL, _ffi.PSI_EDEVICE, _ffi.PSI_ENOSPACE) or (
+                raise_on_status and st != _ffi.PSI_OK):
+            _check(st)
+        out = []
+        for i in range(k):
+            d = _ffi.struct_dict(infos[i])
+            d["status_name"] = _ffi.STATUS_NAMES.get(d["status"], str(d["status"]))
+            out.append(d)
+        return psi, pm, out
+
     def solve_graphs(self, tol: float = 1e-8, max_iter: int = 10000, check_every: int = 0,
                      tile_items: int = 0, stream=None, raise_on_status: bool = False):
         """psi_solve_batched, graph mode: every graph of a block-diagonal

@@ -269,6 +269,19 @@ psi_status psi_solve_batched(psi_operator* op, const psi_params* prm, int32_t n_
   PSI_GUARD_END
 }
 
+psi_status psi_solve_origins(psi_operator* op, const psi_params* prm, int32_t n_origins,
+                             const int32_t* origins, double* p_out, double* psi_out,
+                             psi_info* infos, void* workspace, size_t workspace_bytes,
+                             void* stream) {
+  PSI_GUARD_BEGIN
+  PSI_REQUIRE(op, "op must not be NULL");
+  psi_status st = psi::check_device(op);
+  if (st != PSI_OK) return st;
+  return psi::solve_origins(op, prm, n_origins, origins, p_out, psi_out, infos, workspace,
+                            workspace_bytes, static_cast<hipStream_t>(stream));
+  PSI_GUARD_END
+}
+
 /* ---- learned warm start ---------------------------------------------------- */
 int64_t psi_mpnn_param_count(void) { return psi::mpnn_param_count(); }
 

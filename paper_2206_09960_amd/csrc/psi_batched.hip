@@ -9,6 +9,14 @@
 // each has its own gap, stops at its own iteration (and is frozen afterwards)
 // and gets ψ^k from its own final s^k.
 //
+// Origin mode: the newsfeed shares p_i of chosen origins i (Algorithm 1,
+// Power-NF, eq. fixpt_algo) for K origins at once: one lane per origin, the
+// same row tiles and hub chunks over CSR(A) (rows = followers j, columns =
+// leaders ℓ), P ← A P + B from P = B, with (A P + B)_jk = (1/den_j)
+// Σ_{ℓ∈L(j)} (μ_ℓ P_ℓk + λ_ℓ [ℓ = i_k]); each origin stops on its own
+// p-tolerance ‖p_i(t) − p_i(t−1)‖₁ ≤ ε and ψ_i = (Σ_j c_j p_i^(j) + d_i) / N
+// (eqs. wall and psiscore).
+//
 // Work split.  Rows (leaders) with at most kHubEdges followers are packed
 // whole into wave tiles of about kWaveItems merge-path items; a wave sums its
 // rows edge by edge in order.  Longer rows are cut into chunks of kChunkEdges
@@ -58,6 +66,7 @@ struct BatchWs {
   double* gap_blk;     // [kMaxGrid × Kc]
   double* gap_hub;     // [max_hubs × Kc]
   BatchCtrl* ctrl;
+  int* origin;         // [kMaxK] origins of the current tile (origin mode)
   BatchCtrl* host_ctrl;  // not in the workspace
   int64_t n_wtiles, max_hubs, max_chunks;
 };
@@ -94,6 +103,7 @@ size_t batch_layout(int64_t n, int64_t m, BatchWs* w, char* base) {
   t.gap_blk = (double*)take(8 * size_t(kMaxGrid) * kMaxK);
   t.gap_hub = (double*)take(8 * size_t(max_hubs) * kMaxK);
   t.ctrl = (BatchCtrl*)take(sizeof(BatchCtrl));
+  t.origin = (int*)take(4 * size_t(kMaxK));
   t.n_wtiles = n_wtiles;
   t.max_hubs = max_hubs;
   t.max_chunks = max_chunks;
@@ -224,15 +234,30 @@ struct BArgs {
   double* gap_blk;
   double* gap_hub;
   BatchCtrl* ctrl;
+  const int* origin;   // origin mode: the origin of each lane
 };
+
+// Kernel modes: a scenario step, the scenarios' final ψ pass, an origin step.
+enum : int { kScen = 0, kScenFinal = 1, kOrig = 2 };
 
 // Epilogue of row r for scenario k; a scenario that has met its tolerance
 // keeps its iterate (and contributes no gap).
-template <bool FINAL>
+template <int BM>
 __device__ inline void bepi(const BArgs& a, int r, int k, double y, bool frozen, double& gap) {
   const int64_t t = int64_t(r) * a.Kc + k;
-  if constexpr (FINAL) {
+  if constexpr (BM == kScenFinal) {
     a.psi[int64_t(r) * a.psi_ld + a.psi_col0 + k] = (a.lam[t] * y + a.d[t]) * a.inv_n;
+  } else if constexpr (BM == kOrig) {  // shared μ, 1/den of the operator, indexed by user
+    const double po = a.s_old[t];
+    if (frozen) {
+      a.s_new[t] = po;
+      a.z_new[t] = a.z[t];
+      return;
+    }
+    const double pn = a.invden[r] * y;
+    a.s_new[t] = pn;
+    a.z_new[t] = a.mu[r] * pn;
+    gap += fabs(pn - po);
   } else {
     const double so = a.s_old[t];
     if (frozen) {
@@ -248,14 +273,25 @@ __device__ inline void bepi(const BArgs& a, int r, int k, double y, bool frozen,
 }
 
 // Rows of at most kHubEdges followers: waves walk the wave tiles grid-stride.
-template <bool FINAL>
+// Origin mode adds λ_ℓ on the edge whose column is the lane's origin.
+template <int BM>
+__device__ inline double edge_term(const BArgs& a, int j, int k, int org, double lo) {
+  const double v = a.z[int64_t(j) * a.Kc + k];
+  if constexpr (BM == kOrig) return j == org ? v + lo : v;
+  return v;
+}
+
+template <int BM>
 __global__ __launch_bounds__(kBlock) void k_spmm_rows(BArgs a) {
+  constexpr bool FINAL = BM == kScenFinal;
   __shared__ double red[kBlock / 64][kMaxK];
   if (!FINAL && a.ctrl->c.done) return;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int k = lane < a.Kc ? lane : a.Kc - 1;  // idle lanes shadow the last scenario
   const bool frozen = !FINAL && a.ctrl->kdone[k];
+  const int org = BM == kOrig ? a.origin[k] : -1;
+  const double lo = BM == kOrig ? a.lam[org] : 0.0;
   double gap = 0.0;
   const int stride = gridDim.x * (kBlock / 64);
   for (int tile = blockIdx.x * (kBlock / 64) + wave; tile < a.n_wtiles; tile += stride) {
@@ -271,12 +307,12 @@ __global__ __launch_bounds__(kBlock) void k_spmm_rows(BArgs a) {
 #pragma unroll
         for (int u = 0; u < 8; ++u) j[u] = a.col[e + u];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = a.z[int64_t(j[u]) * a.Kc + k];
+        for (int u = 0; u < 8; ++u) v[u] = edge_term<BM>(a, j[u], k, org, lo);
 #pragma unroll
         for (int u = 0; u < 8; ++u) y += v[u];
       }
-      for (; e < e1; ++e) y += a.z[int64_t(a.col[e]) * a.Kc + k];
-      if (lane < a.Kc) bepi<FINAL>(a, r, k, y, frozen, gap);
+      for (; e < e1; ++e) y += edge_term<BM>(a, a.col[e], k, org, lo);
+      if (lane < a.Kc) bepi<BM>(a, r, k, y, frozen, gap);
     }
   }
   if constexpr (!FINAL) {
@@ -290,12 +326,15 @@ __global__ __launch_bounds__(kBlock) void k_spmm_rows(BArgs a) {
 
 // One workgroup per hub chunk: wave w sums edges e0+w, e0+w+4, ...; the four
 // wave sums are added in wave order.
-__global__ __launch_bounds__(kBlock) void k_spmm_hub_chunk(BArgs a, int final_pass) {
+template <int BM>
+__global__ __launch_bounds__(kBlock) void k_spmm_hub_chunk(BArgs a) {
   __shared__ double red[kBlock / 64][kMaxK];
-  if (!final_pass && a.ctrl->c.done) return;
+  if (BM != kScenFinal && a.ctrl->c.done) return;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int k = lane < a.Kc ? lane : a.Kc - 1;
+  const int org = BM == kOrig ? a.origin[k] : -1;
+  const double lo = BM == kOrig ? a.lam[org] : 0.0;
   const int ch = blockIdx.x;
   const int r = a.chunk_row[ch];
   const int e0 = a.chunk_e0[ch];
@@ -308,11 +347,11 @@ __global__ __launch_bounds__(kBlock) void k_spmm_hub_chunk(BArgs a, int final_pa
 #pragma unroll
     for (int u = 0; u < 8; ++u) j[u] = a.col[e + 4 * u];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = a.z[int64_t(j[u]) * a.Kc + k];
+    for (int u = 0; u < 8; ++u) v[u] = edge_term<BM>(a, j[u], k, org, lo);
 #pragma unroll
     for (int u = 0; u < 8; ++u) y += v[u];
   }
-  for (; e < e1; e += 4) y += a.z[int64_t(a.col[e]) * a.Kc + k];
+  for (; e < e1; e += 4) y += edge_term<BM>(a, a.col[e], k, org, lo);
   red[wave][lane] = y;
   __syncthreads();
   if (wave == 0 && lane < a.Kc)
@@ -321,8 +360,9 @@ __global__ __launch_bounds__(kBlock) void k_spmm_hub_chunk(BArgs a, int final_pa
 }
 
 // One wave per hub row: its chunks in chunk order, then the epilogue.
-template <bool FINAL>
+template <int BM>
 __global__ __launch_bounds__(64) void k_spmm_hub_finish(BArgs a) {
+  constexpr bool FINAL = BM == kScenFinal;
   if (!FINAL && a.ctrl->c.done) return;
   const int lane = threadIdx.x;
   const int h = blockIdx.x;
@@ -333,7 +373,7 @@ __global__ __launch_bounds__(64) void k_spmm_hub_finish(BArgs a) {
   for (int ch = a.hub_chunk0[h]; ch < a.hub_chunk0[h + 1]; ++ch)
     y += a.chunk_part[int64_t(ch) * a.Kc + lane];
   double gap = 0.0;
-  bepi<FINAL>(a, r, lane, y, frozen, gap);
+  bepi<BM>(a, r, lane, y, frozen, gap);
   if constexpr (!FINAL) a.gap_hub[int64_t(h) * a.Kc + lane] = gap;
 }
 
@@ -391,6 +431,47 @@ __global__ void k_bctrl_init(BatchCtrl* bc, double tol, int max_iter) {
     bc->kstatus[k] = PSI_OK;
     bc->kgap[k] = 0.0;
   }
+}
+
+// ---------------------------------------------------------------- origins
+__global__ void k_bzero(double* a, double* b, int64_t total) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= total) return;
+  a[t] = 0.0;
+  b[t] = 0.0;
+}
+
+// Σ_j c_j P[j, k] per workgroup in row order (optionally copying P to the
+// caller's [N × K] output at column k0 + k).
+__global__ __launch_bounds__(kBlock) void k_origin_colsum(const double* P, const double* c,
+                                                         int64_t n, int Kc, int K, int k0,
+                                                         double* p_out, double* part) {
+  __shared__ double red[kBlock / 64][kMaxK];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int k = lane < Kc ? lane : Kc - 1;
+  double acc = 0.0;
+  for (int64_t r = int64_t(blockIdx.x) * (kBlock / 64) + wave; r < n;
+       r += int64_t(gridDim.x) * (kBlock / 64)) {
+    const double v = P[r * Kc + k];
+    acc += c[r] * v;
+    if (p_out && lane < Kc) p_out[r * K + k0 + lane] = v;
+  }
+  red[wave][lane] = acc;
+  __syncthreads();
+  if (wave == 0 && lane < Kc)
+    part[int64_t(blockIdx.x) * Kc + lane] =
+        ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+}
+
+// ψ_i = (Σ_j c_j p_i^(j) + d_i) / N, the workgroup partials in order.
+__global__ void k_origin_psi(const double* part, int n_blk, int Kc, const int* origin,
+                             const double* d, double inv_n, double* psi_out) {
+  const int k = threadIdx.x;
+  if (k >= Kc) return;
+  double sum = 0.0;
+  for (int b = 0; b < n_blk; ++b) sum += part[int64_t(b) * Kc + k];
+  psi_out[k] = (sum + d[origin[k]]) * inv_n;
 }
 
 // ---------------------------------------------------------------- graphs
@@ -477,6 +558,54 @@ int rows_grid() {
 
 }  // namespace
 
+// Row tiles, hub rows and hub chunks of the pattern `row_ptr` (n rows, m
+// entries); blocks to learn the hub and chunk counts.
+struct BSched {
+  uint32_t n_hubs = 0, n_chunks = 0;
+  int64_t n_wtiles = 0;
+};
+
+static psi_status batch_schedule(const int* row_ptr, int64_t n, int64_t m, BatchWs& w,
+                                 hipStream_t st, BSched* out) {
+  // hub rows and their chunks (depend only on the pattern)
+  hipLaunchKernelGGL(k_hub_flags, dim3(grid_for(n + 1)), dim3(kBlock), 0, st, row_ptr, n,
+                     w.flags);
+  psi_status s = scan_exclusive_u32(w.flags, w.flags, n + 1, w.scan_tmp,
+                                    w.scan_tmp + scan_tile_count(n + 1) + 4, st);
+  if (s != PSI_OK) return s;
+  uint32_t n_hubs = 0;
+  PSI_HIP_CHECK(hipMemcpyAsync(&n_hubs, w.flags + n, 4, hipMemcpyDeviceToHost, st));
+  PSI_HIP_CHECK(hipStreamSynchronize(st));
+  uint32_t* nchunks = reinterpret_cast<uint32_t*>(w.chunk_row);  // counts, then scanned in place
+  uint32_t n_chunks = 0;
+  if (n_hubs > 0) {
+    hipLaunchKernelGGL(k_hub_list, dim3(grid_for(n)), dim3(kBlock), 0, st, row_ptr, n,
+                       w.flags, w.hub_rows, nchunks);
+    uint32_t* chunk0 = reinterpret_cast<uint32_t*>(w.chunk_e0);
+    PSI_HIP_CHECK(hipMemsetAsync(nchunks + n_hubs, 0, 4, st));
+    s = scan_exclusive_u32(nchunks, chunk0, int64_t(n_hubs) + 1, w.scan_tmp,
+                           w.scan_tmp + scan_tile_count(n + 1) + 4, st);
+    if (s != PSI_OK) return s;
+    PSI_HIP_CHECK(hipMemcpyAsync(&n_chunks, chunk0 + n_hubs, 4, hipMemcpyDeviceToHost, st));
+    PSI_HIP_CHECK(hipStreamSynchronize(st));
+    // hub_chunk0 = chunk0 (copied), then the chunk table overwrites the scratch
+    PSI_HIP_CHECK(hipMemcpyAsync(w.hub_chunk0, chunk0, 4 * size_t(n_hubs + 1),
+                                 hipMemcpyDeviceToDevice, st));
+    hipLaunchKernelGGL(k_chunk_table, dim3(grid_for(n_hubs)), dim3(kBlock), 0, st, row_ptr,
+                       w.hub_rows, reinterpret_cast<const uint32_t*>(w.hub_chunk0), int(n_hubs),
+                       w.chunk_row, w.chunk_e0, w.hub_chunk0);
+  }
+  const int64_t n_wtiles = std::max<int64_t>((n + m + kWaveItems - 1) / kWaveItems, 1);
+  hipLaunchKernelGGL(k_row_tiles, dim3(grid_for(n_wtiles + 1)), dim3(kBlock), 0, st, row_ptr,
+                     n, m, int64_t(kWaveItems), n_wtiles, w.row_tiles);
+  PSI_HIP_CHECK(hipGetLastError());
+
+  out->n_hubs = n_hubs;
+  out->n_chunks = n_chunks;
+  out->n_wtiles = n_wtiles;
+  return PSI_OK;
+}
+
 psi_status batched_workspace_size(const psi_operator* op, int n_scenarios, size_t* bytes) {
   PSI_REQUIRE(bytes, "bytes must not be NULL");
   PSI_REQUIRE(n_scenarios >= 1, "n_scenarios must be >= 1");
@@ -504,38 +633,11 @@ psi_status solve_batched(psi_operator* op, const psi_params* prm, int K, const d
   batch_layout(op->n, op->m, &w, static_cast<char*>(ws));
   const int64_t n = op->n, m = op->m;
 
-  // hub rows and their chunks (depend only on the pattern)
-  hipLaunchKernelGGL(k_hub_flags, dim3(grid_for(n + 1)), dim3(kBlock), 0, st, op->row_ptr, n,
-                     w.flags);
-  psi_status s = scan_exclusive_u32(w.flags, w.flags, n + 1, w.scan_tmp,
-                                    w.scan_tmp + scan_tile_count(n + 1) + 4, st);
+  BSched sc{};
+  psi_status s = batch_schedule(op->row_ptr, n, m, w, st, &sc);
   if (s != PSI_OK) return s;
-  uint32_t n_hubs = 0;
-  PSI_HIP_CHECK(hipMemcpyAsync(&n_hubs, w.flags + n, 4, hipMemcpyDeviceToHost, st));
-  PSI_HIP_CHECK(hipStreamSynchronize(st));
-  uint32_t* nchunks = reinterpret_cast<uint32_t*>(w.chunk_row);  // counts, then scanned in place
-  uint32_t n_chunks = 0;
-  if (n_hubs > 0) {
-    hipLaunchKernelGGL(k_hub_list, dim3(grid_for(n)), dim3(kBlock), 0, st, op->row_ptr, n,
-                       w.flags, w.hub_rows, nchunks);
-    uint32_t* chunk0 = reinterpret_cast<uint32_t*>(w.chunk_e0);
-    PSI_HIP_CHECK(hipMemsetAsync(nchunks + n_hubs, 0, 4, st));
-    s = scan_exclusive_u32(nchunks, chunk0, int64_t(n_hubs) + 1, w.scan_tmp,
-                           w.scan_tmp + scan_tile_count(n + 1) + 4, st);
-    if (s != PSI_OK) return s;
-    PSI_HIP_CHECK(hipMemcpyAsync(&n_chunks, chunk0 + n_hubs, 4, hipMemcpyDeviceToHost, st));
-    PSI_HIP_CHECK(hipStreamSynchronize(st));
-    // hub_chunk0 = chunk0 (copied), then the chunk table overwrites the scratch
-    PSI_HIP_CHECK(hipMemcpyAsync(w.hub_chunk0, chunk0, 4 * size_t(n_hubs + 1),
-                                 hipMemcpyDeviceToDevice, st));
-    hipLaunchKernelGGL(k_chunk_table, dim3(grid_for(n_hubs)), dim3(kBlock), 0, st, op->row_ptr,
-                       w.hub_rows, reinterpret_cast<const uint32_t*>(w.hub_chunk0), int(n_hubs),
-                       w.chunk_row, w.chunk_e0, w.hub_chunk0);
-  }
-  const int64_t n_wtiles = std::max<int64_t>((n + m + kWaveItems - 1) / kWaveItems, 1);
-  hipLaunchKernelGGL(k_row_tiles, dim3(grid_for(n_wtiles + 1)), dim3(kBlock), 0, st, op->row_ptr,
-                     n, m, int64_t(kWaveItems), n_wtiles, w.row_tiles);
-  PSI_HIP_CHECK(hipGetLastError());
+  const uint32_t n_hubs = sc.n_hubs, n_chunks = sc.n_chunks;
+  const int64_t n_wtiles = sc.n_wtiles;
 
   struct Pinned {
     BatchCtrl* p = nullptr;
@@ -597,13 +699,16 @@ psi_status solve_batched(psi_operator* op, const psi_params* prm, int K, const d
         a.psi = psi_out;
         a.psi_ld = K;
         a.psi_col0 = k0;
-        hipLaunchKernelGGL(k_spmm_rows<true>, dim3(grid), dim3(kBlock), 0, st, a);
-        if (n_chunks) hipLaunchKernelGGL(k_spmm_hub_chunk, dim3(n_chunks), dim3(kBlock), 0, st, a, 1);
-        if (n_hubs) hipLaunchKernelGGL(k_spmm_hub_finish<true>, dim3(n_hubs), dim3(64), 0, st, a);
+        hipLaunchKernelGGL(k_spmm_rows<kScenFinal>, dim3(grid), dim3(kBlock), 0, st, a);
+        if (n_chunks)
+          hipLaunchKernelGGL(k_spmm_hub_chunk<kScenFinal>, dim3(n_chunks), dim3(kBlock), 0, st, a);
+        if (n_hubs)
+          hipLaunchKernelGGL(k_spmm_hub_finish<kScenFinal>, dim3(n_hubs), dim3(64), 0, st, a);
       } else {
-        hipLaunchKernelGGL(k_spmm_rows<false>, dim3(grid), dim3(kBlock), 0, st, a);
-        if (n_chunks) hipLaunchKernelGGL(k_spmm_hub_chunk, dim3(n_chunks), dim3(kBlock), 0, st, a, 0);
-        if (n_hubs) hipLaunchKernelGGL(k_spmm_hub_finish<false>, dim3(n_hubs), dim3(64), 0, st, a);
+        hipLaunchKernelGGL(k_spmm_rows<kScen>, dim3(grid), dim3(kBlock), 0, st, a);
+        if (n_chunks)
+          hipLaunchKernelGGL(k_spmm_hub_chunk<kScen>, dim3(n_chunks), dim3(kBlock), 0, st, a);
+        if (n_hubs) hipLaunchKernelGGL(k_spmm_hub_finish<kScen>, dim3(n_hubs), dim3(64), 0, st, a);
         hipLaunchKernelGGL(k_batch_gap, dim3(1), dim3(1024), 0, st, a, grid);
       }
       PSI_HIP_CHECK(hipGetLastError());
@@ -756,6 +861,140 @@ psi_status solve_graphs(psi_operator* op, const psi_params* prm, double* psi_out
     }
   }
   if (worst != PSI_OK) set_error("a graph did not converge (see its info)");
+  return static_cast<psi_status>(worst);
+}
+
+psi_status solve_origins(psi_operator* op, const psi_params* prm, int K, const int32_t* origins,
+                         double* p_out, double* psi_out, psi_info* infos, void* ws,
+                         size_t ws_bytes, hipStream_t st) {
+  PSI_REQUIRE(prm && psi_out && ws && origins, "params, origins, psi_out and workspace must not be NULL");
+  PSI_REQUIRE(K >= 1, "n_origins must be >= 1");
+  PSI_REQUIRE(prm->tol > 0.0 && std::isfinite(prm->tol), "tol must be finite and > 0");
+  PSI_REQUIRE(prm->max_iter > 0, "max_iter must be > 0");
+  PSI_REQUIRE(prm->tol_mode == PSI_TOL_ABS_L1, "origin batches use PSI_TOL_ABS_L1 (p-tolerance)");
+  PSI_REQUIRE(prm->precision == PSI_PREC_FP64, "origin batches run in PSI_PREC_FP64");
+  PSI_REQUIRE(op->n_graphs == 1, "origin batches need a single-graph operator");
+  const int64_t n = op->n, m = op->m;
+  for (int k = 0; k < K; ++k)
+    PSI_REQUIRE(origins[k] >= 0 && origins[k] < n, "every origin must be a user id in [0, n)");
+  size_t need = batch_layout(n, m, nullptr, nullptr);
+  if (ws_bytes < need) {
+    set_error("workspace smaller than psi_batched_workspace_size reported");
+    return PSI_ENOSPACE;
+  }
+  BatchWs w{};
+  batch_layout(n, m, &w, static_cast<char*>(ws));
+  BSched sc{};
+  psi_status s = batch_schedule(op->fm_row_ptr, n, m, w, st, &sc);  // CSR(A): rows = followers
+  if (s != PSI_OK) return s;
+  struct Pinned {
+    BatchCtrl* p = nullptr;
+    ~Pinned() {
+      if (p) (void)hipHostFree(p);
+    }
+  } pinned;
+  PSI_HIP_CHECK(hipHostMalloc(reinterpret_cast<void**>(&pinned.p), sizeof(BatchCtrl),
+                              hipHostMallocDefault));
+  BatchCtrl* h = pinned.p;
+  const int grid = std::min(rows_grid(), static_cast<int>(sc.n_wtiles));
+  const int cgrid = static_cast<int>(std::min<int64_t>(kMaxGrid, (n + 3) / 4));
+  hipEvent_t ev0, ev1;
+  PSI_HIP_CHECK(hipEventCreate(&ev0));
+  PSI_HIP_CHECK(hipEventCreate(&ev1));
+  PSI_HIP_CHECK(hipEventRecord(ev0, st));
+  int worst = PSI_OK;
+  for (int k0 = 0; k0 < K; k0 += kMaxK) {
+    const int Kc = std::min(kMaxK, K - k0);
+    const int64_t nk = n * Kc;
+    PSI_HIP_CHECK(hipMemcpyAsync(w.origin, origins + k0, 4 * size_t(Kc), hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_bctrl_init, dim3(1), dim3(1), 0, st, w.ctrl, prm->tol, prm->max_iter);
+    hipLaunchKernelGGL(k_bzero, dim3(grid_for(nk)), dim3(kBlock), 0, st, w.s_a, w.z_a, nk);
+    BArgs base{};
+    base.row_ptr = op->fm_row_ptr;
+    base.col = op->fm_col;
+    base.n_rows = static_cast<int>(n);
+    base.Kc = Kc;
+    base.row_tiles = w.row_tiles;
+    base.n_wtiles = static_cast<int>(sc.n_wtiles);
+    base.hub_rows = w.hub_rows;
+    base.hub_chunk0 = w.hub_chunk0;
+    base.n_hubs = static_cast<int>(sc.n_hubs);
+    base.chunk_row = w.chunk_row;
+    base.chunk_e0 = w.chunk_e0;
+    base.n_chunks = static_cast<int>(sc.n_chunks);
+    base.mu = op->mu;
+    base.invden = op->invden;
+    base.lam = op->lam;
+    base.chunk_part = w.chunk_part;
+    base.gap_blk = w.gap_blk;
+    base.gap_hub = w.gap_hub;
+    base.ctrl = w.ctrl;
+    base.origin = w.origin;
+    // pass i reads buffer set i % 2 and writes the other; pass 0 turns P = 0 into P = B
+    // (Algorithm 1's start) and is not an iteration, so it reports no gap
+    auto pass = [&](int i, bool gap) -> psi_status {
+      BArgs a = base;
+      const bool even = (i & 1) == 0;
+      a.z = even ? w.z_a : w.z_b;
+      a.s_old = even ? w.s_a : w.s_b;
+      a.s_new = even ? w.s_b : w.s_a;
+      a.z_new = even ? w.z_b : w.z_a;
+      hipLaunchKernelGGL(k_spmm_rows<kOrig>, dim3(grid), dim3(kBlock), 0, st, a);
+      if (sc.n_chunks)
+        hipLaunchKernelGGL(k_spmm_hub_chunk<kOrig>, dim3(sc.n_chunks), dim3(kBlock), 0, st, a);
+      if (sc.n_hubs) hipLaunchKernelGGL(k_spmm_hub_finish<kOrig>, dim3(sc.n_hubs), dim3(64), 0, st, a);
+      if (gap) hipLaunchKernelGGL(k_batch_gap, dim3(1), dim3(1024), 0, st, a, grid);
+      PSI_HIP_CHECK(hipGetLastError());
+      return PSI_OK;
+    };
+    s = pass(0, false);
+    if (s != PSI_OK) return s;
+    int enq = 0, chunk = prm->check_every > 0 ? prm->check_every : 8;
+    while (true) {
+      const int cnt = std::min(chunk, prm->max_iter - enq);
+      for (int i = 0; i < cnt; ++i) {
+        s = pass(1 + enq + i, true);
+        if (s != PSI_OK) return s;
+      }
+      enq += cnt;
+      PSI_HIP_CHECK(hipMemcpyAsync(h, w.ctrl, sizeof(BatchCtrl), hipMemcpyDeviceToHost, st));
+      PSI_HIP_CHECK(hipStreamSynchronize(st));
+      if (h->c.done || enq >= prm->max_iter) break;
+      if (prm->check_every == 0) chunk = std::min(2 * chunk, 64);
+    }
+    // passes after the last origin converged exit at once: the result is the
+    // output of pass h->c.iter
+    const double* P = (h->c.iter & 1) == 0 ? w.s_b : w.s_a;
+    hipLaunchKernelGGL(k_origin_colsum, dim3(cgrid), dim3(kBlock), 0, st, P, op->c, n, Kc, K, k0,
+                       p_out, w.gap_blk);
+    hipLaunchKernelGGL(k_origin_psi, dim3(1), dim3(64), 0, st, w.gap_blk, cgrid, Kc, w.origin,
+                       op->d, 1.0 / static_cast<double>(n), psi_out + k0);
+    PSI_HIP_CHECK(hipGetLastError());
+    for (int k = 0; k < Kc; ++k) {
+      int stk = h->kdone[k] ? h->kstatus[k] : PSI_ENOTCONV;
+      if (stk != PSI_OK && worst == PSI_OK) worst = stk;
+      if (infos) {
+        psi_info& inf = infos[k0 + k];
+        inf = psi_info{};
+        inf.status = stk;
+        inf.iterations = h->kiter[k];
+        inf.spmv_passes = h->kiter[k] + 1;
+        inf.final_gap = h->kgap[k];
+        inf.final_l1_step = h->kgap[k];
+        inf.col_segments = 1;
+        inf.tile_items = kWaveItems;
+      }
+    }
+  }
+  PSI_HIP_CHECK(hipEventRecord(ev1, st));
+  PSI_HIP_CHECK(hipEventSynchronize(ev1));
+  float ms = 0.f;
+  PSI_HIP_CHECK(hipEventElapsedTime(&ms, ev0, ev1));
+  (void)hipEventDestroy(ev0);
+  (void)hipEventDestroy(ev1);
+  if (infos)
+    for (int k = 0; k < K; ++k) infos[k].device_ms = ms;
+  if (worst != PSI_OK) set_error("an origin did not converge (see its info)");
   return static_cast<psi_status>(worst);
 }
 

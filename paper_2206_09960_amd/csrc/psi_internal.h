@@ -258,6 +258,9 @@ psi_status solve_graphs(psi_operator* op, const psi_params* prm, double* psi_out
 psi_status solve_batched(psi_operator* op, const psi_params* prm, int n_scenarios,
                          const double* lambda, const double* mu, double* psi_out, psi_info* infos,
                          void* ws, size_t ws_bytes, hipStream_t st);
+psi_status solve_origins(psi_operator* op, const psi_params* prm, int K, const int32_t* origins,
+                         double* p_out, double* psi_out, psi_info* infos, void* ws,
+                         size_t ws_bytes, hipStream_t st);
 
 // learned warm start (psi_mpnn.hip)
 int64_t mpnn_param_count();

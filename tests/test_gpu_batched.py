@@ -137,3 +137,60 @@ def test_graphs_with_an_edgeless_graph(gpu_lib):
     bad_l = np.array([1, 3], dtype=np.int32)
     with pytest.raises(api.PsiError, match="joins two graphs"):
         api.Operator(n, bad_f, bad_l, np.ones(n), np.ones(n), node_offsets=offs)
+
+
+# ---------------------------------------------------------------- origin mode
+def test_origins_match_power_nf_and_power_psi(gpu_lib):
+    """Algorithm 1 (Power-NF) for 70 origins at once (two tiles of lanes)."""
+    api = gpu_lib
+    g = synth.chung_lu(4000, 8, 2.1, 81, sigma=1.5)
+    op = api.Operator(g.n, g.follower, g.leader, g.lam, g.mu)
+    A, B, c, d = oracle.operator(g.n, g.follower, g.leader, g.lam, g.mu)
+    n_followers = np.asarray((B > 0).sum(axis=0)).ravel()  # column i of B: followers of i
+    hub = int(np.argmax(n_followers))
+    lonely = int(np.flatnonzero(n_followers == 0)[0])
+    rng = np.random.default_rng(5)
+    origins = np.concatenate([[hub, lonely, hub], rng.choice(g.n, 67, replace=False)])
+    psi_o, P, infos = op.solve_origins(origins, tol=1e-12)
+    psi_o, P = psi_o.cpu().numpy(), P.cpu().numpy()
+    psi_all = oracle.power_psi(A, B, c, d, 1e-13)["psi"]
+    for k, i in enumerate(origins):
+        b = B[:, i].toarray().ravel()
+        p_ref, t_ref = oracle.power_nf(A, b, 1e-12)
+        assert infos[k]["status"] == 0 and abs(infos[k]["iterations"] - t_ref) <= 1, (k, i)
+        assert np.abs(P[:, k] - p_ref).sum() <= 1e-10 * max(np.abs(p_ref).sum(), 1e-300) + 1e-300
+        psi_ref = (c @ p_ref + d[i]) / g.n  # eqs. wall and psiscore
+        assert abs(psi_o[k] - psi_ref) <= 1e-12 * psi_ref
+        assert abs(psi_o[k] - psi_all[i]) <= 1e-9 * psi_all[i]  # the same ψ_i as Power-ψ
+    assert np.array_equal(P[:, 0], P[:, 2])  # a repeated origin gives the same column
+    assert not P[:, 1].any()                 # nobody follows `lonely`: p = 0, ψ = d/N
+    assert psi_o[1] == d[lonely] / g.n
+
+
+def test_origins_invalid(gpu_lib):
+    api = gpu_lib
+    g = synth.chung_lu(500, 5, 2.2, 82)
+    op = api.Operator(g.n, g.follower, g.leader, g.lam, g.mu)
+    with pytest.raises(api.PsiError, match="origin"):
+        op.solve_origins([0, g.n])
+    with pytest.raises(ValueError):
+        op.solve_origins([])
+
+
+def test_origins_with_a_user_who_follows_everyone(gpu_lib):
+    """One follower with 3000 leaders: a chunked row of CSR(A) in origin mode."""
+    api = gpu_lib
+    n = 3001
+    base = synth.chung_lu(n, 4, 2.2, 83, sigma=1.0)
+    f = np.concatenate([base.follower, np.zeros(n - 1, dtype=np.int32)])
+    l = np.concatenate([base.leader, np.arange(1, n, dtype=np.int32)])
+    op = api.Operator(n, f, l, base.lam, base.mu)
+    A, B, c, d = oracle.operator(n, f, l, base.lam, base.mu)
+    origins = np.array([1, 17, 2500, 0])
+    psi_o, P, infos = op.solve_origins(origins, tol=1e-13)
+    psi_o, P = psi_o.cpu().numpy(), P.cpu().numpy()
+    for k, i in enumerate(origins):
+        p_ref, t_ref = oracle.power_nf(A, B[:, i].toarray().ravel(), 1e-13)
+        assert abs(infos[k]["iterations"] - t_ref) <= 1
+        assert np.abs(P[:, k] - p_ref).sum() <= 1e-10 * max(np.abs(p_ref).sum(), 1e-300) + 1e-300
+        assert abs(psi_o[k] - (c @ p_ref + d[i]) / n) <= 1e-12 * psi_o[k]
