@@ -219,6 +219,25 @@ psi_status psi_solve_batched(psi_operator* op, const psi_params* prm, int32_t n_
                              psi_info* infos, void* workspace, size_t workspace_bytes,
                              void* stream);
 
+/* Anderson-accelerated Power-ψ.  The same fixed point as psi_solve, found
+ * with fewer operator passes: each iteration is one Power-ψ pass
+ * g = Aᵀx + c followed by Anderson mixing over the last `depth` residuals
+ * (Anderson 1965; Walker & Ni 2011): γ = argmin ‖f_k − ΔF γ‖₂ with
+ * f = g − x, x ← g − ΔG γ.  The stopping test is the pass's own gap
+ * ‖g − x‖₁ ≤ tol in prm->tol_mode units, and s = g is returned, so the
+ * result is a Power-ψ step of size at most tol (eq. condition), as in
+ * Algorithm 2; ψ = (Bᵀs + d)/N.  depth in [1, 8]; only PSI_PREC_FP64;
+ * tile_items / col_segments as in psi_solve (autotuned values used).
+ * s0 (device FP64 [N], may be NULL = c) is the start, used as given.
+ * info->iterations counts passes (one per iteration), info->refinements
+ * the window restarts.  workspace: device, at least
+ * psi_anderson_workspace_size bytes (2·depth + 2 FP64 vectors of N plus
+ * 130 KB).  Overwrites the operator's solve state; blocks. */
+psi_status psi_anderson_workspace_size(const psi_operator* op, int32_t depth, size_t* bytes);
+psi_status psi_solve_anderson(psi_operator* op, const psi_params* prm, int32_t depth,
+                              const double* s0, double* psi_out, double* s_out, psi_info* info,
+                              void* workspace, size_t workspace_bytes, void* stream);
+
 /* Per-origin newsfeed shares: Algorithm 1 (Power-NF, eq. fixpt_algo) for K
  * chosen origins at once.  For origin i, p_i solves p_i = A p_i + b_i
  * (eq. newsfeed: p_i^(j) is the share of user j's newsfeed that comes from

@@ -72,6 +72,9 @@ SIGNATURES = [
     ("psi_batched_workspace_size", i32, [vp, i32, ctypes.POINTER(sz)]),
     ("psi_solve_batched", i32, [vp, ctypes.POINTER(Params), i32, vp, vp, vp, ctypes.POINTER(Info),
                                 vp, sz, vp]),
+    ("psi_anderson_workspace_size", i32, [vp, i32, ctypes.POINTER(sz)]),
+    ("psi_solve_anderson", i32, [vp, ctypes.POINTER(Params), i32, vp, vp, vp,
+                                 ctypes.POINTER(Info), vp, sz, vp]),
     ("psi_solve_origins", i32, [vp, ctypes.POINTER(Params), i32, vp, vp, vp,
                                 ctypes.POINTER(Info), vp, sz, vp]),
     ("psi_autotune", i32, [vp, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),

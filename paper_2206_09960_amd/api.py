@@ -266,6 +266,36 @@ class Operator:
             out.append(d)
         return psi, out
 
+    def solve_anderson(self, tol: float = 1e-8, depth: int = 4, tol_mode: str = "abs_l1",
+                       max_iter: int = 10000, s0: torch.Tensor | None = None,
+                       check_every: int = 0, tile_items: int = 0, col_segments: int = 0,
+                       return_s: bool = False, stream=None, raise_on_status: bool = False):
+        """psi_solve_anderson: the same ψ with Anderson-accelerated passes;
+        returns (psi, info) or (psi, s, info)."""
+        p = self._params(tol, tol_mode, max_iter, "fp64", check_every, tile_items, col_segments)
+        nbytes = ctypes.c_size_t()
+        _check(self._lib.psi_anderson_workspace_size(self._h, depth, ctypes.byref(nbytes)))
+        ws = self._accel_ws if getattr(self, "_accel_ws", None) is not None and \
+            self._accel_ws.numel() >= nbytes.value else None
+        if ws is None:
+            ws = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+            self._accel_ws = ws
+        psi = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        s = torch.empty(self.n, dtype=torch.float64, device=self.device) if return_s else None
+        if s0 is not None:
+            s0 = s0.to(self.device, torch.float64).contiguous()
+        info = _ffi.Info()
+        with torch.cuda.device(self.device):
+            st = self._lib.psi_solve_anderson(self._h, ctypes.byref(p), depth, _ptr(s0),
+                                              psi.data_ptr(), _ptr(s), ctypes.byref(info),
+                                              ws.data_ptr(), ws.numel(), _stream_handle(stream))
+        d = _ffi.struct_dict(info)
+        d["status_name"] = _ffi.STATUS_NAMES.get(st, str(st))
+        if st in (_ffi.PSI_EINVAL, _ffi.PSI_EDEVICE, _ffi.PSI_ENOSPACE) or (
+                raise_on_status and st != _ffi.PSI_OK):
+            _check(st)
+        return (psi, s, d) if return_s else (psi, d)
+
     def solve_origins(self, origins, tol: float = 1e-8, max_iter: int = 10000,
                       want_p: bool = True, check_every: int = 0, stream=None,
                       raise_on_status: bool = False):

@@ -1,0 +1,441 @@
+// Anderson-accelerated Power-ψ: the fixed point s = Aᵀs + c of eq. (power_psi)
+// found with fewer operator passes.
+//
+// Each iteration is one Power-ψ pass g_k = Aᵀx_k + c (the same kernels as
+// Algorithm 2) followed by Anderson mixing (Anderson, J. ACM 1965; Walker &
+// Ni, SIAM J. Numer. Anal. 2011) over the last m residuals f = g − x:
+//
+//   ΔF = [f_{k−j+1} − f_{k−j}], ΔG = [g_{k−j+1} − g_{k−j}] (j = 1..m_k),
+//   γ = argmin ‖f_k − ΔF γ‖₂,   x_{k+1} = g_k − ΔG γ.
+//
+// For a linear map this is a windowed Krylov method, so the passes needed for
+// a given accuracy fall well below the power iteration's.  The stopping test
+// is the pass's own gap ‖g_k − x_k‖₁ ≤ ε (the s-tolerance of eq. condition,
+// in any PSI_TOL_* unit), and the result is s = g_k: one Power-ψ step from
+// x_k of size at most ε, exactly the criterion Algorithm 2 applies to its
+// last step.  ψ = (Bᵀs + d)/N follows as in Algorithm 2.
+//
+// Device work per iteration: the pass; k_aa_diff (f, ΔF, ΔG into a ring of
+// m columns, and the 2m dot products ⟨ΔF_j, ΔF_new⟩, ⟨ΔF_j, f⟩ as
+// per-workgroup partials); k_aa_solve (one workgroup: the partials in fixed
+// order, the Gram matrix updated by one row/column, a Cholesky solve with a
+// small relative shift; the window is cleared if the factorisation fails or
+// the gap grows tenfold); k_aa_mix (x_{k+1}, z = x/den).  Every reduction
+// has a fixed order, so solves are bitwise repeatable.
+#include <algorithm>
+#include <cmath>
+#include <limits>
+
+#include "psi_internal.h"
+
+namespace psi {
+
+namespace {
+
+constexpr int kMaxDepth = 8;
+constexpr int kAaGrid = 512;
+
+inline unsigned grid_for(int64_t n) { return static_cast<unsigned>((n + kBlock - 1) / kBlock); }
+inline size_t align_up(size_t x) { return (x + 255) / 256 * 256; }
+
+struct AaState {
+  int valid;      // f_prev, g_prev hold the previous iteration
+  int count;      // columns in the window
+  int head;       // ring slot that the next column takes
+  int restarts;
+  double best;    // smallest gap seen
+  double G[kMaxDepth][kMaxDepth];  // Gram matrix of ΔF, by ring slot
+  double gamma[kMaxDepth];          // mixing coefficients, by ring slot
+};
+
+struct AaWs {
+  double* dF;      // [m × N]
+  double* dG;      // [m × N]
+  double* f_prev;  // [N]
+  double* g_prev;  // [N]
+  double* part;    // [kAaGrid × 2m]
+  AaState* st;
+};
+
+size_t aa_layout(int64_t n, int m, AaWs* w, char* base) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char* {
+    char* p = base ? base + off : nullptr;
+    off += align_up(std::max<size_t>(bytes, 1));
+    return p;
+  };
+  AaWs t{};
+  t.dF = (double*)take(8 * size_t(m) * size_t(n));
+  t.dG = (double*)take(8 * size_t(m) * size_t(n));
+  t.f_prev = (double*)take(8 * size_t(n));
+  t.g_prev = (double*)take(8 * size_t(n));
+  t.part = (double*)take(8 * size_t(kAaGrid) * 2 * kMaxDepth);
+  t.st = (AaState*)take(sizeof(AaState));
+  if (w) *w = t;
+  return off;
+}
+
+__global__ void k_aa_init(AaState* s) {
+  s->valid = 0;
+  s->count = 0;
+  s->head = 0;
+  s->restarts = 0;
+  s->best = INFINITY;
+  for (int i = 0; i < kMaxDepth; ++i) {
+    s->gamma[i] = 0.0;
+    for (int j = 0; j < kMaxDepth; ++j) s->G[i][j] = 0.0;
+  }
+}
+
+__device__ inline double block_sum(double v, double* red) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  return (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// f = g − x; the new ΔF, ΔG column at ring slot `head`; f_prev, g_prev ← f, g;
+// partial dot products of every window column (the new one included) with
+// the new ΔF column and with f.
+__global__ __launch_bounds__(kBlock) void k_aa_diff(const double* g, const double* x, int64_t n,
+                                                    int m, AaWs w, const Ctrl* ctrl) {
+  __shared__ double red[kBlock / 64];
+  if (ctrl->done) return;
+  const int valid = w.st->valid, slot = w.st->head;  // uniform
+  const int cnt = valid ? std::min(w.st->count + 1, m) : 0;
+  double vv[kMaxDepth], vb[kMaxDepth];
+#pragma unroll
+  for (int j = 0; j < kMaxDepth; ++j) vv[j] = vb[j] = 0.0;
+  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * kBlock) {
+    const double gi = g[i], fi = gi - x[i];
+    if (valid) {
+      const double df = fi - w.f_prev[i];
+      w.dF[int64_t(slot) * n + i] = df;
+      w.dG[int64_t(slot) * n + i] = gi - w.g_prev[i];
+#pragma unroll
+      for (int q = 0; q < kMaxDepth; ++q) {
+        if (q < cnt) {  // window column q: q steps back from the new one
+          const int sj = (slot - q + m) % m;
+          const double dj = q == 0 ? df : w.dF[int64_t(sj) * n + i];
+          vv[q] += dj * df;
+          vb[q] += dj * fi;
+        }
+      }
+    }
+    w.f_prev[i] = fi;
+    w.g_prev[i] = gi;
+  }
+  if (!valid) return;  // uniform: no dot products on the first iteration
+  for (int q = 0; q < cnt; ++q) {
+    const double a = block_sum(vv[q], red);
+    const double b = block_sum(vb[q], red);
+    if (threadIdx.x == 0) {
+      w.part[int64_t(blockIdx.x) * 2 * kMaxDepth + q] = a;
+      w.part[int64_t(blockIdx.x) * 2 * kMaxDepth + kMaxDepth + q] = b;
+    }
+  }
+}
+
+// One workgroup: reduce the partials (16 interleaved slices, then the slices
+// in order), update the Gram matrix, and solve (G + δI) γ = b over the window
+// by Cholesky.
+__global__ __launch_bounds__(kBlock) void k_aa_solve(AaWs w, int m, int n_blk, const Ctrl* ctrl) {
+  __shared__ double v[2 * kMaxDepth];
+  __shared__ double slice[kBlock / (2 * kMaxDepth)][2 * kMaxDepth];
+  if (ctrl->done) return;
+  AaState* st = w.st;
+  // every thread reads the state before thread 0 changes it
+  const int valid = st->valid;
+  const int cnt = std::min(st->count + 1, m);
+  __syncthreads();
+  if (!valid) {  // uniform
+    if (threadIdx.x == 0) {
+      st->valid = 1;
+      st->count = 0;
+      st->best = ctrl->gap;
+    }
+    return;
+  }
+  {
+    constexpr int kSlices = kBlock / (2 * kMaxDepth);
+    const int q = threadIdx.x % (2 * kMaxDepth), sl = threadIdx.x / (2 * kMaxDepth);
+    double s = 0.0;
+    if ((q % kMaxDepth) < cnt)
+      for (int b = sl; b < n_blk; b += kSlices) s += w.part[int64_t(b) * 2 * kMaxDepth + q];
+    slice[sl][q] = s;
+    __syncthreads();
+    if (threadIdx.x < 2 * kMaxDepth) {
+      double t = 0.0;
+      for (int k = 0; k < kSlices; ++k) t += slice[k][threadIdx.x];
+      v[threadIdx.x] = t;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  const int slot = st->head;
+  // column / row of the new slot; window column q sits at slot (slot − q) mod m
+  for (int k = 0; k < cnt; ++k) {
+    const int sj = (slot - k + m) % m;
+    st->G[slot][sj] = v[k];
+    st->G[sj][slot] = v[k];
+  }
+  st->head = (slot + 1) % m;
+  st->count = cnt;
+  const double gap = ctrl->gap;
+  bool ok = gap <= 10.0 * st->best;
+  if (gap < st->best) st->best = gap;
+  // Cholesky of the window's Gram matrix (order: newest first) with a shift
+  double L[kMaxDepth][kMaxDepth];
+  double y[kMaxDepth];
+  double tr = 0.0;
+  for (int a = 0; a < cnt; ++a) {
+    const int sa = (slot - a + m) % m;
+    tr += st->G[sa][sa];
+  }
+  const double shift = 1e-13 * tr / cnt;
+  for (int a = 0; a < cnt && ok; ++a) {
+    const int sa = (slot - a + m) % m;
+    for (int b = 0; b <= a; ++b) {
+      const int sb = (slot - b + m) % m;
+      double s = st->G[sa][sb] + (a == b ? shift : 0.0);
+      for (int k = 0; k < b; ++k) s -= L[a][k] * L[b][k];
+      if (a == b) {
+        if (!(s > 0.0) || !isfinite(s)) {
+          ok = false;
+          break;
+        }
+        L[a][a] = sqrt(s);
+      } else {
+        L[a][b] = s / L[b][b];
+      }
+    }
+  }
+  for (int j = 0; j < kMaxDepth; ++j) st->gamma[j] = 0.0;
+  if (!ok) {  // clear the window: the next step is a plain Power-ψ step
+    st->count = 0;
+    st->restarts += 1;
+    return;
+  }
+  for (int a = 0; a < cnt; ++a) {  // L y = b
+    double s = v[kMaxDepth + a];
+    for (int k = 0; k < a; ++k) s -= L[a][k] * y[k];
+    y[a] = s / L[a][a];
+  }
+  for (int a = cnt - 1; a >= 0; --a) {  // Lᵀ γ = y
+    double s = y[a];
+    for (int k = a + 1; k < cnt; ++k) s -= L[k][a] * y[k];
+    y[a] = s / L[a][a];
+    st->gamma[(slot - a + m) % m] = y[a];
+  }
+}
+
+// x_{k+1} = g_k − ΔG γ and its gathered form z = x/den.
+__global__ __launch_bounds__(kBlock) void k_aa_mix(const double* g, const double* invden,
+                                                   int64_t n, int m, AaWs w, double* x, double* z,
+                                                   const Ctrl* ctrl) {
+  if (ctrl->done) return;
+  const int cnt = w.st->count;
+  double gam[kMaxDepth];
+#pragma unroll
+  for (int j = 0; j < kMaxDepth; ++j) gam[j] = j < m ? w.st->gamma[j] : 0.0;
+  const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= n) return;
+  double v = g[i];
+  if (cnt > 0) {
+    // slots outside the window have γ = 0 and may never have been written
+#pragma unroll
+    for (int j = 0; j < kMaxDepth; ++j)
+      if (j < m && gam[j] != 0.0) v -= gam[j] * w.dG[int64_t(j) * n + i];
+  }
+  x[i] = v;
+  z[i] = invden[i] * v;
+}
+
+__global__ void k_aa_start(const double* s0, const double* c, const double* invden, int64_t n,
+                           double* s, double* z) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double v = s0 ? s0[i] : c[i];
+  s[i] = v;
+  z[i] = invden[i] * v;
+}
+
+__global__ void k_aa_ctrl(Ctrl* c, double tol, int tol_mode, int max_iter, double bnorm) {
+  c->ticket = 0;
+  c->done = 0;
+  c->iter = 0;
+  c->status = 0;
+  c->gap = 0.0;
+  c->l1 = 0.0;
+  c->snorm = 0.0;
+  c->tol = tol;
+  c->tol_mode = tol_mode;
+  c->max_iter = max_iter;
+  c->bnorm = bnorm;
+}
+
+}  // namespace
+
+psi_status anderson_workspace_size(const psi_operator* op, int depth, size_t* bytes) {
+  PSI_REQUIRE(bytes, "bytes must not be NULL");
+  PSI_REQUIRE(depth >= 1 && depth <= kMaxDepth, "depth must be in [1, 8]");
+  *bytes = aa_layout(op->n, depth, nullptr, nullptr);
+  return PSI_OK;
+}
+
+psi_status solve_anderson(psi_operator* op, const psi_params* prm, int depth, const double* s0,
+                          double* psi_out, double* s_out, psi_info* info, void* ws,
+                          size_t ws_bytes, hipStream_t st) {
+  PSI_REQUIRE(prm && psi_out && ws, "params, psi_out and workspace must not be NULL");
+  PSI_REQUIRE(depth >= 1 && depth <= kMaxDepth, "depth must be in [1, 8]");
+  PSI_REQUIRE(prm->tol > 0.0 && std::isfinite(prm->tol), "tol must be finite and > 0");
+  PSI_REQUIRE(prm->max_iter > 0, "max_iter must be > 0");
+  PSI_REQUIRE(prm->tol_mode >= PSI_TOL_ABS_L1 && prm->tol_mode <= PSI_TOL_REL_L1,
+              "unknown tol_mode");
+  PSI_REQUIRE(prm->precision == PSI_PREC_FP64, "Anderson solves run in PSI_PREC_FP64");
+  PSI_REQUIRE(op->n_graphs == 1, "Anderson solves need a single-graph operator");
+  const size_t need = aa_layout(op->n, depth, nullptr, nullptr);
+  if (ws_bytes < need) {
+    set_error("workspace smaller than psi_anderson_workspace_size reported");
+    return PSI_ENOSPACE;
+  }
+  AaWs w{};
+  aa_layout(op->n, depth, &w, static_cast<char*>(ws));
+  const int64_t n = op->n;
+  const int prec = PSI_PREC_FP64;
+  const int tuned_tile = op->tuned_tile[prec];
+  const int tile = prm->tile_items ? prm->tile_items
+                 : tuned_tile      ? tuned_tile
+                 : (op->sched_items ? op->sched_items : kDefaultTileItems);
+  PSI_REQUIRE(tile_items_supported(tile), "unsupported tile_items");
+  int S = prm->col_segments ? prm->col_segments : op->tuned_S[prec];
+  if (S == 0) {  // the same rule as psi_solve for an FP64 gathered vector
+    const double xb = 8.0 * static_cast<double>(n);
+    S = 1;
+    if (xb > 3.0e6) {
+      S = 2;
+      while (S < 8 && xb / S > 2.5e6) S *= 2;
+    }
+  }
+  PSI_REQUIRE(S == 1 || S == 2 || S == 4 || S == 8, "col_segments must be 0, 1, 2, 4 or 8");
+  psi_status s = ensure_schedule(op, tile, st);
+  if (s != PSI_OK) return s;
+  if (S > 1) {
+    s = ensure_segments(op, S, tile, st);
+    if (s != PSI_OK) return s;
+  }
+  auto pass = [&](PassMode mode, const PassArgs& a) {
+    return S > 1 ? launch_pass_seg(op, mode, a, st) : launch_pass(op, mode, a, st);
+  };
+  hipEvent_t ev0, ev1;
+  PSI_HIP_CHECK(hipEventCreate(&ev0));
+  PSI_HIP_CHECK(hipEventCreate(&ev1));
+  PSI_HIP_CHECK(hipEventRecord(ev0, st));
+  double* X = op->s_a;
+  double* zX = op->z_a;
+  double* Gb = op->s_b;
+  double* zG = op->z_b;
+  hipLaunchKernelGGL(k_aa_start, dim3(grid_for(n)), dim3(kBlock), 0, st, s0, op->c, op->invden,
+                     n, X, zX);
+  hipLaunchKernelGGL(k_aa_ctrl, dim3(1), dim3(1), 0, st, op->ctrl, prm->tol, prm->tol_mode,
+                     prm->max_iter, op->stats.b_norm);
+  hipLaunchKernelGGL(k_aa_init, dim3(1), dim3(1), 0, st, w.st);
+  PSI_HIP_CHECK(hipGetLastError());
+  const int dgrid = static_cast<int>(std::min<int64_t>(kAaGrid, (n + kBlock - 1) / kBlock));
+  PassArgs base = base_args(op);
+  auto iteration = [&]() -> psi_status {
+    PassArgs a = base;
+    a.x = zX;
+    a.s_old = X;
+    a.s_new = Gb;
+    a.z_new = zG;
+    a.count_iter = 1;
+    a.respect_done = 1;
+    a.ctrl = op->ctrl;
+    psi_status r = pass(kStep64, a);
+    if (r != PSI_OK) return r;
+    hipLaunchKernelGGL(k_aa_diff, dim3(dgrid), dim3(kBlock), 0, st, Gb, X, n, depth, w, op->ctrl);
+    hipLaunchKernelGGL(k_aa_solve, dim3(1), dim3(kBlock), 0, st, w, depth, dgrid, op->ctrl);
+    hipLaunchKernelGGL(k_aa_mix, dim3(grid_for(n)), dim3(kBlock), 0, st, Gb, op->invden, n, depth,
+                       w, X, zX, op->ctrl);
+    PSI_HIP_CHECK(hipGetLastError());
+    return PSI_OK;
+  };
+  // enqueue blocks of iterations; iterations after the gap met tol exit at once
+  int enq = 0, k = prm->check_every > 0 ? prm->check_every : 4;
+  int status = PSI_OK;
+  double best = std::numeric_limits<double>::infinity();
+  int best_iter = 0;
+  Ctrl* h = op->host_ctrl;
+  while (true) {
+    const int cnt = std::min(k, prm->max_iter - enq);
+    for (int i = 0; i < cnt; ++i) {
+      s = iteration();
+      if (s != PSI_OK) return s;
+    }
+    enq += cnt;
+    PSI_HIP_CHECK(hipMemcpyAsync(h, op->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+    PSI_HIP_CHECK(hipStreamSynchronize(st));
+    if (h->done) {
+      status = h->status;
+      break;
+    }
+    if (enq >= prm->max_iter) {
+      status = PSI_ENOTCONV;
+      break;
+    }
+    if (h->gap < best * (1.0 - 1e-3)) {
+      best = h->gap;
+      best_iter = h->iter;
+    } else if (h->iter - best_iter >= 25) {
+      status = PSI_ESTAGNATED;
+      break;
+    }
+    if (prm->check_every == 0) k = std::min(2 * k, 16);
+  }
+  // ψ = (Bᵀs + d)/N from s = g of the last pass (the last line of Algorithm 2)
+  {
+    PassArgs a = base;
+    a.x = zG;
+    a.s_new = psi_out;
+    a.count_iter = 0;
+    a.respect_done = 0;
+    s = pass(kFinal64, a);
+    if (s != PSI_OK) return s;
+  }
+  if (s_out) PSI_HIP_CHECK(hipMemcpyAsync(s_out, Gb, 8 * size_t(n), hipMemcpyDeviceToDevice, st));
+  AaState hs{};
+  PSI_HIP_CHECK(hipMemcpyAsync(&hs, w.st, sizeof(AaState), hipMemcpyDeviceToHost, st));
+  PSI_HIP_CHECK(hipEventRecord(ev1, st));
+  PSI_HIP_CHECK(hipEventSynchronize(ev1));
+  float ms = 0.f;
+  PSI_HIP_CHECK(hipEventElapsedTime(&ms, ev0, ev1));
+  (void)hipEventDestroy(ev0);
+  (void)hipEventDestroy(ev1);
+  psi_info inf{};
+  inf.status = status;
+  inf.iterations = h->iter;
+  inf.spmv_passes = h->iter + 1;
+  inf.refinements = hs.restarts;  // window restarts
+  inf.used_s0 = s0 ? 1 : 0;
+  inf.col_segments = S;
+  inf.tile_items = tile;
+  inf.final_gap = h->gap;
+  inf.final_l1_step = h->l1;
+  inf.b_norm = op->stats.b_norm;
+  inf.kappa = op->stats.kappa;
+  inf.err_bound_s = inf.kappa < 1.0 ? inf.kappa / (1.0 - inf.kappa) * h->l1
+                                    : std::numeric_limits<double>::infinity();
+  inf.psi_gap_bound = h->l1 * inf.b_norm / static_cast<double>(n);
+  inf.device_ms = ms;
+  if (info) *info = inf;
+  if (status == PSI_ENOTCONV) set_error("max_iter reached before the gap fell to tol");
+  else if (status == PSI_ESTAGNATED) set_error("the gap stopped decreasing above tol");
+  else if (status == PSI_ENUMERIC) set_error("NaN or Inf in the iteration");
+  return static_cast<psi_status>(status);
+}
+
+}  // namespace psi

@@ -269,6 +269,25 @@ psi_status psi_solve_batched(psi_operator* op, const psi_params* prm, int32_t n_
   PSI_GUARD_END
 }
 
+psi_status psi_anderson_workspace_size(const psi_operator* op, int32_t depth, size_t* bytes) {
+  PSI_GUARD_BEGIN
+  PSI_REQUIRE(op, "op must not be NULL");
+  return psi::anderson_workspace_size(op, depth, bytes);
+  PSI_GUARD_END
+}
+
+psi_status psi_solve_anderson(psi_operator* op, const psi_params* prm, int32_t depth,
+                              const double* s0, double* psi_out, double* s_out, psi_info* info,
+                              void* workspace, size_t workspace_bytes, void* stream) {
+  PSI_GUARD_BEGIN
+  PSI_REQUIRE(op, "op must not be NULL");
+  psi_status st = psi::check_device(op);
+  if (st != PSI_OK) return st;
+  return psi::solve_anderson(op, prm, depth, s0, psi_out, s_out, info, workspace,
+                             workspace_bytes, static_cast<hipStream_t>(stream));
+  PSI_GUARD_END
+}
+
 psi_status psi_solve_origins(psi_operator* op, const psi_params* prm, int32_t n_origins,
                              const int32_t* origins, double* p_out, double* psi_out,
                              psi_info* infos, void* workspace, size_t workspace_bytes,

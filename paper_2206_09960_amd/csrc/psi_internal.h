@@ -242,6 +242,10 @@ psi_status solve(psi_operator* op, const psi_params* prm, const double* s0, doub
                  double* s_out, psi_info* info, hipStream_t stream);
 psi_status autotune(psi_operator* op, int precision, int reps, int* tile_items, int* col_segments,
                     double* best_ms, hipStream_t stream);
+psi_status anderson_workspace_size(const psi_operator* op, int depth, size_t* bytes);
+psi_status solve_anderson(psi_operator* op, const psi_params* prm, int depth, const double* s0,
+                          double* psi_out, double* s_out, psi_info* info, void* ws,
+                          size_t ws_bytes, hipStream_t st);
 
 // Exclusive prefix sum of n uint32 (in may equal out); tile_sums needs
 // scan_tile_count(n) + 1 entries; *total receives the sum.

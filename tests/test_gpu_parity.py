@@ -412,3 +412,42 @@ def test_exact_fixed_point_equals_the_closed_form(gpu_lib):
     A, B, c, d = oracle.operator(g.n, g.follower, g.leader, g.lam, g.mu)
     exact, _ = oracle.psi_closed_form(A, B, c, d)
     assert oracle.rel_l1(exact, psi.cpu().numpy()) <= 1e-12
+
+
+@pytest.mark.parametrize("n,deg,gamma,sigma,tol,depth", [
+    (50_000, 12, 2.2, 1.5, 1e-10, 4),
+    (200_000, 20, 2.1, 2.0, 1e-8, 1),
+    (200_000, 20, 2.1, 2.0, 1e-8, 8),
+])
+def test_anderson_matches_oracle_in_fewer_passes(gpu_lib, n, deg, gamma, sigma, tol, depth):
+    api = gpu_lib
+    g = synth.chung_lu(n, deg, gamma, 91, sigma=sigma)
+    op = api.Operator(g.n, g.follower, g.leader, g.lam, g.mu)
+    A, B, c, d = oracle.operator(g.n, g.follower, g.leader, g.lam, g.mu)
+    r = oracle.power_psi(A, B, c, d, tol)
+    psi, s, info = op.solve_anderson(tol=tol, depth=depth, return_s=True)
+    assert info["status"] == 0, info
+    psi, s = psi.cpu().numpy(), s.cpu().numpy()
+    assert oracle.rel_l1(r["psi"], psi) <= 1e-9
+    # the returned s is a Power-ψ step of size <= tol: its own residual is below tol too
+    res = oracle.fixed_point_residual(A, c, s)
+    assert res <= 1.5 * tol + 1e-15 * np.abs(s).sum(), res
+    if depth > 1:
+        assert info["iterations"] < r["iterations"], (info["iterations"], r["iterations"])
+    again, _ = op.solve_anderson(tol=tol, depth=depth)
+    assert np.array_equal(again.cpu().numpy(), psi)
+    # a start far from the fixed point converges to the same ψ
+    s0 = torch.tensor(np.full(g.n, 3.0))
+    psi2, info2 = op.solve_anderson(tol=tol, depth=depth, s0=s0)
+    assert info2["status"] == 0 and info2["used_s0"] == 1
+    assert oracle.rel_l1(r["psi"], psi2.cpu().numpy()) <= 1e-9
+
+
+def test_anderson_invalid(gpu_lib):
+    api = gpu_lib
+    g = synth.chung_lu(2000, 5, 2.2, 92)
+    op = api.Operator(g.n, g.follower, g.leader, g.lam, g.mu)
+    with pytest.raises(api.PsiError, match="depth"):
+        op.solve_anderson(depth=9)
+    psi, info = op.solve_anderson(tol=1e-14, max_iter=3)
+    assert info["status_name"] == "PSI_ENOTCONV" and info["iterations"] == 3
