@@ -203,6 +203,8 @@ struct psi_operator {
   // (0: CSR(Aᵀ), 1: CSR(A)); built on first use
   psi::MpHubs mp_hubs[2]{};
   int64_t mp_max_hubs = 0, mp_max_chunks = 0;
+  // ‖Aᵀc + c − c‖₁ = ‖Aᵀc‖₁, the residual of the cold start (computed on first need)
+  double rc_l1 = -1.0;
   // schedule chosen by psi_autotune, per precision (0 = not tuned)
   int tuned_tile[4]{};
   int tuned_S[4]{};

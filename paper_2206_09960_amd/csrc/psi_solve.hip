@@ -249,30 +249,60 @@ psi_status solve(psi_operator* op, const psi_params* prm, const double* s0, doub
   inf.col_segments = S;
   inf.tile_items = tile;
 
-  // optional start: keep s0 only if its fixed-point residual beats c's
+  // optional start: keep s0 only if its fixed-point residual beats c's.
+  // ‖r(c)‖₁ depends only on the operator and is computed once.  In FP64 the
+  // pass from s0 is the solve's first iteration (counted, with its gap test),
+  // and the iteration continues from its output when s0 is kept.
+  bool s0_stepped = false;
   if (s0 && !(prm->flags & PSI_NO_FALLBACK)) {
-    for (int which = 0; which < 2; ++which) {
-      hipLaunchKernelGGL(k_init64, dim3(grid_for(n)), dim3(kBlock), 0, st, which ? s0 : nullptr,
-                         op->c, op->invden, n, op->s_a, op->z_a);
+    if (!(op->rc_l1 >= 0.0)) {
+      hipLaunchKernelGGL(k_init64, dim3(grid_for(n)), dim3(kBlock), 0, st, nullptr, op->c,
+                         op->invden, n, op->s_a, op->z_a);
       PassArgs a = base;
       a.x = op->z_a;
       a.s_old = op->s_a;
       a.s_new = op->s_b;
       a.z_new = op->z_b;
-      a.gap_out = op->scal + which;
+      a.gap_out = op->scal;
       a.count_iter = 0;
       a.respect_done = 0;
       a.ctrl = op->ctrl + 1;
       s = run_pass(op, S, kStep64, a, st);
       if (s != PSI_OK) return s;
       inf.spmv_passes += 1;
+      double rc = 0.0;
+      PSI_HIP_CHECK(hipMemcpyAsync(&rc, op->scal, sizeof(rc), hipMemcpyDeviceToHost, st));
+      PSI_HIP_CHECK(hipStreamSynchronize(st));
+      op->rc_l1 = rc;
     }
-    double r[2];
-    PSI_HIP_CHECK(hipMemcpyAsync(r, op->scal, sizeof(r), hipMemcpyDeviceToHost, st));
+    const bool first_iter = prm->precision == PSI_PREC_FP64;
+    hipLaunchKernelGGL(k_init64, dim3(grid_for(n)), dim3(kBlock), 0, st, s0, op->c, op->invden,
+                       n, op->s_a, op->z_a);
+    if (first_iter)
+      hipLaunchKernelGGL(k_ctrl_set, dim3(1), dim3(1), 0, st, op->ctrl, prm->tol, prm->tol_mode,
+                         prm->max_iter, bnorm);
+    PassArgs a = base;
+    a.x = op->z_a;
+    a.s_old = op->s_a;
+    a.s_new = op->s_b;
+    a.z_new = op->z_b;
+    a.gap_out = op->scal + 1;
+    a.count_iter = first_iter ? 1 : 0;
+    a.respect_done = 0;
+    a.ctrl = first_iter ? op->ctrl : op->ctrl + 1;
+    s = run_pass(op, S, kStep64, a, st);
+    if (s != PSI_OK) return s;
+    double r1 = 0.0;
+    PSI_HIP_CHECK(hipMemcpyAsync(&r1, op->scal + 1, sizeof(r1), hipMemcpyDeviceToHost, st));
     PSI_HIP_CHECK(hipStreamSynchronize(st));
-    if (!(r[1] <= r[0])) {
+    if (!(r1 <= op->rc_l1)) {  // c wins: the step from s0 is discarded
       s0 = nullptr;
       inf.used_s0 = 0;
+      inf.spmv_passes += 1;
+    } else if (first_iter) {
+      s0_stepped = true;  // the step is the solve's first iteration, counted below
+    } else {
+      inf.spmv_passes += 1;
     }
   }
 
@@ -302,12 +332,18 @@ psi_status solve(psi_operator* op, const psi_params* prm, const double* s0, doub
   };
 
   if (prec == PSI_PREC_FP64 || prec == PSI_PREC_FP64_WEIGHTED) {
-    hipLaunchKernelGGL(k_init64, dim3(grid_for(n)), dim3(kBlock), 0, st, s0, op->c, op->invden,
-                       n, op->s_a, op->z_a);
-    hipLaunchKernelGGL(k_ctrl_set, dim3(1), dim3(1), 0, st, op->ctrl, prm->tol, prm->tol_mode,
-                       prm->max_iter, bnorm);
     IterResult res;
-    s = plain64(op->s_a, op->z_a, op->s_b, op->z_b, prm->max_iter, &res);
+    if (s0_stepped) {
+      // (s_b, z_b) = the first step from s0, already counted by the control block;
+      // pass i writes s_a for even i, so iteration t ends in s_b when t is odd
+      s = plain64(op->s_b, op->z_b, op->s_a, op->z_a, prm->max_iter - 1, &res);
+    } else {
+      hipLaunchKernelGGL(k_init64, dim3(grid_for(n)), dim3(kBlock), 0, st, s0, op->c,
+                         op->invden, n, op->s_a, op->z_a);
+      hipLaunchKernelGGL(k_ctrl_set, dim3(1), dim3(1), 0, st, op->ctrl, prm->tol,
+                         prm->tol_mode, prm->max_iter, bnorm);
+      s = plain64(op->s_a, op->z_a, op->s_b, op->z_b, prm->max_iter, &res);
+    }
     if (s != PSI_OK) return s;
     inf.iterations = res.iters;
     inf.spmv_passes += res.iters;

@@ -341,6 +341,17 @@ def test_warm_start_and_fallback(gpu_lib):
     psi, info = op.solve(tol=1e-8, s0=bad, no_fallback=True)
     assert info["used_s0"] == 1
     assert oracle.rel_l1(ref.cpu().numpy(), psi.cpu().numpy()) <= 1e-9
+    # the residual of c is kept by the operator and the step from a kept s0 is the
+    # first iteration: a warm FP64 solve runs no pass beyond its iterations and ψ
+    psi, info = op.solve(tol=1e-8, s0=s_ref * (1 + 1e-6))
+    assert info["used_s0"] == 1 and info["spmv_passes"] == info["iterations"] + 1
+    psi, info = op.solve(tol=1e-8, s0=bad)
+    assert info["used_s0"] == 0 and info["spmv_passes"] == info["iterations"] + 2
+    assert oracle.rel_l1(ref.cpu().numpy(), psi.cpu().numpy()) <= 1e-9
+    # the other precisions compare residuals the same way
+    psi, info = op.solve(tol=1e-8, precision="mixed", s0=s_ref * (1 + 1e-6))
+    assert info["status"] == 0 and info["used_s0"] == 1
+    assert oracle.rel_l1(ref.cpu().numpy(), psi.cpu().numpy()) <= 1e-9
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
