@@ -248,6 +248,16 @@ def run_single(args, name):
                     gathers_per_s=round(m / (pass_ms[kind] * 1e-3) / 1e9, 1),
                     gather_unit="G random lines/s")
 
+    # the ceiling the pass is held to: the same random gathers without arithmetic
+    probe = api.gather_probe(g.n, m, col_segments=segs, reps=20)
+    roofline["gather_ceiling"] = dict(
+        gathers_per_s=round(probe["gathers_per_s"] / 1e9, 1), unit="G random lines/s",
+        frac=round(m / (pass_ms[kind] * 1e-3) / probe["gathers_per_s"], 4),
+        probe=f"psi_gather_probe: {m} random 8-byte gathers, 4-byte indices streamed, into a "
+              f"vector of {g.n} FP64 split in {segs} column segment(s) by XCD group")
+    log(f"gather probe: {probe['gathers_per_s'] / 1e9:.1f} G/s; pass at "
+        f"{roofline['gather_ceiling']['frac']:.0%} of it")
+
     if args.copy_calibration:
         a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
         b = torch.empty_like(a)

@@ -272,6 +272,19 @@ psi_status psi_solve_origins(psi_operator* op, const psi_params* prm, int32_t n_
 psi_status psi_pass_time(psi_operator* op, int32_t pass_kind, int32_t reps, int32_t tile_items,
                          int32_t col_segments, double* mean_ms, void* stream);
 
+/* Random-gather probe: the access pattern of an operator pass without its
+ * arithmetic, for the ceiling the pass is held to.  Workgroup b of `grid`
+ * (a multiple of 8) streams its share of idx (device int32 [n_idx]) and
+ * sums x[s·(n_x/S) + idx[k]] with s = (b mod 8) mod S — the column segment
+ * its XCD group gathers from in a segmented pass (workgroups go to the 8
+ * XCDs round-robin) — writing one sum per workgroup to out (device FP64
+ * [grid]).  Indices are clamped into the segment.  x: device FP64 [n_x].
+ * Times `reps` launches with hipEvents on `stream` after one untimed
+ * launch; *mean_ms (host) is the mean.  Blocks. */
+psi_status psi_gather_probe(const double* x, int64_t n_x, int32_t col_segments,
+                            const int32_t* idx, int64_t n_idx, double* out, int32_t grid,
+                            int32_t reps, double* mean_ms, void* stream);
+
 /* Schedule autotuner.  Times `reps` back-to-back launches of the pass that
  * dominates a solve in `precision` (the FP64 step, the FP64 weighted step, or
  * the FP32 correction step for PSI_PREC_MIXED / PSI_PREC_FP32; with the

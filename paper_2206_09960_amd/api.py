@@ -368,6 +368,29 @@ def build_operator(graph, flags: int = 0, stream=None, device=None) -> Operator:
                     node_offsets=graph.node_offsets, flags=flags, stream=stream, device=device)
 
 
+# ---------------------------------------------------------------------- gather probe
+def gather_probe(n_x: int, n_idx: int, col_segments: int = 1, seed: int = 0, reps: int = 20,
+                 grid: int = 0, device=None, stream=None) -> dict:
+    """psi_gather_probe on a random FP64 vector of n_x entries and n_idx
+    random indices (uniform within a segment): the random-gather rate of an
+    operator pass with that many users, edges and column segments."""
+    dev = torch.device(device) if device is not None else torch.device(
+        "cuda", torch.cuda.current_device())
+    gen = torch.Generator(device=dev).manual_seed(seed)
+    x = torch.rand(n_x, dtype=torch.float64, device=dev, generator=gen)
+    seg = n_x // col_segments
+    idx = torch.randint(0, seg, (n_idx,), dtype=torch.int32, device=dev, generator=gen)
+    if grid == 0:
+        grid = 8 * 1024
+    out = torch.empty(grid, dtype=torch.float64, device=dev)
+    ms = ctypes.c_double()
+    with torch.cuda.device(dev):
+        _check(_ffi.load().psi_gather_probe(x.data_ptr(), n_x, col_segments, idx.data_ptr(), n_idx,
+                                            out.data_ptr(), grid, reps, ctypes.byref(ms),
+                                            _stream_handle(stream)))
+    return dict(ms=ms.value, gathers_per_s=n_idx / (ms.value * 1e-3))
+
+
 # ---------------------------------------------------------------------- learned warm start
 def mpnn_param_count() -> int:
     return int(_ffi.load().psi_mpnn_param_count())

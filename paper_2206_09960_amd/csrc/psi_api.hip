@@ -269,6 +269,15 @@ psi_status psi_solve_batched(psi_operator* op, const psi_params* prm, int32_t n_
   PSI_GUARD_END
 }
 
+psi_status psi_gather_probe(const double* x, int64_t n_x, int32_t col_segments,
+                            const int32_t* idx, int64_t n_idx, double* out, int32_t grid,
+                            int32_t reps, double* mean_ms, void* stream) {
+  PSI_GUARD_BEGIN
+  return psi::gather_probe(x, n_x, col_segments, idx, n_idx, out, grid, reps, mean_ms,
+                           static_cast<hipStream_t>(stream));
+  PSI_GUARD_END
+}
+
 psi_status psi_anderson_workspace_size(const psi_operator* op, int32_t depth, size_t* bytes) {
   PSI_GUARD_BEGIN
   PSI_REQUIRE(op, "op must not be NULL");

@@ -5,6 +5,7 @@ within 1e-9 relative L1; mixed precision (FP32 corrections + FP64 residual)
 within 1e-9; FP32-only within 1e-6.  Index work (CSR structure, clean-up
 counts) is compared exactly.
 """
+import ctypes
 import json
 import os
 
@@ -462,3 +463,18 @@ def test_anderson_invalid(gpu_lib):
         op.solve_anderson(depth=9)
     psi, info = op.solve_anderson(tol=1e-14, max_iter=3)
     assert info["status_name"] == "PSI_ENOTCONV" and info["iterations"] == 3
+
+
+def test_gather_probe_runs_and_clamps(gpu_lib):
+    api = gpu_lib
+    r = api.gather_probe(100_000, 1_000_000, col_segments=4, reps=2)
+    assert r["ms"] > 0 and r["gathers_per_s"] > 1e9
+    # indices outside the segment are clamped, not read out of bounds
+    x = torch.arange(16, dtype=torch.float64, device="cuda")
+    idx = torch.tensor([0, 3, 100, -5], dtype=torch.int32, device="cuda")
+    out = torch.zeros(8, dtype=torch.float64, device="cuda")
+    ms = ctypes.c_double()
+    assert api.load().psi_gather_probe(x.data_ptr(), 16, 2, idx.data_ptr(), 4, out.data_ptr(), 8,
+                                       1, ctypes.byref(ms), api._stream_handle(None)) == 0
+    # workgroup 0 gathers segment 0 (entries 0..7): 0 + 3 + 7 + 7
+    assert out[0].item() == 17.0
