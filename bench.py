@@ -22,7 +22,7 @@ Other workloads (--workload): cl_10m (N=1e7, 2e8 edges), cl_40m (N=4e7,
 N=4e6, 8e7-edge graph, batched), graphs256 (256 graphs with N in [1e3, 1e5]
 in one batched solve).
 
-Prints one JSON line.  ``--gpus N`` with N > 1 exits: this build runs on one
+Prints one JSON line.  ``--gpus N`` with N > 1 exits: the benchmark runs on one
 GPU.
 """
 from __future__ import annotations

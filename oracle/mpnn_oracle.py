@@ -1,6 +1,6 @@
 """CPU oracle of the learned warm start — TEST INFRASTRUCTURE ONLY.
 
-The warm start is this build's extension (the paper has no learned part): a
+The warm start is an extension of the method (the paper has no learned part): a
 small message-passing network predicts t_i = log(s_i / c_i) for the fixed
 point s of eq. (power_psi) (s ≥ c because A and c are non-negative), and the
 solver starts from s0 = c ⊙ exp(t̂).  The network, in the order the GPU runs

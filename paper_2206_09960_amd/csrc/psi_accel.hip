@@ -330,9 +330,10 @@ psi_status solve_anderson(psi_operator* op, const psi_params* prm, int depth, co
   auto pass = [&](PassMode mode, const PassArgs& a) {
     return S > 1 ? launch_pass_seg(op, mode, a, st) : launch_pass(op, mode, a, st);
   };
-  hipEvent_t ev0, ev1;
-  PSI_HIP_CHECK(hipEventCreate(&ev0));
-  PSI_HIP_CHECK(hipEventCreate(&ev1));
+  EventPair evp;
+  PSI_HIP_CHECK(hipEventCreate(&evp.a));
+  PSI_HIP_CHECK(hipEventCreate(&evp.b));
+  hipEvent_t ev0 = evp.a, ev1 = evp.b;
   PSI_HIP_CHECK(hipEventRecord(ev0, st));
   double* X = op->s_a;
   double* zX = op->z_a;
@@ -413,8 +414,6 @@ psi_status solve_anderson(psi_operator* op, const psi_params* prm, int depth, co
   PSI_HIP_CHECK(hipEventSynchronize(ev1));
   float ms = 0.f;
   PSI_HIP_CHECK(hipEventElapsedTime(&ms, ev0, ev1));
-  (void)hipEventDestroy(ev0);
-  (void)hipEventDestroy(ev1);
   psi_info inf{};
   inf.status = status;
   inf.iterations = h->iter;

@@ -649,9 +649,10 @@ psi_status solve_batched(psi_operator* op, const psi_params* prm, int K, const d
                               hipHostMallocDefault));
   w.host_ctrl = pinned.p;
   const int grid = std::min(rows_grid(), static_cast<int>(n_wtiles));
-  hipEvent_t ev0, ev1;
-  PSI_HIP_CHECK(hipEventCreate(&ev0));
-  PSI_HIP_CHECK(hipEventCreate(&ev1));
+  EventPair evp;
+  PSI_HIP_CHECK(hipEventCreate(&evp.a));
+  PSI_HIP_CHECK(hipEventCreate(&evp.b));
+  hipEvent_t ev0 = evp.a, ev1 = evp.b;
   PSI_HIP_CHECK(hipEventRecord(ev0, st));
   int worst = PSI_OK;
   for (int k0 = 0; k0 < K; k0 += kMaxK) {
@@ -756,8 +757,6 @@ psi_status solve_batched(psi_operator* op, const psi_params* prm, int K, const d
   PSI_HIP_CHECK(hipEventSynchronize(ev1));
   float ms = 0.f;
   PSI_HIP_CHECK(hipEventElapsedTime(&ms, ev0, ev1));
-  (void)hipEventDestroy(ev0);
-  (void)hipEventDestroy(ev1);
   if (infos)
     for (int k = 0; k < K; ++k) infos[k].device_ms = ms;
   if (worst != PSI_OK) set_error("a scenario did not converge (see its info)");
@@ -779,9 +778,10 @@ psi_status solve_graphs(psi_operator* op, const psi_params* prm, double* psi_out
   if (s != PSI_OK) return s;
   const int64_t n = op->n;
   const int G = op->n_graphs;
-  hipEvent_t ev0, ev1;
-  PSI_HIP_CHECK(hipEventCreate(&ev0));
-  PSI_HIP_CHECK(hipEventCreate(&ev1));
+  EventPair evp;
+  PSI_HIP_CHECK(hipEventCreate(&evp.a));
+  PSI_HIP_CHECK(hipEventCreate(&evp.b));
+  hipEvent_t ev0 = evp.a, ev1 = evp.b;
   PSI_HIP_CHECK(hipEventRecord(ev0, st));
   hipLaunchKernelGGL(k_graph_init, dim3(grid_for(std::max<int64_t>(n, G))), dim3(kBlock), 0, st,
                      op->c, op->invden, n, G, op->s_a, op->z_a, op->gdone, op->giter, op->gstatus,
@@ -841,8 +841,6 @@ psi_status solve_graphs(psi_operator* op, const psi_params* prm, double* psi_out
   PSI_HIP_CHECK(hipEventSynchronize(ev1));
   float ms = 0.f;
   PSI_HIP_CHECK(hipEventElapsedTime(&ms, ev0, ev1));
-  (void)hipEventDestroy(ev0);
-  (void)hipEventDestroy(ev1);
   int worst = PSI_OK;
   for (int g = 0; g < G; ++g) {
     const int stg = dn[g] ? stv[g] : PSI_ENOTCONV;
@@ -898,9 +896,10 @@ psi_status solve_origins(psi_operator* op, const psi_params* prm, int K, const i
   BatchCtrl* h = pinned.p;
   const int grid = std::min(rows_grid(), static_cast<int>(sc.n_wtiles));
   const int cgrid = static_cast<int>(std::min<int64_t>(kMaxGrid, (n + 3) / 4));
-  hipEvent_t ev0, ev1;
-  PSI_HIP_CHECK(hipEventCreate(&ev0));
-  PSI_HIP_CHECK(hipEventCreate(&ev1));
+  EventPair evp;
+  PSI_HIP_CHECK(hipEventCreate(&evp.a));
+  PSI_HIP_CHECK(hipEventCreate(&evp.b));
+  hipEvent_t ev0 = evp.a, ev1 = evp.b;
   PSI_HIP_CHECK(hipEventRecord(ev0, st));
   int worst = PSI_OK;
   for (int k0 = 0; k0 < K; k0 += kMaxK) {
@@ -990,8 +989,6 @@ psi_status solve_origins(psi_operator* op, const psi_params* prm, int K, const i
   PSI_HIP_CHECK(hipEventSynchronize(ev1));
   float ms = 0.f;
   PSI_HIP_CHECK(hipEventElapsedTime(&ms, ev0, ev1));
-  (void)hipEventDestroy(ev0);
-  (void)hipEventDestroy(ev1);
   if (infos)
     for (int k = 0; k < K; ++k) infos[k].device_ms = ms;
   if (worst != PSI_OK) set_error("an origin did not converge (see its info)");

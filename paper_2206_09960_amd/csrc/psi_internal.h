@@ -32,6 +32,18 @@ void clear_error();
     }                                 \
   } while (0)
 
+// A pair of hipEvents destroyed with their scope (also on early error returns).
+struct EventPair {
+  hipEvent_t a = nullptr, b = nullptr;
+  EventPair() = default;
+  EventPair(const EventPair&) = delete;
+  EventPair& operator=(const EventPair&) = delete;
+  ~EventPair() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+};
+
 // ---------------------------------------------------------------- constants
 constexpr int kBlock = 256;            // threads of every operator-pass workgroup
 constexpr int kMinTileItems = 1024;    // smallest merge-path tile (sizes the schedule)

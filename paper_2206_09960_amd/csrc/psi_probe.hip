@@ -51,9 +51,10 @@ psi_status gather_probe(const double* x, int64_t n_x, int S, const int32_t* idx,
   const int64_t seg = n_x / S;
   hipLaunchKernelGGL(k_gather_probe, dim3(grid), dim3(kBlock), 0, st, x, seg, S, idx, n_idx, out);
   PSI_HIP_CHECK(hipGetLastError());
-  hipEvent_t a, b;
-  PSI_HIP_CHECK(hipEventCreate(&a));
-  PSI_HIP_CHECK(hipEventCreate(&b));
+  EventPair evp;
+  PSI_HIP_CHECK(hipEventCreate(&evp.a));
+  PSI_HIP_CHECK(hipEventCreate(&evp.b));
+  hipEvent_t a = evp.a, b = evp.b;
   PSI_HIP_CHECK(hipEventRecord(a, st));
   for (int r = 0; r < reps; ++r)
     hipLaunchKernelGGL(k_gather_probe, dim3(grid), dim3(kBlock), 0, st, x, seg, S, idx, n_idx,
@@ -62,8 +63,6 @@ psi_status gather_probe(const double* x, int64_t n_x, int S, const int32_t* idx,
   PSI_HIP_CHECK(hipEventSynchronize(b));
   float ms = 0.f;
   PSI_HIP_CHECK(hipEventElapsedTime(&ms, a, b));
-  (void)hipEventDestroy(a);
-  (void)hipEventDestroy(b);
   PSI_HIP_CHECK(hipGetLastError());
   *mean_ms = static_cast<double>(ms) / reps;
   return PSI_OK;

@@ -196,14 +196,6 @@ psi_status iterate(psi_operator* op, int S, int ctrl_idx, PassMode mode, Make ma
   }
 }
 
-struct Timer {
-  hipEvent_t a = nullptr, b = nullptr;
-  ~Timer() {
-    if (a) (void)hipEventDestroy(a);
-    if (b) (void)hipEventDestroy(b);
-  }
-};
-
 }  // namespace
 
 psi_status solve(psi_operator* op, const psi_params* prm, const double* s0, double* psi_out,
@@ -236,7 +228,7 @@ psi_status solve(psi_operator* op, const psi_params* prm, const double* s0, doub
   const int64_t n = op->n;
   const double bnorm = op->stats.b_norm;
   const double kap = op->stats.kappa;
-  Timer tm;
+  EventPair tm;
   PSI_HIP_CHECK(hipEventCreate(&tm.a));
   PSI_HIP_CHECK(hipEventCreate(&tm.b));
   PSI_HIP_CHECK(hipEventRecord(tm.a, st));
@@ -613,7 +605,7 @@ psi_status pass_time(psi_operator* op, int kind, int reps, int tile_items, int c
   };
   s = launch(make(0));
   if (s != PSI_OK) return s;
-  Timer tm;
+  EventPair tm;
   PSI_HIP_CHECK(hipEventCreate(&tm.a));
   PSI_HIP_CHECK(hipEventCreate(&tm.b));
   PSI_HIP_CHECK(hipEventRecord(tm.a, st));
