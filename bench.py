@@ -60,10 +60,10 @@ def algorithmic_bytes(kind: str, n: int, m: int, segs: int = 1) -> int:
     """Compulsory HBM bytes of one launch (each array touched once)."""
     if kind == "step64":     # col 4M; row_ptr 4, z 8, c 8, mu 8, invden 8, s_old 8, s_new 8, z_new 8
         return 4 * m + 60 * n
-    if kind == "part64":     # col 4M; S row_ptrs 4SN; z 8N; S partials written 8SN
-        return 4 * m + (12 * segs + 8) * n
-    if kind == "part32":     # col 4M; S row_ptrs 4SN; ze 4N; S FP32 partials 4SN
-        return 4 * m + (8 * segs + 4) * n
+    if kind == "part64":     # follower ids 4M; per segment and row: row id 4 + length 1
+        return 4 * m + (13 * segs + 8) * n  # + partial 8; z 8N
+    if kind == "part32":     # the same with FP32 partials and gathered ze
+        return 4 * m + (9 * segs + 4) * n
     if kind == "step64_w":   # col 4M + val 8M; row_ptr 4, s 8, c 8, s_new 8
         return 12 * m + 28 * n
     if kind == "step32":     # col 4M; row_ptr 4, ze 4, r 4, mu 4, invden 4, e_old 4, e_new 4, ze_new 4
@@ -234,7 +234,7 @@ def run_single(args, name):
     mixed = head_prec == "mixed"
     if segs > 1:
         kind = "part32" if mixed else "part64"
-        kernel = f"k_pass_seg<{info['tile_items'] // 256}, {5 if mixed else 4}>"
+        kernel = f"k_slices<{5 if mixed else 4}>"
         pass_ms[kind] = op.pass_time(kind, reps=50, tile_items=info["tile_items"],
                                      col_segments=segs)
     else:

@@ -324,7 +324,7 @@ psi_status solve_anderson(psi_operator* op, const psi_params* prm, int depth, co
   psi_status s = ensure_schedule(op, tile, st);
   if (s != PSI_OK) return s;
   if (S > 1) {
-    s = ensure_segments(op, S, tile, st);
+    s = ensure_segments(op, S, st);
     if (s != PSI_OK) return s;
   }
   auto pass = [&](PassMode mode, const PassArgs& a) {

@@ -399,6 +399,190 @@ __global__ void k_seg_scatter(const int* row_ptr, const int* col, int64_t n, int
   (void)seg;
 }
 
+// ---------------------------------------------------------------- sliced layout
+// One workgroup per window of kSliceWindow rows of one segment; each thread
+// owns kSliceWindow / kBlock consecutive rows.
+constexpr int kSliceRowsPerThread = kSliceWindow / kBlock;
+static_assert(kSliceWindow % kBlock == 0, "window rows must split evenly over the threads");
+
+struct SliceLds {
+  int cnt[kSliceShort + 1][kBlock];  // per thread, rows of each length; then their ranks
+  int total[kSliceShort + 1];
+  int base[kSliceShort + 1];         // first rank of each length (longest first)
+  int steps[kSliceWindow / 64];      // steps of each short slice
+  int64_t soff[kSliceWindow / 64 + 1];
+  int chunk0[kBlock];                // per thread, first chunk / slot of its long rows
+  int slot0[kBlock];
+  int n_short, n_short_slices, n_chunks, n_slots;
+};
+
+struct SegOffsets {
+  int64_t off[8];  // first edge of each segment in seg_col
+};
+
+// Counts of one window: short rows by length, chunks and slots of long rows;
+// thread 0 then derives the short slices and their interleaved entries.
+__device__ void plan_window(const int* rp, int64_t w0, int64_t w1, SliceLds& L) {
+  const int t = threadIdx.x;
+  for (int b = 0; b <= kSliceShort; ++b) L.cnt[b][t] = 0;
+  const int64_t r0 = w0 + int64_t(t) * kSliceRowsPerThread;
+  const int64_t r1 = r0 + kSliceRowsPerThread < w1 ? r0 + kSliceRowsPerThread : w1;
+  int chunks = 0, slots = 0;
+  for (int64_t r = r0; r < r1; ++r) {
+    const int len = rp[r + 1] - rp[r];
+    if (len <= kSliceShort) {
+      L.cnt[len][t] += 1;
+    } else {
+      const int c = (len + kSliceChunk - 1) / kSliceChunk;
+      chunks += c;
+      if (c > 1) slots += c;
+    }
+  }
+  L.chunk0[t] = chunks;
+  L.slot0[t] = slots;
+  __syncthreads();
+  // exclusive scan over threads of each length's counts (thread b: length b)
+  if (t <= kSliceShort) {
+    int acc = 0;
+    for (int u = 0; u < kBlock; ++u) {
+      const int v = L.cnt[t][u];
+      L.cnt[t][u] = acc;
+      acc += v;
+    }
+    L.total[t] = acc;
+  }
+  if (t == kBlock - 1) {
+    int ac = 0, as = 0;
+    for (int u = 0; u < kBlock; ++u) {
+      const int c = L.chunk0[u], sl = L.slot0[u];
+      L.chunk0[u] = ac;
+      L.slot0[u] = as;
+      ac += c;
+      as += sl;
+    }
+    L.n_chunks = ac;
+    L.n_slots = as;
+  }
+  __syncthreads();
+  if (t == 0) {
+    int acc = 0;
+    for (int b = kSliceShort; b >= 0; --b) {
+      L.base[b] = acc;
+      acc += L.total[b];
+    }
+    L.n_short = acc;
+    const int ns = (acc + 63) / 64;
+    L.n_short_slices = ns;
+    // a slice's steps are the length of its first (longest) row, rank 64·j
+    int j = 0, cum = 0;
+    for (int b = kSliceShort; b >= 0 && j < ns; --b) {
+      while (j < ns && 64 * j < cum + L.total[b]) L.steps[j++] = b;
+      cum += L.total[b];
+    }
+    int64_t o = 0;
+    for (j = 0; j < ns; ++j) {
+      L.soff[j] = o;
+      o += 64 * int64_t(L.steps[j]);
+    }
+    L.soff[ns] = o;
+  }
+  __syncthreads();
+}
+
+// plan[k * stride + window] for k = 0 slices, 1 short slices, 2 interleaved
+// entries, 3 chunks, 4 slots (entry `windows` of each row is set to 0 for the
+// exclusive scan that follows).
+__global__ __launch_bounds__(kBlock) void k_slice_plan(const int* seg_row_ptr, int64_t n,
+                                                       int64_t nw, int64_t windows,
+                                                       uint32_t* plan) {
+  __shared__ SliceLds L;
+  const int64_t b = blockIdx.x;
+  const int64_t s = b / nw, w = b % nw;
+  const int* rp = seg_row_ptr + s * (n + 1);
+  const int64_t w0 = w * kSliceWindow;
+  const int64_t w1 = w0 + kSliceWindow < n ? w0 + kSliceWindow : n;
+  plan_window(rp, w0, w1, L);
+  if (threadIdx.x == 0) {
+    const int64_t stride = windows + 1;
+    plan[0 * stride + b] = uint32_t(L.n_short_slices + L.n_chunks);
+    plan[1 * stride + b] = uint32_t(L.n_short_slices);
+    plan[2 * stride + b] = uint32_t(L.soff[L.n_short_slices]);
+    plan[3 * stride + b] = uint32_t(L.n_chunks);
+    plan[4 * stride + b] = uint32_t(L.n_slots);
+    if (b == 0)
+      for (int k = 0; k < 5; ++k) plan[k * stride + windows] = 0;
+  }
+}
+
+// Writes the window's slices from the scanned plan: short slices first (rows
+// ranked by length, longest first, ties by row), then the chunks of its long
+// rows in row order.
+__global__ __launch_bounds__(kBlock) void k_slice_fill(const int* seg_row_ptr, const int* seg_col,
+                                                       SegOffsets so, int64_t n, int64_t nw,
+                                                       int64_t windows, const uint32_t* plan,
+                                                       SliceDesc* desc, int* lane_row,
+                                                       unsigned char* lane_len, int* scol,
+                                                       int4* chunk) {
+  __shared__ SliceLds L;
+  const int t = threadIdx.x;
+  const int64_t b = blockIdx.x;
+  const int64_t s = b / nw, w = b % nw;
+  const int* rp = seg_row_ptr + s * (n + 1);
+  const int64_t w0 = w * kSliceWindow;
+  const int64_t w1 = w0 + kSliceWindow < n ? w0 + kSliceWindow : n;
+  plan_window(rp, w0, w1, L);
+  const int64_t stride = windows + 1;
+  const int64_t q0 = plan[0 * stride + b];              // first slice of the window
+  const int64_t lane0 = 64 * int64_t(plan[1 * stride + b]);  // first lane slot
+  const int64_t e0 = plan[2 * stride + b];              // first interleaved entry
+  const int64_t c0 = plan[3 * stride + b];              // first chunk
+  const int64_t p0 = plan[4 * stride + b];              // first slot
+  const int ns = L.n_short_slices;
+  for (int j = t; j < ns; j += kBlock) {
+    SliceDesc d;
+    d.off = e0 + L.soff[j];
+    d.len = L.steps[j];
+    d.tag = int(lane0 + 64 * int64_t(j));
+    desc[q0 + j] = d;
+  }
+  const int* col = seg_col + so.off[s];
+  const int64_t r0 = w0 + int64_t(t) * kSliceRowsPerThread;
+  const int64_t r1 = r0 + kSliceRowsPerThread < w1 ? r0 + kSliceRowsPerThread : w1;
+  int ch = L.chunk0[t], sl = L.slot0[t];
+  for (int64_t r = r0; r < r1; ++r) {
+    const int beg = rp[r], len = rp[r + 1] - beg;
+    if (len <= kSliceShort) {
+      const int rank = L.base[len] + L.cnt[len][t]++;
+      const int j = rank >> 6, lane = rank & 63;
+      lane_row[lane0 + rank] = int(r);
+      lane_len[lane0 + rank] = static_cast<unsigned char>(len);
+      int* dst = scol + e0 + L.soff[j] + lane;
+      for (int k = 0; k < L.steps[j]; ++k) dst[int64_t(k) * 64] = k < len ? col[beg + k] : 0;
+    } else {
+      const int nc = (len + kSliceChunk - 1) / kSliceChunk;
+      const int first = nc > 1 ? int(p0 + sl) : -1;
+      for (int i = 0; i < nc; ++i) {
+        SliceDesc d;
+        d.off = so.off[s] + beg + int64_t(i) * kSliceChunk;
+        d.len = len - i * kSliceChunk < kSliceChunk ? len - i * kSliceChunk : kSliceChunk;
+        d.tag = -1 - int(c0 + ch);
+        desc[q0 + ns + ch] = d;
+        chunk[c0 + ch] = make_int4(int(r), nc > 1 ? first + i : -1, first, nc);
+        ++ch;
+      }
+      if (nc > 1) sl += nc;
+    }
+  }
+  // lane slots past the last short row: no row, padding entries
+  for (int rank = L.n_short + t; rank < 64 * ns; rank += kBlock) {
+    const int j = rank >> 6, lane = rank & 63;
+    lane_row[lane0 + rank] = -1;
+    lane_len[lane0 + rank] = 0;
+    int* dst = scol + e0 + L.soff[j] + lane;
+    for (int k = 0; k < L.steps[j]; ++k) dst[int64_t(k) * 64] = 0;
+  }
+}
+
 inline unsigned grid_for(int64_t n, int block = kBlock) {
   return unsigned((n + block - 1) / block);
 }
@@ -508,13 +692,30 @@ static void layout_persistent(int64_t n, int64_t m_raw, int n_graphs, uint32_t f
   char* hist = take(8 * size_t(kHistLen));
   char* scal = take(8 * 8);
   char* goff = take(8 * size_t(n_graphs + 1));
-  const int64_t max_seg_tiles = (8 * n + m_raw) / kMinTileItems + 16;
-  char* seg_col = take(4 * size_t(m_raw));
-  char* seg_row_ptr = take(4 * size_t(8 * (n + 1)));
-  char* seg_tile_row = take(4 * size_t(max_seg_tiles + 8));
-  char* seg_part_open = take(8 * size_t(max_seg_tiles));
-  char* seg_y = take(8 * size_t(8 * n));
-  char* seg_scan_tmp = take(4 * size_t((n + 1) / 4096 + 8));
+  // column segments (S <= 8) and their sliced layout; a block-diagonal
+  // operator has no segmented form
+  const bool segs = n_graphs == 1;
+  const int64_t nw = (n + kSliceWindow - 1) / kSliceWindow;
+  // short slices of a window: ceil(rows / 64); interleaved entries: its short
+  // rows' edges plus at most 64·kSliceShort of padding (lengths fall from
+  // slice to slice); chunks: at most one per long row plus one per kSliceChunk
+  // edges, and a long row has more than kSliceShort edges
+  const int64_t cap_chunks = segs ? m_raw / (kSliceShort + 1) + m_raw / kSliceChunk + 8 : 0;
+  const int64_t cap_slices = segs ? 8 * (n / 64 + nw + 1) + cap_chunks : 0;
+  const int64_t cap_lanes = segs ? 8 * (n + 64 * nw) : 0;
+  const int64_t cap_entries = segs ? m_raw + 8 * nw * int64_t(kSliceChunk) : 0;
+  char* seg_col = take(4 * size_t(segs ? m_raw : 0));
+  char* seg_row_ptr = take(4 * size_t(segs ? 8 * (n + 1) : 0));
+  char* seg_y = take(8 * size_t(segs ? 8 * n : 0));
+  char* seg_scan_tmp = take(4 * size_t((8 * nw + n + 1) / 4096 + 16));
+  char* slice_desc = take(sizeof(SliceDesc) * size_t(cap_slices));
+  char* slice_row = take(4 * size_t(cap_lanes));
+  char* slice_len = take(size_t(cap_lanes));
+  char* slice_col = take(4 * size_t(cap_entries));
+  char* slice_chunk = take(16 * size_t(cap_chunks));
+  char* slice_part = take(8 * size_t(cap_chunks));
+  char* slice_ticket = take(4 * size_t(cap_chunks));
+  char* slice_plan = take(4 * size_t(segs ? 5 * (8 * nw + 1) : 0));
   const int64_t mp_max_hubs = m_raw / (kMpHubEdges + 1) + 1;
   const int64_t mp_max_chunks = m_raw / kMpChunkEdges + mp_max_hubs + 1;
   char* mp[2][3];
@@ -566,11 +767,20 @@ static void layout_persistent(int64_t n, int64_t m_raw, int n_graphs, uint32_t f
   op->graph_off = (int64_t*)goff;
   op->seg_col = (int*)seg_col;
   op->seg_row_ptr = (int*)seg_row_ptr;
-  op->seg_tile_row = (int*)seg_tile_row;
-  op->seg_part_open = (double*)seg_part_open;
   op->seg_y = (double*)seg_y;
   op->seg_scan_tmp = (uint32_t*)seg_scan_tmp;
-  op->max_seg_tiles = max_seg_tiles;
+  op->slice_desc = (SliceDesc*)slice_desc;
+  op->slice_row = (int*)slice_row;
+  op->slice_len = (unsigned char*)slice_len;
+  op->slice_col = (int*)slice_col;
+  op->slice_chunk = (int4*)slice_chunk;
+  op->slice_part = (double*)slice_part;
+  op->slice_ticket = (unsigned*)slice_ticket;
+  op->slice_plan = (uint32_t*)slice_plan;
+  op->cap_slices = cap_slices;
+  op->cap_lanes = cap_lanes;
+  op->cap_entries = cap_entries;
+  op->cap_chunks = cap_chunks;
   op->mp_max_hubs = mp_max_hubs;
   op->mp_max_chunks = mp_max_chunks;
   for (int o = 0; o < 2; ++o) {
@@ -639,8 +849,6 @@ psi_status build_operator(psi_operator* op, const int32_t* follower, const int32
                      reinterpret_cast<uint64_t*>(op->gap_grp), int64_t(2 * kMaxGrid / 64),
                      kEmptySlot);
   PSI_HIP_CHECK(hipMemsetAsync(op->grp_ticket, 0, 4 * size_t(kMaxGrid / 64), st));
-  hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(op->max_seg_tiles)), dim3(kBlock), 0, st,
-                     reinterpret_cast<uint64_t*>(op->seg_part_open), op->max_seg_tiles, kEmptySlot);
   op->seg_S = 0;
   if (op->n_graphs > 1)
     PSI_HIP_CHECK(hipMemcpyAsync(op->graph_off, node_offsets, 8 * size_t(op->n_graphs + 1),
@@ -790,74 +998,90 @@ psi_status ensure_schedule(psi_operator* op, int tile_items, hipStream_t st) {
   return PSI_OK;
 }
 
-psi_status ensure_segments(psi_operator* op, int S, int tile_items, hipStream_t st) {
+psi_status ensure_segments(psi_operator* op, int S, hipStream_t st) {
   PSI_REQUIRE(S == 2 || S == 4 || S == 8, "col_segments must be 1, 2, 4 or 8");
-  PSI_REQUIRE(tile_items_supported(tile_items), "unsupported tile_items");
   PSI_REQUIRE(op->n_graphs == 1, "column segments need a single-graph operator");
+  if (op->seg_S == S) return PSI_OK;
   const int64_t n = op->n;
   const int64_t seg = (n + S - 1) / S;
-  if (op->seg_S != S) {
-    if (op->m > 0) {
-      hipLaunchKernelGGL(k_seg_count, dim3(grid_for(n)), dim3(kBlock), 0, st, op->row_ptr,
-                         op->col, n, S, seg, op->seg_row_ptr);
-    } else {
-      hipLaunchKernelGGL(k_fill_int, dim3(grid_for(int64_t(S) * (n + 1))), dim3(kBlock), 0, st,
-                         op->seg_row_ptr, int64_t(S) * (n + 1), 0);
-    }
-    // exclusive scan of each segment's counts (entry n receives the total)
-    SortBufs sb{};
-    sb.tile_sums = op->seg_scan_tmp;
-    sb.total = op->seg_scan_tmp + ((n + 1) / 4096 + 4);
-    std::vector<uint32_t> totals(S);
-    for (int s = 0; s < S; ++s) {
-      uint32_t* rp = reinterpret_cast<uint32_t*>(op->seg_row_ptr + int64_t(s) * (n + 1));
-      PSI_HIP_CHECK(hipMemsetAsync(rp + n, 0, 4, st));
-      psi_status r = scan_u32(rp, rp, n + 1, sb, st);
-      if (r != PSI_OK) return r;
-      PSI_HIP_CHECK(hipMemcpyAsync(&totals[s], rp + n, 4, hipMemcpyDeviceToHost, st));
-    }
-    PSI_HIP_CHECK(hipStreamSynchronize(st));
-    std::vector<int64_t> off(S + 1, 0);
-    for (int s = 0; s < S; ++s) off[s + 1] = off[s] + totals[s];
-    if (off[S] != op->m) {
-      set_error("column segmentation lost edges");
-      return PSI_EDEVICE;
-    }
-    int64_t* doff = reinterpret_cast<int64_t*>(op->scal);  // 8 values of scratch
-    PSI_HIP_CHECK(hipMemcpyAsync(doff, off.data(), 8 * size_t(S), hipMemcpyHostToDevice, st));
-    if (op->m > 0)
-      hipLaunchKernelGGL(k_seg_scatter, dim3(grid_for(n * 64)), dim3(kBlock), 0, st, op->row_ptr,
-                         op->col, n, S, seg, op->seg_row_ptr, doff, op->seg_col);
-    PSI_HIP_CHECK(hipGetLastError());
-    PSI_HIP_CHECK(hipStreamSynchronize(st));
-    for (int s = 0; s < S; ++s) {
-      op->seg[s].row_ptr = op->seg_row_ptr + int64_t(s) * (n + 1);
-      op->seg[s].col = op->seg_col + off[s];
-      op->seg[s].n_nnz = static_cast<int>(totals[s]);
-    }
-    op->seg_S = S;
-    op->seg_items = 0;
+  if (op->m > 0) {
+    hipLaunchKernelGGL(k_seg_count, dim3(grid_for(n)), dim3(kBlock), 0, st, op->row_ptr, op->col,
+                       n, S, seg, op->seg_row_ptr);
+  } else {
+    hipLaunchKernelGGL(k_fill_int, dim3(grid_for(int64_t(S) * (n + 1))), dim3(kBlock), 0, st,
+                       op->seg_row_ptr, int64_t(S) * (n + 1), 0);
   }
-  if (op->seg_items != tile_items) {
-    int64_t tile_off = 0;
-    for (int s = 0; s < S; ++s) {
-      const int64_t total = n + op->seg[s].n_nnz;
-      const int64_t nt = std::max<int64_t>((total + tile_items - 1) / tile_items, 1);
-      if (tile_off + nt + 1 > op->max_seg_tiles + 8) {
-        set_error("segment schedules do not fit the workspace");
-        return PSI_ENOSPACE;
-      }
-      hipLaunchKernelGGL(k_schedule, dim3(grid_for(nt + 1)), dim3(kBlock), 0, st,
-                         op->seg[s].row_ptr, n, int64_t(op->seg[s].n_nnz), int64_t(tile_items), nt,
-                         op->seg_tile_row + tile_off);
-      op->seg[s].tile_row = op->seg_tile_row + tile_off;
-      op->seg[s].part_open = op->seg_part_open + (tile_off - s);
-      op->seg[s].n_tiles = static_cast<int>(nt);
-      tile_off += nt + 1;
-    }
-    PSI_HIP_CHECK(hipGetLastError());
-    op->seg_items = tile_items;
+  // exclusive scan of each segment's counts (entry n receives the total)
+  SortBufs sb{};
+  sb.tile_sums = op->seg_scan_tmp;
+  sb.total = op->seg_scan_tmp + ((8 * ((n + kSliceWindow - 1) / kSliceWindow) + n + 1) / 4096 + 8);
+  std::vector<uint32_t> totals(S);
+  for (int s = 0; s < S; ++s) {
+    uint32_t* rp = reinterpret_cast<uint32_t*>(op->seg_row_ptr + int64_t(s) * (n + 1));
+    PSI_HIP_CHECK(hipMemsetAsync(rp + n, 0, 4, st));
+    psi_status r = scan_u32(rp, rp, n + 1, sb, st);
+    if (r != PSI_OK) return r;
+    PSI_HIP_CHECK(hipMemcpyAsync(&totals[s], rp + n, 4, hipMemcpyDeviceToHost, st));
   }
+  PSI_HIP_CHECK(hipStreamSynchronize(st));
+  std::vector<int64_t> off(S + 1, 0);
+  for (int s = 0; s < S; ++s) off[s + 1] = off[s] + totals[s];
+  if (off[S] != op->m) {
+    set_error("column segmentation lost edges");
+    return PSI_EDEVICE;
+  }
+  SegOffsets so{};
+  for (int s = 0; s < S; ++s) so.off[s] = off[s];
+  int64_t* doff = reinterpret_cast<int64_t*>(op->scal);  // 8 values of scratch
+  PSI_HIP_CHECK(hipMemcpyAsync(doff, off.data(), 8 * size_t(S), hipMemcpyHostToDevice, st));
+  if (op->m > 0)
+    hipLaunchKernelGGL(k_seg_scatter, dim3(grid_for(n * 64)), dim3(kBlock), 0, st, op->row_ptr,
+                       op->col, n, S, seg, op->seg_row_ptr, doff, op->seg_col);
+  PSI_HIP_CHECK(hipGetLastError());
+  for (int s = 0; s < S; ++s) {
+    op->seg[s].row_ptr = op->seg_row_ptr + int64_t(s) * (n + 1);
+    op->seg[s].col = op->seg_col + off[s];
+    op->seg[s].n_nnz = static_cast<int>(totals[s]);
+  }
+
+  // sliced layout: per-window counts, their exclusive scans, then the fill
+  const int64_t nw = (n + kSliceWindow - 1) / kSliceWindow;
+  const int64_t windows = int64_t(S) * nw;
+  uint32_t* plan = op->slice_plan;
+  hipLaunchKernelGGL(k_slice_plan, dim3(unsigned(windows)), dim3(kBlock), 0, st, op->seg_row_ptr,
+                     n, nw, windows, plan);
+  PSI_HIP_CHECK(hipGetLastError());
+  for (int k = 0; k < 5; ++k) {
+    uint32_t* row = plan + int64_t(k) * (windows + 1);
+    psi_status r = scan_u32(row, row, windows + 1, sb, st);
+    if (r != PSI_OK) return r;
+  }
+  // totals, and the first slice of each segment
+  std::vector<uint32_t> tot(5), first(S + 1);
+  for (int k = 0; k < 5; ++k)
+    PSI_HIP_CHECK(hipMemcpyAsync(&tot[k], plan + int64_t(k) * (windows + 1) + windows, 4,
+                                 hipMemcpyDeviceToHost, st));
+  for (int s = 0; s <= S; ++s)
+    PSI_HIP_CHECK(hipMemcpyAsync(&first[s], plan + int64_t(s) * nw, 4, hipMemcpyDeviceToHost, st));
+  PSI_HIP_CHECK(hipStreamSynchronize(st));
+  if (int64_t(tot[0]) > op->cap_slices || 64 * int64_t(tot[1]) > op->cap_lanes ||
+      int64_t(tot[2]) > op->cap_entries || int64_t(tot[3]) > op->cap_chunks ||
+      int64_t(tot[4]) > op->cap_chunks) {
+    set_error("sliced layout exceeds its workspace");
+    return PSI_ENOSPACE;
+  }
+  if (tot[4] > 0) {
+    hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(tot[4])), dim3(kBlock), 0, st,
+                       reinterpret_cast<uint64_t*>(op->slice_part), int64_t(tot[4]), kEmptySlot);
+    hipLaunchKernelGGL(k_fill_int, dim3(grid_for(tot[4])), dim3(kBlock), 0, st,
+                       reinterpret_cast<int*>(op->slice_ticket), int64_t(tot[4]), 0);
+  }
+  hipLaunchKernelGGL(k_slice_fill, dim3(unsigned(windows)), dim3(kBlock), 0, st, op->seg_row_ptr,
+                     op->seg_col, so, n, nw, windows, plan, op->slice_desc, op->slice_row,
+                     op->slice_len, op->slice_col, op->slice_chunk);
+  PSI_HIP_CHECK(hipGetLastError());
+  for (int s = 0; s <= S; ++s) op->seg_slice0[s] = int(first[s]);
+  op->seg_S = S;
   return PSI_OK;
 }
 

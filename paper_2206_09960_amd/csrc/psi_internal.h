@@ -157,16 +157,53 @@ enum PassMode : int {
 struct SegInfo {
   const int* row_ptr;   // [n_rows + 1], offsets into col (0-based per segment)
   const int* col;       // global follower ids
-  const int* tile_row;  // merge-path schedule of this segment [n_tiles + 1]
-  double* part_open;    // cross-tile slots [n_tiles]
   void* y;              // partial result [n_rows]
   int n_nnz;
-  int n_tiles;
 };
 
 struct SegArgs {
   SegInfo seg[8];
   int S;
+};
+
+// Sliced form of a column segment, the layout its partial pass walks.  Rows
+// are taken in windows of kSliceWindow; inside a window the rows with at most
+// kSliceShort followers in the segment are ordered by length (longest first,
+// ties by row) and packed 64 to a slice, one row per lane, their follower ids
+// interleaved so that step k of all 64 lanes is one contiguous 256-byte run.
+// Longer rows are cut into chunks of kSliceChunk edges, each summed by a whole
+// wave; a row of several chunks is finished by the last of its chunks, which
+// adds the chunk partials in chunk order.
+constexpr int kSliceWindow = 4096;
+constexpr int kSliceShort = 32;
+constexpr int kSliceChunk = 64 * kSliceShort;
+
+struct SliceDesc {
+  int64_t off;  // short slice: first entry in slice_col; chunk: first edge in seg_col
+  int len;      // short slice: steps (its longest row); chunk: edges
+  int tag;      // >= 0: short slice, lane data at slice_row/slice_len[tag + lane];
+                // < 0: chunk -1 - tag of slice_chunk
+};
+
+struct SliceSeg {
+  const SliceDesc* slices;  // this segment's slices
+  int n_slices;
+  void* y;                  // partial result [n_rows]
+};
+
+struct SliceArgs {
+  SliceSeg seg[8];
+  int S;
+  int respect_done;
+  const void* x;              // gathered vector (FP64 or FP32)
+  const int* row;             // [lane slots] row of each lane, -1 if none
+  const unsigned char* len;   // [lane slots] followers of that row
+  const int* col;             // interleaved follower ids of the short slices
+  const int* seg_col;         // CSR of all segments (chunks index it)
+  const int4* chunk;          // {row, slot or -1, first slot of the row, chunks of the row}
+  double* part;               // chunk partials (slots, empty = kEmptySlot)
+  unsigned* ticket;           // arrivals per multi-chunk row, indexed by its first slot
+  Ctrl* ctrl;
 };
 
 }  // namespace psi
@@ -207,10 +244,11 @@ struct psi_operator {
   double* scal = nullptr;  // small FP64 device scratch (8 values)
   int64_t* graph_off = nullptr;  // device copy of node_offsets [n_graphs + 1]
   std::vector<int64_t> node_offsets;
-  // column-segmented form of CSR(Aᵀ) (built on first use for a given S)
+  // column-segmented form of CSR(Aᵀ) and its sliced layout (built on first
+  // use for a given S)
   int seg_S = 0;            // segments currently built (0 = none)
-  int seg_items = 0;        // tile size of their schedules
   psi::SegInfo seg[8]{};
+  int seg_slice0[9]{};      // first slice of each segment in slice_desc
   // hub schedule of the message-passing aggregation, one per orientation
   // (0: CSR(Aᵀ), 1: CSR(A)); built on first use
   psi::MpHubs mp_hubs[2]{};
@@ -222,11 +260,18 @@ struct psi_operator {
   int tuned_S[4]{};
   int* seg_col = nullptr;       // [m]
   int* seg_row_ptr = nullptr;   // [8 * (n + 1)]
-  int* seg_tile_row = nullptr;  // [max_seg_tiles + 8]
-  double* seg_part_open = nullptr;  // [max_seg_tiles]
   double* seg_y = nullptr;      // [8 * n]
   uint32_t* seg_scan_tmp = nullptr;
-  int64_t max_seg_tiles = 0;
+  // sliced layout of the segments, sized for S = 8 (capacities below)
+  psi::SliceDesc* slice_desc = nullptr;
+  int* slice_row = nullptr;
+  unsigned char* slice_len = nullptr;
+  int* slice_col = nullptr;
+  int4* slice_chunk = nullptr;
+  double* slice_part = nullptr;
+  unsigned* slice_ticket = nullptr;
+  uint32_t* slice_plan = nullptr;  // per-window counts and their scans [5 * (8 * windows + 1)]
+  int64_t cap_slices = 0, cap_lanes = 0, cap_entries = 0, cap_chunks = 0;
 };
 
 namespace psi {
@@ -243,8 +288,8 @@ psi_status build_operator(psi_operator* op, const int32_t* follower, const int32
                           char* scratch, size_t scratch_bytes, hipStream_t stream);
 
 psi_status ensure_schedule(psi_operator* op, int tile_items, hipStream_t stream);
-// Build (or keep) the S-segment form of CSR(Aᵀ) with tiles of tile_items.
-psi_status ensure_segments(psi_operator* op, int S, int tile_items, hipStream_t stream);
+// Build (or keep) the S-segment form of CSR(Aᵀ) and its sliced layout.
+psi_status ensure_segments(psi_operator* op, int S, hipStream_t stream);
 bool tile_items_supported(int t);
 psi_status launch_pass(psi_operator* op, PassMode mode, const PassArgs& a, hipStream_t stream);
 psi_status launch_pass_seg(psi_operator* op, PassMode mode, const PassArgs& a, hipStream_t stream);

@@ -25,12 +25,20 @@
 // Column-segmented passes (S = 2, 4, 8).  The gather of x is limited by the
 // rate at which the caches serve random lines, and that rate roughly doubles
 // when the gathered range fits one XCD's L2.  Workgroups are dispatched to
-// the 8 XCDs round-robin, so the XCDs with xcd % S == s run the tiles of
-// column segment s (followers in [s·N/S, (s+1)·N/S)) and write a partial
-// y_s; a streaming combine kernel then adds the S partials in segment order
-// and applies the epilogue and the gap.
+// the 8 XCDs round-robin, so the XCDs with xcd % S == s work on column
+// segment s (followers in [s·N/S, (s+1)·N/S)) and write a partial y_s; a
+// streaming combine kernel then adds the S partials in segment order and
+// applies the epilogue and the gap.  The partial pass walks the segment's
+// sliced layout rather than merge-path tiles: one wave per slice, one lane
+// per short row summing its followers in CSR order, so a wave issues nothing
+// but coalesced index loads, gathers and one store per row, with no LDS and
+// no barrier.  Rows too long for a lane are cut into chunks summed by whole
+// waves; the last chunk of a row to finish adds the chunk partials in chunk
+// order.  Every row's sum has a fixed order, so passes stay bitwise
+// repeatable.
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "psi_internal.h"
 
@@ -95,7 +103,7 @@ struct TileSrc {
 
 template <int MODE>
 __device__ inline double gather(const PassArgs& a, int j, int e) {
-  if constexpr (MODE == kStep32 || MODE == kPart32) {
+  if constexpr (MODE == kStep32) {
     return static_cast<double>(static_cast<const float*>(a.x)[j]);
   } else if constexpr (MODE == kStep64W) {
     return static_cast<const double*>(a.x)[j] * __builtin_nontemporal_load(a.val64 + e);
@@ -183,10 +191,6 @@ __device__ inline void apply_row(const PassArgs& a, void* yout, int r, const Row
     a.ze_new[r] = static_cast<float>(in.a2) * en;
     g += fabs(static_cast<double>(en) - in.a3);
     s += fabs(static_cast<double>(en));
-  } else if constexpr (MODE == kPart64) {
-    static_cast<double*>(yout)[r] = y;
-  } else {
-    static_cast<float*>(yout)[r] = static_cast<float>(y);
   }
 }
 
@@ -540,20 +544,104 @@ __global__ __launch_bounds__(kBlock) void k_pass(PassArgs a) {
   if constexpr (MODE != kFinal64 && MODE != kFinal64G) finalize_gap(a, g, sn, L.red, &L.last);
 }
 
-// Partial pass of one column segment per XCD group: y_s = A_sᵀ x.
-template <int IPT, int MODE>
-__global__ __launch_bounds__(kBlock) void k_pass_seg(PassArgs a, SegArgs sg) {
-  __shared__ TileLds<IPT> L;
+// Partial pass over the sliced layout of the segments: y_s = A_sᵀ x.  XCD
+// group s (workgroups with (blockIdx mod 8) mod S = s) takes the slices of
+// segment s, four per workgroup, one per wave.
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_slices(SliceArgs a) {
   if (a.respect_done && a.ctrl->done) return;
+  using XT = typename std::conditional<MODE == kPart32, float, double>::type;
   const int xcd = blockIdx.x & 7;
-  const int group = xcd % sg.S;
-  const int per_round = 8 / sg.S;  // workgroups of a group among 8 consecutive ones
-  const int rank = (blockIdx.x >> 3) * per_round + xcd / sg.S;
-  const int size = (gridDim.x >> 3) * per_round;
-  const SegInfo& si = sg.seg[group];
-  TileSrc src{si.row_ptr, si.col, si.tile_row, si.part_open, si.y, si.n_nnz, si.n_tiles};
-  double g = 0.0, sn = 0.0;
-  run_tiles<IPT, MODE>(a, src, rank, size, L, g, sn);
+  const int group = xcd % a.S;
+  const int per_round = 8 / a.S;  // workgroups of a group among 8 consecutive ones
+  const int rank = (blockIdx.x >> 3) * per_round + xcd / a.S;
+  const int q = rank * (kBlock / 64) + (threadIdx.x >> 6);
+  const SliceSeg& sg = a.seg[group];
+  if (q >= sg.n_slices) return;
+  const int lane = threadIdx.x & 63;
+  const XT* x = static_cast<const XT*>(a.x);
+  const SliceDesc d = sg.slices[q];
+  double acc = 0.0;
+  if (d.tag >= 0) {
+    // one row per lane; step k of the 64 lanes is one contiguous run of ids
+    const int row = a.row[d.tag + lane];
+    const int len = a.len[d.tag + lane];
+    const int* c = a.col + d.off + lane;
+    // every gather of a step is issued before any add; a lane past its row's
+    // end reads a padding id (0, a valid entry) and adds nothing
+    int k = 0;
+    for (; k + 4 <= d.len; k += 4) {
+      const int j0 = c[(k + 0) * 64], j1 = c[(k + 1) * 64], j2 = c[(k + 2) * 64], j3 = c[(k + 3) * 64];
+      const double v0 = static_cast<double>(x[j0]);
+      const double v1 = static_cast<double>(x[j1]);
+      const double v2 = static_cast<double>(x[j2]);
+      const double v3 = static_cast<double>(x[j3]);
+      acc += k + 0 < len ? v0 : 0.0;
+      acc += k + 1 < len ? v1 : 0.0;
+      acc += k + 2 < len ? v2 : 0.0;
+      acc += k + 3 < len ? v3 : 0.0;
+    }
+    if (k < d.len) {
+      const int r = d.len - k;  // 1..3 steps left
+      const int j0 = c[(k + 0) * 64];
+      const int j1 = r > 1 ? c[(k + 1) * 64] : 0;
+      const int j2 = r > 2 ? c[(k + 2) * 64] : 0;
+      const double v0 = static_cast<double>(x[j0]);
+      const double v1 = static_cast<double>(x[j1]);
+      const double v2 = static_cast<double>(x[j2]);
+      acc += k + 0 < len ? v0 : 0.0;
+      acc += k + 1 < len ? v1 : 0.0;
+      acc += k + 2 < len ? v2 : 0.0;
+    }
+    if (row >= 0) static_cast<XT*>(sg.y)[row] = static_cast<XT>(acc);
+    return;
+  }
+  // a chunk of a long row: the wave strides over its edges (clamped loads,
+  // masked adds), then reduces
+  const int4 ch = a.chunk[-1 - d.tag];  // row, slot, first slot of the row, chunks of the row
+  const int* c = a.seg_col + d.off;
+  const int ne = d.len;
+  const int steps = (ne + 63) >> 6;
+  int k = 0;
+  for (; k + 4 <= steps; k += 4) {
+    const int e0 = (k + 0) * 64 + lane, e1 = (k + 1) * 64 + lane;
+    const int e2 = (k + 2) * 64 + lane, e3 = (k + 3) * 64 + lane;
+    const int j0 = c[min(e0, ne - 1)], j1 = c[min(e1, ne - 1)];
+    const int j2 = c[min(e2, ne - 1)], j3 = c[min(e3, ne - 1)];
+    const double v0 = static_cast<double>(x[j0]);
+    const double v1 = static_cast<double>(x[j1]);
+    const double v2 = static_cast<double>(x[j2]);
+    const double v3 = static_cast<double>(x[j3]);
+    acc += e0 < ne ? v0 : 0.0;
+    acc += e1 < ne ? v1 : 0.0;
+    acc += e2 < ne ? v2 : 0.0;
+    acc += e3 < ne ? v3 : 0.0;
+  }
+  for (; k < steps; ++k) {
+    const int e = k * 64 + lane;
+    const double v = static_cast<double>(x[c[min(e, ne - 1)]]);
+    acc += e < ne ? v : 0.0;
+  }
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if (ch.y < 0) {
+    if (lane == 0) static_cast<XT*>(sg.y)[ch.x] = static_cast<XT>(acc);
+    return;
+  }
+  // several chunks: publish this one; the last to arrive sums them in order
+  int last = 0;
+  if (lane == 0) {
+    st_agent(&a.part[ch.y], acc);
+    last = atomicAdd(&a.ticket[ch.z], 1u) == static_cast<unsigned>(ch.w) - 1u;
+  }
+  last = __shfl(last, 0, 64);
+  if (!last) return;
+  double sum = 0.0;
+  for (int i = lane; i < ch.w; i += 64) sum += take_slot(&a.part[ch.z + i], a.ctrl);
+  for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 64);
+  if (lane == 0) {
+    static_cast<XT*>(sg.y)[ch.x] = static_cast<XT>(sum);
+    a.ticket[ch.z] = 0;
+  }
 }
 
 // y_i = Σ_s y_s[i] in segment order, then the epilogue of MODE and the gap.
@@ -627,18 +715,6 @@ psi_status launch_ipt(const PassArgs& a, hipStream_t st) {
   return PSI_OK;
 }
 
-template <int IPT, int PMODE>
-psi_status launch_seg_ipt(const PassArgs& a, const SegArgs& sg, hipStream_t st) {
-  static const int cap = resident_grid(k_pass_seg<IPT, PMODE>);
-  if (cap <= 0) {
-    set_error("could not size the resident grid");
-    return PSI_EDEVICE;
-  }
-  hipLaunchKernelGGL((k_pass_seg<IPT, PMODE>), dim3(cap), dim3(kBlock), 0, st, a, sg);
-  PSI_HIP_CHECK(hipGetLastError());
-  return PSI_OK;
-}
-
 template <int MODE>
 psi_status launch_mode(const PassArgs& a, hipStream_t st) {
   switch (a.tile_items) {
@@ -653,18 +729,36 @@ psi_status launch_mode(const PassArgs& a, hipStream_t st) {
   }
 }
 
-template <int PMODE>
-psi_status launch_seg_mode(const PassArgs& a, const SegArgs& sg, hipStream_t st) {
-  switch (a.tile_items) {
-    case 1024: return launch_seg_ipt<4, PMODE>(a, sg, st);
-    case 1536: return launch_seg_ipt<6, PMODE>(a, sg, st);
-    case 2048: return launch_seg_ipt<8, PMODE>(a, sg, st);
-    case 3072: return launch_seg_ipt<12, PMODE>(a, sg, st);
-    case 4096: return launch_seg_ipt<16, PMODE>(a, sg, st);
-    default:
-      set_error("unsupported tile size " + std::to_string(a.tile_items));
-      return PSI_EINVAL;
+// Grid of the sliced partial pass: workgroups of XCD group s cover the
+// slices of segment s four at a time.
+template <int MODE>
+psi_status launch_slices(psi_operator* op, const PassArgs& a, const SegArgs& sg, hipStream_t st) {
+  SliceArgs sa{};
+  sa.S = sg.S;
+  sa.respect_done = a.respect_done;
+  sa.x = a.x;
+  sa.row = op->slice_row;
+  sa.len = op->slice_len;
+  sa.col = op->slice_col;
+  sa.seg_col = op->seg_col;
+  sa.chunk = op->slice_chunk;
+  sa.part = op->slice_part;
+  sa.ticket = op->slice_ticket;
+  sa.ctrl = a.ctrl;
+  int most = 0;
+  for (int s = 0; s < sg.S; ++s) {
+    sa.seg[s].slices = op->slice_desc + op->seg_slice0[s];
+    sa.seg[s].n_slices = op->seg_slice0[s + 1] - op->seg_slice0[s];
+    sa.seg[s].y = sg.seg[s].y;
+    most = std::max(most, sa.seg[s].n_slices);
   }
+  const int per_round = 8 / sg.S;
+  const int64_t ranks = (int64_t(most) + kBlock / 64 - 1) / (kBlock / 64);
+  const int64_t grid = 8 * std::max<int64_t>(1, (ranks + per_round - 1) / per_round);
+  PSI_REQUIRE(grid <= int64_t(1) << 30, "too many slices for one launch");
+  hipLaunchKernelGGL(k_slices<MODE>, dim3(unsigned(grid)), dim3(kBlock), 0, st, sa);
+  PSI_HIP_CHECK(hipGetLastError());
+  return PSI_OK;
 }
 
 template <int MODE, class YT>
@@ -734,23 +828,21 @@ psi_status launch_pass_seg(psi_operator* op, PassMode mode, const PassArgs& a, h
   SegArgs sg{};
   sg.S = op->seg_S;
   for (int s = 0; s < sg.S; ++s) sg.seg[s] = op->seg[s];
-  PassArgs b = a;
-  b.tile_items = op->seg_items;
   psi_status r = PSI_OK;
   switch (mode) {
     case kStep64:
     case kFinal64:
       for (int s = 0; s < sg.S; ++s) sg.seg[s].y = op->seg_y + size_t(s) * op->n;
-      r = launch_seg_mode<kPart64>(b, sg, st);
+      r = launch_slices<kPart64>(op, a, sg, st);
       if (r != PSI_OK) return r;
-      return mode == kStep64 ? launch_combine<kStep64, double>(b, sg, st)
-                             : launch_combine<kFinal64, double>(b, sg, st);
+      return mode == kStep64 ? launch_combine<kStep64, double>(a, sg, st)
+                             : launch_combine<kFinal64, double>(a, sg, st);
     case kStep32:
       for (int s = 0; s < sg.S; ++s)
         sg.seg[s].y = reinterpret_cast<float*>(op->seg_y) + size_t(s) * op->n;
-      r = launch_seg_mode<kPart32>(b, sg, st);
+      r = launch_slices<kPart32>(op, a, sg, st);
       if (r != PSI_OK) return r;
-      return launch_combine<kStep32, float>(b, sg, st);
+      return launch_combine<kStep32, float>(a, sg, st);
     default: break;
   }
   set_error("this pass has no column-segmented form");
@@ -761,15 +853,13 @@ psi_status launch_part_seg(psi_operator* op, PassMode mode, const PassArgs& a, h
   SegArgs sg{};
   sg.S = op->seg_S;
   for (int s = 0; s < sg.S; ++s) sg.seg[s] = op->seg[s];
-  PassArgs b = a;
-  b.tile_items = op->seg_items;
   if (mode == kStep32) {
     for (int s = 0; s < sg.S; ++s)
       sg.seg[s].y = reinterpret_cast<float*>(op->seg_y) + size_t(s) * op->n;
-    return launch_seg_mode<kPart32>(b, sg, st);
+    return launch_slices<kPart32>(op, a, sg, st);
   }
   for (int s = 0; s < sg.S; ++s) sg.seg[s].y = op->seg_y + size_t(s) * op->n;
-  return launch_seg_mode<kPart64>(b, sg, st);
+  return launch_slices<kPart64>(op, a, sg, st);
 }
 
 }  // namespace psi

@@ -132,7 +132,7 @@ psi_status resolve_segments(const psi_operator* op, int requested, int bytes, in
 psi_status prepare(psi_operator* op, int tile, int S, hipStream_t st) {
   psi_status s = ensure_schedule(op, tile, st);
   if (s != PSI_OK || S <= 1) return s;
-  return ensure_segments(op, S, tile, st);
+  return ensure_segments(op, S, st);
 }
 
 // A pass in the column-segmented form when S > 1 (the weighted form has none).
@@ -637,8 +637,13 @@ psi_status autotune(psi_operator* op, int precision, int reps, int* tile_items, 
   const int n_segs = precision == PSI_PREC_FP64_WEIGHTED ? 1 : 4;
   double best = 0.0;
   int best_tile = 0, best_S = 0;
+  int tile_s1 = 0;  // fastest tile of the unsegmented pass (S = 1 is timed first)
+  double best_s1 = 0.0;
   for (int si = 0; si < n_segs; ++si) {
     for (int tile : kTiles) {
+      // the segmented partial pass walks slices, not tiles: one timing per S,
+      // with the tile kept for the unsegmented passes of a solve
+      if (kSegs[si] > 1 && tile != tile_s1) continue;
       int r = reps;
       if (r == 0) {  // about 20 ms of passes per candidate, at least 3
         double one = 0.0;
@@ -649,6 +654,10 @@ psi_status autotune(psi_operator* op, int precision, int reps, int* tile_items, 
       double ms = 0.0;
       psi_status s = pass_time(op, kind, r, tile, kSegs[si], &ms, st);
       if (s != PSI_OK) return s;
+      if (kSegs[si] == 1 && (tile_s1 == 0 || ms < best_s1)) {
+        best_s1 = ms;
+        tile_s1 = tile;
+      }
       if (best_tile == 0 || ms < best) {
         best = ms;
         best_tile = tile;
