@@ -171,6 +171,69 @@ def test_segmented_solve(gpu_lib, prec, tol, bar, segs):
     assert oracle.rel_l1(r["psi"], psi.cpu().numpy()) <= bar
 
 
+def _graph_with_rows(n, rows, m_background, seed):
+    """Leader r gets the followers [lo, lo + k) for each (r, lo, k) in rows,
+    plus m_background random edges."""
+    rng = np.random.default_rng(seed)
+    bf = rng.integers(0, n, m_background)
+    bl = rng.integers(0, n, m_background)
+    keep = ~np.isin(bl, [r for r, _, _ in rows])  # the listed rows keep their exact lengths
+    f = [np.arange(lo, lo + k) for _, lo, k in rows] + [bf[keep]]
+    l = [np.full(k, r) for r, _, k in rows] + [bl[keep]]
+    lam = np.exp(rng.normal(0.0, 1.0, n))
+    mu = np.exp(rng.normal(0.0, 1.0, n))
+    return synth.Graph(n, np.concatenate(f).astype(np.int32), np.concatenate(l).astype(np.int32),
+                       lam, mu)
+
+
+@pytest.mark.parametrize("segs", [2, 4, 8])
+def test_sliced_layout_row_lengths(gpu_lib, segs):
+    """Rows at every boundary of the sliced layout: 31/32/33 followers in one
+    segment (short row or chunk), one chunk of 2048 and two of 2049, exactly
+    64 chunks, 66 chunks (the last chunk to finish sums more than 64
+    partials), a row that straddles segment boundaries, and a last window of
+    fewer than 4096 rows (N = 1.1e6)."""
+    api = gpu_lib
+    n = 1_100_000
+    rows = [(7, 100, 135_001), (11, 100, 131_072), (13, 1000, 2048), (17, 5000, 2049),
+            (19, 9000, 32), (23, 9100, 33), (29, 9200, 31), (31, 9300, 1),
+            (4095, 20_000, 40), (4096, 21_000, 40), (n - 1, 30_000, 2050),
+            (37, 130_000, 300_000)]
+    g = _graph_with_rows(n, rows, 3 * n, 41)
+    op = gpu_op(api, g)
+    A, B, c, d = oracle.operator(g.n, g.follower, g.leader, g.lam, g.mu)
+    s_in = np.random.default_rng(3).uniform(0.5, 3.0, g.n)
+    expect = A.T @ s_in + c
+    out, gap = op.step(torch.tensor(s_in, device="cuda"), col_segments=segs)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(out.cpu().numpy(), expect, rtol=1e-13, atol=0)
+    for _ in range(2):  # bitwise repeatable, chunk partials summed in chunk order
+        again, _ = op.step(torch.tensor(s_in, device="cuda"), col_segments=segs)
+        torch.cuda.synchronize()
+        assert torch.equal(again, out)
+    psi, info = op.solve(tol=1e-10, col_segments=segs)
+    _, _, _, _, r = oracle_run(g, 1e-10)
+    assert info["status"] == 0 and oracle.rel_l1(r["psi"], psi.cpu().numpy()) <= 1e-9
+
+
+def test_sliced_layout_degenerate(gpu_lib):
+    """N = 5 with 8 segments (three of them hold no column), and an operator
+    with no edges, in every segment count."""
+    api = gpu_lib
+    f = np.array([1, 2, 3, 4, 0, 0], dtype=np.int32)
+    l = np.array([0, 0, 0, 0, 4, 3], dtype=np.int32)
+    lam = np.array([0.5, 1.0, 2.0, 0.7, 1.3])
+    mu = np.array([1.0, 0.5, 0.2, 0.9, 0.4])
+    s_in = np.array([1.0, 2.0, 3.0, 4.0, 5.0])
+    for n, ff, ll in ((5, f, l), (5, f[:0], l[:0])):
+        A, B, c, d = oracle.operator(n, ff, ll, lam, mu)
+        op = api.Operator(n, ff, ll, lam, mu)
+        for segs in (2, 4, 8):
+            out, _ = op.step(torch.tensor(s_in, device="cuda"), col_segments=segs)
+            torch.cuda.synchronize()
+            np.testing.assert_allclose(out.cpu().numpy(), A.T @ s_in + c, rtol=1e-15, atol=0)
+
+
 def test_step_bitwise_repeatable(gpu_lib):
     api = gpu_lib
     g = synth.chung_lu(200000, 20, 2.1, 12, sigma=2.0)
