@@ -230,13 +230,16 @@ def run_single(args, name):
     launch = {"step64": tuned["fp64"], "step64_w": tuned["fp64_weighted"], "step32": tuned["mixed"],
               "final64": tuned["fp64"]}
     pass_ms = {k: op.pass_time(k, reps=50, tile_items=v["tile_items"],
-                               col_segments=v["col_segments"]) for k, v in launch.items()}
+                               col_segments=v["col_segments"], seg_form=v["seg_form"])
+               for k, v in launch.items()}
     mixed = head_prec == "mixed"
     if segs > 1:
         kind = "part32" if mixed else "part64"
-        kernel = f"k_slices<{5 if mixed else 4}>"
+        form = info["seg_form"]
+        kernel = (f"k_slices<{5 if mixed else 4}>" if form == 2 else
+                  f"k_pass_seg<{info['tile_items'] // 256}, {5 if mixed else 4}>")
         pass_ms[kind] = op.pass_time(kind, reps=50, tile_items=info["tile_items"],
-                                     col_segments=segs)
+                                     col_segments=segs, seg_form=form)
     else:
         kind = "step32" if mixed else "step64"
         kernel = f"k_pass<{info['tile_items'] // 256}, {3 if mixed else 0}>"
@@ -276,7 +279,9 @@ def run_single(args, name):
         "config": {"workload": DESCRIPTIONS[name], "name": name,
                    "n_users": g.n, "n_edges": m, "max_followers": st["max_followers"],
                    "tol": tol, "headline_mode": head, "col_segments": info["col_segments"],
-                   "tile_items": info["tile_items"], "parallelism": "single GPU"},
+                   "tile_items": info["tile_items"],
+                   "seg_form": {0: "none", 1: "tiles", 2: "slices"}[info["seg_form"]],
+                   "parallelism": "single GPU"},
         "time_to_psi_ms": {p: round(v["ms"], 4) for p, v in modes.items()},
         "passes": {p: v["info"]["spmv_passes"] for p, v in modes.items()},
         "speedup_vs_plain_fp64": round(modes["fp64_weighted"]["ms"] / ms, 3),
@@ -286,7 +291,8 @@ def run_single(args, name):
         "warm_start": warm,
         "build_ms": round(builds[-1], 2),
         "autotune_ms": round(tune_ms, 1),
-        "autotuned": {p: {k: v[k] for k in ("tile_items", "col_segments")} for p, v in tuned.items()},
+        "autotuned": {p: {k: v[k] for k in ("tile_items", "col_segments", "seg_form")}
+                      for p, v in tuned.items()},
         "mixed_vs_fp64_rel_l1": float(np.abs(modes["mixed"]["psi"] - modes["fp64"]["psi"]).sum()
                                       / np.abs(modes["fp64"]["psi"]).sum()),
     }

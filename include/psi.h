@@ -65,6 +65,20 @@ typedef enum psi_status {
 /* ---- solve flags ---------------------------------------------------------- */
 #define PSI_NO_FALLBACK     0x1u  /* use s0 even if its residual is worse than c's */
 
+/* ---- partial pass of a column-segmented pass (col_segments > 1) ------------
+ * The same sums (each row's followers in CSR order, partials added in segment
+ * order, so both give the same result to rounding) over two layouts of the
+ * segment:
+ *   TILES:  merge-path tiles of tile_items over the segment's CSR; suits a
+ *           gathered vector whose segment share exceeds an XCD's L2;
+ *   SLICES: one lane per row of at most 32 followers (rows ordered by length
+ *           in windows of 4096, 64 to a slice), one wave per 2048-edge chunk
+ *           of a longer row; suits a segment share that fits the L2.
+ * 0 = the tuned form (psi_autotune), else SLICES when N·(8 or 4 bytes)/S is
+ * at most 6 MB and TILES otherwise. */
+#define PSI_SEG_TILES   1
+#define PSI_SEG_SLICES  2
+
 typedef struct psi_operator psi_operator;
 
 typedef struct psi_operator_stats {
@@ -91,6 +105,8 @@ typedef struct psi_params {
     int32_t tile_items;  /* merge-path items per tile; 0 = library default     */
     int32_t col_segments;/* 1, 2, 4 or 8 column segments (one per XCD group);   */
                          /* 0 = chosen from N and the precision                */
+    int32_t seg_form;    /* partial pass of a segmented pass: PSI_SEG_TILES or  */
+                         /* PSI_SEG_SLICES; 0 = tuned, else from N and precision */
     double inner_tol;    /* PSI_PREC_MIXED: relative tol of each FP32 solve; 0 = default */
 } psi_params;
 
@@ -110,6 +126,7 @@ typedef struct psi_info {
     double err_bound_s;       /* κ/(1−κ)·‖s_t − s_{t−1}‖₁ ≥ ‖s − s_t‖₁        */
     double psi_gap_bound;     /* ‖s_t − s_{t−1}‖₁·‖B‖/N ≥ ‖ψ_t − ψ_{t−1}‖₁    */
     double device_ms;         /* time from first to last kernel of the solve  */
+    int32_t seg_form;         /* PSI_SEG_* of the segmented passes, 0 if S = 1 */
 } psi_info;
 
 /* Library version string. */
@@ -183,10 +200,11 @@ psi_status psi_solve(psi_operator* op, const psi_params* prm, const double* s0,
 /* One Power-ψ step (eq. power_psi), enqueued only:
  *   s_out = Aᵀ s_in + c,  *gap_out (device FP64 scalar, may be NULL)
  *   = ‖s_out − s_in‖₁.  precision PSI_PREC_FP64 or PSI_PREC_FP64_WEIGHTED.
- * s_in, s_out: device FP64 [N], distinct.  tile_items and col_segments as in
- * psi_params (0 = default). */
+ * s_in, s_out: device FP64 [N], distinct.  tile_items, col_segments and
+ * seg_form as in psi_params (0 = default). */
 psi_status psi_step(psi_operator* op, int32_t precision, const double* s_in, double* s_out,
-                    double* gap_out, int32_t tile_items, int32_t col_segments, void* stream);
+                    double* gap_out, int32_t tile_items, int32_t col_segments,
+                    int32_t seg_form, void* stream);
 
 /* The last line of Algorithm 2, enqueued only: psi_out = (Bᵀ s + d)/N.
  * s, psi_out: device FP64 [N]. */
@@ -268,9 +286,11 @@ psi_status psi_solve_origins(psi_operator* op, const psi_params* prm, int32_t n_
 /* Time `reps` back-to-back launches of one operator pass (the kernels a solve
  * runs in its loop: with col_segments > 1 the partial pass and the combine),
  * between two hipEvents recorded on `stream`, after one untimed launch.  Writes the mean duration of one launch in milliseconds to
- * *mean_ms (host).  Overwrites the operator's solve state.  Blocks until done. */
+ * *mean_ms (host).  tile_items, col_segments and seg_form as in psi_params.
+ * Overwrites the operator's solve state.  Blocks until done. */
 psi_status psi_pass_time(psi_operator* op, int32_t pass_kind, int32_t reps, int32_t tile_items,
-                         int32_t col_segments, double* mean_ms, void* stream);
+                         int32_t col_segments, int32_t seg_form, double* mean_ms,
+                         void* stream);
 
 /* Random-gather probe: the access pattern of an operator pass without its
  * arithmetic, for the ceiling the pass is held to.  Workgroup b of `grid`
@@ -290,14 +310,16 @@ psi_status psi_gather_probe(const double* x, int64_t n_x, int32_t col_segments,
  * the FP32 correction step for PSI_PREC_MIXED / PSI_PREC_FP32; with the
  * combine kernel when col_segments > 1) for every supported tile_items
  * (1024, 1536, 2048, 3072, 4096) and col_segments (1, 2, 4, 8; 1 only for
- * the weighted form), with hipEvents on `stream`, and keeps the fastest in
- * the operator: later psi_solve calls in that precision whose psi_params
- * leave tile_items / col_segments at 0 use it.  reps = 0 picks about 20 ms
+ * the weighted form), and for col_segments > 1 in both partial-pass forms
+ * (the sliced form once, it has no tiles), with hipEvents on `stream`, and
+ * keeps the fastest in the operator: later psi_solve calls in that precision
+ * whose psi_params leave tile_items / col_segments / seg_form at 0 use it.  reps = 0 picks about 20 ms
  * of passes per candidate (at least 3).  Writes the choice and its mean pass
  * time (ms) to the host pointers, each of which may be NULL.  Overwrites the
  * operator's solve state; blocks.  Single-graph operators only. */
 psi_status psi_autotune(psi_operator* op, int32_t precision, int32_t reps, int32_t* tile_items,
-                        int32_t* col_segments, double* best_ms, void* stream);
+                        int32_t* col_segments, int32_t* seg_form, double* best_ms,
+                        void* stream);
 
 /* ---- learned warm start ---------------------------------------------------
  * An extension of the method (the paper has none): a small message-passing

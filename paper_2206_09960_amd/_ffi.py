@@ -21,6 +21,8 @@ PSI_TOL_ABS_L1, PSI_TOL_BNORM, PSI_TOL_REL_L1 = 0, 1, 2
 PSI_PREC_FP64, PSI_PREC_FP64_WEIGHTED, PSI_PREC_MIXED, PSI_PREC_FP32 = 0, 1, 2, 3
 # solve flags
 PSI_NO_FALLBACK = 0x1
+# partial pass of a column-segmented pass
+PSI_SEG_TILES, PSI_SEG_SLICES = 1, 2
 # pass kinds
 PSI_PASS_STEP64, PSI_PASS_STEP64_W, PSI_PASS_FINAL64, PSI_PASS_STEP32 = 0, 1, 2, 3
 PSI_PASS_PART64, PSI_PASS_PART32 = 4, 5
@@ -38,6 +40,7 @@ class OperatorStats(ctypes.Structure):
 class Params(ctypes.Structure):
     _fields_ = [("tol", f64), ("tol_mode", i32), ("max_iter", i32), ("precision", i32),
                 ("check_every", i32), ("flags", u32), ("tile_items", i32), ("col_segments", i32),
+                ("seg_form", i32),
                 ("inner_tol", f64)]
 
 
@@ -46,7 +49,7 @@ class Info(ctypes.Structure):
                 ("refinements", i32), ("used_s0", i32), ("col_segments", i32),
                 ("tile_items", i32), ("final_gap", f64),
                 ("final_l1_step", f64), ("b_norm", f64), ("kappa", f64), ("err_bound_s", f64),
-                ("psi_gap_bound", f64), ("device_ms", f64)]
+                ("psi_gap_bound", f64), ("device_ms", f64), ("seg_form", i32)]
 
 
 def struct_dict(s: ctypes.Structure) -> dict:
@@ -66,9 +69,9 @@ SIGNATURES = [
                                  ctypes.POINTER(vp), ctypes.POINTER(vp)]),
     ("psi_params_default", i32, [ctypes.POINTER(Params)]),
     ("psi_solve", i32, [vp, ctypes.POINTER(Params), vp, vp, vp, ctypes.POINTER(Info), vp]),
-    ("psi_step", i32, [vp, i32, vp, vp, vp, i32, i32, vp]),
+    ("psi_step", i32, [vp, i32, vp, vp, vp, i32, i32, i32, vp]),
     ("psi_final", i32, [vp, vp, vp, vp]),
-    ("psi_pass_time", i32, [vp, i32, i32, i32, i32, ctypes.POINTER(f64), vp]),
+    ("psi_pass_time", i32, [vp, i32, i32, i32, i32, i32, ctypes.POINTER(f64), vp]),
     ("psi_batched_workspace_size", i32, [vp, i32, ctypes.POINTER(sz)]),
     ("psi_solve_batched", i32, [vp, ctypes.POINTER(Params), i32, vp, vp, vp, ctypes.POINTER(Info),
                                 vp, sz, vp]),
@@ -79,7 +82,7 @@ SIGNATURES = [
     ("psi_solve_origins", i32, [vp, ctypes.POINTER(Params), i32, vp, vp, vp,
                                 ctypes.POINTER(Info), vp, sz, vp]),
     ("psi_autotune", i32, [vp, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
-                           ctypes.POINTER(f64), vp]),
+                           ctypes.POINTER(i32), ctypes.POINTER(f64), vp]),
     ("psi_mpnn_param_count", i64, []),
     ("psi_model_state_size", i32, [ctypes.POINTER(sz)]),
     ("psi_model_create", i32, [vp, i64, u32, vp, sz, vp, ctypes.POINTER(vp)]),

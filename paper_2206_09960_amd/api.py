@@ -19,6 +19,12 @@ from ._ffi import (PSI_INPUT_HOST, PSI_NO_FALLBACK, PSI_PREC_FP32,  # noqa: F401
 PRECISIONS = {"fp64": PSI_PREC_FP64, "fp64_weighted": PSI_PREC_FP64_WEIGHTED,
               "mixed": PSI_PREC_MIXED, "fp32": PSI_PREC_FP32}
 TOL_MODES = {"abs_l1": PSI_TOL_ABS_L1, "bnorm": PSI_TOL_BNORM, "rel_l1": PSI_TOL_REL_L1}
+SEG_FORMS = {"auto": 0, "none": 0, "tiles": _ffi.PSI_SEG_TILES, "slices": _ffi.PSI_SEG_SLICES}
+SEG_FORM_NAMES = {0: "none", _ffi.PSI_SEG_TILES: "tiles", _ffi.PSI_SEG_SLICES: "slices"}
+
+
+def _seg_form(f) -> int:
+    return SEG_FORMS[f] if isinstance(f, str) else int(f)
 
 
 class PsiError(RuntimeError):
@@ -147,10 +153,11 @@ class Operator:
     def solve(self, tol: float = 1e-8, tol_mode: str = "abs_l1", max_iter: int = 10000,
               precision: str = "fp64", s0: torch.Tensor | None = None, check_every: int = 0,
               tile_items: int = 0, col_segments: int = 0, inner_tol: float = 0.0,
-              no_fallback: bool = False,
+              no_fallback: bool = False, seg_form: str | int = 0,
               return_s: bool = False, psi_out: torch.Tensor | None = None, stream=None,
               raise_on_status: bool = False):
-        """psi_solve: ψ (and s) by Algorithm 2; returns (psi, info) or (psi, s, info)."""
+        """psi_solve: ψ (and s) by Algorithm 2; returns (psi, info) or (psi, s, info).
+        seg_form: 0 / "auto", "tiles" or "slices" (partial pass of a segmented pass)."""
         p = _ffi.Params()
         _check(self._lib.psi_params_default(ctypes.byref(p)))
         p.tol = tol
@@ -161,6 +168,7 @@ class Operator:
         p.flags = PSI_NO_FALLBACK if no_fallback else 0
         p.tile_items = tile_items
         p.col_segments = col_segments
+        p.seg_form = _seg_form(seg_form)
         p.inner_tol = inner_tol
         psi = psi_out if psi_out is not None else torch.empty(self.n, dtype=torch.float64,
                                                               device=self.device)
@@ -179,7 +187,7 @@ class Operator:
         return (psi, s, d) if return_s else (psi, d)
 
     def step(self, s_in: torch.Tensor, precision: str = "fp64", tile_items: int = 0,
-             col_segments: int = 0, stream=None):
+             col_segments: int = 0, seg_form: str | int = 0, stream=None):
         """psi_step: one Power-ψ step s_out = Aᵀ s_in + c and its L1 gap (enqueued)."""
         s_in = s_in.to(self.device, torch.float64).contiguous()
         out = torch.empty_like(s_in)
@@ -187,7 +195,8 @@ class Operator:
         with torch.cuda.device(self.device):
             _check(self._lib.psi_step(self._h, PRECISIONS[precision], s_in.data_ptr(),
                                       out.data_ptr(), gap.data_ptr(), tile_items,
-                                      col_segments, _stream_handle(stream)))
+                                      col_segments, _seg_form(seg_form),
+                                      _stream_handle(stream)))
         return out, gap
 
     def final(self, s: torch.Tensor, stream=None) -> torch.Tensor:
@@ -200,7 +209,7 @@ class Operator:
         return out
 
     def pass_time(self, kind: str, reps: int = 50, tile_items: int = 0, col_segments: int = 0,
-                  stream=None) -> float:
+                  seg_form: str | int = 0, stream=None) -> float:
         """psi_pass_time: mean ms of one launch of a pass kind (HIP events on the stream)."""
         kinds = {"step64": _ffi.PSI_PASS_STEP64, "step64_w": _ffi.PSI_PASS_STEP64_W,
                  "final64": _ffi.PSI_PASS_FINAL64, "step32": _ffi.PSI_PASS_STEP32,
@@ -208,21 +217,24 @@ class Operator:
         out = ctypes.c_double()
         with torch.cuda.device(self.device):
             _check(self._lib.psi_pass_time(self._h, kinds[kind], reps, tile_items, col_segments,
-                                           ctypes.byref(out), _stream_handle(stream)))
+                                           _seg_form(seg_form), ctypes.byref(out),
+                                           _stream_handle(stream)))
         return out.value
 
     def autotune(self, precision: str = "fp64", reps: int = 0, stream=None) -> dict:
-        """psi_autotune: the fastest tile_items / col_segments for `precision`,
-        kept in the operator for later solves."""
-        t, sg, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        """psi_autotune: the fastest tile_items / col_segments / seg_form for
+        `precision`, kept in the operator for later solves."""
+        t, sg, fm, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
         prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         with torch.cuda.device(self.device):
             _check(self._lib.psi_autotune(self._h, prec, reps, ctypes.byref(t), ctypes.byref(sg),
-                                          ctypes.byref(ms), _stream_handle(stream)))
-        return dict(tile_items=t.value, col_segments=sg.value, pass_ms=ms.value)
+                                          ctypes.byref(fm), ctypes.byref(ms),
+                                          _stream_handle(stream)))
+        return dict(tile_items=t.value, col_segments=sg.value, seg_form=SEG_FORM_NAMES[fm.value],
+                    pass_ms=ms.value)
 
     def _params(self, tol, tol_mode, max_iter, precision, check_every, tile_items=0,
-                col_segments=0, inner_tol=0.0, no_fallback=False):
+                col_segments=0, inner_tol=0.0, no_fallback=False, seg_form=0):
         p = _ffi.Params()
         _check(self._lib.psi_params_default(ctypes.byref(p)))
         p.tol = tol
@@ -233,6 +245,7 @@ class Operator:
         p.flags = PSI_NO_FALLBACK if no_fallback else 0
         p.tile_items = tile_items
         p.col_segments = col_segments
+        p.seg_form = _seg_form(seg_form)
         p.inner_tol = inner_tol
         return p
 
@@ -269,10 +282,12 @@ class Operator:
     def solve_anderson(self, tol: float = 1e-8, depth: int = 4, tol_mode: str = "abs_l1",
                        max_iter: int = 10000, s0: torch.Tensor | None = None,
                        check_every: int = 0, tile_items: int = 0, col_segments: int = 0,
+                       seg_form: str | int = 0,
                        return_s: bool = False, stream=None, raise_on_status: bool = False):
         """psi_solve_anderson: the same ψ with Anderson-accelerated passes;
         returns (psi, info) or (psi, s, info)."""
-        p = self._params(tol, tol_mode, max_iter, "fp64", check_every, tile_items, col_segments)
+        p = self._params(tol, tol_mode, max_iter, "fp64", check_every, tile_items, col_segments,
+                         seg_form=seg_form)
         nbytes = ctypes.c_size_t()
         _check(self._lib.psi_anderson_workspace_size(self._h, depth, ctypes.byref(nbytes)))
         ws = self._accel_ws if getattr(self, "_accel_ws", None) is not None and \

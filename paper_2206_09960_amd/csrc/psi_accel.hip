@@ -321,12 +321,11 @@ psi_status solve_anderson(psi_operator* op, const psi_params* prm, int depth, co
     }
   }
   PSI_REQUIRE(S == 1 || S == 2 || S == 4 || S == 8, "col_segments must be 0, 1, 2, 4 or 8");
-  psi_status s = ensure_schedule(op, tile, st);
+  int form = 0;
+  psi_status s = resolve_form(op, prm->seg_form, prec, S, 8, &form);
   if (s != PSI_OK) return s;
-  if (S > 1) {
-    s = ensure_segments(op, S, st);
-    if (s != PSI_OK) return s;
-  }
+  s = prepare(op, tile, S, form, st);
+  if (s != PSI_OK) return s;
   auto pass = [&](PassMode mode, const PassArgs& a) {
     return S > 1 ? launch_pass_seg(op, mode, a, st) : launch_pass(op, mode, a, st);
   };
@@ -422,6 +421,7 @@ psi_status solve_anderson(psi_operator* op, const psi_params* prm, int depth, co
   inf.used_s0 = s0 ? 1 : 0;
   inf.col_segments = S;
   inf.tile_items = tile;
+  inf.seg_form = form;
   inf.final_gap = h->gap;
   inf.final_l1_step = h->l1;
   inf.b_norm = op->stats.b_norm;

@@ -15,10 +15,11 @@ void set_error(const std::string& msg) { g_last_error = msg; }
 void clear_error() { g_last_error.clear(); }
 
 psi_status step(psi_operator* op, int precision, const double* s_in, double* s_out,
-                double* gap_out, int tile_items, int col_segments, hipStream_t st);
+                double* gap_out, int tile_items, int col_segments, int seg_form,
+                hipStream_t st);
 psi_status final_psi(psi_operator* op, const double* s_vec, double* psi_out, hipStream_t st);
 psi_status pass_time(psi_operator* op, int kind, int reps, int tile_items, int col_segments,
-                     double* mean_ms, hipStream_t st);
+                     int seg_form, double* mean_ms, hipStream_t st);
 
 static psi_status check_device(const psi_operator* op) {
   int dev = -1;
@@ -175,6 +176,7 @@ psi_status psi_params_default(psi_params* p) {
   p->flags = 0;
   p->tile_items = 0;
   p->col_segments = 0;
+  p->seg_form = 0;
   p->inner_tol = 0.0;
   return PSI_OK;
   PSI_GUARD_END
@@ -191,12 +193,13 @@ psi_status psi_solve(psi_operator* op, const psi_params* prm, const double* s0,
 }
 
 psi_status psi_step(psi_operator* op, int32_t precision, const double* s_in, double* s_out,
-                    double* gap_out, int32_t tile_items, int32_t col_segments, void* stream) {
+                    double* gap_out, int32_t tile_items, int32_t col_segments,
+                    int32_t seg_form, void* stream) {
   PSI_GUARD_BEGIN
   PSI_REQUIRE(op, "op must not be NULL");
   psi_status s = psi::check_device(op);
   if (s != PSI_OK) return s;
-  return psi::step(op, precision, s_in, s_out, gap_out, tile_items, col_segments,
+  return psi::step(op, precision, s_in, s_out, gap_out, tile_items, col_segments, seg_form,
                    static_cast<hipStream_t>(stream));
   PSI_GUARD_END
 }
@@ -212,28 +215,32 @@ psi_status psi_final(psi_operator* op, const double* s, double* psi_out, void* s
 }
 
 psi_status psi_pass_time(psi_operator* op, int32_t pass_kind, int32_t reps, int32_t tile_items,
-                         int32_t col_segments, double* mean_ms, void* stream) {
+                         int32_t col_segments, int32_t seg_form, double* mean_ms,
+                         void* stream) {
   PSI_GUARD_BEGIN
   PSI_REQUIRE(op, "op must not be NULL");
   PSI_REQUIRE(op->n_graphs == 1, "psi_pass_time needs a single-graph operator");
   psi_status st = psi::check_device(op);
   if (st != PSI_OK) return st;
-  return psi::pass_time(op, pass_kind, reps, tile_items, col_segments, mean_ms,
+  return psi::pass_time(op, pass_kind, reps, tile_items, col_segments, seg_form, mean_ms,
                         static_cast<hipStream_t>(stream));
   PSI_GUARD_END
 }
 
 psi_status psi_autotune(psi_operator* op, int32_t precision, int32_t reps, int32_t* tile_items,
-                        int32_t* col_segments, double* best_ms, void* stream) {
+                        int32_t* col_segments, int32_t* seg_form, double* best_ms,
+                        void* stream) {
   PSI_GUARD_BEGIN
   PSI_REQUIRE(op, "op must not be NULL");
   psi_status st = psi::check_device(op);
   if (st != PSI_OK) return st;
-  int t = 0, sg = 0;
-  st = psi::autotune(op, precision, reps, &t, &sg, best_ms, static_cast<hipStream_t>(stream));
+  int t = 0, sg = 0, fm = 0;
+  st = psi::autotune(op, precision, reps, &t, &sg, &fm, best_ms,
+                     static_cast<hipStream_t>(stream));
   if (st == PSI_OK) {
     if (tile_items) *tile_items = t;
     if (col_segments) *col_segments = sg;
+    if (seg_form) *seg_form = fm;
   }
   return st;
   PSI_GUARD_END

@@ -706,6 +706,9 @@ static void layout_persistent(int64_t n, int64_t m_raw, int n_graphs, uint32_t f
   const int64_t cap_entries = segs ? m_raw + 8 * nw * int64_t(kSliceChunk) : 0;
   char* seg_col = take(4 * size_t(segs ? m_raw : 0));
   char* seg_row_ptr = take(4 * size_t(segs ? 8 * (n + 1) : 0));
+  const int64_t max_seg_tiles = segs ? (8 * n + m_raw) / kMinTileItems + 16 : 0;
+  char* seg_tile_row = take(4 * size_t(max_seg_tiles + 8));
+  char* seg_part_open = take(8 * size_t(max_seg_tiles));
   char* seg_y = take(8 * size_t(segs ? 8 * n : 0));
   char* seg_scan_tmp = take(4 * size_t((8 * nw + n + 1) / 4096 + 16));
   char* slice_desc = take(sizeof(SliceDesc) * size_t(cap_slices));
@@ -767,6 +770,9 @@ static void layout_persistent(int64_t n, int64_t m_raw, int n_graphs, uint32_t f
   op->graph_off = (int64_t*)goff;
   op->seg_col = (int*)seg_col;
   op->seg_row_ptr = (int*)seg_row_ptr;
+  op->seg_tile_row = (int*)seg_tile_row;
+  op->seg_part_open = (double*)seg_part_open;
+  op->max_seg_tiles = max_seg_tiles;
   op->seg_y = (double*)seg_y;
   op->seg_scan_tmp = (uint32_t*)seg_scan_tmp;
   op->slice_desc = (SliceDesc*)slice_desc;
@@ -849,6 +855,10 @@ psi_status build_operator(psi_operator* op, const int32_t* follower, const int32
                      reinterpret_cast<uint64_t*>(op->gap_grp), int64_t(2 * kMaxGrid / 64),
                      kEmptySlot);
   PSI_HIP_CHECK(hipMemsetAsync(op->grp_ticket, 0, 4 * size_t(kMaxGrid / 64), st));
+  if (op->max_seg_tiles > 0)
+    hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(op->max_seg_tiles)), dim3(kBlock), 0, st,
+                       reinterpret_cast<uint64_t*>(op->seg_part_open), op->max_seg_tiles,
+                       kEmptySlot);
   op->seg_S = 0;
   if (op->n_graphs > 1)
     PSI_HIP_CHECK(hipMemcpyAsync(op->graph_off, node_offsets, 8 * size_t(op->n_graphs + 1),
@@ -1030,8 +1040,6 @@ psi_status ensure_segments(psi_operator* op, int S, hipStream_t st) {
     set_error("column segmentation lost edges");
     return PSI_EDEVICE;
   }
-  SegOffsets so{};
-  for (int s = 0; s < S; ++s) so.off[s] = off[s];
   int64_t* doff = reinterpret_cast<int64_t*>(op->scal);  // 8 values of scratch
   PSI_HIP_CHECK(hipMemcpyAsync(doff, off.data(), 8 * size_t(S), hipMemcpyHostToDevice, st));
   if (op->m > 0)
@@ -1043,8 +1051,54 @@ psi_status ensure_segments(psi_operator* op, int S, hipStream_t st) {
     op->seg[s].col = op->seg_col + off[s];
     op->seg[s].n_nnz = static_cast<int>(totals[s]);
   }
+  for (int s = 0; s <= S; ++s) op->seg_off[s] = off[s];
+  op->seg_S = S;
+  op->seg_items = 0;
+  op->seg_sliced = false;
+  return PSI_OK;
+}
 
-  // sliced layout: per-window counts, their exclusive scans, then the fill
+// Merge-path schedules of the current segments for tiles of tile_items.
+psi_status ensure_seg_tiles(psi_operator* op, int tile_items, hipStream_t st) {
+  PSI_REQUIRE(op->seg_S > 1, "no column segments built");
+  PSI_REQUIRE(tile_items_supported(tile_items), "unsupported tile_items");
+  if (op->seg_items == tile_items) return PSI_OK;
+  const int64_t n = op->n;
+  int64_t tile_off = 0;
+  for (int s = 0; s < op->seg_S; ++s) {
+    const int64_t total = n + op->seg[s].n_nnz;
+    const int64_t nt = std::max<int64_t>((total + tile_items - 1) / tile_items, 1);
+    if (tile_off + nt + 1 > op->max_seg_tiles + 8) {
+      set_error("segment schedules do not fit the workspace");
+      return PSI_ENOSPACE;
+    }
+    hipLaunchKernelGGL(k_schedule, dim3(grid_for(nt + 1)), dim3(kBlock), 0, st,
+                       op->seg[s].row_ptr, n, int64_t(op->seg[s].n_nnz), int64_t(tile_items), nt,
+                       op->seg_tile_row + tile_off);
+    op->seg[s].tile_row = op->seg_tile_row + tile_off;
+    op->seg[s].part_open = op->seg_part_open + (tile_off - s);
+    op->seg[s].n_tiles = static_cast<int>(nt);
+    tile_off += nt + 1;
+  }
+  PSI_HIP_CHECK(hipGetLastError());
+  op->seg_items = tile_items;
+  return PSI_OK;
+}
+
+// Sliced layout of the current segments: per-window counts, their exclusive
+// scans, then the fill.
+psi_status ensure_seg_slices(psi_operator* op, hipStream_t st) {
+  PSI_REQUIRE(op->seg_S > 1, "no column segments built");
+  PSI_REQUIRE(op->cap_lanes < (int64_t(1) << 31) && op->cap_chunks < (int64_t(1) << 31),
+              "too many users for the sliced layout's 32-bit lane and chunk indices");
+  if (op->seg_sliced) return PSI_OK;
+  const int64_t n = op->n;
+  const int S = op->seg_S;
+  SortBufs sb{};
+  sb.tile_sums = op->seg_scan_tmp;
+  sb.total = op->seg_scan_tmp + ((8 * ((n + kSliceWindow - 1) / kSliceWindow) + n + 1) / 4096 + 8);
+  SegOffsets so{};
+  for (int s = 0; s < S; ++s) so.off[s] = op->seg_off[s];
   const int64_t nw = (n + kSliceWindow - 1) / kSliceWindow;
   const int64_t windows = int64_t(S) * nw;
   uint32_t* plan = op->slice_plan;
@@ -1081,7 +1135,7 @@ psi_status ensure_segments(psi_operator* op, int S, hipStream_t st) {
                      op->slice_len, op->slice_col, op->slice_chunk);
   PSI_HIP_CHECK(hipGetLastError());
   for (int s = 0; s <= S; ++s) op->seg_slice0[s] = int(first[s]);
-  op->seg_S = S;
+  op->seg_sliced = true;
   return PSI_OK;
 }
 

@@ -157,9 +157,16 @@ enum PassMode : int {
 struct SegInfo {
   const int* row_ptr;   // [n_rows + 1], offsets into col (0-based per segment)
   const int* col;       // global follower ids
+  const int* tile_row;  // merge-path schedule of this segment [n_tiles + 1] (tiled form)
+  double* part_open;    // cross-tile slots [n_tiles] (tiled form)
   void* y;              // partial result [n_rows]
   int n_nnz;
+  int n_tiles;
 };
+
+// The two forms of a segment's partial pass: merge-path tiles over the
+// segment's CSR, or one lane per row over its sliced layout.
+enum SegForm : int { kSegTiles = PSI_SEG_TILES, kSegSlices = PSI_SEG_SLICES };
 
 struct SegArgs {
   SegInfo seg[8];
@@ -247,8 +254,12 @@ struct psi_operator {
   // column-segmented form of CSR(Aᵀ) and its sliced layout (built on first
   // use for a given S)
   int seg_S = 0;            // segments currently built (0 = none)
+  int seg_items = 0;        // tile size of their merge-path schedules (0 = none)
+  bool seg_sliced = false;  // their sliced layout is built
+  int seg_form = 0;         // form the segmented passes of the current call use
   psi::SegInfo seg[8]{};
   int seg_slice0[9]{};      // first slice of each segment in slice_desc
+  int64_t seg_off[9]{};     // first edge of each segment in seg_col
   // hub schedule of the message-passing aggregation, one per orientation
   // (0: CSR(Aᵀ), 1: CSR(A)); built on first use
   psi::MpHubs mp_hubs[2]{};
@@ -258,8 +269,12 @@ struct psi_operator {
   // schedule chosen by psi_autotune, per precision (0 = not tuned)
   int tuned_tile[4]{};
   int tuned_S[4]{};
+  int tuned_form[4]{};
   int* seg_col = nullptr;       // [m]
   int* seg_row_ptr = nullptr;   // [8 * (n + 1)]
+  int* seg_tile_row = nullptr;  // [max_seg_tiles + 8]
+  double* seg_part_open = nullptr;  // [max_seg_tiles]
+  int64_t max_seg_tiles = 0;
   double* seg_y = nullptr;      // [8 * n]
   uint32_t* seg_scan_tmp = nullptr;
   // sliced layout of the segments, sized for S = 8 (capacities below)
@@ -288,8 +303,16 @@ psi_status build_operator(psi_operator* op, const int32_t* follower, const int32
                           char* scratch, size_t scratch_bytes, hipStream_t stream);
 
 psi_status ensure_schedule(psi_operator* op, int tile_items, hipStream_t stream);
-// Build (or keep) the S-segment form of CSR(Aᵀ) and its sliced layout.
+// Build (or keep) the S-segment form of CSR(Aᵀ), then the layout the chosen
+// partial-pass form walks: merge-path schedules of tile_items, or slices.
 psi_status ensure_segments(psi_operator* op, int S, hipStream_t stream);
+psi_status ensure_seg_tiles(psi_operator* op, int tile_items, hipStream_t stream);
+psi_status ensure_seg_slices(psi_operator* op, hipStream_t stream);
+// Partial-pass form of a call (requested, tuned, or from the segment share)
+// and the schedules and layouts its passes need.
+psi_status resolve_form(const psi_operator* op, int requested, int precision, int S, int bytes,
+                        int* form);
+psi_status prepare(psi_operator* op, int tile, int S, int form, hipStream_t stream);
 bool tile_items_supported(int t);
 psi_status launch_pass(psi_operator* op, PassMode mode, const PassArgs& a, hipStream_t stream);
 psi_status launch_pass_seg(psi_operator* op, PassMode mode, const PassArgs& a, hipStream_t stream);
@@ -300,7 +323,7 @@ PassArgs base_args(psi_operator* op);
 psi_status solve(psi_operator* op, const psi_params* prm, const double* s0, double* psi_out,
                  double* s_out, psi_info* info, hipStream_t stream);
 psi_status autotune(psi_operator* op, int precision, int reps, int* tile_items, int* col_segments,
-                    double* best_ms, hipStream_t stream);
+                    int* seg_form, double* best_ms, hipStream_t stream);
 psi_status gather_probe(const double* x, int64_t n_x, int S, const int32_t* idx, int64_t n_idx,
                         double* out, int grid, int reps, double* mean_ms, hipStream_t st);
 psi_status anderson_workspace_size(const psi_operator* op, int depth, size_t* bytes);

@@ -28,14 +28,17 @@
 // the 8 XCDs round-robin, so the XCDs with xcd % S == s work on column
 // segment s (followers in [s·N/S, (s+1)·N/S)) and write a partial y_s; a
 // streaming combine kernel then adds the S partials in segment order and
-// applies the epilogue and the gap.  The partial pass walks the segment's
-// sliced layout rather than merge-path tiles: one wave per slice, one lane
-// per short row summing its followers in CSR order, so a wave issues nothing
-// but coalesced index loads, gathers and one store per row, with no LDS and
-// no barrier.  Rows too long for a lane are cut into chunks summed by whole
-// waves; the last chunk of a row to finish adds the chunk partials in chunk
-// order.  Every row's sum has a fixed order, so passes stay bitwise
-// repeatable.
+// applies the epilogue and the gap.  The partial pass has two forms over the
+// same sums.  Tiled: the merge-path tiles above over the segment's CSR.
+// Sliced: one wave per slice of the segment's sliced layout, one lane per
+// short row summing its followers in CSR order, so a wave issues nothing but
+// coalesced index loads, gathers and one store per row, with no LDS and no
+// barrier; rows too long for a lane are cut into chunks summed by whole
+// waves, and the last chunk of a row to finish adds the chunk partials in
+// chunk order.  The sliced form wins while a segment's share of the gathered
+// vector stays in an XCD's L2; beyond that its stores, scattered over rows
+// ordered by length, cost more than the tiles' row-ordered ones.  Every row's
+// sum has a fixed order in both forms, so passes stay bitwise repeatable.
 #include <algorithm>
 #include <cmath>
 #include <type_traits>
@@ -103,7 +106,7 @@ struct TileSrc {
 
 template <int MODE>
 __device__ inline double gather(const PassArgs& a, int j, int e) {
-  if constexpr (MODE == kStep32) {
+  if constexpr (MODE == kStep32 || MODE == kPart32) {
     return static_cast<double>(static_cast<const float*>(a.x)[j]);
   } else if constexpr (MODE == kStep64W) {
     return static_cast<const double*>(a.x)[j] * __builtin_nontemporal_load(a.val64 + e);
@@ -191,6 +194,10 @@ __device__ inline void apply_row(const PassArgs& a, void* yout, int r, const Row
     a.ze_new[r] = static_cast<float>(in.a2) * en;
     g += fabs(static_cast<double>(en) - in.a3);
     s += fabs(static_cast<double>(en));
+  } else if constexpr (MODE == kPart64) {
+    static_cast<double*>(yout)[r] = y;
+  } else {
+    static_cast<float*>(yout)[r] = static_cast<float>(y);
   }
 }
 
@@ -544,6 +551,23 @@ __global__ __launch_bounds__(kBlock) void k_pass(PassArgs a) {
   if constexpr (MODE != kFinal64 && MODE != kFinal64G) finalize_gap(a, g, sn, L.red, &L.last);
 }
 
+// Partial pass of one column segment per XCD group over merge-path tiles
+// (tiled form): y_s = A_sᵀ x.
+template <int IPT, int MODE>
+__global__ __launch_bounds__(kBlock) void k_pass_seg(PassArgs a, SegArgs sg) {
+  __shared__ TileLds<IPT> L;
+  if (a.respect_done && a.ctrl->done) return;
+  const int xcd = blockIdx.x & 7;
+  const int group = xcd % sg.S;
+  const int per_round = 8 / sg.S;  // workgroups of a group among 8 consecutive ones
+  const int rank = (blockIdx.x >> 3) * per_round + xcd / sg.S;
+  const int size = (gridDim.x >> 3) * per_round;
+  const SegInfo& si = sg.seg[group];
+  TileSrc src{si.row_ptr, si.col, si.tile_row, si.part_open, si.y, si.n_nnz, si.n_tiles};
+  double g = 0.0, sn = 0.0;
+  run_tiles<IPT, MODE>(a, src, rank, size, L, g, sn);
+}
+
 // Partial pass over the sliced layout of the segments: y_s = A_sᵀ x.  XCD
 // group s (workgroups with (blockIdx mod 8) mod S = s) takes the slices of
 // segment s, four per workgroup, one per wave.
@@ -715,6 +739,18 @@ psi_status launch_ipt(const PassArgs& a, hipStream_t st) {
   return PSI_OK;
 }
 
+template <int IPT, int PMODE>
+psi_status launch_seg_ipt(const PassArgs& a, const SegArgs& sg, hipStream_t st) {
+  static const int cap = resident_grid(k_pass_seg<IPT, PMODE>);
+  if (cap <= 0) {
+    set_error("could not size the resident grid");
+    return PSI_EDEVICE;
+  }
+  hipLaunchKernelGGL((k_pass_seg<IPT, PMODE>), dim3(cap), dim3(kBlock), 0, st, a, sg);
+  PSI_HIP_CHECK(hipGetLastError());
+  return PSI_OK;
+}
+
 template <int MODE>
 psi_status launch_mode(const PassArgs& a, hipStream_t st) {
   switch (a.tile_items) {
@@ -729,10 +765,25 @@ psi_status launch_mode(const PassArgs& a, hipStream_t st) {
   }
 }
 
+template <int PMODE>
+psi_status launch_seg_mode(const PassArgs& a, const SegArgs& sg, hipStream_t st) {
+  switch (a.tile_items) {
+    case 1024: return launch_seg_ipt<4, PMODE>(a, sg, st);
+    case 1536: return launch_seg_ipt<6, PMODE>(a, sg, st);
+    case 2048: return launch_seg_ipt<8, PMODE>(a, sg, st);
+    case 3072: return launch_seg_ipt<12, PMODE>(a, sg, st);
+    case 4096: return launch_seg_ipt<16, PMODE>(a, sg, st);
+    default:
+      set_error("unsupported tile size " + std::to_string(a.tile_items));
+      return PSI_EINVAL;
+  }
+}
+
 // Grid of the sliced partial pass: workgroups of XCD group s cover the
 // slices of segment s four at a time.
 template <int MODE>
 psi_status launch_slices(psi_operator* op, const PassArgs& a, const SegArgs& sg, hipStream_t st) {
+  PSI_REQUIRE(op->seg_sliced, "sliced layout not built");
   SliceArgs sa{};
   sa.S = sg.S;
   sa.respect_done = a.respect_done;
@@ -823,6 +874,16 @@ psi_status launch_pass(psi_operator* op, PassMode mode, const PassArgs& a, hipSt
   return PSI_EINVAL;
 }
 
+// The partial kernel of a segmented pass in the operator's current form.
+template <int PMODE>
+psi_status launch_partial(psi_operator* op, const PassArgs& a, const SegArgs& sg, hipStream_t st) {
+  if (op->seg_form == kSegSlices) return launch_slices<PMODE>(op, a, sg, st);
+  PSI_REQUIRE(op->seg_form == kSegTiles && op->seg_items > 0, "segment layout not prepared");
+  PassArgs b = a;
+  b.tile_items = op->seg_items;
+  return launch_seg_mode<PMODE>(b, sg, st);
+}
+
 // A pass in column-segmented form: partial pass + combine (S = op->seg_S).
 psi_status launch_pass_seg(psi_operator* op, PassMode mode, const PassArgs& a, hipStream_t st) {
   SegArgs sg{};
@@ -833,14 +894,14 @@ psi_status launch_pass_seg(psi_operator* op, PassMode mode, const PassArgs& a, h
     case kStep64:
     case kFinal64:
       for (int s = 0; s < sg.S; ++s) sg.seg[s].y = op->seg_y + size_t(s) * op->n;
-      r = launch_slices<kPart64>(op, a, sg, st);
+      r = launch_partial<kPart64>(op, a, sg, st);
       if (r != PSI_OK) return r;
       return mode == kStep64 ? launch_combine<kStep64, double>(a, sg, st)
                              : launch_combine<kFinal64, double>(a, sg, st);
     case kStep32:
       for (int s = 0; s < sg.S; ++s)
         sg.seg[s].y = reinterpret_cast<float*>(op->seg_y) + size_t(s) * op->n;
-      r = launch_slices<kPart32>(op, a, sg, st);
+      r = launch_partial<kPart32>(op, a, sg, st);
       if (r != PSI_OK) return r;
       return launch_combine<kStep32, float>(a, sg, st);
     default: break;
@@ -856,10 +917,10 @@ psi_status launch_part_seg(psi_operator* op, PassMode mode, const PassArgs& a, h
   if (mode == kStep32) {
     for (int s = 0; s < sg.S; ++s)
       sg.seg[s].y = reinterpret_cast<float*>(op->seg_y) + size_t(s) * op->n;
-    return launch_slices<kPart32>(op, a, sg, st);
+    return launch_partial<kPart32>(op, a, sg, st);
   }
   for (int s = 0; s < sg.S; ++s) sg.seg[s].y = op->seg_y + size_t(s) * op->n;
-  return launch_slices<kPart64>(op, a, sg, st);
+  return launch_partial<kPart64>(op, a, sg, st);
 }
 
 }  // namespace psi

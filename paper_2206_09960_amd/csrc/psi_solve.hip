@@ -129,12 +129,6 @@ psi_status resolve_segments(const psi_operator* op, int requested, int bytes, in
   return PSI_OK;
 }
 
-psi_status prepare(psi_operator* op, int tile, int S, hipStream_t st) {
-  psi_status s = ensure_schedule(op, tile, st);
-  if (s != PSI_OK || S <= 1) return s;
-  return ensure_segments(op, S, st);
-}
-
 // A pass in the column-segmented form when S > 1 (the weighted form has none).
 psi_status run_pass(psi_operator* op, int S, PassMode mode, const PassArgs& a, hipStream_t st) {
   if (S > 1 && mode != kStep64W) return launch_pass_seg(op, mode, a, st);
@@ -198,6 +192,41 @@ psi_status iterate(psi_operator* op, int S, int ctrl_idx, PassMode mode, Make ma
 
 }  // namespace
 
+// Partial-pass form for S segments: the requested one, else the tuned one
+// (when it was tuned for this S), else sliced while a segment's share of the
+// gathered vector (`bytes` per user) is at most 6 MB, about what an XCD's L2
+// keeps.
+psi_status resolve_form(const psi_operator* op, int requested, int precision, int S, int bytes,
+                        int* form) {
+  PSI_REQUIRE(requested == 0 || requested == PSI_SEG_TILES || requested == PSI_SEG_SLICES,
+              "seg_form must be 0, PSI_SEG_TILES or PSI_SEG_SLICES");
+  if (S <= 1) {
+    *form = 0;
+  } else if (requested) {
+    *form = requested;
+  } else if (op->tuned_form[precision] && op->tuned_S[precision] == S) {
+    *form = op->tuned_form[precision];
+  } else {
+    *form = static_cast<double>(op->n) * bytes / S <= 6.0e6 ? kSegSlices : kSegTiles;
+  }
+  return PSI_OK;
+}
+
+// Schedules and layouts the passes of one call need; the segmented passes of
+// the call then use `form`.
+psi_status prepare(psi_operator* op, int tile, int S, int form, hipStream_t st) {
+  psi_status s = ensure_schedule(op, tile, st);
+  if (s != PSI_OK) return s;
+  op->seg_form = 0;
+  if (S <= 1) return PSI_OK;
+  s = ensure_segments(op, S, st);
+  if (s != PSI_OK) return s;
+  s = form == kSegSlices ? ensure_seg_slices(op, st) : ensure_seg_tiles(op, tile, st);
+  if (s != PSI_OK) return s;
+  op->seg_form = form;
+  return PSI_OK;
+}
+
 psi_status solve(psi_operator* op, const psi_params* prm, const double* s0, double* psi_out,
                  double* s_out, psi_info* info, hipStream_t st) {
   PSI_REQUIRE(prm, "params must not be NULL");
@@ -222,7 +251,11 @@ psi_status solve(psi_operator* op, const psi_params* prm, const double* s0, doub
   psi_status s = resolve_segments(op, want_S, prm->precision == PSI_PREC_FP64 ? 8 : 4, &S);
   if (s != PSI_OK) return s;
   if (prm->precision == PSI_PREC_FP64_WEIGHTED) S = 1;
-  s = prepare(op, tile, S, st);
+  int form = 0;
+  s = resolve_form(op, prm->seg_form, prm->precision, S,
+                   prm->precision == PSI_PREC_FP64 ? 8 : 4, &form);
+  if (s != PSI_OK) return s;
+  s = prepare(op, tile, S, form, st);
   if (s != PSI_OK) return s;
 
   const int64_t n = op->n;
@@ -240,6 +273,7 @@ psi_status solve(psi_operator* op, const psi_params* prm, const double* s0, doub
   inf.used_s0 = s0 ? 1 : 0;
   inf.col_segments = S;
   inf.tile_items = tile;
+  inf.seg_form = form;
 
   // optional start: keep s0 only if its fixed-point residual beats c's.
   // ‖r(c)‖₁ depends only on the operator and is computed once.  In FP64 the
@@ -503,7 +537,8 @@ psi_status solve(psi_operator* op, const psi_params* prm, const double* s0, doub
 }
 
 psi_status step(psi_operator* op, int precision, const double* s_in, double* s_out,
-                double* gap_out, int tile_items, int col_segments, hipStream_t st) {
+                double* gap_out, int tile_items, int col_segments, int seg_form,
+                hipStream_t st) {
   PSI_REQUIRE(s_in && s_out && s_in != s_out, "s_in and s_out must be distinct device arrays");
   PSI_REQUIRE(precision == PSI_PREC_FP64 || precision == PSI_PREC_FP64_WEIGHTED,
               "psi_step supports PSI_PREC_FP64 and PSI_PREC_FP64_WEIGHTED");
@@ -515,7 +550,10 @@ psi_status step(psi_operator* op, int precision, const double* s_in, double* s_o
   psi_status s = resolve_segments(op, col_segments, 8, &S);
   if (s != PSI_OK) return s;
   if (precision == PSI_PREC_FP64_WEIGHTED) S = 1;
-  s = prepare(op, tile, S, st);
+  int form = 0;
+  s = resolve_form(op, seg_form, precision, S, 8, &form);
+  if (s != PSI_OK) return s;
+  s = prepare(op, tile, S, form, st);
   if (s != PSI_OK) return s;
   PassArgs a = base_args(op);
   a.s_old = s_in;
@@ -538,7 +576,10 @@ psi_status step(psi_operator* op, int precision, const double* s_in, double* s_o
 psi_status final_psi(psi_operator* op, const double* s_vec, double* psi_out, hipStream_t st) {
   PSI_REQUIRE(s_vec && psi_out, "s and psi_out must not be NULL");
   const int S = auto_segments(op, 8);
-  psi_status s = prepare(op, op->sched_items ? op->sched_items : kDefaultTileItems, S, st);
+  int form = 0;
+  psi_status s = resolve_form(op, 0, PSI_PREC_FP64, S, 8, &form);
+  if (s != PSI_OK) return s;
+  s = prepare(op, op->sched_items ? op->sched_items : kDefaultTileItems, S, form, st);
   if (s != PSI_OK) return s;
   hipLaunchKernelGGL(k_make_z, dim3(grid_for(op->n)), dim3(kBlock), 0, st, s_vec, op->invden,
                      op->n, op->z_a);
@@ -549,7 +590,7 @@ psi_status final_psi(psi_operator* op, const double* s_vec, double* psi_out, hip
 }
 
 psi_status pass_time(psi_operator* op, int kind, int reps, int tile_items, int col_segments,
-                     double* mean_ms, hipStream_t st) {
+                     int seg_form, double* mean_ms, hipStream_t st) {
   PSI_REQUIRE(mean_ms, "mean_ms must not be NULL");
   PSI_REQUIRE(reps >= 1, "reps must be >= 1");
   PSI_REQUIRE(kind >= PSI_PASS_STEP64 && kind <= PSI_PASS_PART32, "unknown pass kind");
@@ -565,7 +606,12 @@ psi_status pass_time(psi_operator* op, int kind, int reps, int tile_items, int c
   if (s != PSI_OK) return s;
   if (kind == PSI_PASS_STEP64_W) S = 1;
   PSI_REQUIRE(!part_only || S > 1, "a partial pass needs col_segments > 1");
-  s = prepare(op, tile, S, st);
+  int form = 0;
+  s = resolve_form(op, seg_form,
+                   kind == PSI_PASS_STEP32 ? PSI_PREC_MIXED : PSI_PREC_FP64, S,
+                   kind == PSI_PASS_STEP32 ? 4 : 8, &form);
+  if (s != PSI_OK) return s;
+  s = prepare(op, tile, S, form, st);
   if (s != PSI_OK) return s;
   const int64_t n = op->n;
   hipLaunchKernelGGL(k_init64, dim3(grid_for(n)), dim3(kBlock), 0, st, nullptr, op->c, op->invden,
@@ -624,7 +670,7 @@ psi_status pass_time(psi_operator* op, int kind, int reps, int tile_items, int c
 // Times the loop kernels of a solve in `precision` for every supported tile
 // size and column-segment count and keeps the fastest in the operator.
 psi_status autotune(psi_operator* op, int precision, int reps, int* tile_items, int* col_segments,
-                    double* best_ms, hipStream_t st) {
+                    int* seg_form, double* best_ms, hipStream_t st) {
   PSI_REQUIRE(precision >= PSI_PREC_FP64 && precision <= PSI_PREC_FP32, "unknown precision");
   PSI_REQUIRE(reps >= 0, "reps must be >= 0");
   PSI_REQUIRE(op->n_graphs == 1, "psi_autotune needs a single-graph operator");
@@ -636,41 +682,54 @@ psi_status autotune(psi_operator* op, int precision, int reps, int* tile_items, 
   static const int kSegs[] = {1, 2, 4, 8};
   const int n_segs = precision == PSI_PREC_FP64_WEIGHTED ? 1 : 4;
   double best = 0.0;
-  int best_tile = 0, best_S = 0;
+  int best_tile = 0, best_S = 0, best_form = 0;
   int tile_s1 = 0;  // fastest tile of the unsegmented pass (S = 1 is timed first)
   double best_s1 = 0.0;
-  for (int si = 0; si < n_segs; ++si) {
-    for (int tile : kTiles) {
-      // the segmented partial pass walks slices, not tiles: one timing per S,
-      // with the tile kept for the unsegmented passes of a solve
-      if (kSegs[si] > 1 && tile != tile_s1) continue;
-      int r = reps;
-      if (r == 0) {  // about 20 ms of passes per candidate, at least 3
-        double one = 0.0;
-        psi_status s = pass_time(op, kind, 1, tile, kSegs[si], &one, st);
-        if (s != PSI_OK) return s;
-        r = static_cast<int>(std::min(50.0, std::max(3.0, 20.0 / std::max(one, 1e-3))));
-      }
-      double ms = 0.0;
-      psi_status s = pass_time(op, kind, r, tile, kSegs[si], &ms, st);
+  auto time_one = [&](int tile, int S, int form, double* ms) -> psi_status {
+    int r = reps;
+    if (r == 0) {  // about 20 ms of passes per candidate, at least 3
+      double one = 0.0;
+      psi_status s = pass_time(op, kind, 1, tile, S, form, &one, st);
       if (s != PSI_OK) return s;
-      if (kSegs[si] == 1 && (tile_s1 == 0 || ms < best_s1)) {
+      r = static_cast<int>(std::min(50.0, std::max(3.0, 20.0 / std::max(one, 1e-3))));
+    }
+    return pass_time(op, kind, r, tile, S, form, ms, st);
+  };
+  auto keep = [&](int tile, int S, int form, double ms) {
+    if (best_tile == 0 || ms < best) {
+      best = ms;
+      best_tile = tile;
+      best_S = S;
+      best_form = form;
+    }
+  };
+  for (int si = 0; si < n_segs; ++si) {
+    const int S = kSegs[si];
+    for (int tile : kTiles) {  // S = 1, or the tiled form of S segments
+      double ms = 0.0;
+      psi_status s = time_one(tile, S, S > 1 ? kSegTiles : 0, &ms);
+      if (s != PSI_OK) return s;
+      if (S == 1 && (tile_s1 == 0 || ms < best_s1)) {
         best_s1 = ms;
         tile_s1 = tile;
       }
-      if (best_tile == 0 || ms < best) {
-        best = ms;
-        best_tile = tile;
-        best_S = kSegs[si];
-      }
+      keep(tile, S, S > 1 ? kSegTiles : 0, ms);
+    }
+    if (S > 1) {  // the sliced form has no tiles: one timing, with the S = 1 tile kept
+      double ms = 0.0;
+      psi_status s = time_one(tile_s1, S, kSegSlices, &ms);
+      if (s != PSI_OK) return s;
+      keep(tile_s1, S, kSegSlices, ms);
     }
   }
-  psi_status s = prepare(op, best_tile, best_S, st);
+  psi_status s = prepare(op, best_tile, best_S, best_form, st);
   if (s != PSI_OK) return s;
   op->tuned_tile[precision] = best_tile;
   op->tuned_S[precision] = best_S;
+  op->tuned_form[precision] = best_form;
   if (tile_items) *tile_items = best_tile;
   if (col_segments) *col_segments = best_S;
+  if (seg_form) *seg_form = best_form;
   if (best_ms) *best_ms = best;
   return PSI_OK;
 }

@@ -139,35 +139,41 @@ def test_step_matches_oracle(gpu_lib, tile):
 
 
 @pytest.mark.parametrize("segs", [2, 4, 8])
-@pytest.mark.parametrize("tile", [1024, 2048, 4096])
-def test_segmented_step_matches_oracle(gpu_lib, segs, tile):
-    """Column-segmented pass (per-XCD-group partials + combine) vs the oracle."""
+@pytest.mark.parametrize("form,tile", [("tiles", 1024), ("tiles", 2048), ("tiles", 4096),
+                                       ("slices", 0)])
+def test_segmented_step_matches_oracle(gpu_lib, segs, form, tile):
+    """Column-segmented pass (per-XCD-group partials + combine) vs the oracle,
+    with the partial pass over merge-path tiles or over slices."""
     api = gpu_lib
     g = synth.chung_lu(40000, 15, 2.1, 13, sigma=2.0)
     op = gpu_op(api, g)
     A, B, c, d = oracle.operator(g.n, g.follower, g.leader, g.lam, g.mu)
     s_in = np.random.default_rng(2).uniform(0.5, 3.0, g.n)
     expect = A.T @ s_in + c
-    out, gap = op.step(torch.tensor(s_in, device="cuda"), tile_items=tile, col_segments=segs)
+    out, gap = op.step(torch.tensor(s_in, device="cuda"), tile_items=tile, col_segments=segs,
+                       seg_form=form)
     torch.cuda.synchronize()
     np.testing.assert_allclose(out.cpu().numpy(), expect, rtol=1e-13, atol=0)
     assert abs(gap.item() - np.abs(expect - s_in).sum()) <= 1e-12 * np.abs(expect - s_in).sum()
     for _ in range(3):  # bitwise repeatable
-        again, gap2 = op.step(torch.tensor(s_in, device="cuda"), tile_items=tile, col_segments=segs)
+        again, gap2 = op.step(torch.tensor(s_in, device="cuda"), tile_items=tile, col_segments=segs,
+                              seg_form=form)
         torch.cuda.synchronize()
         assert torch.equal(again, out) and torch.equal(gap2, gap)
 
 
 @pytest.mark.parametrize("prec,tol,bar", [("fp64", 1e-9, 1e-9), ("mixed", 1e-9, 1e-9),
                                           ("fp32", 1e-5, 1e-6)])
-@pytest.mark.parametrize("segs", [1, 2, 4, 8])
-def test_segmented_solve(gpu_lib, prec, tol, bar, segs):
+@pytest.mark.parametrize("segs,form", [(1, "auto"), (2, "tiles"), (2, "slices"), (4, "tiles"),
+                                       (4, "slices"), (8, "tiles"), (8, "slices")])
+def test_segmented_solve(gpu_lib, prec, tol, bar, segs, form):
     api = gpu_lib
     g = synth.chung_lu(60000, 20, 2.2, 14, sigma=1.5)
     A, B, c, d, r = oracle_run(g, tol)
     op = gpu_op(api, g)
-    psi, info = op.solve(tol=tol, precision=prec, col_segments=segs)
+    psi, info = op.solve(tol=tol, precision=prec, col_segments=segs, seg_form=form)
     assert info["status"] == 0, info
+    assert info["seg_form"] == (0 if segs == 1 else api.SEG_FORMS[form])
     assert oracle.rel_l1(r["psi"], psi.cpu().numpy()) <= bar
 
 
@@ -204,14 +210,18 @@ def test_sliced_layout_row_lengths(gpu_lib, segs):
     A, B, c, d = oracle.operator(g.n, g.follower, g.leader, g.lam, g.mu)
     s_in = np.random.default_rng(3).uniform(0.5, 3.0, g.n)
     expect = A.T @ s_in + c
-    out, gap = op.step(torch.tensor(s_in, device="cuda"), col_segments=segs)
+    out, gap = op.step(torch.tensor(s_in, device="cuda"), col_segments=segs, seg_form="slices")
     torch.cuda.synchronize()
     np.testing.assert_allclose(out.cpu().numpy(), expect, rtol=1e-13, atol=0)
     for _ in range(2):  # bitwise repeatable, chunk partials summed in chunk order
-        again, _ = op.step(torch.tensor(s_in, device="cuda"), col_segments=segs)
+        again, _ = op.step(torch.tensor(s_in, device="cuda"), col_segments=segs,
+                           seg_form="slices")
         torch.cuda.synchronize()
         assert torch.equal(again, out)
-    psi, info = op.solve(tol=1e-10, col_segments=segs)
+    tiled, _ = op.step(torch.tensor(s_in, device="cuda"), col_segments=segs, seg_form="tiles")
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(tiled.cpu().numpy(), expect, rtol=1e-13, atol=0)
+    psi, info = op.solve(tol=1e-10, col_segments=segs, seg_form="slices")
     _, _, _, _, r = oracle_run(g, 1e-10)
     assert info["status"] == 0 and oracle.rel_l1(r["psi"], psi.cpu().numpy()) <= 1e-9
 
@@ -229,9 +239,12 @@ def test_sliced_layout_degenerate(gpu_lib):
         A, B, c, d = oracle.operator(n, ff, ll, lam, mu)
         op = api.Operator(n, ff, ll, lam, mu)
         for segs in (2, 4, 8):
-            out, _ = op.step(torch.tensor(s_in, device="cuda"), col_segments=segs)
-            torch.cuda.synchronize()
-            np.testing.assert_allclose(out.cpu().numpy(), A.T @ s_in + c, rtol=1e-15, atol=0)
+            for form in ("slices", "tiles"):
+                out, _ = op.step(torch.tensor(s_in, device="cuda"), col_segments=segs,
+                                 seg_form=form)
+                torch.cuda.synchronize()
+                np.testing.assert_allclose(out.cpu().numpy(), A.T @ s_in + c, rtol=1e-15,
+                                           atol=0)
 
 
 def test_step_bitwise_repeatable(gpu_lib):
@@ -444,9 +457,12 @@ def test_autotune_picks_a_supported_schedule_that_solves_use(gpu_lib):
         t = op.autotune(prec, reps=3)
         assert t["tile_items"] in (1024, 1536, 2048, 3072, 4096)
         assert t["col_segments"] in (1, 2, 4, 8) and t["pass_ms"] > 0
+        assert t["seg_form"] == ("none" if t["col_segments"] == 1 else t["seg_form"])
+        assert t["seg_form"] in ("none", "tiles", "slices")
         psi, info = op.solve(tol=1e-10, precision=prec)
         assert info["status"] == 0
         assert (info["tile_items"], info["col_segments"]) == (t["tile_items"], t["col_segments"])
+        assert api.SEG_FORM_NAMES[info["seg_form"]] == t["seg_form"]
         assert oracle.rel_l1(ref, psi.cpu().numpy()) <= bar
         # an explicit choice still wins over the tuned one
         _, info2 = op.solve(tol=1e-10, precision=prec, tile_items=1024, col_segments=1)
