@@ -577,10 +577,15 @@ __global__ __launch_bounds__(kBlock) void k_slices(SliceArgs a) {
   using XT = typename std::conditional<MODE == kPart32, float, double>::type;
   const int xcd = blockIdx.x & 7;
   const int group = xcd % a.S;
-  const int per_round = 8 / a.S;  // workgroups of a group among 8 consecutive ones
-  const int rank = (blockIdx.x >> 3) * per_round + xcd / a.S;
-  const int q = rank * (kBlock / 64) + (threadIdx.x >> 6);
+  const int per_round = 8 / a.S;  // XCDs of a group
   const SliceSeg& sg = a.seg[group];
+  // each XCD of the group takes a contiguous run of the segment's slices, in
+  // dispatch order, so the stores of a window land in one L2
+  const int ranks = (sg.n_slices + kBlock / 64 - 1) / (kBlock / 64);
+  const int run = (ranks + per_round - 1) / per_round;
+  if (static_cast<int>(blockIdx.x >> 3) >= run) return;  // this group's runs are shorter
+  const int rank = (xcd / a.S) * run + static_cast<int>(blockIdx.x >> 3);
+  const int q = rank * (kBlock / 64) + (threadIdx.x >> 6);
   if (q >= sg.n_slices) return;
   const int lane = threadIdx.x & 63;
   const XT* x = static_cast<const XT*>(a.x);
