@@ -266,6 +266,8 @@ __global__ void k_aa_start(const double* s0, const double* c, const double* invd
 __global__ void k_aa_ctrl(Ctrl* c, double tol, int tol_mode, int max_iter, double bnorm) {
   c->ticket = 0;
   c->done = 0;
+  c->done_pass = -1;
+  c->pending = 0;
   c->iter = 0;
   c->status = 0;
   c->gap = 0.0;

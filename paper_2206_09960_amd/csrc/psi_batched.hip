@@ -518,7 +518,10 @@ __global__ __launch_bounds__(kBlock) void k_graph_gap(const int64_t* graph_off, 
     const unsigned n_done = (t >> 16) + static_cast<unsigned>(done);
     ctrl->ticket = 0;
     ctrl->iter += 1;
-    if (n_done == static_cast<unsigned>(n_graphs)) ctrl->done = 1;
+    if (n_done == static_cast<unsigned>(n_graphs)) {
+      ctrl->done_pass = -1;
+      ctrl->done = 1;
+    }
   }
 }
 

@@ -684,7 +684,7 @@ static void layout_persistent(int64_t n, int64_t m_raw, int n_graphs, uint32_t f
   char* ze_b = take(4 * size_t(n));
   char* r32 = take(4 * size_t(n));
   char* part_open = take(8 * size_t(max_tiles));
-  char* gap_part = take(16 * size_t(kMaxGrid));
+  char* gap_part = take(2 * 16 * size_t(kMaxGrid));  // two buffers (deferred gaps alternate)
   char* gap_grp = take(16 * size_t(kMaxGrid / 64));
   char* grp_ticket = take(4 * size_t(kMaxGrid / 64));
   char* tile_row = take(4 * size_t(max_tiles + 1));
@@ -849,8 +849,8 @@ psi_status build_operator(psi_operator* op, const int32_t* follower, const int32
   PSI_HIP_CHECK(hipMemsetAsync(op->ctrl, 0, 2 * sizeof(Ctrl), st));
   hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(op->max_tiles)), dim3(kBlock), 0, st,
                      reinterpret_cast<uint64_t*>(op->part_open), op->max_tiles, kEmptySlot);
-  hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(2 * kMaxGrid)), dim3(kBlock), 0, st,
-                     reinterpret_cast<uint64_t*>(op->gap_part), int64_t(2 * kMaxGrid), kEmptySlot);
+  hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(4 * kMaxGrid)), dim3(kBlock), 0, st,
+                     reinterpret_cast<uint64_t*>(op->gap_part), int64_t(4 * kMaxGrid), kEmptySlot);
   hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(2 * kMaxGrid / 64)), dim3(kBlock), 0, st,
                      reinterpret_cast<uint64_t*>(op->gap_grp), int64_t(2 * kMaxGrid / 64),
                      kEmptySlot);

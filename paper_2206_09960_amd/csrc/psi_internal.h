@@ -50,6 +50,7 @@ constexpr int kMinTileItems = 1024;    // smallest merge-path tile (sizes the sc
 constexpr int kDefaultTileItems = 2048;
 constexpr int kHistLen = 1 << 16;      // device gap history entries
 constexpr int kMaxGrid = 4096;         // largest grid of a pass kernel (64 groups of 64)
+constexpr int kNoPass = 0x7fffffff;    // pass_id of a pass outside a deferred solve loop
 // Cross-tile slots hold this signalling-NaN pattern while empty.  Every value
 // a tile publishes is the result of floating-point arithmetic, which never
 // produces a signalling NaN, so the pattern cannot collide with data.
@@ -89,7 +90,9 @@ struct Ctrl {
   int max_iter;
   double bnorm;
   unsigned int err_flags;           // build validation
-  unsigned int pad0;
+  unsigned int pending;   // gap pairs a deferred pass left for the next kernel to decide
+  int done_pass;          // pass whose workgroup 0 set done (-1: a kernel's tail or a
+                          // separate decision); passes up to it still run in full
   unsigned long long bnorm_bits;    // max over rows (bit pattern of a non-negative double)
   unsigned long long kappa_bits;
   unsigned long long n_self_loops;
@@ -129,6 +132,9 @@ struct PassArgs {
   // cross-tile state
   double* part_open;   // [n_tiles] a tile's partial of its open last row (slot)
   double* gap_part;    // [2*grid] (Σ|Δ|, Σ|new|) of each workgroup (slot)
+  double* gap_prev;    // deferred form: the previous pass's pairs, decided by workgroup 0
+  int defer_gap;       // 1: write the pairs and leave the decision to the next kernel
+  int pass_id;         // index of the pass in its solve loop (kNoPass outside one)
   double* gap_grp;     // [2*ceil(grid/64)] the same per group of 64 workgroups (slot)
   unsigned* grp_ticket;  // [ceil(grid/64)] arrivals per group (reset by its last)
   Ctrl* ctrl;
@@ -211,6 +217,12 @@ struct SliceArgs {
   double* part;               // chunk partials (slots, empty = kEmptySlot)
   unsigned* ticket;           // arrivals per multi-chunk row, indexed by its first slot
   Ctrl* ctrl;
+  // a deferred gap of the previous pass, decided by workgroup 0
+  double* gap_prev;
+  double* hist;
+  int count_iter;
+  int defer_gap;
+  int pass_id;
 };
 
 }  // namespace psi
@@ -318,6 +330,9 @@ psi_status launch_pass(psi_operator* op, PassMode mode, const PassArgs& a, hipSt
 psi_status launch_pass_seg(psi_operator* op, PassMode mode, const PassArgs& a, hipStream_t stream);
 // Only the per-segment partial kernel of a segmented kStep64 / kStep32 pass.
 psi_status launch_part_seg(psi_operator* op, PassMode mode, const PassArgs& a, hipStream_t stream);
+// Decide a deferred gap: the pairs in `pairs` left by the last pass on ctrl.
+psi_status launch_gap_decide(Ctrl* ctrl, double* pairs, double* hist, int count_iter,
+                             hipStream_t stream);
 PassArgs base_args(psi_operator* op);
 
 psi_status solve(psi_operator* op, const psi_params* prm, const double* s0, double* psi_out,

@@ -479,13 +479,81 @@ __device__ inline void take_pairs(double* base, int count, Ctrl* ctrl, double& G
   }
 }
 
-// One partial per workgroup (g, sn), reduced in two levels of at most 64 in
-// workgroup order: the last workgroup of each group of 64 sums its group,
-// the last group sums the groups, records the gap and decides termination.
-// Counters are spread over groups, so no single address takes every arrival.
+// The termination decision on the reduced gap (thread 0): the iteration
+// count, the gap in tol_mode units, its history, and done/status.
+__device__ void decide_gap(Ctrl* c, double G, double S, double* hist, double* gap_out,
+                           int count_iter, int done_pass) {
+  if (gap_out) *gap_out = G;
+  if (!count_iter) return;
+  double gap = G;
+  if (c->tol_mode == PSI_TOL_BNORM) gap = G * c->bnorm;
+  else if (c->tol_mode == PSI_TOL_REL_L1) gap = S > 0.0 ? G / S : G;
+  const int it = c->iter + 1;
+  c->iter = it;
+  c->gap = gap;
+  c->l1 = G;
+  c->snorm = S;
+  if (hist && it - 1 < kHistLen) hist[it - 1] = gap;
+  int st = -1;
+  if (!isfinite(gap)) st = PSI_ENUMERIC;
+  else if (gap <= c->tol) st = PSI_OK;
+  else if (it >= c->max_iter) st = PSI_ENOTCONV;
+  if (st >= 0) {
+    c->status = st;
+    c->done_pass = done_pass;
+    c->done = 1;
+  }
+}
+
+// Deferred gap, the whole workgroup: the c->pending pairs a previous kernel
+// left in `pairs` (complete, since that kernel has ended), summed in
+// workgroup order — thread t a contiguous run, then a fixed tree — and
+// decided as pass `pass_id`; the slots are emptied again.  Pairs of a pass
+// that ran after the decision (its workgroups could not see it) are only
+// emptied.
+__device__ void take_deferred(Ctrl* c, double* pairs, double* hist, int count_iter, int pass_id,
+                              double* red) {
+  const int n = static_cast<int>(c->pending);  // uniform
+  if (n == 0) return;
+  const int already = c->done;                  // uniform
+  const int tid = threadIdx.x;
+  const int per = (n + kBlock - 1) / kBlock;
+  const int q_end = min(n, (tid + 1) * per);
+  double G = 0.0, S = 0.0;
+  for (int q = tid * per; q < q_end; ++q) {
+    unsigned long long* p = reinterpret_cast<unsigned long long*>(pairs + 2 * q);
+    G += __longlong_as_double(static_cast<long long>(
+        __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
+    S += __longlong_as_double(static_cast<long long>(
+        __hip_atomic_load(p + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
+    __hip_atomic_store(p, kEmptySlot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(p + 1, kEmptySlot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  block_sum2(G, S, red);
+  if (tid == 0) {
+    c->pending = 0;
+    if (!already) decide_gap(c, G, S, hist, nullptr, count_iter, pass_id);
+  }
+  __syncthreads();
+}
+
+// One partial per workgroup (g, sn).  Deferred form: the pair is stored and
+// the next kernel on this control block decides.  Otherwise the pairs are
+// reduced in two levels of at most 64 in workgroup order: the last workgroup
+// of each group of 64 sums its group, the last group sums the groups and
+// decides termination.  Counters are spread over groups, so no single address
+// takes every arrival.
 __device__ void finalize_gap(const PassArgs& a, double g, double sn, double* red, int* s_last) {
   const int tid = threadIdx.x;
   block_sum2(g, sn, red);
+  if (a.defer_gap) {
+    if (tid == 0) {
+      st_agent(&a.gap_part[2 * blockIdx.x], g);
+      st_agent(&a.gap_part[2 * blockIdx.x + 1], sn);
+      if (blockIdx.x == 0) a.ctrl->pending = gridDim.x;
+    }
+    return;
+  }
   const int grp = blockIdx.x >> 6;
   const int n_grp = (gridDim.x + 63) >> 6;
   const int in_grp = min(64, static_cast<int>(gridDim.x) - (grp << 6));
@@ -513,38 +581,26 @@ __device__ void finalize_gap(const PassArgs& a, double g, double sn, double* red
   double G, S;
   take_pairs(a.gap_grp, n_grp, a.ctrl, G, S);
   if (tid == 0) {
-    Ctrl* c = a.ctrl;
-    c->ticket = 0;
-    if (a.gap_out) *a.gap_out = G;
-    if (a.count_iter) {
-      double gap = G;
-      if (c->tol_mode == PSI_TOL_BNORM) gap = G * c->bnorm;
-      else if (c->tol_mode == PSI_TOL_REL_L1) gap = S > 0.0 ? G / S : G;
-      const int it = c->iter + 1;
-      c->iter = it;
-      c->gap = gap;
-      c->l1 = G;
-      c->snorm = S;
-      if (a.hist && it - 1 < kHistLen) a.hist[it - 1] = gap;
-      if (!isfinite(gap)) {
-        c->done = 1;
-        c->status = PSI_ENUMERIC;
-      } else if (gap <= c->tol) {
-        c->done = 1;
-        c->status = PSI_OK;
-      } else if (it >= c->max_iter) {
-        c->done = 1;
-        c->status = PSI_ENOTCONV;
-      }
-    }
+    a.ctrl->ticket = 0;
+    decide_gap(a.ctrl, G, S, a.hist, a.gap_out, a.count_iter, -1);
   }
+}
+
+__global__ __launch_bounds__(kBlock) void k_gap_decide(Ctrl* c, double* pairs, double* hist,
+                                                       int count_iter) {
+  __shared__ double red[8];
+  take_deferred(c, pairs, hist, count_iter, -1, red);
 }
 
 // Fused pass over the whole of CSR(Aᵀ).
 template <int IPT, int MODE>
 __global__ __launch_bounds__(kBlock) void k_pass(PassArgs a) {
   __shared__ TileLds<IPT> L;
-  if (a.respect_done && a.ctrl->done) return;
+  if (a.defer_gap && blockIdx.x == 0)
+    take_deferred(a.ctrl, a.gap_prev, a.hist, a.count_iter, a.pass_id, L.red);
+  // a decision of this very pass (by workgroup 0) does not stop it: every
+  // workgroup must run, or cross-tile slots would be left half filled
+  if (a.respect_done && a.ctrl->done && a.ctrl->done_pass < a.pass_id) return;
   TileSrc src{a.row_ptr, a.col, a.tile_row, a.part_open, nullptr, a.n_nnz, a.n_tiles};
   double g = 0.0, sn = 0.0;
   run_tiles<IPT, MODE>(a, src, blockIdx.x, gridDim.x, L, g, sn);
@@ -556,7 +612,9 @@ __global__ __launch_bounds__(kBlock) void k_pass(PassArgs a) {
 template <int IPT, int MODE>
 __global__ __launch_bounds__(kBlock) void k_pass_seg(PassArgs a, SegArgs sg) {
   __shared__ TileLds<IPT> L;
-  if (a.respect_done && a.ctrl->done) return;
+  if (a.defer_gap && blockIdx.x == 0)
+    take_deferred(a.ctrl, a.gap_prev, a.hist, a.count_iter, a.pass_id, L.red);
+  if (a.respect_done && a.ctrl->done && a.ctrl->done_pass < a.pass_id) return;
   const int xcd = blockIdx.x & 7;
   const int group = xcd % sg.S;
   const int per_round = 8 / sg.S;  // workgroups of a group among 8 consecutive ones
@@ -573,7 +631,10 @@ __global__ __launch_bounds__(kBlock) void k_pass_seg(PassArgs a, SegArgs sg) {
 // segment s, four per workgroup, one per wave.
 template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_slices(SliceArgs a) {
-  if (a.respect_done && a.ctrl->done) return;
+  __shared__ double red[8];
+  if (a.defer_gap && blockIdx.x == 0)
+    take_deferred(a.ctrl, a.gap_prev, a.hist, a.count_iter, a.pass_id, red);
+  if (a.respect_done && a.ctrl->done && a.ctrl->done_pass < a.pass_id) return;
   using XT = typename std::conditional<MODE == kPart32, float, double>::type;
   const int xcd = blockIdx.x & 7;
   const int group = xcd % a.S;
@@ -678,7 +739,8 @@ template <int MODE, class YT>
 __global__ __launch_bounds__(kBlock) void k_combine(PassArgs a, SegArgs sg) {
   __shared__ double red[8];
   __shared__ int last;
-  if (a.respect_done && a.ctrl->done) return;
+  // the combine follows its own pass's partial kernel, whose decision it sees
+  if (a.respect_done && a.ctrl->done && a.ctrl->done_pass <= a.pass_id) return;
   double g = 0.0, sn = 0.0;
   const YT* y0 = static_cast<const YT*>(sg.seg[0].y);
   const YT* y1 = static_cast<const YT*>(sg.seg[1].y);
@@ -801,6 +863,11 @@ psi_status launch_slices(psi_operator* op, const PassArgs& a, const SegArgs& sg,
   sa.part = op->slice_part;
   sa.ticket = op->slice_ticket;
   sa.ctrl = a.ctrl;
+  sa.gap_prev = a.gap_prev;
+  sa.hist = a.hist;
+  sa.count_iter = a.count_iter;
+  sa.defer_gap = a.defer_gap;
+  sa.pass_id = a.pass_id;
   int most = 0;
   for (int s = 0; s < sg.S; ++s) {
     sa.seg[s].slices = op->slice_desc + op->seg_slice0[s];
@@ -828,6 +895,13 @@ psi_status launch_combine(const PassArgs& a, const SegArgs& sg, hipStream_t st) 
 }
 
 }  // namespace
+
+psi_status launch_gap_decide(Ctrl* ctrl, double* pairs, double* hist, int count_iter,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(k_gap_decide, dim3(1), dim3(kBlock), 0, st, ctrl, pairs, hist, count_iter);
+  PSI_HIP_CHECK(hipGetLastError());
+  return PSI_OK;
+}
 
 bool tile_items_supported(int t) {
   return t == 1024 || t == 1536 || t == 2048 || t == 3072 || t == 4096;
@@ -861,6 +935,8 @@ PassArgs base_args(psi_operator* op) {
   a.grp_ticket = op->grp_ticket;
   a.ctrl = op->ctrl;
   a.hist = op->hist;
+  a.defer_gap = 0;
+  a.pass_id = kNoPass;
   return a;
 }
 

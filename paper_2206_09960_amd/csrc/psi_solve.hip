@@ -46,6 +46,8 @@ __global__ void k_init32(const double* s0, const double* c, const float* invden3
 __global__ void k_ctrl_set(Ctrl* c, double tol, int tol_mode, int max_iter, double bnorm) {
   c->ticket = 0;
   c->done = 0;
+  c->done_pass = -1;
+  c->pending = 0;
   c->iter = 0;
   c->status = 0;
   c->gap = 0.0;
@@ -61,6 +63,8 @@ __global__ void k_ctrl_set(Ctrl* c, double tol, int tol_mode, int max_iter, doub
 __global__ void k_ctrl_inner(const Ctrl* outer, Ctrl* inner, double eta, int max_iter) {
   inner->ticket = 0;
   inner->done = 0;
+  inner->done_pass = -1;
+  inner->pending = 0;
   inner->iter = 0;
   inner->status = 0;
   inner->gap = 0.0;
@@ -150,11 +154,26 @@ psi_status iterate(psi_operator* op, int S, int ctrl_idx, PassMode mode, Make ma
   int best_iter = 0;
   while (true) {
     const int cnt = std::min(k, max_iter - enq);
+    // deferred gaps: pass p stores its per-workgroup pairs in buffer p mod 2
+    // and the next pass's workgroup 0 decides on them, so no pass ends with
+    // a chain of reductions; the batch's last pairs are decided before the
+    // host reads the control block
     for (int i = 0; i < cnt; ++i) {
-      psi_status s = run_pass(op, S, mode, make(enq + i), st);
+      const int p = enq + i;
+      PassArgs a = make(p);
+      a.defer_gap = 1;
+      a.pass_id = p;
+      a.gap_part = op->gap_part + size_t(p & 1) * 2 * kMaxGrid;
+      a.gap_prev = op->gap_part + size_t((p & 1) ^ 1) * 2 * kMaxGrid;
+      psi_status s = run_pass(op, S, mode, a, st);
       if (s != PSI_OK) return s;
     }
     enq += cnt;
+    {
+      psi_status s = launch_gap_decide(dctrl, op->gap_part + size_t((enq - 1) & 1) * 2 * kMaxGrid,
+                                       op->hist, 1, st);
+      if (s != PSI_OK) return s;
+    }
     PSI_HIP_CHECK(hipMemcpyAsync(hctrl, dctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
     PSI_HIP_CHECK(hipStreamSynchronize(st));
     out->iters = hctrl->iter;
