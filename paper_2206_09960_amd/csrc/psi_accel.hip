@@ -15,13 +15,15 @@
 // x_k of size at most ε, exactly the criterion Algorithm 2 applies to its
 // last step.  ψ = (Bᵀs + d)/N follows as in Algorithm 2.
 //
-// Device work per iteration: the pass; k_aa_diff (f, ΔF, ΔG into a ring of
-// m columns, and the 2m dot products ⟨ΔF_j, ΔF_new⟩, ⟨ΔF_j, f⟩ as
-// per-workgroup partials); k_aa_solve (one workgroup: the partials in fixed
-// order, the Gram matrix updated by one row/column, a Cholesky solve with a
-// small relative shift; the window is cleared if the factorisation fails or
-// the gap grows tenfold); k_aa_mix (x_{k+1}, z = x/den).  Every reduction
-// has a fixed order, so solves are bitwise repeatable.
+// Device work per iteration: the pass, which leaves its gap as per-workgroup
+// pairs; k_aa_diff (its workgroup 0 first decides the pass's gap; then f,
+// ΔF, ΔG into a ring of m columns, and the 2m dot products ⟨ΔF_j, ΔF_new⟩,
+// ⟨ΔF_j, f⟩ as per-workgroup partials); k_aa_solve (one workgroup: the
+// partials in fixed order, the Gram matrix updated by one row/column, a
+// Cholesky solve with a small relative shift; the window is cleared if the
+// factorisation fails or the gap grows tenfold); k_aa_mix (x_{k+1},
+// z = x/den).  Every reduction has a fixed order, so solves are bitwise
+// repeatable.
 #include <algorithm>
 #include <cmath>
 #include <limits>
@@ -33,7 +35,8 @@ namespace psi {
 namespace {
 
 constexpr int kMaxDepth = 8;
-constexpr int kAaGrid = 512;
+constexpr int kAaGrid = 2048;       // most workgroups of k_aa_diff (one partial row each)
+constexpr int kAaSolveBlock = 1024; // threads of k_aa_solve
 
 inline unsigned grid_for(int64_t n) { return static_cast<unsigned>((n + kBlock - 1) / kBlock); }
 inline size_t align_up(size_t x) { return (x + 255) / 256 * 256; }
@@ -100,9 +103,18 @@ __device__ inline double block_sum(double v, double* red) {
 // partial dot products of every window column (the new one included) with
 // the new ΔF column and with f.
 __global__ __launch_bounds__(kBlock) void k_aa_diff(const double* g, const double* x, int64_t n,
-                                                    int m, AaWs w, const Ctrl* ctrl) {
-  __shared__ double red[kBlock / 64];
-  if (ctrl->done) return;
+                                                    int m, AaWs w, Ctrl* ctrl, double* pairs,
+                                                    double* hist) {
+  __shared__ double red[2 * (kBlock / 64)];
+  __shared__ int s_done;
+  // the pass's gap: decided here, before k_aa_solve reads it
+  if (blockIdx.x == 0) take_deferred(ctrl, pairs, hist, 1, -1, red);
+  // one reading per workgroup.  A decision by workgroup 0 just now may reach
+  // some workgroups and not others, which is harmless: once done, nothing
+  // later in the solve reads what this kernel writes.
+  if (threadIdx.x == 0) s_done = ctrl->done;
+  __syncthreads();
+  if (s_done) return;
   const int valid = w.st->valid, slot = w.st->head;  // uniform
   const int cnt = valid ? std::min(w.st->count + 1, m) : 0;
   double vv[kMaxDepth], vb[kMaxDepth];
@@ -139,12 +151,16 @@ __global__ __launch_bounds__(kBlock) void k_aa_diff(const double* g, const doubl
   }
 }
 
-// One workgroup: reduce the partials (16 interleaved slices, then the slices
-// in order), update the Gram matrix, and solve (G + δI) γ = b over the window
-// by Cholesky.
-__global__ __launch_bounds__(kBlock) void k_aa_solve(AaWs w, int m, int n_blk, const Ctrl* ctrl) {
-  __shared__ double v[2 * kMaxDepth];
-  __shared__ double slice[kBlock / (2 * kMaxDepth)][2 * kMaxDepth];
+// One workgroup: reduce the partials (64 interleaved slices with every load
+// in flight at once, then the slices in order), update the Gram matrix, and
+// solve (G + δI) γ = b over the window by Cholesky.
+__global__ __launch_bounds__(kAaSolveBlock) void k_aa_solve(AaWs w, int m, int n_blk,
+                                                           const Ctrl* ctrl) {
+  constexpr int kCols = 2 * kMaxDepth;
+  constexpr int kSlices = kAaSolveBlock / kCols;
+  constexpr int kPer = kAaGrid / kSlices;  // partial rows per slice at most
+  __shared__ double v[kCols];
+  __shared__ double slice[kSlices][kCols];
   if (ctrl->done) return;
   AaState* st = w.st;
   // every thread reads the state before thread 0 changes it
@@ -160,14 +176,19 @@ __global__ __launch_bounds__(kBlock) void k_aa_solve(AaWs w, int m, int n_blk, c
     return;
   }
   {
-    constexpr int kSlices = kBlock / (2 * kMaxDepth);
-    const int q = threadIdx.x % (2 * kMaxDepth), sl = threadIdx.x / (2 * kMaxDepth);
+    const int q = threadIdx.x % kCols, sl = threadIdx.x / kCols;
+    double part[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int b = sl + k * kSlices;
+      part[k] = (q % kMaxDepth) < cnt && b < n_blk ? w.part[int64_t(b) * kCols + q] : 0.0;
+    }
     double s = 0.0;
-    if ((q % kMaxDepth) < cnt)
-      for (int b = sl; b < n_blk; b += kSlices) s += w.part[int64_t(b) * 2 * kMaxDepth + q];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) s += part[k];
     slice[sl][q] = s;
     __syncthreads();
-    if (threadIdx.x < 2 * kMaxDepth) {
+    if (threadIdx.x < kCols) {
       double t = 0.0;
       for (int k = 0; k < kSlices; ++k) t += slice[k][threadIdx.x];
       v[threadIdx.x] = t;
@@ -357,10 +378,14 @@ psi_status solve_anderson(psi_operator* op, const psi_params* prm, int depth, co
     a.count_iter = 1;
     a.respect_done = 1;
     a.ctrl = op->ctrl;
+    a.defer_gap = 1;  // pairs in gap_part, decided by k_aa_diff
+    a.gap_prev = op->gap_part + 2 * kMaxGrid;  // nothing is ever pending there
     psi_status r = pass(kStep64, a);
     if (r != PSI_OK) return r;
-    hipLaunchKernelGGL(k_aa_diff, dim3(dgrid), dim3(kBlock), 0, st, Gb, X, n, depth, w, op->ctrl);
-    hipLaunchKernelGGL(k_aa_solve, dim3(1), dim3(kBlock), 0, st, w, depth, dgrid, op->ctrl);
+    hipLaunchKernelGGL(k_aa_diff, dim3(dgrid), dim3(kBlock), 0, st, Gb, X, n, depth, w, op->ctrl,
+                       op->gap_part, op->hist);
+    hipLaunchKernelGGL(k_aa_solve, dim3(1), dim3(kAaSolveBlock), 0, st, w, depth, dgrid,
+                       op->ctrl);
     hipLaunchKernelGGL(k_aa_mix, dim3(grid_for(n)), dim3(kBlock), 0, st, Gb, op->invden, n, depth,
                        w, X, zX, op->ctrl);
     PSI_HIP_CHECK(hipGetLastError());

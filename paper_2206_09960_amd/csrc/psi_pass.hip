@@ -49,12 +49,6 @@ namespace psi {
 
 namespace {
 
-__device__ inline void st_agent(double* p, double x) {
-  __hip_atomic_store(reinterpret_cast<unsigned long long*>(p),
-                     static_cast<unsigned long long>(__double_as_longlong(x)), __ATOMIC_RELAXED,
-                     __HIP_MEMORY_SCOPE_AGENT);
-}
-
 // Wait (bounded) until a slot is filled, take its value and empty it again.
 // The writer fills the slot before the reader can need it (see the kernels),
 // so the wait is short; the bound only guarantees the kernel ends.
@@ -71,25 +65,6 @@ __device__ inline double take_slot(double* p, Ctrl* ctrl) {
   }
   __hip_atomic_store(q, kEmptySlot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   return __longlong_as_double(static_cast<long long>(v));
-}
-
-// Fixed-order sum over the workgroup of two values; result in thread 0.
-__device__ inline void block_sum2(double& a, double& b, double* sh) {
-  for (int off = 32; off > 0; off >>= 1) {
-    a += __shfl_down(a, off, 64);
-    b += __shfl_down(b, off, 64);
-  }
-  const int w = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) {
-    sh[2 * w] = a;
-    sh[2 * w + 1] = b;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    a = (sh[0] + sh[2]) + (sh[4] + sh[6]);
-    b = (sh[1] + sh[3]) + (sh[5] + sh[7]);
-  }
-  __syncthreads();
 }
 
 // The CSR a group of workgroups walks: the whole of CSR(Aᵀ), or one column
@@ -477,64 +452,6 @@ __device__ inline void take_pairs(double* base, int count, Ctrl* ctrl, double& G
     G += __shfl_down(G, off, 64);
     S += __shfl_down(S, off, 64);
   }
-}
-
-// The termination decision on the reduced gap (thread 0): the iteration
-// count, the gap in tol_mode units, its history, and done/status.
-__device__ void decide_gap(Ctrl* c, double G, double S, double* hist, double* gap_out,
-                           int count_iter, int done_pass) {
-  if (gap_out) *gap_out = G;
-  if (!count_iter) return;
-  double gap = G;
-  if (c->tol_mode == PSI_TOL_BNORM) gap = G * c->bnorm;
-  else if (c->tol_mode == PSI_TOL_REL_L1) gap = S > 0.0 ? G / S : G;
-  const int it = c->iter + 1;
-  c->iter = it;
-  c->gap = gap;
-  c->l1 = G;
-  c->snorm = S;
-  if (hist && it - 1 < kHistLen) hist[it - 1] = gap;
-  int st = -1;
-  if (!isfinite(gap)) st = PSI_ENUMERIC;
-  else if (gap <= c->tol) st = PSI_OK;
-  else if (it >= c->max_iter) st = PSI_ENOTCONV;
-  if (st >= 0) {
-    c->status = st;
-    c->done_pass = done_pass;
-    c->done = 1;
-  }
-}
-
-// Deferred gap, the whole workgroup: the c->pending pairs a previous kernel
-// left in `pairs` (complete, since that kernel has ended), summed in
-// workgroup order — thread t a contiguous run, then a fixed tree — and
-// decided as pass `pass_id`; the slots are emptied again.  Pairs of a pass
-// that ran after the decision (its workgroups could not see it) are only
-// emptied.
-__device__ void take_deferred(Ctrl* c, double* pairs, double* hist, int count_iter, int pass_id,
-                              double* red) {
-  const int n = static_cast<int>(c->pending);  // uniform
-  if (n == 0) return;
-  const int already = c->done;                  // uniform
-  const int tid = threadIdx.x;
-  const int per = (n + kBlock - 1) / kBlock;
-  const int q_end = min(n, (tid + 1) * per);
-  double G = 0.0, S = 0.0;
-  for (int q = tid * per; q < q_end; ++q) {
-    unsigned long long* p = reinterpret_cast<unsigned long long*>(pairs + 2 * q);
-    G += __longlong_as_double(static_cast<long long>(
-        __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
-    S += __longlong_as_double(static_cast<long long>(
-        __hip_atomic_load(p + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
-    __hip_atomic_store(p, kEmptySlot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(p + 1, kEmptySlot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-  block_sum2(G, S, red);
-  if (tid == 0) {
-    c->pending = 0;
-    if (!already) decide_gap(c, G, S, hist, nullptr, count_iter, pass_id);
-  }
-  __syncthreads();
 }
 
 // One partial per workgroup (g, sn).  Deferred form: the pair is stored and
