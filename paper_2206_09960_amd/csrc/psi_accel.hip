@@ -90,15 +90,6 @@ __global__ void k_aa_init(AaState* s) {
   }
 }
 
-__device__ inline double block_sum(double v, double* red) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) red[wave] = v;
-  __syncthreads();
-  return (red[0] + red[1]) + (red[2] + red[3]);
-}
-
 // f = g − x; the new ΔF, ΔG column at ring slot `head`; f_prev, g_prev ← f, g;
 // partial dot products of every window column (the new one included) with
 // the new ΔF column and with f.
@@ -141,13 +132,27 @@ __global__ __launch_bounds__(kBlock) void k_aa_diff(const double* g, const doubl
     w.g_prev[i] = gi;
   }
   if (!valid) return;  // uniform: no dot products on the first iteration
-  for (int q = 0; q < cnt; ++q) {
-    const double a = block_sum(vv[q], red);
-    const double b = block_sum(vb[q], red);
-    if (threadIdx.x == 0) {
-      w.part[int64_t(blockIdx.x) * 2 * kMaxDepth + q] = a;
-      w.part[int64_t(blockIdx.x) * 2 * kMaxDepth + kMaxDepth + q] = b;
+  // all 2m sums at once: wave shuffles, one LDS round, waves added in order
+  __shared__ double wsum[kBlock / 64][2 * kMaxDepth];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < kMaxDepth; ++q) {
+    if (q >= cnt) break;  // uniform
+    double a = vv[q], b = vb[q];
+    for (int off = 32; off > 0; off >>= 1) {
+      a += __shfl_down(a, off, 64);
+      b += __shfl_down(b, off, 64);
     }
+    if (lane == 0) {
+      wsum[wave][q] = a;
+      wsum[wave][kMaxDepth + q] = b;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 2 * kMaxDepth && (threadIdx.x % kMaxDepth) < cnt) {
+    const int q = threadIdx.x;
+    w.part[int64_t(blockIdx.x) * 2 * kMaxDepth + q] =
+        (wsum[0][q] + wsum[1][q]) + (wsum[2][q] + wsum[3][q]);
   }
 }
 
@@ -195,13 +200,22 @@ __global__ __launch_bounds__(kAaSolveBlock) void k_aa_solve(AaWs w, int m, int n
     }
     __syncthreads();
   }
+  // the window's state in LDS; thread 0 then works there (no scratch, no
+  // dependent global loads)
+  __shared__ double Gs[kMaxDepth][kMaxDepth];
+  __shared__ double Ls[kMaxDepth][kMaxDepth];
+  __shared__ double ys[kMaxDepth];
+  if (threadIdx.x < kMaxDepth * kMaxDepth)
+    Gs[threadIdx.x / kMaxDepth][threadIdx.x % kMaxDepth] =
+        st->G[threadIdx.x / kMaxDepth][threadIdx.x % kMaxDepth];
+  __syncthreads();
   if (threadIdx.x != 0) return;
   const int slot = st->head;
   // column / row of the new slot; window column q sits at slot (slot − q) mod m
   for (int k = 0; k < cnt; ++k) {
     const int sj = (slot - k + m) % m;
-    st->G[slot][sj] = v[k];
-    st->G[sj][slot] = v[k];
+    Gs[slot][sj] = v[k];
+    Gs[sj][slot] = v[k];
   }
   st->head = (slot + 1) % m;
   st->count = cnt;
@@ -209,48 +223,50 @@ __global__ __launch_bounds__(kAaSolveBlock) void k_aa_solve(AaWs w, int m, int n
   bool ok = gap <= 10.0 * st->best;
   if (gap < st->best) st->best = gap;
   // Cholesky of the window's Gram matrix (order: newest first) with a shift
-  double L[kMaxDepth][kMaxDepth];
-  double y[kMaxDepth];
   double tr = 0.0;
   for (int a = 0; a < cnt; ++a) {
     const int sa = (slot - a + m) % m;
-    tr += st->G[sa][sa];
+    tr += Gs[sa][sa];
   }
   const double shift = 1e-13 * tr / cnt;
   for (int a = 0; a < cnt && ok; ++a) {
     const int sa = (slot - a + m) % m;
     for (int b = 0; b <= a; ++b) {
       const int sb = (slot - b + m) % m;
-      double s = st->G[sa][sb] + (a == b ? shift : 0.0);
-      for (int k = 0; k < b; ++k) s -= L[a][k] * L[b][k];
+      double sum = Gs[sa][sb] + (a == b ? shift : 0.0);
+      for (int k = 0; k < b; ++k) sum -= Ls[a][k] * Ls[b][k];
       if (a == b) {
-        if (!(s > 0.0) || !isfinite(s)) {
+        if (!(sum > 0.0) || !isfinite(sum)) {
           ok = false;
           break;
         }
-        L[a][a] = sqrt(s);
+        Ls[a][a] = sqrt(sum);
       } else {
-        L[a][b] = s / L[b][b];
+        Ls[a][b] = sum / Ls[b][b];
       }
     }
   }
-  for (int j = 0; j < kMaxDepth; ++j) st->gamma[j] = 0.0;
-  if (!ok) {  // clear the window: the next step is a plain Power-ψ step
+  if (ok) {
+    for (int a = 0; a < cnt; ++a) {  // L y = b
+      double sum = v[kMaxDepth + a];
+      for (int k = 0; k < a; ++k) sum -= Ls[a][k] * ys[k];
+      ys[a] = sum / Ls[a][a];
+    }
+    for (int a = cnt - 1; a >= 0; --a) {  // Lᵀ γ = y
+      double sum = ys[a];
+      for (int k = a + 1; k < cnt; ++k) sum -= Ls[k][a] * ys[k];
+      ys[a] = sum / Ls[a][a];
+    }
+  } else {  // clear the window: the next step is a plain Power-ψ step
     st->count = 0;
     st->restarts += 1;
-    return;
   }
-  for (int a = 0; a < cnt; ++a) {  // L y = b
-    double s = v[kMaxDepth + a];
-    for (int k = 0; k < a; ++k) s -= L[a][k] * y[k];
-    y[a] = s / L[a][a];
-  }
-  for (int a = cnt - 1; a >= 0; --a) {  // Lᵀ γ = y
-    double s = y[a];
-    for (int k = a + 1; k < cnt; ++k) s -= L[k][a] * y[k];
-    y[a] = s / L[a][a];
-    st->gamma[(slot - a + m) % m] = y[a];
-  }
+  // window column a sits at ring slot (slot − a) mod m; slots outside it get γ = 0
+  for (int sj = 0; sj < kMaxDepth; ++sj) st->gamma[sj] = 0.0;
+  if (ok)
+    for (int a = 0; a < cnt; ++a) st->gamma[(slot - a + m) % m] = ys[a];
+  for (int i = 0; i < kMaxDepth; ++i)
+    for (int j = 0; j < kMaxDepth; ++j) st->G[i][j] = Gs[i][j];
 }
 
 // x_{k+1} = g_k − ΔG γ and its gathered form z = x/den.
