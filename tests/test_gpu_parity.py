@@ -287,6 +287,39 @@ def test_solve_fp64_matches_oracle(gpu_lib, name, make, tol):
     assert oracle.fixed_point_residual(A, c, s_np) <= tol * 1.5 + 1e-15 * np.abs(s_np).sum()
 
 
+@pytest.mark.parametrize("segs,form", [(1, "auto"), (4, "slices"), (4, "tiles")])
+def test_deferred_decision_stops_at_the_first_step_under_tol(gpu_lib, segs, form):
+    """The solve loop decides each pass's gap in the next pass (deferred);
+    single psi_step calls reduce it inside the pass.  Both run the same
+    kernels, so the solve must stop exactly at the first step whose gap is
+    at most tol, with that step's iterate bit for bit — one pass later would
+    overshoot, a missed decision would run on."""
+    api = gpu_lib
+    g = synth.chung_lu(50_000, 12, 2.2, 61, sigma=1.5)
+    op = gpu_op(api, g)
+    A, B, c, d = oracle.operator(g.n, g.follower, g.leader, g.lam, g.mu)
+    tol = 1e-9
+    s = torch.tensor(c, device="cuda")
+    t = 0
+    while True:
+        s_next, gap = op.step(s, tile_items=2048, col_segments=segs, seg_form=form)
+        torch.cuda.synchronize()
+        t += 1
+        s = s_next
+        if gap.item() <= tol:
+            break
+        assert t < 500
+    psi, s_solve, info = op.solve(tol=tol, tile_items=2048, col_segments=segs, seg_form=form,
+                                  return_s=True)
+    assert info["status"] == 0, info
+    assert info["iterations"] == t and info["spmv_passes"] == t + 1
+    assert torch.equal(s_solve, s)
+    for check_every in (1, 3, 64):  # batch ends at every step, mid-run, or past convergence
+        _, s2, info2 = op.solve(tol=tol, tile_items=2048, col_segments=segs, seg_form=form,
+                                check_every=check_every, return_s=True)
+        assert info2["iterations"] == t and torch.equal(s2, s), (check_every, info2)
+
+
 def test_star_hub_closed_form(gpu_lib):
     """One 3M-long row: ψ_h = d_h(1 + Σ_{j≠h} c_j)/N, ψ_j = d_j/N."""
     api = gpu_lib
