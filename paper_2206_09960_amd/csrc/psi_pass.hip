@@ -19,8 +19,11 @@
 // partials, in tile order, by the workgroup that owns the tile where the row
 // ends; partials travel through coherent slots (see take_slot), so no cache
 // flush or floating-point atomic is needed and every pass is bitwise
-// repeatable.  The gap is one partial per workgroup, summed in workgroup order
-// by the last workgroup to finish, which also decides termination.
+// repeatable.  The gap is one partial per workgroup.  A single pass sums the
+// partials itself (the last workgroup to finish adds them in workgroup order
+// and decides termination); in the solve loop the pass only stores them and
+// workgroup 0 of the next pass sums them and decides (deferred: see
+// take_deferred), so no pass ends with a chain of device-scope round trips.
 //
 // Column-segmented passes (S = 2, 4, 8).  The gather of x is limited by the
 // rate at which the caches serve random lines, and that rate roughly doubles

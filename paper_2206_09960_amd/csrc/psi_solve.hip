@@ -2,9 +2,10 @@
 //
 // The host only enqueues passes and, every few passes, reads a pinned copy of
 // the device control block; the gap test of eq. (condition) is made on the
-// device by the last tile of each pass, and passes enqueued after it exit at
-// once.  The number of passes between host checks is predicted from the
-// observed geometric decay of the gap.
+// device — for a pass of the solve loop by workgroup 0 of the next pass (or by
+// a one-workgroup kernel at the end of a batch) — and passes after the one
+// that met it exit at once.  The number of passes between host checks is
+// predicted from the observed geometric decay of the gap.
 //
 // PSI_PREC_MIXED refines in FP64 around FP32 correction solves: with
 // r = Aᵀs + c − s computed in FP64 (one FP64 pass, whose L1 norm is also the
