@@ -74,13 +74,15 @@ def algorithmic_bytes(kind: str, n: int, m: int, segs: int = 1) -> int:
 
 
 def source_hash() -> str:
-    """Hash of the source that defines the pass kernels whose HBM traffic the
-    committed counter summaries record."""
+    """Hash of the code (comments and blank lines left out) of the source that
+    defines the pass kernels whose HBM traffic the committed counter summaries
+    record."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2206_09960_amd", "csrc")
     for f in ("psi_pass.hip",):
-        with open(os.path.join(csrc, f), "rb") as fh:
-            h.update(f.encode() + fh.read())
+        with open(os.path.join(csrc, f), encoding="utf-8") as fh:
+            code = [ln.split("//", 1)[0].rstrip() for ln in fh]
+        h.update(f.encode() + "\n".join(ln for ln in code if ln).encode())
     return h.hexdigest()[:16]
 
 
