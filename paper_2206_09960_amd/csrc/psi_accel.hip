@@ -422,6 +422,10 @@ psi_status solve_anderson(psi_operator* op, const psi_params* prm, int depth, co
     enq += cnt;
     PSI_HIP_CHECK(hipMemcpyAsync(h, op->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
     PSI_HIP_CHECK(hipStreamSynchronize(st));
+    if (h->err_flags & kErrSlotTimeout) {  // never expected: a bounded wait gave up
+      set_error("a cross-workgroup partial did not arrive in time; the pass is invalid");
+      return PSI_EDEVICE;
+    }
     if (h->done) {
       status = h->status;
       break;

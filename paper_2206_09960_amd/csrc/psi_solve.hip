@@ -177,6 +177,10 @@ psi_status iterate(psi_operator* op, int S, int ctrl_idx, PassMode mode, Make ma
     }
     PSI_HIP_CHECK(hipMemcpyAsync(hctrl, dctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
     PSI_HIP_CHECK(hipStreamSynchronize(st));
+    if (hctrl->err_flags & kErrSlotTimeout) {  // never expected: a bounded wait gave up
+      set_error("a cross-workgroup partial did not arrive in time; the pass is invalid");
+      return PSI_EDEVICE;
+    }
     out->iters = hctrl->iter;
     out->gap = hctrl->gap;
     out->l1 = hctrl->l1;
