@@ -21,8 +21,9 @@
 // whole into wave tiles of about kWaveItems merge-path items; a wave sums its
 // rows edge by edge in order.  Longer rows are cut into chunks of kChunkEdges
 // edges; a workgroup reduces each chunk in a fixed order and a finishing
-// kernel adds a row's chunks in chunk order.  Every sum has a fixed order, so
-// batched solves are bitwise repeatable.
+// kernel adds a row's chunks in chunk order.  A pass's per-scenario gap is
+// summed in two fixed-order levels.  Every sum has a fixed order, so batched
+// solves are bitwise repeatable.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -37,6 +38,8 @@ constexpr int kWaveItems = 256;    // merge-path items per wave tile
 constexpr int kHubEdges = 256;     // rows longer than this are chunked
 constexpr int kChunkEdges = 1024;  // edges per hub chunk
 constexpr int kMaxK = 64;          // scenarios per batch tile (one per lane)
+constexpr int kHubFinGrid = 1024;  // largest grid of the hub-finishing kernel
+constexpr int kGapParts = 64;      // first-level partials of a pass's gaps
 
 inline unsigned grid_for(int64_t n, int block = kBlock) {
   return static_cast<unsigned>((n + block - 1) / block);
@@ -64,7 +67,8 @@ struct BatchWs {
   uint32_t* scan_tmp;
   double* chunk_part;  // [max_chunks × Kc]
   double* gap_blk;     // [kMaxGrid × Kc]
-  double* gap_hub;     // [max_hubs × Kc]
+  double* gap_hub;     // [kHubFinGrid × Kc]
+  double* gap_lvl;     // [kGapParts × Kc]
   BatchCtrl* ctrl;
   int* origin;         // [kMaxK] origins of the current tile (origin mode)
   BatchCtrl* host_ctrl;  // not in the workspace
@@ -101,7 +105,8 @@ size_t batch_layout(int64_t n, int64_t m, BatchWs* w, char* base) {
   t.scan_tmp = (uint32_t*)take(4 * size_t(scan_tile_count(n + 1) + 8));
   t.chunk_part = (double*)take(8 * size_t(max_chunks) * kMaxK);
   t.gap_blk = (double*)take(8 * size_t(kMaxGrid) * kMaxK);
-  t.gap_hub = (double*)take(8 * size_t(max_hubs) * kMaxK);
+  t.gap_hub = (double*)take(8 * size_t(kHubFinGrid) * kMaxK);
+  t.gap_lvl = (double*)take(8 * size_t(kGapParts) * kMaxK);
   t.ctrl = (BatchCtrl*)take(sizeof(BatchCtrl));
   t.origin = (int*)take(4 * size_t(kMaxK));
   t.n_wtiles = n_wtiles;
@@ -233,6 +238,7 @@ struct BArgs {
   double* chunk_part;
   double* gap_blk;
   double* gap_hub;
+  double* gap_lvl;
   BatchCtrl* ctrl;
   const int* origin;   // origin mode: the origin of each lane
 };
@@ -240,39 +246,63 @@ struct BArgs {
 // Kernel modes: a scenario step, the scenarios' final ψ pass, an origin step.
 enum : int { kScen = 0, kScenFinal = 1, kOrig = 2 };
 
-// Epilogue of row r for scenario k; a scenario that has met its tolerance
-// keeps its iterate (and contributes no gap).
+// Epilogue inputs of row r for scenario k, loaded before the row's gathers.
+// A scenario that has met its tolerance keeps its iterate, so it reads its s
+// and z instead of the coefficients.
+struct BRow {
+  double a0, a1, a2, so;
+};
+
 template <int BM>
-__device__ inline void bepi(const BArgs& a, int r, int k, double y, bool frozen, double& gap) {
+__device__ inline BRow bload(const BArgs& a, int r, int k, bool frozen) {
+  const int64_t t = int64_t(r) * a.Kc + k;
+  BRow in{0.0, 0.0, 0.0, 0.0};
+  if constexpr (BM == kScenFinal) {
+    in.a0 = a.lam[t];
+    in.a1 = a.d[t];
+  } else {
+    in.so = a.s_old[t];
+    if (frozen) {
+      in.a0 = a.z[t];
+    } else if constexpr (BM == kOrig) {  // shared 1/den, μ of the operator, indexed by user
+      in.a1 = a.invden[r];
+      in.a2 = a.mu[r];
+    } else {
+      in.a0 = a.c[t];
+      in.a1 = a.mu[t];
+      in.a2 = a.invden[t];
+    }
+  }
+  return in;
+}
+
+// Row r's result for scenario k from its sum y.  Frozen scenarios store their
+// kept iterate (and add no gap), so a wave's stores always cover whole lines.
+template <int BM>
+__device__ inline void bapply(const BArgs& a, int r, int k, const BRow& in, double y, bool frozen,
+                              double& gap) {
   const int64_t t = int64_t(r) * a.Kc + k;
   if constexpr (BM == kScenFinal) {
-    a.psi[int64_t(r) * a.psi_ld + a.psi_col0 + k] = (a.lam[t] * y + a.d[t]) * a.inv_n;
-  } else if constexpr (BM == kOrig) {  // shared μ, 1/den of the operator, indexed by user
-    const double po = a.s_old[t];
-    if (frozen) {
-      a.s_new[t] = po;
-      a.z_new[t] = a.z[t];
-      return;
-    }
-    const double pn = a.invden[r] * y;
-    a.s_new[t] = pn;
-    a.z_new[t] = a.mu[r] * pn;
-    gap += fabs(pn - po);
+    a.psi[int64_t(r) * a.psi_ld + a.psi_col0 + k] = (in.a0 * y + in.a1) * a.inv_n;
   } else {
-    const double so = a.s_old[t];
-    if (frozen) {
-      a.s_new[t] = so;
-      a.z_new[t] = a.z[t];
-      return;
+    double sn, zn;
+    if constexpr (BM == kOrig) {
+      sn = in.a1 * y;   // p = y / den
+      zn = in.a2 * sn;  // μ p, gathered by the next pass
+    } else {
+      sn = in.a0 + in.a1 * y;  // c + μ y
+      zn = in.a2 * sn;         // s / den
     }
-    const double sn = a.c[t] + a.mu[t] * y;
+    if (frozen) {
+      sn = in.so;
+      zn = in.a0;
+    }
     a.s_new[t] = sn;
-    a.z_new[t] = a.invden[t] * sn;
-    gap += fabs(sn - so);
+    a.z_new[t] = zn;
+    if (!frozen) gap += fabs(sn - in.so);
   }
 }
 
-// Rows of at most kHubEdges followers: waves walk the wave tiles grid-stride.
 // Origin mode adds λ_ℓ on the edge whose column is the lane's origin.
 template <int BM>
 __device__ inline double edge_term(const BArgs& a, int j, int k, int org, double lo) {
@@ -281,10 +311,19 @@ __device__ inline double edge_term(const BArgs& a, int j, int k, int org, double
   return v;
 }
 
+// Rows of at most kHubEdges followers: waves walk the wave tiles grid-stride.
+// A wave reads the row ends of up to 63 rows in one load and, when those
+// rows span at most kStage edges (no hub among them), stages their column
+// indices in its slice of LDS; a row's epilogue inputs are loaded before its
+// gathers, and up to 16 gathers are in flight.  A row's edges are added one
+// by one in order.
 template <int BM>
 __global__ __launch_bounds__(kBlock) void k_spmm_rows(BArgs a) {
   constexpr bool FINAL = BM == kScenFinal;
+  constexpr int kB = 16;       // gathers in flight per wave
+  constexpr int kStage = 256;  // staged column indices per wave
   __shared__ double red[kBlock / 64][kMaxK];
+  __shared__ int s_col[kBlock / 64][kStage];
   if (!FINAL && a.ctrl->c.done) return;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -292,27 +331,52 @@ __global__ __launch_bounds__(kBlock) void k_spmm_rows(BArgs a) {
   const bool frozen = !FINAL && a.ctrl->kdone[k];
   const int org = BM == kOrig ? a.origin[k] : -1;
   const double lo = BM == kOrig ? a.lam[org] : 0.0;
+  int* cw = s_col[wave];
   double gap = 0.0;
   const int stride = gridDim.x * (kBlock / 64);
   for (int tile = blockIdx.x * (kBlock / 64) + wave; tile < a.n_wtiles; tile += stride) {
     const int r0 = a.row_tiles[tile], r1 = a.row_tiles[tile + 1];
-    for (int r = r0; r < r1; ++r) {
-      const int e0 = a.row_ptr[r], e1 = a.row_ptr[r + 1];
-      if (e1 - e0 > kHubEdges) continue;  // finished by the hub kernels
-      double y = 0.0;
-      int e = e0;
-      for (; e + 8 <= e1; e += 8) {
-        int j[8];
-        double v[8];
+    for (int rb = r0; rb < r1; rb += 63) {
+      const int nb = min(63, r1 - rb);
+      const int rp = a.row_ptr[rb + min(lane, nb)];  // row rb + i spans [rp_i, rp_{i+1})
+      const int E0 = __builtin_amdgcn_readlane(rp, 0);
+      const int E1 = __builtin_amdgcn_readlane(rp, nb);
+      const bool staged = E1 - E0 <= kStage;
+      if (staged && E1 > E0) {
+        int t[kStage / 64];  // all four loads in flight, then the LDS writes
 #pragma unroll
-        for (int u = 0; u < 8; ++u) j[u] = a.col[e + u];
+        for (int q = 0; q < kStage / 64; ++q) t[q] = a.col[min(E0 + q * 64 + lane, E1 - 1)];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = edge_term<BM>(a, j[u], k, org, lo);
-#pragma unroll
-        for (int u = 0; u < 8; ++u) y += v[u];
+        for (int q = 0; q < kStage / 64; ++q) cw[q * 64 + lane] = t[q];
       }
-      for (; e < e1; ++e) y += edge_term<BM>(a, a.col[e], k, org, lo);
-      if (lane < a.Kc) bepi<BM>(a, r, k, y, frozen, gap);
+      // y of a row from its column indices idx(0 .. len), in order
+      auto row_sum = [&](int len, auto idx) -> double {
+        double y = 0.0;
+        for (int u0 = 0; u0 < len; u0 += kB) {
+          int jj[kB];
+#pragma unroll
+          for (int u = 0; u < kB; ++u) jj[u] = idx(min(u0 + u, len - 1));
+          double v[kB];
+#pragma unroll
+          for (int u = 0; u < kB; ++u) {
+            v[u] = 0.0;
+            if (u0 + u < len) v[u] = edge_term<BM>(a, jj[u], k, org, lo);
+          }
+#pragma unroll
+          for (int u = 0; u < kB; ++u) y += v[u];
+        }
+        return y;
+      };
+      for (int i = 0; i < nb; ++i) {
+        const int e0 = __builtin_amdgcn_readlane(rp, i);
+        const int len = __builtin_amdgcn_readlane(rp, i + 1) - e0;
+        if (len > kHubEdges) continue;  // finished by the hub kernels
+        const int r = rb + i;
+        const BRow in = bload<BM>(a, r, k, frozen);
+        const double y = staged ? row_sum(len, [&](int q) { return cw[e0 - E0 + q]; })
+                                : row_sum(len, [&](int q) { return a.col[e0 + q]; });
+        if (lane < a.Kc) bapply<BM>(a, r, k, in, y, frozen, gap);
+      }
     }
   }
   if constexpr (!FINAL) {
@@ -359,44 +423,80 @@ __global__ __launch_bounds__(kBlock) void k_spmm_hub_chunk(BArgs a) {
         ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
 }
 
-// One wave per hub row: its chunks in chunk order, then the epilogue.
+// Hub rows: wave w of workgroup b finishes hubs 4b + w, 4b + w + 4·grid, ...
+// (a row's chunks in chunk order, 16 loads in flight, then the epilogue).  A
+// wave adds the gaps of its hubs in order and the workgroup adds its waves in
+// order.
 template <int BM>
-__global__ __launch_bounds__(64) void k_spmm_hub_finish(BArgs a) {
+__global__ __launch_bounds__(kBlock) void k_spmm_hub_finish(BArgs a) {
   constexpr bool FINAL = BM == kScenFinal;
+  __shared__ double red[kBlock / 64][kMaxK];
   if (!FINAL && a.ctrl->c.done) return;
-  const int lane = threadIdx.x;
-  const int h = blockIdx.x;
-  if (lane >= a.Kc) return;
-  const bool frozen = !FINAL && a.ctrl->kdone[lane];
-  const int r = a.hub_rows[h];
-  double y = 0.0;
-  for (int ch = a.hub_chunk0[h]; ch < a.hub_chunk0[h + 1]; ++ch)
-    y += a.chunk_part[int64_t(ch) * a.Kc + lane];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int k = lane < a.Kc ? lane : a.Kc - 1;
+  const bool frozen = !FINAL && a.ctrl->kdone[k];
   double gap = 0.0;
-  bepi<BM>(a, r, lane, y, frozen, gap);
-  if constexpr (!FINAL) a.gap_hub[int64_t(h) * a.Kc + lane] = gap;
+  const int stride = gridDim.x * (kBlock / 64);
+  for (int h = blockIdx.x * (kBlock / 64) + wave; h < a.n_hubs; h += stride) {
+    const int r = a.hub_rows[h];
+    const BRow in = bload<BM>(a, r, k, frozen);
+    const int c0 = a.hub_chunk0[h], c1 = a.hub_chunk0[h + 1];
+    double y = 0.0;
+    for (int ch = c0; ch < c1; ch += 16) {
+      double p[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) p[u] = a.chunk_part[int64_t(min(ch + u, c1 - 1)) * a.Kc + k];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) y += ch + u < c1 ? p[u] : 0.0;
+    }
+    if (lane < a.Kc) bapply<BM>(a, r, k, in, y, frozen, gap);
+  }
+  if constexpr (!FINAL) {
+    red[wave][lane] = gap;
+    __syncthreads();
+    if (wave == 0 && lane < a.Kc)
+      a.gap_hub[int64_t(blockIdx.x) * a.Kc + lane] =
+          ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+  }
 }
 
-// Per-scenario gaps in a fixed order (workgroups, then hub rows), tolerance
-// test and freezing; done when every scenario is done.
-__global__ __launch_bounds__(1024) void k_batch_gap(BArgs a, int n_blk) {
-  __shared__ double red[16][kMaxK];
-  __shared__ int n_done;
-  BatchCtrl* bc = a.ctrl;
-  if (bc->c.done) return;  // uniform: read by every thread before any barrier
+// Per-scenario gaps, first level: workgroup p sums a contiguous range of the
+// rows kernel's and then the hub kernel's per-workgroup partials (wave w
+// takes entries w, w + 4, ... of the range in order; then waves in order).
+__global__ __launch_bounds__(kBlock) void k_batch_gap_part(BArgs a, int n_blk, int n_hblk) {
+  __shared__ double red[kBlock / 64][kMaxK];
+  if (a.ctrl->c.done) return;  // uniform
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;  // 16 waves split the partials
+  const int wave = threadIdx.x >> 6;
+  const int64_t total = int64_t(n_blk) + n_hblk;
+  const int b0 = static_cast<int>(total * blockIdx.x / gridDim.x);
+  const int b1 = static_cast<int>(total * (blockIdx.x + 1) / gridDim.x);
   double g = 0.0;
   if (lane < a.Kc) {
-    for (int b = wave; b < n_blk; b += 16) g += a.gap_blk[int64_t(b) * a.Kc + lane];
-    for (int h = wave; h < a.n_hubs; h += 16) g += a.gap_hub[int64_t(h) * a.Kc + lane];
+#pragma unroll 4
+    for (int b = b0 + wave; b < b1; b += 4)
+      g += b < n_blk ? a.gap_blk[int64_t(b) * a.Kc + lane]
+                     : a.gap_hub[int64_t(b - n_blk) * a.Kc + lane];
   }
   red[wave][lane] = g;
-  if (threadIdx.x == 0) n_done = 0;
   __syncthreads();
-  if (wave == 0 && lane < a.Kc) {
+  if (wave == 0 && lane < a.Kc)
+    a.gap_lvl[int64_t(blockIdx.x) * a.Kc + lane] =
+        ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+}
+
+// Second level, one wave: lane k adds scenario k's kGapParts partials in
+// order, tests the tolerance and freezes; done when every scenario is done.
+__global__ __launch_bounds__(64) void k_batch_gap(BArgs a) {
+  BatchCtrl* bc = a.ctrl;
+  if (bc->c.done) return;  // uniform
+  const int lane = threadIdx.x;
+  int done = 1;
+  if (lane < a.Kc) {
     double G = 0.0;
-    for (int w = 0; w < 16; ++w) G += red[w][lane];
+#pragma unroll 8
+    for (int p = 0; p < kGapParts; ++p) G += a.gap_lvl[int64_t(p) * a.Kc + lane];
     if (!bc->kdone[lane]) {
       const int it = bc->kiter[lane] + 1;
       bc->kiter[lane] = it;
@@ -412,12 +512,12 @@ __global__ __launch_bounds__(1024) void k_batch_gap(BArgs a, int n_blk) {
         bc->kstatus[lane] = PSI_ENOTCONV;
       }
     }
-    if (bc->kdone[lane]) atomicAdd(&n_done, 1);
+    done = bc->kdone[lane];
   }
-  __syncthreads();
-  if (threadIdx.x == 0) {
+  const int all = __all(done);
+  if (lane == 0) {
     bc->c.iter += 1;
-    if (n_done == a.Kc) bc->c.done = 1;
+    if (all) bc->c.done = 1;
   }
 }
 
@@ -547,6 +647,18 @@ __global__ void k_graph_init(const double* c, const double* invden, int64_t n, i
   }
 }
 
+// Hub-finishing grid: four hubs per workgroup, at most kHubFinGrid workgroups.
+int hub_finish_grid(int64_t n_hubs) {
+  return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(kHubFinGrid, (n_hubs + 3) / 4)));
+}
+
+// The gap of a pass: kGapParts first-level sums of the n_blk rows-kernel and
+// n_hblk hub-kernel partials, then one wave decides.
+void launch_batch_gap(const BArgs& a, int n_blk, int n_hblk, hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_gap_part, dim3(kGapParts), dim3(kBlock), 0, st, a, n_blk, n_hblk);
+  hipLaunchKernelGGL(k_batch_gap, dim3(1), dim3(64), 0, st, a);
+}
+
 int rows_grid() {
   static int cap = 0;
   if (!cap) {
@@ -652,6 +764,7 @@ psi_status solve_batched(psi_operator* op, const psi_params* prm, int K, const d
                               hipHostMallocDefault));
   w.host_ctrl = pinned.p;
   const int grid = std::min(rows_grid(), static_cast<int>(n_wtiles));
+  const int hgrid = hub_finish_grid(n_hubs);
   EventPair evp;
   PSI_HIP_CHECK(hipEventCreate(&evp.a));
   PSI_HIP_CHECK(hipEventCreate(&evp.b));
@@ -691,6 +804,7 @@ psi_status solve_batched(psi_operator* op, const psi_params* prm, int K, const d
     base.chunk_part = w.chunk_part;
     base.gap_blk = w.gap_blk;
     base.gap_hub = w.gap_hub;
+    base.gap_lvl = w.gap_lvl;
     base.ctrl = w.ctrl;
     auto pass = [&](int i, bool final_pass) -> psi_status {
       BArgs a = base;
@@ -707,13 +821,13 @@ psi_status solve_batched(psi_operator* op, const psi_params* prm, int K, const d
         if (n_chunks)
           hipLaunchKernelGGL(k_spmm_hub_chunk<kScenFinal>, dim3(n_chunks), dim3(kBlock), 0, st, a);
         if (n_hubs)
-          hipLaunchKernelGGL(k_spmm_hub_finish<kScenFinal>, dim3(n_hubs), dim3(64), 0, st, a);
+          hipLaunchKernelGGL(k_spmm_hub_finish<kScenFinal>, dim3(hgrid), dim3(kBlock), 0, st, a);
       } else {
         hipLaunchKernelGGL(k_spmm_rows<kScen>, dim3(grid), dim3(kBlock), 0, st, a);
         if (n_chunks)
           hipLaunchKernelGGL(k_spmm_hub_chunk<kScen>, dim3(n_chunks), dim3(kBlock), 0, st, a);
-        if (n_hubs) hipLaunchKernelGGL(k_spmm_hub_finish<kScen>, dim3(n_hubs), dim3(64), 0, st, a);
-        hipLaunchKernelGGL(k_batch_gap, dim3(1), dim3(1024), 0, st, a, grid);
+        if (n_hubs) hipLaunchKernelGGL(k_spmm_hub_finish<kScen>, dim3(hgrid), dim3(kBlock), 0, st, a);
+        launch_batch_gap(a, grid, n_hubs ? hgrid : 0, st);
       }
       PSI_HIP_CHECK(hipGetLastError());
       return PSI_OK;
@@ -898,6 +1012,7 @@ psi_status solve_origins(psi_operator* op, const psi_params* prm, int K, const i
                               hipHostMallocDefault));
   BatchCtrl* h = pinned.p;
   const int grid = std::min(rows_grid(), static_cast<int>(sc.n_wtiles));
+  const int hgrid = hub_finish_grid(sc.n_hubs);
   const int cgrid = static_cast<int>(std::min<int64_t>(kMaxGrid, (n + 3) / 4));
   EventPair evp;
   PSI_HIP_CHECK(hipEventCreate(&evp.a));
@@ -930,6 +1045,7 @@ psi_status solve_origins(psi_operator* op, const psi_params* prm, int K, const i
     base.chunk_part = w.chunk_part;
     base.gap_blk = w.gap_blk;
     base.gap_hub = w.gap_hub;
+    base.gap_lvl = w.gap_lvl;
     base.ctrl = w.ctrl;
     base.origin = w.origin;
     // pass i reads buffer set i % 2 and writes the other; pass 0 turns P = 0 into P = B
@@ -944,8 +1060,9 @@ psi_status solve_origins(psi_operator* op, const psi_params* prm, int K, const i
       hipLaunchKernelGGL(k_spmm_rows<kOrig>, dim3(grid), dim3(kBlock), 0, st, a);
       if (sc.n_chunks)
         hipLaunchKernelGGL(k_spmm_hub_chunk<kOrig>, dim3(sc.n_chunks), dim3(kBlock), 0, st, a);
-      if (sc.n_hubs) hipLaunchKernelGGL(k_spmm_hub_finish<kOrig>, dim3(sc.n_hubs), dim3(64), 0, st, a);
-      if (gap) hipLaunchKernelGGL(k_batch_gap, dim3(1), dim3(1024), 0, st, a, grid);
+      if (sc.n_hubs)
+        hipLaunchKernelGGL(k_spmm_hub_finish<kOrig>, dim3(hgrid), dim3(kBlock), 0, st, a);
+      if (gap) launch_batch_gap(a, grid, sc.n_hubs ? hgrid : 0, st);
       PSI_HIP_CHECK(hipGetLastError());
       return PSI_OK;
     };

@@ -71,6 +71,40 @@ def test_scenarios_star_hub_closed_form(gpu_lib):
         np.testing.assert_allclose(psi[:, s], expect, rtol=1e-12, atol=0)
 
 
+def test_scenarios_row_length_boundaries(gpu_lib):
+    """Rows whose follower counts sit on the batched kernels' boundaries: 16
+    gathers in flight, 64 indices per register load, 256 staged indices and
+    the 256-follower hub limit (rows above it are chunked)."""
+    api = gpu_lib
+    n = 6000
+    lengths = [0, 1, 2, 15, 16, 17, 31, 32, 33, 63, 64, 65, 127, 128, 129, 255, 256, 257, 300,
+               1024, 1025, 3000]
+    rng = np.random.default_rng(49)
+    follower, leader = [], []
+    for i in range(400):
+        cnt = lengths[i % len(lengths)]
+        fol = rng.choice(n - 1, cnt, replace=False)
+        fol[fol >= i] += 1  # no self-loops
+        follower.append(fol)
+        leader.append(np.full(cnt, i))
+    # a sparse background so every user has some leader
+    bg_f = rng.integers(0, n, 20000)
+    bg_l = rng.integers(400, n, 20000)
+    keep = bg_f != bg_l
+    follower = np.concatenate(follower + [bg_f[keep]]).astype(np.int32)
+    leader = np.concatenate(leader + [bg_l[keep]]).astype(np.int32)
+    lam, mu = scenarios(n, 3, 50)
+    op = api.Operator(n, follower, leader, lam[:, 0], mu[:, 0])
+    psi, infos = op.solve_batched(torch.tensor(lam), torch.tensor(mu), tol=1e-11)
+    psi = psi.cpu().numpy()
+    for s in range(3):
+        A, B, c, d = oracle.operator(n, follower, leader, lam[:, s], mu[:, s])
+        r = oracle.power_psi(A, B, c, d, 1e-11)
+        assert infos[s]["status"] == 0
+        assert abs(infos[s]["iterations"] - r["iterations"]) <= 1
+        assert oracle.rel_l1(r["psi"], psi[:, s]) <= 1e-9, s
+
+
 def test_scenarios_invalid_and_statuses(gpu_lib):
     api = gpu_lib
     g = synth.chung_lu(5000, 10, 2.2, 47)
@@ -93,7 +127,8 @@ def subgraph(g, k):
     return synth.Graph(hi - lo, g.follower[sel] - lo, g.leader[sel] - lo, g.lam[lo:hi], g.mu[lo:hi])
 
 
-@pytest.mark.parametrize("n_graphs,lo,hi", [(7, 500, 3000), (256, 100, 400)])
+@pytest.mark.parametrize("n_graphs,lo,hi", [(7, 500, 3000), (256, 100, 400), (3, 20, 40),
+                                             (4, 20000, 40000)])
 def test_graphs_match_oracle_and_lone_solves(gpu_lib, n_graphs, lo, hi):
     api = gpu_lib
     g = synth.multi_graph(n_graphs, lo, hi, 8, 2.2, seed=51, sigma=1.5)
