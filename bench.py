@@ -352,6 +352,17 @@ def run_batched(args, name):
         ms1, (_, info1) = timed(lambda: single.solve(tol=tol), max(1, args.steps // 2), 1)
         ref = dict(single_solve_ms=round(ms1, 3), single_passes=info1["spmv_passes"],
                    sequential_estimate_ms=round(ms1 * k, 2))
+        del single
+        # the same batch with FP32 corrections refined in FP64 (reported beside)
+        ms_m, (psi_m, infos_m) = timed(
+            lambda: op.solve_batched(lam_t, mu_t, tol=tol, precision="mixed"),
+            max(1, args.steps // 2), 1)
+        assert all(i["status"] == 0 for i in infos_m), [i["status_name"] for i in infos_m][:5]
+        ref["mixed"] = dict(ms=round(ms_m, 3),
+                            fp64_passes_max=int(max(i["iterations"] for i in infos_m)),
+                            fp32_passes_max=int(max(i["fp32_passes"] for i in infos_m)),
+                            rel_l1_vs_fp64=float((psi_m - psi).abs().sum() / psi.abs().sum()))
+        del psi_m
     else:
         ms, (psi, infos) = timed(lambda: op.solve_graphs(tol=tol), args.steps, args.warmup)
         units = len(infos)

@@ -210,8 +210,11 @@ psi_status psi_step(psi_operator* op, int32_t precision, const double* s_in, dou
  * s, psi_out: device FP64 [N]. */
 psi_status psi_final(psi_operator* op, const double* s, double* psi_out, void* stream);
 
-/* Device workspace (bytes) of psi_solve_batched on this operator. */
-psi_status psi_batched_workspace_size(const psi_operator* op, int32_t n_scenarios, size_t* bytes);
+/* Device workspace (bytes) of psi_solve_batched on this operator, for
+ * precision PSI_PREC_FP64 or PSI_PREC_MIXED (scenario mode; the FP32
+ * correction blocks add 28 bytes per user and scenario of a tile). */
+psi_status psi_batched_workspace_size(const psi_operator* op, int32_t n_scenarios,
+                                      int32_t precision, size_t* bytes);
 
 /* Many independent Power-ψ solves in one call.
  * Scenario mode (n_scenarios = K ≥ 1, lambda and mu given): K activity
@@ -228,8 +231,15 @@ psi_status psi_batched_workspace_size(const psi_operator* op, int32_t n_scenario
  * own gap (over its users), stops at its own tolerance (and is frozen) and
  * its ψ uses its own N; psi_out (device [n_users]) holds every graph's ψ at
  * its users' positions, infos[g] (host, may be NULL) graph g's result.
- * Both modes: only PSI_PREC_FP64 and PSI_TOL_ABS_L1; returns the first
- * non-OK scenario/graph status, if any.
+ * Scenario mode also takes PSI_PREC_MIXED: each refinement is one FP64
+ * residual pass r = Aᵀs + c − s for every scenario (‖r‖₁ is its gap, the
+ * stopping test), then the FP32 correction solves e = Aᵀe + r of all
+ * unfinished scenarios together, each to prm->inner_tol·‖r‖₁ (0 = 2e-6),
+ * and s ← s + e; when a refinement stops shrinking some scenario's gap
+ * fourfold the batch finishes with FP64 steps.  infos[k].iterations counts
+ * scenario k's FP64 passes, fp32_passes its correction passes.
+ * Both modes: PSI_TOL_ABS_L1 only; graph mode PSI_PREC_FP64 only; returns
+ * the first non-OK scenario/graph status, if any.
  * workspace: device, at least psi_batched_workspace_size bytes (0 in graph
  * mode: the operator's own workspace holds the state). */
 psi_status psi_solve_batched(psi_operator* op, const psi_params* prm, int32_t n_scenarios,

@@ -72,7 +72,7 @@ SIGNATURES = [
     ("psi_step", i32, [vp, i32, vp, vp, vp, i32, i32, i32, vp]),
     ("psi_final", i32, [vp, vp, vp, vp]),
     ("psi_pass_time", i32, [vp, i32, i32, i32, i32, i32, ctypes.POINTER(f64), vp]),
-    ("psi_batched_workspace_size", i32, [vp, i32, ctypes.POINTER(sz)]),
+    ("psi_batched_workspace_size", i32, [vp, i32, i32, ctypes.POINTER(sz)]),
     ("psi_solve_batched", i32, [vp, ctypes.POINTER(Params), i32, vp, vp, vp, ctypes.POINTER(Info),
                                 vp, sz, vp]),
     ("psi_gather_probe", i32, [vp, i64, i32, vp, i64, vp, i32, i32, ctypes.POINTER(f64), vp]),

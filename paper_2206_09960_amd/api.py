@@ -250,18 +250,19 @@ class Operator:
         return p
 
     def solve_batched(self, lam: torch.Tensor, mu: torch.Tensor, tol: float = 1e-8,
-                      max_iter: int = 10000, check_every: int = 0, stream=None,
-                      raise_on_status: bool = False):
+                      max_iter: int = 10000, check_every: int = 0, precision: str = "fp64",
+                      inner_tol: float = 0.0, stream=None, raise_on_status: bool = False):
         """psi_solve_batched, scenario mode: lam, mu [N × K] (one column per
-        scenario); returns (psi [N × K], list of K info dicts)."""
+        scenario); precision "fp64" or "mixed" (FP32 corrections refined in
+        FP64); returns (psi [N × K], list of K info dicts)."""
         lam = lam.to(self.device, torch.float64).contiguous()
         mu = mu.to(self.device, torch.float64).contiguous()
         if lam.dim() != 2 or lam.shape != mu.shape or lam.shape[0] != self.n:
             raise ValueError("lam and mu must both be [n_users, n_scenarios]")
         k = int(lam.shape[1])
-        p = self._params(tol, "abs_l1", max_iter, "fp64", check_every)
+        p = self._params(tol, "abs_l1", max_iter, precision, check_every, inner_tol=inner_tol)
         nbytes = ctypes.c_size_t()
-        _check(self._lib.psi_batched_workspace_size(self._h, k, ctypes.byref(nbytes)))
+        _check(self._lib.psi_batched_workspace_size(self._h, k, p.precision, ctypes.byref(nbytes)))
         ws = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
         psi = torch.empty((self.n, k), dtype=torch.float64, device=self.device)
         infos = (_ffi.Info * k)()
@@ -323,7 +324,8 @@ class Operator:
         k = int(org.size)
         p = self._params(tol, "abs_l1", max_iter, "fp64", check_every)
         nbytes = ctypes.c_size_t()
-        _check(self._lib.psi_batched_workspace_size(self._h, k, ctypes.byref(nbytes)))
+        _check(self._lib.psi_batched_workspace_size(self._h, k, PSI_PREC_FP64,
+                                                    ctypes.byref(nbytes)))
         ws = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
         psi = torch.empty(k, dtype=torch.float64, device=self.device)
         pm = torch.empty((self.n, k), dtype=torch.float64, device=self.device) if want_p else None

@@ -246,7 +246,8 @@ psi_status psi_autotune(psi_operator* op, int32_t precision, int32_t reps, int32
   PSI_GUARD_END
 }
 
-psi_status psi_batched_workspace_size(const psi_operator* op, int32_t n_scenarios, size_t* bytes) {
+psi_status psi_batched_workspace_size(const psi_operator* op, int32_t n_scenarios,
+                                      int32_t precision, size_t* bytes) {
   PSI_GUARD_BEGIN
   PSI_REQUIRE(op, "op must not be NULL");
   if (op->n_graphs > 1) {
@@ -254,7 +255,7 @@ psi_status psi_batched_workspace_size(const psi_operator* op, int32_t n_scenario
     *bytes = 0;
     return PSI_OK;
   }
-  return psi::batched_workspace_size(op, n_scenarios, bytes);
+  return psi::batched_workspace_size(op, n_scenarios, precision, bytes);
   PSI_GUARD_END
 }
 

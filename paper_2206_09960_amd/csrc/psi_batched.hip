@@ -9,6 +9,14 @@
 // each has its own gap, stops at its own iteration (and is frozen afterwards)
 // and gets ψ^k from its own final s^k.
 //
+// Mixed precision (scenario mode): the FP64 residual r^k = Aᵀs^k + c^k − s^k
+// of every scenario comes from one FP64 pass (its L1 norm is the scenario's
+// gap); the corrections e^k = Aᵀe^k + r^k are iterated together in FP32 on
+// [N × Kc] FP32 blocks, each to its own tolerance η‖r^k‖₁, and s^k ← s^k + e^k.
+// The fixed point is that of the FP64 iteration; when a refinement stops
+// shrinking some scenario's residual fourfold, the batch finishes with plain
+// FP64 steps.
+//
 // Origin mode: the newsfeed shares p_i of chosen origins i (Algorithm 1,
 // Power-NF, eq. fixpt_algo) for K origins at once: one lane per origin, the
 // same row tiles and hub chunks over CSR(A) (rows = followers j, columns =
@@ -26,6 +34,7 @@
 // solves are bitwise repeatable.
 #include <algorithm>
 #include <cmath>
+#include <limits>
 #include <vector>
 
 #include "psi_internal.h"
@@ -52,6 +61,7 @@ struct BatchCtrl {
   int kiter[kMaxK];
   int kstatus[kMaxK];
   double kgap[kMaxK];
+  double ktol[kMaxK];  // each scenario's tolerance
 };
 
 // Workspace of one batch tile (reused for every tile of Kc scenarios).
@@ -70,12 +80,15 @@ struct BatchWs {
   double* gap_hub;     // [kHubFinGrid × Kc]
   double* gap_lvl;     // [kGapParts × Kc]
   BatchCtrl* ctrl;
+  BatchCtrl* ctrl2;    // the FP32 correction solves (mixed precision)
   int* origin;         // [kMaxK] origins of the current tile (origin mode)
+  // mixed precision only: μ, 1/den, r, e (×2), z_e = e/den (×2) as FP32 [N × Kc]
+  float *mu32, *invden32, *r32, *e_a, *e_b, *ze_a, *ze_b;
   BatchCtrl* host_ctrl;  // not in the workspace
   int64_t n_wtiles, max_hubs, max_chunks;
 };
 
-size_t batch_layout(int64_t n, int64_t m, BatchWs* w, char* base) {
+size_t batch_layout(int64_t n, int64_t m, BatchWs* w, char* base, bool mixed) {
   size_t off = 0;
   auto take = [&](size_t bytes) -> char* {
     char* p = base ? base + off : nullptr;
@@ -108,7 +121,18 @@ size_t batch_layout(int64_t n, int64_t m, BatchWs* w, char* base) {
   t.gap_hub = (double*)take(8 * size_t(kHubFinGrid) * kMaxK);
   t.gap_lvl = (double*)take(8 * size_t(kGapParts) * kMaxK);
   t.ctrl = (BatchCtrl*)take(sizeof(BatchCtrl));
+  t.ctrl2 = (BatchCtrl*)take(sizeof(BatchCtrl));
   t.origin = (int*)take(4 * size_t(kMaxK));
+  if (mixed) {
+    const size_t nk4 = 4 * size_t(n) * kMaxK;
+    t.mu32 = (float*)take(nk4);
+    t.invden32 = (float*)take(nk4);
+    t.r32 = (float*)take(nk4);
+    t.e_a = (float*)take(nk4);
+    t.e_b = (float*)take(nk4);
+    t.ze_a = (float*)take(nk4);
+    t.ze_b = (float*)take(nk4);
+  }
   t.n_wtiles = n_wtiles;
   t.max_hubs = max_hubs;
   t.max_chunks = max_chunks;
@@ -149,6 +173,43 @@ __global__ void k_bprep_den(const int* fm_row_ptr, const int* fm_col, const doub
   const double lj = lam[t], mj = mu[t];
   c[t] = mj / (lj + mj);
   d[t] = lj / (lj + mj);
+}
+
+// FP32 copies of μ and 1/den for the correction solves.
+__global__ void k_bprep32(const double* mu, const double* invden, int64_t total, float* mu32,
+                          float* invden32) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= total) return;
+  mu32[t] = static_cast<float>(mu[t]);
+  invden32[t] = static_cast<float>(invden[t]);
+}
+
+// r = Y − X (the FP64 residual Aᵀs + c − s of X), rounded to FP32; e_0 = r.
+__global__ void k_bprep_inner(const double* Y, const double* X, const float* invden32,
+                              int64_t total, float* r32, float* e, float* ze) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= total) return;
+  const float r = static_cast<float>(Y[t] - X[t]);
+  r32[t] = r;
+  e[t] = r;
+  ze[t] = invden32[t] * r;
+}
+
+// After a correction solve: X ← X + e for the scenarios still running; a
+// finished scenario takes its final step Y (so X holds every finished
+// scenario's result, which the next FP64 pass copies unchanged).
+__global__ void k_bupdate(double* X, double* zX, const double* Y, const double* zY, const float* e,
+                          const double* invden, const BatchCtrl* bc, int64_t total, int Kc) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= total) return;
+  if (bc->kdone[t % Kc]) {
+    X[t] = Y[t];
+    zX[t] = zY[t];
+  } else {
+    const double v = X[t] + static_cast<double>(e[t]);
+    X[t] = v;
+    zX[t] = invden[t] * v;
+  }
 }
 
 __global__ void k_binit(const double* c, const double* invden, int64_t total, double* s,
@@ -241,10 +302,19 @@ struct BArgs {
   double* gap_lvl;
   BatchCtrl* ctrl;
   const int* origin;   // origin mode: the origin of each lane
+  // FP32 correction step: gathered z_e [N × Kc], r, μ, 1/den, e_old → e_new, z_e new
+  const float* z32;
+  const float* r32;
+  const float* mu32;
+  const float* invden32;
+  const float* e_old;
+  float* e_new;
+  float* ze_new;
 };
 
-// Kernel modes: a scenario step, the scenarios' final ψ pass, an origin step.
-enum : int { kScen = 0, kScenFinal = 1, kOrig = 2 };
+// Kernel modes: a scenario step, the scenarios' final ψ pass, an origin step,
+// an FP32 correction step of the scenarios.
+enum : int { kScen = 0, kScenFinal = 1, kOrig = 2, kScen32 = 3 };
 
 // Epilogue inputs of row r for scenario k, loaded before the row's gathers.
 // A scenario that has met its tolerance keeps its iterate, so it reads its s
@@ -260,6 +330,15 @@ __device__ inline BRow bload(const BArgs& a, int r, int k, bool frozen) {
   if constexpr (BM == kScenFinal) {
     in.a0 = a.lam[t];
     in.a1 = a.d[t];
+  } else if constexpr (BM == kScen32) {
+    in.so = a.e_old[t];
+    if (frozen) {
+      in.a0 = a.z32[t];
+    } else {
+      in.a0 = a.r32[t];
+      in.a1 = a.mu32[t];
+      in.a2 = a.invden32[t];
+    }
   } else {
     in.so = a.s_old[t];
     if (frozen) {
@@ -284,6 +363,17 @@ __device__ inline void bapply(const BArgs& a, int r, int k, const BRow& in, doub
   const int64_t t = int64_t(r) * a.Kc + k;
   if constexpr (BM == kScenFinal) {
     a.psi[int64_t(r) * a.psi_ld + a.psi_col0 + k] = (in.a0 * y + in.a1) * a.inv_n;
+  } else if constexpr (BM == kScen32) {
+    // e = r + μ y, z_e = e / den, in FP32
+    float en = static_cast<float>(in.a0) + static_cast<float>(in.a1) * static_cast<float>(y);
+    float zn = static_cast<float>(in.a2) * en;
+    if (frozen) {
+      en = static_cast<float>(in.so);
+      zn = static_cast<float>(in.a0);
+    }
+    a.e_new[t] = en;
+    a.ze_new[t] = zn;
+    if (!frozen) gap += fabs(static_cast<double>(en) - in.so);
   } else {
     double sn, zn;
     if constexpr (BM == kOrig) {
@@ -306,9 +396,13 @@ __device__ inline void bapply(const BArgs& a, int r, int k, const BRow& in, doub
 // Origin mode adds λ_ℓ on the edge whose column is the lane's origin.
 template <int BM>
 __device__ inline double edge_term(const BArgs& a, int j, int k, int org, double lo) {
-  const double v = a.z[int64_t(j) * a.Kc + k];
-  if constexpr (BM == kOrig) return j == org ? v + lo : v;
-  return v;
+  if constexpr (BM == kScen32) {
+    return static_cast<double>(a.z32[int64_t(j) * a.Kc + k]);
+  } else {
+    const double v = a.z[int64_t(j) * a.Kc + k];
+    if constexpr (BM == kOrig) return j == org ? v + lo : v;
+    return v;
+  }
 }
 
 // Rows of at most kHubEdges followers: waves walk the wave tiles grid-stride.
@@ -504,7 +598,7 @@ __global__ __launch_bounds__(64) void k_batch_gap(BArgs a) {
       if (!isfinite(G)) {
         bc->kdone[lane] = 1;
         bc->kstatus[lane] = PSI_ENUMERIC;
-      } else if (G <= bc->c.tol) {
+      } else if (G <= bc->ktol[lane]) {
         bc->kdone[lane] = 1;
         bc->kstatus[lane] = PSI_OK;
       } else if (it >= bc->c.max_iter) {
@@ -530,7 +624,27 @@ __global__ void k_bctrl_init(BatchCtrl* bc, double tol, int max_iter) {
     bc->kiter[k] = 0;
     bc->kstatus[k] = PSI_OK;
     bc->kgap[k] = 0.0;
+    bc->ktol[k] = tol;
   }
+}
+
+// Control block of a correction solve: scenario k runs to η·‖r^k‖₁ (its last
+// FP64 gap); scenarios already finished are frozen from the start.
+__global__ void k_bctrl_inner(BatchCtrl* in, const BatchCtrl* out, double eta, int max_iter,
+                              int Kc) {
+  in->c = Ctrl{};
+  in->c.max_iter = max_iter;
+  int all = 1;
+  for (int k = 0; k < kMaxK; ++k) {
+    const int dn = k < Kc ? out->kdone[k] : 1;
+    in->kdone[k] = dn;
+    in->kiter[k] = 0;
+    in->kstatus[k] = PSI_OK;
+    in->kgap[k] = 0.0;
+    in->ktol[k] = eta * out->kgap[k];
+    all &= dn;
+  }
+  in->c.done = all;
 }
 
 // ---------------------------------------------------------------- origins
@@ -721,10 +835,13 @@ static psi_status batch_schedule(const int* row_ptr, int64_t n, int64_t m, Batch
   return PSI_OK;
 }
 
-psi_status batched_workspace_size(const psi_operator* op, int n_scenarios, size_t* bytes) {
+psi_status batched_workspace_size(const psi_operator* op, int n_scenarios, int precision,
+                                  size_t* bytes) {
   PSI_REQUIRE(bytes, "bytes must not be NULL");
   PSI_REQUIRE(n_scenarios >= 1, "n_scenarios must be >= 1");
-  *bytes = batch_layout(op->n, op->m, nullptr, nullptr);
+  PSI_REQUIRE(precision == PSI_PREC_FP64 || precision == PSI_PREC_MIXED,
+              "batched solves run in PSI_PREC_FP64 or PSI_PREC_MIXED");
+  *bytes = batch_layout(op->n, op->m, nullptr, nullptr, precision == PSI_PREC_MIXED);
   return PSI_OK;
 }
 
@@ -737,15 +854,17 @@ psi_status solve_batched(psi_operator* op, const psi_params* prm, int K, const d
   PSI_REQUIRE(prm->tol > 0.0 && std::isfinite(prm->tol), "tol must be finite and > 0");
   PSI_REQUIRE(prm->max_iter > 0, "max_iter must be > 0");
   PSI_REQUIRE(prm->tol_mode == PSI_TOL_ABS_L1, "batched solves use PSI_TOL_ABS_L1");
-  PSI_REQUIRE(prm->precision == PSI_PREC_FP64, "batched solves run in PSI_PREC_FP64");
+  PSI_REQUIRE(prm->precision == PSI_PREC_FP64 || prm->precision == PSI_PREC_MIXED,
+              "batched solves run in PSI_PREC_FP64 or PSI_PREC_MIXED");
   PSI_REQUIRE(op->n_graphs == 1, "scenario batches need a single-graph operator");
-  size_t need = batch_layout(op->n, op->m, nullptr, nullptr);
+  const bool mixed = prm->precision == PSI_PREC_MIXED;
+  size_t need = batch_layout(op->n, op->m, nullptr, nullptr, mixed);
   if (ws_bytes < need) {
     set_error("batched workspace smaller than psi_batched_workspace_size reported");
     return PSI_ENOSPACE;
   }
   BatchWs w{};
-  batch_layout(op->n, op->m, &w, static_cast<char*>(ws));
+  batch_layout(op->n, op->m, &w, static_cast<char*>(ws), mixed);
   const int64_t n = op->n, m = op->m;
 
   BSched sc{};
@@ -760,11 +879,13 @@ psi_status solve_batched(psi_operator* op, const psi_params* prm, int K, const d
       if (p) (void)hipHostFree(p);
     }
   } pinned;
-  PSI_HIP_CHECK(hipHostMalloc(reinterpret_cast<void**>(&pinned.p), sizeof(BatchCtrl),
+  PSI_HIP_CHECK(hipHostMalloc(reinterpret_cast<void**>(&pinned.p), 2 * sizeof(BatchCtrl),
                               hipHostMallocDefault));
-  w.host_ctrl = pinned.p;
+  BatchCtrl* h = pinned.p;       // the scenarios' own iteration
+  BatchCtrl* h2 = pinned.p + 1;  // a correction solve
   const int grid = std::min(rows_grid(), static_cast<int>(n_wtiles));
   const int hgrid = hub_finish_grid(n_hubs);
+  const double eta = prm->inner_tol > 0.0 ? prm->inner_tol : 2e-6;
   EventPair evp;
   PSI_HIP_CHECK(hipEventCreate(&evp.a));
   PSI_HIP_CHECK(hipEventCreate(&evp.b));
@@ -781,6 +902,9 @@ psi_status solve_batched(psi_operator* op, const psi_params* prm, int K, const d
                        op->fm_col, w.lam, w.mu, n, Kc, w.invden, w.c, w.d);
     hipLaunchKernelGGL(k_binit, dim3(grid_for(nk)), dim3(kBlock), 0, st, w.c, w.invden, nk, w.s_a,
                        w.z_a);
+    if (mixed)
+      hipLaunchKernelGGL(k_bprep32, dim3(grid_for(nk)), dim3(kBlock), 0, st, w.mu, w.invden, nk,
+                         w.mu32, w.invden32);
     PSI_HIP_CHECK(hipGetLastError());
     BArgs base{};
     base.row_ptr = op->row_ptr;
@@ -806,13 +930,18 @@ psi_status solve_batched(psi_operator* op, const psi_params* prm, int K, const d
     base.gap_hub = w.gap_hub;
     base.gap_lvl = w.gap_lvl;
     base.ctrl = w.ctrl;
-    auto pass = [&](int i, bool final_pass) -> psi_status {
+    base.r32 = w.r32;
+    base.mu32 = w.mu32;
+    base.invden32 = w.invden32;
+    // one FP64 step s_new = Aᵀ s_old + c of every scenario (z = s / den
+    // gathered), or the final ψ pass from z
+    auto pass64 = [&](const double* z, const double* s_old, double* s_new, double* z_new,
+                      bool final_pass) -> psi_status {
       BArgs a = base;
-      const bool even = (i & 1) == 0;
-      a.z = even ? w.z_a : w.z_b;
-      a.s_old = even ? w.s_a : w.s_b;
-      a.s_new = even ? w.s_b : w.s_a;
-      a.z_new = even ? w.z_b : w.z_a;
+      a.z = z;
+      a.s_old = s_old;
+      a.s_new = s_new;
+      a.z_new = z_new;
       if (final_pass) {
         a.psi = psi_out;
         a.psi_ld = K;
@@ -832,27 +961,108 @@ psi_status solve_batched(psi_operator* op, const psi_params* prm, int K, const d
       PSI_HIP_CHECK(hipGetLastError());
       return PSI_OK;
     };
-    // enqueue blocks of passes; passes after the last scenario converged exit at once
-    int enq = 0, chunk = prm->check_every > 0 ? prm->check_every : 8;
-    BatchCtrl* h = w.host_ctrl;
-    while (true) {
-      const int cnt = std::min(chunk, prm->max_iter - enq);
-      for (int i = 0; i < cnt; ++i) {
-        s = pass(enq + i, false);
+    // step i of a correction solve e = Aᵀe + r (FP32, buffers alternate)
+    auto pass32 = [&](int i) -> psi_status {
+      BArgs a = base;
+      const bool even = (i & 1) == 0;
+      a.ctrl = w.ctrl2;
+      a.z32 = even ? w.ze_a : w.ze_b;
+      a.e_old = even ? w.e_a : w.e_b;
+      a.e_new = even ? w.e_b : w.e_a;
+      a.ze_new = even ? w.ze_b : w.ze_a;
+      hipLaunchKernelGGL(k_spmm_rows<kScen32>, dim3(grid), dim3(kBlock), 0, st, a);
+      if (n_chunks)
+        hipLaunchKernelGGL(k_spmm_hub_chunk<kScen32>, dim3(n_chunks), dim3(kBlock), 0, st, a);
+      if (n_hubs) hipLaunchKernelGGL(k_spmm_hub_finish<kScen32>, dim3(hgrid), dim3(kBlock), 0, st, a);
+      launch_batch_gap(a, grid, n_hubs ? hgrid : 0, st);
+      PSI_HIP_CHECK(hipGetLastError());
+      return PSI_OK;
+    };
+    // enqueue steps in blocks (growing unless check_every is set) and read the
+    // control block between blocks; steps after the last scenario finished
+    // exit at once
+    auto loop = [&](BatchCtrl* dctrl, BatchCtrl* hctrl, int budget, auto&& step) -> psi_status {
+      int enq = 0, chunk = prm->check_every > 0 ? prm->check_every : 8;
+      while (true) {
+        const int cnt = std::min(chunk, budget - enq);
+        for (int i = 0; i < cnt; ++i) {
+          psi_status r = step(enq + i);
+          if (r != PSI_OK) return r;
+        }
+        enq += cnt;
+        PSI_HIP_CHECK(hipMemcpyAsync(hctrl, dctrl, sizeof(BatchCtrl), hipMemcpyDeviceToHost, st));
+        PSI_HIP_CHECK(hipStreamSynchronize(st));
+        if (hctrl->c.err_flags & kErrActivity) {
+          set_error("activity must satisfy lambda > 0 and mu >= 0, both finite");
+          return PSI_EINVAL;
+        }
+        if (hctrl->c.done || enq >= budget) break;
+        if (prm->check_every == 0) chunk = std::min(2 * chunk, 64);
+      }
+      return PSI_OK;
+    };
+    // plain FP64 steps from (P, zP), the other buffer pair (Q, zQ) taking
+    // turns, after `before` steps of this tile; returns the pair that holds
+    // the last step
+    auto plain = [&](double* P, double* zP, double* Q, double* zQ, int budget, int before,
+                     const double** z_last) -> psi_status {
+      psi_status r = loop(w.ctrl, h, budget, [&](int i) {
+        const bool even = (i & 1) == 0;
+        return pass64(even ? zP : zQ, even ? P : Q, even ? Q : P, even ? zQ : zP, false);
+      });
+      if (r != PSI_OK) return r;
+      *z_last = ((h->c.iter - before) & 1) ? zQ : zP;
+      return PSI_OK;
+    };
+    std::vector<int> fp32_passes(Kc, 0), refinements(Kc, 0);
+    const double* z_fin = nullptr;
+    if (!mixed) {
+      s = plain(w.s_a, w.z_a, w.s_b, w.z_b, prm->max_iter, 0, &z_fin);
+      if (s != PSI_OK) return s;
+    } else {
+      double *X = w.s_a, *zX = w.z_a, *Y = w.s_b, *zY = w.z_b;
+      std::vector<double> prev(Kc, std::numeric_limits<double>::infinity());
+      while (true) {
+        // FP64 residual pass: Y = Aᵀ X + c, gap_k = ‖Y_k − X_k‖₁
+        s = pass64(zX, X, Y, zY, false);
         if (s != PSI_OK) return s;
+        PSI_HIP_CHECK(hipMemcpyAsync(h, w.ctrl, sizeof(BatchCtrl), hipMemcpyDeviceToHost, st));
+        PSI_HIP_CHECK(hipStreamSynchronize(st));
+        if (h->c.err_flags & kErrActivity) {
+          set_error("activity must satisfy lambda > 0 and mu >= 0, both finite");
+          return PSI_EINVAL;
+        }
+        z_fin = zY;
+        if (h->c.done) break;
+        bool gains = true;
+        for (int k = 0; k < Kc; ++k)
+          if (!h->kdone[k] && !(h->kgap[k] < 0.25 * prev[k])) gains = false;
+        if (!gains) {
+          // a refinement no longer gains for some scenario: plain FP64 steps from Y
+          s = plain(Y, zY, X, zX, std::max(1, prm->max_iter - h->c.iter), h->c.iter, &z_fin);
+          if (s != PSI_OK) return s;
+          break;
+        }
+        for (int k = 0; k < Kc; ++k) {
+          prev[k] = h->kgap[k];
+          if (!h->kdone[k]) ++refinements[k];
+        }
+        // FP32 correction solve e = Aᵀe + r, each scenario to η‖r‖₁
+        hipLaunchKernelGGL(k_bprep_inner, dim3(grid_for(nk)), dim3(kBlock), 0, st, Y, X,
+                           w.invden32, nk, w.r32, w.e_a, w.ze_a);
+        hipLaunchKernelGGL(k_bctrl_inner, dim3(1), dim3(1), 0, st, w.ctrl2, w.ctrl, eta,
+                           prm->max_iter, Kc);
+        PSI_HIP_CHECK(hipGetLastError());
+        s = loop(w.ctrl2, h2, prm->max_iter, pass32);
+        if (s != PSI_OK) return s;
+        for (int k = 0; k < Kc; ++k) fp32_passes[k] += h2->kiter[k];
+        const float* e_fin = (h2->c.iter & 1) ? w.e_b : w.e_a;
+        hipLaunchKernelGGL(k_bupdate, dim3(grid_for(nk)), dim3(kBlock), 0, st, X, zX, Y, zY,
+                           e_fin, w.invden, w.ctrl, nk, Kc);
+        PSI_HIP_CHECK(hipGetLastError());
       }
-      enq += cnt;
-      PSI_HIP_CHECK(hipMemcpyAsync(h, w.ctrl, sizeof(BatchCtrl), hipMemcpyDeviceToHost, st));
-      PSI_HIP_CHECK(hipStreamSynchronize(st));
-      if (h->c.err_flags & kErrActivity) {
-        set_error("activity must satisfy lambda > 0 and mu >= 0, both finite");
-        return PSI_EINVAL;
-      }
-      if (h->c.done || enq >= prm->max_iter) break;
-      if (prm->check_every == 0) chunk = std::min(2 * chunk, 64);
     }
-    const int passes = h->c.iter;
-    s = pass(passes, true);
+    s = pass64(z_fin, nullptr, nullptr, nullptr, true);
     if (s != PSI_OK) return s;
     for (int k = 0; k < Kc; ++k) {
       int stk = h->kdone[k] ? h->kstatus[k] : PSI_ENOTCONV;
@@ -862,7 +1072,9 @@ psi_status solve_batched(psi_operator* op, const psi_params* prm, int K, const d
         inf = psi_info{};
         inf.status = stk;
         inf.iterations = h->kiter[k];
-        inf.spmv_passes = h->kiter[k] + 1;
+        inf.fp32_passes = fp32_passes[k];
+        inf.refinements = refinements[k];
+        inf.spmv_passes = h->kiter[k] + fp32_passes[k] + 1;
         inf.final_gap = h->kgap[k];
         inf.final_l1_step = h->kgap[k];
         inf.col_segments = 1;
@@ -992,13 +1204,13 @@ psi_status solve_origins(psi_operator* op, const psi_params* prm, int K, const i
   const int64_t n = op->n, m = op->m;
   for (int k = 0; k < K; ++k)
     PSI_REQUIRE(origins[k] >= 0 && origins[k] < n, "every origin must be a user id in [0, n)");
-  size_t need = batch_layout(n, m, nullptr, nullptr);
+  size_t need = batch_layout(n, m, nullptr, nullptr, false);
   if (ws_bytes < need) {
     set_error("workspace smaller than psi_batched_workspace_size reported");
     return PSI_ENOSPACE;
   }
   BatchWs w{};
-  batch_layout(n, m, &w, static_cast<char*>(ws));
+  batch_layout(n, m, &w, static_cast<char*>(ws), false);
   BSched sc{};
   psi_status s = batch_schedule(op->fm_row_ptr, n, m, w, st, &sc);  // CSR(A): rows = followers
   if (s != PSI_OK) return s;

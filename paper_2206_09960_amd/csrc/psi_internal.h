@@ -444,7 +444,8 @@ int64_t scan_tile_count(int64_t n);
 psi_status build_schedule(const int* row_ptr, int64_t n, int64_t m, int items, int64_t n_tiles,
                           int* tile_row, hipStream_t st);
 
-psi_status batched_workspace_size(const psi_operator* op, int n_scenarios, size_t* bytes);
+psi_status batched_workspace_size(const psi_operator* op, int n_scenarios, int precision,
+                                  size_t* bytes);
 psi_status solve_graphs(psi_operator* op, const psi_params* prm, double* psi_out, psi_info* infos,
                         hipStream_t st);
 psi_status solve_batched(psi_operator* op, const psi_params* prm, int n_scenarios,

@@ -71,7 +71,8 @@ def test_scenarios_star_hub_closed_form(gpu_lib):
         np.testing.assert_allclose(psi[:, s], expect, rtol=1e-12, atol=0)
 
 
-def test_scenarios_row_length_boundaries(gpu_lib):
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_scenarios_row_length_boundaries(gpu_lib, prec):
     """Rows whose follower counts sit on the batched kernels' boundaries: 16
     gathers in flight, 64 indices per register load, 256 staged indices and
     the 256-follower hub limit (rows above it are chunked)."""
@@ -95,14 +96,59 @@ def test_scenarios_row_length_boundaries(gpu_lib):
     leader = np.concatenate(leader + [bg_l[keep]]).astype(np.int32)
     lam, mu = scenarios(n, 3, 50)
     op = api.Operator(n, follower, leader, lam[:, 0], mu[:, 0])
-    psi, infos = op.solve_batched(torch.tensor(lam), torch.tensor(mu), tol=1e-11)
+    psi, infos = op.solve_batched(torch.tensor(lam), torch.tensor(mu), tol=1e-11, precision=prec)
     psi = psi.cpu().numpy()
     for s in range(3):
         A, B, c, d = oracle.operator(n, follower, leader, lam[:, s], mu[:, s])
         r = oracle.power_psi(A, B, c, d, 1e-11)
         assert infos[s]["status"] == 0
-        assert abs(infos[s]["iterations"] - r["iterations"]) <= 1
+        if prec == "fp64":
+            assert abs(infos[s]["iterations"] - r["iterations"]) <= 1
+        else:  # FP64 residual passes, the last of which met tol
+            assert infos[s]["final_gap"] <= 1e-11 and infos[s]["fp32_passes"] > 0
         assert oracle.rel_l1(r["psi"], psi[:, s]) <= 1e-9, s
+
+
+@pytest.mark.parametrize("n,k,gamma", [(20000, 5, 2.2), (3000, 70, 2.1), (50000, 64, 2.2)])
+def test_scenarios_mixed_match_oracle(gpu_lib, n, k, gamma):
+    """Mixed precision: FP32 corrections refined by FP64 residual passes; each
+    scenario stops on its FP64 gap, so it must match the oracle's Algorithm 2
+    at the same tolerance and the FP64 batch."""
+    api = gpu_lib
+    g = synth.chung_lu(n, 15, gamma, 41, sigma=1.5)
+    lam, mu = scenarios(n, k, 42)
+    op = api.Operator(g.n, g.follower, g.leader, g.lam, g.mu)
+    psi, infos = op.solve_batched(torch.tensor(lam), torch.tensor(mu), tol=1e-9,
+                                  precision="mixed")
+    psi64, _ = op.solve_batched(torch.tensor(lam), torch.tensor(mu), tol=1e-9)
+    again, _ = op.solve_batched(torch.tensor(lam), torch.tensor(mu), tol=1e-9, precision="mixed")
+    assert torch.equal(psi, again)
+    psi = psi.cpu().numpy()
+    assert oracle.rel_l1(psi64.cpu().numpy(), psi) <= 1e-9
+    for s in sorted({0, 1, k // 2, k - 1}):
+        A, B, c, d = oracle.operator(g.n, g.follower, g.leader, lam[:, s], mu[:, s])
+        r = oracle.power_psi(A, B, c, d, 1e-9)
+        i = infos[s]
+        assert i["status"] == 0 and i["final_gap"] <= 1e-9, i
+        assert i["fp32_passes"] > 0 and i["refinements"] >= 1, i
+        assert i["spmv_passes"] == i["iterations"] + i["fp32_passes"] + 1
+        assert oracle.rel_l1(r["psi"], psi[:, s]) <= 1e-9, s
+
+
+def test_scenarios_mixed_statuses(gpu_lib):
+    api = gpu_lib
+    g = synth.chung_lu(5000, 10, 2.2, 47)
+    lam, mu = scenarios(g.n, 4, 48)
+    op = api.Operator(g.n, g.follower, g.leader, g.lam, g.mu)
+    bad = lam.copy()
+    bad[10, 2] = -1.0
+    with pytest.raises(api.PsiError, match="activity"):
+        op.solve_batched(torch.tensor(bad), torch.tensor(mu), precision="mixed")
+    psi, infos = op.solve_batched(torch.tensor(lam), torch.tensor(mu), tol=1e-14, max_iter=3,
+                                  precision="mixed")
+    assert all(i["status_name"] == "PSI_ENOTCONV" and i["iterations"] == 3 for i in infos), infos
+    with pytest.raises(api.PsiError, match="PSI_PREC"):
+        op.solve_batched(torch.tensor(lam), torch.tensor(mu), precision="fp32")
 
 
 def test_scenarios_invalid_and_statuses(gpu_lib):

@@ -93,12 +93,22 @@ def test_c4a_64_scenarios_full_oracle_on_one(gpu_lib):
     for j in range(k):
         lam[:, j], mu[:, j] = synth.activity(g.n, wl["seed"], "lognormal", wl["sigma"], scenario=j)
     op = api.Operator(g.n, g.follower, g.leader, g.lam, g.mu)
-    psi, infos = op.solve_batched(torch.from_numpy(lam).cuda(), torch.from_numpy(mu).cuda(),
-                                  tol=tol)
+    lam_d, mu_d = torch.from_numpy(lam).cuda(), torch.from_numpy(mu).cuda()
+    psi, infos = op.solve_batched(lam_d, mu_d, tol=tol)
     psi = psi.cpu().numpy()
     assert all(i["status"] == 0 for i in infos)
     say(f"C4a: passes per scenario {min(i['spmv_passes'] for i in infos)}.."
         f"{max(i['spmv_passes'] for i in infos)}")
+    # mixed precision: every scenario meets its FP64 gap and matches the FP64 batch
+    psi_m, infos_m = op.solve_batched(lam_d, mu_d, tol=tol, precision="mixed")
+    del lam_d, mu_d
+    assert all(i["status"] == 0 and i["final_gap"] <= tol for i in infos_m)
+    err_m = oracle.rel_l1(psi, psi_m.cpu().numpy())
+    say(f"C4a: mixed vs FP64 batch rel L1 {err_m:.2e}, FP32 passes "
+        f"{max(i['fp32_passes'] for i in infos_m)}, FP64 passes "
+        f"{max(i['iterations'] for i in infos_m)}")
+    assert err_m <= 1e-9
+    del psi_m
     # the last scenario against its lone single-graph solve
     lone = api.Operator(g.n, g.follower, g.leader, lam[:, k - 1], mu[:, k - 1])
     p1, i1 = lone.solve(tol=tol)
