@@ -213,6 +213,22 @@ def run_single(args, name):
     modes["fp64_anderson"] = dict(ms=ms_aa, info=info_aa, psi=psi_aa.cpu().numpy())
     log(f"fp64_anderson: {ms_aa:.3f} ms/solve, {info_aa['spmv_passes']} passes")
 
+    # per-origin newsfeed shares (Algorithm 1 for 64 origins at once), for the
+    # 64 most influential users; their ψ_i must agree with Power-ψ's
+    origins = None
+    if g.n <= 4_000_000:
+        psi64 = modes["fp64"]["psi"]
+        top = np.argsort(-psi64, kind="stable")[:64]
+        ms_o, (psi_o, _, infos_o) = timed(
+            lambda: op.solve_origins(top, tol=tol, want_p=False), max(1, args.steps // 2), 1)
+        assert all(i["status"] == 0 for i in infos_o), [i["status_name"] for i in infos_o][:5]
+        po = [i["spmv_passes"] for i in infos_o]
+        origins = dict(ms=round(ms_o, 3), origins=64, passes_max=int(max(po)),
+                       origin_gteps=round(sum(po) * m / (ms_o * 1e-3) / 1e9, 1),
+                       psi_rel_err_max=float(np.max(np.abs(psi_o.cpu().numpy() - psi64[top])
+                                                    / psi64[top])))
+        log(f"origins: 64 origins in {ms_o:.3f} ms, up to {max(po)} passes")
+
     head = min((p for p in modes if p not in ("fp64_weighted", "fp64_anderson")),
                key=lambda p: modes[p]["ms"])
     head_prec = head.replace("_warm", "")
@@ -291,6 +307,7 @@ def run_single(args, name):
         "pass_us": {k: round(v * 1e3, 2) for k, v in pass_ms.items()},
         "roofline": roofline,
         "warm_start": warm,
+        "per_origin_shares": origins,
         "build_ms": round(builds[-1], 2),
         "autotune_ms": round(tune_ms, 1),
         "autotuned": {p: {k: v[k] for k in ("tile_items", "col_segments", "seg_form")}
