@@ -49,6 +49,7 @@ constexpr int kChunkEdges = 1024;  // edges per hub chunk
 constexpr int kMaxK = 64;          // scenarios per batch tile (one per lane)
 constexpr int kHubFinGrid = 1024;  // largest grid of the hub-finishing kernel
 constexpr int kGapParts = 64;      // first-level partials of a pass's gaps
+constexpr int kGraphGapBlock = 1024;  // threads summing one graph's |Δ|
 
 inline unsigned grid_for(int64_t n, int block = kBlock) {
   return static_cast<unsigned>((n + block - 1) / block);
@@ -693,25 +694,38 @@ __global__ void k_origin_psi(const double* part, int n_blk, int Kc, const int* o
 // a fixed order, records it, and freezes when it meets the tolerance; the
 // last graph to report sets done when every graph is done.  One counter
 // carries both the arrivals (low 16 bits) and the done graphs (high bits).
-__global__ __launch_bounds__(kBlock) void k_graph_gap(const int64_t* graph_off, int n_graphs,
-                                                      const double* row_delta, Ctrl* ctrl,
-                                                      int* gdone, int* giter, int* gstatus,
-                                                      double* ggap) {
-  __shared__ double red[kBlock / 64];
+__global__ __launch_bounds__(kGraphGapBlock) void k_graph_gap(const int64_t* graph_off,
+                                                              int n_graphs,
+                                                              const double* row_delta, Ctrl* ctrl,
+                                                              int* gdone, int* giter, int* gstatus,
+                                                              double* ggap) {
+  constexpr int W = kGraphGapBlock / 64;
+  __shared__ double red[W];
   if (ctrl->done) return;
   const int g = blockIdx.x;
   const int was_done = gdone[g];
   double sum = 0.0;
-  if (!was_done)
-    for (int64_t r = graph_off[g] + threadIdx.x; r < graph_off[g + 1]; r += kBlock)
-      sum += row_delta[r];
+  if (!was_done) {
+    // thread t adds users t, t + B, t + 2B, ... of the graph in order, eight loads in flight
+    const int64_t r1 = graph_off[g + 1];
+    int64_t r = graph_off[g] + threadIdx.x;
+    for (; r + 7 * kGraphGapBlock < r1; r += 8 * kGraphGapBlock) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = row_delta[r + u * kGraphGapBlock];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) sum += v[u];
+    }
+    for (; r < r1; r += kGraphGapBlock) sum += row_delta[r];
+  }
   for (int off = 32; off > 0; off >>= 1) sum += __shfl_down(sum, off, 64);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sum;
   __syncthreads();
   if (threadIdx.x != 0) return;
   int done = was_done;
   if (!was_done) {
-    const double G = (red[0] + red[1]) + (red[2] + red[3]);
+    double G = 0.0;
+    for (int w = 0; w < W; ++w) G += red[w];
     const int it = giter[g] + 1;
     giter[g] = it;
     ggap[g] = G;
@@ -1127,8 +1141,8 @@ psi_status solve_graphs(psi_operator* op, const psi_params* prm, double* psi_out
     a.z_new = even ? op->z_b : op->z_a;
     psi_status r = launch_pass(op, kStep64G, a, st);
     if (r != PSI_OK) return r;
-    hipLaunchKernelGGL(k_graph_gap, dim3(G), dim3(kBlock), 0, st, op->graph_off, G, op->row_delta,
-                       op->ctrl, op->gdone, op->giter, op->gstatus, op->ggap);
+    hipLaunchKernelGGL(k_graph_gap, dim3(G), dim3(kGraphGapBlock), 0, st, op->graph_off, G,
+                       op->row_delta, op->ctrl, op->gdone, op->giter, op->gstatus, op->ggap);
     PSI_HIP_CHECK(hipGetLastError());
     return PSI_OK;
   };
