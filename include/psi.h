@@ -230,7 +230,10 @@ psi_status psi_batched_workspace_size(const psi_operator* op, int32_t n_scenario
  * solved together, one pass over all of them per step; each graph has its
  * own gap (over its users), stops at its own tolerance (and is frozen) and
  * its ψ uses its own N; psi_out (device [n_users]) holds every graph's ψ at
- * its users' positions, infos[g] (host, may be NULL) graph g's result.
+ * its users' positions, infos[g] (host, may be NULL) graph g's result;
+ * prm->col_segments / seg_form choose the pass as in psi_solve (0: two
+ * segments with tiled partial passes from 10^6 users on, one fused pass
+ * below).
  * Scenario mode also takes PSI_PREC_MIXED: each refinement is one FP64
  * residual pass r = Aᵀs + c − s for every scenario (‖r‖₁ is its gap, the
  * stopping test), then the FP32 correction solves e = Aᵀe + r of all

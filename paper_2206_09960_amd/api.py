@@ -345,12 +345,16 @@ class Operator:
         return psi, pm, out
 
     def solve_graphs(self, tol: float = 1e-8, max_iter: int = 10000, check_every: int = 0,
-                     tile_items: int = 0, stream=None, raise_on_status: bool = False):
+                     tile_items: int = 0, col_segments: int = 0, seg_form: str | int = 0,
+                     stream=None, raise_on_status: bool = False):
         """psi_solve_batched, graph mode: every graph of a block-diagonal
-        operator solved to its own tolerance; returns (psi [N], G info dicts)."""
+        operator solved to its own tolerance; returns (psi [N], G info dicts).
+        col_segments > 1 runs each pass as a column-segmented partial pass
+        (seg_form "tiles" or "slices") and a combine."""
         if self.n_graphs < 2:
             raise ValueError("graph mode needs an operator built with node_offsets")
-        p = self._params(tol, "abs_l1", max_iter, "fp64", check_every, tile_items)
+        p = self._params(tol, "abs_l1", max_iter, "fp64", check_every, tile_items, col_segments,
+                         seg_form=seg_form)
         psi = torch.empty(self.n, dtype=torch.float64, device=self.device)
         infos = (_ffi.Info * self.n_graphs)()
         with torch.cuda.device(self.device):

@@ -692,9 +692,8 @@ static void layout_persistent(int64_t n, int64_t m_raw, int n_graphs, uint32_t f
   char* hist = take(8 * size_t(kHistLen));
   char* scal = take(8 * 8);
   char* goff = take(8 * size_t(n_graphs + 1));
-  // column segments (S <= 8) and their sliced layout; a block-diagonal
-  // operator has no segmented form
-  const bool segs = n_graphs == 1;
+  // column segments (S <= 8) and their sliced layout
+  const bool segs = true;
   const int64_t nw = (n + kSliceWindow - 1) / kSliceWindow;
   // short slices of a window: ceil(rows / 64); interleaved entries: its short
   // rows' edges plus at most 64·kSliceShort of padding (lengths fall from
@@ -1010,7 +1009,6 @@ psi_status ensure_schedule(psi_operator* op, int tile_items, hipStream_t st) {
 
 psi_status ensure_segments(psi_operator* op, int S, hipStream_t st) {
   PSI_REQUIRE(S == 2 || S == 4 || S == 8, "col_segments must be 1, 2, 4 or 8");
-  PSI_REQUIRE(op->n_graphs == 1, "column segments need a single-graph operator");
   if (op->seg_S == S) return PSI_OK;
   const int64_t n = op->n;
   const int64_t seg = (n + S - 1) / S;

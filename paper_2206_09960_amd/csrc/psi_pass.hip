@@ -696,7 +696,8 @@ __global__ __launch_bounds__(kBlock) void k_combine(PassArgs a, SegArgs sg) {
       if (r < a.n_rows) apply_row<MODE>(a, nullptr, r, in[u], y[u], g, sn);
     }
   }
-  if constexpr (MODE != kFinal64) finalize_gap(a, g, sn, red, &last);
+  // block-diagonal operators take each graph's gap from its rows' |Δ| instead
+  if constexpr (MODE == kStep64 || MODE == kStep32) finalize_gap(a, g, sn, red, &last);
 }
 
 // Co-resident workgroups of a kernel: CUs × workgroups per CU, a multiple of 8.
@@ -899,6 +900,13 @@ psi_status launch_pass_seg(psi_operator* op, PassMode mode, const PassArgs& a, h
       if (r != PSI_OK) return r;
       return mode == kStep64 ? launch_combine<kStep64, double>(a, sg, st)
                              : launch_combine<kFinal64, double>(a, sg, st);
+    case kStep64G:
+    case kFinal64G:
+      for (int s = 0; s < sg.S; ++s) sg.seg[s].y = op->seg_y + size_t(s) * op->n;
+      r = launch_partial<kPart64>(op, a, sg, st);
+      if (r != PSI_OK) return r;
+      return mode == kStep64G ? launch_combine<kStep64G, double>(a, sg, st)
+                              : launch_combine<kFinal64G, double>(a, sg, st);
     case kStep32:
       for (int s = 0; s < sg.S; ++s)
         sg.seg[s].y = reinterpret_cast<float*>(op->seg_y) + size_t(s) * op->n;

@@ -198,6 +198,28 @@ def test_graphs_match_oracle_and_lone_solves(gpu_lib, n_graphs, lo, hi):
         assert oracle.rel_l1(p1.cpu().numpy(), part) <= 1e-12
 
 
+@pytest.mark.parametrize("S,form", [(2, "tiles"), (2, "slices"), (4, "slices"), (8, "tiles")])
+def test_graphs_column_segmented_passes(gpu_lib, S, form):
+    """Graph batches through a column-segmented pass (partial kernel in either
+    form, then the combine with the per-graph epilogue): the same results as
+    the fused pass, and the oracle's on a sampled graph."""
+    api = gpu_lib
+    g = synth.multi_graph(5, 20000, 40000, 10, 2.1, seed=53, sigma=1.5)
+    op = api.Operator(g.n, g.follower, g.leader, g.lam, g.mu, node_offsets=g.node_offsets)
+    fused, i_f = op.solve_graphs(tol=1e-10, col_segments=1)
+    seg, i_s = op.solve_graphs(tol=1e-10, col_segments=S, seg_form=form)
+    assert all(i["col_segments"] == S for i in i_s)
+    assert oracle.rel_l1(fused.cpu().numpy(), seg.cpu().numpy()) <= 1e-12
+    assert all(abs(a["iterations"] - b["iterations"]) <= 1 for a, b in zip(i_f, i_s))
+    k = 3
+    sub = subgraph(g, k)
+    A, B, c, d = oracle.operator(sub.n, sub.follower, sub.leader, sub.lam, sub.mu)
+    r = oracle.power_psi(A, B, c, d, 1e-10)
+    part = seg.cpu().numpy()[g.node_offsets[k]:g.node_offsets[k + 1]]
+    assert i_s[k]["status"] == 0 and abs(i_s[k]["iterations"] - r["iterations"]) <= 1
+    assert oracle.rel_l1(r["psi"], part) <= 1e-9
+
+
 def test_graphs_with_an_edgeless_graph(gpu_lib):
     api = gpu_lib
     a = synth.chung_lu(2000, 6, 2.2, 52)
