@@ -697,8 +697,8 @@ __global__ void k_origin_psi(const double* part, int n_blk, int Kc, const int* o
 __global__ __launch_bounds__(kGraphGapBlock) void k_graph_gap(const int64_t* graph_off,
                                                               int n_graphs,
                                                               const double* row_delta, Ctrl* ctrl,
-                                                              int* gdone, int* giter, int* gstatus,
-                                                              double* ggap) {
+                                                              int* gdone, int* gskip, int* giter,
+                                                              int* gstatus, double* ggap) {
   constexpr int W = kGraphGapBlock / 64;
   __shared__ double red[W];
   if (ctrl->done) return;
@@ -723,6 +723,8 @@ __global__ __launch_bounds__(kGraphGapBlock) void k_graph_gap(const int64_t* gra
   __syncthreads();
   if (threadIdx.x != 0) return;
   int done = was_done;
+  // a graph frozen before this pass was copied into both buffers by it
+  if (was_done) gskip[g] = 1;
   if (!was_done) {
     double G = 0.0;
     for (int w = 0; w < W; ++w) G += red[w];
@@ -754,8 +756,8 @@ __global__ __launch_bounds__(kGraphGapBlock) void k_graph_gap(const int64_t* gra
 }
 
 __global__ void k_graph_init(const double* c, const double* invden, int64_t n, int n_graphs,
-                             double* s, double* z, int* gdone, int* giter, int* gstatus,
-                             double* ggap, Ctrl* ctrl, double tol, int max_iter) {
+                             double* s, double* z, int* gdone, int* gskip, int* giter,
+                             int* gstatus, double* ggap, Ctrl* ctrl, double tol, int max_iter) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n) {
     s[i] = c[i];
@@ -763,6 +765,7 @@ __global__ void k_graph_init(const double* c, const double* invden, int64_t n, i
   }
   if (i < n_graphs) {
     gdone[i] = 0;
+    gskip[i] = 0;
     giter[i] = 0;
     gstatus[i] = PSI_OK;
     ggap[i] = 0.0;
@@ -1143,11 +1146,12 @@ psi_status solve_graphs(psi_operator* op, const psi_params* prm, double* psi_out
   hipEvent_t ev0 = evp.a, ev1 = evp.b;
   PSI_HIP_CHECK(hipEventRecord(ev0, st));
   hipLaunchKernelGGL(k_graph_init, dim3(grid_for(std::max<int64_t>(n, G))), dim3(kBlock), 0, st,
-                     op->c, op->invden, n, G, op->s_a, op->z_a, op->gdone, op->giter, op->gstatus,
-                     op->ggap, op->ctrl, prm->tol, prm->max_iter);
+                     op->c, op->invden, n, G, op->s_a, op->z_a, op->gdone, op->gskip, op->giter,
+                     op->gstatus, op->ggap, op->ctrl, prm->tol, prm->max_iter);
   PassArgs base = base_args(op);
   base.count_iter = 0;
   base.respect_done = 1;
+  base.gskip = op->gskip;  // step passes skip the gathers of graphs frozen a pass ago
   auto pass = [&](int i) -> psi_status {
     PassArgs a = base;
     const bool even = (i & 1) == 0;
@@ -1158,7 +1162,8 @@ psi_status solve_graphs(psi_operator* op, const psi_params* prm, double* psi_out
     psi_status r = graph_pass(kStep64G, a);
     if (r != PSI_OK) return r;
     hipLaunchKernelGGL(k_graph_gap, dim3(G), dim3(kGraphGapBlock), 0, st, op->graph_off, G,
-                       op->row_delta, op->ctrl, op->gdone, op->giter, op->gstatus, op->ggap);
+                       op->row_delta, op->ctrl, op->gdone, op->gskip, op->giter, op->gstatus,
+                       op->ggap);
     PSI_HIP_CHECK(hipGetLastError());
     return PSI_OK;
   };
@@ -1184,6 +1189,7 @@ psi_status solve_graphs(psi_operator* op, const psi_params* prm, double* psi_out
   {
     PassArgs a = base;
     a.respect_done = 0;
+    a.gskip = nullptr;  // ψ needs every graph's sums
     a.x = (passes & 1) ? op->z_b : op->z_a;
     a.s_new = psi_out;
     s = graph_pass(kFinal64G, a);

@@ -662,6 +662,7 @@ static void layout_persistent(int64_t n, int64_t m_raw, int n_graphs, uint32_t f
   char* inv_ng = n_graphs > 1 ? take(8 * size_t(n)) : nullptr;
   char* row_delta = n_graphs > 1 ? take(8 * size_t(n)) : nullptr;
   char* gdone = n_graphs > 1 ? take(4 * size_t(n_graphs)) : nullptr;
+  char* gskip = n_graphs > 1 ? take(4 * size_t(n_graphs)) : nullptr;
   char* giter = n_graphs > 1 ? take(4 * size_t(n_graphs)) : nullptr;
   char* gstatus = n_graphs > 1 ? take(4 * size_t(n_graphs)) : nullptr;
   char* ggap = n_graphs > 1 ? take(8 * size_t(n_graphs)) : nullptr;
@@ -736,6 +737,7 @@ static void layout_persistent(int64_t n, int64_t m_raw, int n_graphs, uint32_t f
   op->inv_ng = (double*)inv_ng;
   op->row_delta = (double*)row_delta;
   op->gdone = (int*)gdone;
+  op->gskip = (int*)gskip;
   op->giter = (int*)giter;
   op->gstatus = (int*)gstatus;
   op->ggap = (double*)ggap;

@@ -143,6 +143,9 @@ struct PassArgs {
   const int* graph_of;  // block-diagonal operators: graph of each user
   const double* inv_ng; //   1/N of each user's graph
   const int* gdone;     //   graphs that met their tolerance (frozen)
+  const int* gskip;     //   graphs frozen for a whole pass (both iterate buffers hold
+                        //   their result): step passes may skip their gathers; NULL
+                        //   in every other pass
   double* row_delta;    //   |s_new − s_old| of each user
   int count_iter;       // 1: the pass is a Power-ψ step that advances ctrl->iter
   int respect_done;     // 1: exit at once when ctrl->done is set
@@ -331,6 +334,7 @@ struct psi_operator {
   double* inv_ng = nullptr;    // 1/N of each user's graph (n_graphs > 1)
   double* row_delta = nullptr; // per-user |Δ| of the last pass (n_graphs > 1)
   int* gdone = nullptr;        // per-graph state (n_graphs > 1)
+  int* gskip = nullptr;
   int* giter = nullptr;
   int* gstatus = nullptr;
   double* ggap = nullptr;

@@ -240,6 +240,30 @@ __device__ inline void gather_tile(const PassArgs& a, const TileMeta& m, const i
   }
 }
 
+// Block-diagonal step passes: every row the tile touches belongs to a graph
+// frozen for a whole pass (its result is in both iterate buffers and its
+// rows only keep it), so the tile's sums are unused and its gathers can be
+// skipped.  Uniform across the workgroup.
+__device__ inline bool tile_frozen(const PassArgs& a, const TileMeta& m) {
+  if (!a.gskip) return false;
+  const int g0 = a.graph_of[min(m.r0, a.n_rows - 1)];
+  const int g1 = a.graph_of[min(m.r1, a.n_rows - 1)];
+  for (int g = g0; g <= g1; ++g)
+    if (!a.gskip[g]) return false;
+  return true;
+}
+
+template <int IPT, int MODE>
+__device__ inline void gather_live_tile(const PassArgs& a, const TileMeta& m, const int* j,
+                                        double* v) {
+  if (tile_frozen(a, m)) {
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) v[i] = 0.0;
+  } else {
+    gather_tile<IPT, MODE>(a, m, j, v);
+  }
+}
+
 // Walk tiles first, first+stride, ... of src, software-pipelined: while a
 // tile is reduced in LDS, the next tile's indices are in flight, and its
 // gathers are issued before this tile's epilogue.  A tile publishes the
@@ -260,7 +284,7 @@ __device__ void run_tiles(const PassArgs& a, const TileSrc& src, int first, int 
   int j[IPT], re[IPT];
   double v[IPT];
   load_tile<IPT>(src, cur, j, re);
-  gather_tile<IPT, MODE>(a, cur, j, v);
+  gather_live_tile<IPT, MODE>(a, cur, j, v);
 
   // row that ended in the previous tile but began earlier (uniform)
   int pend_row = -1, pend_tile = 0;
@@ -371,7 +395,7 @@ __device__ void run_tiles(const PassArgs& a, const TileSrc& src, int first, int 
 
     // 6. gathers of the next tile, then this tile's epilogue
     double vn[IPT];
-    if (has_next) gather_tile<IPT, MODE>(a, nxt, jn, vn);
+    if (has_next) gather_live_tile<IPT, MODE>(a, nxt, jn, vn);
     if (tid == 0 && open) st_agent(&src.part_open[cur.tile], L.cval[kBlock - 1]);
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
