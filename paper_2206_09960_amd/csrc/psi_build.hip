@@ -278,27 +278,59 @@ __global__ void k_fill_int(int* p, int64_t n, int v) {
 // 1/den_j (0 for an empty newsfeed), and the row sums of B and A.
 __global__ void k_den(const int* fm_row_ptr, const int* fm_col, const double* lam,
                       const double* mu, int64_t n, double* invden, Ctrl* ctrl) {
-  int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (j >= n) return;
-  int e0 = fm_row_ptr[j], e1 = fm_row_ptr[j + 1];
-  double den = 0.0, sl = 0.0, sm = 0.0;
-  for (int e = e0; e < e1; ++e) {
-    int k = fm_col[e];
-    double lk = lam[k], mk = mu[k];
-    den += lk + mk;
-    sl += lk;
-    sm += mk;
+  const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  double bj = 0.0, kj = 0.0;  // row sums of B and A (0 for an empty newsfeed)
+  int empty = 0;
+  if (j < n) {
+    const int e0 = fm_row_ptr[j], e1 = fm_row_ptr[j + 1];
+    double den = 0.0, sl = 0.0, sm = 0.0;
+    int e = e0;
+    for (; e + 4 <= e1; e += 4) {  // four leaders' rates in flight, added in order
+      int k[4];
+      double lk[4], mk[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) k[u] = fm_col[e + u];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        lk[u] = lam[k[u]];
+        mk[u] = mu[k[u]];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        den += lk[u] + mk[u];
+        sl += lk[u];
+        sm += mk[u];
+      }
+    }
+    for (; e < e1; ++e) {
+      const int k = fm_col[e];
+      const double lk = lam[k], mk = mu[k];
+      den += lk + mk;
+      sl += lk;
+      sm += mk;
+    }
+    if (e1 == e0) {
+      invden[j] = 0.0;
+      empty = 1;
+    } else {
+      const double inv = 1.0 / den;
+      invden[j] = inv;
+      bj = sl * inv;
+      kj = sm * inv;
+    }
   }
-  if (e1 == e0) {
-    invden[j] = 0.0;
-    atomicAdd(&ctrl->n_no_leaders, 1ull);
-    return;
+  // one atomic per wave: the maxima of non-negative values (bit patterns
+  // order like the values) and the count of empty newsfeeds
+  for (int off = 32; off > 0; off >>= 1) {
+    bj = fmax(bj, __shfl_xor(bj, off, 64));
+    kj = fmax(kj, __shfl_xor(kj, off, 64));
   }
-  double inv = 1.0 / den;
-  invden[j] = inv;
-  double bj = sl * inv, kj = sm * inv;
-  atomicMax(&ctrl->bnorm_bits, (unsigned long long)__double_as_longlong(bj));
-  atomicMax(&ctrl->kappa_bits, (unsigned long long)__double_as_longlong(kj));
+  const unsigned long long n_empty = __popcll(__ballot(empty));
+  if ((threadIdx.x & 63) == 0) {
+    atomicMax(&ctrl->bnorm_bits, (unsigned long long)__double_as_longlong(bj));
+    atomicMax(&ctrl->kappa_bits, (unsigned long long)__double_as_longlong(kj));
+    if (n_empty) atomicAdd(&ctrl->n_no_leaders, n_empty);
+  }
 }
 
 __global__ void k_node_consts(const double* lam, const double* mu, const double* invden,
@@ -330,20 +362,21 @@ __global__ void k_graph_rows(const int64_t* graph_off, int n_graphs, int64_t n, 
 }
 
 __global__ void k_max_row(const int* row_ptr, int64_t n, Ctrl* ctrl) {
-  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  unsigned long long len = (unsigned long long)(row_ptr[i + 1] - row_ptr[i]);
-  if (len) atomicMax(&ctrl->max_row, len);
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  int len = i < n ? row_ptr[i + 1] - row_ptr[i] : 0;
+  for (int off = 32; off > 0; off >>= 1) len = max(len, __shfl_xor(len, off, 64));
+  if ((threadIdx.x & 63) == 0 && len) atomicMax(&ctrl->max_row, (unsigned long long)len);
 }
 
-// a_ji = μ_i / den_j stored per edge of CSR(Aᵀ) row i (weighted form).
-__global__ void k_weights64(const int* row_ptr, const int* col, const double* mu,
-                            const double* invden, int64_t n, double* val) {
-  int64_t row = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
-  int lane = threadIdx.x & 63;
-  if (row >= n) return;
-  double mi = mu[row];
-  for (int e = row_ptr[row] + lane; e < row_ptr[row + 1]; e += 64) val[e] = mi * invden[col[e]];
+// a_ji = μ_i / den_j stored per edge of CSR(Aᵀ) row i (weighted form), one
+// thread per edge, the row and column read from the edge's sorted key.
+__global__ void k_weights64(const uint64_t* keys, int64_t m, int nb, const double* mu,
+                            const double* invden, double* val) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= m) return;
+  const uint64_t v = keys[e];
+  const uint64_t mask = (uint64_t(1) << nb) - 1;
+  val[e] = mu[int64_t(v >> nb)] * invden[int64_t(v & mask)];
 }
 
 // First row of every merge-path tile: on the path that merges the row ends
@@ -382,21 +415,50 @@ __global__ void k_seg_count(const int* row_ptr, const int* col, int64_t n, int S
   }
 }
 
-// Copy each row's run of segment s into that segment's CSR (one wave per row).
-__global__ void k_seg_scatter(const int* row_ptr, const int* col, int64_t n, int S, int64_t seg,
-                              const int* seg_row_ptr, const int64_t* seg_off, int* seg_col) {
-  const int64_t row = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
-  const int lane = threadIdx.x & 63;
-  if (row >= n) return;
-  int e = row_ptr[row];
-  for (int s = 0; s < S; ++s) {
-    const int* rp = seg_row_ptr + int64_t(s) * (n + 1);
-    const int cnt = rp[row + 1] - rp[row];
-    int* dst = seg_col + seg_off[s] + rp[row];
-    for (int k = lane; k < cnt; k += 64) dst[k] = col[e + k];
-    e += cnt;
+// Copy each row's run of segment s into that segment's CSR, edge-parallel
+// (a hub row is spread over many threads): thread t moves edges
+// kSegScatterEdges·t onwards, finds its first edge's row by binary search
+// over the row ends and steps to later rows as it goes.  A row's columns
+// ascend, so its entries of segment s are one run, which starts after the
+// row's entries of the segments before s.
+constexpr int kSegScatterEdges = 8;
+__global__ void k_seg_scatter(const int* row_ptr, const int* col, int64_t n, int64_t m, int S,
+                              int64_t seg, const int* seg_row_ptr, const int64_t* seg_off,
+                              int* seg_col) {
+  const int64_t e_lo = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) * kSegScatterEdges;
+  if (e_lo >= m) return;
+  const int64_t e_hi = e_lo + kSegScatterEdges < m ? e_lo + kSegScatterEdges : m;
+  // the first row whose end exceeds e_lo holds edge e_lo (row_ptr[n] = m > e_lo)
+  int64_t lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int64_t mid = lo + ((hi - lo) >> 1);
+    if (row_ptr[mid + 1] > e_lo) hi = mid; else lo = mid + 1;
   }
-  (void)seg;
+  int64_t row = lo;
+  int64_t r_end = row_ptr[row + 1];
+  int cnt[8];  // the row's entries in each segment
+  auto load_counts = [&]() {
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const int* rp = seg_row_ptr + int64_t(s) * (n + 1);
+      cnt[s] = s < S ? rp[row + 1] - rp[row] : 0;
+    }
+  };
+  load_counts();
+  for (int64_t e = e_lo; e < e_hi; ++e) {
+    while (e >= r_end) {
+      ++row;
+      r_end = row_ptr[row + 1];
+      load_counts();
+    }
+    const int j = col[e];
+    const int s = static_cast<int>(j / seg);
+    int64_t run = row_ptr[row];  // start of the row's run of segment s
+#pragma unroll
+    for (int s2 = 0; s2 < 8; ++s2)
+      if (s2 < s) run += cnt[s2];
+    seg_col[seg_off[s] + seg_row_ptr[int64_t(s) * (n + 1) + row] + (e - run)] = j;
+  }
 }
 
 // ---------------------------------------------------------------- sliced layout
@@ -954,6 +1016,9 @@ psi_status build_operator(psi_operator* op, const int32_t* follower, const int32
     if (s != PSI_OK) return s;
     hipLaunchKernelGGL(k_csr_from_keys, dim3(grid_for(m)), dim3(kBlock), 0, st, res, m, n, nb,
                        op->row_ptr, op->col);
+    if (op->val64)
+      hipLaunchKernelGGL(k_weights64, dim3(grid_for(m)), dim3(kBlock), 0, st, res, m, nb, op->mu,
+                         op->invden, op->val64);
   } else {
     hipLaunchKernelGGL(k_fill_int, dim3(grid_for(n + 1)), dim3(kBlock), 0, st, op->row_ptr, n + 1,
                        0);
@@ -962,9 +1027,6 @@ psi_status build_operator(psi_operator* op, const int32_t* follower, const int32
   if (op->n_graphs > 1)
     hipLaunchKernelGGL(k_graph_rows, dim3(grid_for(n)), dim3(kBlock), 0, st, op->graph_off,
                        op->n_graphs, n, op->graph_of, op->inv_ng);
-  if (op->val64 && m > 0)
-    hipLaunchKernelGGL(k_weights64, dim3(grid_for(n * 64)), dim3(kBlock), 0, st, op->row_ptr,
-                       op->col, op->mu, op->invden, n, op->val64);
   PSI_HIP_CHECK(hipGetLastError());
   PSI_HIP_CHECK(hipMemcpyAsync(&hc, op->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
   PSI_HIP_CHECK(hipStreamSynchronize(st));
@@ -1043,8 +1105,10 @@ psi_status ensure_segments(psi_operator* op, int S, hipStream_t st) {
   int64_t* doff = reinterpret_cast<int64_t*>(op->scal);  // 8 values of scratch
   PSI_HIP_CHECK(hipMemcpyAsync(doff, off.data(), 8 * size_t(S), hipMemcpyHostToDevice, st));
   if (op->m > 0)
-    hipLaunchKernelGGL(k_seg_scatter, dim3(grid_for(n * 64)), dim3(kBlock), 0, st, op->row_ptr,
-                       op->col, n, S, seg, op->seg_row_ptr, doff, op->seg_col);
+    hipLaunchKernelGGL(k_seg_scatter,
+                       dim3(grid_for((op->m + kSegScatterEdges - 1) / kSegScatterEdges)),
+                       dim3(kBlock), 0, st, op->row_ptr, op->col, n, op->m, S, seg,
+                       op->seg_row_ptr, doff, op->seg_col);
   PSI_HIP_CHECK(hipGetLastError());
   for (int s = 0; s < S; ++s) {
     op->seg[s].row_ptr = op->seg_row_ptr + int64_t(s) * (n + 1);
