@@ -276,12 +276,48 @@ __global__ void k_fill_int(int* p, int64_t n, int v) {
 
 // Per follower j over CSR(A): den_j = Σ_{ℓ∈L(j)}(λ_ℓ+μ_ℓ) in ascending ℓ,
 // 1/den_j (0 for an empty newsfeed), and the row sums of B and A.
-__global__ void k_den(const int* fm_row_ptr, const int* fm_col, const double* lam,
-                      const double* mu, int64_t n, double* invden, Ctrl* ctrl) {
-  const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  double bj = 0.0, kj = 0.0;  // row sums of B and A (0 for an empty newsfeed)
-  int empty = 0;
-  if (j < n) {
+// Maxima of non-negative doubles (bit patterns order like the values) and a
+// count, reduced over the workgroup and added with one atomic each: the
+// control block takes one atomic per workgroup, never one per user.
+__device__ inline void block_max2_count(double bm, double km, unsigned long long cnt,
+                                        unsigned long long* bm_bits, unsigned long long* km_bits,
+                                        unsigned long long* count) {
+  __shared__ double rb[kBlock / 64], rk[kBlock / 64];
+  __shared__ unsigned long long rc[kBlock / 64];
+  for (int off = 32; off > 0; off >>= 1) {
+    bm = fmax(bm, __shfl_xor(bm, off, 64));
+    km = fmax(km, __shfl_xor(km, off, 64));
+    cnt += __shfl_xor(cnt, off, 64);
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    rb[w] = bm;
+    rk[w] = km;
+    rc[w] = cnt;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < kBlock / 64; ++i) {
+      bm = fmax(bm, rb[i]);
+      km = fmax(km, rk[i]);
+      cnt += rc[i];
+    }
+    if (bm_bits) atomicMax(bm_bits, (unsigned long long)__double_as_longlong(bm));
+    if (km_bits) atomicMax(km_bits, (unsigned long long)__double_as_longlong(km));
+    if (count && cnt) atomicAdd(count, cnt);
+  }
+}
+
+// Per follower j over CSR(A): den_j = Σ_{ℓ∈L(j)}(λ_ℓ+μ_ℓ) in ascending ℓ,
+// 1/den_j (0 for an empty newsfeed), and the row sums of B and A.  The grid
+// strides over the followers.
+__global__ __launch_bounds__(kBlock) void k_den(const int* fm_row_ptr, const int* fm_col,
+                                                const double* lam, const double* mu, int64_t n,
+                                                double* invden, Ctrl* ctrl) {
+  double bmax = 0.0, kmax = 0.0;  // row sums of B and A
+  unsigned long long n_empty = 0;
+  for (int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; j < n;
+       j += int64_t(gridDim.x) * blockDim.x) {
     const int e0 = fm_row_ptr[j], e1 = fm_row_ptr[j + 1];
     double den = 0.0, sl = 0.0, sm = 0.0;
     int e = e0;
@@ -311,26 +347,16 @@ __global__ void k_den(const int* fm_row_ptr, const int* fm_col, const double* la
     }
     if (e1 == e0) {
       invden[j] = 0.0;
-      empty = 1;
+      ++n_empty;
     } else {
       const double inv = 1.0 / den;
       invden[j] = inv;
-      bj = sl * inv;
-      kj = sm * inv;
+      bmax = fmax(bmax, sl * inv);
+      kmax = fmax(kmax, sm * inv);
     }
   }
-  // one atomic per wave: the maxima of non-negative values (bit patterns
-  // order like the values) and the count of empty newsfeeds
-  for (int off = 32; off > 0; off >>= 1) {
-    bj = fmax(bj, __shfl_xor(bj, off, 64));
-    kj = fmax(kj, __shfl_xor(kj, off, 64));
-  }
-  const unsigned long long n_empty = __popcll(__ballot(empty));
-  if ((threadIdx.x & 63) == 0) {
-    atomicMax(&ctrl->bnorm_bits, (unsigned long long)__double_as_longlong(bj));
-    atomicMax(&ctrl->kappa_bits, (unsigned long long)__double_as_longlong(kj));
-    if (n_empty) atomicAdd(&ctrl->n_no_leaders, n_empty);
-  }
+  block_max2_count(bmax, kmax, n_empty, &ctrl->bnorm_bits, &ctrl->kappa_bits,
+                   &ctrl->n_no_leaders);
 }
 
 __global__ void k_node_consts(const double* lam, const double* mu, const double* invden,
@@ -361,11 +387,21 @@ __global__ void k_graph_rows(const int64_t* graph_off, int n_graphs, int64_t n, 
   inv_ng[i] = 1.0 / static_cast<double>(graph_off[lo + 1] - graph_off[lo]);
 }
 
-__global__ void k_max_row(const int* row_ptr, int64_t n, Ctrl* ctrl) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  int len = i < n ? row_ptr[i + 1] - row_ptr[i] : 0;
+// Longest row; the grid strides over the rows and each workgroup adds its
+// maximum with one atomic.
+__global__ __launch_bounds__(kBlock) void k_max_row(const int* row_ptr, int64_t n, Ctrl* ctrl) {
+  __shared__ unsigned long long red[kBlock / 64];
+  unsigned long long len = 0;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x)
+    len = max(len, (unsigned long long)(row_ptr[i + 1] - row_ptr[i]));
   for (int off = 32; off > 0; off >>= 1) len = max(len, __shfl_xor(len, off, 64));
-  if ((threadIdx.x & 63) == 0 && len) atomicMax(&ctrl->max_row, (unsigned long long)len);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = len;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kBlock / 64; ++w) len = max(len, red[w]);
+    if (len) atomicMax(&ctrl->max_row, len);
+  }
 }
 
 // a_ji = μ_i / den_j stored per edge of CSR(Aᵀ) row i (weighted form), one
@@ -686,11 +722,15 @@ psi_status scan_u32(const uint32_t* in, uint32_t* out, int64_t n, SortBufs& sb,
 }
 
 // Sorts sb.a[0..m) on the low `bits` bits; returns the buffer holding the result.
-psi_status radix_sort(SortBufs& sb, int64_t m, int bits, hipStream_t st, uint64_t** result) {
+// LSD passes over the 8-bit digits from bit first_bit up: a caller whose keys
+// are already ordered by their bits below first_bit (within every run of equal
+// higher bits) skips those digits.
+psi_status radix_sort(SortBufs& sb, int64_t m, int bits, hipStream_t st, uint64_t** result,
+                      int first_bit = 0) {
   int n_blocks = int((m + kSortTile - 1) / kSortTile);
   uint64_t* src = sb.a;
   uint64_t* dst = sb.b;
-  for (int shift = 0; shift < bits; shift += 8) {
+  for (int shift = first_bit; shift < bits; shift += 8) {
     hipLaunchKernelGGL(k_radix_hist, dim3(n_blocks), dim3(kBlock), 0, st, src, m, shift,
                        sb.counts, n_blocks);
     psi_status s = scan_u32(sb.counts, sb.counts, int64_t(256) * n_blocks, sb, st);
@@ -997,8 +1037,9 @@ psi_status build_operator(psi_operator* op, const int32_t* follower, const int32
     hipLaunchKernelGGL(k_fill_int, dim3(grid_for(n + 1)), dim3(kBlock), 0, st, fm_row_ptr, n + 1,
                        0);
   }
-  hipLaunchKernelGGL(k_den, dim3(grid_for(n)), dim3(kBlock), 0, st, fm_row_ptr, fm_col, op->lam,
-                     op->mu, n, op->invden, op->ctrl);
+  // bounded grids: each workgroup adds its maxima to the control block once
+  hipLaunchKernelGGL(k_den, dim3(std::max(1u, std::min(grid_for(n), 1024u))), dim3(kBlock), 0, st,
+                     fm_row_ptr, fm_col, op->lam, op->mu, n, op->invden, op->ctrl);
   hipLaunchKernelGGL(k_node_consts, dim3(grid_for(n)), dim3(kBlock), 0, st, op->lam, op->mu,
                      op->invden, n, op->c, op->d, op->mu32, op->invden32, op->c32);
   PSI_HIP_CHECK(hipGetLastError());
@@ -1012,7 +1053,11 @@ psi_status build_operator(psi_operator* op, const int32_t* follower, const int32
     sb2.a = other;
     sb2.b = sorted;
     uint64_t* res = nullptr;
-    psi_status s = radix_sort(sb2, m, key_bits, st, &res);
+    // the swapped keys (leader, follower) arrive ordered by follower, their
+    // low nb bits, so the digits wholly inside the follower field are already
+    // in order: within any run of equal higher bits (same leader, same
+    // high follower bits) ascending follower means ascending low bits
+    psi_status s = radix_sort(sb2, m, key_bits, st, &res, (nb / 8) * 8);
     if (s != PSI_OK) return s;
     hipLaunchKernelGGL(k_csr_from_keys, dim3(grid_for(m)), dim3(kBlock), 0, st, res, m, n, nb,
                        op->row_ptr, op->col);
@@ -1023,7 +1068,8 @@ psi_status build_operator(psi_operator* op, const int32_t* follower, const int32
     hipLaunchKernelGGL(k_fill_int, dim3(grid_for(n + 1)), dim3(kBlock), 0, st, op->row_ptr, n + 1,
                        0);
   }
-  hipLaunchKernelGGL(k_max_row, dim3(grid_for(n)), dim3(kBlock), 0, st, op->row_ptr, n, op->ctrl);
+  hipLaunchKernelGGL(k_max_row, dim3(std::max(1u, std::min(grid_for(n), 256u))), dim3(kBlock), 0,
+                     st, op->row_ptr, n, op->ctrl);
   if (op->n_graphs > 1)
     hipLaunchKernelGGL(k_graph_rows, dim3(grid_for(n)), dim3(kBlock), 0, st, op->graph_off,
                        op->n_graphs, n, op->graph_of, op->inv_ng);
