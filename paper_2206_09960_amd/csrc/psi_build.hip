@@ -138,12 +138,16 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint64_t* keys_i
                                                           int n_blocks) {
   __shared__ uint32_t wave_cnt[kSortWaves][256];
   __shared__ uint32_t glob[256];
+  __shared__ uint32_t loff[256];         // first slot of each digit in the staged tile
+  __shared__ uint32_t wsum[kSortWaves];
+  __shared__ uint64_t stage[kSortTile];  // the tile's keys, stably grouped by digit
   const int wave = threadIdx.x >> 6;
   const int lane = __lane_id();
   for (int w = 0; w < kSortWaves; ++w) wave_cnt[w][threadIdx.x] = 0;
   glob[threadIdx.x] = offsets[int64_t(threadIdx.x) * n_blocks + blockIdx.x];
   __syncthreads();
-  int64_t base = int64_t(blockIdx.x) * kSortTile + int64_t(wave) * (kSortRounds * 64);
+  const int64_t tile0 = int64_t(blockIdx.x) * kSortTile;
+  int64_t base = tile0 + int64_t(wave) * (kSortRounds * 64);
   uint64_t key[kSortRounds];
   uint32_t pos[kSortRounds];
   for (int r = 0; r < kSortRounds; ++r) {
@@ -164,22 +168,42 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint64_t* keys_i
     __builtin_amdgcn_wave_barrier();
   }
   __syncthreads();
-  {
-    uint32_t run = 0;
-    for (int w = 0; w < kSortWaves; ++w) {
-      uint32_t t = wave_cnt[w][threadIdx.x];
-      wave_cnt[w][threadIdx.x] = run;
-      run += t;
-    }
+  // digit t (thread t): the waves' exclusive prefix in wave order, the total
+  uint32_t total = 0;
+  for (int w = 0; w < kSortWaves; ++w) {
+    const uint32_t t = wave_cnt[w][threadIdx.x];
+    wave_cnt[w][threadIdx.x] = total;
+    total += t;
   }
+  // exclusive scan of the 256 digit totals: the digit's first slot in the tile
+  uint32_t incl = total;
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += y;
+  }
+  if (lane == 63) wsum[wave] = incl;
   __syncthreads();
+  uint32_t before = 0;
+  for (int w = 0; w < wave; ++w) before += wsum[w];
+  loff[threadIdx.x] = before + incl - total;
+  __syncthreads();
+  // stage every key at its place in the tile's stable digit order ...
   for (int r = 0; r < kSortRounds; ++r) {
     int64_t k = base + int64_t(r) * 64 + lane;
     if (k < n) {
       uint32_t dig = uint32_t(key[r] >> shift) & 255u;
-      const uint64_t p = uint64_t(glob[dig]) + wave_cnt[wave][dig] + pos[r];
-      if (p < uint64_t(n)) keys_out[p] = key[r];
+      stage[loff[dig] + wave_cnt[wave][dig] + pos[r]] = key[r];
     }
+  }
+  __syncthreads();
+  // ... and write each digit's run out, consecutive threads on consecutive
+  // addresses (the same positions as writing every key from its own lane)
+  const int cnt = static_cast<int>(n - tile0 < kSortTile ? n - tile0 : kSortTile);
+  for (int i = threadIdx.x; i < cnt; i += kBlock) {
+    const uint64_t v = stage[i];
+    const uint32_t dig = uint32_t(v >> shift) & 255u;
+    const uint64_t p = uint64_t(glob[dig]) + uint32_t(i - loff[dig]);
+    if (p < uint64_t(n)) keys_out[p] = v;
   }
 }
 
