@@ -25,6 +25,14 @@
 // p-tolerance ‖p_i(t) − p_i(t−1)‖₁ ≤ ε and ψ_i = (Σ_j c_j p_i^(j) + d_i) / N
 // (eqs. wall and psiscore).
 //
+// Graph mode: G independent graphs stacked as one block-diagonal operator are
+// solved together; each pass is an ordinary pass over the whole operator
+// (fused, or column-segmented with a combine that applies the per-graph
+// epilogue), then a per-graph kernel sums each graph's |Δ|, tests its own
+// tolerance and freezes it.  A graph frozen for a whole pass holds its result
+// in both iterate buffers, and the tiled passes skip the gathers of tiles
+// that lie wholly in such graphs.
+//
 // Work split.  Rows (leaders) with at most kHubEdges followers are packed
 // whole into wave tiles of about kWaveItems merge-path items; a wave sums its
 // rows edge by edge in order.  Longer rows are cut into chunks of kChunkEdges
@@ -691,9 +699,11 @@ __global__ void k_origin_psi(const double* part, int n_blk, int Kc, const int* o
 
 // ---------------------------------------------------------------- graphs
 // Per-graph gap of a block-diagonal operator: graph g sums its users' |Δ| in
-// a fixed order, records it, and freezes when it meets the tolerance; the
-// last graph to report sets done when every graph is done.  One counter
-// carries both the arrivals (low 16 bits) and the done graphs (high bits).
+// a fixed order, records it, and freezes when it meets the tolerance (a graph
+// frozen before this pass was copied into both buffers by it, so it is marked
+// skippable); the last graph to report sets done when every graph is done.
+// One counter carries both the arrivals (low 16 bits) and the done graphs
+// (high bits).
 __global__ __launch_bounds__(kGraphGapBlock) void k_graph_gap(const int64_t* graph_off,
                                                               int n_graphs,
                                                               const double* row_delta, Ctrl* ctrl,
