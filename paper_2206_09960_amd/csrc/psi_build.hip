@@ -335,8 +335,14 @@ __device__ inline void block_max2_count(double bm, double km, unsigned long long
 // Per follower j over CSR(A): den_j = Σ_{ℓ∈L(j)}(λ_ℓ+μ_ℓ) in ascending ℓ,
 // 1/den_j (0 for an empty newsfeed), and the row sums of B and A.  The grid
 // strides over the followers.
+// (λ_i, μ_i) side by side, so den reads one 16-byte record per leader.
+__global__ void k_pack_rates(const double* lam, const double* mu, int64_t n, double2* rates) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) rates[i] = make_double2(lam[i], mu[i]);
+}
+
 __global__ __launch_bounds__(kBlock) void k_den(const int* fm_row_ptr, const int* fm_col,
-                                                const double* lam, const double* mu, int64_t n,
+                                                const double2* rates, int64_t n,
                                                 double* invden, Ctrl* ctrl) {
   double bmax = 0.0, kmax = 0.0;  // row sums of B and A
   unsigned long long n_empty = 0;
@@ -352,8 +358,9 @@ __global__ __launch_bounds__(kBlock) void k_den(const int* fm_row_ptr, const int
       for (int u = 0; u < 4; ++u) k[u] = fm_col[e + u];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        lk[u] = lam[k[u]];
-        mk[u] = mu[k[u]];
+        const double2 r = rates[k[u]];
+        lk[u] = r.x;
+        mk[u] = r.y;
       }
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
@@ -363,8 +370,8 @@ __global__ __launch_bounds__(kBlock) void k_den(const int* fm_row_ptr, const int
       }
     }
     for (; e < e1; ++e) {
-      const int k = fm_col[e];
-      const double lk = lam[k], mk = mu[k];
+      const double2 r = rates[fm_col[e]];
+      const double lk = r.x, mk = r.y;
       den += lk + mk;
       sl += lk;
       sm += mk;
@@ -934,6 +941,7 @@ static size_t scratch_size(int64_t n, int64_t m_raw) {
   s += align_up(4 * size_t((scan_len + kScanTile - 1) / kScanTile + 1));
   s += align_up(4 * 4);                                               // scan total
   s += align_up(4 * size_t(n + 1));                                   // CSR(A) rows
+  s += align_up(16 * size_t(n));                                      // (λ, μ) interleaved
   return s;
 }
 
@@ -967,8 +975,9 @@ psi_status build_operator(psi_operator* op, const int32_t* follower, const int32
   sb.tile_sums = sc.take<uint32_t>((scan_len + kScanTile - 1) / kScanTile + 1);
   sb.total = sc.take<uint32_t>(4);
   int* fm_row_ptr_tmp = sc.take<int>(n + 1);
+  double2* rates = sc.take<double2>(n);
   if (!sb.a || !sb.b || !sb.counts || !sb.flags || !sb.tile_sums || !sb.total ||
-      !fm_row_ptr_tmp) {
+      !fm_row_ptr_tmp || !rates) {
     set_error("scratch workspace too small");
     return PSI_ENOSPACE;
   }
@@ -1062,8 +1071,10 @@ psi_status build_operator(psi_operator* op, const int32_t* follower, const int32
                        0);
   }
   // bounded grids: each workgroup adds its maxima to the control block once
+  hipLaunchKernelGGL(k_pack_rates, dim3(grid_for(n)), dim3(kBlock), 0, st, op->lam, op->mu, n,
+                     rates);
   hipLaunchKernelGGL(k_den, dim3(std::max(1u, std::min(grid_for(n), 1024u))), dim3(kBlock), 0, st,
-                     fm_row_ptr, fm_col, op->lam, op->mu, n, op->invden, op->ctrl);
+                     fm_row_ptr, fm_col, rates, n, op->invden, op->ctrl);
   hipLaunchKernelGGL(k_node_consts, dim3(grid_for(n)), dim3(kBlock), 0, st, op->lam, op->mu,
                      op->invden, n, op->c, op->d, op->mu32, op->invden32, op->c32);
   PSI_HIP_CHECK(hipGetLastError());
