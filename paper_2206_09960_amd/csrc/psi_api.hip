@@ -1,6 +1,7 @@
 // extern "C" entry points of the Power-ψ library (declared in include/psi.h).
 #include <cstring>
 #include <exception>
+#include <memory>
 #include <new>
 
 #include "psi_internal.h"
@@ -104,7 +105,8 @@ psi_status psi_build_operator(int64_t n_users, int64_t n_edges, const int32_t* f
     return PSI_ENOSPACE;
   }
   hipStream_t st = static_cast<hipStream_t>(stream);
-  psi_operator* o = new psi_operator();
+  // owned here until the build succeeds, so early returns and exceptions free it
+  std::unique_ptr<psi_operator> o(new psi_operator());
   PSI_HIP_CHECK(hipGetDevice(&o->device));
   o->n = n_users;
   o->m_in = n_edges;
@@ -112,8 +114,8 @@ psi_status psi_build_operator(int64_t n_users, int64_t n_edges, const int32_t* f
   o->flags = flags;
   if (n_graphs > 1) o->node_offsets.assign(node_offsets, node_offsets + n_graphs + 1);
   else o->node_offsets = {0, n_users};
-  psi::carve_persistent(o, static_cast<char*>(persistent), n_edges, n_graphs);
-  psi_status s = psi::build_operator(o, follower, leader, lambda, mu, node_offsets,
+  psi::carve_persistent(o.get(), static_cast<char*>(persistent), n_edges, n_graphs);
+  psi_status s = psi::build_operator(o.get(), follower, leader, lambda, mu, node_offsets,
                                      static_cast<char*>(scratch), scratch_bytes, st);
   if (s == PSI_OK) {
     hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&o->host_ctrl), 2 * sizeof(psi::Ctrl),
@@ -125,10 +127,9 @@ psi_status psi_build_operator(int64_t n_users, int64_t n_edges, const int32_t* f
   }
   if (s != PSI_OK) {
     if (o->host_ctrl) (void)hipHostFree(o->host_ctrl);
-    delete o;
     return s;
   }
-  *op = o;
+  *op = o.release();
   return PSI_OK;
   PSI_GUARD_END
 }
