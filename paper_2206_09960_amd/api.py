@@ -51,6 +51,34 @@ def _ptr(t) -> int | None:
     return None if t is None else int(t.data_ptr())
 
 
+def _device(device) -> torch.device:
+    """A CUDA device with its index (the current device when none is given)."""
+    d = torch.device(device) if device is not None else torch.device("cuda")
+    if d.type != "cuda":
+        raise ValueError(f"the library runs on a GPU, not on {d}")
+    return d if d.index is not None else torch.device("cuda", torch.cuda.current_device())
+
+
+def _vec_in(t, n: int, device: torch.device, dtype: torch.dtype, name: str) -> torch.Tensor:
+    """An input vector as a contiguous device tensor of exactly n values: the
+    kernels read n entries from its pointer, so a shorter one is refused."""
+    t = torch.as_tensor(t).to(device, dtype).contiguous()
+    if t.numel() != n:
+        raise ValueError(f"{name} must hold {n} values, not {t.numel()}")
+    return t
+
+
+def _vec_out(t, n: int, device: torch.device, dtype: torch.dtype, name: str) -> torch.Tensor:
+    """A result buffer: a new one, or the caller's if it is a contiguous
+    tensor of n values of the right type on the operator's device."""
+    if t is None:
+        return torch.empty(n, dtype=dtype, device=device)
+    if not isinstance(t, torch.Tensor) or t.dtype != dtype or t.device != device or \
+            not t.is_contiguous() or t.numel() != n:
+        raise ValueError(f"{name} must be a contiguous {dtype} tensor of {n} values on {device}")
+    return t
+
+
 def version() -> str:
     return _ffi.load().psi_version().decode()
 
@@ -75,8 +103,7 @@ class Operator:
                  stream=None, device=None):
         lib = _ffi.load()
         self._lib = lib
-        self.device = torch.device(device) if device is not None else torch.device(
-            "cuda", torch.cuda.current_device())
+        self.device = _device(device)
         host = isinstance(follower, np.ndarray)
         keep = []
         if host:
@@ -96,10 +123,17 @@ class Operator:
             keep = [f, l, la, m_]
             ptrs = [a.data_ptr() for a in keep]
             n_edges = int(f.shape[0])
+        # the build reads n_edges pairs and n_users activities from these pointers
+        if f.ndim != 1 or l.shape != f.shape:
+            raise ValueError("follower and leader must be 1-D arrays of the same length")
+        if la.shape != (int(n_users),) or m_.shape != (int(n_users),):
+            raise ValueError(f"lam and mu must each hold n_users = {int(n_users)} values")
         n_graphs = 1
         offs_ptr = None
         if node_offsets is not None:
             offs = np.ascontiguousarray(node_offsets, dtype=np.int64)
+            if offs.ndim != 1 or offs.size < 2:
+                raise ValueError("node_offsets must be a 1-D array of n_graphs + 1 offsets")
             n_graphs = int(offs.shape[0] - 1)
             keep.append(offs)
             offs_ptr = offs.ctypes.data
@@ -170,11 +204,10 @@ class Operator:
         p.col_segments = col_segments
         p.seg_form = _seg_form(seg_form)
         p.inner_tol = inner_tol
-        psi = psi_out if psi_out is not None else torch.empty(self.n, dtype=torch.float64,
-                                                              device=self.device)
+        psi = _vec_out(psi_out, self.n, self.device, torch.float64, "psi_out")
         s = torch.empty(self.n, dtype=torch.float64, device=self.device) if return_s else None
         if s0 is not None:
-            s0 = s0.to(self.device, torch.float64).contiguous()
+            s0 = _vec_in(s0, self.n, self.device, torch.float64, "s0")
         info = _ffi.Info()
         with torch.cuda.device(self.device):
             st = self._lib.psi_solve(self._h, ctypes.byref(p), _ptr(s0), _ptr(psi), _ptr(s),
@@ -189,7 +222,7 @@ class Operator:
     def step(self, s_in: torch.Tensor, precision: str = "fp64", tile_items: int = 0,
              col_segments: int = 0, seg_form: str | int = 0, stream=None):
         """psi_step: one Power-ψ step s_out = Aᵀ s_in + c and its L1 gap (enqueued)."""
-        s_in = s_in.to(self.device, torch.float64).contiguous()
+        s_in = _vec_in(s_in, self.n, self.device, torch.float64, "s_in")
         out = torch.empty_like(s_in)
         gap = torch.empty(1, dtype=torch.float64, device=self.device)
         with torch.cuda.device(self.device):
@@ -201,7 +234,7 @@ class Operator:
 
     def final(self, s: torch.Tensor, stream=None) -> torch.Tensor:
         """psi_final: ψ = (Bᵀ s + d)/N (enqueued)."""
-        s = s.to(self.device, torch.float64).contiguous()
+        s = _vec_in(s, self.n, self.device, torch.float64, "s")
         out = torch.empty_like(s)
         with torch.cuda.device(self.device):
             _check(self._lib.psi_final(self._h, s.data_ptr(), out.data_ptr(),
@@ -299,7 +332,7 @@ class Operator:
         psi = torch.empty(self.n, dtype=torch.float64, device=self.device)
         s = torch.empty(self.n, dtype=torch.float64, device=self.device) if return_s else None
         if s0 is not None:
-            s0 = s0.to(self.device, torch.float64).contiguous()
+            s0 = _vec_in(s0, self.n, self.device, torch.float64, "s0")
         info = _ffi.Info()
         with torch.cuda.device(self.device):
             st = self._lib.psi_solve_anderson(self._h, ctypes.byref(p), depth, _ptr(s0),
@@ -395,8 +428,7 @@ def gather_probe(n_x: int, n_idx: int, col_segments: int = 1, seed: int = 0, rep
     """psi_gather_probe on a random FP64 vector of n_x entries and n_idx
     random indices (uniform within a segment): the random-gather rate of an
     operator pass with that many users, edges and column segments."""
-    dev = torch.device(device) if device is not None else torch.device(
-        "cuda", torch.cuda.current_device())
+    dev = _device(device)
     gen = torch.Generator(device=dev).manual_seed(seed)
     x = torch.rand(n_x, dtype=torch.float64, device=dev, generator=gen)
     seg = n_x // col_segments
@@ -426,8 +458,7 @@ class Model:
     def __init__(self, params, device=None, stream=None):
         lib = _ffi.load()
         self._lib = lib
-        self.device = torch.device(device) if device is not None else torch.device(
-            "cuda", torch.cuda.current_device())
+        self.device = _device(device)
         p = np.ascontiguousarray(params, dtype=np.float32)
         if p.shape != (mpnn_param_count(),):
             raise ValueError(f"params must have {mpnn_param_count()} values")
@@ -475,8 +506,7 @@ class Model:
 
     def warmstart(self, op: Operator, s0_out: torch.Tensor | None = None, stream=None):
         ws = self.workspace(op, False)
-        s0 = s0_out if s0_out is not None else torch.empty(op.n, dtype=torch.float64,
-                                                           device=self.device)
+        s0 = _vec_out(s0_out, op.n, self.device, torch.float64, "s0_out")
         _check(self._lib.psi_warmstart(self._h, op.handle, s0.data_ptr(), ws.data_ptr(),
                                        ws.numel(), _stream_handle(stream)))
         return s0
@@ -485,7 +515,7 @@ class Model:
                       stream=None):
         """Returns (loss, t_hat or None); the gradient stays in the model."""
         ws = self.workspace(op, True)
-        s_target = s_target.to(self.device, torch.float64).contiguous()
+        s_target = _vec_in(s_target, op.n, self.device, torch.float64, "s_target")
         t_hat = torch.empty(op.n, dtype=torch.float32, device=self.device) if want_t_hat else None
         loss = ctypes.c_double()
         _check(self._lib.psi_mpnn_loss_backward(self._h, op.handle, s_target.data_ptr(),

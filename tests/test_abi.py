@@ -80,3 +80,20 @@ int main(void){printf("%zu %zu %zu\n", sizeof(psi_operator_stats), sizeof(psi_pa
         out = subprocess.run([exe], capture_output=True, text=True).stdout.split()
     assert [int(x) for x in out] == [ctypes.sizeof(_ffi.OperatorStats), ctypes.sizeof(_ffi.Params),
                                      ctypes.sizeof(_ffi.Info)]
+
+
+def test_binding_refuses_mismatched_inputs(lib):
+    """Lengths are checked before any pointer reaches the library (no GPU needed)."""
+    import numpy as np
+
+    from paper_2206_09960_amd import api
+    one = np.ones(3)
+    with pytest.raises(ValueError, match="same length"):
+        api.Operator(3, np.array([0, 1]), np.array([1]), one, one, device="cuda:0")
+    with pytest.raises(ValueError, match="n_users"):
+        api.Operator(3, np.array([0, 1]), np.array([1, 2]), np.ones(2), one, device="cuda:0")
+    with pytest.raises(ValueError, match="node_offsets"):
+        api.Operator(3, np.array([0, 1]), np.array([1, 2]), one, one, node_offsets=[0],
+                     device="cuda:0")
+    with pytest.raises(ValueError, match="GPU"):
+        api.Operator(3, np.array([0, 1]), np.array([1, 2]), one, one, device="cpu")

@@ -117,6 +117,21 @@ def test_strict_and_invalid_inputs(gpu_lib):
         op.solve(tol=0.0)
     with pytest.raises(api.PsiError, match="tile"):
         op.solve(tile_items=1000)
+    # the binding refuses buffers the kernels would read or write past
+    short = torch.ones(g.n - 1, dtype=torch.float64, device="cuda")
+    with pytest.raises(ValueError, match="s0"):
+        op.solve(s0=short)
+    with pytest.raises(ValueError, match="s_in"):
+        op.step(short)
+    with pytest.raises(ValueError, match="must hold"):
+        op.final(short)
+    with pytest.raises(ValueError, match="psi_out"):
+        op.solve(psi_out=torch.empty(g.n, dtype=torch.float32, device="cuda"))
+    with pytest.raises(ValueError, match="psi_out"):
+        op.solve(psi_out=torch.empty(2 * g.n, dtype=torch.float64, device="cuda")[::2])
+    psi_buf = torch.empty(g.n, dtype=torch.float64, device="cuda")
+    psi, info = op.solve(psi_out=psi_buf)
+    assert info["status"] == 0 and psi.data_ptr() == psi_buf.data_ptr()
 
 
 # ---------------------------------------------------------------- one step
