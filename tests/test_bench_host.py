@@ -1,0 +1,47 @@
+"""Host logic of bench.py (no GPU): the one-GPU guard, the algorithmic byte
+counts it divides by, and the rule that counter traffic is reported only for
+the kernel sources and launch it was measured on."""
+import json
+import os
+import subprocess
+import sys
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_exits_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
+
+
+def test_algorithmic_bytes_count_each_array_once():
+    n, m = 1000, 20000
+    # pull step: 4 B per follower id; per user row_ptr, z, c, μ, 1/den, s_old in, s_new, z_new out
+    assert bench.algorithmic_bytes("step64", n, m) == 4 * m + (4 + 7 * 8) * n
+    assert bench.algorithmic_bytes("final64", n, m) == 4 * m + (4 + 4 * 8) * n
+    # partial passes grow with the number of column segments, by the per-segment row data
+    one = bench.algorithmic_bytes("part64", n, m, 1)
+    assert bench.algorithmic_bytes("part64", n, m, 4) - one == 3 * 13 * n
+    assert bench.algorithmic_bytes("part32", n, m, 4) < bench.algorithmic_bytes("part64", n, m, 4)
+
+
+def test_traffic_only_for_the_measured_sources(tmp_path, monkeypatch):
+    h = bench.source_hash()
+    rec = {"source_hash": h, "kernel": "k_slices<4>",
+           "algorithmic_bytes": 123, "hbm_bytes_per_launch": 456.0}
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    (prof / "traffic_part64_wl.json").write_text(json.dumps(rec))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "source_hash", lambda: h)
+    assert bench.traffic_from_profile("part64", "wl", "k_slices<4>", 123) == 456.0
+    assert bench.traffic_from_profile("part64", "wl", "k_slices<5>", 123) is None
+    assert bench.traffic_from_profile("part64", "wl", "k_slices<4>", 124) is None
+    assert bench.traffic_from_profile("part64", "other", "k_slices<4>", 123) is None
+    (prof / "traffic_part64_wl.json").write_text(json.dumps(dict(rec, source_hash="0" * 16)))
+    assert bench.traffic_from_profile("part64", "wl", "k_slices<4>", 123) is None
