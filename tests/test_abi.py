@@ -97,3 +97,26 @@ def test_binding_refuses_mismatched_inputs(lib):
                      device="cuda:0")
     with pytest.raises(ValueError, match="GPU"):
         api.Operator(3, np.array([0, 1]), np.array([1, 2]), one, one, device="cpu")
+
+
+def test_product_path_never_imports_the_oracle():
+    """The package and its HIP sources neither import nor include anything
+    under oracle/ (the oracle is test infrastructure only)."""
+    import ast
+
+    pkg = os.path.join(ROOT, "paper_2206_09960_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            path = os.path.join(dirpath, f)
+            if f.endswith(".py"):
+                tree = ast.parse(open(path, encoding="utf-8").read())
+                for node in ast.walk(tree):
+                    names = []
+                    if isinstance(node, ast.Import):
+                        names = [a.name for a in node.names]
+                    elif isinstance(node, ast.ImportFrom):
+                        names = [node.module or ""]
+                    assert not any(n.split(".")[0] == "oracle" for n in names), path
+            elif f.endswith((".hip", ".h", ".cpp")):
+                src = open(path, encoding="utf-8").read()
+                assert not re.search(r'#include\s+[<"][^>"]*oracle', src), path
