@@ -482,13 +482,16 @@ def test_warm_start_and_fallback(gpu_lib):
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_full_size_1m(gpu_lib, prec):
     """The measured workload (N = 1,000,000, mean degree 20, γ = 2.2, σ = 1.5,
-    tol 1e-8), element by element against the oracle."""
+    tol 1e-8), element by element against the oracle, in the schedule the
+    autotuner picks (the launch configuration the benchmark times)."""
     api = gpu_lib
     g = synth.workload("cl_1m")
     A, B, c, d, r = oracle_run(g, 1e-8)
     op = gpu_op(api, g)
+    tuned = op.autotune(prec)
     psi, s, info = op.solve(tol=1e-8, precision=prec, return_s=True)
     assert info["status"] == 0, info
+    assert info["col_segments"] == tuned["col_segments"], (info, tuned)
     assert oracle.rel_l1(r["psi"], psi.cpu().numpy()) <= 1e-9
     assert oracle.rel_l2(r["psi"], psi.cpu().numpy()) <= 1e-9
     s_np = s.cpu().numpy()
