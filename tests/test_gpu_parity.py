@@ -95,6 +95,30 @@ def test_operator_structure(gpu_lib, case):
     assert st["max_followers"] == int(np.diff(AT.indptr).max())
 
 
+@pytest.mark.parametrize("case", ["random_small", "chung_lu_20k"])
+def test_host_and_device_inputs_build_the_same_operator(gpu_lib, case):
+    """Edge lists and activities passed as device memory (no PSI_INPUT_HOST)
+    build the operator of the same inputs passed from the host, bit for bit,
+    and its solve returns the same ψ bit for bit."""
+    api = gpu_lib
+    if case == "random_small":
+        g = synth.random_small(300, 0.03, 4, dangling=True, extra_self_loops=5, extra_duplicates=9)
+    else:
+        g = synth.chung_lu(20000, 12, 2.2, 10, sigma=1.5)
+    op_h = gpu_op(api, g)
+    op_d = api.Operator(g.n, torch.from_numpy(g.follower).cuda(), torch.from_numpy(g.leader).cuda(),
+                        torch.from_numpy(g.lam).cuda(), torch.from_numpy(g.mu).cuda())
+    sh, sd = op_h.stats(), op_d.stats()
+    assert sh.pop("flags") == api.PSI_INPUT_HOST and sd.pop("flags") == 0
+    assert sd == sh
+    vh, vd = op_h.views(), op_d.views()
+    for key in vh:
+        assert torch.equal(vh[key], vd[key]), key
+    psi_h, _ = op_h.solve(tol=1e-10)
+    psi_d, _ = op_d.solve(tol=1e-10)
+    assert torch.equal(psi_h, psi_d)
+
+
 def test_strict_and_invalid_inputs(gpu_lib):
     api = gpu_lib
     g = synth.random_small(40, 0.1, 5, extra_self_loops=2)
