@@ -120,3 +120,31 @@ def test_product_path_never_imports_the_oracle():
             elif f.endswith((".hip", ".h", ".cpp")):
                 src = open(path, encoding="utf-8").read()
                 assert not re.search(r'#include\s+[<"][^>"]*oracle', src), path
+
+
+def test_workspace_queries_and_limits(lib):
+    """Host-only size queries: monotone in users and edges, the per-edge
+    FP64 weights add at least 8 bytes per edge, and the documented limits
+    are refused with PSI_EINVAL and a message that a later success clears."""
+    from paper_2206_09960_amd import _ffi
+
+    def size(n, m, graphs=1, flags=0):
+        a, b = ctypes.c_size_t(), ctypes.c_size_t()
+        st = lib.psi_operator_workspace_size(n, m, graphs, flags, ctypes.byref(a), ctypes.byref(b))
+        return st, a.value, b.value
+
+    st0, p0, s0 = size(10_000, 100_000)
+    assert st0 == _ffi.PSI_OK
+    _, p1, s1 = size(20_000, 100_000)
+    _, p2, s2 = size(10_000, 200_000)
+    assert p1 > p0 and p2 > p0 and s2 >= s0 and s1 >= s0
+    _, pw, _ = size(10_000, 100_000, flags=_ffi.PSI_WEIGHTED_FP64)
+    assert pw >= p0 + 8 * 100_000
+    _, pg, _ = size(10_000, 100_000, graphs=16)
+    assert pg >= p0
+    for args, word in (((1 << 30, 0), b"n_users"), ((1 << 29, (1 << 31) - (1 << 29)), b"too large"),
+                       ((10, -1), b"n_edges"), ((10, 10, 0), b"n_graphs")):
+        st, _, _ = size(*args)
+        assert st == _ffi.PSI_EINVAL, args
+        assert word in lib.psi_last_error(), (args, lib.psi_last_error())
+    assert size(10, 10)[0] == _ffi.PSI_OK and lib.psi_last_error() == b""
