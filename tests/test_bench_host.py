@@ -45,3 +45,25 @@ def test_traffic_only_for_the_measured_sources(tmp_path, monkeypatch):
     assert bench.traffic_from_profile("part64", "other", "k_slices<4>", 123) is None
     (prof / "traffic_part64_wl.json").write_text(json.dumps(dict(rec, source_hash="0" * 16)))
     assert bench.traffic_from_profile("part64", "wl", "k_slices<4>", 123) is None
+
+
+def test_bench_descriptions_match_the_generator():
+    """The workload text bench.py prints in `config` states the generator's
+    own parameters (sizes, degree, exponent, activity spread, tolerance)."""
+    import synth
+    for name, text in bench.DESCRIPTIONS.items():
+        w = synth.WORKLOADS[name]
+        if w.get("kind") == "multi":
+            assert f"{w['n_graphs']} directed Chung-Lu graphs" in text
+            assert f"[{w['n_lo']:,}, {w['n_hi']:,}]" in text
+        else:
+            assert f"N={w['n']:,}" in text, name
+        assert f"mean degree {w['mean_degree']}" in text, name
+        assert f"exponent {w['gamma']}" in text, name
+        sig = f"{w['sigma']:g}" if w["sigma"] != int(w["sigma"]) else f"{int(w['sigma'])}"
+        assert f"LogNormal(0,{sig})" in text, name
+        assert f"tol {w['tol']:.0e}".replace("e-0", "e-") in text, name
+        if "d_max" in w:
+            assert f"max followers {w['d_max']:,}" in text
+        if "scenarios" in w:
+            assert text.startswith(f"{w['scenarios']} activity scenarios")
