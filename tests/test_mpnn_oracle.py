@@ -2,7 +2,6 @@
 its loss, the bfloat16 rounding against its definition, and Adam against a
 hand-computed first step."""
 import numpy as np
-import pytest
 
 import oracle
 import oracle.mpnn_oracle as mo
