@@ -27,6 +27,12 @@ Everything here is FP64.  With ``bf16_storage=True`` the values the GPU stores i
 bfloat16 (Wm, Wl, and h, the scaled message p and m after each layer) are rounded the same way
 (round to nearest even) so GPU and oracle differ only by FP32 summation
 order; the backward pass treats the rounding as the identity, as the GPU does.
+
+Pins: the gradient against central finite differences of the loss, a descent
+step lowering the loss, the bfloat16 rounding against its definition and the
+first Adam step against its closed form.  How well a trained network predicts
+t has no reference value in the paper: that quality is parity unpinned, and the
+solver, which keeps c whenever s0's residual is larger, stays the judge of ψ.
 """
 from __future__ import annotations
 
