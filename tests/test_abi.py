@@ -148,3 +148,14 @@ def test_workspace_queries_and_limits(lib):
         assert st == _ffi.PSI_EINVAL, args
         assert word in lib.psi_last_error(), (args, lib.psi_last_error())
     assert size(10, 10)[0] == _ffi.PSI_OK and lib.psi_last_error() == b""
+
+
+def test_build_compiles_every_source_for_gfx950_without_packed_fp32():
+    """The build covers every HIP source, targets gfx950 and turns packed FP32
+    instructions off in device code."""
+    from paper_2206_09960_amd import build as b
+    on_disk = sorted(f for f in os.listdir(b.CSRC) if f.endswith(".hip"))
+    assert sorted(b.SOURCES) == on_disk
+    flags = " ".join(b.FLAGS)
+    assert "--offload-arch=gfx950" in flags or os.environ.get("PSI_OFFLOAD_ARCH")
+    assert "-Xclang -target-feature -Xclang -packed-fp32-ops" in flags
