@@ -21,7 +21,8 @@ Functions and the passages they follow:
 * ``power_nf``          — Algorithm 1 (Power-NF) for one origin.
 * ``psi_closed_form``   — eq. (ultimsol) with the series summed exactly: one
                           solve of (I − Aᵀ) s = c, then ψ = (Bᵀ s + d) / N.
-* ``power_psi``         — Algorithm 2 (Power-ψ), FP64, in the paper's order.
+* ``power_psi``         — Algorithm 2 (Power-ψ), FP64: the recursion of
+                          eq. (power_psi) from s_0 = c, stopped by eq. (condition).
 * ``pagerank_power``    — the PageRank power method, eq. (pagerank_power).
 * ``fixed_point_residual``, ``b_norm``, ``kappa`` — the L1 fixed-point residual
                           of eq. (power_psi) and the norms used by the bound of
@@ -133,17 +134,27 @@ def psi_by_definition(n, follower, leader, lam, mu):
     return psi, P, Q
 
 
+def _finite_gap(gap, what):
+    """A NaN or infinite gap means the iteration has left the reals: raise
+    instead of letting a NaN comparison end the loop as if it had converged."""
+    if not np.isfinite(gap):
+        raise FloatingPointError(f"{what}: the step size is {gap} (not finite)")
+    return gap
+
+
 def power_nf(A, b_i, tol, max_iter=100_000):
-    """Algorithm 1 (Power-NF): p ← b_i; repeat p ← A p + b_i until ‖Δp‖₁ ≤ ε."""
+    """Algorithm 1 (Power-NF) for one origin i: the fixed point of
+    p = A p + b_i (eq. fixpt_algo) by repeated substitution from p = b_i,
+    ended by the p-tolerance ‖p_t − p_{t−1}‖₁ ≤ ε (Sec. V)."""
     p = np.array(b_i, dtype=np.float64)
     t = 0
     gap = 1.0
     while gap > tol:
         if t >= max_iter:
             raise RuntimeError("Power-NF did not converge")
-        p_old = p
-        p = A @ p_old + b_i
-        gap = np.abs(p - p_old).sum()
+        p_next = A @ p + b_i
+        gap = _finite_gap(np.abs(p_next - p).sum(), "Power-NF")
+        p = p_next
         t += 1
     return p, t
 
@@ -171,40 +182,47 @@ def kappa(A):
 
 def power_psi(A, B, c, d, tol, tol_mode="abs_l1", max_iter=100_000, s0=None,
               record=False, steps=None):
-    """Algorithm 2 (Power-ψ) in FP64, steps in the paper's order.
+    """Algorithm 2 (Power-ψ) in FP64.
 
-        s ← c (or a given start);  B_norm ← ‖B‖;  t ← 0;  gap ← 1
-        while gap > ε:  s_old ← s;  sᵀ ← s_oldᵀA + cᵀ;  gap ← ‖s_old − s‖₁
-                        (× B_norm for tol_mode "bnorm", ÷ ‖s‖₁ for "rel_l1");
-                        t ← t + 1
-        ψᵀ ← (sᵀB + dᵀ) / N
+    The iterate is the partial sum of the series of eq. (ultimsol): the
+    recursion of eq. (power_psi), s_t = Aᵀ s_{t−1} + c, from s_0 = c (or a
+    given start).  It stops at the first t whose step size ε_t = ‖s_t −
+    s_{t−1}‖₁ (eq. eps_t) passes the test of eq. (condition); ``tol_mode``
+    "bnorm" multiplies ε_t by ‖B‖ before the test, as Algorithm 2 does, and
+    "rel_l1" divides it by ‖s_t‖₁.  Algorithm 2 starts from a gap of 1, so
+    ε ≥ 1 takes no step.  ψ = (Bᵀ s + d) / N is formed from the final s.
 
     Returns a dict with psi, s, iterations t, the final gap and (optionally)
     every gap.  ``steps`` runs exactly that many iterations whatever the gap
-    (used to inspect ψ_t at a fixed t).
+    (used to inspect ψ_t at a fixed t).  A step size that is not finite
+    raises FloatingPointError.
     """
     if not tol > 0:
         raise ValueError("tolerance must be positive")
+    if tol_mode not in ("abs_l1", "bnorm", "rel_l1"):
+        raise ValueError(f"unknown tol_mode {tol_mode!r}")
     n = A.shape[0]
     AT = A.T.tocsr()
     BT = B.T.tocsr()
-    s = np.array(c if s0 is None else s0, dtype=np.float64)
     bnorm = b_norm(B)
-    t = 0
-    gap = 1.0
+
+    def scaled(step_l1, s_new):
+        if tol_mode == "bnorm":
+            return step_l1 * bnorm
+        if tol_mode == "rel_l1":
+            return step_l1 / np.abs(s_new).sum()
+        return step_l1
+
+    s = np.array(c if s0 is None else s0, dtype=np.float64)
     gaps = []
-    while (gap > tol) if steps is None else (t < steps):
+    gap = 1.0
+    t = 0
+    while (t < steps) if steps is not None else (gap > tol):
         if t >= max_iter:
             raise RuntimeError("Power-psi did not converge")
-        s_old = s
-        s = AT @ s_old + c
-        gap = np.abs(s_old - s).sum()
-        if tol_mode == "bnorm":
-            gap *= bnorm
-        elif tol_mode == "rel_l1":
-            gap /= np.abs(s).sum()
-        elif tol_mode != "abs_l1":
-            raise ValueError(f"unknown tol_mode {tol_mode!r}")
+        s_next = AT @ s + c
+        gap = _finite_gap(scaled(np.abs(s_next - s).sum(), s_next), "Power-psi")
+        s = s_next
         t += 1
         if record:
             gaps.append(gap)
@@ -231,9 +249,9 @@ def pagerank_power(W, alpha, tol, max_iter=100_000):
     while gap > tol:
         if t >= max_iter:
             raise RuntimeError("PageRank power method did not converge")
-        old = pi
-        pi = alpha * (WT @ old) + (1.0 - alpha) / n
-        gap = np.abs(pi - old).sum()
+        pi_next = alpha * (WT @ pi) + (1.0 - alpha) / n
+        gap = _finite_gap(np.abs(pi_next - pi).sum(), "PageRank power method")
+        pi = pi_next
         t += 1
     return pi, t
 

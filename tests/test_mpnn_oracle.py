@@ -52,7 +52,9 @@ def test_bf16_rounding():
     x = np.array([1.0, 1.0 + 2 ** -8, 1.0 + 2 ** -7 + 2 ** -9, -3.1415926, 0.0, 65504.0])
     r = mo.bf16(x)
     assert r[0] == 1.0 and r[1] == 1.0  # tie rounds to even
-    assert r[2] == 1.0 + 2 ** -6 or r[2] == 1.0 + 2 ** -7
+    # 1 + 2^-7 + 2^-9 lies below the midpoint 1 + 2^-7 + 2^-8 of its two
+    # neighbours 1 + 2^-7 and 1 + 2^-6: only the lower one is correct
+    assert r[2] == 1.0 + 2 ** -7
     assert abs(r[3] + 3.140625) < 1e-12 and r[4] == 0.0
     # every rounded value has at most 8 significant bits
     for v in r[r != 0]:

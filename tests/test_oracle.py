@@ -21,6 +21,11 @@ def two_user():
         return json.load(fh)
 
 
+def three_user():
+    with open(os.path.join(GOLDEN, "three_user.json")) as fh:
+        return json.load(fh)
+
+
 def op_of(g):
     return oracle.operator(g.n, g.follower, g.leader, g.lam, g.mu)
 
@@ -52,6 +57,31 @@ def test_two_user_iterates_bit_exact():
         assert r["gap"] == gd["gaps"][t - 1]
     r = oracle.power_psi(A, B, c, d, tol=0.3, record=True)
     assert r["gaps"] == gd["gaps"][:3] and r["iterations"] == 3
+
+
+def test_three_user_norms_are_row_sums():
+    """‖B‖ and κ are the largest row sums (row-vector L1 norm); in this
+    hand-derived case the largest column sums differ, so a transposed
+    reading fails here."""
+    gd = three_user()
+    A, B, c, d = oracle.operator(gd["n"], gd["follower"], gd["leader"], gd["lambda"], gd["mu"])
+    assert oracle.b_norm(B) == pytest.approx(gd["b_norm"], rel=1e-15)
+    assert oracle.kappa(A) == pytest.approx(gd["kappa"], rel=1e-15)
+    assert gd["b_norm"] != gd["b_norm_columns"] and gd["kappa"] != gd["kappa_columns"]
+    assert oracle.b_norm(B.T.tocsr()) == pytest.approx(gd["b_norm_columns"], rel=1e-15)
+    assert oracle.kappa(A.T.tocsr()) == pytest.approx(gd["kappa_columns"], rel=1e-15)
+    assert np.array_equal(c, gd["c"]) and np.array_equal(d, gd["d"])
+    r = oracle.power_psi(A, B, c, d, 1e-15)
+    np.testing.assert_allclose(r["s"], gd["s_fixed_point"], rtol=1e-15, atol=0)
+    np.testing.assert_allclose(r["psi"], gd["psi"], rtol=1e-15, atol=0)
+    assert r["psi"].sum() == pytest.approx(gd["psi_sum"], rel=1e-15)
+    psi_def, _, _ = oracle.psi_by_definition(gd["n"], gd["follower"], gd["leader"],
+                                             gd["lambda"], gd["mu"])
+    np.testing.assert_allclose(psi_def, gd["psi"], rtol=1e-15, atol=0)
+    # the bnorm stopping mode uses the row-sum norm: first gap = ‖B‖·‖s_1 − c‖₁
+    rb = oracle.power_psi(A, B, c, d, tol=1e-3, tol_mode="bnorm", record=True)
+    s1 = A.T @ c + c
+    assert rb["gaps"][0] == pytest.approx(gd["b_norm"] * np.abs(s1 - c).sum(), rel=1e-15)
 
 
 # ---------------------------------------------------------------- definition (N solves)
@@ -253,9 +283,24 @@ def test_pins_reject_planted_mistakes(mutant):
     try:
         r = oracle.power_psi(A, B, c, d, 1e-13, max_iter=5000)
         bad = r["psi"]
-    except RuntimeError:
+    except (RuntimeError, FloatingPointError):
         return  # diverged: caught
     assert oracle.rel_l1(psi_def, bad) > 1e-6
+
+
+def test_non_finite_gap_raises():
+    """A dropped term in den makes the row sums of A exceed 1: the iterates
+    overflow, and the loop must raise rather than stop on a NaN gap."""
+    g = synth.random_small(40, 0.12, 51, dangling=True)
+    A, B, c, d = _den_variant(g.n, g.follower, g.leader, g.lam, g.mu)
+    assert oracle.kappa(A) > 1
+    with pytest.raises(FloatingPointError):
+        oracle.power_psi(A, B, c, d, 1e-13, max_iter=100_000)
+    with pytest.raises(FloatingPointError):
+        oracle.power_nf(A, B[:, 0].toarray().ravel(), 1e-13, max_iter=100_000)
+    W = sp.csr_matrix(np.full((3, 3), 1.0))
+    with pytest.raises(FloatingPointError):
+        oracle.pagerank_power(W, 2.0, 1e-13, max_iter=100_000)
 
 
 def test_sampled_rows_agree_with_the_full_operator():
