@@ -53,7 +53,7 @@ import scipy.sparse as sp
 __all__ = [
     "clean_edges", "operator", "psi_by_definition", "power_nf", "psi_closed_form",
     "power_psi", "pagerank_power", "transition_matrix", "fixed_point_residual",
-    "b_norm", "kappa", "rel_l1", "rel_l2", "sampled_rows",
+    "b_norm", "kappa", "rel_l1", "rel_l2", "max_rel", "sampled_rows",
 ]
 
 
@@ -264,6 +264,16 @@ def fixed_point_residual(A, c, s):
 def rel_l1(ref, x):
     ref = np.asarray(ref, dtype=np.float64)
     return float(np.abs(np.asarray(x) - ref).sum() / np.abs(ref).sum())
+
+
+def max_rel(ref, x):
+    """Largest element-wise relative error max_i |x_i − ref_i| / |ref_i| (ψ_i ≥
+    d_i/N > 0 and s_i ≥ c_i > 0, so the ratio is defined for both)."""
+    ref = np.asarray(ref, dtype=np.float64)
+    x = np.asarray(x, dtype=np.float64)
+    if np.any(ref == 0):
+        raise ValueError("max_rel needs a reference without zeros")
+    return float(np.max(np.abs(x - ref) / np.abs(ref))) if ref.size else 0.0
 
 
 def rel_l2(ref, x):

@@ -13,6 +13,20 @@ def pytest_configure(config):
     config.addinivalue_line("markers", "slow: long-running test (full-size inputs)")
 
 
+@pytest.fixture
+def progress(request):
+    """say(msg): a progress line written past pytest's output capture, so a
+    long phase of a test (a full-size oracle run) shows that it is alive."""
+    import time
+    capman = request.config.pluginmanager.getplugin("capturemanager")
+
+    def say(msg):
+        with capman.global_and_fixture_disabled():
+            sys.stderr.write(f"[{request.node.name} {time.strftime('%H:%M:%S')}] {msg}\n")
+            sys.stderr.flush()
+    return say
+
+
 @pytest.fixture(scope="session")
 def gpu_lib():
     """The HIP path through its C ABI; skips when no GPU is visible."""

@@ -1,40 +1,59 @@
 """Parity at the full sizes of the benchmark configurations.
 
-Where the whole oracle fits (the 64-scenario batch's first scenario, the
-graphs of the 256-graph batch) it runs in full and the bar is 1e-9 relative
-L1.  Where it does not (40M users / 1.4G edges, 10M users / 200M edges), the
-oracle evaluates the definitions at sampled users one by one
-(oracle.sampled_rows): the fixed-point residual of the GPU's s must be
-within the solve's tolerance at every sampled user (a converged solve has
-‖Aᵀs + c − s‖₁ ≲ tol over all users), and the GPU's ψ must be the last line
-of Algorithm 2 applied to that s.  Invariants that hold at any size (s ≥ c,
-ψ ≥ d/N, Σψ ≤ 1) are checked on every user.  Inputs are drawn on the GPU by
-the torch twin of the generator (the same values as the NumPy generator).
+Every check here is over all users.  The 64-scenario batch's first scenario
+and the graphs of the 256-graph batch run through the NumPy oracle.  The two
+big single graphs (40M users / 1.4G edges, 10M users / 200M edges) run
+through the C/OpenMP oracle (oracle/psi_oracle_c.c) on the host: its own
+clean-up and operator from the raw edges, then
+  * the fixed-point residual r = Aᵀs + c − s of eq. (power_psi) at every
+    user, from the GPU's s: ‖r‖₁ must be within the solve's tolerance plus
+    the rounding of two different summation orders (a few units in the last
+    place of each s_i);
+  * ψ = (Bᵀs + d)/N (the last line of Algorithm 2) from the GPU's s, against
+    the GPU's ψ at every user;
+  * the oracle's own Algorithm 2 at the same tolerance, against the GPU's ψ
+    at every user (relative L1 and the largest element-wise error).
+Invariants that hold at any size (s ≥ c, ψ ≥ d/N, Σψ ≤ 1) are checked too.
+Inputs are drawn on the GPU by the torch twin of the generator (the same
+values as the NumPy generator) and copied to the host for the oracle.
 """
 import os
+import time
 
 import numpy as np
 import pytest
 import torch
 
 import oracle
+import oracle.psi_oracle_c as oc
 import synth
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
 WEIGHTS = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
                        "paper_2206_09960_amd", "weights", "warmstart_cl.npy")
+U = 2.0 ** -53  # unit roundoff of FP64
 
 
-def say(msg):
-    print(f"\n[fullsize] {msg}", flush=True)
+say = print  # replaced per test by the uncaptured progress writer
 
 
-def sample(row_len, k, seed, n_hubs=1):
-    rng = np.random.default_rng(seed)
-    rows = rng.choice(row_len.size, k, replace=False)
-    top = np.argsort(row_len)[-n_hubs:]
-    return np.unique(np.concatenate([rows, top]))
+@pytest.fixture(autouse=True)
+def _progress(progress):
+    global say
+    say = progress
+    yield
+    say = print
+
+
+def oracle_solve(G, tol):
+    """The C oracle's Algorithm 2 with a progress line every 10 steps."""
+    t0 = time.time()
+
+    def tick(t, gap):
+        if t % 10 == 0:
+            say(f"oracle step {t}: gap {gap:.3e} ({time.time() - t0:.0f} s)")
+    return G.power_psi(tol, progress=tick)
 
 
 def check_invariants(psi, s, lam, mu):
@@ -46,16 +65,50 @@ def check_invariants(psi, s, lam, mu):
     assert psi.sum() <= 1 + 1e-9
 
 
-def check_sampled(n, f, l, lam, mu, s, psi, rows, tol):
-    res, psi_rows = oracle.sampled_rows(n, f, l, lam, mu, s, rows)
-    slack = tol + 1e-13 * np.abs(s[rows])
-    bad = np.abs(res) > slack
-    assert not bad.any(), (rows[bad], res[bad])
-    np.testing.assert_allclose(psi[rows], psi_rows, rtol=1e-12, atol=0)
-    return float(np.abs(res).max())
+def host_oracle(n, f, l, lam, mu, gpu_stats):
+    """The C oracle's operator from the raw edges; its clean-up counts and
+    longest row must equal the GPU build's exactly."""
+    t = time.time()
+    G = oc.Graph(n, f, l, lam, mu)
+    say(f"oracle build on {oc.max_threads()} threads: {time.time() - t:.1f} s, M={G.m}")
+    assert (G.m, G.n_self_loops, G.n_duplicates, G.max_followers, G.n_no_leaders) == (
+        gpu_stats["n_edges"], gpu_stats["n_self_loops"], gpu_stats["n_duplicates"],
+        gpu_stats["max_followers"], gpu_stats["n_no_leaders"])
+    return G
 
 
-@pytest.mark.timeout(600)
+def check_against_oracle(G, name, s, psi, tol):
+    """Residual at every user and ψ from the same s at every user."""
+    t = time.time()
+    r, l1 = G.residual(s)
+    c, _, _ = G.vectors()
+    # both sides round each s_i' = c_i + μ_i y_i to within a few ulps, in
+    # different summation orders: allow 8 units of roundoff of s_i and s_i'
+    slack = 8 * U * (2 * s + c)
+    assert np.all(np.abs(r) <= tol + slack), int(np.argmax(np.abs(r) - slack))
+    assert l1 <= tol + slack.sum(), (l1, tol, slack.sum())
+    psi_o = G.final(s)
+    mr = oracle.max_rel(psi_o, psi)
+    say(f"{name}: ‖Aᵀs + c − s‖₁ = {l1:.3e} (tol {tol:.0e}, rounding slack "
+        f"{slack.sum():.2e}), max |r_i| {np.abs(r).max():.2e}; ψ(s) max rel err {mr:.2e} "
+        f"({time.time() - t:.1f} s)")
+    assert mr <= 1e-12
+    return l1
+
+
+def check_full_solve(G, ref, runs, tol):
+    """The oracle's Algorithm 2 against every GPU result, user by user."""
+    for name, psi, s, info, elem in runs:
+        e1 = oracle.rel_l1(ref["psi"], psi)
+        mr = oracle.max_rel(ref["psi"], psi)
+        es = oracle.rel_l1(ref["s"], s)
+        say(f"{name} vs oracle Algorithm 2: ψ rel L1 {e1:.2e}, max rel {mr:.2e}; s rel L1 "
+            f"{es:.2e}; iterations GPU {info['iterations']} oracle {ref['iterations']}")
+        assert e1 <= 1e-9 and es <= 1e-9
+        assert mr <= elem
+
+
+@pytest.mark.timeout(1200)
 def test_c5_warm_start_10m_users(gpu_lib):
     api = gpu_lib
     tol = synth.WORKLOADS["cl_10m"]["tol"]
@@ -77,9 +130,15 @@ def test_c5_warm_start_10m_users(gpu_lib):
     psi_c, s_c, psi_w, s_w = (t.cpu().numpy() for t in (psi_c, s_c, psi_w, s_w))
     assert oracle.rel_l1(psi_c, psi_w) <= 1e-9  # one fixed point, whatever the start
     check_invariants(psi_w, s_w, g.lam, g.mu)
-    row_len = np.diff(op.views()["row_ptr"].cpu().numpy())
-    rows = sample(row_len, 48, 5, n_hubs=1)
-    check_sampled(g.n, f, l, g.lam, g.mu, s_w, psi_w, rows, tol)
+    G = host_oracle(g.n, f, l, g.lam, g.mu, op.stats())
+    del f, l
+    check_against_oracle(G, "C5 cold", s_c, psi_c, tol)
+    check_against_oracle(G, "C5 warm", s_w, psi_w, tol)
+    ref = oracle_solve(G, tol)
+    say(f"C5: oracle Algorithm 2 {ref['iterations']} iterations in {ref['seconds']:.1f} s")
+    check_full_solve(G, ref, [("C5 cold", psi_c, s_c, cold, 1e-9 if cold["iterations"] ==
+                               ref["iterations"] else 1e-6),
+                              ("C5 warm", psi_w, s_w, warm, 1e-6)], tol)
 
 
 @pytest.mark.timeout(900)
@@ -151,7 +210,7 @@ def test_c4b_256_graphs_full_oracle_on_samples(gpu_lib):
     say(f"C4b: graphs {picks} match the full oracle")
 
 
-@pytest.mark.timeout(900)
+@pytest.mark.timeout(1800)
 def test_c3_40m_users_hub_rows(gpu_lib):
     api = gpu_lib
     tol = synth.WORKLOADS["cl_40m"]["tol"]
@@ -175,8 +234,13 @@ def test_c3_40m_users_hub_rows(gpu_lib):
     psi64, s64, psim, sm = (t.cpu().numpy() for t in (psi64, s64, psim, sm))
     assert oracle.rel_l1(psi64, psim) <= 1e-6
     check_invariants(psi64, s64, g.lam, g.mu)
-    row_len = np.diff(op.views()["row_ptr"].cpu().numpy())
-    rows = sample(row_len, 48, 3, n_hubs=1)
-    r64 = check_sampled(g.n, f, l, g.lam, g.mu, s64, psi64, rows, tol)
-    rm = check_sampled(g.n, f, l, g.lam, g.mu, sm, psim, rows, tol)
-    say(f"C3: max sampled |residual| fp64 {r64:.2e}, mixed {rm:.2e}")
+    G = host_oracle(g.n, f, l, g.lam, g.mu, st)
+    del f, l
+    check_against_oracle(G, "C3 fp64", s64, psi64, tol)
+    check_against_oracle(G, "C3 mixed", sm, psim, tol)
+    ref = oracle_solve(G, tol)
+    say(f"C3: oracle Algorithm 2 {ref['iterations']} iterations in {ref['seconds']:.1f} s "
+        f"({G.m * ref['iterations'] / ref['seconds'] / 1e9:.2f} G edges/s)")
+    check_full_solve(G, ref, [("C3 fp64", psi64, s64, i64, 1e-9 if i64["iterations"] ==
+                               ref["iterations"] else 1e-6),
+                              ("C3 mixed", psim, sm, im, 1e-6)], tol)

@@ -2,8 +2,12 @@
 
 Tolerances: FP64 solves match the oracle's Algorithm 2 at the same tolerance
 within 1e-9 relative L1; mixed precision (FP32 corrections + FP64 residual)
-within 1e-9; FP32-only within 1e-6.  Index work (CSR structure, clean-up
-counts) is compared exactly.
+within 1e-9; FP32-only within 1e-6.  Element by element (ψ_i ≥ d_i/N > 0, so
+the relative error of every user is defined): 1e-9 when the GPU and the
+oracle stop at the same step, 1e-6 when their stopping steps differ by one
+(allowed: rounding can move the last gap across tol) or the solve is mixed,
+1e-4 for FP32-only.  Index work (CSR structure, clean-up counts) is compared
+exactly.
 """
 import ctypes
 import json
@@ -25,6 +29,22 @@ def oracle_run(g, tol, tol_mode="abs_l1"):
     A, B, c, d = oracle.operator(g.n, g.follower, g.leader, g.lam, g.mu)
     r = oracle.power_psi(A, B, c, d, tol, tol_mode=tol_mode)
     return A, B, c, d, r
+
+
+def assert_psi(ref, got, bar, elem_bar):
+    """ψ (or s) against the oracle: relative L1 ≤ bar and the largest
+    element-wise relative error ≤ elem_bar; returns the latter."""
+    got = got if isinstance(got, np.ndarray) else got.cpu().numpy()
+    assert oracle.rel_l1(ref, got) <= bar
+    mr = oracle.max_rel(ref, got)
+    print(f"max element-wise relative error {mr:.2e}")
+    assert mr <= elem_bar, mr
+    return mr
+
+
+def elem_bar_fp64(info, r):
+    """1e-9 when both stopped at the same step, else 1e-6."""
+    return 1e-9 if info["iterations"] == r["iterations"] else 1e-6
 
 
 def gpu_op(api, g, flags=0):
@@ -213,7 +233,8 @@ def test_segmented_solve(gpu_lib, prec, tol, bar, segs, form):
     psi, info = op.solve(tol=tol, precision=prec, col_segments=segs, seg_form=form)
     assert info["status"] == 0, info
     assert info["seg_form"] == (0 if segs == 1 else api.SEG_FORMS[form])
-    assert oracle.rel_l1(r["psi"], psi.cpu().numpy()) <= bar
+    elem = {"fp64": elem_bar_fp64(info, r), "mixed": 1e-6, "fp32": 1e-4}[prec]
+    assert_psi(r["psi"], psi, bar, elem)
 
 
 def _graph_with_rows(n, rows, m_background, seed):
@@ -319,8 +340,8 @@ def test_solve_fp64_matches_oracle(gpu_lib, name, make, tol):
     psi = psi.cpu().numpy()
     assert info["status"] == 0, info
     assert abs(info["iterations"] - r["iterations"]) <= 1
-    assert oracle.rel_l1(r["psi"], psi) <= 1e-9
-    assert oracle.rel_l1(r["s"], s.cpu().numpy()) <= 1e-9
+    assert_psi(r["psi"], psi, 1e-9, elem_bar_fp64(info, r))
+    assert_psi(r["s"], s, 1e-9, elem_bar_fp64(info, r))
     s_np = s.cpu().numpy()
     # the CPU's own evaluation of the residual rounds at about eps·Σ|s|
     assert oracle.fixed_point_residual(A, c, s_np) <= tol * 1.5 + 1e-15 * np.abs(s_np).sum()
@@ -405,7 +426,7 @@ def test_weighted_form(gpu_lib):
     op = gpu_op(api, g, flags=api.PSI_WEIGHTED_FP64)
     psi, info = op.solve(tol=1e-9, precision="fp64_weighted")
     assert info["status"] == 0
-    assert oracle.rel_l1(r["psi"], psi.cpu().numpy()) <= 1e-9
+    assert_psi(r["psi"], psi, 1e-9, elem_bar_fp64(info, r))
 
 
 def test_mixed_and_fp32(gpu_lib):
@@ -416,12 +437,11 @@ def test_mixed_and_fp32(gpu_lib):
     psi_m, s_m, info_m = op.solve(tol=1e-8, precision="mixed", return_s=True)
     assert info_m["status"] == 0, info_m
     assert info_m["fp32_passes"] > 0 and info_m["refinements"] >= 1
-    assert oracle.rel_l1(r["psi"], psi_m.cpu().numpy()) <= 1e-9
+    assert_psi(r["psi"], psi_m, 1e-9, 1e-6)
     s_np = s_m.cpu().numpy()
     assert oracle.fixed_point_residual(A, c, s_np) <= 1.5e-8 + 1e-15 * np.abs(s_np).sum()
     psi_f, info_f = op.solve(tol=1e-4, precision="fp32")
-    err = oracle.rel_l1(r["psi"], psi_f.cpu().numpy())
-    assert err <= 1e-6, err
+    assert_psi(r["psi"], psi_f, 1e-6, 1e-4)
 
 
 def test_edge_cases(gpu_lib):
@@ -516,7 +536,7 @@ def test_full_size_1m(gpu_lib, prec):
     psi, s, info = op.solve(tol=1e-8, precision=prec, return_s=True)
     assert info["status"] == 0, info
     assert info["col_segments"] == tuned["col_segments"], (info, tuned)
-    assert oracle.rel_l1(r["psi"], psi.cpu().numpy()) <= 1e-9
+    assert_psi(r["psi"], psi, 1e-9, elem_bar_fp64(info, r) if prec == "fp64" else 1e-6)
     assert oracle.rel_l2(r["psi"], psi.cpu().numpy()) <= 1e-9
     s_np = s.cpu().numpy()
     assert oracle.fixed_point_residual(A, c, s_np) <= 1.5e-8 + 1e-15 * np.abs(s_np).sum()
