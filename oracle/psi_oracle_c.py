@@ -116,6 +116,12 @@ class Graph:
         lib().po_rows(self._h, _ptr(row), _ptr(fol))
         return row, fol
 
+    def row_lengths(self):
+        """Followers of each user (leader-major row lengths), int64 [n]."""
+        row = np.empty(self.n + 1, dtype=np.int64)
+        lib().po_rows(self._h, _ptr(row), None)
+        return np.diff(row)
+
     def b_norm(self) -> float:
         return float(lib().po_row_sum_max(self._h, 0))
 

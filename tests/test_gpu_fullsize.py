@@ -78,26 +78,40 @@ def host_oracle(n, f, l, lam, mu, gpu_stats):
 
 
 def check_against_oracle(G, name, s, psi, tol):
-    """Residual at every user and ψ from the same s at every user."""
+    """Residual at every user and ψ from the same s at every user.
+
+    In exact arithmetic r(s_t) = Aᵀ(s_t − s_{t−1}), so |r_i| ≤ ‖s_t − s_{t−1}‖₁
+    ≤ tol (every a_ji ≤ 1) and ‖r‖₁ ≤ κ·tol ≤ tol.  The GPU and the oracle
+    each round s_i' = c_i + μ_i Σ_{j∈F(i)} s_j/den_j in their own summation
+    order, which moves it by at most (|F(i)| + 3) units of roundoff of its
+    magnitude on each side; that is the slack allowed per user."""
     t = time.time()
     r, l1 = G.residual(s)
     c, _, _ = G.vectors()
-    # both sides round each s_i' = c_i + μ_i y_i to within a few ulps, in
-    # different summation orders: allow 8 units of roundoff of s_i and s_i'
-    slack = 8 * U * (2 * s + c)
-    assert np.all(np.abs(r) <= tol + slack), int(np.argmax(np.abs(r) - slack))
+    deg = G.row_lengths()
+    slack = 2 * U * (deg + 3) * (np.abs(s) + c)
+    over = np.abs(r) - (tol + slack)
+    worst = int(np.argmax(over))
+    say(f"{name}: ‖Aᵀs + c − s‖₁ = {l1:.3e} (tol {tol:.0e}, rounding slack {slack.sum():.2e}); "
+        f"max |r_i| {np.abs(r).max():.2e}; tightest user {worst}: |r| {abs(r[worst]):.2e}, "
+        f"slack {slack[worst]:.2e}, followers {deg[worst]}, s {s[worst]:.4g}")
+    assert over[worst] <= 0, (worst, r[worst], slack[worst], deg[worst], s[worst])
     assert l1 <= tol + slack.sum(), (l1, tol, slack.sum())
     psi_o = G.final(s)
     mr = oracle.max_rel(psi_o, psi)
-    say(f"{name}: ‖Aᵀs + c − s‖₁ = {l1:.3e} (tol {tol:.0e}, rounding slack "
-        f"{slack.sum():.2e}), max |r_i| {np.abs(r).max():.2e}; ψ(s) max rel err {mr:.2e} "
-        f"({time.time() - t:.1f} s)")
+    say(f"{name}: ψ(s) max rel err {mr:.2e} ({time.time() - t:.1f} s)")
     assert mr <= 1e-12
     return l1
 
 
-def check_full_solve(G, ref, runs, tol):
-    """The oracle's Algorithm 2 against every GPU result, user by user."""
+def check_full_solve(G, ref, runs, tol, residuals=None):
+    """The oracle's Algorithm 2 against every GPU result, user by user.  At
+    these sizes ‖s‖₁ ≈ N, so the L1 residual of any FP64 iterate near the
+    fixed point is at the level of its rounding (tens of ulps summed over
+    10⁷–10⁸ users), which can exceed tol; the GPU's residual must then be no
+    worse than twice that of the oracle's own result."""
+    _, l1_ref = G.residual(ref["s"])
+    say(f"oracle's own result: ‖Aᵀs + c − s‖₁ = {l1_ref:.3e}")
     for name, psi, s, info, elem in runs:
         e1 = oracle.rel_l1(ref["psi"], psi)
         mr = oracle.max_rel(ref["psi"], psi)
@@ -106,6 +120,8 @@ def check_full_solve(G, ref, runs, tol):
             f"{es:.2e}; iterations GPU {info['iterations']} oracle {ref['iterations']}")
         assert e1 <= 1e-9 and es <= 1e-9
         assert mr <= elem
+        if residuals and name in residuals:
+            assert residuals[name] <= max(tol, 2.0 * l1_ref), (residuals[name], l1_ref)
 
 
 @pytest.mark.timeout(1200)
@@ -132,13 +148,13 @@ def test_c5_warm_start_10m_users(gpu_lib):
     check_invariants(psi_w, s_w, g.lam, g.mu)
     G = host_oracle(g.n, f, l, g.lam, g.mu, op.stats())
     del f, l
-    check_against_oracle(G, "C5 cold", s_c, psi_c, tol)
-    check_against_oracle(G, "C5 warm", s_w, psi_w, tol)
+    res = {"C5 cold": check_against_oracle(G, "C5 cold", s_c, psi_c, tol),
+           "C5 warm": check_against_oracle(G, "C5 warm", s_w, psi_w, tol)}
     ref = oracle_solve(G, tol)
     say(f"C5: oracle Algorithm 2 {ref['iterations']} iterations in {ref['seconds']:.1f} s")
     check_full_solve(G, ref, [("C5 cold", psi_c, s_c, cold, 1e-9 if cold["iterations"] ==
                                ref["iterations"] else 1e-6),
-                              ("C5 warm", psi_w, s_w, warm, 1e-6)], tol)
+                              ("C5 warm", psi_w, s_w, warm, 1e-6)], tol, res)
 
 
 @pytest.mark.timeout(900)
@@ -236,11 +252,11 @@ def test_c3_40m_users_hub_rows(gpu_lib):
     check_invariants(psi64, s64, g.lam, g.mu)
     G = host_oracle(g.n, f, l, g.lam, g.mu, st)
     del f, l
-    check_against_oracle(G, "C3 fp64", s64, psi64, tol)
-    check_against_oracle(G, "C3 mixed", sm, psim, tol)
+    res = {"C3 fp64": check_against_oracle(G, "C3 fp64", s64, psi64, tol),
+           "C3 mixed": check_against_oracle(G, "C3 mixed", sm, psim, tol)}
     ref = oracle_solve(G, tol)
     say(f"C3: oracle Algorithm 2 {ref['iterations']} iterations in {ref['seconds']:.1f} s "
         f"({G.m * ref['iterations'] / ref['seconds'] / 1e9:.2f} G edges/s)")
     check_full_solve(G, ref, [("C3 fp64", psi64, s64, i64, 1e-9 if i64["iterations"] ==
                                ref["iterations"] else 1e-6),
-                              ("C3 mixed", psim, sm, im, 1e-6)], tol)
+                              ("C3 mixed", psim, sm, im, 1e-6)], tol, res)

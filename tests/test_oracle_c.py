@@ -77,6 +77,7 @@ def test_clean_up_counts_match_the_numpy_oracle():
     assert (g.n_self_loops, g.n_duplicates) == (loops, dups)
     assert g.m + loops + dups == gs.m_raw
     row, fol = g.rows()
+    assert np.array_equal(g.row_lengths(), np.diff(row))
     ff, ll, _, _ = oracle.clean_edges(gs.n, gs.follower, gs.leader)
     order = np.lexsort((ff, ll))  # by leader, then follower
     assert np.array_equal(np.repeat(np.arange(gs.n), np.diff(row)), ll[order])
