@@ -42,7 +42,7 @@ typedef enum psi_status {
     PSI_ENOTCONV = 2,    /* max_iter reached before the gap fell to tol       */
     PSI_ESTAGNATED = 3,  /* the gap stopped decreasing above tol              */
     PSI_ENUMERIC = 4,    /* NaN or Inf in the iteration                        */
-    PSI_EDEVICE = 5,     /* a HIP runtime call failed                          */
+    PSI_EDEVICE = 5,     /* a HIP runtime call failed or a bounded wait gave up */
     PSI_ENOSPACE = 6     /* a workspace is smaller than the size query said    */
 } psi_status;
 
@@ -288,51 +288,8 @@ psi_status psi_solve_origins(psi_operator* op, const psi_params* prm, int32_t n_
                              psi_info* infos, void* workspace, size_t workspace_bytes,
                              void* stream);
 
-/* ---- operator pass kinds (for timing and tuning) -------------------------- */
-#define PSI_PASS_STEP64     0  /* FP64 factored step: s' = c + μ⊙Σ_{j∈F(i)} s_j/den_j */
-#define PSI_PASS_STEP64_W   1  /* FP64 weighted step: s' = c + Σ_j a_ji s_j           */
-#define PSI_PASS_FINAL64    2  /* ψ = (λ⊙Σ_{j∈F(i)} s_j/den_j + d)/N                 */
-#define PSI_PASS_STEP32     3  /* FP32 correction step: e' = r + μ⊙Σ e_j/den_j        */
-#define PSI_PASS_PART64     4  /* only the per-segment partial kernel of STEP64       */
-#define PSI_PASS_PART32     5  /* only the per-segment partial kernel of STEP32       */
-
-/* Time `reps` back-to-back launches of one operator pass (the kernels a solve
- * runs in its loop: with col_segments > 1 the partial pass and the combine),
- * between two hipEvents recorded on `stream`, after one untimed launch.  Writes the mean duration of one launch in milliseconds to
- * *mean_ms (host).  tile_items, col_segments and seg_form as in psi_params.
- * Overwrites the operator's solve state.  Blocks until done. */
-psi_status psi_pass_time(psi_operator* op, int32_t pass_kind, int32_t reps, int32_t tile_items,
-                         int32_t col_segments, int32_t seg_form, double* mean_ms,
-                         void* stream);
-
-/* Random-gather probe: the access pattern of an operator pass without its
- * arithmetic, for the ceiling the pass is held to.  Workgroup b of `grid`
- * (a multiple of 8) streams its share of idx (device int32 [n_idx]) and
- * sums x[s·(n_x/S) + idx[k]] with s = (b mod 8) mod S — the column segment
- * its XCD group gathers from in a segmented pass (workgroups go to the 8
- * XCDs round-robin) — writing one sum per workgroup to out (device FP64
- * [grid]).  Indices are clamped into the segment.  x: device FP64 [n_x].
- * Times `reps` launches with hipEvents on `stream` after one untimed
- * launch; *mean_ms (host) is the mean.  Blocks. */
-psi_status psi_gather_probe(const double* x, int64_t n_x, int32_t col_segments,
-                            const int32_t* idx, int64_t n_idx, double* out, int32_t grid,
-                            int32_t reps, double* mean_ms, void* stream);
-
-/* Schedule autotuner.  Times `reps` back-to-back launches of the pass that
- * dominates a solve in `precision` (the FP64 step, the FP64 weighted step, or
- * the FP32 correction step for PSI_PREC_MIXED / PSI_PREC_FP32; with the
- * combine kernel when col_segments > 1) for every supported tile_items
- * (1024, 1536, 2048, 3072, 4096) and col_segments (1, 2, 4, 8; 1 only for
- * the weighted form), and for col_segments > 1 in both partial-pass forms
- * (the sliced form once, it has no tiles), with hipEvents on `stream`, and
- * keeps the fastest in the operator: later psi_solve calls in that precision
- * whose psi_params leave tile_items / col_segments / seg_form at 0 use it.  reps = 0 picks about 20 ms
- * of passes per candidate (at least 3).  Writes the choice and its mean pass
- * time (ms) to the host pointers, each of which may be NULL.  Overwrites the
- * operator's solve state; blocks.  Single-graph operators only. */
-psi_status psi_autotune(psi_operator* op, int32_t precision, int32_t reps, int32_t* tile_items,
-                        int32_t* col_segments, int32_t* seg_form, double* best_ms,
-                        void* stream);
+/* Schedule tuning, pass timing and the random-gather probe are declared in
+ * psi_tools.h. */
 
 /* ---- learned warm start ---------------------------------------------------
  * An extension of the method (the paper has none): a small message-passing

@@ -71,6 +71,7 @@ SIGNATURES = [
     ("psi_solve", i32, [vp, ctypes.POINTER(Params), vp, vp, vp, ctypes.POINTER(Info), vp]),
     ("psi_step", i32, [vp, i32, vp, vp, vp, i32, i32, i32, vp]),
     ("psi_final", i32, [vp, vp, vp, vp]),
+    ("psi_debug_force_slot_timeout", i32, [vp, i32]),
     ("psi_pass_time", i32, [vp, i32, i32, i32, i32, i32, ctypes.POINTER(f64), vp]),
     ("psi_batched_workspace_size", i32, [vp, i32, i32, ctypes.POINTER(sz)]),
     ("psi_solve_batched", i32, [vp, ctypes.POINTER(Params), i32, vp, vp, vp, ctypes.POINTER(Info),

@@ -183,6 +183,11 @@ class Operator:
             out[name] = self.workspace[off:off + nbytes].view(dt)
         return out
 
+    def debug_force_slot_timeout(self, on: bool) -> None:
+        """psi_debug_force_slot_timeout: make every bounded wait of this
+        operator's passes give up at once (tests of the recovery path)."""
+        _check(self._lib.psi_debug_force_slot_timeout(self._h, 1 if on else 0))
+
     # ------------------------------------------------------------------ compute
     def solve(self, tol: float = 1e-8, tol_mode: str = "abs_l1", max_iter: int = 10000,
               precision: str = "fp64", s0: torch.Tensor | None = None, check_every: int = 0,

@@ -422,10 +422,7 @@ psi_status solve_anderson(psi_operator* op, const psi_params* prm, int depth, co
     enq += cnt;
     PSI_HIP_CHECK(hipMemcpyAsync(h, op->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
     PSI_HIP_CHECK(hipStreamSynchronize(st));
-    if (h->err_flags & kErrSlotTimeout) {  // never expected: a bounded wait gave up
-      set_error("a cross-workgroup partial did not arrive in time; the pass is invalid");
-      return PSI_EDEVICE;
-    }
+    if (h->err_flags & kErrSlotTimeout) return check_waits(op, st);
     if (h->done) {
       status = h->status;
       break;
@@ -460,6 +457,8 @@ psi_status solve_anderson(psi_operator* op, const psi_params* prm, int depth, co
   PSI_HIP_CHECK(hipEventSynchronize(ev1));
   float ms = 0.f;
   PSI_HIP_CHECK(hipEventElapsedTime(&ms, ev0, ev1));
+  s = check_waits(op, st);
+  if (s != PSI_OK) return s;
   psi_info inf{};
   inf.status = status;
   inf.iterations = h->iter;

@@ -5,6 +5,7 @@
 #include <new>
 
 #include "psi_internal.h"
+#include "psi_tools.h"
 
 namespace psi {
 
@@ -212,6 +213,19 @@ psi_status psi_final(psi_operator* op, const double* s, double* psi_out, void* s
   psi_status st = psi::check_device(op);
   if (st != PSI_OK) return st;
   return psi::final_psi(op, s, psi_out, static_cast<hipStream_t>(stream));
+  PSI_GUARD_END
+}
+
+psi_status psi_debug_force_slot_timeout(psi_operator* op, int32_t on) {
+  PSI_GUARD_BEGIN
+  PSI_REQUIRE(op, "operator must not be NULL");
+  PSI_REQUIRE(on == 0 || on == 1, "on must be 0 or 1");
+  psi_status s = psi::check_device(op);
+  if (s != PSI_OK) return s;
+  const int v = on;
+  for (int k = 0; k < 2; ++k)
+    PSI_HIP_CHECK(hipMemcpy(&op->ctrl[k].force_timeout, &v, sizeof(v), hipMemcpyHostToDevice));
+  return PSI_OK;
   PSI_GUARD_END
 }
 

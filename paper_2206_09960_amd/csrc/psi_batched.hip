@@ -758,10 +758,7 @@ __global__ __launch_bounds__(kGraphGapBlock) void k_graph_gap(const int64_t* gra
     const unsigned n_done = (t >> 16) + static_cast<unsigned>(done);
     ctrl->ticket = 0;
     ctrl->iter += 1;
-    if (n_done == static_cast<unsigned>(n_graphs)) {
-      ctrl->done_pass = -1;
-      ctrl->done = 1;
-    }
+    if (n_done == static_cast<unsigned>(n_graphs)) publish_done(ctrl, -1);
   }
 }
 
@@ -781,7 +778,12 @@ __global__ void k_graph_init(const double* c, const double* invden, int64_t n, i
     ggap[i] = 0.0;
   }
   if (i == 0) {
+    // a pending wait time-out and the host's test switch survive the reset
+    const unsigned err = ctrl->err_flags;
+    const int force = ctrl->force_timeout;
     *ctrl = Ctrl{};
+    ctrl->err_flags = err;
+    ctrl->force_timeout = force;
     ctrl->tol = tol;
     ctrl->max_iter = max_iter;
     ctrl->bnorm = 1.0;
@@ -1188,10 +1190,7 @@ psi_status solve_graphs(psi_operator* op, const psi_params* prm, double* psi_out
     enq += cnt;
     PSI_HIP_CHECK(hipMemcpyAsync(h, op->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
     PSI_HIP_CHECK(hipStreamSynchronize(st));
-    if (h->err_flags & kErrSlotTimeout) {
-      set_error("a cross-tile slot was not filled in time");
-      return PSI_EDEVICE;
-    }
+    if (h->err_flags & kErrSlotTimeout) return check_waits(op, st);
     if (h->done || enq >= prm->max_iter) break;
     if (prm->check_every == 0) chunk = std::min(2 * chunk, 64);
   }
@@ -1216,6 +1215,8 @@ psi_status solve_graphs(psi_operator* op, const psi_params* prm, double* psi_out
   PSI_HIP_CHECK(hipEventSynchronize(ev1));
   float ms = 0.f;
   PSI_HIP_CHECK(hipEventElapsedTime(&ms, ev0, ev1));
+  s = check_waits(op, st);
+  if (s != PSI_OK) return s;
   int worst = PSI_OK;
   for (int g = 0; g < G; ++g) {
     const int stg = dn[g] ? stv[g] : PSI_ENOTCONV;

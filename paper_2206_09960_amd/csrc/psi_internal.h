@@ -3,11 +3,13 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cstddef>
 #include <cstdint>
 #include <string>
 #include <vector>
 
 #include "psi.h"
+#include "psi_tools.h"
 
 namespace psi {
 
@@ -78,10 +80,16 @@ struct MpHubs {
 
 // Device-side control block of one operator (one solve at a time).
 struct Ctrl {
-  unsigned int ticket;    // tiles finished in the current pass
+  // done and done_pass share one aligned 64-bit word, published together by
+  // a single atomic store (publish_done) and read together (pass_cancelled), so
+  // no reader sees done = 1 beside a stale done_pass
   int done;               // 1 once the gap met tol, max_iter hit or NaN seen
+  int done_pass;          // pass whose workgroup 0 set done (-1: a kernel's tail or a
+                          // separate decision); passes up to it still run in full
+  unsigned int ticket;    // tiles finished in the current pass
   int iter;               // steps performed in the current solve
   int status;             // psi_status decided on the device
+  unsigned int pending;   // gap pairs a deferred pass left for the next kernel to decide
   double gap;             // last gap in tol_mode units
   double l1;              // last ‖Δ‖₁
   double snorm;           // last ‖s_new‖₁
@@ -89,10 +97,9 @@ struct Ctrl {
   int tol_mode;
   int max_iter;
   double bnorm;
-  unsigned int err_flags;           // build validation
-  unsigned int pending;   // gap pairs a deferred pass left for the next kernel to decide
-  int done_pass;          // pass whose workgroup 0 set done (-1: a kernel's tail or a
-                          // separate decision); passes up to it still run in full
+  unsigned int err_flags;           // build validation and wait time-outs
+  int force_timeout;      // set by the host (psi_debug_force_slot_timeout): every bounded
+                          // wait gives up at once, to test the recovery path
   unsigned long long bnorm_bits;    // max over rows (bit pattern of a non-negative double)
   unsigned long long kappa_bits;
   unsigned long long n_self_loops;
@@ -100,6 +107,8 @@ struct Ctrl {
   unsigned long long n_no_leaders;
   unsigned long long max_row;
 };
+static_assert(offsetof(Ctrl, done) == 0 && offsetof(Ctrl, done_pass) == 4,
+              "done and done_pass form the first 64-bit word of Ctrl");
 
 // Arguments of one merge-path operator pass.  The pass gathers x over the
 // follower lists of CSR(Aᵀ) and applies a per-row epilogue.
@@ -259,6 +268,28 @@ __device__ inline void block_sum2(double& a, double& b, double* sh) {
   __syncthreads();
 }
 
+// done = 1 and done_pass in one relaxed agent-scope store of their shared
+// word: every workgroup sees both or neither.
+__device__ inline void publish_done(Ctrl* c, int done_pass) {
+  const unsigned long long w = 1ull | (static_cast<unsigned long long>(
+                                           static_cast<unsigned>(done_pass)) << 32);
+  __hip_atomic_store(reinterpret_cast<unsigned long long*>(&c->done), w, __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// A pass of a solve loop that may stop at once: the device decided
+// termination on an earlier pass (done_pass < pass_id), or, for the later
+// kernels of a pass (inclusive), on this pass's own first kernel.  done and
+// done_pass are read as one word.
+__device__ inline bool pass_cancelled(const Ctrl* c, int pass_id, bool inclusive) {
+  const unsigned long long w = __hip_atomic_load(
+      reinterpret_cast<const unsigned long long*>(&c->done), __ATOMIC_RELAXED,
+      __HIP_MEMORY_SCOPE_AGENT);
+  if (!(w & 0xffffffffull)) return false;
+  const int dp = static_cast<int>(static_cast<unsigned>(w >> 32));
+  return inclusive ? dp <= pass_id : dp < pass_id;
+}
+
 // The termination decision on the reduced gap (thread 0): the iteration
 // count, the gap in tol_mode units, its history, and done/status.
 __device__ inline void decide_gap(Ctrl* c, double G, double S, double* hist, double* gap_out,
@@ -280,8 +311,7 @@ __device__ inline void decide_gap(Ctrl* c, double G, double S, double* hist, dou
   else if (it >= c->max_iter) st = PSI_ENOTCONV;
   if (st >= 0) {
     c->status = st;
-    c->done_pass = done_pass;
-    c->done = 1;
+    publish_done(c, done_pass);
   }
 }
 
@@ -427,6 +457,13 @@ psi_status launch_part_seg(psi_operator* op, PassMode mode, const PassArgs& a, h
 psi_status launch_gap_decide(Ctrl* ctrl, double* pairs, double* hist, int count_iter,
                              hipStream_t stream);
 PassArgs base_args(psi_operator* op);
+
+// Reads the wait-timeout bit of both control blocks (blocks the host).  When a
+// bounded wait gave up, every cross-workgroup slot, ticket and gap slot is
+// emptied again (a partial that arrived after its reader gave up would
+// otherwise be read by a later pass), the bit is cleared, and PSI_EDEVICE is
+// returned; otherwise PSI_OK.
+psi_status check_waits(psi_operator* op, hipStream_t st);
 
 psi_status solve(psi_operator* op, const psi_params* prm, const double* s0, double* psi_out,
                  double* s_out, psi_info* info, hipStream_t stream);

@@ -58,7 +58,8 @@ namespace {
 __device__ inline double take_slot(double* p, Ctrl* ctrl) {
   unsigned long long* q = reinterpret_cast<unsigned long long*>(p);
   unsigned long long v = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  for (int spin = 0; v == kEmptySlot && spin < (1 << 22); ++spin) {
+  if (ctrl->force_timeout) v = kEmptySlot;  // host-forced give-up (recovery test)
+  for (int spin = 0; v == kEmptySlot && spin < (1 << 22) && !ctrl->force_timeout; ++spin) {
     __builtin_amdgcn_s_sleep(1);
     v = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
@@ -413,7 +414,9 @@ __device__ void run_tiles(const PassArgs& a, const TileSrc& src, int first, int 
           if (lane < pnq) {
             unsigned long long* q =
                 reinterpret_cast<unsigned long long*>(&src.part_open[pbs + lane]);
-            for (int spin = 0; pslot == kEmptySlot && spin < (1 << 22); ++spin) {
+            if (a.ctrl->force_timeout) pslot = kEmptySlot;  // host-forced give-up
+            for (int spin = 0; pslot == kEmptySlot && spin < (1 << 22) && !a.ctrl->force_timeout;
+                 ++spin) {
               __builtin_amdgcn_s_sleep(1);
               pslot = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
@@ -461,7 +464,10 @@ __device__ inline void take_pairs(double* base, int count, Ctrl* ctrl, double& G
     unsigned long long* q0 = reinterpret_cast<unsigned long long*>(base + 2 * lane);
     unsigned long long v0 = __hip_atomic_load(q0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     unsigned long long v1 = __hip_atomic_load(q0 + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    for (int spin = 0; (v0 == kEmptySlot || v1 == kEmptySlot) && spin < (1 << 22); ++spin) {
+    if (ctrl->force_timeout) v0 = kEmptySlot;  // host-forced give-up (recovery test)
+    for (int spin = 0; (v0 == kEmptySlot || v1 == kEmptySlot) && spin < (1 << 22) &&
+                       !ctrl->force_timeout;
+         ++spin) {
       __builtin_amdgcn_s_sleep(1);
       v0 = __hip_atomic_load(q0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       v1 = __hip_atomic_load(q0 + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -544,7 +550,7 @@ __global__ __launch_bounds__(kBlock) void k_pass(PassArgs a) {
     take_deferred(a.ctrl, a.gap_prev, a.hist, a.count_iter, a.pass_id, L.red);
   // a decision of this very pass (by workgroup 0) does not stop it: every
   // workgroup must run, or cross-tile slots would be left half filled
-  if (a.respect_done && a.ctrl->done && a.ctrl->done_pass < a.pass_id) return;
+  if (a.respect_done && pass_cancelled(a.ctrl, a.pass_id, false)) return;
   TileSrc src{a.row_ptr, a.col, a.tile_row, a.part_open, nullptr, a.n_nnz, a.n_tiles};
   double g = 0.0, sn = 0.0;
   run_tiles<IPT, MODE>(a, src, blockIdx.x, gridDim.x, L, g, sn);
@@ -558,7 +564,7 @@ __global__ __launch_bounds__(kBlock) void k_pass_seg(PassArgs a, SegArgs sg) {
   __shared__ TileLds<IPT> L;
   if (a.defer_gap && blockIdx.x == 0)
     take_deferred(a.ctrl, a.gap_prev, a.hist, a.count_iter, a.pass_id, L.red);
-  if (a.respect_done && a.ctrl->done && a.ctrl->done_pass < a.pass_id) return;
+  if (a.respect_done && pass_cancelled(a.ctrl, a.pass_id, false)) return;
   const int xcd = blockIdx.x & 7;
   const int group = xcd % sg.S;
   const int per_round = 8 / sg.S;  // workgroups of a group among 8 consecutive ones
@@ -578,7 +584,7 @@ __global__ __launch_bounds__(kBlock) void k_slices(SliceArgs a) {
   __shared__ double red[8];
   if (a.defer_gap && blockIdx.x == 0)
     take_deferred(a.ctrl, a.gap_prev, a.hist, a.count_iter, a.pass_id, red);
-  if (a.respect_done && a.ctrl->done && a.ctrl->done_pass < a.pass_id) return;
+  if (a.respect_done && pass_cancelled(a.ctrl, a.pass_id, false)) return;
   using XT = typename std::conditional<MODE == kPart32, float, double>::type;
   const int xcd = blockIdx.x & 7;
   const int group = xcd % a.S;
@@ -684,7 +690,7 @@ __global__ __launch_bounds__(kBlock) void k_combine(PassArgs a, SegArgs sg) {
   __shared__ double red[8];
   __shared__ int last;
   // the combine follows its own pass's partial kernel, whose decision it sees
-  if (a.respect_done && a.ctrl->done && a.ctrl->done_pass <= a.pass_id) return;
+  if (a.respect_done && pass_cancelled(a.ctrl, a.pass_id, true)) return;
   double g = 0.0, sn = 0.0;
   const YT* y0 = static_cast<const YT*>(sg.seg[0].y);
   const YT* y1 = static_cast<const YT*>(sg.seg[1].y);

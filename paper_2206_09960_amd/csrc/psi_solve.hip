@@ -108,6 +108,26 @@ __global__ void k_make_z(const double* s, const double* invden, int64_t n, doubl
   if (i < n) z[i] = invden[i] * s[i];
 }
 
+__global__ void k_fill_slots(unsigned long long* p, int64_t n, unsigned long long v) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void k_fill_u32(unsigned* p, int64_t n) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x)
+    p[i] = 0u;
+}
+
+__global__ void k_ctrl_clear_wait(Ctrl* c) {
+  for (int k = 0; k < 2; ++k) {
+    c[k].ticket = 0;
+    c[k].pending = 0;
+    c[k].err_flags &= ~static_cast<unsigned>(kErrSlotTimeout);
+  }
+}
+
 struct IterResult {
   int iters = 0;       // passes that ran on the device (ctrl->iter)
   int status = PSI_OK;
@@ -177,10 +197,7 @@ psi_status iterate(psi_operator* op, int S, int ctrl_idx, PassMode mode, Make ma
     }
     PSI_HIP_CHECK(hipMemcpyAsync(hctrl, dctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
     PSI_HIP_CHECK(hipStreamSynchronize(st));
-    if (hctrl->err_flags & kErrSlotTimeout) {  // never expected: a bounded wait gave up
-      set_error("a cross-workgroup partial did not arrive in time; the pass is invalid");
-      return PSI_EDEVICE;
-    }
+    if (hctrl->err_flags & kErrSlotTimeout) return check_waits(op, st);  // never expected
     out->iters = hctrl->iter;
     out->gap = hctrl->gap;
     out->l1 = hctrl->l1;
@@ -215,6 +232,38 @@ psi_status iterate(psi_operator* op, int S, int ctrl_idx, PassMode mode, Make ma
 }
 
 }  // namespace
+
+psi_status check_waits(psi_operator* op, hipStream_t st) {
+  Ctrl* h = op->host_ctrl;
+  PSI_HIP_CHECK(hipMemcpyAsync(h, op->ctrl, 2 * sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+  PSI_HIP_CHECK(hipStreamSynchronize(st));
+  if (!((h[0].err_flags | h[1].err_flags) & kErrSlotTimeout)) return PSI_OK;
+  // a partial that arrives after its reader gave up must not be read by a
+  // later pass: empty every slot and ticket again
+  auto fill = [&](void* p, int64_t cnt) {
+    if (p && cnt > 0)
+      hipLaunchKernelGGL(k_fill_slots, dim3(unsigned(std::min<int64_t>(1024, (cnt + 255) / 256))),
+                         dim3(256), 0, st, static_cast<unsigned long long*>(p), cnt, kEmptySlot);
+  };
+  auto zero = [&](unsigned* p, int64_t cnt) {
+    if (p && cnt > 0)
+      hipLaunchKernelGGL(k_fill_u32, dim3(unsigned(std::min<int64_t>(1024, (cnt + 255) / 256))),
+                         dim3(256), 0, st, p, cnt);
+  };
+  fill(op->part_open, op->max_tiles);
+  fill(op->seg_part_open, op->max_seg_tiles);
+  fill(op->slice_part, op->cap_chunks);
+  zero(op->slice_ticket, op->cap_chunks);
+  fill(op->gap_part, 4 * int64_t(kMaxGrid));
+  fill(op->gap_grp, 2 * int64_t(kMaxGrid / 64));
+  zero(op->grp_ticket, kMaxGrid / 64);
+  hipLaunchKernelGGL(k_ctrl_clear_wait, dim3(1), dim3(1), 0, st, op->ctrl);
+  PSI_HIP_CHECK(hipGetLastError());
+  PSI_HIP_CHECK(hipStreamSynchronize(st));
+  set_error("a bounded wait for a partial of another workgroup gave up: the result of this "
+            "call is invalid (the operator's slots were emptied, later calls are unaffected)");
+  return PSI_EDEVICE;
+}
 
 // Partial-pass form for S segments: the requested one, else the tuned one
 // (when it was tuned for this S), else sliced while a segment's share of the
@@ -322,7 +371,8 @@ psi_status solve(psi_operator* op, const psi_params* prm, const double* s0, doub
       inf.spmv_passes += 1;
       double rc = 0.0;
       PSI_HIP_CHECK(hipMemcpyAsync(&rc, op->scal, sizeof(rc), hipMemcpyDeviceToHost, st));
-      PSI_HIP_CHECK(hipStreamSynchronize(st));
+      s = check_waits(op, st);
+      if (s != PSI_OK) return s;
       op->rc_l1 = rc;
     }
     const bool first_iter = prm->precision == PSI_PREC_FP64;
@@ -344,7 +394,8 @@ psi_status solve(psi_operator* op, const psi_params* prm, const double* s0, doub
     if (s != PSI_OK) return s;
     double r1 = 0.0;
     PSI_HIP_CHECK(hipMemcpyAsync(&r1, op->scal + 1, sizeof(r1), hipMemcpyDeviceToHost, st));
-    PSI_HIP_CHECK(hipStreamSynchronize(st));
+    s = check_waits(op, st);
+    if (s != PSI_OK) return s;
     if (!(r1 <= op->rc_l1)) {  // c wins: the step from s0 is discarded
       s0 = nullptr;
       inf.used_s0 = 0;
@@ -466,8 +517,8 @@ psi_status solve(psi_operator* op, const psi_params* prm, const double* s0, doub
       if (s != PSI_OK) return s;
       ++fp64_passes;
       Ctrl* h = op->host_ctrl;
-      PSI_HIP_CHECK(hipMemcpyAsync(h, op->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
-      PSI_HIP_CHECK(hipStreamSynchronize(st));
+      s = check_waits(op, st);  // copies both control blocks to the host
+      if (s != PSI_OK) return s;
       inf.final_gap = h->gap;
       last_l1 = h->l1;
       s_fin = Y;
@@ -548,6 +599,8 @@ psi_status solve(psi_operator* op, const psi_params* prm, const double* s0, doub
   PSI_HIP_CHECK(hipEventSynchronize(tm.b));
   float ms = 0.f;
   PSI_HIP_CHECK(hipEventElapsedTime(&ms, tm.a, tm.b));
+  s = check_waits(op, st);  // the final pass, like every pass, must have had all its partials
+  if (s != PSI_OK) return s;
   inf.device_ms = ms;
   inf.final_l1_step = last_l1;
   inf.err_bound_s = kap < 1.0 ? kap / (1.0 - kap) * last_l1 : std::numeric_limits<double>::infinity();

@@ -652,3 +652,27 @@ def test_gather_probe_runs_and_clamps(gpu_lib):
                                        1, ctypes.byref(ms), api._stream_handle(None)) == 0
     # workgroup 0 gathers segment 0 (entries 0..7): 0 + 3 + 7 + 7
     assert out[0].item() == 17.0
+
+
+@pytest.mark.parametrize("segs,form", [(1, "auto"), (4, "tiles"), (4, "slices")])
+def test_a_wait_that_gives_up_fails_the_call_and_is_recovered(gpu_lib, segs, form):
+    """The host forces every bounded wait of the passes to give up at once (no
+    wait runs long; every kernel ends normally): the solve must fail with
+    PSI_EDEVICE instead of returning a ψ built from missing partials, and the
+    next solve, with normal waits, must be exact again (the partials left in
+    their slots were emptied)."""
+    api = gpu_lib
+    g = synth.star(300001, 24)  # one 300k-follower hub: its row spans many tiles and chunks
+    A, B, c, d, r = oracle_run(g, 1e-10)
+    op = gpu_op(api, g)
+    op.debug_force_slot_timeout(True)
+    with pytest.raises(api.PsiError) as e:
+        op.solve(tol=1e-10, col_segments=segs, seg_form=form)
+    assert e.value.status == 5  # PSI_EDEVICE
+    with pytest.raises(api.PsiError):
+        op.solve(tol=1e-10, precision="mixed", col_segments=segs, seg_form=form)
+    op.debug_force_slot_timeout(False)
+    for prec in ("fp64", "mixed"):
+        psi, info = op.solve(tol=1e-10, precision=prec, col_segments=segs, seg_form=form)
+        assert info["status"] == 0, info
+        assert_psi(r["psi"], psi, 1e-9, 1e-6)
