@@ -65,19 +65,29 @@ typedef enum psi_status {
 /* ---- solve flags ---------------------------------------------------------- */
 #define PSI_NO_FALLBACK     0x1u  /* use s0 even if its residual is worse than c's */
 
-/* ---- partial pass of a column-segmented pass (col_segments > 1) ------------
- * The same sums (each row's followers in CSR order, partials added in segment
- * order, so both give the same result to rounding) over two layouts of the
- * segment:
+/* ---- layout of the passes ---------------------------------------------------
+ * Every layout computes the same sums (each row's followers added in a fixed
+ * order, so results agree to rounding and each layout is bitwise repeatable).
+ * Column-segmented passes (col_segments = S > 1) split the followers into S
+ * segments, one per group of XCDs, and add the S partial sums per row; the
+ * partial pass walks each segment in one of two layouts:
  *   TILES:  merge-path tiles of tile_items over the segment's CSR; suits a
  *           gathered vector whose segment share exceeds an XCD's L2;
  *   SLICES: one lane per row of at most 32 followers (rows ordered by length
  *           in windows of 4096, 64 to a slice), one wave per 2048-edge chunk
  *           of a longer row; suits a segment share that fits the L2.
+ * BANDS is a layout of its own (col_segments is then ignored): followers are
+ * cut into blocks of 2^17 or 2^18 users (1-2 MB of the FP64 iterate) and
+ * leaders into row blocks of at most 1024 or 2048 rows, each summed by one
+ * wave in LDS; the waves of one launch walk the follower blocks in step, so
+ * their gathers hit L2 however large the graph; rows longer than a row block
+ * are cut into pieces added in order afterwards.  It suits iterates larger
+ * than the caches.
  * 0 = the tuned form (psi_autotune), else SLICES when N·(8 or 4 bytes)/S is
  * at most 6 MB and TILES otherwise. */
 #define PSI_SEG_TILES   1
 #define PSI_SEG_SLICES  2
+#define PSI_SEG_BANDS   3
 
 typedef struct psi_operator psi_operator;
 
@@ -105,9 +115,14 @@ typedef struct psi_params {
     int32_t tile_items;  /* merge-path items per tile; 0 = library default     */
     int32_t col_segments;/* 1, 2, 4 or 8 column segments (one per XCD group);   */
                          /* 0 = chosen from N and the precision                */
-    int32_t seg_form;    /* partial pass of a segmented pass: PSI_SEG_TILES or  */
-                         /* PSI_SEG_SLICES; 0 = tuned, else from N and precision */
+    int32_t seg_form;    /* layout: PSI_SEG_TILES or PSI_SEG_SLICES (partial pass  */
+                         /* of a segmented pass), PSI_SEG_BANDS; 0 = tuned, else */
+                         /* from N and precision                                 */
     double inner_tol;    /* PSI_PREC_MIXED: relative tol of each FP32 solve; 0 = default */
+    int32_t band_col_log;/* PSI_SEG_BANDS: column blocks of 2^17 or 2^18 users;     */
+                         /* 0 = tuned, else 18                                    */
+    int32_t band_rows;   /* PSI_SEG_BANDS: rows per row block, 1024 or 2048;        */
+                         /* 0 = tuned, else 2048                                  */
 } psi_params;
 
 typedef struct psi_info {
@@ -126,7 +141,7 @@ typedef struct psi_info {
     double err_bound_s;       /* κ/(1−κ)·‖s_t − s_{t−1}‖₁ ≥ ‖s − s_t‖₁        */
     double psi_gap_bound;     /* ‖s_t − s_{t−1}‖₁·‖B‖/N ≥ ‖ψ_t − ψ_{t−1}‖₁    */
     double device_ms;         /* time from first to last kernel of the solve  */
-    int32_t seg_form;         /* PSI_SEG_* of the segmented passes, 0 if S = 1 */
+    int32_t seg_form;         /* PSI_SEG_* of the passes (0: fused, S = 1)    */
 } psi_info;
 
 /* Library version string. */

@@ -63,6 +63,15 @@ psi_status psi_autotune(psi_operator* op, int32_t precision, int32_t reps, int32
                         int32_t* col_segments, int32_t* seg_form, double* best_ms,
                         void* stream);
 
+/* The band layout built on the operator (by a call that used PSI_SEG_BANDS or
+ * by psi_autotune), for reports: column blocks of 2^col_log users (*col_blocks
+ * of them), *row_blocks row blocks of at most *rows rows, run as *bands
+ * launches per pass, *split_rows rows cut into pieces.  All zero when no band
+ * layout is built.  Any out pointer may be NULL. */
+psi_status psi_operator_band_info(const psi_operator* op, int32_t* col_log, int32_t* rows,
+                                  int32_t* col_blocks, int32_t* row_blocks, int32_t* bands,
+                                  int32_t* split_rows);
+
 /* Test hook for the recovery of a bounded wait that gives up.  The passes
  * hand partial sums between workgroups through slots that the reader waits
  * for (bounded); a wait that gives up makes the blocking call that saw it

@@ -22,7 +22,7 @@ PSI_PREC_FP64, PSI_PREC_FP64_WEIGHTED, PSI_PREC_MIXED, PSI_PREC_FP32 = 0, 1, 2, 
 # solve flags
 PSI_NO_FALLBACK = 0x1
 # partial pass of a column-segmented pass
-PSI_SEG_TILES, PSI_SEG_SLICES = 1, 2
+PSI_SEG_TILES, PSI_SEG_SLICES, PSI_SEG_BANDS = 1, 2, 3
 # pass kinds
 PSI_PASS_STEP64, PSI_PASS_STEP64_W, PSI_PASS_FINAL64, PSI_PASS_STEP32 = 0, 1, 2, 3
 PSI_PASS_PART64, PSI_PASS_PART32 = 4, 5
@@ -41,7 +41,7 @@ class Params(ctypes.Structure):
     _fields_ = [("tol", f64), ("tol_mode", i32), ("max_iter", i32), ("precision", i32),
                 ("check_every", i32), ("flags", u32), ("tile_items", i32), ("col_segments", i32),
                 ("seg_form", i32),
-                ("inner_tol", f64)]
+                ("inner_tol", f64), ("band_col_log", i32), ("band_rows", i32)]
 
 
 class Info(ctypes.Structure):
@@ -72,6 +72,7 @@ SIGNATURES = [
     ("psi_step", i32, [vp, i32, vp, vp, vp, i32, i32, i32, vp]),
     ("psi_final", i32, [vp, vp, vp, vp]),
     ("psi_debug_force_slot_timeout", i32, [vp, i32]),
+    ("psi_operator_band_info", i32, [vp] + [ctypes.POINTER(i32)] * 6),
     ("psi_pass_time", i32, [vp, i32, i32, i32, i32, i32, ctypes.POINTER(f64), vp]),
     ("psi_batched_workspace_size", i32, [vp, i32, i32, ctypes.POINTER(sz)]),
     ("psi_solve_batched", i32, [vp, ctypes.POINTER(Params), i32, vp, vp, vp, ctypes.POINTER(Info),

@@ -19,8 +19,10 @@ from ._ffi import (PSI_INPUT_HOST, PSI_NO_FALLBACK, PSI_PREC_FP32,  # noqa: F401
 PRECISIONS = {"fp64": PSI_PREC_FP64, "fp64_weighted": PSI_PREC_FP64_WEIGHTED,
               "mixed": PSI_PREC_MIXED, "fp32": PSI_PREC_FP32}
 TOL_MODES = {"abs_l1": PSI_TOL_ABS_L1, "bnorm": PSI_TOL_BNORM, "rel_l1": PSI_TOL_REL_L1}
-SEG_FORMS = {"auto": 0, "none": 0, "tiles": _ffi.PSI_SEG_TILES, "slices": _ffi.PSI_SEG_SLICES}
-SEG_FORM_NAMES = {0: "none", _ffi.PSI_SEG_TILES: "tiles", _ffi.PSI_SEG_SLICES: "slices"}
+SEG_FORMS = {"auto": 0, "none": 0, "tiles": _ffi.PSI_SEG_TILES, "slices": _ffi.PSI_SEG_SLICES,
+             "bands": _ffi.PSI_SEG_BANDS}
+SEG_FORM_NAMES = {0: "none", _ffi.PSI_SEG_TILES: "tiles", _ffi.PSI_SEG_SLICES: "slices",
+                  _ffi.PSI_SEG_BANDS: "bands"}
 
 
 def _seg_form(f) -> int:
@@ -183,6 +185,13 @@ class Operator:
             out[name] = self.workspace[off:off + nbytes].view(dt)
         return out
 
+    def band_info(self) -> dict:
+        """psi_operator_band_info: the band layout built on the operator."""
+        v = [ctypes.c_int32() for _ in range(6)]
+        _check(self._lib.psi_operator_band_info(self._h, *[ctypes.byref(x) for x in v]))
+        keys = ("col_log", "rows", "col_blocks", "row_blocks", "bands", "split_rows")
+        return {k: x.value for k, x in zip(keys, v)}
+
     def debug_force_slot_timeout(self, on: bool) -> None:
         """psi_debug_force_slot_timeout: make every bounded wait of this
         operator's passes give up at once (tests of the recovery path)."""
@@ -194,9 +203,10 @@ class Operator:
               tile_items: int = 0, col_segments: int = 0, inner_tol: float = 0.0,
               no_fallback: bool = False, seg_form: str | int = 0,
               return_s: bool = False, psi_out: torch.Tensor | None = None, stream=None,
-              raise_on_status: bool = False):
+              raise_on_status: bool = False, band_col_log: int = 0, band_rows: int = 0):
         """psi_solve: ψ (and s) by Algorithm 2; returns (psi, info) or (psi, s, info).
-        seg_form: 0 / "auto", "tiles" or "slices" (partial pass of a segmented pass)."""
+        seg_form: 0 / "auto", "tiles" or "slices" (partial pass of a segmented
+        pass), or "bands" (column-blocked layout with band_col_log, band_rows)."""
         p = _ffi.Params()
         _check(self._lib.psi_params_default(ctypes.byref(p)))
         p.tol = tol
@@ -209,6 +219,8 @@ class Operator:
         p.col_segments = col_segments
         p.seg_form = _seg_form(seg_form)
         p.inner_tol = inner_tol
+        p.band_col_log = band_col_log
+        p.band_rows = band_rows
         psi = _vec_out(psi_out, self.n, self.device, torch.float64, "psi_out")
         s = torch.empty(self.n, dtype=torch.float64, device=self.device) if return_s else None
         if s0 is not None:

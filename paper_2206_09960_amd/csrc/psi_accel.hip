@@ -361,13 +361,24 @@ psi_status solve_anderson(psi_operator* op, const psi_params* prm, int depth, co
   }
   PSI_REQUIRE(S == 1 || S == 2 || S == 4 || S == 8, "col_segments must be 0, 1, 2, 4 or 8");
   int form = 0;
-  psi_status s = resolve_form(op, prm->seg_form, prec, S, 8, &form);
+  psi_status s = resolve_form(op, prm->seg_form, prm->col_segments, prec, S, 8, &form);
   if (s != PSI_OK) return s;
-  s = prepare(op, tile, S, form, st);
+  if (form == kSegBands) S = 1;
+  {
+    int wlog = 0, rows = 0;
+    if (form == kSegBands) band_params(op, prec, &wlog, &rows);
+    if (prm->band_col_log) wlog = prm->band_col_log;
+    if (prm->band_rows) rows = prm->band_rows;
+    PSI_REQUIRE(form != kSegBands || ((wlog == 17 || wlog == 18) && (rows == 1024 || rows == 2048)),
+                "band_col_log must be 0, 17 or 18 and band_rows 0, 1024 or 2048");
+    s = prepare(op, tile, S, form, st, wlog, rows);
+    op->band_pace_ticks = form == kSegBands && op->tuned_band_wlog[prec] == wlog &&
+                                  op->tuned_band_rows[prec] == rows
+                              ? op->tuned_band_pace[prec]
+                              : 0ull;
+  }
   if (s != PSI_OK) return s;
-  auto pass = [&](PassMode mode, const PassArgs& a) {
-    return S > 1 ? launch_pass_seg(op, mode, a, st) : launch_pass(op, mode, a, st);
-  };
+  auto pass = [&](PassMode mode, const PassArgs& a) { return run_pass(op, S, mode, a, st); };
   EventPair evp;
   PSI_HIP_CHECK(hipEventCreate(&evp.a));
   PSI_HIP_CHECK(hipEventCreate(&evp.b));

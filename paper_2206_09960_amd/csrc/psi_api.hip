@@ -216,6 +216,22 @@ psi_status psi_final(psi_operator* op, const double* s, double* psi_out, void* s
   PSI_GUARD_END
 }
 
+psi_status psi_operator_band_info(const psi_operator* op, int32_t* col_log, int32_t* rows,
+                                  int32_t* col_blocks, int32_t* row_blocks, int32_t* bands,
+                                  int32_t* split_rows) {
+  PSI_GUARD_BEGIN
+  PSI_REQUIRE(op, "operator must not be NULL");
+  const bool b = op->band_built;
+  if (col_log) *col_log = b ? op->band_wlog : 0;
+  if (rows) *rows = b ? op->band_rows : 0;
+  if (col_blocks) *col_blocks = b ? op->band_B : 0;
+  if (row_blocks) *row_blocks = b ? op->band_nb : 0;
+  if (bands) *bands = b ? op->band_count : 0;
+  if (split_rows) *split_rows = b ? op->band_n_split : 0;
+  return PSI_OK;
+  PSI_GUARD_END
+}
+
 psi_status psi_debug_force_slot_timeout(psi_operator* op, int32_t on) {
   PSI_GUARD_BEGIN
   PSI_REQUIRE(op, "operator must not be NULL");

@@ -1142,7 +1142,8 @@ psi_status solve_graphs(psi_operator* op, const psi_params* prm, double* psi_out
   const int S = prm->col_segments ? prm->col_segments : (big ? 2 : 1);
   PSI_REQUIRE(S == 1 || S == 2 || S == 4 || S == 8, "col_segments must be 0, 1, 2, 4 or 8");
   int form = 0;
-  psi_status s = resolve_form(op, prm->seg_form ? prm->seg_form : (big ? kSegTiles : 0),
+  PSI_REQUIRE(prm->seg_form != PSI_SEG_BANDS, "graph batches have no band layout");
+  psi_status s = resolve_form(op, prm->seg_form ? prm->seg_form : (big ? kSegTiles : 0), S,
                               PSI_PREC_FP64, S, 8, &form);
   if (s != PSI_OK) return s;
   s = prepare(op, tile, S, form, st);

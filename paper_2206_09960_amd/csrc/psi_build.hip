@@ -852,6 +852,22 @@ static void layout_persistent(int64_t n, int64_t m_raw, int n_graphs, uint32_t f
   char* slice_part = take(8 * size_t(cap_chunks));
   char* slice_ticket = take(4 * size_t(cap_chunks));
   char* slice_plan = take(4 * size_t(segs ? 5 * (8 * nw + 1) : 0));
+  // column-blocked layout (single-graph operators).  Row blocks: at most
+  // n/R closed by their row count, 2M/E closed by their edge budget, 2M/E
+  // pieces of split rows and one per split row, where the planner keeps
+  // M/E <= n/R + waves of a launch (R >= 1024)
+  const bool bands = n_graphs == 1;
+  const int64_t band_cols =
+      bands ? std::max<int64_t>(1, (n + (int64_t(1) << kBandMinLog) - 1) >> kBandMinLog) : 0;
+  const int64_t cap_band_blocks = bands ? 6 * ((n + 1023) / 1024) + 5 * int64_t(kBandWaveCap) + 64 : 0;
+  const int64_t cap_band_toff = bands ? cap_band_blocks * band_cols + 1 : 0;
+  char* band_ent = take(4 * size_t(bands ? m_raw : 0));
+  char* band_toff = take(4 * size_t(cap_band_toff));
+  char* band_blocks = take(sizeof(BandBlock) * size_t(cap_band_blocks + 1));
+  char* band_split = take(16 * size_t(cap_band_blocks));
+  char* band_piece = take(8 * size_t(cap_band_blocks));
+  char* band_pairs = take(16 * size_t(cap_band_blocks / 4 + 1));
+  char* band_scan_tmp = take(4 * size_t((cap_band_toff + 4095) / 4096 + 8));
   const int64_t mp_max_hubs = m_raw / (kMpHubEdges + 1) + 1;
   const int64_t mp_max_chunks = m_raw / kMpChunkEdges + mp_max_hubs + 1;
   char* mp[2][3];
@@ -921,6 +937,17 @@ static void layout_persistent(int64_t n, int64_t m_raw, int n_graphs, uint32_t f
   op->cap_lanes = cap_lanes;
   op->cap_entries = cap_entries;
   op->cap_chunks = cap_chunks;
+  op->band_ent = (uint32_t*)band_ent;
+  op->band_toff = (uint32_t*)band_toff;
+  op->band_blocks = (BandBlock*)band_blocks;
+  op->band_split = (int4*)band_split;
+  op->band_piece = (double*)band_piece;
+  op->band_pairs = (double*)band_pairs;
+  op->band_scan_tmp = (uint32_t*)band_scan_tmp;
+  op->cap_band_blocks = cap_band_blocks;
+  op->cap_band_toff = cap_band_toff;
+  op->cap_band_cols = band_cols;
+  op->band_built = false;
   op->mp_max_hubs = mp_max_hubs;
   op->mp_max_chunks = mp_max_chunks;
   for (int o = 0; o < 2; ++o) {

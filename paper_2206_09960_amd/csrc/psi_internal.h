@@ -184,7 +184,53 @@ struct SegInfo {
 
 // The two forms of a segment's partial pass: merge-path tiles over the
 // segment's CSR, or one lane per row over its sliced layout.
-enum SegForm : int { kSegTiles = PSI_SEG_TILES, kSegSlices = PSI_SEG_SLICES };
+enum SegForm : int {
+  kSegTiles = PSI_SEG_TILES,
+  kSegSlices = PSI_SEG_SLICES,
+  kSegBands = PSI_SEG_BANDS,  // column-blocked layout (psi_band.hip), not a segmentation
+};
+
+// Column-blocked ("band") layout: row blocks of at most 1024 or 2048 rows, each
+// summed by one wave in LDS, over column blocks of 2^17 or 2^18 users.
+constexpr int kBandMinLog = 17;
+constexpr int kBandMaxLog = 18;
+constexpr int kBandMaxCols = 1024;     // column blocks (LDS of the layout build)
+constexpr int kBandWaveCap = 4096;     // waves of one band launch the capacities allow
+constexpr int kBandMinEdges = 2048;    // smallest edge budget of a row block
+constexpr int kBandFixGrid = 64;       // workgroups of the kernel that ends a band pass
+
+struct BandBlock {
+  int row_lo;  // first row
+  int nrows;   // rows (1 for a piece of a split row)
+  int piece;   // piece slot of a split row, -1 for whole rows
+  int e_lo;    // first edge of the block in CSR(Aᵀ) (the next block's is its end)
+};
+
+// Arguments of one band launch.
+struct BandArgs {
+  const uint32_t* ent;      // entries (row in block << wlog | column in block)
+  const uint32_t* toff;     // [n_blocks·B + 1] first entry of each (row block, column block)
+  const BandBlock* blocks;  // [n_blocks + 1]
+  double* piece;            // sums of the pieces of split rows
+  double* pairs;            // (Σ|Δ|, Σ|new|) of each workgroup of the pass's band launches
+  int B;
+  int wlog;
+  int first_block;          // first row block of this launch
+  int n_blocks;             // row blocks of the whole layout
+  int pair_base;            // first pair of this launch's workgroups
+  int first_launch;         // 1 for the first launch of a pass (it decides a deferred gap)
+  unsigned long long pace;  // wall-clock ticks between column-block starts (0 = no pacing)
+};
+
+// Arguments of the kernel that ends a band pass: the split rows, and the
+// band launches' gap pairs reduced into this kernel's own.
+struct BandFixArgs {
+  const int4* split;        // {row, first piece, end piece, 0}
+  const double* piece;
+  const double* pairs;
+  int n_split;
+  int n_pairs;
+};
 
 struct SegArgs {
   SegInfo seg[8];
@@ -422,6 +468,25 @@ struct psi_operator {
   unsigned* slice_ticket = nullptr;
   uint32_t* slice_plan = nullptr;  // per-window counts and their scans [5 * (8 * windows + 1)]
   int64_t cap_slices = 0, cap_lanes = 0, cap_entries = 0, cap_chunks = 0;
+  // column-blocked (band) layout, built on first use
+  bool band_built = false;
+  int band_wlog = 0, band_rows = 0;  // column-block width 2^wlog, rows per row block
+  int band_B = 0;                    // column blocks
+  int band_nb = 0;                   // row blocks
+  int band_waves = 0;                // row blocks (waves) per band launch
+  int band_count = 0;                // band launches per pass
+  int band_n_split = 0;              // rows cut into pieces
+  unsigned long long band_pace_ticks = 0;  // pacing of the band launches (0 = none)
+  int tuned_band_wlog[4]{}, tuned_band_rows[4]{};
+  unsigned long long tuned_band_pace[4]{};
+  uint32_t* band_ent = nullptr;      // [m]
+  uint32_t* band_toff = nullptr;     // [cap_band_toff]
+  psi::BandBlock* band_blocks = nullptr;  // [cap_band_blocks]
+  int4* band_split = nullptr;        // [cap_band_blocks]
+  double* band_piece = nullptr;      // [cap_band_blocks]
+  double* band_pairs = nullptr;      // [2 * (cap_band_blocks / 4 + 1)]
+  uint32_t* band_scan_tmp = nullptr;
+  int64_t cap_band_blocks = 0, cap_band_toff = 0, cap_band_cols = 0;
 };
 
 namespace psi {
@@ -443,11 +508,27 @@ psi_status ensure_schedule(psi_operator* op, int tile_items, hipStream_t stream)
 psi_status ensure_segments(psi_operator* op, int S, hipStream_t stream);
 psi_status ensure_seg_tiles(psi_operator* op, int tile_items, hipStream_t stream);
 psi_status ensure_seg_slices(psi_operator* op, hipStream_t stream);
-// Partial-pass form of a call (requested, tuned, or from the segment share)
-// and the schedules and layouts its passes need.
-psi_status resolve_form(const psi_operator* op, int requested, int precision, int S, int bytes,
-                        int* form);
+// The column-blocked layout for column blocks of 2^wlog users and row blocks
+// of at most `rows` rows (psi_band.hip), and the waves of one band launch.
+psi_status ensure_bands(psi_operator* op, int wlog, int rows, hipStream_t stream);
+int band_waves(int rows);
+// Layout of a call (requested, tuned, or from the gathered vector's size:
+// band layout, or the partial-pass form of S segments) and the schedules and
+// layouts its passes need; requested_S is the caller's col_segments.
+psi_status resolve_form(const psi_operator* op, int requested, int requested_S, int precision,
+                        int S, int bytes, int* form);
 psi_status prepare(psi_operator* op, int tile, int S, int form, hipStream_t stream);
+// The same with the band layout's parameters (0: those built, else defaults).
+psi_status prepare(psi_operator* op, int tile, int S, int form, hipStream_t stream, int wlog,
+                   int rows);
+// Band layout parameters a call uses: tuned ones for `precision`, else defaults.
+void band_params(const psi_operator* op, int precision, int* wlog, int* rows);
+// One pass in the band form: the band launches, then the kernel that adds the
+// pieces of split rows and ends the gap (band_only: the band launches only).
+psi_status launch_pass_bands(psi_operator* op, PassMode mode, const PassArgs& a, bool band_only,
+                             hipStream_t stream);
+// A pass in the operator's current form: bands, S column segments, or fused.
+psi_status run_pass(psi_operator* op, int S, PassMode mode, const PassArgs& a, hipStream_t stream);
 bool tile_items_supported(int t);
 psi_status launch_pass(psi_operator* op, PassMode mode, const PassArgs& a, hipStream_t stream);
 psi_status launch_pass_seg(psi_operator* op, PassMode mode, const PassArgs& a, hipStream_t stream);

@@ -730,6 +730,220 @@ __global__ __launch_bounds__(kBlock) void k_combine(PassArgs a, SegArgs sg) {
   if constexpr (MODE == kStep64 || MODE == kStep32) finalize_gap(a, g, sn, red, &last);
 }
 
+// ---------------------------------------------------------------- band form
+// One wave per row block (see psi_band.hip): its rows' sums in LDS, its
+// entries walked column block by column block in chunks of 64 (a chunk never
+// spans two column blocks, so its rows are distinct runs in row order).  A
+// chunk's runs are summed by a segmented scan across the wave (a fixed
+// tree); the last lane of each run adds the run to its row's sum.
+//
+// A workgroup holds four row blocks (four waves); each wave walks the column
+// blocks on its own, loading the next column block's entries while it sums
+// the current one.  Waves that start a launch together gather from the same
+// column blocks, but drift apart over hundreds of them; an optional pacing
+// (a start time per column block) keeps them together.
+constexpr int kBandUnroll = 4;  // chunks in flight per wave
+
+// Adds the run sums of one chunk to y: lanes in entry order, rl = row in the
+// block (>= nrows for lanes past the column block's end).
+__device__ inline void band_chunk_add(double* y, unsigned rl, double v, int nrows, int lane) {
+  const unsigned prev = __shfl_up(rl, 1, 64);
+  const bool head = lane == 0 || rl != prev;
+  const unsigned long long hm = __ballot(head);
+  const int h = 63 - __clzll(hm & (~0ull >> (63 - lane)));  // first lane of this lane's run
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const double t = __shfl_up(v, off, 64);
+    if (lane - off >= h) v += t;
+  }
+  const bool tail = lane == 63 || ((hm >> (lane + 1)) & 1ull);
+  if (tail && rl < static_cast<unsigned>(nrows)) y[rl] += v;
+}
+
+// Entries [e, end) of a column block, up to kBandUnroll chunks (0xFFFFFFFF
+// past the end).
+__device__ inline void band_load(const uint32_t* ent, uint32_t e, uint32_t end, int lane,
+                                 uint32_t* out) {
+#pragma unroll
+  for (int u = 0; u < kBandUnroll; ++u) {
+    const uint32_t i = e + u * 64 + lane;
+    out[u] = i < end ? ent[i] : 0xFFFFFFFFu;
+  }
+}
+
+// Gathers and adds up to kBandUnroll chunks of entries.
+template <class XT>
+__device__ inline void band_group(double* y, const XT* xc, const uint32_t* en, uint32_t e,
+                                  uint32_t end, int wlog, int nrows, int lane) {
+  const uint32_t wmask = (1u << wlog) - 1u;
+  double v[kBandUnroll];
+#pragma unroll
+  for (int u = 0; u < kBandUnroll; ++u)
+    v[u] = en[u] != 0xFFFFFFFFu ? static_cast<double>(xc[en[u] & wmask]) : 0.0;
+#pragma unroll
+  for (int u = 0; u < kBandUnroll; ++u) {
+    if (e + u * 64 >= end) break;  // uniform
+    band_chunk_add(y, en[u] >> wlog, v[u], nrows, lane);
+  }
+}
+
+// Fixed-order sum over the NW waves of a workgroup of two values; result in
+// thread 0.
+template <int NW>
+__device__ inline void block_sum2_n(double& a, double& b, double* sh) {
+  for (int off = 32; off > 0; off >>= 1) {
+    a += __shfl_down(a, off, 64);
+    b += __shfl_down(b, off, 64);
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    sh[2 * w] = a;
+    sh[2 * w + 1] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    a = 0.0;
+    b = 0.0;
+    for (int k = 0; k < NW; ++k) {
+      a += sh[2 * k];
+      b += sh[2 * k + 1];
+    }
+  }
+  __syncthreads();
+}
+
+// Deferred gap of the previous pass (as take_deferred) for a workgroup of NW
+// waves: thread t sums a contiguous run of the pairs, then a fixed tree.
+template <int NW>
+__device__ inline void take_deferred_n(Ctrl* c, double* pairs, double* hist, int count_iter,
+                                       int pass_id, double* red) {
+  const int n = static_cast<int>(c->pending);  // uniform
+  if (n == 0) return;
+  const int already = c->done;                  // uniform
+  const int tid = threadIdx.x;
+  constexpr int NT = NW * 64;
+  const int per = (n + NT - 1) / NT;
+  const int q_end = min(n, (tid + 1) * per);
+  double G = 0.0, S = 0.0;
+  for (int q = tid * per; q < q_end; ++q) {
+    unsigned long long* p = reinterpret_cast<unsigned long long*>(pairs + 2 * q);
+    G += __longlong_as_double(static_cast<long long>(
+        __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
+    S += __longlong_as_double(static_cast<long long>(
+        __hip_atomic_load(p + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
+    __hip_atomic_store(p, kEmptySlot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(p + 1, kEmptySlot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  block_sum2_n<NW>(G, S, red);
+  if (tid == 0) {
+    c->pending = 0;
+    if (!already) decide_gap(c, G, S, hist, nullptr, count_iter, pass_id);
+  }
+  __syncthreads();
+}
+
+template <int MODE, int R, int NW>
+__global__ __launch_bounds__(NW * 64) void k_band(PassArgs a, BandArgs b) {
+  __shared__ double ylds[NW][R];
+  __shared__ double red[2 * NW];
+  using XT = typename std::conditional<MODE == kStep32, float, double>::type;
+  if (b.first_launch && a.defer_gap && blockIdx.x == 0)
+    take_deferred_n<NW>(a.ctrl, a.gap_prev, a.hist, a.count_iter, a.pass_id, red);
+  // a decision made during the first launch concerns the previous pass and
+  // carries this pass's id, which stops only the later launches
+  if (a.respect_done && pass_cancelled(a.ctrl, a.pass_id, !b.first_launch)) return;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int blk = b.first_block + static_cast<int>(blockIdx.x) * NW + wave;
+  double g = 0.0, sn = 0.0;
+  if (blk < b.n_blocks) {
+    const BandBlock bb = b.blocks[blk];
+    double* y = ylds[wave];
+    for (int k = lane; k < bb.nrows; k += 64) y[k] = 0.0;
+    __builtin_amdgcn_wave_barrier();
+    const uint32_t* toff = b.toff + static_cast<int64_t>(blk) * b.B;
+    const XT* x = static_cast<const XT*>(a.x);
+    // pacing: column block c starts no earlier than c·pace after this wave's
+    // start, so that waves which run ahead wait for the others and the
+    // gathers of all waves stay in the same few column blocks (0 = off)
+    const unsigned long long t_start = b.pace ? wall_clock64() : 0ull;
+    uint32_t t0 = toff[0], t1 = toff[1];
+    uint32_t pre[kBandUnroll];
+    band_load(b.ent, t0, t1, lane, pre);
+    for (int c = 0; c < b.B; ++c) {
+      uint32_t cur[kBandUnroll];
+#pragma unroll
+      for (int u = 0; u < kBandUnroll; ++u) cur[u] = pre[u];
+      const uint32_t e0 = t0, e1 = t1;
+      // the next column block's bounds and first chunks, in flight meanwhile
+      if (c + 1 < b.B) {
+        t0 = t1;
+        t1 = toff[c + 2];
+        band_load(b.ent, t0, t1, lane, pre);
+      }
+      if (b.pace) {
+        const unsigned long long due = t_start + static_cast<unsigned long long>(c) * b.pace;
+        while (wall_clock64() < due) __builtin_amdgcn_s_sleep(2);
+      }
+      const XT* xc = x + (static_cast<int64_t>(c) << b.wlog);
+      if (e0 < e1) {
+        band_group(y, xc, cur, e0, e1, b.wlog, bb.nrows, lane);
+        for (uint32_t e = e0 + 64 * kBandUnroll; e < e1; e += 64 * kBandUnroll) {
+          band_load(b.ent, e, e1, lane, cur);
+          band_group(y, xc, cur, e, e1, b.wlog, bb.nrows, lane);
+        }
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (bb.piece >= 0) {
+      if (lane == 0) b.piece[bb.piece] = y[0];
+    } else {
+      for (int k = lane; k < bb.nrows; k += 64) {
+        const int r = bb.row_lo + k;
+        apply_row<MODE>(a, nullptr, r, load_row<MODE>(a, r), y[k], g, sn);
+      }
+    }
+  }
+  if constexpr (MODE != kFinal64) {
+    block_sum2_n<NW>(g, sn, red);
+    if (threadIdx.x == 0) {
+      const int q = b.pair_base + static_cast<int>(blockIdx.x);
+      b.pairs[2 * q] = g;
+      b.pairs[2 * q + 1] = sn;
+    }
+  }
+}
+
+// The end of a band pass: rows cut into pieces get their sum (pieces in
+// order) and epilogue; the band launches' gap pairs are summed in order, a
+// contiguous share per workgroup, and the gap is finished as in every pass.
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_band_fix(PassArgs a, BandFixArgs f) {
+  __shared__ double red[8];
+  __shared__ int last;
+  if (a.respect_done && pass_cancelled(a.ctrl, a.pass_id, true)) return;
+  const int tid = threadIdx.x;
+  double g = 0.0, sn = 0.0;
+  if constexpr (MODE != kFinal64) {
+    const int per = (f.n_pairs + static_cast<int>(gridDim.x) - 1) / static_cast<int>(gridDim.x);
+    const int lo = static_cast<int>(blockIdx.x) * per;
+    const int hi = min(f.n_pairs, lo + per);
+    const int per_t = (max(hi - lo, 0) + kBlock - 1) / kBlock;
+    const int q_end = min(hi, lo + (tid + 1) * per_t);
+    for (int q = lo + tid * per_t; q < q_end; ++q) {
+      g += f.pairs[2 * q];
+      sn += f.pairs[2 * q + 1];
+    }
+  }
+  for (int q = static_cast<int>(blockIdx.x) * kBlock + tid; q < f.n_split;
+       q += static_cast<int>(gridDim.x) * kBlock) {
+    const int4 sr = f.split[q];
+    double y = 0.0;
+    for (int p = sr.y; p < sr.z; ++p) y += f.piece[p];
+    apply_row<MODE>(a, nullptr, sr.x, load_row<MODE>(a, sr.x), y, g, sn);
+  }
+  if constexpr (MODE != kFinal64) finalize_gap(a, g, sn, red, &last);
+}
+
 // Co-resident workgroups of a kernel: CUs × workgroups per CU, a multiple of 8.
 template <class K>
 int resident_grid(K kernel) {
@@ -845,7 +1059,90 @@ psi_status launch_combine(const PassArgs& a, const SegArgs& sg, hipStream_t st) 
   return PSI_OK;
 }
 
+template <int MODE, int R, int NW>
+psi_status launch_bands_r(psi_operator* op, const PassArgs& a, bool band_only, hipStream_t st) {
+  BandArgs b{};
+  b.ent = op->band_ent;
+  b.toff = op->band_toff;
+  b.blocks = op->band_blocks;
+  b.piece = op->band_piece;
+  b.pairs = op->band_pairs;
+  b.B = op->band_B;
+  b.wlog = op->band_wlog;
+  b.n_blocks = op->band_nb;
+  const int wg_per_band = op->band_waves / NW;
+  int n_pairs = 0;
+  for (int k = 0; k < op->band_count; ++k) {
+    b.first_block = k * op->band_waves;
+    const int nb = std::min(op->band_waves, op->band_nb - b.first_block);
+    const int grid = (nb + NW - 1) / NW;
+    b.pair_base = k * wg_per_band;
+    b.first_launch = k == 0;
+    b.pace = op->band_pace_ticks;
+    hipLaunchKernelGGL((k_band<MODE, R, NW>), dim3(grid), dim3(NW * 64), 0, st, a, b);
+    n_pairs = b.pair_base + grid;
+  }
+  PSI_HIP_CHECK(hipGetLastError());
+  if (band_only) return PSI_OK;
+  BandFixArgs f{};
+  f.split = op->band_split;
+  f.piece = op->band_piece;
+  f.pairs = op->band_pairs;
+  f.n_split = op->band_n_split;
+  f.n_pairs = MODE == kFinal64 ? 0 : n_pairs;
+  const int want = std::max((f.n_split + kBlock - 1) / kBlock, (n_pairs + 255) / 256);
+  const int grid = std::max(1, std::min(kBandFixGrid, want));
+  hipLaunchKernelGGL(k_band_fix<MODE>, dim3(grid), dim3(kBlock), 0, st, a, f);
+  PSI_HIP_CHECK(hipGetLastError());
+  return PSI_OK;
+}
+
+template <int MODE>
+psi_status launch_bands_mode(psi_operator* op, const PassArgs& a, bool band_only,
+                             hipStream_t st) {
+  if (op->band_rows == 2048) return launch_bands_r<MODE, 2048, 4>(op, a, band_only, st);
+  return launch_bands_r<MODE, 1024, 4>(op, a, band_only, st);
+}
+
+// Co-resident workgroups of a kernel of `threads` threads per workgroup.
+template <class K>
+int resident_groups(K kernel, int threads) {
+  int dev = 0, per_cu = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess)
+    return 0;
+  return std::max(1, per_cu) * cus;
+}
+
 }  // namespace
+
+int band_waves(int rows) {
+  // every workgroup of a launch resident at once, up to the capacities' cap
+  const int waves = rows == 2048 ? resident_groups(k_band<kStep64, 2048, 4>, 4 * 64) * 4
+                                 : resident_groups(k_band<kStep64, 1024, 4>, 4 * 64) * 4;
+  return std::min(kBandWaveCap, waves);
+}
+
+psi_status launch_pass_bands(psi_operator* op, PassMode mode, const PassArgs& a, bool band_only,
+                             hipStream_t st) {
+  PSI_REQUIRE(op->band_built, "band layout not built");
+  switch (mode) {
+    case kStep64: return launch_bands_mode<kStep64>(op, a, band_only, st);
+    case kFinal64: return launch_bands_mode<kFinal64>(op, a, band_only, st);
+    case kStep32: return launch_bands_mode<kStep32>(op, a, band_only, st);
+    default: break;
+  }
+  set_error("this pass has no band form");
+  return PSI_EINVAL;
+}
+
+psi_status run_pass(psi_operator* op, int S, PassMode mode, const PassArgs& a, hipStream_t st) {
+  if (op->seg_form == kSegBands && (mode == kStep64 || mode == kFinal64 || mode == kStep32))
+    return launch_pass_bands(op, mode, a, false, st);
+  if (S > 1 && mode != kStep64W) return launch_pass_seg(op, mode, a, st);
+  return launch_pass(op, mode, a, st);
+}
 
 psi_status launch_gap_decide(Ctrl* ctrl, double* pairs, double* hist, int count_iter,
                              hipStream_t st) {

@@ -154,12 +154,6 @@ psi_status resolve_segments(const psi_operator* op, int requested, int bytes, in
   return PSI_OK;
 }
 
-// A pass in the column-segmented form when S > 1 (the weighted form has none).
-psi_status run_pass(psi_operator* op, int S, PassMode mode, const PassArgs& a, hipStream_t st) {
-  if (S > 1 && mode != kStep64W) return launch_pass_seg(op, mode, a, st);
-  return launch_pass(op, mode, a, st);
-}
-
 // Enqueue passes until the device sets done; make(i) gives the arguments of
 // pass i (i counts passes enqueued in this call).
 template <class Make>
@@ -265,15 +259,30 @@ psi_status check_waits(psi_operator* op, hipStream_t st) {
   return PSI_EDEVICE;
 }
 
-// Partial-pass form for S segments: the requested one, else the tuned one
-// (when it was tuned for this S), else sliced while a segment's share of the
-// gathered vector (`bytes` per user) is at most 6 MB, about what an XCD's L2
-// keeps.
-psi_status resolve_form(const psi_operator* op, int requested, int precision, int S, int bytes,
-                        int* form) {
-  PSI_REQUIRE(requested == 0 || requested == PSI_SEG_TILES || requested == PSI_SEG_SLICES,
-              "seg_form must be 0, PSI_SEG_TILES or PSI_SEG_SLICES");
-  if (S <= 1) {
+// Layout of a call's passes.  The band layout when it is requested, or when
+// nothing is requested (seg_form = col_segments = 0) and it was tuned for this
+// precision or, untuned, the gathered vector (`bytes` per user) exceeds
+// kBandAutoBytes on a single-graph operator.  Otherwise the partial-pass form
+// for S segments: the requested one, else the tuned one (when it was tuned for
+// this S), else sliced while a segment's share of the gathered vector is at
+// most 6 MB, about what an XCD's L2 keeps.
+constexpr double kBandAutoBytes = 32.0e6;
+
+psi_status resolve_form(const psi_operator* op, int requested, int requested_S, int precision,
+                        int S, int bytes, int* form) {
+  PSI_REQUIRE(requested == 0 || requested == PSI_SEG_TILES || requested == PSI_SEG_SLICES ||
+                  requested == PSI_SEG_BANDS,
+              "seg_form must be 0, PSI_SEG_TILES, PSI_SEG_SLICES or PSI_SEG_BANDS");
+  const bool untuned = op->tuned_tile[precision] == 0;
+  if (requested == kSegBands ||
+      (requested == 0 && requested_S == 0 && precision != PSI_PREC_FP64_WEIGHTED &&
+       op->n_graphs == 1 &&
+       (op->tuned_form[precision] == kSegBands ||
+        (untuned && static_cast<double>(op->n) * bytes >= kBandAutoBytes)))) {
+    PSI_REQUIRE(op->n_graphs == 1, "the band layout is for single-graph operators");
+    PSI_REQUIRE(precision != PSI_PREC_FP64_WEIGHTED, "the weighted pass has no band layout");
+    *form = kSegBands;
+  } else if (S <= 1) {
     *form = 0;
   } else if (requested) {
     *form = requested;
@@ -285,18 +294,68 @@ psi_status resolve_form(const psi_operator* op, int requested, int precision, in
   return PSI_OK;
 }
 
-// Schedules and layouts the passes of one call need; the segmented passes of
-// the call then use `form`.
-psi_status prepare(psi_operator* op, int tile, int S, int form, hipStream_t st) {
+// Tuned for `precision`, else the layout already built, else 2^18 x 2048.
+void band_params(const psi_operator* op, int precision, int* wlog, int* rows) {
+  if (op->tuned_band_wlog[precision]) {
+    *wlog = op->tuned_band_wlog[precision];
+    *rows = op->tuned_band_rows[precision];
+  } else if (op->band_built) {
+    *wlog = op->band_wlog;
+    *rows = op->band_rows;
+  } else {
+    *wlog = kBandMaxLog;
+    *rows = 2048;
+  }
+}
+
+// Schedules and layouts the passes of one call need; the passes of the call
+// then use `form` (band layout with column blocks of 2^wlog users and row
+// blocks of `rows` rows; 0 = those of op->band_* if built, else the defaults).
+psi_status prepare(psi_operator* op, int tile, int S, int form, hipStream_t st, int wlog,
+                   int rows) {
   psi_status s = ensure_schedule(op, tile, st);
   if (s != PSI_OK) return s;
   op->seg_form = 0;
+  if (form == kSegBands) {
+    if (!wlog) wlog = op->band_built ? op->band_wlog : kBandMaxLog;
+    if (!rows) rows = op->band_built ? op->band_rows : 2048;
+    s = ensure_bands(op, wlog, rows, st);
+    if (s != PSI_OK) return s;
+    op->seg_form = kSegBands;
+    return PSI_OK;
+  }
   if (S <= 1) return PSI_OK;
   s = ensure_segments(op, S, st);
   if (s != PSI_OK) return s;
   s = form == kSegSlices ? ensure_seg_slices(op, st) : ensure_seg_tiles(op, tile, st);
   if (s != PSI_OK) return s;
   op->seg_form = form;
+  return PSI_OK;
+}
+
+psi_status prepare(psi_operator* op, int tile, int S, int form, hipStream_t st) {
+  return prepare(op, tile, S, form, st, 0, 0);
+}
+
+// prepare() with the band parameters tuned for `precision` (or the defaults).
+psi_status prepare_for(psi_operator* op, int precision, int tile, int S, int form,
+                       hipStream_t st, int wlog = 0, int rows = 0) {
+  PSI_REQUIRE(wlog == 0 || (wlog >= kBandMinLog && wlog <= kBandMaxLog),
+              "band_col_log must be 0, 17 or 18");
+  PSI_REQUIRE(rows == 0 || rows == 1024 || rows == 2048, "band_rows must be 0, 1024 or 2048");
+  if (form == kSegBands) {
+    int tw = 0, tr = 0;
+    band_params(op, precision, &tw, &tr);
+    if (!wlog) wlog = tw;
+    if (!rows) rows = tr;
+  }
+  psi_status s = prepare(op, tile, S, form, st, wlog, rows);
+  if (s != PSI_OK) return s;
+  // the pacing tuned for this layout, else none
+  op->band_pace_ticks = form == kSegBands && op->tuned_band_wlog[precision] == wlog &&
+                                op->tuned_band_rows[precision] == rows
+                            ? op->tuned_band_pace[precision]
+                            : 0ull;
   return PSI_OK;
 }
 
@@ -325,10 +384,11 @@ psi_status solve(psi_operator* op, const psi_params* prm, const double* s0, doub
   if (s != PSI_OK) return s;
   if (prm->precision == PSI_PREC_FP64_WEIGHTED) S = 1;
   int form = 0;
-  s = resolve_form(op, prm->seg_form, prm->precision, S,
+  s = resolve_form(op, prm->seg_form, prm->col_segments, prm->precision, S,
                    prm->precision == PSI_PREC_FP64 ? 8 : 4, &form);
   if (s != PSI_OK) return s;
-  s = prepare(op, tile, S, form, st);
+  if (form == kSegBands) S = 1;
+  s = prepare_for(op, prm->precision, tile, S, form, st, prm->band_col_log, prm->band_rows);
   if (s != PSI_OK) return s;
 
   const int64_t n = op->n;
@@ -628,9 +688,10 @@ psi_status step(psi_operator* op, int precision, const double* s_in, double* s_o
   if (s != PSI_OK) return s;
   if (precision == PSI_PREC_FP64_WEIGHTED) S = 1;
   int form = 0;
-  s = resolve_form(op, seg_form, precision, S, 8, &form);
+  s = resolve_form(op, seg_form, col_segments, precision, S, 8, &form);
   if (s != PSI_OK) return s;
-  s = prepare(op, tile, S, form, st);
+  if (form == kSegBands) S = 1;
+  s = prepare_for(op, precision, tile, S, form, st);
   if (s != PSI_OK) return s;
   PassArgs a = base_args(op);
   a.s_old = s_in;
@@ -652,11 +713,13 @@ psi_status step(psi_operator* op, int precision, const double* s_in, double* s_o
 
 psi_status final_psi(psi_operator* op, const double* s_vec, double* psi_out, hipStream_t st) {
   PSI_REQUIRE(s_vec && psi_out, "s and psi_out must not be NULL");
-  const int S = auto_segments(op, 8);
+  int S = auto_segments(op, 8);
   int form = 0;
-  psi_status s = resolve_form(op, 0, PSI_PREC_FP64, S, 8, &form);
+  psi_status s = resolve_form(op, 0, 0, PSI_PREC_FP64, S, 8, &form);
   if (s != PSI_OK) return s;
-  s = prepare(op, op->sched_items ? op->sched_items : kDefaultTileItems, S, form, st);
+  if (form == kSegBands) S = 1;
+  s = prepare_for(op, PSI_PREC_FP64, op->sched_items ? op->sched_items : kDefaultTileItems, S,
+                  form, st);
   if (s != PSI_OK) return s;
   hipLaunchKernelGGL(k_make_z, dim3(grid_for(op->n)), dim3(kBlock), 0, st, s_vec, op->invden,
                      op->n, op->z_a);
@@ -666,8 +729,12 @@ psi_status final_psi(psi_operator* op, const double* s_vec, double* psi_out, hip
   return run_pass(op, S, kFinal64, a, st);
 }
 
-psi_status pass_time(psi_operator* op, int kind, int reps, int tile_items, int col_segments,
-                     int seg_form, double* mean_ms, hipStream_t st) {
+// Times `reps` launches of a pass kind (see psi_pass_time); band layouts
+// with column blocks of 2^wlog users and row blocks of `rows` rows (0: tuned
+// or default).  A partial pass in the band layout is its band launches
+// without the closing kernel, reported per launch.
+psi_status pass_time_ex(psi_operator* op, int kind, int reps, int tile_items, int col_segments,
+                        int seg_form, int wlog, int rows, double* mean_ms, hipStream_t st) {
   PSI_REQUIRE(mean_ms, "mean_ms must not be NULL");
   PSI_REQUIRE(reps >= 1, "reps must be >= 1");
   PSI_REQUIRE(kind >= PSI_PASS_STEP64 && kind <= PSI_PASS_PART32, "unknown pass kind");
@@ -682,13 +749,16 @@ psi_status pass_time(psi_operator* op, int kind, int reps, int tile_items, int c
   psi_status s = resolve_segments(op, col_segments, kind == PSI_PASS_STEP32 ? 4 : 8, &S);
   if (s != PSI_OK) return s;
   if (kind == PSI_PASS_STEP64_W) S = 1;
-  PSI_REQUIRE(!part_only || S > 1, "a partial pass needs col_segments > 1");
+  const int prec = kind == PSI_PASS_STEP32 ? PSI_PREC_MIXED
+                 : kind == PSI_PASS_STEP64_W ? PSI_PREC_FP64_WEIGHTED : PSI_PREC_FP64;
   int form = 0;
-  s = resolve_form(op, seg_form,
-                   kind == PSI_PASS_STEP32 ? PSI_PREC_MIXED : PSI_PREC_FP64, S,
-                   kind == PSI_PASS_STEP32 ? 4 : 8, &form);
+  s = resolve_form(op, seg_form, col_segments, prec, S, kind == PSI_PASS_STEP32 ? 4 : 8, &form);
   if (s != PSI_OK) return s;
-  s = prepare(op, tile, S, form, st);
+  if (form == kSegBands) S = 1;
+  PSI_REQUIRE(!part_only || S > 1 || form == kSegBands,
+              "a partial pass needs col_segments > 1 or the band layout");
+  if (form == kSegBands && !wlog && !rows) band_params(op, prec, &wlog, &rows);
+  s = prepare(op, tile, S, form, st, wlog, rows);
   if (s != PSI_OK) return s;
   const int64_t n = op->n;
   hipLaunchKernelGGL(k_init64, dim3(grid_for(n)), dim3(kBlock), 0, st, nullptr, op->c, op->invden,
@@ -724,7 +794,9 @@ psi_status pass_time(psi_operator* op, int kind, int reps, int tile_items, int c
     return a;
   };
   auto launch = [&](const PassArgs& a) {
-    return part_only ? launch_part_seg(op, mode, a, st) : run_pass(op, S, mode, a, st);
+    if (!part_only) return run_pass(op, S, mode, a, st);
+    return form == kSegBands ? launch_pass_bands(op, mode, a, true, st)
+                             : launch_part_seg(op, mode, a, st);
   };
   s = launch(make(0));
   if (s != PSI_OK) return s;
@@ -741,7 +813,13 @@ psi_status pass_time(psi_operator* op, int kind, int reps, int tile_items, int c
   float ms = 0.f;
   PSI_HIP_CHECK(hipEventElapsedTime(&ms, tm.a, tm.b));
   *mean_ms = static_cast<double>(ms) / reps;
+  if (part_only && form == kSegBands) *mean_ms /= std::max(1, op->band_count);
   return PSI_OK;
+}
+
+psi_status pass_time(psi_operator* op, int kind, int reps, int tile_items, int col_segments,
+                     int seg_form, double* mean_ms, hipStream_t st) {
+  return pass_time_ex(op, kind, reps, tile_items, col_segments, seg_form, 0, 0, mean_ms, st);
 }
 
 // Times the loop kernels of a solve in `precision` for every supported tile
@@ -759,51 +837,96 @@ psi_status autotune(psi_operator* op, int precision, int reps, int* tile_items, 
   static const int kSegs[] = {1, 2, 4, 8};
   const int n_segs = precision == PSI_PREC_FP64_WEIGHTED ? 1 : 4;
   double best = 0.0;
-  int best_tile = 0, best_S = 0, best_form = 0;
+  int best_tile = 0, best_S = 0, best_form = 0, best_wlog = 0, best_rows = 0;
+  unsigned long long best_pace = 0;
   int tile_s1 = 0;  // fastest tile of the unsegmented pass (S = 1 is timed first)
   double best_s1 = 0.0;
-  auto time_one = [&](int tile, int S, int form, double* ms) -> psi_status {
+  auto time_one = [&](int tile, int S, int form, int wlog, int rows, double* ms) -> psi_status {
     int r = reps;
     if (r == 0) {  // about 20 ms of passes per candidate, at least 3
       double one = 0.0;
-      psi_status s = pass_time(op, kind, 1, tile, S, form, &one, st);
+      psi_status s = pass_time_ex(op, kind, 1, tile, S, form, wlog, rows, &one, st);
       if (s != PSI_OK) return s;
       r = static_cast<int>(std::min(50.0, std::max(3.0, 20.0 / std::max(one, 1e-3))));
     }
-    return pass_time(op, kind, r, tile, S, form, ms, st);
+    return pass_time_ex(op, kind, r, tile, S, form, wlog, rows, ms, st);
   };
-  auto keep = [&](int tile, int S, int form, double ms) {
+  auto keep = [&](int tile, int S, int form, int wlog, int rows, double ms,
+                  unsigned long long pace = 0) {
     if (best_tile == 0 || ms < best) {
       best = ms;
       best_tile = tile;
       best_S = S;
       best_form = form;
+      best_wlog = wlog;
+      best_rows = rows;
+      best_pace = pace;
     }
   };
   for (int si = 0; si < n_segs; ++si) {
     const int S = kSegs[si];
     for (int tile : kTiles) {  // S = 1, or the tiled form of S segments
       double ms = 0.0;
-      psi_status s = time_one(tile, S, S > 1 ? kSegTiles : 0, &ms);
+      psi_status s = time_one(tile, S, S > 1 ? kSegTiles : 0, 0, 0, &ms);
       if (s != PSI_OK) return s;
       if (S == 1 && (tile_s1 == 0 || ms < best_s1)) {
         best_s1 = ms;
         tile_s1 = tile;
       }
-      keep(tile, S, S > 1 ? kSegTiles : 0, ms);
+      keep(tile, S, S > 1 ? kSegTiles : 0, 0, 0, ms);
     }
     if (S > 1) {  // the sliced form has no tiles: one timing, with the S = 1 tile kept
       double ms = 0.0;
-      psi_status s = time_one(tile_s1, S, kSegSlices, &ms);
+      psi_status s = time_one(tile_s1, S, kSegSlices, 0, 0, &ms);
       if (s != PSI_OK) return s;
-      keep(tile_s1, S, kSegSlices, ms);
+      keep(tile_s1, S, kSegSlices, 0, 0, ms);
     }
   }
-  psi_status s = prepare(op, best_tile, best_S, best_form, st);
+  if (precision != PSI_PREC_FP64_WEIGHTED) {  // the band layout: column width x row-block size
+    int bw = 0, br = 0;
+    double bms = 0.0;
+    op->band_pace_ticks = 0;
+    for (int wlog = kBandMinLog; wlog <= kBandMaxLog; ++wlog)
+      for (int rows : {1024, 2048}) {
+        double ms = 0.0;
+        psi_status s = time_one(tile_s1, 1, kSegBands, wlog, rows, &ms);
+        if (s != PSI_OK) return s;
+        keep(tile_s1, 1, kSegBands, wlog, rows, ms);
+        if (bw == 0 || ms < bms) {
+          bw = wlog;
+          br = rows;
+          bms = ms;
+        }
+      }
+    // pacing of the fastest band layout: column block c of a launch starts no
+    // earlier than c·pace, with pace a fraction of the unpaced time per column
+    // block; waves drift apart less and their gathers stay in L2
+    int dev = 0, khz = 0;
+    PSI_HIP_CHECK(hipGetDevice(&dev));
+    PSI_HIP_CHECK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+    psi_status s = prepare(op, tile_s1, 1, kSegBands, st, bw, br);
+    if (s != PSI_OK) return s;
+    const double step_us = bms * 1e3 / (double(std::max(1, op->band_count)) * op->band_B);
+    if (khz > 0 && op->band_B > 1) {
+      for (double f : {0.4, 0.5, 0.6, 0.7, 0.8}) {
+        op->band_pace_ticks = static_cast<unsigned long long>(f * step_us * khz / 1e3);
+        double ms = 0.0;
+        s = time_one(tile_s1, 1, kSegBands, bw, br, &ms);
+        if (s != PSI_OK) return s;
+        keep(tile_s1, 1, kSegBands, bw, br, ms, op->band_pace_ticks);
+      }
+    }
+    op->band_pace_ticks = 0;
+  }
+  psi_status s = prepare(op, best_tile, best_S, best_form, st, best_wlog, best_rows);
   if (s != PSI_OK) return s;
   op->tuned_tile[precision] = best_tile;
   op->tuned_S[precision] = best_S;
   op->tuned_form[precision] = best_form;
+  op->tuned_band_wlog[precision] = best_wlog;
+  op->tuned_band_rows[precision] = best_rows;
+  op->tuned_band_pace[precision] = best_pace;
+  op->band_pace_ticks = best_form == kSegBands ? best_pace : 0ull;
   if (tile_items) *tile_items = best_tile;
   if (col_segments) *col_segments = best_S;
   if (seg_form) *seg_form = best_form;

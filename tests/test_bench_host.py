@@ -20,14 +20,17 @@ def test_more_than_one_gpu_exits_with_a_message():
 
 
 def test_algorithmic_bytes_count_each_array_once():
+    """The compulsory bytes of one pass, whatever kernels it runs in: 4 B per
+    follower id; per user row_ptr 4 and, in FP64, z, c, μ, 1/den, s_new (8 B
+    each) — the factored pass's 4M + 44N — or the weighted pass's 12M + 28N."""
     n, m = 1000, 20000
-    # pull step: 4 B per follower id; per user row_ptr, z, c, μ, 1/den, s_old in, s_new, z_new out
-    assert bench.algorithmic_bytes("step64", n, m) == 4 * m + (4 + 7 * 8) * n
+    assert bench.algorithmic_bytes("step64", n, m) == 4 * m + 44 * n
+    for k in ("part64", "band64"):  # the gather kernel of a pass carries the pass's bytes
+        assert bench.algorithmic_bytes(k, n, m) == bench.algorithmic_bytes("step64", n, m)
+    assert bench.algorithmic_bytes("step64_w", n, m) == 12 * m + 28 * n
     assert bench.algorithmic_bytes("final64", n, m) == 4 * m + (4 + 4 * 8) * n
-    # partial passes grow with the number of column segments, by the per-segment row data
-    one = bench.algorithmic_bytes("part64", n, m, 1)
-    assert bench.algorithmic_bytes("part64", n, m, 4) - one == 3 * 13 * n
-    assert bench.algorithmic_bytes("part32", n, m, 4) < bench.algorithmic_bytes("part64", n, m, 4)
+    assert bench.algorithmic_bytes("step32", n, m) == 4 * m + 32 * n
+    assert bench.algorithmic_bytes("band32", n, m) < bench.algorithmic_bytes("band64", n, m)
 
 
 def test_traffic_only_for_the_measured_sources(tmp_path, monkeypatch):

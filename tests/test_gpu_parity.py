@@ -224,7 +224,7 @@ def test_segmented_step_matches_oracle(gpu_lib, segs, form, tile):
 @pytest.mark.parametrize("prec,tol,bar", [("fp64", 1e-9, 1e-9), ("mixed", 1e-9, 1e-9),
                                           ("fp32", 1e-5, 1e-6)])
 @pytest.mark.parametrize("segs,form", [(1, "auto"), (2, "tiles"), (2, "slices"), (4, "tiles"),
-                                       (4, "slices"), (8, "tiles"), (8, "slices")])
+                                       (4, "slices"), (8, "tiles"), (8, "slices"), (0, "bands")])
 def test_segmented_solve(gpu_lib, prec, tol, bar, segs, form):
     api = gpu_lib
     g = synth.chung_lu(60000, 20, 2.2, 14, sigma=1.5)
@@ -552,8 +552,9 @@ def test_autotune_picks_a_supported_schedule_that_solves_use(gpu_lib):
         t = op.autotune(prec, reps=3)
         assert t["tile_items"] in (1024, 1536, 2048, 3072, 4096)
         assert t["col_segments"] in (1, 2, 4, 8) and t["pass_ms"] > 0
-        assert t["seg_form"] == ("none" if t["col_segments"] == 1 else t["seg_form"])
-        assert t["seg_form"] in ("none", "tiles", "slices")
+        assert t["seg_form"] in ("none", "tiles", "slices", "bands")
+        if t["seg_form"] != "bands":
+            assert t["seg_form"] == ("none" if t["col_segments"] == 1 else t["seg_form"])
         psi, info = op.solve(tol=1e-10, precision=prec)
         assert info["status"] == 0
         assert (info["tile_items"], info["col_segments"]) == (t["tile_items"], t["col_segments"])
