@@ -235,6 +235,12 @@ def run_single(args, name):
     assert info_aa["status"] == 0, info_aa
     modes["fp64_anderson"] = dict(ms=ms_aa, info=info_aa, psi=psi_aa.cpu().numpy())
     log(f"fp64_anderson: {ms_aa:.3f} ms/solve, {info_aa['spmv_passes']} passes")
+    # asynchronous local updates: block Gauss–Seidel sweeps over the band layout
+    # (same fixed point and stopping test; reported beside, like Anderson)
+    ms_gs, (psi_gs, info_gs) = timed(lambda: op.solve_async(tol=tol), cmp_k, cmp_w)
+    assert info_gs["status"] == 0, info_gs
+    modes["fp64_async"] = dict(ms=ms_gs, info=info_gs, psi=psi_gs.cpu().numpy())
+    log(f"fp64_async: {ms_gs:.3f} ms/solve, {info_gs['spmv_passes']} passes (sweeps + final)")
 
     # per-origin newsfeed shares (Algorithm 1 for 64 origins at once), for the
     # 64 most influential users; their ψ_i must agree with Power-ψ's
@@ -252,7 +258,7 @@ def run_single(args, name):
                                                     / psi64[top])))
         log(f"origins: 64 origins in {ms_o:.3f} ms, up to {max(po)} passes")
 
-    head = min((p for p in modes if p not in ("fp64_weighted", "fp64_anderson")),
+    head = min((p for p in modes if p not in ("fp64_weighted", "fp64_anderson", "fp64_async")),
                key=lambda p: modes[p]["ms"])
     head_prec = head.replace("_warm", "")
     # the timed region of the reported value: K solves of the headline mode

@@ -212,6 +212,26 @@ psi_status psi_params_default(psi_params* p);
 psi_status psi_solve(psi_operator* op, const psi_params* prm, const double* s0,
                      double* psi_out, double* s_out, psi_info* info, void* stream);
 
+/* Asynchronous local updates (Sec. I names local-update methods such as Push
+ * as the way beyond the power iteration): the same fixed point as psi_solve,
+ * s = Aᵀs + c of eq. (power_psi), found by block Gauss–Seidel sweeps in a
+ * fixed order.  The users are cut into consecutive bands (the band layout,
+ * PSI_SEG_BANDS); in a sweep the bands are updated one after another, and
+ * band k reads the users of bands 0..k−1 at their values from this sweep,
+ * the others at the previous sweep's, so each user updates from fresher
+ * values than Power-ψ's and fewer sweeps are needed.  The order is fixed, so
+ * results are bitwise repeatable.  Stops when the sweep's change
+ * ‖s_k − s_{k−1}‖₁ (tol_mode units) is at most tol (eq. condition); ψ =
+ * (Bᵀs + d)/N from the final s (the last line of Algorithm 2).
+ *   prm:    tol, tol_mode, max_iter (sweeps), check_every, band_col_log,
+ *           band_rows as in psi_solve; precision must be PSI_PREC_FP64 and
+ *           seg_form 0 or PSI_SEG_BANDS;
+ *   s0:     device FP64 [N] start, or NULL for c (used as given);
+ *   psi_out, s_out, info: as in psi_solve (info->iterations counts sweeps).
+ * Single-graph operators; builds the band layout on first use; blocks. */
+psi_status psi_solve_async(psi_operator* op, const psi_params* prm, const double* s0,
+                           double* psi_out, double* s_out, psi_info* info, void* stream);
+
 /* One Power-ψ step (eq. power_psi), enqueued only:
  *   s_out = Aᵀ s_in + c,  *gap_out (device FP64 scalar, may be NULL)
  *   = ‖s_out − s_in‖₁.  precision PSI_PREC_FP64 or PSI_PREC_FP64_WEIGHTED.

@@ -236,6 +236,35 @@ class Operator:
             _check(st)
         return (psi, s, d) if return_s else (psi, d)
 
+    def solve_async(self, tol: float = 1e-8, tol_mode: str = "abs_l1", max_iter: int = 10000,
+                    s0: torch.Tensor | None = None, check_every: int = 0,
+                    band_col_log: int = 0, band_rows: int = 0, return_s: bool = False,
+                    stream=None, raise_on_status: bool = False):
+        """psi_solve_async: the same ψ by block Gauss–Seidel sweeps over the band
+        layout; returns (psi, info) or (psi, s, info)."""
+        p = _ffi.Params()
+        _check(self._lib.psi_params_default(ctypes.byref(p)))
+        p.tol = tol
+        p.tol_mode = TOL_MODES[tol_mode] if isinstance(tol_mode, str) else int(tol_mode)
+        p.max_iter = max_iter
+        p.check_every = check_every
+        p.band_col_log = band_col_log
+        p.band_rows = band_rows
+        psi = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        s = torch.empty(self.n, dtype=torch.float64, device=self.device) if return_s else None
+        if s0 is not None:
+            s0 = _vec_in(s0, self.n, self.device, torch.float64, "s0")
+        info = _ffi.Info()
+        with torch.cuda.device(self.device):
+            st = self._lib.psi_solve_async(self._h, ctypes.byref(p), _ptr(s0), _ptr(psi), _ptr(s),
+                                           ctypes.byref(info), _stream_handle(stream))
+        d = _ffi.struct_dict(info)
+        d["status_name"] = _ffi.STATUS_NAMES.get(st, str(st))
+        if st in (_ffi.PSI_EINVAL, _ffi.PSI_EDEVICE, _ffi.PSI_ENOSPACE) or (
+                raise_on_status and st != _ffi.PSI_OK):
+            _check(st)
+        return (psi, s, d) if return_s else (psi, d)
+
     def step(self, s_in: torch.Tensor, precision: str = "fp64", tile_items: int = 0,
              col_segments: int = 0, seg_form: str | int = 0, stream=None):
         """psi_step: one Power-ψ step s_out = Aᵀ s_in + c and its L1 gap (enqueued)."""

@@ -124,7 +124,8 @@ void plan_blocks(const std::vector<int>& rp, int64_t n, int rows, int64_t emax,
         const int64_t lo = rp[i] + len * q / k;
         blocks.push_back(BandBlock{static_cast<int>(i), 1, piece++, static_cast<int>(lo)});
       }
-      split.push_back(int4{static_cast<int>(i), p0, piece, 0});
+      split.push_back(int4{static_cast<int>(i), p0, piece,
+                           static_cast<int>(blocks.size()) - 1});
       ++i;
       continue;
     }
@@ -216,6 +217,17 @@ psi_status ensure_bands(psi_operator* op, int wlog, int rows, hipStream_t st) {
   op->band_waves = waves;
   op->band_count = static_cast<int>((nb + waves - 1) / waves);
   op->band_n_split = static_cast<int>(split.size());
+  // per band: its first row, and the split rows whose pieces all lie in it or
+  // an earlier band (a Gauss–Seidel sweep finishes them after that band)
+  op->band_row0.assign(op->band_count + 1, static_cast<int>(n));
+  op->band_split_end.assign(op->band_count, 0);
+  for (int k = 0; k < op->band_count; ++k) {
+    op->band_row0[k] = blocks[size_t(k) * waves].row_lo;
+    const int64_t end_block = std::min<int64_t>(nb, int64_t(k + 1) * waves);
+    int q = k ? op->band_split_end[k - 1] : 0;
+    while (q < static_cast<int>(split.size()) && split[q].w < end_block) ++q;
+    op->band_split_end[k] = q;
+  }
   op->band_built = true;
   return PSI_OK;
 }

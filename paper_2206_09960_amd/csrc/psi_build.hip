@@ -866,7 +866,9 @@ static void layout_persistent(int64_t n, int64_t m_raw, int n_graphs, uint32_t f
   char* band_blocks = take(sizeof(BandBlock) * size_t(cap_band_blocks + 1));
   char* band_split = take(16 * size_t(cap_band_blocks));
   char* band_piece = take(8 * size_t(cap_band_blocks));
-  char* band_pairs = take(16 * size_t(cap_band_blocks / 4 + 1));
+  // pairs: one per workgroup of the band launches (four row blocks each) and
+  // one per band for the split rows a Gauss–Seidel sweep finishes per band
+  char* band_pairs = take(16 * size_t(cap_band_blocks / 4 + cap_band_blocks / 256 + 64));
   char* band_scan_tmp = take(4 * size_t((cap_band_toff + 4095) / 4096 + 8));
   const int64_t mp_max_hubs = m_raw / (kMpHubEdges + 1) + 1;
   const int64_t mp_max_chunks = m_raw / kMpChunkEdges + mp_max_hubs + 1;

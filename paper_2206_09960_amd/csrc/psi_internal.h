@@ -158,6 +158,7 @@ struct PassArgs {
   double* row_delta;    //   |s_new − s_old| of each user
   int count_iter;       // 1: the pass is a Power-ψ step that advances ctrl->iter
   int respect_done;     // 1: exit at once when ctrl->done is set
+  int gs_sweep;         // 1: band-layout Gauss–Seidel sweep (psi_solve_async)
 };
 
 enum PassMode : int {
@@ -220,12 +221,16 @@ struct BandArgs {
   int pair_base;            // first pair of this launch's workgroups
   int first_launch;         // 1 for the first launch of a pass (it decides a deferred gap)
   unsigned long long pace;  // wall-clock ticks between column-block starts (0 = no pacing)
+  // Gauss–Seidel sweeps: users below fresh_below were updated earlier in this
+  // sweep and are gathered from x_new, the others from the pass's x
+  const void* x_new;
+  int fresh_below;
 };
 
 // Arguments of the kernel that ends a band pass: the split rows, and the
 // band launches' gap pairs reduced into this kernel's own.
 struct BandFixArgs {
-  const int4* split;        // {row, first piece, end piece, 0}
+  const int4* split;        // {row, first piece, end piece, last block}
   const double* piece;
   const double* pairs;
   int n_split;
@@ -476,15 +481,17 @@ struct psi_operator {
   int band_waves = 0;                // row blocks (waves) per band launch
   int band_count = 0;                // band launches per pass
   int band_n_split = 0;              // rows cut into pieces
+  std::vector<int> band_row0;        // first row of each band, and N
+  std::vector<int> band_split_end;   // split rows whose last piece lies in bands 0..k
   unsigned long long band_pace_ticks = 0;  // pacing of the band launches (0 = none)
   int tuned_band_wlog[4]{}, tuned_band_rows[4]{};
   unsigned long long tuned_band_pace[4]{};
   uint32_t* band_ent = nullptr;      // [m]
   uint32_t* band_toff = nullptr;     // [cap_band_toff]
   psi::BandBlock* band_blocks = nullptr;  // [cap_band_blocks]
-  int4* band_split = nullptr;        // [cap_band_blocks]
+  int4* band_split = nullptr;        // [cap_band_blocks] {row, first piece, end piece, last block}
   double* band_piece = nullptr;      // [cap_band_blocks]
-  double* band_pairs = nullptr;      // [2 * (cap_band_blocks / 4 + 1)]
+  double* band_pairs = nullptr;      // [2 * (cap_band_blocks / 4 + cap_band_blocks / 256 + 64)]
   uint32_t* band_scan_tmp = nullptr;
   int64_t cap_band_blocks = 0, cap_band_toff = 0, cap_band_cols = 0;
 };
@@ -546,6 +553,8 @@ PassArgs base_args(psi_operator* op);
 // returned; otherwise PSI_OK.
 psi_status check_waits(psi_operator* op, hipStream_t st);
 
+psi_status solve_async(psi_operator* op, const psi_params* prm, const double* s0,
+                       double* psi_out, double* s_out, psi_info* info, hipStream_t stream);
 psi_status solve(psi_operator* op, const psi_params* prm, const double* s0, double* psi_out,
                  double* s_out, psi_info* info, hipStream_t stream);
 psi_status autotune(psi_operator* op, int precision, int reps, int* tile_items, int* col_segments,

@@ -771,15 +771,22 @@ __device__ inline void band_load(const uint32_t* ent, uint32_t e, uint32_t end, 
   }
 }
 
-// Gathers and adds up to kBandUnroll chunks of entries.
-template <class XT>
-__device__ inline void band_group(double* y, const XT* xc, const uint32_t* en, uint32_t e,
-                                  uint32_t end, int wlog, int nrows, int lane) {
+// Gathers and adds up to kBandUnroll chunks of entries of column block c.  In
+// a Gauss–Seidel sweep (GS) a follower below `fresh` is read from xn_c, this
+// sweep's values, else from xc, the previous sweep's.
+template <bool GS, class XT>
+__device__ inline void band_group(double* y, const XT* xc, const XT* xn_c, int64_t col0,
+                                  int64_t fresh, const uint32_t* en, uint32_t e, uint32_t end,
+                                  int wlog, int nrows, int lane) {
   const uint32_t wmask = (1u << wlog) - 1u;
   double v[kBandUnroll];
 #pragma unroll
-  for (int u = 0; u < kBandUnroll; ++u)
-    v[u] = en[u] != 0xFFFFFFFFu ? static_cast<double>(xc[en[u] & wmask]) : 0.0;
+  for (int u = 0; u < kBandUnroll; ++u) {
+    const uint32_t jl = en[u] & wmask;
+    const XT* src = xc;
+    if constexpr (GS) src = col0 + jl < fresh ? xn_c : xc;
+    v[u] = en[u] != 0xFFFFFFFFu ? static_cast<double>(src[jl]) : 0.0;
+  }
 #pragma unroll
   for (int u = 0; u < kBandUnroll; ++u) {
     if (e + u * 64 >= end) break;  // uniform
@@ -842,7 +849,7 @@ __device__ inline void take_deferred_n(Ctrl* c, double* pairs, double* hist, int
   __syncthreads();
 }
 
-template <int MODE, int R, int NW>
+template <int MODE, int R, int NW, bool GS>
 __global__ __launch_bounds__(NW * 64) void k_band(PassArgs a, BandArgs b) {
   __shared__ double ylds[NW][R];
   __shared__ double red[2 * NW];
@@ -862,6 +869,7 @@ __global__ __launch_bounds__(NW * 64) void k_band(PassArgs a, BandArgs b) {
     __builtin_amdgcn_wave_barrier();
     const uint32_t* toff = b.toff + static_cast<int64_t>(blk) * b.B;
     const XT* x = static_cast<const XT*>(a.x);
+    const XT* xn = static_cast<const XT*>(b.x_new);
     // pacing: column block c starts no earlier than c·pace after this wave's
     // start, so that waves which run ahead wait for the others and the
     // gathers of all waves stay in the same few column blocks (0 = off)
@@ -884,12 +892,14 @@ __global__ __launch_bounds__(NW * 64) void k_band(PassArgs a, BandArgs b) {
         const unsigned long long due = t_start + static_cast<unsigned long long>(c) * b.pace;
         while (wall_clock64() < due) __builtin_amdgcn_s_sleep(2);
       }
-      const XT* xc = x + (static_cast<int64_t>(c) << b.wlog);
+      const int64_t col0 = static_cast<int64_t>(c) << b.wlog;
+      const XT* xc = x + col0;
+      const XT* xn_c = GS ? xn + col0 : xc;
       if (e0 < e1) {
-        band_group(y, xc, cur, e0, e1, b.wlog, bb.nrows, lane);
+        band_group<GS>(y, xc, xn_c, col0, b.fresh_below, cur, e0, e1, b.wlog, bb.nrows, lane);
         for (uint32_t e = e0 + 64 * kBandUnroll; e < e1; e += 64 * kBandUnroll) {
           band_load(b.ent, e, e1, lane, cur);
-          band_group(y, xc, cur, e, e1, b.wlog, bb.nrows, lane);
+          band_group<GS>(y, xc, xn_c, col0, b.fresh_below, cur, e, e1, b.wlog, bb.nrows, lane);
         }
       }
     }
@@ -942,6 +952,29 @@ __global__ __launch_bounds__(kBlock) void k_band_fix(PassArgs a, BandFixArgs f) 
     apply_row<MODE>(a, nullptr, sr.x, load_row<MODE>(a, sr.x), y, g, sn);
   }
   if constexpr (MODE != kFinal64) finalize_gap(a, g, sn, red, &last);
+}
+
+// Gauss–Seidel sweep: after band k, the split rows whose pieces all lie in
+// bands 0..k get their sum and epilogue, so that later bands gather their new
+// values; one workgroup, rows [lo, hi) of the split table, the gap pair of
+// these rows stored at pairs[q].
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_band_split(PassArgs a, BandFixArgs f, int lo, int hi,
+                                                      int q, int first_launch) {
+  __shared__ double red[8];
+  if (a.respect_done && pass_cancelled(a.ctrl, a.pass_id, !first_launch)) return;
+  double g = 0.0, sn = 0.0;
+  for (int i = lo + static_cast<int>(threadIdx.x); i < hi; i += kBlock) {
+    const int4 sr = f.split[i];
+    double y = 0.0;
+    for (int p = sr.y; p < sr.z; ++p) y += f.piece[p];
+    apply_row<MODE>(a, nullptr, sr.x, load_row<MODE>(a, sr.x), y, g, sn);
+  }
+  block_sum2(g, sn, red);
+  if (threadIdx.x == 0) {
+    const_cast<double*>(f.pairs)[2 * q] = g;
+    const_cast<double*>(f.pairs)[2 * q + 1] = sn;
+  }
 }
 
 // Co-resident workgroups of a kernel: CUs × workgroups per CU, a multiple of 8.
@@ -1070,7 +1103,17 @@ psi_status launch_bands_r(psi_operator* op, const PassArgs& a, bool band_only, h
   b.B = op->band_B;
   b.wlog = op->band_wlog;
   b.n_blocks = op->band_nb;
+  b.pace = op->band_pace_ticks;
+  const bool gs = a.gs_sweep && MODE == kStep64;
+  b.x_new = gs ? static_cast<const void*>(a.z_new) : nullptr;
+  BandFixArgs f{};
+  f.split = op->band_split;
+  f.piece = op->band_piece;
+  f.pairs = op->band_pairs;
   const int wg_per_band = op->band_waves / NW;
+  // pairs: the band launches' workgroups first, then one per band for the split
+  // rows a Gauss–Seidel sweep finishes after that band
+  const int band_pairs = (op->band_nb + NW - 1) / NW;
   int n_pairs = 0;
   for (int k = 0; k < op->band_count; ++k) {
     b.first_block = k * op->band_waves;
@@ -1078,19 +1121,23 @@ psi_status launch_bands_r(psi_operator* op, const PassArgs& a, bool band_only, h
     const int grid = (nb + NW - 1) / NW;
     b.pair_base = k * wg_per_band;
     b.first_launch = k == 0;
-    b.pace = op->band_pace_ticks;
-    hipLaunchKernelGGL((k_band<MODE, R, NW>), dim3(grid), dim3(NW * 64), 0, st, a, b);
+    b.fresh_below = gs ? op->band_row0[k] : 0;
+    if (gs)
+      hipLaunchKernelGGL((k_band<MODE, R, NW, true>), dim3(grid), dim3(NW * 64), 0, st, a, b);
+    else
+      hipLaunchKernelGGL((k_band<MODE, R, NW, false>), dim3(grid), dim3(NW * 64), 0, st, a, b);
     n_pairs = b.pair_base + grid;
+    if (gs) {
+      const int lo = k ? op->band_split_end[k - 1] : 0, hi = op->band_split_end[k];
+      hipLaunchKernelGGL(k_band_split<MODE>, dim3(1), dim3(kBlock), 0, st, a, f, lo, hi,
+                         band_pairs + k, 0);
+    }
   }
   PSI_HIP_CHECK(hipGetLastError());
   if (band_only) return PSI_OK;
-  BandFixArgs f{};
-  f.split = op->band_split;
-  f.piece = op->band_piece;
-  f.pairs = op->band_pairs;
-  f.n_split = op->band_n_split;
-  f.n_pairs = MODE == kFinal64 ? 0 : n_pairs;
-  const int want = std::max((f.n_split + kBlock - 1) / kBlock, (n_pairs + 255) / 256);
+  f.n_split = gs ? 0 : op->band_n_split;
+  f.n_pairs = MODE == kFinal64 ? 0 : (gs ? band_pairs + op->band_count : n_pairs);
+  const int want = std::max((f.n_split + kBlock - 1) / kBlock, (f.n_pairs + 255) / 256);
   const int grid = std::max(1, std::min(kBandFixGrid, want));
   hipLaunchKernelGGL(k_band_fix<MODE>, dim3(grid), dim3(kBlock), 0, st, a, f);
   PSI_HIP_CHECK(hipGetLastError());
@@ -1119,8 +1166,8 @@ int resident_groups(K kernel, int threads) {
 
 int band_waves(int rows) {
   // every workgroup of a launch resident at once, up to the capacities' cap
-  const int waves = rows == 2048 ? resident_groups(k_band<kStep64, 2048, 4>, 4 * 64) * 4
-                                 : resident_groups(k_band<kStep64, 1024, 4>, 4 * 64) * 4;
+  const int waves = rows == 2048 ? resident_groups(k_band<kStep64, 2048, 4, false>, 4 * 64) * 4
+                                 : resident_groups(k_band<kStep64, 1024, 4, false>, 4 * 64) * 4;
   return std::min(kBandWaveCap, waves);
 }
 

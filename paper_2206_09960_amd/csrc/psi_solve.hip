@@ -673,6 +673,99 @@ psi_status solve(psi_operator* op, const psi_params* prm, const double* s0, doub
   return static_cast<psi_status>(status);
 }
 
+// Asynchronous local updates in a fixed order: block Gauss–Seidel sweeps of
+// s ← Aᵀs + c over the band layout.  The bands of a sweep run one after
+// another and each gathers the users of earlier bands from this sweep's new
+// values (split rows are finished after the band holding their last piece), so
+// later users update from fresher values, as in the local-update methods the
+// paper names as follow-ups (Sec. I).  The fixed point is that of
+// eq. (power_psi); the stopping test is eq. (condition) on the sweep's change
+// ‖s_sweep − s_prev‖₁ in tol_mode units; ψ = (Bᵀs + d)/N from the final s.
+psi_status solve_async(psi_operator* op, const psi_params* prm, const double* s0,
+                       double* psi_out, double* s_out, psi_info* info, hipStream_t st) {
+  PSI_REQUIRE(prm, "params must not be NULL");
+  PSI_REQUIRE(psi_out, "psi_out must not be NULL");
+  PSI_REQUIRE(prm->tol > 0.0 && std::isfinite(prm->tol), "tol must be finite and > 0");
+  PSI_REQUIRE(prm->max_iter > 0, "max_iter must be > 0");
+  PSI_REQUIRE(prm->tol_mode >= PSI_TOL_ABS_L1 && prm->tol_mode <= PSI_TOL_REL_L1,
+              "unknown tol_mode");
+  PSI_REQUIRE(prm->precision == PSI_PREC_FP64, "asynchronous sweeps run in PSI_PREC_FP64");
+  PSI_REQUIRE(prm->check_every >= 0, "check_every must be >= 0");
+  PSI_REQUIRE(op->n_graphs == 1, "asynchronous sweeps need a single-graph operator");
+  PSI_REQUIRE(prm->seg_form == 0 || prm->seg_form == PSI_SEG_BANDS,
+              "asynchronous sweeps run in the band layout (seg_form 0 or PSI_SEG_BANDS)");
+  const int tile = op->sched_items ? op->sched_items : kDefaultTileItems;
+  psi_status s = prepare_for(op, PSI_PREC_FP64, tile, 1, kSegBands, st, prm->band_col_log,
+                             prm->band_rows);
+  if (s != PSI_OK) return s;
+  const int64_t n = op->n;
+  EventPair tm;
+  PSI_HIP_CHECK(hipEventCreate(&tm.a));
+  PSI_HIP_CHECK(hipEventCreate(&tm.b));
+  PSI_HIP_CHECK(hipEventRecord(tm.a, st));
+  PassArgs base = base_args(op);
+  hipLaunchKernelGGL(k_init64, dim3(grid_for(n)), dim3(kBlock), 0, st, s0, op->c, op->invden, n,
+                     op->s_a, op->z_a);
+  hipLaunchKernelGGL(k_ctrl_set, dim3(1), dim3(1), 0, st, op->ctrl, prm->tol, prm->tol_mode,
+                     prm->max_iter, op->stats.b_norm);
+  auto make = [&](int i) {
+    PassArgs a = base;
+    const bool even = (i & 1) == 0;
+    a.x = even ? op->z_a : op->z_b;
+    a.s_old = even ? op->s_a : op->s_b;
+    a.s_new = even ? op->s_b : op->s_a;
+    a.z_new = even ? op->z_b : op->z_a;
+    a.count_iter = 1;
+    a.respect_done = 1;
+    a.gs_sweep = 1;
+    a.ctrl = op->ctrl;
+    return a;
+  };
+  IterResult res;
+  s = iterate(op, 1, 0, kStep64, make, prm->max_iter, prm->check_every, st, &res);
+  if (s != PSI_OK) return s;
+  const bool odd = res.iters & 1;
+  double* s_fin = odd ? op->s_b : op->s_a;
+  double* z_fin = odd ? op->z_b : op->z_a;
+  {
+    PassArgs a = base;
+    a.x = z_fin;
+    a.s_new = psi_out;
+    a.count_iter = 0;
+    a.respect_done = 0;
+    s = run_pass(op, 1, kFinal64, a, st);
+    if (s != PSI_OK) return s;
+  }
+  if (s_out) PSI_HIP_CHECK(hipMemcpyAsync(s_out, s_fin, 8 * size_t(n), hipMemcpyDeviceToDevice, st));
+  PSI_HIP_CHECK(hipEventRecord(tm.b, st));
+  PSI_HIP_CHECK(hipEventSynchronize(tm.b));
+  float ms = 0.f;
+  PSI_HIP_CHECK(hipEventElapsedTime(&ms, tm.a, tm.b));
+  s = check_waits(op, st);
+  if (s != PSI_OK) return s;
+  const double kap = op->stats.kappa;
+  psi_info inf{};
+  inf.status = res.status;
+  inf.iterations = res.iters;
+  inf.spmv_passes = res.iters + 1;
+  inf.used_s0 = s0 ? 1 : 0;
+  inf.col_segments = 1;
+  inf.tile_items = tile;
+  inf.seg_form = kSegBands;
+  inf.final_gap = res.gap;
+  inf.final_l1_step = res.l1;
+  inf.b_norm = op->stats.b_norm;
+  inf.kappa = kap;
+  inf.err_bound_s = kap < 1.0 ? kap / (1.0 - kap) * res.l1 : std::numeric_limits<double>::infinity();
+  inf.psi_gap_bound = n > 0 ? res.l1 * op->stats.b_norm / static_cast<double>(n) : 0.0;
+  inf.device_ms = ms;
+  if (info) *info = inf;
+  if (res.status == PSI_ENOTCONV) set_error("max_iter reached before the gap fell to tol");
+  else if (res.status == PSI_ESTAGNATED) set_error("the gap stopped decreasing above tol");
+  else if (res.status == PSI_ENUMERIC) set_error("NaN or Inf in the iteration");
+  return static_cast<psi_status>(res.status);
+}
+
 psi_status step(psi_operator* op, int precision, const double* s_in, double* s_out,
                 double* gap_out, int tile_items, int col_segments, int seg_form,
                 hipStream_t st) {

@@ -151,3 +151,45 @@ def test_band_degenerate_operators(gpu_lib):
     op = api.Operator(1, np.zeros(0, np.int32), np.zeros(0, np.int32), [2.0], [1.0])
     psi, info = op.solve(tol=1e-12, seg_form="bands")
     assert info["status"] == 0 and abs(psi.item() - 2.0 / 3.0) <= 1e-15
+
+
+@pytest.mark.parametrize("col_log,rows", [(17, 1024), (18, 2048)])
+def test_async_sweeps_match_the_oracle_in_fewer_sweeps(gpu_lib, special, col_log, rows):
+    """Block Gauss–Seidel sweeps over the bands: the oracle's Algorithm 2 result
+    at the same tolerance, in fewer sweeps than Power-ψ's passes, bitwise
+    repeatable, and a fixed point whose residual the oracle confirms."""
+    api = gpu_lib
+    g, A, B, c, d = special
+    r = oracle.power_psi(A, B, c, d, 1e-10)
+    op = api.Operator(g.n, g.follower, g.leader, g.lam, g.mu)
+    psi, s, info = op.solve_async(tol=1e-10, band_col_log=col_log, band_rows=rows,
+                                  return_s=True)
+    assert info["status"] == 0 and info["seg_form"] == api.SEG_FORMS["bands"], info
+    got = psi.cpu().numpy()
+    assert oracle.rel_l1(r["psi"], got) <= 1e-9
+    assert oracle.max_rel(r["psi"], got) <= 1e-6
+    s_np = s.cpu().numpy()
+    assert oracle.fixed_point_residual(A, c, s_np) <= 1e-10 * 1.5 + 1e-15 * np.abs(s_np).sum()
+    assert info["iterations"] < r["iterations"], (info["iterations"], r["iterations"])
+    psi2, info2 = op.solve_async(tol=1e-10, band_col_log=col_log, band_rows=rows)
+    assert torch.equal(psi2, psi) and info2["iterations"] == info["iterations"]
+
+
+def test_async_sweeps_several_bands_and_a_start(gpu_lib):
+    """Several bands per sweep (5·10⁶ users) against the C oracle, and a start
+    vector used as given."""
+    api = gpu_lib
+    g = synth.chung_lu(5_000_000, 4, 2.1, 17, sigma=2.0)
+    G = oc.Graph(g.n, g.follower, g.leader, g.lam, g.mu)
+    ref = G.power_psi(1e-8)
+    op = api.Operator(g.n, g.follower, g.leader, g.lam, g.mu)
+    psi, s, info = op.solve_async(tol=1e-8, band_col_log=17, band_rows=1024, return_s=True)
+    assert info["status"] == 0, info
+    assert op.band_info()["bands"] >= 2
+    assert oracle.rel_l1(ref["psi"], psi.cpu().numpy()) <= 1e-9
+    assert info["iterations"] < ref["iterations"]
+    psi_w, info_w = op.solve_async(tol=1e-8, s0=s)  # from the fixed point: one sweep
+    assert info_w["status"] == 0 and info_w["iterations"] <= 2 and info_w["used_s0"] == 1
+    assert oracle.rel_l1(ref["psi"], psi_w.cpu().numpy()) <= 1e-9
+    with pytest.raises(api.PsiError):
+        op.solve_async(tol=0.0)
