@@ -351,6 +351,8 @@ def run_single(args, name):
         "solves_timed": {p: (args.steps if p == head else cmp_k) for p in modes},
         "passes": {p: v["info"]["spmv_passes"] for p, v in modes.items()},
         "speedup_vs_plain_fp64": round(modes["fp64_weighted"]["ms"] / ms, 3),
+        "speedup_vs_plain_fp64_by_mode": {p: round(modes["fp64_weighted"]["ms"] / v["ms"], 3)
+                                          for p, v in modes.items()},
         "gteps_per_pass": {k: round(m / (v * 1e-3) / 1e9, 1) for k, v in pass_ms.items()
                            if not k.startswith(("band", "part"))},
         "pass_us": {k: round(v * 1e3, 2) for k, v in pass_ms.items()},
