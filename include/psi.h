@@ -304,6 +304,21 @@ psi_status psi_solve_anderson(psi_operator* op, const psi_params* prm, int32_t d
                               const double* s0, double* psi_out, double* s_out, psi_info* info,
                               void* workspace, size_t workspace_bytes, void* stream);
 
+/* psi_solve_anderson for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same solve, with its scratch (the ΔF/ΔG window, the
+ * previous f and g, the partial sums and the mixing state) in a fixed device
+ * array of 64 MiB inside the library instead of a caller workspace.  The
+ * limit: (2·depth + 2)·8 bytes per user plus 130 KB must fit 64 MiB (about
+ * 837,000 users at depth 4), else PSI_ENOSPACE with the sizes in the message.
+ * The array is per device and shared by every call on that device: calls that
+ * overlap on one GPU race (the solve blocks, so calls from one host thread do
+ * not overlap).  It calls no hipMalloc or hipFree; every other argument and
+ * result is as in psi_solve_anderson. */
+psi_status psi_solve_anderson_noalloc(psi_operator* op, const psi_params* prm, int32_t depth,
+                                      const double* s0, double* psi_out, double* s_out,
+                                      psi_info* info, void* stream);
+
 /* Per-origin newsfeed shares: Algorithm 1 (Power-NF, eq. fixpt_algo) for K
  * chosen origins at once.  For origin i, p_i solves p_i = A p_i + b_i
  * (eq. newsfeed: p_i^(j) is the share of user j's newsfeed that comes from

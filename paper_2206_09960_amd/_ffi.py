@@ -80,6 +80,8 @@ SIGNATURES = [
                                 vp, sz, vp]),
     ("psi_gather_probe", i32, [vp, i64, i32, vp, i64, vp, i32, i32, ctypes.POINTER(f64), vp]),
     ("psi_anderson_workspace_size", i32, [vp, i32, ctypes.POINTER(sz)]),
+    ("psi_solve_anderson_noalloc", i32, [vp, ctypes.POINTER(Params), i32, vp, vp, vp,
+                                     ctypes.POINTER(Info), vp]),
     ("psi_solve_anderson", i32, [vp, ctypes.POINTER(Params), i32, vp, vp, vp,
                                  ctypes.POINTER(Info), vp, sz, vp]),
     ("psi_solve_origins", i32, [vp, ctypes.POINTER(Params), i32, vp, vp, vp,

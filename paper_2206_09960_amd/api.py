@@ -391,6 +391,31 @@ class Operator:
             _check(st)
         return (psi, s, d) if return_s else (psi, d)
 
+    def solve_anderson_noalloc(self, tol: float = 1e-8, depth: int = 4, tol_mode: str = "abs_l1",
+                               max_iter: int = 10000, s0: torch.Tensor | None = None,
+                               check_every: int = 0, tile_items: int = 0, col_segments: int = 0,
+                               seg_form: str | int = 0, return_s: bool = False, stream=None,
+                               raise_on_status: bool = False):
+        """psi_solve_anderson_noalloc: psi_solve_anderson with its scratch in the
+        library's fixed device array (no workspace, no device allocation)."""
+        p = self._params(tol, tol_mode, max_iter, "fp64", check_every, tile_items, col_segments,
+                         seg_form=seg_form)
+        psi = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        s = torch.empty(self.n, dtype=torch.float64, device=self.device) if return_s else None
+        if s0 is not None:
+            s0 = _vec_in(s0, self.n, self.device, torch.float64, "s0")
+        info = _ffi.Info()
+        with torch.cuda.device(self.device):
+            st = self._lib.psi_solve_anderson_noalloc(self._h, ctypes.byref(p), depth, _ptr(s0),
+                                                      psi.data_ptr(), _ptr(s), ctypes.byref(info),
+                                                      _stream_handle(stream))
+        d = _ffi.struct_dict(info)
+        d["status_name"] = _ffi.STATUS_NAMES.get(st, str(st))
+        if st in (_ffi.PSI_EINVAL, _ffi.PSI_EDEVICE, _ffi.PSI_ENOSPACE) or (
+                raise_on_status and st != _ffi.PSI_OK):
+            _check(st)
+        return (psi, s, d) if return_s else (psi, d)
+
     def solve_origins(self, origins, tol: float = 1e-8, max_iter: int = 10000,
                       want_p: bool = True, check_every: int = 0, stream=None,
                       raise_on_status: bool = False):

@@ -28,6 +28,9 @@
 #include <cmath>
 #include <limits>
 
+#include <mutex>
+#include <string>
+
 #include "psi_internal.h"
 
 namespace psi {
@@ -317,6 +320,54 @@ __global__ void k_aa_ctrl(Ctrl* c, double tol, int tol_mode, int max_iter, doubl
 }
 
 }  // namespace
+
+// ---------------------------------------------------------------- no-allocation entry
+// Scratch of psi_solve_anderson_noalloc: a file-scope device array, so that a
+// caller that cannot allocate device memory can still run the Anderson
+// solve.  Each device the library runs on holds its own copy until the
+// process ends; its address on a device comes from hipGetSymbolAddress with
+// that device current (the array's name in host code is only a stand-in).
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[64] = {};
+}  // namespace
+
+// Device address of the scratch array on device `dev` (current), looked up
+// once per device.
+psi_status noalloc_scratch(int dev, void** ptr, size_t* bytes) {
+  PSI_REQUIRE(dev >= 0 && dev < 64, "device index out of range for the no-allocation scratch");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    PSI_HIP_CHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[dev] = p;
+  }
+  *ptr = g_scratch_ptr[dev];
+  *bytes = kNoAllocScratchBytes;
+  return PSI_OK;
+}
+
+psi_status solve_anderson_noalloc(psi_operator* op, const psi_params* prm, int depth,
+                                  const double* s0, double* psi_out, double* s_out,
+                                  psi_info* info, hipStream_t st) {
+  PSI_REQUIRE(depth >= 1 && depth <= kMaxDepth, "depth must be in [1, 8]");
+  const size_t need = aa_layout(op->n, depth, nullptr, nullptr);
+  if (need > kNoAllocScratchBytes) {
+    set_error("psi_solve_anderson_noalloc: " + std::to_string(op->n) + " users at depth " +
+              std::to_string(depth) + " need " + std::to_string(need) +
+              " bytes of scratch, more than its fixed " +
+              std::to_string(kNoAllocScratchBytes) + " (use psi_solve_anderson)");
+    return PSI_ENOSPACE;
+  }
+  void* ws = nullptr;
+  size_t bytes = 0;
+  psi_status s = noalloc_scratch(op->device, &ws, &bytes);
+  if (s != PSI_OK) return s;
+  return solve_anderson(op, prm, depth, s0, psi_out, s_out, info, ws, bytes, st);
+}
 
 psi_status anderson_workspace_size(const psi_operator* op, int depth, size_t* bytes) {
   PSI_REQUIRE(bytes, "bytes must not be NULL");

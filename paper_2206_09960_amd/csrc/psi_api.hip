@@ -334,6 +334,18 @@ psi_status psi_anderson_workspace_size(const psi_operator* op, int32_t depth, si
   PSI_GUARD_END
 }
 
+psi_status psi_solve_anderson_noalloc(psi_operator* op, const psi_params* prm, int32_t depth,
+                                      const double* s0, double* psi_out, double* s_out,
+                                      psi_info* info, void* stream) {
+  PSI_GUARD_BEGIN
+  PSI_REQUIRE(op, "op must not be NULL");
+  psi_status s = psi::check_device(op);
+  if (s != PSI_OK) return s;
+  return psi::solve_anderson_noalloc(op, prm, depth, s0, psi_out, s_out, info,
+                                     static_cast<hipStream_t>(stream));
+  PSI_GUARD_END
+}
+
 psi_status psi_solve_anderson(psi_operator* op, const psi_params* prm, int32_t depth,
                               const double* s0, double* psi_out, double* s_out, psi_info* info,
                               void* workspace, size_t workspace_bytes, void* stream) {

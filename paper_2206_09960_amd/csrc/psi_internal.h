@@ -562,6 +562,9 @@ psi_status autotune(psi_operator* op, int precision, int reps, int* tile_items, 
 psi_status gather_probe(const double* x, int64_t n_x, int S, const int32_t* idx, int64_t n_idx,
                         double* out, int grid, int reps, double* mean_ms, hipStream_t st);
 psi_status anderson_workspace_size(const psi_operator* op, int depth, size_t* bytes);
+psi_status solve_anderson_noalloc(psi_operator* op, const psi_params* prm, int depth,
+                                  const double* s0, double* psi_out, double* s_out,
+                                  psi_info* info, hipStream_t stream);
 psi_status solve_anderson(psi_operator* op, const psi_params* prm, int depth, const double* s0,
                           double* psi_out, double* s_out, psi_info* info, void* ws,
                           size_t ws_bytes, hipStream_t st);
