@@ -748,13 +748,21 @@ constexpr int kBandUnroll = 4;  // chunks in flight per wave
 // block (>= nrows for lanes past the column block's end).
 __device__ inline void band_chunk_add(double* y, unsigned rl, double v, int nrows, int lane) {
   const unsigned prev = __shfl_up(rl, 1, 64);
-  const bool head = lane == 0 || rl != prev;
+  // lanes past the column block's end (rl >= nrows) each start a run of their
+  // own, so they never lengthen the scan
+  const bool head = lane == 0 || rl != prev || rl >= static_cast<unsigned>(nrows);
   const unsigned long long hm = __ballot(head);
   const int h = 63 - __clzll(hm & (~0ull >> (63 - lane)));  // first lane of this lane's run
+  // the step with offset off matters only if some run holds more than off
+  // lanes: pos holds the lanes at position >= off in their run (a uniform
+  // mask), so the scan stops after the longest run (usually one or two steps)
+  unsigned long long pos = ~hm;
 #pragma unroll
   for (int off = 1; off < 64; off <<= 1) {
+    if (pos == 0ull) break;
     const double t = __shfl_up(v, off, 64);
     if (lane - off >= h) v += t;
+    pos &= pos << off;
   }
   const bool tail = lane == 63 || ((hm >> (lane + 1)) & 1ull);
   if (tail && rl < static_cast<unsigned>(nrows)) y[rl] += v;
