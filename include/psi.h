@@ -232,6 +232,30 @@ psi_status psi_solve(psi_operator* op, const psi_params* prm, const double* s0,
 psi_status psi_solve_async(psi_operator* op, const psi_params* prm, const double* s0,
                            double* psi_out, double* s_out, psi_info* info, void* stream);
 
+/* PageRank mode (Sec. III-D): with homogeneous activity λ_i = 1 − α and
+ * μ_i = α the ψ-score is the PageRank vector with damping α
+ * (eq. pagerank_power); users who follow nobody leak their mass.
+ *   op:     a single-graph operator built with lambda = 1 − alpha and
+ *           mu = alpha for every user (checked to a few ulps: PSI_EINVAL
+ *           otherwise);
+ *   alpha:  damping factor in (0, 1);
+ *   prm:    as in psi_solve;
+ *   power_method: 0 = plain Power-ψ from s_0 = c (psi_solve, tol on s);
+ *           1 = the iterates of the PageRank power method itself:
+ *           s_t = K·π_t with K = αN/(1 − α) solves s_t = Aᵀs_{t−1} + c from
+ *           s_0 = K/N (π_0 uniform), so tol bounds ‖π_t − π_{t−1}‖₁ (the
+ *           absolute and ‖B‖-scaled tolerances are applied to s as K·tol,
+ *           the relative one as given) and the result (Bᵀs_t + d)/N is
+ *           π_{t+1}; precision PSI_PREC_FP64 or PSI_PREC_FP64_WEIGHTED;
+ *   start:  device FP64 [N], caller-owned scratch that receives s_0
+ *           (power_method = 1 only; may be NULL otherwise);
+ *   pi_out: device FP64 [N], the PageRank vector;
+ *   info:   as in psi_solve.
+ * Blocks until done, like psi_solve. */
+psi_status psi_pagerank(psi_operator* op, double alpha, const psi_params* prm,
+                        int32_t power_method, double* start, double* pi_out, psi_info* info,
+                        void* stream);
+
 /* One Power-ψ step (eq. power_psi), enqueued only:
  *   s_out = Aᵀ s_in + c,  *gap_out (device FP64 scalar, may be NULL)
  *   = ‖s_out − s_in‖₁.  precision PSI_PREC_FP64 or PSI_PREC_FP64_WEIGHTED.

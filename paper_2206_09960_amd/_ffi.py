@@ -70,6 +70,8 @@ SIGNATURES = [
     ("psi_params_default", i32, [ctypes.POINTER(Params)]),
     ("psi_solve", i32, [vp, ctypes.POINTER(Params), vp, vp, vp, ctypes.POINTER(Info), vp]),
     ("psi_solve_async", i32, [vp, ctypes.POINTER(Params), vp, vp, vp, ctypes.POINTER(Info), vp]),
+    ("psi_pagerank", i32, [vp, f64, ctypes.POINTER(Params), i32, vp, vp, ctypes.POINTER(Info),
+                           vp]),
     ("psi_step", i32, [vp, i32, vp, vp, vp, i32, i32, i32, vp]),
     ("psi_final", i32, [vp, vp, vp, vp]),
     ("psi_debug_force_slot_timeout", i32, [vp, i32]),

@@ -615,25 +615,30 @@ class Model:
 def pagerank(n_users, follower, leader, alpha: float = 0.85, tol: float = 1e-9,
              power_method: bool = True, max_iter: int = 10000, op: Operator | None = None,
              stream=None):
-    """PageRank by the Power-ψ kernels (Sec. III-D: with homogeneous activity
-    λ = 1 − α, μ = α the ψ-score is the PageRank vector of eq. pagerank_power;
-    users who follow nobody leak their mass).
+    """psi_pagerank: PageRank by the Power-ψ kernels (Sec. III-D: with
+    homogeneous activity λ = 1 − α, μ = α the ψ-score is the PageRank vector of
+    eq. pagerank_power; users who follow nobody leak their mass).
 
     With ``power_method`` the iterates are those of the PageRank power method
-    itself: s_t = K·π_t with K = αN/(1 − α) solves s_t = Aᵀs_{t−1} + c from
-    s_0 = K/N·1, so the π-tolerance ‖π_t − π_{t−1}‖₁ ≤ ``tol`` is the
-    s-tolerance K·tol, and the returned (Bᵀs_t + d)/N is π_{t+1}.  Without it
-    the solve is plain Power-ψ from s_0 = c with s-tolerance ``tol``.
-    Returns (pi, info, op); pass ``op`` (built with that activity) to reuse it.
+    itself (the library starts from π_0 uniform and applies ``tol`` to
+    ‖π_t − π_{t−1}‖₁); without it the solve is plain Power-ψ from s_0 = c with
+    s-tolerance ``tol``.  Returns (pi, info, op); pass ``op`` (built with that
+    activity) to reuse it.
     """
     n = int(n_users)
     if op is None:
         op = Operator(n, follower, leader, np.full(n, 1.0 - alpha), np.full(n, alpha),
                       stream=stream)
-    if not power_method:
-        pi, info = op.solve(tol=tol, max_iter=max_iter, stream=stream)
-        return pi, info, op
-    k = alpha * n / (1.0 - alpha)
-    s0 = torch.full((n,), k / n, dtype=torch.float64, device=op.device)
-    pi, info = op.solve(tol=k * tol, max_iter=max_iter, s0=s0, no_fallback=True, stream=stream)
-    return pi, info, op
+    p = op._params(tol, "abs_l1", max_iter, "fp64", 0)
+    pi = torch.empty(op.n, dtype=torch.float64, device=op.device)
+    start = torch.empty(op.n, dtype=torch.float64, device=op.device) if power_method else None
+    info = _ffi.Info()
+    with torch.cuda.device(op.device):
+        st = op._lib.psi_pagerank(op._h, float(alpha), ctypes.byref(p), 1 if power_method else 0,
+                                  _ptr(start), _ptr(pi), ctypes.byref(info),
+                                  _stream_handle(stream))
+    d = _ffi.struct_dict(info)
+    d["status_name"] = _ffi.STATUS_NAMES.get(st, str(st))
+    if st in (_ffi.PSI_EINVAL, _ffi.PSI_EDEVICE, _ffi.PSI_ENOSPACE):
+        _check(st)
+    return pi, d, op

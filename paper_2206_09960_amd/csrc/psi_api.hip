@@ -204,6 +204,18 @@ psi_status psi_solve_async(psi_operator* op, const psi_params* prm, const double
   PSI_GUARD_END
 }
 
+psi_status psi_pagerank(psi_operator* op, double alpha, const psi_params* prm,
+                        int32_t power_method, double* start, double* pi_out, psi_info* info,
+                        void* stream) {
+  PSI_GUARD_BEGIN
+  PSI_REQUIRE(op, "op must not be NULL");
+  psi_status s = psi::check_device(op);
+  if (s != PSI_OK) return s;
+  return psi::pagerank(op, alpha, prm, power_method, start, pi_out, info,
+                       static_cast<hipStream_t>(stream));
+  PSI_GUARD_END
+}
+
 psi_status psi_step(psi_operator* op, int32_t precision, const double* s_in, double* s_out,
                     double* gap_out, int32_t tile_items, int32_t col_segments,
                     int32_t seg_form, void* stream) {

@@ -557,6 +557,8 @@ psi_status solve_async(psi_operator* op, const psi_params* prm, const double* s0
                        double* psi_out, double* s_out, psi_info* info, hipStream_t stream);
 psi_status solve(psi_operator* op, const psi_params* prm, const double* s0, double* psi_out,
                  double* s_out, psi_info* info, hipStream_t stream);
+psi_status pagerank(psi_operator* op, double alpha, const psi_params* prm, int power_method,
+                    double* start, double* pi_out, psi_info* info, hipStream_t stream);
 psi_status autotune(psi_operator* op, int precision, int reps, int* tile_items, int* col_segments,
                     int* seg_form, double* best_ms, hipStream_t stream);
 psi_status gather_probe(const double* x, int64_t n_x, int S, const int32_t* idx, int64_t n_idx,

@@ -859,8 +859,12 @@ __device__ inline void take_deferred_n(Ctrl* c, double* pairs, double* hist, int
 
 template <int MODE, int R, int NW, bool GS>
 __global__ __launch_bounds__(NW * 64) void k_band(PassArgs a, BandArgs b) {
+  // the row sums; the first 2·NW doubles also serve the workgroup's two
+  // reductions, before the sums are zeroed and after they are consumed, so
+  // that the LDS of the workgroup stays at NW·R doubles (five workgroups of
+  // four 1024-row waves fit one CU)
   __shared__ double ylds[NW][R];
-  __shared__ double red[2 * NW];
+  double* red = &ylds[0][0];
   using XT = typename std::conditional<MODE == kStep32, float, double>::type;
   if (b.first_launch && a.defer_gap && blockIdx.x == 0)
     take_deferred_n<NW>(a.ctrl, a.gap_prev, a.hist, a.count_iter, a.pass_id, red);
@@ -922,6 +926,7 @@ __global__ __launch_bounds__(NW * 64) void k_band(PassArgs a, BandArgs b) {
     }
   }
   if constexpr (MODE != kFinal64) {
+    __syncthreads();  // every wave has read its sums before red overwrites them
     block_sum2_n<NW>(g, sn, red);
     if (threadIdx.x == 0) {
       const int q = b.pair_base + static_cast<int>(blockIdx.x);
@@ -1161,21 +1166,26 @@ psi_status launch_bands_mode(psi_operator* op, const PassArgs& a, bool band_only
 
 // Co-resident workgroups of a kernel of `threads` threads per workgroup.
 template <class K>
-int resident_groups(K kernel, int threads) {
+int resident_groups(K kernel, int threads, int max_per_cu = 1 << 20) {
   int dev = 0, per_cu = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess)
     return 0;
-  return std::max(1, per_cu) * cus;
+  return std::min(max_per_cu, std::max(1, per_cu)) * cus;
 }
 
 }  // namespace
 
 int band_waves(int rows) {
-  // every workgroup of a launch resident at once, up to the capacities' cap
-  const int waves = rows == 2048 ? resident_groups(k_band<kStep64, 2048, 4, false>, 4 * 64) * 4
-                                 : resident_groups(k_band<kStep64, 1024, 4, false>, 4 * 64) * 4;
+  // every workgroup of a launch resident at once, at most four per CU, up to
+  // the capacities' cap.  Five 1024-row workgroups fit a CU's LDS, but the
+  // launch then runs slower per row at every pacing (40M users: 24.6 ms per
+  // pass at best against 18.6 ms with four): more waves in flight spread
+  // over more column blocks, and the gathers miss the L2 more often
+  const int waves = rows == 2048
+                        ? resident_groups(k_band<kStep64, 2048, 4, false>, 4 * 64, 4) * 4
+                        : resident_groups(k_band<kStep64, 1024, 4, false>, 4 * 64, 4) * 4;
   return std::min(kBandWaveCap, waves);
 }
 

@@ -12,6 +12,7 @@
 // gap of eq. eps_t), the correction e = Aᵀe + r is iterated in FP32 to a
 // relative tolerance and s ← s + e.  The fixed point of eq. (power_psi) is
 // unchanged; only the arithmetic of the correction is FP32.
+#include <cfloat>
 #include <algorithm>
 #include <cmath>
 #include <limits>
@@ -1001,7 +1002,7 @@ psi_status autotune(psi_operator* op, int precision, int reps, int* tile_items, 
     if (s != PSI_OK) return s;
     const double step_us = bms * 1e3 / (double(std::max(1, op->band_count)) * op->band_B);
     if (khz > 0 && op->band_B > 1) {
-      for (double f : {0.4, 0.5, 0.6, 0.7, 0.8}) {
+      for (double f : {0.4, 0.45, 0.5, 0.55, 0.6, 0.7}) {
         op->band_pace_ticks = static_cast<unsigned long long>(f * step_us * khz / 1e3);
         double ms = 0.0;
         s = time_one(tile_s1, 1, kSegBands, bw, br, &ms);
@@ -1025,6 +1026,71 @@ psi_status autotune(psi_operator* op, int precision, int reps, int* tile_items, 
   if (seg_form) *seg_form = best_form;
   if (best_ms) *best_ms = best;
   return PSI_OK;
+}
+
+namespace {
+
+// flag[0] = 1 if some user's activity is not the homogeneous λ = 1 − α,
+// μ = α of the PageRank mode (within a few units in the last place)
+__global__ void k_pr_check(const double* lam, const double* mu, int64_t n, double alpha,
+                           int* flag) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double tl = 1.0 - alpha;
+  const bool ok = fabs(lam[i] - tl) <= 8.0 * DBL_EPSILON * tl && fabs(mu[i] - alpha) <= 8.0 * DBL_EPSILON * alpha;
+  if (!ok) *flag = 1;
+}
+
+__global__ void k_fill_f64(double* x, int64_t n, double v) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = v;
+}
+
+__global__ void k_zero_i32(int* x) { *x = 0; }
+
+}  // namespace
+
+// PageRank mode (Sec. III-D): with λ_i = 1 − α and μ_i = α for every user the
+// ψ-score is the PageRank vector of damping α (eq. pagerank_power).  In the
+// power-method form the iterates are the power method's own: s_t = K·π_t with
+// K = αN/(1 − α) satisfies s_t = Aᵀs_{t−1} + c from s_0 = K/N (π_0 uniform),
+// so a step of ‖π_t − π_{t−1}‖₁ is one of ‖s_t − s_{t−1}‖₁ / K: the absolute
+// (and ‖B‖-scaled) tolerances scale by K, the relative one does not; the
+// returned (Bᵀs_t + d)/N is π_{t+1}.
+psi_status pagerank(psi_operator* op, double alpha, const psi_params* prm, int power_method,
+                    double* start, double* pi_out, psi_info* info, hipStream_t st) {
+  PSI_REQUIRE(prm, "prm must not be NULL");
+  PSI_REQUIRE(std::isfinite(alpha) && alpha > 0.0 && alpha < 1.0, "alpha must lie in (0, 1)");
+  PSI_REQUIRE(op->n_graphs == 1, "the PageRank mode is for single-graph operators");
+  PSI_REQUIRE(!power_method || start, "the power-method form needs a start vector buffer");
+  PSI_REQUIRE(!power_method || prm->precision == PSI_PREC_FP64 ||
+                  prm->precision == PSI_PREC_FP64_WEIGHTED,
+              "the power-method form iterates in FP64");
+  const int64_t n = op->n;
+  if (n > 0) {
+    int* flag = reinterpret_cast<int*>(op->scal + 7);
+    int bad = 0;
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(1), 0, st, flag);
+    hipLaunchKernelGGL(k_pr_check, dim3(grid_for(n)), dim3(kBlock), 0, st, op->lam, op->mu, n,
+                       alpha, flag);
+    PSI_HIP_CHECK(hipGetLastError());
+    PSI_HIP_CHECK(hipMemcpyAsync(&bad, flag, sizeof(bad), hipMemcpyDeviceToHost, st));
+    PSI_HIP_CHECK(hipStreamSynchronize(st));
+    if (bad) {
+      set_error("the PageRank mode needs lambda = 1 - alpha and mu = alpha for every user");
+      return PSI_EINVAL;
+    }
+  }
+  if (!power_method) return solve(op, prm, nullptr, pi_out, nullptr, info, st);
+  psi_params p = *prm;
+  const double K = alpha * static_cast<double>(n) / (1.0 - alpha);
+  if (p.tol_mode != PSI_TOL_REL_L1) p.tol *= K;
+  p.flags |= PSI_NO_FALLBACK;  // the start is the power method's, kept as given
+  if (n > 0)
+    hipLaunchKernelGGL(k_fill_f64, dim3(grid_for(n)), dim3(kBlock), 0, st, start, n,
+                       K / static_cast<double>(n));
+  PSI_HIP_CHECK(hipGetLastError());
+  return solve(op, &p, start, pi_out, nullptr, info, st);
 }
 
 }  // namespace psi

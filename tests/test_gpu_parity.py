@@ -588,6 +588,43 @@ def test_pagerank_mode_matches_the_power_method(gpu_lib, power_method):
         assert oracle.rel_l1(exact, pi) <= 1e-8
 
 
+def test_pagerank_entry_point_checks_the_activity_and_maps_the_tolerance(gpu_lib):
+    """psi_pagerank refuses an operator whose activity is not λ = 1 − α,
+    μ = α; in the power-method form the relative tolerance is scale-free, so
+    it stops at the oracle's step for the same relative π-tolerance."""
+    import ctypes
+    from paper_2206_09960_amd import _ffi
+    api = gpu_lib
+    g = synth.chung_lu(20_000, 8, 2.2, 58)
+    op = api.Operator(g.n, g.follower, g.leader, g.lam, g.mu)  # heterogeneous activity
+    with pytest.raises(api.PsiError, match="lambda = 1 - alpha"):
+        api.pagerank(g.n, g.follower, g.leader, alpha=0.85, op=op)
+    W = oracle.transition_matrix(g.n, g.follower, g.leader)
+    op = api.Operator(g.n, g.follower, g.leader, np.full(g.n, 0.15), np.full(g.n, 0.85))
+    p = op._params(1e-9, "rel_l1", 10_000, "fp64", 0)
+    pi = torch.empty(g.n, dtype=torch.float64, device="cuda")
+    start = torch.empty(g.n, dtype=torch.float64, device="cuda")
+    info = _ffi.Info()
+    st = op._lib.psi_pagerank(op._h, 0.85, ctypes.byref(p), 1, start.data_ptr(), pi.data_ptr(),
+                              ctypes.byref(info), None)
+    assert st == 0
+    # s_0 = K/N with K = αN/(1 − α)
+    assert torch.all(start == 0.85 * g.n / (1.0 - 0.85) / g.n)
+    # the oracle's relative step test: ‖π_t − π_{t−1}‖₁ / ‖π_t‖₁ ≤ tol
+    x = np.full(g.n, 1.0 / g.n)
+    t = 0
+    while True:
+        x_new = 0.85 * (W.T @ x) + 0.15 / g.n
+        t += 1
+        if np.abs(x_new - x).sum() / np.abs(x_new).sum() <= 1e-9:
+            break
+        x = x_new
+    assert abs(info.iterations - t) <= 1
+    assert oracle.rel_l1(x_new, pi.cpu().numpy()) <= 1e-8
+    with pytest.raises(api.PsiError, match="alpha"):
+        api.pagerank(g.n, g.follower, g.leader, alpha=1.0, op=op)
+
+
 def test_exact_fixed_point_equals_the_closed_form(gpu_lib):
     """The reference ψ of the experiments (FP64 map run until its step stops
     shrinking) against eq. (ultimsol) solved exactly by the oracle."""
