@@ -123,6 +123,12 @@ typedef struct psi_params {
                          /* 0 = tuned, else 18                                    */
     int32_t band_rows;   /* PSI_SEG_BANDS: rows per row block, 1024 or 2048;        */
                          /* 0 = tuned, else 2048                                  */
+    int32_t batch_tile;  /* scenario batches: scenarios per tile, 1..64;          */
+                         /* 0 = tuned, else 64                                    */
+    int32_t batch_items; /* scenario batches: merge-path items per wave tile,     */
+                         /* 128..8192; 0 = tuned, else 256                        */
+    int32_t hub_chunk;   /* scenario batches: edges per chunk of a long row,      */
+                         /* 512..8192; 0 = tuned, else 1024                       */
 } psi_params;
 
 typedef struct psi_info {
@@ -142,6 +148,8 @@ typedef struct psi_info {
     double psi_gap_bound;     /* ‖s_t − s_{t−1}‖₁·‖B‖/N ≥ ‖ψ_t − ψ_{t−1}‖₁    */
     double device_ms;         /* time from first to last kernel of the solve  */
     int32_t seg_form;         /* PSI_SEG_* of the passes (0: fused, S = 1)    */
+    int32_t batch_tile;       /* scenario batches: scenarios per tile         */
+    int32_t hub_chunk;        /* scenario batches: edges per long-row chunk   */
 } psi_info;
 
 /* Library version string. */

@@ -63,6 +63,39 @@ psi_status psi_autotune(psi_operator* op, int32_t precision, int32_t reps, int32
                         int32_t* col_segments, int32_t* seg_form, double* best_ms,
                         void* stream);
 
+/* Scenario-batch autotuner (the multi-vector product over K activity
+ * scenarios of psi_solve_batched).  Times the pass that dominates a batched
+ * solve in `precision` (the FP64 step for PSI_PREC_FP64, the FP32 correction
+ * step for PSI_PREC_MIXED, each with its gap kernels) over all K scenarios,
+ * i.e. ceil(K / batch_tile) tile passes, on the operator's own rates in every
+ * scenario, and keeps the fastest schedule in the operator for later
+ * psi_solve_batched calls in that precision whose psi_params leave
+ * batch_tile / batch_items / hub_chunk at 0.  Searched by coordinates:
+ * scenarios per tile (8, 16, 32, 64 and K, at most 64), then merge-path items
+ * per wave tile (128, 256, 512, 1024), then edges per long-row chunk (512,
+ * 1024, 2048, 4096).  workspace: device, at least psi_batched_workspace_size
+ * bytes for `precision` (overwritten).  reps = 0 picks about 20 ms of passes
+ * per candidate (at least 3).  Writes the choice and the time of one pass
+ * over all K scenarios (ms) to the host pointers (each may be NULL).
+ * Single-graph operators; blocks. */
+psi_status psi_autotune_batched(psi_operator* op, int32_t precision, int32_t n_scenarios,
+                                void* workspace, size_t workspace_bytes, int32_t reps,
+                                int32_t* batch_tile, int32_t* batch_items, int32_t* hub_chunk,
+                                double* best_ms, void* stream);
+
+/* Graph-batch autotuner (a multi-graph operator of psi_solve_batched).
+ * Times the block-diagonal step pass that dominates a graph batch in
+ * `precision` (FP64 step, or the FP32 correction step for PSI_PREC_MIXED),
+ * with its per-graph gap kernel, for tile_items 1024, 2048, 3072, 4096 at
+ * col_segments 1, 2, 4, 8 (at most 4 for PSI_PREC_MIXED) in the tiled form
+ * and, for col_segments > 1, the sliced form; keeps the fastest in the
+ * operator for later graph batches in that precision whose psi_params leave
+ * tile_items / col_segments / seg_form at 0.  reps as in psi_autotune.
+ * Overwrites the operator's solve state; blocks. */
+psi_status psi_autotune_graphs(psi_operator* op, int32_t precision, int32_t reps,
+                               int32_t* tile_items, int32_t* col_segments, int32_t* seg_form,
+                               double* best_ms, void* stream);
+
 /* The band layout built on the operator (by a call that used PSI_SEG_BANDS or
  * by psi_autotune), for reports: column blocks of 2^col_log users (*col_blocks
  * of them), *row_blocks row blocks of at most *rows rows, run as *bands

@@ -41,7 +41,8 @@ class Params(ctypes.Structure):
     _fields_ = [("tol", f64), ("tol_mode", i32), ("max_iter", i32), ("precision", i32),
                 ("check_every", i32), ("flags", u32), ("tile_items", i32), ("col_segments", i32),
                 ("seg_form", i32),
-                ("inner_tol", f64), ("band_col_log", i32), ("band_rows", i32)]
+                ("inner_tol", f64), ("band_col_log", i32), ("band_rows", i32),
+                ("batch_tile", i32), ("batch_items", i32), ("hub_chunk", i32)]
 
 
 class Info(ctypes.Structure):
@@ -49,7 +50,8 @@ class Info(ctypes.Structure):
                 ("refinements", i32), ("used_s0", i32), ("col_segments", i32),
                 ("tile_items", i32), ("final_gap", f64),
                 ("final_l1_step", f64), ("b_norm", f64), ("kappa", f64), ("err_bound_s", f64),
-                ("psi_gap_bound", f64), ("device_ms", f64), ("seg_form", i32)]
+                ("psi_gap_bound", f64), ("device_ms", f64), ("seg_form", i32),
+                ("batch_tile", i32), ("hub_chunk", i32)]
 
 
 def struct_dict(s: ctypes.Structure) -> dict:
@@ -77,6 +79,11 @@ SIGNATURES = [
     ("psi_debug_force_slot_timeout", i32, [vp, i32]),
     ("psi_operator_band_info", i32, [vp] + [ctypes.POINTER(i32)] * 6),
     ("psi_pass_time", i32, [vp, i32, i32, i32, i32, i32, ctypes.POINTER(f64), vp]),
+    ("psi_autotune_batched", i32, [vp, i32, i32, vp, sz, i32, ctypes.POINTER(i32),
+                                   ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(f64),
+                                   vp]),
+    ("psi_autotune_graphs", i32, [vp, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                  ctypes.POINTER(i32), ctypes.POINTER(f64), vp]),
     ("psi_batched_workspace_size", i32, [vp, i32, i32, ctypes.POINTER(sz)]),
     ("psi_solve_batched", i32, [vp, ctypes.POINTER(Params), i32, vp, vp, vp, ctypes.POINTER(Info),
                                 vp, sz, vp]),

@@ -328,18 +328,65 @@ class Operator:
         p.inner_tol = inner_tol
         return p
 
+    def batched_workspace(self, n_scenarios: int, precision: str = "fp64") -> torch.Tensor:
+        """A device workspace of psi_batched_workspace_size bytes (kept and
+        reused while large enough)."""
+        prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        nbytes = ctypes.c_size_t()
+        _check(self._lib.psi_batched_workspace_size(self._h, int(n_scenarios), prec,
+                                                    ctypes.byref(nbytes)))
+        ws = getattr(self, "_batch_ws", None)
+        if ws is None or ws.numel() < nbytes.value:
+            ws = None
+            self._batch_ws = None
+            ws = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+            self._batch_ws = ws
+        return ws
+
+    def autotune_batched(self, n_scenarios: int, precision: str = "fp64", reps: int = 0,
+                         stream=None) -> dict:
+        """psi_autotune_batched: the fastest scenarios per tile / items per wave
+        tile / hub chunk for K = n_scenarios, kept for later batched solves."""
+        prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        ws = self.batched_workspace(n_scenarios, precision)
+        bt, bi, bc, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        with torch.cuda.device(self.device):
+            _check(self._lib.psi_autotune_batched(self._h, prec, int(n_scenarios), ws.data_ptr(),
+                                                  ws.numel(), reps, ctypes.byref(bt),
+                                                  ctypes.byref(bi), ctypes.byref(bc),
+                                                  ctypes.byref(ms), _stream_handle(stream)))
+        return dict(batch_tile=bt.value, batch_items=bi.value, hub_chunk=bc.value,
+                    pass_ms=ms.value)
+
+    def autotune_graphs(self, precision: str = "fp64", reps: int = 0, stream=None) -> dict:
+        """psi_autotune_graphs: the fastest tile_items / col_segments / seg_form
+        of a graph batch, kept for later graph solves."""
+        prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        t, sg, fm, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        with torch.cuda.device(self.device):
+            _check(self._lib.psi_autotune_graphs(self._h, prec, reps, ctypes.byref(t),
+                                                 ctypes.byref(sg), ctypes.byref(fm),
+                                                 ctypes.byref(ms), _stream_handle(stream)))
+        return dict(tile_items=t.value, col_segments=sg.value, seg_form=SEG_FORM_NAMES[fm.value],
+                    pass_ms=ms.value)
+
     def solve_batched(self, lam: torch.Tensor, mu: torch.Tensor, tol: float = 1e-8,
                       max_iter: int = 10000, check_every: int = 0, precision: str = "fp64",
-                      inner_tol: float = 0.0, stream=None, raise_on_status: bool = False):
+                      inner_tol: float = 0.0, batch_tile: int = 0, batch_items: int = 0,
+                      hub_chunk: int = 0, stream=None, raise_on_status: bool = False):
         """psi_solve_batched, scenario mode: lam, mu [N × K] (one column per
         scenario); precision "fp64" or "mixed" (FP32 corrections refined in
-        FP64); returns (psi [N × K], list of K info dicts)."""
+        FP64); batch_tile / batch_items / hub_chunk pick the schedule (0 =
+        tuned or default); returns (psi [N × K], list of K info dicts)."""
         lam = lam.to(self.device, torch.float64).contiguous()
         mu = mu.to(self.device, torch.float64).contiguous()
         if lam.dim() != 2 or lam.shape != mu.shape or lam.shape[0] != self.n:
             raise ValueError("lam and mu must both be [n_users, n_scenarios]")
         k = int(lam.shape[1])
         p = self._params(tol, "abs_l1", max_iter, precision, check_every, inner_tol=inner_tol)
+        p.batch_tile = batch_tile
+        p.batch_items = batch_items
+        p.hub_chunk = hub_chunk
         nbytes = ctypes.c_size_t()
         _check(self._lib.psi_batched_workspace_size(self._h, k, p.precision, ctypes.byref(nbytes)))
         ws = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
@@ -450,15 +497,17 @@ class Operator:
 
     def solve_graphs(self, tol: float = 1e-8, max_iter: int = 10000, check_every: int = 0,
                      tile_items: int = 0, col_segments: int = 0, seg_form: str | int = 0,
+                     precision: str = "fp64", inner_tol: float = 0.0,
                      stream=None, raise_on_status: bool = False):
         """psi_solve_batched, graph mode: every graph of a block-diagonal
         operator solved to its own tolerance; returns (psi [N], G info dicts).
         col_segments > 1 runs each pass as a column-segmented partial pass
-        (seg_form "tiles" or "slices") and a combine."""
+        (seg_form "tiles" or "slices") and a combine; precision "fp64" or
+        "mixed" (FP32 corrections refined in FP64, per graph)."""
         if self.n_graphs < 2:
             raise ValueError("graph mode needs an operator built with node_offsets")
-        p = self._params(tol, "abs_l1", max_iter, "fp64", check_every, tile_items, col_segments,
-                         seg_form=seg_form)
+        p = self._params(tol, "abs_l1", max_iter, precision, check_every, tile_items,
+                         col_segments, inner_tol=inner_tol, seg_form=seg_form)
         psi = torch.empty(self.n, dtype=torch.float64, device=self.device)
         infos = (_ffi.Info * self.n_graphs)()
         with torch.cuda.device(self.device):

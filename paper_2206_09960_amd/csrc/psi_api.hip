@@ -299,6 +299,45 @@ psi_status psi_autotune(psi_operator* op, int32_t precision, int32_t reps, int32
   PSI_GUARD_END
 }
 
+psi_status psi_autotune_batched(psi_operator* op, int32_t precision, int32_t n_scenarios,
+                                void* workspace, size_t workspace_bytes, int32_t reps,
+                                int32_t* batch_tile, int32_t* batch_items, int32_t* hub_chunk,
+                                double* best_ms, void* stream) {
+  PSI_GUARD_BEGIN
+  PSI_REQUIRE(op, "op must not be NULL");
+  psi_status st = psi::check_device(op);
+  if (st != PSI_OK) return st;
+  int bt = 0, bi = 0, bc = 0;
+  st = psi::autotune_batched(op, precision, n_scenarios, workspace, workspace_bytes, reps, &bt,
+                             &bi, &bc, best_ms, static_cast<hipStream_t>(stream));
+  if (st == PSI_OK) {
+    if (batch_tile) *batch_tile = bt;
+    if (batch_items) *batch_items = bi;
+    if (hub_chunk) *hub_chunk = bc;
+  }
+  return st;
+  PSI_GUARD_END
+}
+
+psi_status psi_autotune_graphs(psi_operator* op, int32_t precision, int32_t reps,
+                               int32_t* tile_items, int32_t* col_segments, int32_t* seg_form,
+                               double* best_ms, void* stream) {
+  PSI_GUARD_BEGIN
+  PSI_REQUIRE(op, "op must not be NULL");
+  psi_status st = psi::check_device(op);
+  if (st != PSI_OK) return st;
+  int t = 0, sg = 0, fm = 0;
+  st = psi::autotune_graphs(op, precision, reps, &t, &sg, &fm, best_ms,
+                            static_cast<hipStream_t>(stream));
+  if (st == PSI_OK) {
+    if (tile_items) *tile_items = t;
+    if (col_segments) *col_segments = sg;
+    if (seg_form) *seg_form = fm;
+  }
+  return st;
+  PSI_GUARD_END
+}
+
 psi_status psi_batched_workspace_size(const psi_operator* op, int32_t n_scenarios,
                                       int32_t precision, size_t* bytes) {
   PSI_GUARD_BEGIN

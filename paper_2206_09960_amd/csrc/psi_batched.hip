@@ -41,6 +41,7 @@
 // summed in two fixed-order levels.  Every sum has a fixed order, so batched
 // solves are bitwise repeatable.
 #include <algorithm>
+#include <cstdint>
 #include <cmath>
 #include <limits>
 #include <vector>
@@ -51,10 +52,13 @@ namespace psi {
 
 namespace {
 
-constexpr int kWaveItems = 256;    // merge-path items per wave tile
+constexpr int kWaveItems = 256;    // merge-path items per wave tile (default)
+constexpr int kMinWaveItems = 128; // smallest wave tile the workspace holds
 constexpr int kHubEdges = 256;     // rows longer than this are chunked
-constexpr int kChunkEdges = 1024;  // edges per hub chunk
-constexpr int kMaxK = 64;          // scenarios per batch tile (one per lane)
+constexpr int kChunkEdges = 1024;  // edges per hub chunk (default)
+constexpr int kMinChunkEdges = 512;   // smallest hub chunk the workspace holds
+constexpr int kMaxChunkEdges = 8192;
+constexpr int kMaxK = 64;          // scenarios per batch tile (at most one per lane)
 constexpr int kHubFinGrid = 1024;  // largest grid of the hub-finishing kernel
 constexpr int kGapParts = 64;      // first-level partials of a pass's gaps
 constexpr int kGraphGapBlock = 1024;  // threads summing one graph's |Δ|
@@ -104,9 +108,9 @@ size_t batch_layout(int64_t n, int64_t m, BatchWs* w, char* base, bool mixed) {
     off += align_up(std::max<size_t>(bytes, 1));
     return p;
   };
-  const int64_t n_wtiles = (n + m) / kWaveItems + 2;
+  const int64_t n_wtiles = (n + m) / kMinWaveItems + 2;
   const int64_t max_hubs = m / (kHubEdges + 1) + 1;
-  const int64_t max_chunks = m / kChunkEdges + max_hubs + 1;
+  const int64_t max_chunks = m / kMinChunkEdges + max_hubs + 1;
   const size_t nk = 8 * size_t(n) * kMaxK;
   BatchWs t{};
   t.lam = (double*)take(nk);
@@ -162,6 +166,16 @@ __global__ void k_bprep_act(const double* lam_in, const double* mu_in, int64_t n
     atomicOr(&ctrl->err_flags, kErrActivity);
   lam[t] = l;
   mu[t] = m;
+}
+
+// λ, μ of the operator's own users in every scenario of a tile (the timing
+// runs of the batch autotuner: a pass's work does not depend on the rates).
+__global__ void k_bprep_rep(const double* lam_op, const double* mu_op, int64_t n, int Kc,
+                            double* lam, double* mu) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= n * Kc) return;
+  lam[t] = lam_op[t / Kc];
+  mu[t] = mu_op[t / Kc];
 }
 
 // den_j^k = Σ_{ℓ∈L(j)} (λ_ℓ^k + μ_ℓ^k) in ascending ℓ over CSR(A), one wave
@@ -253,26 +267,27 @@ __global__ void k_hub_flags(const int* row_ptr, int64_t n, uint32_t* flags) {
   flags[i] = (i < n && row_ptr[i + 1] - row_ptr[i] > kHubEdges) ? 1u : 0u;
 }
 
-__global__ void k_hub_list(const int* row_ptr, int64_t n, const uint32_t* pos, int* hub_rows,
-                           uint32_t* nchunks) {
+__global__ void k_hub_list(const int* row_ptr, int64_t n, const uint32_t* pos, int chunk_edges,
+                           int* hub_rows, uint32_t* nchunks) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int len = row_ptr[i + 1] - row_ptr[i];
   if (len > kHubEdges) {
     hub_rows[pos[i]] = static_cast<int>(i);
-    nchunks[pos[i]] = static_cast<uint32_t>((len + kChunkEdges - 1) / kChunkEdges);
+    nchunks[pos[i]] = static_cast<uint32_t>((len + chunk_edges - 1) / chunk_edges);
   }
 }
 
 __global__ void k_chunk_table(const int* row_ptr, const int* hub_rows, const uint32_t* chunk0,
-                              int n_hubs, int* chunk_row, int* chunk_e0, int* hub_chunk0) {
+                              int n_hubs, int chunk_edges, int* chunk_row, int* chunk_e0,
+                              int* hub_chunk0) {
   const int h = blockIdx.x * blockDim.x + threadIdx.x;
   if (h >= n_hubs) return;
   const int r = hub_rows[h];
   const int e0 = row_ptr[r], e1 = row_ptr[r + 1];
   int c = static_cast<int>(chunk0[h]);
   hub_chunk0[h] = c;
-  for (int e = e0; e < e1; e += kChunkEdges, ++c) {
+  for (int e = e0; e < e1; e += chunk_edges, ++c) {
     chunk_row[c] = r;
     chunk_e0[c] = e;
   }
@@ -292,6 +307,7 @@ struct BArgs {
   const int* chunk_row;
   const int* chunk_e0;
   int n_chunks;
+  int chunk_edges;     // edges per hub chunk
   const double* z;     // gathered [N × Kc]
   const double* s_old;
   double* s_new;
@@ -414,23 +430,52 @@ __device__ inline double edge_term(const BArgs& a, int j, int k, int org, double
   }
 }
 
+// Lanes of a wave in G groups of Kc (G·Kc ≤ 64): lane g·Kc + k works on
+// scenario k of group g's row (or hub, or chunk); lanes past G·Kc shadow
+// the last lane of the last group and store nothing.
+template <int G>
+struct LaneGroup {
+  int g, k;
+  bool active;
+  __device__ LaneGroup(int lane, int Kc) {
+    const int q = min(lane, G * Kc - 1);
+    g = G == 1 ? 0 : q / Kc;
+    k = q - g * Kc;
+    active = lane < G * Kc;
+  }
+};
+
+// Sum of the G groups' values of scenario `lane` (lane < Kc) over the four
+// waves' rows of red, in wave then group order.
+template <int G>
+__device__ inline double sum_groups(double (*red)[64], int lane, int Kc) {
+  double t = 0.0;
+#pragma unroll
+  for (int w = 0; w < kBlock / 64; ++w)
+#pragma unroll
+    for (int g = 0; g < G; ++g) t += red[w][g * Kc + lane];
+  return t;
+}
+
 // Rows of at most kHubEdges followers: waves walk the wave tiles grid-stride.
 // A wave reads the row ends of up to 63 rows in one load and, when those
 // rows span at most kStage edges (no hub among them), stages their column
-// indices in its slice of LDS; a row's epilogue inputs are loaded before its
-// gathers, and up to 16 gathers are in flight.  A row's edges are added one
-// by one in order.
-template <int BM>
+// indices in its slice of LDS; the G lane groups take consecutive rows; a
+// row's epilogue inputs are loaded before its gathers, and up to 16 gathers
+// per lane are in flight.  A row's edges are added one by one in order, so
+// a row's sum does not depend on G.
+template <int BM, int G>
 __global__ __launch_bounds__(kBlock) void k_spmm_rows(BArgs a) {
   constexpr bool FINAL = BM == kScenFinal;
-  constexpr int kB = 16;       // gathers in flight per wave
+  constexpr int kB = 16;       // gathers in flight per lane
   constexpr int kStage = 256;  // staged column indices per wave
-  __shared__ double red[kBlock / 64][kMaxK];
+  __shared__ double red[kBlock / 64][64];
   __shared__ int s_col[kBlock / 64][kStage];
   if (!FINAL && a.ctrl->c.done) return;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int k = lane < a.Kc ? lane : a.Kc - 1;  // idle lanes shadow the last scenario
+  const LaneGroup<G> lg(lane, a.Kc);
+  const int k = lg.k;
   const bool frozen = !FINAL && a.ctrl->kdone[k];
   const int org = BM == kOrig ? a.origin[k] : -1;
   const double lo = BM == kOrig ? a.lam[org] : 0.0;
@@ -470,15 +515,26 @@ __global__ __launch_bounds__(kBlock) void k_spmm_rows(BArgs a) {
         }
         return y;
       };
-      for (int i = 0; i < nb; ++i) {
-        const int e0 = __builtin_amdgcn_readlane(rp, i);
-        const int len = __builtin_amdgcn_readlane(rp, i + 1) - e0;
-        if (len > kHubEdges) continue;  // finished by the hub kernels
-        const int r = rb + i;
-        const BRow in = bload<BM>(a, r, k, frozen);
-        const double y = staged ? row_sum(len, [&](int q) { return cw[e0 - E0 + q]; })
-                                : row_sum(len, [&](int q) { return a.col[e0 + q]; });
-        if (lane < a.Kc) bapply<BM>(a, r, k, in, y, frozen, gap);
+      for (int i0 = 0; i0 < nb; i0 += G) {
+        int i, e0, len;
+        if constexpr (G == 1) {  // one row per wave: its bounds are uniform
+          i = i0;
+          e0 = __builtin_amdgcn_readlane(rp, i0);
+          len = __builtin_amdgcn_readlane(rp, i0 + 1) - e0;
+          if (len > kHubEdges) continue;  // finished by the hub kernels
+        } else {
+          i = min(i0 + lg.g, nb);  // i == nb: past the block, an empty row
+          e0 = __shfl(rp, i, 64);
+          len = __shfl(rp, min(i + 1, nb), 64) - e0;
+          if (len > kHubEdges) len = -1;  // finished by the hub kernels
+        }
+        const bool mine = i < nb && len >= 0;
+        const int r = rb + min(i, nb - 1);
+        const BRow in = mine ? bload<BM>(a, r, k, frozen) : BRow{0.0, 0.0, 0.0, 0.0};
+        const int n_e = max(len, 0);
+        const double y = staged ? row_sum(n_e, [&](int q) { return cw[e0 - E0 + q]; })
+                                : row_sum(n_e, [&](int q) { return a.col[e0 + q]; });
+        if (lg.active && mine) bapply<BM>(a, r, k, in, y, frozen, gap);
       }
     }
   }
@@ -486,26 +542,29 @@ __global__ __launch_bounds__(kBlock) void k_spmm_rows(BArgs a) {
     red[wave][lane] = gap;
     __syncthreads();
     if (wave == 0 && lane < a.Kc)
-      a.gap_blk[int64_t(blockIdx.x) * a.Kc + lane] =
-          ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+      a.gap_blk[int64_t(blockIdx.x) * a.Kc + lane] = sum_groups<G>(red, lane, a.Kc);
   }
 }
 
-// One workgroup per hub chunk: wave w sums edges e0+w, e0+w+4, ...; the four
-// wave sums are added in wave order.
-template <int BM>
+// G hub chunks per workgroup, one per lane group: wave w sums its group's
+// chunk's edges e0+w, e0+w+4, ...; the four wave sums are added in wave
+// order (the same order for every G).
+template <int BM, int G>
 __global__ __launch_bounds__(kBlock) void k_spmm_hub_chunk(BArgs a) {
-  __shared__ double red[kBlock / 64][kMaxK];
+  __shared__ double red[kBlock / 64][64];
   if (BM != kScenFinal && a.ctrl->c.done) return;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int k = lane < a.Kc ? lane : a.Kc - 1;
+  const LaneGroup<G> lg(lane, a.Kc);
+  const int k = lg.k;
   const int org = BM == kOrig ? a.origin[k] : -1;
   const double lo = BM == kOrig ? a.lam[org] : 0.0;
-  const int ch = blockIdx.x;
-  const int r = a.chunk_row[ch];
-  const int e0 = a.chunk_e0[ch];
-  const int e1 = min(e0 + kChunkEdges, a.row_ptr[r + 1]);
+  const int ch = static_cast<int>(blockIdx.x) * G + lg.g;
+  const bool mine = ch < a.n_chunks;
+  const int chc = min(ch, a.n_chunks - 1);
+  const int r = a.chunk_row[chc];
+  const int e0 = a.chunk_e0[chc];
+  const int e1 = mine ? min(e0 + a.chunk_edges, a.row_ptr[r + 1]) : e0;
   double y = 0.0;
   int e = e0 + wave;
   for (; e + 28 < e1; e += 32) {
@@ -521,27 +580,28 @@ __global__ __launch_bounds__(kBlock) void k_spmm_hub_chunk(BArgs a) {
   for (; e < e1; e += 4) y += edge_term<BM>(a, a.col[e], k, org, lo);
   red[wave][lane] = y;
   __syncthreads();
-  if (wave == 0 && lane < a.Kc)
-    a.chunk_part[int64_t(ch) * a.Kc + lane] =
+  if (wave == 0 && lg.active && mine)
+    a.chunk_part[int64_t(ch) * a.Kc + k] =
         ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
 }
 
-// Hub rows: wave w of workgroup b finishes hubs 4b + w, 4b + w + 4·grid, ...
-// (a row's chunks in chunk order, 16 loads in flight, then the epilogue).  A
-// wave adds the gaps of its hubs in order and the workgroup adds its waves in
-// order.
-template <int BM>
+// Hub rows: lane group g of wave w of workgroup b finishes hubs
+// (4b + w)·G + g, then every 4·G·grid further (a row's chunks in chunk
+// order, 16 loads in flight, then the epilogue).  A lane adds the gaps of
+// its hubs in order; the workgroup adds its waves and groups in order.
+template <int BM, int G>
 __global__ __launch_bounds__(kBlock) void k_spmm_hub_finish(BArgs a) {
   constexpr bool FINAL = BM == kScenFinal;
-  __shared__ double red[kBlock / 64][kMaxK];
+  __shared__ double red[kBlock / 64][64];
   if (!FINAL && a.ctrl->c.done) return;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int k = lane < a.Kc ? lane : a.Kc - 1;
+  const LaneGroup<G> lg(lane, a.Kc);
+  const int k = lg.k;
   const bool frozen = !FINAL && a.ctrl->kdone[k];
   double gap = 0.0;
-  const int stride = gridDim.x * (kBlock / 64);
-  for (int h = blockIdx.x * (kBlock / 64) + wave; h < a.n_hubs; h += stride) {
+  const int stride = gridDim.x * (kBlock / 64) * G;
+  for (int h = (blockIdx.x * (kBlock / 64) + wave) * G + lg.g; h < a.n_hubs; h += stride) {
     const int r = a.hub_rows[h];
     const BRow in = bload<BM>(a, r, k, frozen);
     const int c0 = a.hub_chunk0[h], c1 = a.hub_chunk0[h + 1];
@@ -553,14 +613,13 @@ __global__ __launch_bounds__(kBlock) void k_spmm_hub_finish(BArgs a) {
 #pragma unroll
       for (int u = 0; u < 16; ++u) y += ch + u < c1 ? p[u] : 0.0;
     }
-    if (lane < a.Kc) bapply<BM>(a, r, k, in, y, frozen, gap);
+    if (lg.active) bapply<BM>(a, r, k, in, y, frozen, gap);
   }
   if constexpr (!FINAL) {
     red[wave][lane] = gap;
     __syncthreads();
     if (wave == 0 && lane < a.Kc)
-      a.gap_hub[int64_t(blockIdx.x) * a.Kc + lane] =
-          ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+      a.gap_hub[int64_t(blockIdx.x) * a.Kc + lane] = sum_groups<G>(red, lane, a.Kc);
   }
 }
 
@@ -708,7 +767,8 @@ __global__ __launch_bounds__(kGraphGapBlock) void k_graph_gap(const int64_t* gra
                                                               int n_graphs,
                                                               const double* row_delta, Ctrl* ctrl,
                                                               int* gdone, int* gskip, int* giter,
-                                                              int* gstatus, double* ggap) {
+                                                              int* gstatus, double* ggap,
+                                                              const double* gtol) {
   constexpr int W = kGraphGapBlock / 64;
   __shared__ double red[W];
   if (ctrl->done) return;
@@ -744,7 +804,7 @@ __global__ __launch_bounds__(kGraphGapBlock) void k_graph_gap(const int64_t* gra
     if (!isfinite(G)) {
       done = 1;
       gstatus[g] = PSI_ENUMERIC;
-    } else if (G <= ctrl->tol) {
+    } else if (G <= (gtol ? gtol[g] : ctrl->tol)) {
       done = 1;
       gstatus[g] = PSI_OK;
     } else if (it >= ctrl->max_iter) {
@@ -790,9 +850,123 @@ __global__ void k_graph_init(const double* c, const double* invden, int64_t n, i
   }
 }
 
+// Per-graph state of an iteration reset (every graph live), with its control
+// block: a pending wait time-out and the host's test switch survive.
+__global__ void k_graph_reset(int n_graphs, int* gdone, int* gskip, int* giter, int* gstatus,
+                              double* ggap, Ctrl* ctrl, double tol, int max_iter) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < n_graphs) {
+    gdone[g] = 0;
+    gskip[g] = 0;
+    giter[g] = 0;
+    gstatus[g] = PSI_OK;
+    ggap[g] = 0.0;
+  }
+  if (g == 0) {
+    const unsigned err = ctrl->err_flags;
+    const int force = ctrl->force_timeout;
+    *ctrl = Ctrl{};
+    ctrl->err_flags = err;
+    ctrl->force_timeout = force;
+    ctrl->tol = tol;
+    ctrl->max_iter = max_iter;
+    ctrl->bnorm = 1.0;
+  }
+}
+
+// The correction solves of a mixed-precision graph batch: graph g runs to
+// eta·‖r_g‖₁ (its last FP64 gap); graphs already finished are frozen from the
+// start (and done is set at once when every graph is).
+__global__ void k_graph_inner_init(int n_graphs, const int* gdone, const double* ggap, double eta,
+                                   int* gdone2, int* gskip2, int* giter2, int* gstatus2,
+                                   double* ggap2, double* gtol, Ctrl* ctrl2, int max_iter,
+                                   int all_done) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < n_graphs) {
+    gdone2[g] = gdone[g];
+    gskip2[g] = 0;
+    giter2[g] = 0;
+    gstatus2[g] = PSI_OK;
+    ggap2[g] = 0.0;
+    gtol[g] = eta * ggap[g];
+  }
+  if (g == 0) {
+    const unsigned err = ctrl2->err_flags;
+    const int force = ctrl2->force_timeout;
+    *ctrl2 = Ctrl{};
+    ctrl2->err_flags = err;
+    ctrl2->force_timeout = force;
+    ctrl2->tol = 0.0;
+    ctrl2->max_iter = max_iter;
+    ctrl2->bnorm = 1.0;
+    if (all_done) publish_done(ctrl2, -1);
+  }
+}
+
+// r = Y − X rounded to FP32 (the FP64 residual of X); e_0 = r, z_e = e/den.
+__global__ void k_graph_prep_inner(const double* Y, const double* X, const float* invden32,
+                                   int64_t n, float* r32, float* e, float* ze) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float r = static_cast<float>(Y[i] - X[i]);
+  r32[i] = r;
+  e[i] = r;
+  ze[i] = invden32[i] * r;
+}
+
+// After a correction solve: X ← X + e in the graphs still running; a graph
+// that has finished takes its final step Y.
+__global__ void k_graph_update(double* X, double* zX, const double* Y, const double* zY,
+                               const float* e, const double* invden, const int* graph_of,
+                               const int* gdone, int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (gdone[graph_of[i]]) {
+    X[i] = Y[i];
+    zX[i] = zY[i];
+  } else {
+    const double v = X[i] + static_cast<double>(e[i]);
+    X[i] = v;
+    zX[i] = invden[i] * v;
+  }
+}
+
 // Hub-finishing grid: four hubs per workgroup, at most kHubFinGrid workgroups.
-int hub_finish_grid(int64_t n_hubs) {
-  return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(kHubFinGrid, (n_hubs + 3) / 4)));
+int hub_finish_grid(int64_t n_hubs, int G) {
+  const int64_t per = 4 * int64_t(G);
+  return static_cast<int>(
+      std::max<int64_t>(1, std::min<int64_t>(kHubFinGrid, (n_hubs + per - 1) / per)));
+}
+
+// Lane groups of a tile of Kc scenarios: as many as fit a wave.
+int lane_groups(int Kc) { return Kc <= 8 ? 8 : Kc <= 16 ? 4 : Kc <= 32 ? 2 : 1; }
+
+template <int BM, int G>
+void launch_spmm_g(const BArgs& a, int grid, hipStream_t st) {
+  hipLaunchKernelGGL((k_spmm_rows<BM, G>), dim3(grid), dim3(kBlock), 0, st, a);
+  if (a.n_chunks)
+    hipLaunchKernelGGL((k_spmm_hub_chunk<BM, G>), dim3((a.n_chunks + G - 1) / G), dim3(kBlock), 0,
+                       st, a);
+  if (a.n_hubs)
+    hipLaunchKernelGGL((k_spmm_hub_finish<BM, G>), dim3(hub_finish_grid(a.n_hubs, G)),
+                       dim3(kBlock), 0, st, a);
+}
+
+// One multi-vector product of mode BM: the rows kernel (grid workgroups),
+// then the hub chunks and the hub rows.
+template <int BM>
+void launch_spmm(const BArgs& a, int grid, hipStream_t st) {
+  switch (lane_groups(a.Kc)) {
+    case 8: return launch_spmm_g<BM, 8>(a, grid, st);
+    case 4: return launch_spmm_g<BM, 4>(a, grid, st);
+    case 2: return launch_spmm_g<BM, 2>(a, grid, st);
+    default: return launch_spmm_g<BM, 1>(a, grid, st);
+  }
+}
+
+// Workgroups of the hub-finishing kernel of a product (its gap partials).
+int hub_blocks(const BArgs& a) {
+  return a.n_hubs ? hub_finish_grid(a.n_hubs, lane_groups(a.Kc)) : 0;
 }
 
 // The gap of a pass: kGapParts first-level sums of the n_blk rows-kernel and
@@ -808,7 +982,7 @@ int rows_grid() {
     int dev = 0, per_cu = 0, cus = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_spmm_rows<false>, kBlock, 0);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_spmm_rows<kScen, 1>, kBlock, 0);
     cap = std::min(kMaxGrid, std::max(1, per_cu) * std::max(1, cus));
   }
   return cap;
@@ -824,7 +998,7 @@ struct BSched {
 };
 
 static psi_status batch_schedule(const int* row_ptr, int64_t n, int64_t m, BatchWs& w,
-                                 hipStream_t st, BSched* out) {
+                                 int items, int chunk_edges, hipStream_t st, BSched* out) {
   // hub rows and their chunks (depend only on the pattern)
   hipLaunchKernelGGL(k_hub_flags, dim3(grid_for(n + 1)), dim3(kBlock), 0, st, row_ptr, n,
                      w.flags);
@@ -838,7 +1012,7 @@ static psi_status batch_schedule(const int* row_ptr, int64_t n, int64_t m, Batch
   uint32_t n_chunks = 0;
   if (n_hubs > 0) {
     hipLaunchKernelGGL(k_hub_list, dim3(grid_for(n)), dim3(kBlock), 0, st, row_ptr, n,
-                       w.flags, w.hub_rows, nchunks);
+                       w.flags, chunk_edges, w.hub_rows, nchunks);
     uint32_t* chunk0 = reinterpret_cast<uint32_t*>(w.chunk_e0);
     PSI_HIP_CHECK(hipMemsetAsync(nchunks + n_hubs, 0, 4, st));
     s = scan_exclusive_u32(nchunks, chunk0, int64_t(n_hubs) + 1, w.scan_tmp,
@@ -851,17 +1025,51 @@ static psi_status batch_schedule(const int* row_ptr, int64_t n, int64_t m, Batch
                                  hipMemcpyDeviceToDevice, st));
     hipLaunchKernelGGL(k_chunk_table, dim3(grid_for(n_hubs)), dim3(kBlock), 0, st, row_ptr,
                        w.hub_rows, reinterpret_cast<const uint32_t*>(w.hub_chunk0), int(n_hubs),
-                       w.chunk_row, w.chunk_e0, w.hub_chunk0);
+                       chunk_edges, w.chunk_row, w.chunk_e0, w.hub_chunk0);
   }
-  const int64_t n_wtiles = std::max<int64_t>((n + m + kWaveItems - 1) / kWaveItems, 1);
+  const int64_t n_wtiles = std::max<int64_t>((n + m + items - 1) / items, 1);
   hipLaunchKernelGGL(k_row_tiles, dim3(grid_for(n_wtiles + 1)), dim3(kBlock), 0, st, row_ptr,
-                     n, m, int64_t(kWaveItems), n_wtiles, w.row_tiles);
+                     n, m, int64_t(items), n_wtiles, w.row_tiles);
   PSI_HIP_CHECK(hipGetLastError());
 
   out->n_hubs = n_hubs;
   out->n_chunks = n_chunks;
   out->n_wtiles = n_wtiles;
   return PSI_OK;
+}
+
+// Pass arguments of a scenario tile of Kc scenarios (the tile's data in w).
+static BArgs scenario_args(const psi_operator* op, const BatchWs& w, const BSched& sc, int Kc,
+                           int chunk) {
+  BArgs b{};
+  b.row_ptr = op->row_ptr;
+  b.col = op->col;
+  b.n_rows = static_cast<int>(op->n);
+  b.Kc = Kc;
+  b.row_tiles = w.row_tiles;
+  b.n_wtiles = static_cast<int>(sc.n_wtiles);
+  b.hub_rows = w.hub_rows;
+  b.hub_chunk0 = w.hub_chunk0;
+  b.n_hubs = static_cast<int>(sc.n_hubs);
+  b.chunk_row = w.chunk_row;
+  b.chunk_e0 = w.chunk_e0;
+  b.n_chunks = static_cast<int>(sc.n_chunks);
+  b.chunk_edges = chunk;
+  b.c = w.c;
+  b.mu = w.mu;
+  b.invden = w.invden;
+  b.lam = w.lam;
+  b.d = w.d;
+  b.inv_n = 1.0 / static_cast<double>(op->n);
+  b.chunk_part = w.chunk_part;
+  b.gap_blk = w.gap_blk;
+  b.gap_hub = w.gap_hub;
+  b.gap_lvl = w.gap_lvl;
+  b.ctrl = w.ctrl;
+  b.r32 = w.r32;
+  b.mu32 = w.mu32;
+  b.invden32 = w.invden32;
+  return b;
 }
 
 psi_status batched_workspace_size(const psi_operator* op, int n_scenarios, int precision,
@@ -892,12 +1100,26 @@ psi_status solve_batched(psi_operator* op, const psi_params* prm, int K, const d
     set_error("batched workspace smaller than psi_batched_workspace_size reported");
     return PSI_ENOSPACE;
   }
+  // the schedule: explicit, else tuned for this precision, else the defaults
+  const int pi = prm->precision;
+  const int Kt = prm->batch_tile ? prm->batch_tile
+                                 : (op->tuned_batch_tile[pi] ? op->tuned_batch_tile[pi] : kMaxK);
+  const int items = prm->batch_items ? prm->batch_items
+                                     : (op->tuned_batch_items[pi] ? op->tuned_batch_items[pi]
+                                                                  : kWaveItems);
+  const int chunk = prm->hub_chunk ? prm->hub_chunk
+                                   : (op->tuned_batch_chunk[pi] ? op->tuned_batch_chunk[pi]
+                                                                : kChunkEdges);
+  PSI_REQUIRE(Kt >= 1 && Kt <= kMaxK, "batch_tile must be 0 or in [1, 64]");
+  PSI_REQUIRE(items >= kMinWaveItems && items <= 8192, "batch_items must be 0 or in [128, 8192]");
+  PSI_REQUIRE(chunk >= kMinChunkEdges && chunk <= kMaxChunkEdges,
+              "hub_chunk must be 0 or in [512, 8192]");
   BatchWs w{};
   batch_layout(op->n, op->m, &w, static_cast<char*>(ws), mixed);
   const int64_t n = op->n, m = op->m;
 
   BSched sc{};
-  psi_status s = batch_schedule(op->row_ptr, n, m, w, st, &sc);
+  psi_status s = batch_schedule(op->row_ptr, n, m, w, items, chunk, st, &sc);
   if (s != PSI_OK) return s;
   const uint32_t n_hubs = sc.n_hubs, n_chunks = sc.n_chunks;
   const int64_t n_wtiles = sc.n_wtiles;
@@ -913,7 +1135,6 @@ psi_status solve_batched(psi_operator* op, const psi_params* prm, int K, const d
   BatchCtrl* h = pinned.p;       // the scenarios' own iteration
   BatchCtrl* h2 = pinned.p + 1;  // a correction solve
   const int grid = std::min(rows_grid(), static_cast<int>(n_wtiles));
-  const int hgrid = hub_finish_grid(n_hubs);
   const double eta = prm->inner_tol > 0.0 ? prm->inner_tol : 2e-6;
   EventPair evp;
   PSI_HIP_CHECK(hipEventCreate(&evp.a));
@@ -921,8 +1142,8 @@ psi_status solve_batched(psi_operator* op, const psi_params* prm, int K, const d
   hipEvent_t ev0 = evp.a, ev1 = evp.b;
   PSI_HIP_CHECK(hipEventRecord(ev0, st));
   int worst = PSI_OK;
-  for (int k0 = 0; k0 < K; k0 += kMaxK) {
-    const int Kc = std::min(kMaxK, K - k0);
+  for (int k0 = 0; k0 < K; k0 += Kt) {
+    const int Kc = std::min(Kt, K - k0);
     const int64_t nk = n * Kc;
     hipLaunchKernelGGL(k_bctrl_init, dim3(1), dim3(1), 0, st, w.ctrl, prm->tol, prm->max_iter);
     hipLaunchKernelGGL(k_bprep_act, dim3(grid_for(nk)), dim3(kBlock), 0, st, lam_in, mu_in, n, K,
@@ -935,33 +1156,7 @@ psi_status solve_batched(psi_operator* op, const psi_params* prm, int K, const d
       hipLaunchKernelGGL(k_bprep32, dim3(grid_for(nk)), dim3(kBlock), 0, st, w.mu, w.invden, nk,
                          w.mu32, w.invden32);
     PSI_HIP_CHECK(hipGetLastError());
-    BArgs base{};
-    base.row_ptr = op->row_ptr;
-    base.col = op->col;
-    base.n_rows = static_cast<int>(n);
-    base.Kc = Kc;
-    base.row_tiles = w.row_tiles;
-    base.n_wtiles = static_cast<int>(n_wtiles);
-    base.hub_rows = w.hub_rows;
-    base.hub_chunk0 = w.hub_chunk0;
-    base.n_hubs = static_cast<int>(n_hubs);
-    base.chunk_row = w.chunk_row;
-    base.chunk_e0 = w.chunk_e0;
-    base.n_chunks = static_cast<int>(n_chunks);
-    base.c = w.c;
-    base.mu = w.mu;
-    base.invden = w.invden;
-    base.lam = w.lam;
-    base.d = w.d;
-    base.inv_n = 1.0 / static_cast<double>(n);
-    base.chunk_part = w.chunk_part;
-    base.gap_blk = w.gap_blk;
-    base.gap_hub = w.gap_hub;
-    base.gap_lvl = w.gap_lvl;
-    base.ctrl = w.ctrl;
-    base.r32 = w.r32;
-    base.mu32 = w.mu32;
-    base.invden32 = w.invden32;
+    const BArgs base = scenario_args(op, w, sc, Kc, chunk);
     // one FP64 step s_new = Aᵀ s_old + c of every scenario (z = s / den
     // gathered), or the final ψ pass from z
     auto pass64 = [&](const double* z, const double* s_old, double* s_new, double* z_new,
@@ -975,17 +1170,10 @@ psi_status solve_batched(psi_operator* op, const psi_params* prm, int K, const d
         a.psi = psi_out;
         a.psi_ld = K;
         a.psi_col0 = k0;
-        hipLaunchKernelGGL(k_spmm_rows<kScenFinal>, dim3(grid), dim3(kBlock), 0, st, a);
-        if (n_chunks)
-          hipLaunchKernelGGL(k_spmm_hub_chunk<kScenFinal>, dim3(n_chunks), dim3(kBlock), 0, st, a);
-        if (n_hubs)
-          hipLaunchKernelGGL(k_spmm_hub_finish<kScenFinal>, dim3(hgrid), dim3(kBlock), 0, st, a);
+        launch_spmm<kScenFinal>(a, grid, st);
       } else {
-        hipLaunchKernelGGL(k_spmm_rows<kScen>, dim3(grid), dim3(kBlock), 0, st, a);
-        if (n_chunks)
-          hipLaunchKernelGGL(k_spmm_hub_chunk<kScen>, dim3(n_chunks), dim3(kBlock), 0, st, a);
-        if (n_hubs) hipLaunchKernelGGL(k_spmm_hub_finish<kScen>, dim3(hgrid), dim3(kBlock), 0, st, a);
-        launch_batch_gap(a, grid, n_hubs ? hgrid : 0, st);
+        launch_spmm<kScen>(a, grid, st);
+        launch_batch_gap(a, grid, hub_blocks(a), st);
       }
       PSI_HIP_CHECK(hipGetLastError());
       return PSI_OK;
@@ -999,11 +1187,8 @@ psi_status solve_batched(psi_operator* op, const psi_params* prm, int K, const d
       a.e_old = even ? w.e_a : w.e_b;
       a.e_new = even ? w.e_b : w.e_a;
       a.ze_new = even ? w.ze_b : w.ze_a;
-      hipLaunchKernelGGL(k_spmm_rows<kScen32>, dim3(grid), dim3(kBlock), 0, st, a);
-      if (n_chunks)
-        hipLaunchKernelGGL(k_spmm_hub_chunk<kScen32>, dim3(n_chunks), dim3(kBlock), 0, st, a);
-      if (n_hubs) hipLaunchKernelGGL(k_spmm_hub_finish<kScen32>, dim3(hgrid), dim3(kBlock), 0, st, a);
-      launch_batch_gap(a, grid, n_hubs ? hgrid : 0, st);
+      launch_spmm<kScen32>(a, grid, st);
+      launch_batch_gap(a, grid, hub_blocks(a), st);
       PSI_HIP_CHECK(hipGetLastError());
       return PSI_OK;
     };
@@ -1107,7 +1292,9 @@ psi_status solve_batched(psi_operator* op, const psi_params* prm, int K, const d
         inf.final_gap = h->kgap[k];
         inf.final_l1_step = h->kgap[k];
         inf.col_segments = 1;
-        inf.tile_items = kWaveItems;
+        inf.tile_items = items;
+        inf.batch_tile = Kt;
+        inf.hub_chunk = chunk;
       }
     }
   }
@@ -1121,6 +1308,67 @@ psi_status solve_batched(psi_operator* op, const psi_params* prm, int K, const d
   return static_cast<psi_status>(worst);
 }
 
+// The schedule of a graph batch in `precision`: explicit, else tuned, else by
+// default batches of at least 10^6 users take two segments with tiled partial
+// passes: the graphs lie in one segment or the other, and the partial kernel
+// plus a streaming combine beat the fused pass with its per-graph epilogue
+// (measured on 256 graphs of 13.3M users: 84 against 96 ms).
+static psi_status graph_schedule(psi_operator* op, const psi_params* prm, int precision,
+                                 int* tile, int* S, int* form) {
+  const bool tuned = op->tuned_graph_S[precision] > 0;
+  *tile = prm->tile_items ? prm->tile_items
+        : tuned           ? op->tuned_graph_tile[precision]
+        : (op->sched_items ? op->sched_items : kDefaultTileItems);
+  PSI_REQUIRE(tile_items_supported(*tile), "unsupported tile_items");
+  const bool big = op->n >= 1000000;
+  *S = prm->col_segments ? prm->col_segments : tuned ? op->tuned_graph_S[precision] : (big ? 2 : 1);
+  PSI_REQUIRE(*S == 1 || *S == 2 || *S == 4 || *S == 8, "col_segments must be 0, 1, 2, 4 or 8");
+  PSI_REQUIRE(precision != PSI_PREC_MIXED || *S <= 4,
+              "a mixed-precision graph batch takes at most 4 column segments");
+  PSI_REQUIRE(prm->seg_form != PSI_SEG_BANDS, "graph batches have no band layout");
+  const int req = prm->seg_form ? prm->seg_form
+                : (tuned && !prm->col_segments) ? op->tuned_graph_form[precision]
+                : (big && *S > 1 ? kSegTiles : 0);
+  return resolve_form(op, req, *S, precision, *S, precision == PSI_PREC_MIXED ? 4 : 8, form);
+}
+
+// One step pass of a graph batch: the FP64 step X → Y (outer state) or an
+// FP32 correction step e_i → e_{i+1} (inner state), then the per-graph gaps.
+// `skip`: gathers of graphs frozen a whole pass are skipped.
+static psi_status graph_pass(psi_operator* op, int S, bool fp32, int i, const double* X,
+                             const double* zX, double* Y, double* zY, Ctrl* ctrl, bool skip,
+                             const double* gtol, hipStream_t st) {
+  const int G = op->n_graphs;
+  const int off = fp32 ? G : 0;
+  PassArgs a = base_args(op);
+  a.count_iter = 0;
+  a.respect_done = 1;
+  a.ctrl = ctrl;
+  a.gdone = op->gdone + off;
+  a.gskip = skip ? op->gskip + off : nullptr;
+  if (fp32) {
+    const bool even = (i & 1) == 0;
+    a.x = even ? op->ze_a : op->ze_b;
+    a.e_old = even ? op->e_a : op->e_b;
+    a.e_new = even ? op->e_b : op->e_a;
+    a.ze_new = even ? op->ze_b : op->ze_a;
+    a.r32 = op->r32;
+  } else {
+    a.x = zX;
+    a.s_old = X;
+    a.s_new = Y;
+    a.z_new = zY;
+  }
+  const PassMode mode = fp32 ? kStep32G : kStep64G;
+  psi_status r = S > 1 ? launch_pass_seg(op, mode, a, st) : launch_pass(op, mode, a, st);
+  if (r != PSI_OK) return r;
+  hipLaunchKernelGGL(k_graph_gap, dim3(G), dim3(kGraphGapBlock), 0, st, op->graph_off, G,
+                     op->row_delta, ctrl, op->gdone + off, op->gskip + off, op->giter + off,
+                     op->gstatus + off, op->ggap + off, gtol);
+  PSI_HIP_CHECK(hipGetLastError());
+  return PSI_OK;
+}
+
 psi_status solve_graphs(psi_operator* op, const psi_params* prm, double* psi_out, psi_info* infos,
                         hipStream_t st) {
   PSI_REQUIRE(prm && psi_out, "params and psi_out must not be NULL");
@@ -1128,29 +1376,14 @@ psi_status solve_graphs(psi_operator* op, const psi_params* prm, double* psi_out
   PSI_REQUIRE(prm->tol > 0.0 && std::isfinite(prm->tol), "tol must be finite and > 0");
   PSI_REQUIRE(prm->max_iter > 0, "max_iter must be > 0");
   PSI_REQUIRE(prm->tol_mode == PSI_TOL_ABS_L1, "graph batches use PSI_TOL_ABS_L1");
-  PSI_REQUIRE(prm->precision == PSI_PREC_FP64, "graph batches run in PSI_PREC_FP64");
-  const int tile = prm->tile_items ? prm->tile_items : (op->sched_items ? op->sched_items
-                                                                        : kDefaultTileItems);
-  PSI_REQUIRE(tile_items_supported(tile), "unsupported tile_items");
-  // one fused pass over all graphs, or (col_segments > 1) a column-segmented
-  // pass whose partial kernel takes the requested form.  By default, batches
-  // of at least 10^6 users take two segments with tiled partial passes: the
-  // graphs lie in one segment or the other, and the partial kernel plus a
-  // streaming combine beat the fused pass with its per-graph epilogue
-  // (measured on 256 graphs of 13.3M users: 84 against 96 ms)
-  const bool big = op->n >= 1000000;
-  const int S = prm->col_segments ? prm->col_segments : (big ? 2 : 1);
-  PSI_REQUIRE(S == 1 || S == 2 || S == 4 || S == 8, "col_segments must be 0, 1, 2, 4 or 8");
-  int form = 0;
-  PSI_REQUIRE(prm->seg_form != PSI_SEG_BANDS, "graph batches have no band layout");
-  psi_status s = resolve_form(op, prm->seg_form ? prm->seg_form : (big ? kSegTiles : 0), S,
-                              PSI_PREC_FP64, S, 8, &form);
+  PSI_REQUIRE(prm->precision == PSI_PREC_FP64 || prm->precision == PSI_PREC_MIXED,
+              "graph batches run in PSI_PREC_FP64 or PSI_PREC_MIXED");
+  const bool mixed = prm->precision == PSI_PREC_MIXED;
+  int tile = 0, S = 1, form = 0;
+  psi_status s = graph_schedule(op, prm, prm->precision, &tile, &S, &form);
   if (s != PSI_OK) return s;
   s = prepare(op, tile, S, form, st);
   if (s != PSI_OK) return s;
-  auto graph_pass = [&](PassMode mode, const PassArgs& a) {
-    return S > 1 ? launch_pass_seg(op, mode, a, st) : launch_pass(op, mode, a, st);
-  };
   const int64_t n = op->n;
   const int G = op->n_graphs;
   EventPair evp;
@@ -1161,48 +1394,115 @@ psi_status solve_graphs(psi_operator* op, const psi_params* prm, double* psi_out
   hipLaunchKernelGGL(k_graph_init, dim3(grid_for(std::max<int64_t>(n, G))), dim3(kBlock), 0, st,
                      op->c, op->invden, n, G, op->s_a, op->z_a, op->gdone, op->gskip, op->giter,
                      op->gstatus, op->ggap, op->ctrl, prm->tol, prm->max_iter);
-  PassArgs base = base_args(op);
-  base.count_iter = 0;
-  base.respect_done = 1;
-  base.gskip = op->gskip;  // step passes skip the gathers of graphs frozen a pass ago
-  auto pass = [&](int i) -> psi_status {
-    PassArgs a = base;
-    const bool even = (i & 1) == 0;
-    a.x = even ? op->z_a : op->z_b;
-    a.s_old = even ? op->s_a : op->s_b;
-    a.s_new = even ? op->s_b : op->s_a;
-    a.z_new = even ? op->z_b : op->z_a;
-    psi_status r = graph_pass(kStep64G, a);
-    if (r != PSI_OK) return r;
-    hipLaunchKernelGGL(k_graph_gap, dim3(G), dim3(kGraphGapBlock), 0, st, op->graph_off, G,
-                       op->row_delta, op->ctrl, op->gdone, op->gskip, op->giter, op->gstatus,
-                       op->ggap);
-    PSI_HIP_CHECK(hipGetLastError());
+  Ctrl* h = op->host_ctrl;
+  // enqueue passes in blocks (growing unless check_every is set) and read the
+  // control block between blocks; passes after the last graph finished exit
+  // at once.  Returns the number of passes enqueued.
+  auto loop = [&](Ctrl* dctrl, int budget, auto&& pass, int* enqueued) -> psi_status {
+    int enq = 0, chunk = prm->check_every > 0 ? prm->check_every : 8;
+    while (true) {
+      const int cnt = std::min(chunk, budget - enq);
+      for (int i = 0; i < cnt; ++i) {
+        psi_status r = pass(enq + i);
+        if (r != PSI_OK) return r;
+      }
+      enq += cnt;
+      PSI_HIP_CHECK(hipMemcpyAsync(h, dctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+      PSI_HIP_CHECK(hipStreamSynchronize(st));
+      if (h->err_flags & kErrSlotTimeout) return check_waits(op, st);
+      if (h->done || enq >= budget) break;
+      if (prm->check_every == 0) chunk = std::min(2 * chunk, 64);
+    }
+    *enqueued = enq;
     return PSI_OK;
   };
-  int enq = 0, chunk = prm->check_every > 0 ? prm->check_every : 8;
-  Ctrl* h = op->host_ctrl;
-  while (true) {
-    const int cnt = std::min(chunk, prm->max_iter - enq);
-    for (int i = 0; i < cnt; ++i) {
-      s = pass(enq + i);
-      if (s != PSI_OK) return s;
-    }
-    enq += cnt;
-    PSI_HIP_CHECK(hipMemcpyAsync(h, op->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+  // plain FP64 steps from (P, zP), (Q, zQ) taking turns; returns the z of the
+  // buffer that holds the last step in *z_last
+  auto plain = [&](double* P, double* zP, double* Q, double* zQ, int budget,
+                   const double** z_last) -> psi_status {
+    const int before = 0;
+    (void)before;
+    Ctrl* c0 = op->ctrl;
+    int it0 = 0;
+    PSI_HIP_CHECK(hipMemcpyAsync(h, c0, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
     PSI_HIP_CHECK(hipStreamSynchronize(st));
-    if (h->err_flags & kErrSlotTimeout) return check_waits(op, st);
-    if (h->done || enq >= prm->max_iter) break;
-    if (prm->check_every == 0) chunk = std::min(2 * chunk, 64);
+    it0 = h->iter;
+    int enq = 0;
+    psi_status r = loop(c0, budget, [&](int i) {
+      const bool even = (i & 1) == 0;
+      return graph_pass(op, S, false, i, even ? P : Q, even ? zP : zQ, even ? Q : P,
+                        even ? zQ : zP, c0, true, nullptr, st);
+    }, &enq);
+    if (r != PSI_OK) return r;
+    *z_last = ((h->iter - it0) & 1) ? zQ : zP;
+    return PSI_OK;
+  };
+  std::vector<int> fp32(G, 0), refine(G, 0);
+  const double* z_fin = nullptr;
+  if (!mixed) {
+    s = plain(op->s_a, op->z_a, op->s_b, op->z_b, prm->max_iter, &z_fin);
+    if (s != PSI_OK) return s;
+  } else {
+    // FP64 residual passes X → Y, each followed by FP32 correction solves of
+    // the graphs still running, X ← X + e (as the single-graph mixed solve)
+    const double eta = prm->inner_tol > 0.0 ? prm->inner_tol : 2e-6;
+    double *X = op->s_a, *zX = op->z_a, *Y = op->s_b, *zY = op->z_b;
+    std::vector<double> prev(G, std::numeric_limits<double>::infinity()), gap(G);
+    std::vector<int> dn(G), it2(G);
+    while (true) {
+      s = graph_pass(op, S, false, 0, X, zX, Y, zY, op->ctrl, true, nullptr, st);
+      if (s != PSI_OK) return s;
+      PSI_HIP_CHECK(hipMemcpyAsync(h, op->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+      PSI_HIP_CHECK(hipMemcpyAsync(gap.data(), op->ggap, 8 * size_t(G), hipMemcpyDeviceToHost, st));
+      PSI_HIP_CHECK(hipMemcpyAsync(dn.data(), op->gdone, 4 * size_t(G), hipMemcpyDeviceToHost, st));
+      PSI_HIP_CHECK(hipStreamSynchronize(st));
+      if (h->err_flags & kErrSlotTimeout) return check_waits(op, st);
+      z_fin = zY;
+      if (h->done || h->iter >= prm->max_iter) break;
+      bool gains = true;
+      for (int g = 0; g < G; ++g)
+        if (!dn[g] && !(gap[g] < 0.25 * prev[g])) gains = false;
+      if (!gains) {
+        // a refinement no longer gains for some graph: plain FP64 steps from Y
+        s = plain(Y, zY, X, zX, std::max(1, prm->max_iter - h->iter), &z_fin);
+        if (s != PSI_OK) return s;
+        break;
+      }
+      for (int g = 0; g < G; ++g) {
+        prev[g] = gap[g];
+        if (!dn[g]) ++refine[g];
+      }
+      hipLaunchKernelGGL(k_graph_prep_inner, dim3(grid_for(n)), dim3(kBlock), 0, st, Y, X,
+                         op->invden32, n, op->r32, op->e_a, op->ze_a);
+      hipLaunchKernelGGL(k_graph_inner_init, dim3(grid_for(G)), dim3(kBlock), 0, st, G,
+                         op->gdone, op->ggap, eta, op->gdone + G, op->gskip + G, op->giter + G,
+                         op->gstatus + G, op->ggap + G, op->gtol, op->ctrl + 1, prm->max_iter, 0);
+      PSI_HIP_CHECK(hipGetLastError());
+      int enq = 0;
+      s = loop(op->ctrl + 1, prm->max_iter, [&](int i) {
+        return graph_pass(op, S, true, i, nullptr, nullptr, nullptr, nullptr, op->ctrl + 1, true,
+                          op->gtol, st);
+      }, &enq);
+      if (s != PSI_OK) return s;
+      const int inner_passes = h->iter;  // h holds the inner control block
+      PSI_HIP_CHECK(hipMemcpyAsync(it2.data(), op->giter + G, 4 * size_t(G),
+                                   hipMemcpyDeviceToHost, st));
+      PSI_HIP_CHECK(hipStreamSynchronize(st));
+      for (int g = 0; g < G; ++g) fp32[g] += it2[g];
+      const float* e_fin = (inner_passes & 1) ? op->e_b : op->e_a;
+      hipLaunchKernelGGL(k_graph_update, dim3(grid_for(n)), dim3(kBlock), 0, st, X, zX, Y, zY,
+                         e_fin, op->invden, op->graph_of, op->gdone, n);
+      PSI_HIP_CHECK(hipGetLastError());
+    }
   }
-  const int passes = h->iter;
   {
-    PassArgs a = base;
+    PassArgs a = base_args(op);
+    a.count_iter = 0;
     a.respect_done = 0;
     a.gskip = nullptr;  // ψ needs every graph's sums
-    a.x = (passes & 1) ? op->z_b : op->z_a;
+    a.x = z_fin;
     a.s_new = psi_out;
-    s = graph_pass(kFinal64G, a);
+    s = S > 1 ? launch_pass_seg(op, kFinal64G, a, st) : launch_pass(op, kFinal64G, a, st);
     if (s != PSI_OK) return s;
   }
   std::vector<int> it(G), stv(G);
@@ -1227,7 +1527,9 @@ psi_status solve_graphs(psi_operator* op, const psi_params* prm, double* psi_out
       inf = psi_info{};
       inf.status = stg;
       inf.iterations = it[g];
-      inf.spmv_passes = it[g] + 1;
+      inf.fp32_passes = fp32[g];
+      inf.refinements = refine[g];
+      inf.spmv_passes = it[g] + fp32[g] + 1;
       inf.final_gap = gap[g];
       inf.final_l1_step = gap[g];
       inf.col_segments = S;
@@ -1261,7 +1563,8 @@ psi_status solve_origins(psi_operator* op, const psi_params* prm, int K, const i
   BatchWs w{};
   batch_layout(n, m, &w, static_cast<char*>(ws), false);
   BSched sc{};
-  psi_status s = batch_schedule(op->fm_row_ptr, n, m, w, st, &sc);  // CSR(A): rows = followers
+  psi_status s = batch_schedule(op->fm_row_ptr, n, m, w, kWaveItems, kChunkEdges, st,
+                                &sc);  // CSR(A): rows = followers
   if (s != PSI_OK) return s;
   struct Pinned {
     BatchCtrl* p = nullptr;
@@ -1273,7 +1576,6 @@ psi_status solve_origins(psi_operator* op, const psi_params* prm, int K, const i
                               hipHostMallocDefault));
   BatchCtrl* h = pinned.p;
   const int grid = std::min(rows_grid(), static_cast<int>(sc.n_wtiles));
-  const int hgrid = hub_finish_grid(sc.n_hubs);
   const int cgrid = static_cast<int>(std::min<int64_t>(kMaxGrid, (n + 3) / 4));
   EventPair evp;
   PSI_HIP_CHECK(hipEventCreate(&evp.a));
@@ -1300,6 +1602,7 @@ psi_status solve_origins(psi_operator* op, const psi_params* prm, int K, const i
     base.chunk_row = w.chunk_row;
     base.chunk_e0 = w.chunk_e0;
     base.n_chunks = static_cast<int>(sc.n_chunks);
+    base.chunk_edges = kChunkEdges;
     base.mu = op->mu;
     base.invden = op->invden;
     base.lam = op->lam;
@@ -1318,12 +1621,8 @@ psi_status solve_origins(psi_operator* op, const psi_params* prm, int K, const i
       a.s_old = even ? w.s_a : w.s_b;
       a.s_new = even ? w.s_b : w.s_a;
       a.z_new = even ? w.z_b : w.z_a;
-      hipLaunchKernelGGL(k_spmm_rows<kOrig>, dim3(grid), dim3(kBlock), 0, st, a);
-      if (sc.n_chunks)
-        hipLaunchKernelGGL(k_spmm_hub_chunk<kOrig>, dim3(sc.n_chunks), dim3(kBlock), 0, st, a);
-      if (sc.n_hubs)
-        hipLaunchKernelGGL(k_spmm_hub_finish<kOrig>, dim3(hgrid), dim3(kBlock), 0, st, a);
-      if (gap) launch_batch_gap(a, grid, sc.n_hubs ? hgrid : 0, st);
+      launch_spmm<kOrig>(a, grid, st);
+      if (gap) launch_batch_gap(a, grid, hub_blocks(a), st);
       PSI_HIP_CHECK(hipGetLastError());
       return PSI_OK;
     };
@@ -1363,6 +1662,8 @@ psi_status solve_origins(psi_operator* op, const psi_params* prm, int K, const i
         inf.final_l1_step = h->kgap[k];
         inf.col_segments = 1;
         inf.tile_items = kWaveItems;
+        inf.batch_tile = kMaxK;
+        inf.hub_chunk = kChunkEdges;
       }
     }
   }
@@ -1374,6 +1675,240 @@ psi_status solve_origins(psi_operator* op, const psi_params* prm, int K, const i
     for (int k = 0; k < K; ++k) infos[k].device_ms = ms;
   if (worst != PSI_OK) set_error("an origin did not converge (see its info)");
   return static_cast<psi_status>(worst);
+}
+
+// Scenario batches: the schedule whose pass over all K scenarios is fastest.
+// A candidate is timed on the operator's own rates in every scenario, with a
+// control block that never converges: the FP64 step pass (PSI_PREC_FP64) or
+// the FP32 correction pass that dominates a mixed solve (PSI_PREC_MIXED),
+// each with its gap kernels, times ceil(K / Kc) tiles.  The search is by
+// coordinates: scenarios per tile (8, 16, 32, 64 and K, up to 64), then
+// items per wave tile (128 to 1024), then edges per hub chunk (512 to 4096).
+psi_status autotune_batched(psi_operator* op, int precision, int K, void* ws, size_t ws_bytes,
+                            int reps, int* batch_tile, int* batch_items, int* hub_chunk,
+                            double* best_ms, hipStream_t st) {
+  PSI_REQUIRE(op->n_graphs == 1, "scenario batches need a single-graph operator");
+  PSI_REQUIRE(precision == PSI_PREC_FP64 || precision == PSI_PREC_MIXED,
+              "batched solves run in PSI_PREC_FP64 or PSI_PREC_MIXED");
+  PSI_REQUIRE(K >= 1, "n_scenarios must be >= 1");
+  PSI_REQUIRE(ws, "workspace must not be NULL");
+  PSI_REQUIRE(reps >= 0, "reps must be >= 0");
+  const bool mixed = precision == PSI_PREC_MIXED;
+  if (ws_bytes < batch_layout(op->n, op->m, nullptr, nullptr, mixed)) {
+    set_error("batched workspace smaller than psi_batched_workspace_size reported");
+    return PSI_ENOSPACE;
+  }
+  BatchWs w{};
+  batch_layout(op->n, op->m, &w, static_cast<char*>(ws), mixed);
+  const int64_t n = op->n, m = op->m;
+  EventPair tm;
+  PSI_HIP_CHECK(hipEventCreate(&tm.a));
+  PSI_HIP_CHECK(hipEventCreate(&tm.b));
+  // mean ms of one pass of a tile of Kc scenarios in the schedule (items, chunk)
+  auto time_tile = [&](int Kc, int items, int chunk, double* ms) -> psi_status {
+    BSched sc{};
+    psi_status s = batch_schedule(op->row_ptr, n, m, w, items, chunk, st, &sc);
+    if (s != PSI_OK) return s;
+    const int64_t nk = n * Kc;
+    hipLaunchKernelGGL(k_bprep_rep, dim3(grid_for(nk)), dim3(kBlock), 0, st, op->lam, op->mu, n,
+                       Kc, w.lam, w.mu);
+    hipLaunchKernelGGL(k_bprep_den, dim3(grid_for(n * 64)), dim3(kBlock), 0, st, op->fm_row_ptr,
+                       op->fm_col, w.lam, w.mu, n, Kc, w.invden, w.c, w.d);
+    hipLaunchKernelGGL(k_binit, dim3(grid_for(nk)), dim3(kBlock), 0, st, w.c, w.invden, nk,
+                       w.s_a, w.z_a);
+    BArgs a = scenario_args(op, w, sc, Kc, chunk);
+    if (mixed) {
+      hipLaunchKernelGGL(k_bprep32, dim3(grid_for(nk)), dim3(kBlock), 0, st, w.mu, w.invden, nk,
+                         w.mu32, w.invden32);
+      hipLaunchKernelGGL(k_bprep_inner, dim3(grid_for(nk)), dim3(kBlock), 0, st, w.s_a, w.z_a,
+                         w.invden32, nk, w.r32, w.e_a, w.ze_a);
+      hipLaunchKernelGGL(k_bctrl_init, dim3(1), dim3(1), 0, st, w.ctrl2, -1.0, INT32_MAX);
+      a.ctrl = w.ctrl2;
+      a.z32 = w.ze_a;
+      a.e_old = w.e_a;
+      a.e_new = w.e_b;
+      a.ze_new = w.ze_b;
+    } else {
+      hipLaunchKernelGGL(k_bctrl_init, dim3(1), dim3(1), 0, st, w.ctrl, -1.0, INT32_MAX);
+      a.z = w.z_a;
+      a.s_old = w.s_a;
+      a.s_new = w.s_b;
+      a.z_new = w.z_b;
+    }
+    const int grid = std::min(rows_grid(), static_cast<int>(sc.n_wtiles));
+    auto pass = [&]() {
+      if (mixed) launch_spmm<kScen32>(a, grid, st);
+      else launch_spmm<kScen>(a, grid, st);
+      launch_batch_gap(a, grid, hub_blocks(a), st);
+    };
+    pass();  // warm-up
+    int r = reps;
+    if (r == 0) {  // about 20 ms of passes, at least 3
+      PSI_HIP_CHECK(hipEventRecord(tm.a, st));
+      pass();
+      PSI_HIP_CHECK(hipEventRecord(tm.b, st));
+      PSI_HIP_CHECK(hipEventSynchronize(tm.b));
+      float one = 0.f;
+      PSI_HIP_CHECK(hipEventElapsedTime(&one, tm.a, tm.b));
+      r = static_cast<int>(std::min(50.0, std::max(3.0, 20.0 / std::max<double>(one, 1e-3))));
+    }
+    PSI_HIP_CHECK(hipEventRecord(tm.a, st));
+    for (int i = 0; i < r; ++i) pass();
+    PSI_HIP_CHECK(hipEventRecord(tm.b, st));
+    PSI_HIP_CHECK(hipEventSynchronize(tm.b));
+    PSI_HIP_CHECK(hipGetLastError());
+    float tot = 0.f;
+    PSI_HIP_CHECK(hipEventElapsedTime(&tot, tm.a, tm.b));
+    *ms = tot / r;
+    return PSI_OK;
+  };
+  int bt = std::min(K, kMaxK), bi = kWaveItems, bc = kChunkEdges;
+  double best = 0.0;
+  auto consider = [&](int Kc, int items, int chunk) -> psi_status {
+    double ms = 0.0;
+    psi_status s = time_tile(Kc, items, chunk, &ms);
+    if (s != PSI_OK) return s;
+    const double total = ms * static_cast<double>((K + Kc - 1) / Kc);
+    if (best == 0.0 || total < best) {
+      best = total;
+      bt = Kc;
+      bi = items;
+      bc = chunk;
+    }
+    return PSI_OK;
+  };
+  std::vector<int> tiles;
+  for (int Kc : {8, 16, 32, 64})
+    if (Kc < std::min(K, kMaxK)) tiles.push_back(Kc);
+  tiles.push_back(std::min(K, kMaxK));
+  for (int Kc : tiles) {
+    psi_status s = consider(Kc, kWaveItems, kChunkEdges);
+    if (s != PSI_OK) return s;
+  }
+  const int Kb = bt;
+  for (int items : {128, 512, 1024}) {
+    psi_status s = consider(Kb, items, kChunkEdges);
+    if (s != PSI_OK) return s;
+  }
+  const int Ib = bi;
+  for (int chunk : {512, 2048, 4096}) {
+    psi_status s = consider(Kb, Ib, chunk);
+    if (s != PSI_OK) return s;
+  }
+  op->tuned_batch_tile[precision] = bt;
+  op->tuned_batch_items[precision] = bi;
+  op->tuned_batch_chunk[precision] = bc;
+  if (batch_tile) *batch_tile = bt;
+  if (batch_items) *batch_items = bi;
+  if (hub_chunk) *hub_chunk = bc;
+  if (best_ms) *best_ms = best;
+  return PSI_OK;
+}
+
+// Graph batches: the pass schedule (tile items, column segments, partial-pass
+// form) whose block-diagonal step pass, with its per-graph gap kernel, is
+// fastest; timed from s = c with a control block that never converges.
+psi_status autotune_graphs(psi_operator* op, int precision, int reps, int* tile_items,
+                           int* col_segments, int* seg_form, double* best_ms, hipStream_t st) {
+  PSI_REQUIRE(op->n_graphs > 1, "graph mode needs a multi-graph operator");
+  PSI_REQUIRE(precision == PSI_PREC_FP64 || precision == PSI_PREC_MIXED,
+              "graph batches run in PSI_PREC_FP64 or PSI_PREC_MIXED");
+  PSI_REQUIRE(reps >= 0, "reps must be >= 0");
+  const int64_t n = op->n;
+  const int G = op->n_graphs;
+  const bool mixed = precision == PSI_PREC_MIXED;
+  EventPair tm;
+  PSI_HIP_CHECK(hipEventCreate(&tm.a));
+  PSI_HIP_CHECK(hipEventCreate(&tm.b));
+  auto time_one = [&](int tile, int S, int form, double* ms) -> psi_status {
+    psi_status s = prepare(op, tile, S, form, st);
+    if (s != PSI_OK) return s;
+    // s = c in every graph, and a control block (the second) that never
+    // converges; the FP32 pass corrects from r = s − z
+    Ctrl* ctl = op->ctrl + 1;
+    hipLaunchKernelGGL(k_graph_init, dim3(grid_for(std::max<int64_t>(n, G))), dim3(kBlock), 0,
+                       st, op->c, op->invden, n, G, op->s_a, op->z_a, op->gdone, op->gskip,
+                       op->giter, op->gstatus, op->ggap, ctl, -1.0, INT32_MAX);
+    if (mixed) {
+      hipLaunchKernelGGL(k_graph_prep_inner, dim3(grid_for(n)), dim3(kBlock), 0, st, op->s_a,
+                         op->z_a, op->invden32, n, op->r32, op->e_a, op->ze_a);
+      hipLaunchKernelGGL(k_graph_reset, dim3(grid_for(G)), dim3(kBlock), 0, st, G, op->gdone + G,
+                         op->gskip + G, op->giter + G, op->gstatus + G, op->ggap + G, ctl, -1.0,
+                         INT32_MAX);
+    }
+    PSI_HIP_CHECK(hipGetLastError());
+    int i = 0;
+    auto pass = [&]() -> psi_status {
+      const int k = i++;
+      return graph_pass(op, S, mixed, k, op->s_a, op->z_a, op->s_b, op->z_b, ctl, false, nullptr,
+                        st);
+    };
+    s = pass();  // warm-up
+    if (s != PSI_OK) return s;
+    int r = reps;
+    if (r == 0) {
+      PSI_HIP_CHECK(hipEventRecord(tm.a, st));
+      s = pass();
+      if (s != PSI_OK) return s;
+      PSI_HIP_CHECK(hipEventRecord(tm.b, st));
+      PSI_HIP_CHECK(hipEventSynchronize(tm.b));
+      float one = 0.f;
+      PSI_HIP_CHECK(hipEventElapsedTime(&one, tm.a, tm.b));
+      r = static_cast<int>(std::min(50.0, std::max(3.0, 20.0 / std::max<double>(one, 1e-3))));
+    }
+    PSI_HIP_CHECK(hipEventRecord(tm.a, st));
+    for (int i = 0; i < r; ++i) {
+      s = pass();
+      if (s != PSI_OK) return s;
+    }
+    PSI_HIP_CHECK(hipEventRecord(tm.b, st));
+    PSI_HIP_CHECK(hipEventSynchronize(tm.b));
+    float tot = 0.f;
+    PSI_HIP_CHECK(hipEventElapsedTime(&tot, tm.a, tm.b));
+    *ms = tot / r;
+    return check_waits(op, st);
+  };
+  static const int kTiles[] = {1024, 2048, 3072, 4096};
+  double best = 0.0;
+  int bt = 0, bS = 0, bf = 0, tile_s1 = kDefaultTileItems;
+  double best_s1 = 0.0;
+  for (int S : {1, 2, 4, 8}) {
+    if (mixed && S == 8) break;  // the FP32 pass takes at most four segments
+    for (int tile : kTiles) {
+      double ms = 0.0;
+      psi_status s = time_one(tile, S, S > 1 ? kSegTiles : 0, &ms);
+      if (s != PSI_OK) return s;
+      if (S == 1 && (best_s1 == 0.0 || ms < best_s1)) {
+        best_s1 = ms;
+        tile_s1 = tile;
+      }
+      if (best == 0.0 || ms < best) {
+        best = ms;
+        bt = tile;
+        bS = S;
+        bf = S > 1 ? kSegTiles : 0;
+      }
+    }
+    if (S > 1) {
+      double ms = 0.0;
+      psi_status s = time_one(tile_s1, S, kSegSlices, &ms);
+      if (s != PSI_OK) return s;
+      if (ms < best) {
+        best = ms;
+        bt = tile_s1;
+        bS = S;
+        bf = kSegSlices;
+      }
+    }
+  }
+  op->tuned_graph_tile[precision] = bt;
+  op->tuned_graph_S[precision] = bS;
+  op->tuned_graph_form[precision] = bf;
+  if (tile_items) *tile_items = bt;
+  if (col_segments) *col_segments = bS;
+  if (seg_form) *seg_form = bf;
+  if (best_ms) *best_ms = best;
+  return PSI_OK;
 }
 
 }  // namespace psi

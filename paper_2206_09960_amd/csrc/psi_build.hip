@@ -794,11 +794,13 @@ static void layout_persistent(int64_t n, int64_t m_raw, int n_graphs, uint32_t f
   char* graph_of = n_graphs > 1 ? take(4 * size_t(n)) : nullptr;
   char* inv_ng = n_graphs > 1 ? take(8 * size_t(n)) : nullptr;
   char* row_delta = n_graphs > 1 ? take(8 * size_t(n)) : nullptr;
-  char* gdone = n_graphs > 1 ? take(4 * size_t(n_graphs)) : nullptr;
-  char* gskip = n_graphs > 1 ? take(4 * size_t(n_graphs)) : nullptr;
-  char* giter = n_graphs > 1 ? take(4 * size_t(n_graphs)) : nullptr;
-  char* gstatus = n_graphs > 1 ? take(4 * size_t(n_graphs)) : nullptr;
-  char* ggap = n_graphs > 1 ? take(8 * size_t(n_graphs)) : nullptr;
+  // per-graph state: the graphs' own iteration, then their correction solves
+  char* gdone = n_graphs > 1 ? take(4 * 2 * size_t(n_graphs)) : nullptr;
+  char* gskip = n_graphs > 1 ? take(4 * 2 * size_t(n_graphs)) : nullptr;
+  char* giter = n_graphs > 1 ? take(4 * 2 * size_t(n_graphs)) : nullptr;
+  char* gstatus = n_graphs > 1 ? take(4 * 2 * size_t(n_graphs)) : nullptr;
+  char* ggap = n_graphs > 1 ? take(8 * 2 * size_t(n_graphs)) : nullptr;
+  char* gtol = n_graphs > 1 ? take(8 * size_t(n_graphs)) : nullptr;
   char* lam = take(8 * size_t(n));
   char* mu = take(8 * size_t(n));
   char* c = take(8 * size_t(n));
@@ -892,6 +894,7 @@ static void layout_persistent(int64_t n, int64_t m_raw, int n_graphs, uint32_t f
   op->giter = (int*)giter;
   op->gstatus = (int*)gstatus;
   op->ggap = (double*)ggap;
+  op->gtol = (double*)gtol;
   op->lam = (double*)lam;
   op->mu = (double*)mu;
   op->c = (double*)c;

@@ -170,6 +170,7 @@ enum PassMode : int {
   kPart32 = 5,      // same with x FP32, y_s stored FP32
   kStep64G = 6,     // kStep64 on a block-diagonal operator: per-graph freezing, |Δ| per row
   kFinal64G = 7,    // kFinal64 with 1/N of each user's own graph
+  kStep32G = 8,     // kStep32 on a block-diagonal operator: per-graph freezing, |Δ| per row
 };
 
 // One column segment of CSR(Aᵀ): the followers in [lo, hi) of every row.
@@ -414,11 +415,14 @@ struct psi_operator {
   int* graph_of = nullptr;     // graph of each user (n_graphs > 1)
   double* inv_ng = nullptr;    // 1/N of each user's graph (n_graphs > 1)
   double* row_delta = nullptr; // per-user |Δ| of the last pass (n_graphs > 1)
-  int* gdone = nullptr;        // per-graph state (n_graphs > 1)
+  // per-graph state (n_graphs > 1): G entries of the graphs' own iteration,
+  // then G of the FP32 correction solve of a mixed-precision batch
+  int* gdone = nullptr;
   int* gskip = nullptr;
   int* giter = nullptr;
   int* gstatus = nullptr;
   double* ggap = nullptr;
+  double* gtol = nullptr;      // [G] tolerance of each graph's correction solve
   double *lam = nullptr, *mu = nullptr, *c = nullptr, *d = nullptr, *invden = nullptr;
   float *mu32 = nullptr, *invden32 = nullptr, *c32 = nullptr;
   double* val64 = nullptr;
@@ -456,6 +460,16 @@ struct psi_operator {
   int tuned_tile[4]{};
   int tuned_S[4]{};
   int tuned_form[4]{};
+  // scenario batches (psi_autotune_batched), per precision: scenarios per
+  // tile, items per wave tile, edges per hub chunk (0 = not tuned)
+  int tuned_batch_tile[4]{};
+  int tuned_batch_items[4]{};
+  int tuned_batch_chunk[4]{};
+  // graph batches (psi_autotune_batched on a multi-graph operator), per
+  // precision: tile items, column segments, partial-pass form (S = 0: not tuned)
+  int tuned_graph_tile[4]{};
+  int tuned_graph_S[4]{};
+  int tuned_graph_form[4]{};
   int* seg_col = nullptr;       // [m]
   int* seg_row_ptr = nullptr;   // [8 * (n + 1)]
   int* seg_tile_row = nullptr;  // [max_seg_tiles + 8]
@@ -561,6 +575,11 @@ psi_status pagerank(psi_operator* op, double alpha, const psi_params* prm, int p
                     double* start, double* pi_out, psi_info* info, hipStream_t stream);
 psi_status autotune(psi_operator* op, int precision, int reps, int* tile_items, int* col_segments,
                     int* seg_form, double* best_ms, hipStream_t stream);
+psi_status autotune_batched(psi_operator* op, int precision, int K, void* ws, size_t ws_bytes,
+                            int reps, int* batch_tile, int* batch_items, int* hub_chunk,
+                            double* best_ms, hipStream_t stream);
+psi_status autotune_graphs(psi_operator* op, int precision, int reps, int* tile_items,
+                           int* col_segments, int* seg_form, double* best_ms, hipStream_t stream);
 psi_status gather_probe(const double* x, int64_t n_x, int S, const int32_t* idx, int64_t n_idx,
                         double* out, int grid, int reps, double* mean_ms, hipStream_t st);
 psi_status anderson_workspace_size(const psi_operator* op, int depth, size_t* bytes);

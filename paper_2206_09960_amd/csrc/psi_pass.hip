@@ -85,7 +85,7 @@ struct TileSrc {
 
 template <int MODE>
 __device__ inline double gather(const PassArgs& a, int j, int e) {
-  if constexpr (MODE == kStep32 || MODE == kPart32) {
+  if constexpr (MODE == kStep32 || MODE == kPart32 || MODE == kStep32G) {
     return static_cast<double>(static_cast<const float*>(a.x)[j]);
   } else if constexpr (MODE == kStep64W) {
     return static_cast<const double*>(a.x)[j] * __builtin_nontemporal_load(a.val64 + e);
@@ -130,6 +130,13 @@ __device__ inline RowIn load_row(const PassArgs& a, int r) {
     in.a1 = static_cast<double>(a.mu32[r]);
     in.a2 = static_cast<double>(a.invden32[r]);
     in.a3 = static_cast<double>(a.e_old[r]);
+  } else if constexpr (MODE == kStep32G) {
+    in.a0 = static_cast<double>(a.r32[r]);
+    in.a1 = static_cast<double>(a.mu32[r]);
+    in.a2 = static_cast<double>(a.invden32[r]);
+    in.a3 = static_cast<double>(a.e_old[r]);
+    in.a4 = static_cast<double>(static_cast<const float*>(a.x)[r]);  // z_e of e_old
+    in.frozen = a.gdone[a.graph_of[r]];
   }
   return in;
 }
@@ -172,6 +179,20 @@ __device__ inline void apply_row(const PassArgs& a, void* yout, int r, const Row
     a.e_new[r] = en;
     a.ze_new[r] = static_cast<float>(in.a2) * en;
     g += fabs(static_cast<double>(en) - in.a3);
+    s += fabs(static_cast<double>(en));
+  } else if constexpr (MODE == kStep32G) {
+    if (in.frozen) {
+      a.e_new[r] = static_cast<float>(in.a3);
+      a.ze_new[r] = static_cast<float>(in.a4);
+      a.row_delta[r] = 0.0;
+      return;
+    }
+    const float en = static_cast<float>(in.a0) + static_cast<float>(in.a1) * static_cast<float>(y);
+    a.e_new[r] = en;
+    a.ze_new[r] = static_cast<float>(in.a2) * en;
+    const double dlt = fabs(static_cast<double>(en) - in.a3);
+    a.row_delta[r] = dlt;
+    g += dlt;
     s += fabs(static_cast<double>(en));
   } else if constexpr (MODE == kPart64) {
     static_cast<double*>(yout)[r] = y;
@@ -1262,6 +1283,7 @@ psi_status launch_pass(psi_operator* op, PassMode mode, const PassArgs& a, hipSt
     case kStep32: return launch_mode<kStep32>(a, st);
     case kStep64G: return launch_mode<kStep64G>(a, st);
     case kFinal64G: return launch_mode<kFinal64G>(a, st);
+    case kStep32G: return launch_mode<kStep32G>(a, st);
     default: break;
   }
   set_error("unknown pass mode");
@@ -1300,11 +1322,13 @@ psi_status launch_pass_seg(psi_operator* op, PassMode mode, const PassArgs& a, h
       return mode == kStep64G ? launch_combine<kStep64G, double>(a, sg, st)
                               : launch_combine<kFinal64G, double>(a, sg, st);
     case kStep32:
+    case kStep32G:
       for (int s = 0; s < sg.S; ++s)
         sg.seg[s].y = reinterpret_cast<float*>(op->seg_y) + size_t(s) * op->n;
       r = launch_partial<kPart32>(op, a, sg, st);
       if (r != PSI_OK) return r;
-      return launch_combine<kStep32, float>(a, sg, st);
+      return mode == kStep32 ? launch_combine<kStep32, float>(a, sg, st)
+                             : launch_combine<kStep32G, float>(a, sg, st);
     default: break;
   }
   set_error("this pass has no column-segmented form");

@@ -71,8 +71,8 @@ def test_scenarios_star_hub_closed_form(gpu_lib):
         np.testing.assert_allclose(psi[:, s], expect, rtol=1e-12, atol=0)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_scenarios_row_length_boundaries(gpu_lib, prec):
+@pytest.mark.parametrize("prec,tile", [("fp64", 0), ("mixed", 0), ("fp64", 8), ("mixed", 3)])
+def test_scenarios_row_length_boundaries(gpu_lib, prec, tile):
     """Rows whose follower counts sit on the batched kernels' boundaries: 16
     gathers in flight, 64 indices per register load, 256 staged indices and
     the 256-follower hub limit (rows above it are chunked)."""
@@ -96,7 +96,9 @@ def test_scenarios_row_length_boundaries(gpu_lib, prec):
     leader = np.concatenate(leader + [bg_l[keep]]).astype(np.int32)
     lam, mu = scenarios(n, 3, 50)
     op = api.Operator(n, follower, leader, lam[:, 0], mu[:, 0])
-    psi, infos = op.solve_batched(torch.tensor(lam), torch.tensor(mu), tol=1e-11, precision=prec)
+    psi, infos = op.solve_batched(torch.tensor(lam), torch.tensor(mu), tol=1e-11, precision=prec,
+                                  batch_tile=tile)
+    assert all(i["batch_tile"] == (tile or 64) for i in infos)
     psi = psi.cpu().numpy()
     for s in range(3):
         A, B, c, d = oracle.operator(n, follower, leader, lam[:, s], mu[:, s])
@@ -133,6 +135,66 @@ def test_scenarios_mixed_match_oracle(gpu_lib, n, k, gamma):
         assert i["fp32_passes"] > 0 and i["refinements"] >= 1, i
         assert i["spmv_passes"] == i["iterations"] + i["fp32_passes"] + 1
         assert oracle.rel_l1(r["psi"], psi[:, s]) <= 1e-9, s
+
+
+def test_scenario_schedules_give_the_same_sums(gpu_lib):
+    """Scenarios per tile (lane groups of a wave: 64/Kc rows at a time), items
+    per wave tile and hub chunk sizes change only the schedule: each row's sum
+    keeps its order for a given chunk size, so a scenario that stops at the
+    same step has the same bits; every schedule matches the oracle."""
+    api = gpu_lib
+    g = synth.chung_lu(40_000, 14, 2.05, 61, sigma=1.5)  # hubs of thousands of followers
+    k = 20
+    lam, mu = scenarios(g.n, k, 62)
+    op = api.Operator(g.n, g.follower, g.leader, g.lam, g.mu)
+    assert op.stats()["max_followers"] > 2048
+    ref, i_ref = op.solve_batched(torch.tensor(lam), torch.tensor(mu), tol=1e-11)
+    for tile, items, chunk in [(8, 256, 1024), (16, 128, 1024), (5, 1024, 1024), (20, 512, 1024),
+                               (64, 256, 512), (7, 256, 4096)]:
+        psi, infos = op.solve_batched(torch.tensor(lam), torch.tensor(mu), tol=1e-11,
+                                      batch_tile=tile, batch_items=items, hub_chunk=chunk)
+        assert all((i["batch_tile"], i["tile_items"], i["hub_chunk"]) == (tile, items, chunk)
+                   for i in infos)
+        for s in range(k):
+            same_step = infos[s]["iterations"] == i_ref[s]["iterations"]
+            if chunk == 1024 and same_step:
+                assert torch.equal(psi[:, s], ref[:, s]), (tile, items, s)
+            assert abs(infos[s]["iterations"] - i_ref[s]["iterations"]) <= 1
+        for s in (0, k - 1):
+            A, B, c, d = oracle.operator(g.n, g.follower, g.leader, lam[:, s], mu[:, s])
+            r = oracle.power_psi(A, B, c, d, 1e-11)
+            assert oracle.rel_l1(r["psi"], psi[:, s].cpu().numpy()) <= 1e-9, (tile, s)
+    with pytest.raises(api.PsiError, match="batch_tile"):
+        op.solve_batched(torch.tensor(lam), torch.tensor(mu), batch_tile=65)
+    with pytest.raises(api.PsiError, match="hub_chunk"):
+        op.solve_batched(torch.tensor(lam), torch.tensor(mu), hub_chunk=100)
+    with pytest.raises(api.PsiError, match="batch_items"):
+        op.solve_batched(torch.tensor(lam), torch.tensor(mu), batch_items=64)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_autotune_batched_schedule_is_used(gpu_lib, prec):
+    api = gpu_lib
+    g = synth.chung_lu(30_000, 12, 2.1, 63, sigma=1.5)
+    k = 24
+    lam, mu = scenarios(g.n, k, 64)
+    op = api.Operator(g.n, g.follower, g.leader, g.lam, g.mu)
+    t = op.autotune_batched(k, prec)
+    assert t["batch_tile"] in (8, 16, 24) and t["pass_ms"] > 0
+    assert t["batch_items"] in (128, 256, 512, 1024)
+    assert t["hub_chunk"] in (512, 1024, 2048, 4096)
+    psi, infos = op.solve_batched(torch.tensor(lam), torch.tensor(mu), tol=1e-10, precision=prec)
+    assert all((i["batch_tile"], i["tile_items"], i["hub_chunk"]) ==
+               (t["batch_tile"], t["batch_items"], t["hub_chunk"]) for i in infos)
+    for s in (0, k - 1):
+        A, B, c, d = oracle.operator(g.n, g.follower, g.leader, lam[:, s], mu[:, s])
+        r = oracle.power_psi(A, B, c, d, 1e-10)
+        assert infos[s]["status"] == 0
+        assert oracle.rel_l1(r["psi"], psi[:, s].cpu().numpy()) <= 1e-9
+    # an explicit schedule still wins over the tuned one
+    _, i2 = op.solve_batched(torch.tensor(lam), torch.tensor(mu), tol=1e-10, precision=prec,
+                             batch_tile=64)
+    assert i2[0]["batch_tile"] == 64
 
 
 def test_scenarios_mixed_statuses(gpu_lib):
@@ -217,6 +279,58 @@ def test_graphs_column_segmented_passes(gpu_lib, S, form):
     r = oracle.power_psi(A, B, c, d, 1e-10)
     part = seg.cpu().numpy()[g.node_offsets[k]:g.node_offsets[k + 1]]
     assert i_s[k]["status"] == 0 and abs(i_s[k]["iterations"] - r["iterations"]) <= 1
+    assert oracle.rel_l1(r["psi"], part) <= 1e-9
+
+
+@pytest.mark.parametrize("n_graphs,lo,hi,S,form", [(7, 500, 3000, 1, "auto"),
+                                                   (4, 20000, 40000, 1, "auto"),
+                                                   (5, 20000, 40000, 2, "tiles"),
+                                                   (5, 20000, 40000, 4, "slices")])
+def test_graphs_mixed_match_oracle(gpu_lib, n_graphs, lo, hi, S, form):
+    """Graph batches in mixed precision: per graph, FP32 correction solves
+    refined by FP64 residual passes, stopping on the FP64 gap: each graph
+    matches the oracle's Algorithm 2 at the same tolerance and the FP64 batch;
+    repeat solves are bitwise equal."""
+    api = gpu_lib
+    g = synth.multi_graph(n_graphs, lo, hi, 10, 2.1, seed=54, sigma=1.5)
+    op = api.Operator(g.n, g.follower, g.leader, g.lam, g.mu, node_offsets=g.node_offsets)
+    psi, infos = op.solve_graphs(tol=1e-10, precision="mixed", col_segments=S, seg_form=form)
+    again, _ = op.solve_graphs(tol=1e-10, precision="mixed", col_segments=S, seg_form=form)
+    assert torch.equal(psi, again)
+    psi64, _ = op.solve_graphs(tol=1e-10)
+    psi = psi.cpu().numpy()
+    assert oracle.rel_l1(psi64.cpu().numpy(), psi) <= 1e-9
+    assert sum(i["fp32_passes"] for i in infos) > 0
+    for k in sorted({0, n_graphs // 2, n_graphs - 1}):
+        i = infos[k]
+        assert i["status"] == 0 and i["final_gap"] <= 1e-10, i
+        assert i["spmv_passes"] == i["iterations"] + i["fp32_passes"] + 1
+        assert i["col_segments"] == S
+        sub = subgraph(g, k)
+        A, B, c, d = oracle.operator(sub.n, sub.follower, sub.leader, sub.lam, sub.mu)
+        r = oracle.power_psi(A, B, c, d, 1e-10)
+        part = psi[g.node_offsets[k]:g.node_offsets[k + 1]]
+        assert oracle.rel_l1(r["psi"], part) <= 1e-9
+        assert oracle.max_rel(r["psi"], part) <= 1e-7
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_autotune_graphs_schedule_is_used(gpu_lib, prec):
+    api = gpu_lib
+    g = synth.multi_graph(6, 20000, 40000, 10, 2.1, seed=55, sigma=1.5)
+    op = api.Operator(g.n, g.follower, g.leader, g.lam, g.mu, node_offsets=g.node_offsets)
+    t = op.autotune_graphs(prec)
+    assert t["col_segments"] in ((1, 2, 4) if prec == "mixed" else (1, 2, 4, 8))
+    assert t["tile_items"] in (1024, 2048, 3072, 4096) and t["pass_ms"] > 0
+    psi, infos = op.solve_graphs(tol=1e-10, precision=prec)
+    for i in infos:
+        assert (i["tile_items"], i["col_segments"]) == (t["tile_items"], t["col_segments"])
+        assert i["status"] == 0
+    k = 2
+    sub = subgraph(g, k)
+    A, B, c, d = oracle.operator(sub.n, sub.follower, sub.leader, sub.lam, sub.mu)
+    r = oracle.power_psi(A, B, c, d, 1e-10)
+    part = psi.cpu().numpy()[g.node_offsets[k]:g.node_offsets[k + 1]]
     assert oracle.rel_l1(r["psi"], part) <= 1e-9
 
 
