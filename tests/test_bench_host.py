@@ -33,6 +33,15 @@ def test_algorithmic_bytes_count_each_array_once():
     assert bench.algorithmic_bytes("band32", n, m) < bench.algorithmic_bytes("band64", n, m)
 
 
+def test_batched_bytes_read_the_pattern_once():
+    """One pass over K scenarios reads col and row_ptr once and, per user and
+    scenario, five FP64 (step) or five FP32 (correction) vectors."""
+    n, m, k = 1000, 20000, 64
+    assert bench.batched_bytes("scen64", n, m, 1) == bench.algorithmic_bytes("step64", n, m)
+    assert bench.batched_bytes("scen32", n, m, k) == 4 * m + 4 * n + 20 * k * n
+    assert bench.batched_bytes("scen64", n, m, k) - bench.batched_bytes("scen64", n, m, k - 1) == 40 * n
+
+
 def test_traffic_only_for_the_measured_sources(tmp_path, monkeypatch):
     h = bench.source_hash()
     rec = {"source_hash": h, "kernel": "k_slices<4>",
