@@ -13,10 +13,11 @@ operator build is timed separately.
 value = edges traversed per second over the whole solve (Σ passes × M / t),
 in GTEPS; ms_per_step = time-to-ψ.  The headline mode is the fastest of FP64
 (factored operator), MIXED (FP32 corrections + FP64 residual) and the
-learned warm start ahead of the faster of those two, each in the schedule the
+learned warm start ahead of each of those two, each in the schedule the
 autotuner picked; all are reported with the plain FP64 per-edge-weight
-iteration as the comparator.  The Anderson-accelerated solve (same fixed
-point and stopping test, fewer passes) is reported beside them.  On big
+iteration as the comparator.  The Anderson-accelerated solve and the
+asynchronous block Gauss–Seidel sweeps (same fixed point and stopping test,
+fewer passes) are reported beside them.  On big
 workloads the comparison modes are timed over fewer solves
 (--compare-steps); the headline mode is timed over --steps after --warmup.
 
@@ -216,29 +217,32 @@ def run_single(args, name):
         log(f"{prec}: {ms:.3f} ms/solve, {info['spmv_passes']} passes "
             f"({info['iterations']} FP64, {info['fp32_passes']} FP32), layout "
             f"{api.SEG_FORM_NAMES[info['seg_form']]}")
-    base = min(("fp64", "mixed"), key=lambda p: modes[p]["ms"])
 
     warm = None
     if not args.no_warm and os.path.exists(WEIGHTS):
         model = api.Model(np.load(WEIGHTS))
         s0 = model.warmstart(op)
         ms_inf, _ = timed(lambda: model.warmstart(op, s0_out=s0), cmp_k, cmp_w)
-        wname = f"{base}_warm"
-        ms, (psi, info) = timed(lambda: op.solve(tol=tol, precision=base,
-                                                 s0=model.warmstart(op, s0_out=s0)),
-                                cmp_k, cmp_w)
-        assert info["status"] == 0, (wname, info)
-        modes[wname] = dict(ms=ms, info=info, psi=psi.cpu().numpy())
         with open(os.path.splitext(WEIGHTS)[0] + ".json") as fh:
             rec = json.load(fh)
-        warm = dict(mode=wname, ms_inference=round(ms_inf, 4), ms_total=round(ms, 4),
-                    iterations_warm=info["iterations"],
-                    iterations_cold=modes[base]["info"]["iterations"], used_s0=info["used_s0"],
+        lo = rec.get("n_users_min", min(rec.get("n_users", [0])))
+        hi = rec.get("n_users_max", max(rec.get("n_users", [0])))
+        warm = dict(ms_inference=round(ms_inf, 4),
                     model=f"3-layer message passing, hidden 64, trained on {rec['n_graphs']} "
-                          f"Chung-Lu graphs of N in [{min(rec['n_users'])}, "
-                          f"{max(rec['n_users'])}] ({rec['steps']} Adam steps)")
-        log(f"{wname}: {ms:.3f} ms/solve incl. {ms_inf:.3f} ms inference, "
-            f"{info['iterations']} iterations (cold {warm['iterations_cold']})")
+                          f"Chung-Lu graphs of N in [{lo}, {hi}] ({rec['steps']} Adam steps)")
+        # the warm start ahead of each cold mode: the solve from s0 plus inference
+        for prec in ("fp64", "mixed"):
+            wname = f"{prec}_warm"
+            ms, (psi, info) = timed(lambda: op.solve(tol=tol, precision=prec,
+                                                     s0=model.warmstart(op, s0_out=s0)),
+                                    cmp_k, cmp_w)
+            assert info["status"] == 0, (wname, info)
+            modes[wname] = dict(ms=ms, info=info, psi=psi.cpu().numpy())
+            warm[wname] = dict(ms_total=round(ms, 4), passes_warm=info["spmv_passes"],
+                               passes_cold=modes[prec]["info"]["spmv_passes"],
+                               ms_cold=round(modes[prec]["ms"], 4), used_s0=info["used_s0"])
+            log(f"{wname}: {ms:.3f} ms/solve incl. {ms_inf:.3f} ms inference, "
+                f"{info['spmv_passes']} passes (cold {modes[prec]['info']['spmv_passes']})")
 
     # Anderson-accelerated passes (same fixed point and stopping test; reported,
     # not a headline candidate: the headline is Power-ψ itself)

@@ -103,11 +103,10 @@ def chung_lu_edges(n: int, m_target: int, gamma: float, seed: int,
     return follower, leader
 
 
-def chung_lu_edges_torch(n: int, m_target: int, gamma: float, seed: int,
-                         d_max: float | None = None, device="cpu"):
-    """chung_lu_edges drawn with torch on ``device``: the same edges, bit for
-    bit (the N-sized weights and permutation are still computed by NumPy)."""
-    import torch
+def chung_lu_plan(n: int, m_target: int, gamma: float, seed: int,
+                  d_max: float | None = None) -> tuple[np.ndarray, np.ndarray]:
+    """The N-sized host part of a Chung–Lu draw: the leader CDF and the
+    rank-to-user permutation (NumPy; independent of the device)."""
     if n < 2:
         raise ValueError("need at least two users")
     if d_max is None:
@@ -115,8 +114,20 @@ def chung_lu_edges_torch(n: int, m_target: int, gamma: float, seed: int,
     w = capped_weights(n, float(m_target), gamma, float(d_max))
     cdf = np.cumsum(w)
     cdf /= cdf[-1]
+    return cdf, permutation(n, seed)
+
+
+def chung_lu_edges_torch(n: int, m_target: int, gamma: float, seed: int,
+                         d_max: float | None = None, device="cpu", plan=None):
+    """chung_lu_edges drawn with torch on ``device``: the same edges, bit for
+    bit (the N-sized weights and permutation are still computed by NumPy, or
+    passed in as ``plan`` from chung_lu_plan)."""
+    import torch
+    if n < 2:
+        raise ValueError("need at least two users")
+    cdf, perm = plan if plan is not None else chung_lu_plan(n, m_target, gamma, seed, d_max)
     cdf_t = torch.from_numpy(cdf).to(device)
-    perm_t = torch.from_numpy(permutation(n, seed)).to(device)
+    perm_t = torch.from_numpy(perm).to(device)
     follower = torch.empty(m_target, dtype=torch.int32, device=device)
     leader = torch.empty(m_target, dtype=torch.int32, device=device)
     chunk = 1 << 26
