@@ -121,7 +121,8 @@ typedef struct psi_params {
     double inner_tol;    /* PSI_PREC_MIXED: relative tol of each FP32 solve; 0 = default */
     int32_t band_col_log;/* PSI_SEG_BANDS: column blocks of 2^17 or 2^18 users;     */
                          /* 0 = tuned, else 18                                    */
-    int32_t band_rows;   /* PSI_SEG_BANDS: rows per row block, 1024 or 2048;        */
+    int32_t band_rows;   /* PSI_SEG_BANDS: rows per row block, 1024, 1280, 1536   */
+                         /* or 2048;                                               */
                          /* 0 = tuned, else 2048                                  */
     int32_t batch_tile;  /* scenario batches: scenarios per tile, 1..64;          */
                          /* 0 = tuned, else 64                                    */

@@ -420,7 +420,7 @@ psi_status solve_anderson(psi_operator* op, const psi_params* prm, int depth, co
     if (form == kSegBands) band_params(op, prec, &wlog, &rows);
     if (prm->band_col_log) wlog = prm->band_col_log;
     if (prm->band_rows) rows = prm->band_rows;
-    PSI_REQUIRE(form != kSegBands || ((wlog == 17 || wlog == 18) && (rows == 1024 || rows == 2048)),
+    PSI_REQUIRE(form != kSegBands || ((wlog == 17 || wlog == 18) && band_rows_supported(rows)),
                 "band_col_log must be 0, 17 or 18 and band_rows 0, 1024 or 2048");
     s = prepare(op, tile, S, form, st, wlog, rows);
     op->band_pace_ticks = form == kSegBands && op->tuned_band_wlog[prec] == wlog &&

@@ -149,7 +149,7 @@ int band_waves(int rows);
 // blocks of at most `rows` rows.
 psi_status ensure_bands(psi_operator* op, int wlog, int rows, hipStream_t st) {
   PSI_REQUIRE(wlog >= kBandMinLog && wlog <= kBandMaxLog, "unsupported band column width");
-  PSI_REQUIRE(rows == 1024 || rows == 2048, "unsupported band row-block size");
+  PSI_REQUIRE(band_rows_supported(rows), "unsupported band row-block size");
   PSI_REQUIRE(op->n_graphs == 1, "the band layout is for single-graph operators");
   if (op->band_built && op->band_wlog == wlog && op->band_rows == rows) return PSI_OK;
   op->band_built = false;

@@ -198,7 +198,9 @@ constexpr int kBandMinLog = 17;
 constexpr int kBandMaxLog = 18;
 constexpr int kBandMaxCols = 1024;     // column blocks (LDS of the layout build)
 constexpr int kBandWaveCap = 4096;     // waves of one band launch the capacities allow
-constexpr int kBandMinEdges = 2048;    // smallest edge budget of a row block
+constexpr int kBandMinEdges = 2048;
+// rows per row block of the band layout: a wave's sums in LDS (8 B a row)
+inline bool band_rows_supported(int r) { return r == 1024 || r == 1280 || r == 1536 || r == 2048; }    // smallest edge budget of a row block
 constexpr int kBandFixGrid = 64;       // workgroups of the kernel that ends a band pass
 
 struct BandBlock {

@@ -1181,8 +1181,12 @@ psi_status launch_bands_r(psi_operator* op, const PassArgs& a, bool band_only, h
 template <int MODE>
 psi_status launch_bands_mode(psi_operator* op, const PassArgs& a, bool band_only,
                              hipStream_t st) {
-  if (op->band_rows == 2048) return launch_bands_r<MODE, 2048, 4>(op, a, band_only, st);
-  return launch_bands_r<MODE, 1024, 4>(op, a, band_only, st);
+  switch (op->band_rows) {
+    case 2048: return launch_bands_r<MODE, 2048, 4>(op, a, band_only, st);
+    case 1536: return launch_bands_r<MODE, 1536, 4>(op, a, band_only, st);
+    case 1280: return launch_bands_r<MODE, 1280, 4>(op, a, band_only, st);
+    default: return launch_bands_r<MODE, 1024, 4>(op, a, band_only, st);
+  }
 }
 
 // Co-resident workgroups of a kernel of `threads` threads per workgroup.
@@ -1204,9 +1208,14 @@ int band_waves(int rows) {
   // launch then runs slower per row at every pacing (40M users: 24.6 ms per
   // pass at best against 18.6 ms with four): more waves in flight spread
   // over more column blocks, and the gathers miss the L2 more often
-  const int waves = rows == 2048
-                        ? resident_groups(k_band<kStep64, 2048, 4, false>, 4 * 64, 4) * 4
-                        : resident_groups(k_band<kStep64, 1024, 4, false>, 4 * 64, 4) * 4;
+  int groups = 0;
+  switch (rows) {
+    case 2048: groups = resident_groups(k_band<kStep64, 2048, 4, false>, 4 * 64, 4); break;
+    case 1536: groups = resident_groups(k_band<kStep64, 1536, 4, false>, 4 * 64, 4); break;
+    case 1280: groups = resident_groups(k_band<kStep64, 1280, 4, false>, 4 * 64, 4); break;
+    default: groups = resident_groups(k_band<kStep64, 1024, 4, false>, 4 * 64, 4); break;
+  }
+  const int waves = groups * 4;
   return std::min(kBandWaveCap, waves);
 }
 

@@ -343,7 +343,8 @@ psi_status prepare_for(psi_operator* op, int precision, int tile, int S, int for
                        hipStream_t st, int wlog = 0, int rows = 0) {
   PSI_REQUIRE(wlog == 0 || (wlog >= kBandMinLog && wlog <= kBandMaxLog),
               "band_col_log must be 0, 17 or 18");
-  PSI_REQUIRE(rows == 0 || rows == 1024 || rows == 2048, "band_rows must be 0, 1024 or 2048");
+  PSI_REQUIRE(rows == 0 || band_rows_supported(rows),
+              "band_rows must be 0, 1024, 1280, 1536 or 2048");
   if (form == kSegBands) {
     int tw = 0, tr = 0;
     band_params(op, precision, &tw, &tr);
@@ -977,37 +978,61 @@ psi_status autotune(psi_operator* op, int precision, int reps, int* tile_items, 
     }
   }
   if (precision != PSI_PREC_FP64_WEIGHTED) {  // the band layout: column width x row-block size
-    int bw = 0, br = 0;
-    double bms = 0.0;
+    static const int kRows[] = {1024, 1280, 1536, 2048};
+    int bw[4] = {0, 0, 0, 0};
+    double bms[4] = {0.0, 0.0, 0.0, 0.0};
     op->band_pace_ticks = 0;
     for (int wlog = kBandMinLog; wlog <= kBandMaxLog; ++wlog)
-      for (int rows : {1024, 2048}) {
+      for (int ri = 0; ri < 4; ++ri) {
         double ms = 0.0;
-        psi_status s = time_one(tile_s1, 1, kSegBands, wlog, rows, &ms);
+        psi_status s = time_one(tile_s1, 1, kSegBands, wlog, kRows[ri], &ms);
         if (s != PSI_OK) return s;
-        keep(tile_s1, 1, kSegBands, wlog, rows, ms);
-        if (bw == 0 || ms < bms) {
-          bw = wlog;
-          br = rows;
-          bms = ms;
+        keep(tile_s1, 1, kSegBands, wlog, kRows[ri], ms);
+        if (bw[ri] == 0 || ms < bms[ri]) {
+          bw[ri] = wlog;
+          bms[ri] = ms;
         }
       }
-    // pacing of the fastest band layout: column block c of a launch starts no
-    // earlier than c·pace, with pace a fraction of the unpaced time per column
-    // block; waves drift apart less and their gathers stay in L2
+    // pacing of each row-block size at its faster column width: column block
+    // c of a launch starts no earlier than c·pace, with pace a fraction of the
+    // unpaced time per column block; waves drift apart less and their
+    // gathers stay in L2 (the best pace is sharp and differs per layout)
     int dev = 0, khz = 0;
     PSI_HIP_CHECK(hipGetDevice(&dev));
     PSI_HIP_CHECK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
-    psi_status s = prepare(op, tile_s1, 1, kSegBands, st, bw, br);
-    if (s != PSI_OK) return s;
-    const double step_us = bms * 1e3 / (double(std::max(1, op->band_count)) * op->band_B);
-    if (khz > 0 && op->band_B > 1) {
+    int pr = -1;       // row-block size of the best paced candidate
+    double pf = 0.0, pms = 0.0, pstep = 0.0;
+    for (int ri = 0; ri < 4 && khz > 0; ++ri) {
+      op->band_pace_ticks = 0;
+      psi_status s = prepare(op, tile_s1, 1, kSegBands, st, bw[ri], kRows[ri]);
+      if (s != PSI_OK) return s;
+      if (op->band_B <= 1) break;
+      const double step_us =
+          bms[ri] * 1e3 / (double(std::max(1, op->band_count)) * op->band_B);
       for (double f : {0.4, 0.45, 0.5, 0.55, 0.6, 0.7}) {
         op->band_pace_ticks = static_cast<unsigned long long>(f * step_us * khz / 1e3);
         double ms = 0.0;
-        s = time_one(tile_s1, 1, kSegBands, bw, br, &ms);
+        s = time_one(tile_s1, 1, kSegBands, bw[ri], kRows[ri], &ms);
         if (s != PSI_OK) return s;
-        keep(tile_s1, 1, kSegBands, bw, br, ms, op->band_pace_ticks);
+        keep(tile_s1, 1, kSegBands, bw[ri], kRows[ri], ms, op->band_pace_ticks);
+        if (pr < 0 || ms < pms) {
+          pr = ri;
+          pf = f;
+          pms = ms;
+          pstep = step_us;
+        }
+      }
+    }
+    if (pr >= 0) {  // the optimum is sharp: finer paces around the best one
+      op->band_pace_ticks = 0;
+      psi_status s = prepare(op, tile_s1, 1, kSegBands, st, bw[pr], kRows[pr]);
+      if (s != PSI_OK) return s;
+      for (double df : {-0.025, -0.0125, 0.0125, 0.025}) {
+        op->band_pace_ticks = static_cast<unsigned long long>((pf + df) * pstep * khz / 1e3);
+        double ms = 0.0;
+        s = time_one(tile_s1, 1, kSegBands, bw[pr], kRows[pr], &ms);
+        if (s != PSI_OK) return s;
+        keep(tile_s1, 1, kSegBands, bw[pr], kRows[pr], ms, op->band_pace_ticks);
       }
     }
     op->band_pace_ticks = 0;

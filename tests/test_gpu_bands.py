@@ -20,7 +20,7 @@ import synth
 
 pytestmark = pytest.mark.gpu
 
-PARAMS = [(17, 1024), (17, 2048), (18, 1024), (18, 2048)]
+PARAMS = [(17, 1024), (17, 1280), (17, 1536), (17, 2048), (18, 1024), (18, 2048)]
 
 
 def graph_with_rows(n, rows, m_background, seed):
@@ -113,7 +113,7 @@ def test_band_several_bands_against_the_c_oracle(gpu_lib):
     op = api.Operator(g.n, g.follower, g.leader, g.lam, g.mu)
     s_in = np.random.default_rng(5).uniform(0.5, 3.0, g.n)
     ref = G.power_psi(1e-8)
-    for col_log, rows in ((17, 2048), (18, 1024)):
+    for col_log, rows in ((17, 2048), (18, 1024), (17, 1280), (18, 1536)):
         psi, s, info = op.solve(tol=1e-8, seg_form="bands", band_col_log=col_log,
                                 band_rows=rows, return_s=True)
         assert info["status"] == 0, info
