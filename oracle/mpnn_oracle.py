@@ -32,7 +32,7 @@ Pins: the gradient against central finite differences of the loss, a descent
 step lowering the loss, the bfloat16 rounding against its definition and the
 first Adam step against its closed form.  How well a trained network predicts
 t has no reference value in the paper: that quality is parity unpinned, and the
-solver, which keeps c whenever s0's residual is larger, stays the judge of ψ.
+solver, which keeps c whenever s0's residual is larger, alone decides ψ.
 """
 from __future__ import annotations
 
