@@ -446,9 +446,8 @@ def run_batched(args, name):
                    sequential_estimate_ms=round(ms1 * k, 2))
         del single
         # the same batch with FP32 corrections refined in FP64 (reported beside)
-        ms_m, (psi_m, infos_m) = timed(
-            lambda: op.solve_batched(lam_t, mu_t, tol=tol, precision="mixed"),
-            max(1, args.steps // 2), 1)
+        solve_mixed = lambda: op.solve_batched(lam_t, mu_t, tol=tol, precision="mixed")  # noqa: E731
+        ms_m, (psi_m, infos_m) = timed(solve_mixed, max(1, args.steps // 2), 1)
         assert all(i["status"] == 0 for i in infos_m), [i["status_name"] for i in infos_m][:5]
         ref["mixed"] = dict(ms=round(ms_m, 3),
                             fp64_passes_max=int(max(i["iterations"] for i in infos_m)),
@@ -469,7 +468,6 @@ def run_batched(args, name):
                        "algorithmic_bytes": alg, "pass_ms": round(pms, 4),
                        "schedule": {x: tuned[p][x] for x in ("batch_tile", "batch_items",
                                                               "hub_chunk")}}
-        roofline = dict(roof["fp64"], mixed=roof["mixed"])
     else:
         t0 = time.perf_counter()
         tuned = {p: op.autotune_graphs(p) for p in ("fp64", "mixed")}
@@ -478,8 +476,8 @@ def run_batched(args, name):
         ms, (psi, infos) = timed(lambda: op.solve_graphs(tol=tol), args.steps, args.warmup)
         units = len(infos)
         unit_name = "graphs"
-        ms_m, (psi_m, infos_m) = timed(lambda: op.solve_graphs(tol=tol, precision="mixed"),
-                                       max(1, args.steps // 2), 1)
+        solve_mixed = lambda: op.solve_graphs(tol=tol, precision="mixed")  # noqa: E731
+        ms_m, (psi_m, infos_m) = timed(solve_mixed, max(1, args.steps // 2), 1)
         assert all(i["status"] == 0 for i in infos_m), [i["status_name"] for i in infos_m][:5]
         ref = {"mixed": dict(ms=round(ms_m, 3),
                              fp64_passes_max=int(max(i["iterations"] for i in infos_m)),
@@ -498,8 +496,18 @@ def run_batched(args, name):
                        "algorithmic_bytes": alg, "pass_ms": round(pms, 4),
                        "schedule": {x: tuned[p][x] for x in ("tile_items", "col_segments",
                                                               "seg_form")}}
-        roofline = dict(roof["fp64"], mixed=roof["mixed"])
     assert all(i["status"] == 0 for i in infos), [i["status_name"] for i in infos][:5]
+    # the headline is the faster precision, timed over --steps (the other one
+    # stays in the reference block)
+    headline = "fp64"
+    if ms_m < ms:
+        headline = "mixed"
+        ref["fp64"] = dict(ms=round(ms, 3), passes_max=int(max(i["spmv_passes"] for i in infos)))
+        ms, (_, infos) = timed(solve_mixed, args.steps, args.warmup)
+        assert all(i["status"] == 0 for i in infos), [i["status_name"] for i in infos][:5]
+        log(f"headline mixed: {ms:.3f} ms")
+    other = "fp64" if headline == "mixed" else "mixed"
+    roofline = dict(roof[headline], **{other: roof[other]})
     passes = [i["spmv_passes"] for i in infos]
     if name == "cl_4m_k64":
         edge_visits = sum(p * m for p in passes)
@@ -521,10 +529,11 @@ def run_batched(args, name):
         "value": round(edge_visits / (ms * 1e-3) / 1e9, 2),
         "unit": "GTEPS (edges x passes summed over the batch)",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
-        "data": "synthetic",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64" if headline == "mixed" else "f64", "data": "synthetic",
         "config": {"workload": DESCRIPTIONS[name], "name": name, "n_users": g.n, "n_edges": m,
-                   "units": units, "tol": tol, "parallelism": "single GPU"},
+                   "units": units, "tol": tol, "headline_mode": headline,
+                   "parallelism": "single GPU"},
         "passes": {"min": int(min(passes)), "max": int(max(passes)),
                    "mean": round(float(np.mean(passes)), 2)},
         "single_scenario_reference" if name == "cl_4m_k64" else "reference": ref,

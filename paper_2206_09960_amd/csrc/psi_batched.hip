@@ -515,6 +515,48 @@ __global__ __launch_bounds__(kBlock) void k_spmm_rows(BArgs a) {
         }
         return y;
       };
+      if constexpr (G == 1) {
+        if (staged) {
+          // The block's edges as one stream, kB gathers in flight across row
+          // boundaries; a row's sum still adds its edges one by one in order
+          // (the same bits as row by row), and each row's epilogue inputs are
+          // loaded while the row before it is summed.  A staged block holds
+          // no hub (at most kStage <= kHubEdges edges in all).
+          int i = 0;
+          int bnd = __builtin_amdgcn_readlane(rp, 1);  // end of row i
+          BRow cur = bload<BM>(a, rb, k, frozen);
+          BRow nxt = nb > 1 ? bload<BM>(a, rb + 1, k, frozen) : BRow{0.0, 0.0, 0.0, 0.0};
+          double acc = 0.0;
+          auto flush = [&]() {
+            if (lane < a.Kc) bapply<BM>(a, rb + i, k, cur, acc, frozen, gap);
+            acc = 0.0;
+            ++i;
+            cur = nxt;
+            if (i + 1 < nb) nxt = bload<BM>(a, rb + i + 1, k, frozen);
+            bnd = __builtin_amdgcn_readlane(rp, min(i + 1, nb));
+          };
+          for (int q0 = E0; q0 < E1; q0 += kB) {
+            int jj[kB];
+#pragma unroll
+            for (int u = 0; u < kB; ++u) jj[u] = cw[min(q0 + u, E1 - 1) - E0];
+            double v[kB];
+#pragma unroll
+            for (int u = 0; u < kB; ++u) {
+              v[u] = 0.0;
+              if (q0 + u < E1) v[u] = edge_term<BM>(a, jj[u], k, org, lo);
+            }
+#pragma unroll
+            for (int u = 0; u < kB; ++u) {
+              const int q = q0 + u;
+              if (q >= E1) break;  // uniform
+              while (q >= bnd) flush();
+              acc += v[u];
+            }
+          }
+          while (i < nb) flush();
+          continue;
+        }
+      }
       for (int i0 = 0; i0 < nb; i0 += G) {
         int i, e0, len;
         if constexpr (G == 1) {  // one row per wave: its bounds are uniform
