@@ -84,15 +84,17 @@ psi_status psi_autotune_batched(psi_operator* op, int32_t precision, int32_t n_s
                                 double* best_ms, void* stream);
 
 /* Graph-batch autotuner (a multi-graph operator of psi_solve_batched).
- * Times the block-diagonal step pass that dominates a graph batch in
- * `precision` (FP64 step, or the FP32 correction step for PSI_PREC_MIXED),
- * with its per-graph gap kernel, for tile_items 1024, 2048, 3072, 4096 at
- * col_segments 1, 2, 4, 8 (at most 4 for PSI_PREC_MIXED) in the tiled form
- * and, for col_segments > 1, the sliced form; keeps the fastest in the
- * operator for later graph batches in that precision whose psi_params leave
- * tile_items / col_segments / seg_form at 0.  reps as in psi_autotune.
- * Overwrites the operator's solve state; blocks. */
-psi_status psi_autotune_graphs(psi_operator* op, int32_t precision, int32_t reps,
+ * Times whole graph batches in `precision` (PSI_PREC_FP64 or
+ * PSI_PREC_MIXED) to the absolute L1 tolerance `tol`, without the final ψ
+ * pass, for tile_items 1024, 2048, 3072, 4096 at col_segments 1, 2, 4, 8 (at
+ * most 4 for PSI_PREC_MIXED) in the tiled form and, for col_segments > 1, the
+ * sliced form; keeps the fastest in the operator for later graph batches in
+ * that precision whose psi_params leave tile_items / col_segments / seg_form
+ * at 0.  Whole solves are timed because graphs freeze as they converge and
+ * only the tiled forms skip frozen graphs' gathers.  reps: timed solves per
+ * candidate after one untimed (0 = 1).  *best_ms: the fastest solve's
+ * device time.  Overwrites the operator's solve state; blocks. */
+psi_status psi_autotune_graphs(psi_operator* op, int32_t precision, double tol, int32_t reps,
                                int32_t* tile_items, int32_t* col_segments, int32_t* seg_form,
                                double* best_ms, void* stream);
 

@@ -82,7 +82,7 @@ SIGNATURES = [
     ("psi_autotune_batched", i32, [vp, i32, i32, vp, sz, i32, ctypes.POINTER(i32),
                                    ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(f64),
                                    vp]),
-    ("psi_autotune_graphs", i32, [vp, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
+    ("psi_autotune_graphs", i32, [vp, i32, f64, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
                                   ctypes.POINTER(i32), ctypes.POINTER(f64), vp]),
     ("psi_batched_workspace_size", i32, [vp, i32, i32, ctypes.POINTER(sz)]),
     ("psi_solve_batched", i32, [vp, ctypes.POINTER(Params), i32, vp, vp, vp, ctypes.POINTER(Info),

@@ -358,17 +358,18 @@ class Operator:
         return dict(batch_tile=bt.value, batch_items=bi.value, hub_chunk=bc.value,
                     pass_ms=ms.value)
 
-    def autotune_graphs(self, precision: str = "fp64", reps: int = 0, stream=None) -> dict:
-        """psi_autotune_graphs: the fastest tile_items / col_segments / seg_form
-        of a graph batch, kept for later graph solves."""
+    def autotune_graphs(self, precision: str = "fp64", tol: float = 1e-8, reps: int = 0,
+                        stream=None) -> dict:
+        """psi_autotune_graphs: the tile_items / col_segments / seg_form whose
+        whole graph batch to `tol` is fastest, kept for later graph solves."""
         prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         t, sg, fm, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
         with torch.cuda.device(self.device):
-            _check(self._lib.psi_autotune_graphs(self._h, prec, reps, ctypes.byref(t),
+            _check(self._lib.psi_autotune_graphs(self._h, prec, float(tol), reps, ctypes.byref(t),
                                                  ctypes.byref(sg), ctypes.byref(fm),
                                                  ctypes.byref(ms), _stream_handle(stream)))
         return dict(tile_items=t.value, col_segments=sg.value, seg_form=SEG_FORM_NAMES[fm.value],
-                    pass_ms=ms.value)
+                    solve_ms=ms.value)
 
     def solve_batched(self, lam: torch.Tensor, mu: torch.Tensor, tol: float = 1e-8,
                       max_iter: int = 10000, check_every: int = 0, precision: str = "fp64",

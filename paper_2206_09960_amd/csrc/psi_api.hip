@@ -319,7 +319,7 @@ psi_status psi_autotune_batched(psi_operator* op, int32_t precision, int32_t n_s
   PSI_GUARD_END
 }
 
-psi_status psi_autotune_graphs(psi_operator* op, int32_t precision, int32_t reps,
+psi_status psi_autotune_graphs(psi_operator* op, int32_t precision, double tol, int32_t reps,
                                int32_t* tile_items, int32_t* col_segments, int32_t* seg_form,
                                double* best_ms, void* stream) {
   PSI_GUARD_BEGIN
@@ -327,7 +327,7 @@ psi_status psi_autotune_graphs(psi_operator* op, int32_t precision, int32_t reps
   psi_status st = psi::check_device(op);
   if (st != PSI_OK) return st;
   int t = 0, sg = 0, fm = 0;
-  st = psi::autotune_graphs(op, precision, reps, &t, &sg, &fm, best_ms,
+  st = psi::autotune_graphs(op, precision, tol, reps, &t, &sg, &fm, best_ms,
                             static_cast<hipStream_t>(stream));
   if (st == PSI_OK) {
     if (tile_items) *tile_items = t;

@@ -1411,9 +1411,11 @@ static psi_status graph_pass(psi_operator* op, int S, bool fp32, int i, const do
   return PSI_OK;
 }
 
-psi_status solve_graphs(psi_operator* op, const psi_params* prm, double* psi_out, psi_info* infos,
-                        hipStream_t st) {
-  PSI_REQUIRE(prm && psi_out, "params and psi_out must not be NULL");
+// A graph batch to its tolerance; psi_out may be NULL (no final ψ pass: the
+// autotuner's timing runs), *ms_out (if given) the device time of the solve.
+static psi_status graph_solve(psi_operator* op, const psi_params* prm, double* psi_out,
+                              psi_info* infos, hipStream_t st, float* ms_out) {
+  PSI_REQUIRE(prm, "params must not be NULL");
   PSI_REQUIRE(op->n_graphs > 1, "graph mode needs a multi-graph operator");
   PSI_REQUIRE(prm->tol > 0.0 && std::isfinite(prm->tol), "tol must be finite and > 0");
   PSI_REQUIRE(prm->max_iter > 0, "max_iter must be > 0");
@@ -1537,7 +1539,7 @@ psi_status solve_graphs(psi_operator* op, const psi_params* prm, double* psi_out
       PSI_HIP_CHECK(hipGetLastError());
     }
   }
-  {
+  if (psi_out) {
     PassArgs a = base_args(op);
     a.count_iter = 0;
     a.respect_done = 0;
@@ -1558,6 +1560,7 @@ psi_status solve_graphs(psi_operator* op, const psi_params* prm, double* psi_out
   PSI_HIP_CHECK(hipEventSynchronize(ev1));
   float ms = 0.f;
   PSI_HIP_CHECK(hipEventElapsedTime(&ms, ev0, ev1));
+  if (ms_out) *ms_out = ms;
   s = check_waits(op, st);
   if (s != PSI_OK) return s;
   int worst = PSI_OK;
@@ -1582,6 +1585,12 @@ psi_status solve_graphs(psi_operator* op, const psi_params* prm, double* psi_out
   }
   if (worst != PSI_OK) set_error("a graph did not converge (see its info)");
   return static_cast<psi_status>(worst);
+}
+
+psi_status solve_graphs(psi_operator* op, const psi_params* prm, double* psi_out, psi_info* infos,
+                        hipStream_t st) {
+  PSI_REQUIRE(psi_out, "psi_out must not be NULL");
+  return graph_solve(op, prm, psi_out, infos, st, nullptr);
 }
 
 psi_status solve_origins(psi_operator* op, const psi_params* prm, int K, const int32_t* origins,
@@ -1847,68 +1856,45 @@ psi_status autotune_batched(psi_operator* op, int precision, int K, void* ws, si
   return PSI_OK;
 }
 
-// Graph batches: the pass schedule (tile items, column segments, partial-pass
-// form) whose block-diagonal step pass, with its per-graph gap kernel, is
-// fastest; timed from s = c with a control block that never converges.
-psi_status autotune_graphs(psi_operator* op, int precision, int reps, int* tile_items,
-                           int* col_segments, int* seg_form, double* best_ms, hipStream_t st) {
+// Graph batches: the schedule (tile items, column segments, partial-pass
+// form) whose whole batch solve to `tol` is fastest (without the final ψ
+// pass).  Whole solves, not single passes, are timed: graphs freeze as they
+// converge, and only the tiled forms skip the gathers of frozen graphs, so the
+// fastest pass over a fully live batch need not give the fastest solve.
+psi_status autotune_graphs(psi_operator* op, int precision, double tol, int reps,
+                           int* tile_items, int* col_segments, int* seg_form, double* best_ms,
+                           hipStream_t st) {
   PSI_REQUIRE(op->n_graphs > 1, "graph mode needs a multi-graph operator");
   PSI_REQUIRE(precision == PSI_PREC_FP64 || precision == PSI_PREC_MIXED,
               "graph batches run in PSI_PREC_FP64 or PSI_PREC_MIXED");
+  PSI_REQUIRE(tol > 0.0 && std::isfinite(tol), "tol must be finite and > 0");
   PSI_REQUIRE(reps >= 0, "reps must be >= 0");
-  const int64_t n = op->n;
-  const int G = op->n_graphs;
   const bool mixed = precision == PSI_PREC_MIXED;
-  EventPair tm;
-  PSI_HIP_CHECK(hipEventCreate(&tm.a));
-  PSI_HIP_CHECK(hipEventCreate(&tm.b));
+  // the candidates run with these explicit schedules; what a failing
+  // candidate leaves tuned is cleared first
+  op->tuned_graph_S[precision] = 0;
   auto time_one = [&](int tile, int S, int form, double* ms) -> psi_status {
-    psi_status s = prepare(op, tile, S, form, st);
-    if (s != PSI_OK) return s;
-    // s = c in every graph, and a control block (the second) that never
-    // converges; the FP32 pass corrects from r = s − z
-    Ctrl* ctl = op->ctrl + 1;
-    hipLaunchKernelGGL(k_graph_init, dim3(grid_for(std::max<int64_t>(n, G))), dim3(kBlock), 0,
-                       st, op->c, op->invden, n, G, op->s_a, op->z_a, op->gdone, op->gskip,
-                       op->giter, op->gstatus, op->ggap, ctl, -1.0, INT32_MAX);
-    if (mixed) {
-      hipLaunchKernelGGL(k_graph_prep_inner, dim3(grid_for(n)), dim3(kBlock), 0, st, op->s_a,
-                         op->z_a, op->invden32, n, op->r32, op->e_a, op->ze_a);
-      hipLaunchKernelGGL(k_graph_reset, dim3(grid_for(G)), dim3(kBlock), 0, st, G, op->gdone + G,
-                         op->gskip + G, op->giter + G, op->gstatus + G, op->ggap + G, ctl, -1.0,
-                         INT32_MAX);
-    }
-    PSI_HIP_CHECK(hipGetLastError());
-    int i = 0;
-    auto pass = [&]() -> psi_status {
-      const int k = i++;
-      return graph_pass(op, S, mixed, k, op->s_a, op->z_a, op->s_b, op->z_b, ctl, false, nullptr,
-                        st);
-    };
-    s = pass();  // warm-up
-    if (s != PSI_OK) return s;
-    int r = reps;
-    if (r == 0) {
-      PSI_HIP_CHECK(hipEventRecord(tm.a, st));
-      s = pass();
-      if (s != PSI_OK) return s;
-      PSI_HIP_CHECK(hipEventRecord(tm.b, st));
-      PSI_HIP_CHECK(hipEventSynchronize(tm.b));
-      float one = 0.f;
-      PSI_HIP_CHECK(hipEventElapsedTime(&one, tm.a, tm.b));
-      r = static_cast<int>(std::min(50.0, std::max(3.0, 20.0 / std::max<double>(one, 1e-3))));
-    }
-    PSI_HIP_CHECK(hipEventRecord(tm.a, st));
+    psi_params p{};
+    p.tol = tol;
+    p.tol_mode = PSI_TOL_ABS_L1;
+    p.max_iter = 100000;
+    p.precision = precision;
+    p.tile_items = tile;
+    p.col_segments = S;
+    p.seg_form = form == 0 ? 0 : form;
+    if (S == 1) p.seg_form = 0;
+    float one = 0.f;
+    psi_status s = graph_solve(op, &p, nullptr, nullptr, st, &one);  // warm-up
+    if (s != PSI_OK && s != PSI_ENOTCONV) return s;
+    const int r = std::max(1, reps);
+    double tot = 0.0;
     for (int i = 0; i < r; ++i) {
-      s = pass();
-      if (s != PSI_OK) return s;
+      s = graph_solve(op, &p, nullptr, nullptr, st, &one);
+      if (s != PSI_OK && s != PSI_ENOTCONV) return s;
+      tot += one;
     }
-    PSI_HIP_CHECK(hipEventRecord(tm.b, st));
-    PSI_HIP_CHECK(hipEventSynchronize(tm.b));
-    float tot = 0.f;
-    PSI_HIP_CHECK(hipEventElapsedTime(&tot, tm.a, tm.b));
     *ms = tot / r;
-    return check_waits(op, st);
+    return PSI_OK;
   };
   static const int kTiles[] = {1024, 2048, 3072, 4096};
   double best = 0.0;

@@ -580,8 +580,9 @@ psi_status autotune(psi_operator* op, int precision, int reps, int* tile_items, 
 psi_status autotune_batched(psi_operator* op, int precision, int K, void* ws, size_t ws_bytes,
                             int reps, int* batch_tile, int* batch_items, int* hub_chunk,
                             double* best_ms, hipStream_t stream);
-psi_status autotune_graphs(psi_operator* op, int precision, int reps, int* tile_items,
-                           int* col_segments, int* seg_form, double* best_ms, hipStream_t stream);
+psi_status autotune_graphs(psi_operator* op, int precision, double tol, int reps,
+                           int* tile_items, int* col_segments, int* seg_form, double* best_ms,
+                           hipStream_t stream);
 psi_status gather_probe(const double* x, int64_t n_x, int S, const int32_t* idx, int64_t n_idx,
                         double* out, int grid, int reps, double* mean_ms, hipStream_t st);
 psi_status anderson_workspace_size(const psi_operator* op, int depth, size_t* bytes);

@@ -321,7 +321,7 @@ def test_autotune_graphs_schedule_is_used(gpu_lib, prec):
     op = api.Operator(g.n, g.follower, g.leader, g.lam, g.mu, node_offsets=g.node_offsets)
     t = op.autotune_graphs(prec)
     assert t["col_segments"] in ((1, 2, 4) if prec == "mixed" else (1, 2, 4, 8))
-    assert t["tile_items"] in (1024, 2048, 3072, 4096) and t["pass_ms"] > 0
+    assert t["tile_items"] in (1024, 2048, 3072, 4096) and t["solve_ms"] > 0
     psi, infos = op.solve_graphs(tol=1e-10, precision=prec)
     for i in infos:
         assert (i["tile_items"], i["col_segments"]) == (t["tile_items"], t["col_segments"])
