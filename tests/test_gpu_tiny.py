@@ -47,6 +47,14 @@ def test_one_user_every_solver(gpu_lib):
     psi, info = op.solve_anderson(tol=1e-12, depth=2)
     assert info["status"] == 0
     np.testing.assert_allclose(psi.cpu().numpy(), D1, rtol=1e-15)
+    # the band layout (one column block, one row block) and its sweeps
+    psi, info = op.solve(tol=1e-12, seg_form="bands", band_col_log=17, band_rows=1280)
+    assert info["status"] == 0
+    np.testing.assert_allclose(psi.cpu().numpy(), D1, rtol=1e-15)
+    assert op.band_info()["bands"] == 1
+    psi, info = op.solve_async(tol=1e-12)
+    assert info["status"] == 0
+    np.testing.assert_allclose(psi.cpu().numpy(), D1, rtol=1e-15)
 
 
 def test_one_user_batches_and_warm_start(gpu_lib):
@@ -58,6 +66,12 @@ def test_one_user_batches_and_warm_start(gpu_lib):
         psi, infos = op.solve_batched(lam, mu, tol=1e-12, precision=prec)
         assert all(i["status"] == 0 for i in infos), prec
         np.testing.assert_allclose(psi.cpu().numpy(), (lam / (lam + mu)).numpy(), rtol=1e-15)
+        # one scenario per lane group (eight groups of one lane)
+        psi1, infos1 = op.solve_batched(lam, mu, tol=1e-12, precision=prec, batch_tile=1)
+        assert all(i["status"] == 0 and i["batch_tile"] == 1 for i in infos1), prec
+        assert torch.equal(psi1, psi)
+        t = op.autotune_batched(3, prec)
+        assert t["batch_tile"] == 3
     psi, p, infos = op.solve_origins([0], tol=1e-12)
     assert infos[0]["status"] == 0
     # Algorithm 1 for the only origin: its newsfeed is empty, so p = 0 and ψ = d
@@ -84,13 +98,16 @@ def test_graphs_of_one_and_two_users(gpu_lib, segs, form):
     lam = np.array([0.8, 1.5, 0.4, 2.0, 0.3])
     mu = np.array([0.6, 0.5, 1.2, 0.0, 0.9])
     op = api.Operator(5, f, l, lam, mu, node_offsets=offs)
-    psi, infos = op.solve_graphs(tol=1e-12, col_segments=segs, seg_form=form)
-    psi = psi.cpu().numpy()
-    assert len(infos) == 4 and all(i["status"] == 0 for i in infos)
     d = lam / (lam + mu)
-    for u in (0, 3, 4):  # one-user graphs: ψ = d
-        assert abs(psi[u] - d[u]) <= 1e-15 * d[u]
     A, B, c, dd = oracle.operator(2, np.array([0], np.int32), np.array([1], np.int32),
                                   lam[1:3], mu[1:3])
     ref = oracle.power_psi(A, B, c, dd, 1e-12)
-    assert oracle.rel_l1(ref["psi"], psi[1:3]) <= 1e-14
+    for prec in ("fp64", "mixed"):
+        psi, infos = op.solve_graphs(tol=1e-12, col_segments=segs, seg_form=form, precision=prec)
+        psi = psi.cpu().numpy()
+        assert len(infos) == 4 and all(i["status"] == 0 for i in infos), prec
+        for u in (0, 3, 4):  # one-user graphs: ψ = d
+            assert abs(psi[u] - d[u]) <= 1e-15 * d[u], prec
+        assert oracle.rel_l1(ref["psi"], psi[1:3]) <= 1e-14, prec
+    t = op.autotune_graphs("mixed", tol=1e-12)
+    assert t["col_segments"] in (1, 2, 4)
