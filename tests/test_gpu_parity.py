@@ -347,6 +347,28 @@ def test_solve_fp64_matches_oracle(gpu_lib, name, make, tol):
     assert oracle.fixed_point_residual(A, c, s_np) <= tol * 1.5 + 1e-15 * np.abs(s_np).sum()
 
 
+@pytest.mark.parametrize("segs,form", [(1, "auto"), (4, "slices"), (1, "bands")])
+def test_resume_from_a_checkpointed_iterate_is_bitwise_equal(gpu_lib, segs, form):
+    """A solve stopped by max_iter (PSI_ENOTCONV) returns its iterate s_k;
+    restarting from it (used as given) runs the remaining steps of eq.
+    (power_psi) and ends on the same s and ψ, bit for bit, as an
+    uninterrupted solve."""
+    api = gpu_lib
+    g = synth.chung_lu(60_000, 12, 2.2, 62, sigma=1.5)
+    op = gpu_op(api, g)
+    tol = 1e-10
+    kw = dict(tile_items=2048, col_segments=segs, seg_form=form)
+    psi, s, info = op.solve(tol=tol, return_s=True, **kw)
+    assert info["status"] == 0
+    t = info["iterations"]
+    k = t // 2
+    _, s_k, info_k = op.solve(tol=tol, max_iter=k, return_s=True, **kw)
+    assert info_k["status_name"] == "PSI_ENOTCONV" and info_k["iterations"] == k
+    psi2, s2, info2 = op.solve(tol=tol, s0=s_k, no_fallback=True, return_s=True, **kw)
+    assert info2["status"] == 0 and info2["iterations"] == t - k, (info2, t, k)
+    assert torch.equal(s2, s) and torch.equal(psi2, psi)
+
+
 @pytest.mark.parametrize("segs,form", [(1, "auto"), (4, "slices"), (4, "tiles")])
 def test_deferred_decision_stops_at_the_first_step_under_tol(gpu_lib, segs, form):
     """The solve loop decides each pass's gap in the next pass (deferred);
