@@ -289,7 +289,10 @@ psi_status psi_batched_workspace_size(const psi_operator* op, int32_t n_scenario
  * scenarios on the operator's graph — scenario k has rates
  * lambda[i*K + k], mu[i*K + k] (device FP64, user-major [N × K]) and its own
  * A, B, c, d (Sec. II) — solved together as one multi-vector pass per step
- * (scenarios in tiles of 64).  Each scenario runs Algorithm 2 to its own
+ * (scenarios in tiles of prm->batch_tile, 1..64: explicit, else as
+ * psi_autotune_batched kept for the precision, else 64; prm->batch_items and
+ * prm->hub_chunk likewise set the rows kernel's wave tiles and the long
+ * rows' chunks; infos[k] reports the three).  Each scenario runs Algorithm 2 to its own
  * tolerance and is frozen afterwards; psi_out[i*K + k] (device FP64 [N × K])
  * is its ψ; infos[k] (host, may be NULL) its iteration count and gap.
  * The operator's own λ, μ are not used.
@@ -299,18 +302,20 @@ psi_status psi_batched_workspace_size(const psi_operator* op, int32_t n_scenario
  * own gap (over its users), stops at its own tolerance (and is frozen) and
  * its ψ uses its own N; psi_out (device [n_users]) holds every graph's ψ at
  * its users' positions, infos[g] (host, may be NULL) graph g's result;
- * prm->col_segments / seg_form choose the pass as in psi_solve (0: two
+ * prm->tile_items / col_segments / seg_form choose the pass as in
+ * psi_solve (0: as psi_autotune_graphs kept for the precision, else two
  * segments with tiled partial passes from 10^6 users on, one fused pass
  * below).
- * Scenario mode also takes PSI_PREC_MIXED: each refinement is one FP64
- * residual pass r = Aᵀs + c − s for every scenario (‖r‖₁ is its gap, the
- * stopping test), then the FP32 correction solves e = Aᵀe + r of all
- * unfinished scenarios together, each to prm->inner_tol·‖r‖₁ (0 = 2e-6),
- * and s ← s + e; when a refinement stops shrinking some scenario's gap
- * fourfold the batch finishes with FP64 steps.  infos[k].iterations counts
- * scenario k's FP64 passes, fp32_passes its correction passes.
- * Both modes: PSI_TOL_ABS_L1 only; graph mode PSI_PREC_FP64 only; returns
- * the first non-OK scenario/graph status, if any.
+ * Both modes also take PSI_PREC_MIXED: each refinement is one FP64
+ * residual pass r = Aᵀs + c − s for every scenario (graph) — ‖r‖₁ is its
+ * gap, the stopping test — then the FP32 correction solves e = Aᵀe + r of
+ * all unfinished scenarios (graphs) together, each to
+ * prm->inner_tol·‖r‖₁ (0 = 2e-6), and s ← s + e; when a refinement stops
+ * shrinking some unfinished scenario's (graph's) gap fourfold the batch
+ * finishes with FP64 steps.  infos[k].iterations counts the FP64 passes,
+ * fp32_passes the correction passes.
+ * Both modes: PSI_TOL_ABS_L1 only; returns the first non-OK scenario/graph
+ * status, if any.
  * workspace: device, at least psi_batched_workspace_size bytes (0 in graph
  * mode: the operator's own workspace holds the state). */
 psi_status psi_solve_batched(psi_operator* op, const psi_params* prm, int32_t n_scenarios,
