@@ -918,11 +918,10 @@ __global__ void k_graph_reset(int n_graphs, int* gdone, int* gskip, int* giter, 
 
 // The correction solves of a mixed-precision graph batch: graph g runs to
 // eta·‖r_g‖₁ (its last FP64 gap); graphs already finished are frozen from the
-// start (and done is set at once when every graph is).
+// start.
 __global__ void k_graph_inner_init(int n_graphs, const int* gdone, const double* ggap, double eta,
                                    int* gdone2, int* gskip2, int* giter2, int* gstatus2,
-                                   double* ggap2, double* gtol, Ctrl* ctrl2, int max_iter,
-                                   int all_done) {
+                                   double* ggap2, double* gtol, Ctrl* ctrl2, int max_iter) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g < n_graphs) {
     gdone2[g] = gdone[g];
@@ -941,7 +940,6 @@ __global__ void k_graph_inner_init(int n_graphs, const int* gdone, const double*
     ctrl2->tol = 0.0;
     ctrl2->max_iter = max_iter;
     ctrl2->bnorm = 1.0;
-    if (all_done) publish_done(ctrl2, -1);
   }
 }
 
@@ -1520,7 +1518,7 @@ static psi_status graph_solve(psi_operator* op, const psi_params* prm, double* p
                          op->invden32, n, op->r32, op->e_a, op->ze_a);
       hipLaunchKernelGGL(k_graph_inner_init, dim3(grid_for(G)), dim3(kBlock), 0, st, G,
                          op->gdone, op->ggap, eta, op->gdone + G, op->gskip + G, op->giter + G,
-                         op->gstatus + G, op->ggap + G, op->gtol, op->ctrl + 1, prm->max_iter, 0);
+                         op->gstatus + G, op->ggap + G, op->gtol, op->ctrl + 1, prm->max_iter);
       PSI_HIP_CHECK(hipGetLastError());
       int enq = 0;
       s = loop(op->ctrl + 1, prm->max_iter, [&](int i) {
