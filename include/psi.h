@@ -83,11 +83,22 @@ typedef enum psi_status {
  * their gathers hit L2 however large the graph; rows longer than a row block
  * are cut into pieces added in order afterwards.  It suits iterates larger
  * than the caches.
+ * BINS is another layout of its own for iterates larger than the caches
+ * (single-graph operators; FP64 factored, FP32 and final passes): followers
+ * are cut into blocks of 2^14 users and leaders into bins of at most 1280
+ * rows.  A pass is two streaming launches: the first reads each follower
+ * block's slice of the iterate into LDS and writes one value per edge, in
+ * the order the bins read them (8 bytes an edge, 4 in FP32 passes); the
+ * second adds each bin's values to its rows' sums in LDS (propagation
+ * blocking).  No gather leaves LDS, at the price of writing and reading the
+ * per-edge values once per pass.  Its layout costs 12 bytes per edge of the
+ * operator's workspace plus a run table.
  * 0 = the tuned form (psi_autotune), else SLICES when N·(8 or 4 bytes)/S is
  * at most 6 MB and TILES otherwise. */
 #define PSI_SEG_TILES   1
 #define PSI_SEG_SLICES  2
 #define PSI_SEG_BANDS   3
+#define PSI_SEG_BINS    4
 
 typedef struct psi_operator psi_operator;
 
@@ -116,7 +127,8 @@ typedef struct psi_params {
     int32_t col_segments;/* 1, 2, 4 or 8 column segments (one per XCD group);   */
                          /* 0 = chosen from N and the precision                */
     int32_t seg_form;    /* layout: PSI_SEG_TILES or PSI_SEG_SLICES (partial pass  */
-                         /* of a segmented pass), PSI_SEG_BANDS; 0 = tuned, else */
+                         /* of a segmented pass), PSI_SEG_BANDS, PSI_SEG_BINS;   */
+                         /* 0 = tuned, else                                      */
                          /* from N and precision                                 */
     double inner_tol;    /* PSI_PREC_MIXED: relative tol of each FP32 solve; 0 = default */
     int32_t band_col_log;/* PSI_SEG_BANDS: column blocks of 2^17 or 2^18 users;     */

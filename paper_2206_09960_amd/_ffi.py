@@ -22,7 +22,7 @@ PSI_PREC_FP64, PSI_PREC_FP64_WEIGHTED, PSI_PREC_MIXED, PSI_PREC_FP32 = 0, 1, 2, 
 # solve flags
 PSI_NO_FALLBACK = 0x1
 # partial pass of a column-segmented pass
-PSI_SEG_TILES, PSI_SEG_SLICES, PSI_SEG_BANDS = 1, 2, 3
+PSI_SEG_TILES, PSI_SEG_SLICES, PSI_SEG_BANDS, PSI_SEG_BINS = 1, 2, 3, 4
 # pass kinds
 PSI_PASS_STEP64, PSI_PASS_STEP64_W, PSI_PASS_FINAL64, PSI_PASS_STEP32 = 0, 1, 2, 3
 PSI_PASS_PART64, PSI_PASS_PART32 = 4, 5

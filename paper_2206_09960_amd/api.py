@@ -20,9 +20,9 @@ PRECISIONS = {"fp64": PSI_PREC_FP64, "fp64_weighted": PSI_PREC_FP64_WEIGHTED,
               "mixed": PSI_PREC_MIXED, "fp32": PSI_PREC_FP32}
 TOL_MODES = {"abs_l1": PSI_TOL_ABS_L1, "bnorm": PSI_TOL_BNORM, "rel_l1": PSI_TOL_REL_L1}
 SEG_FORMS = {"auto": 0, "none": 0, "tiles": _ffi.PSI_SEG_TILES, "slices": _ffi.PSI_SEG_SLICES,
-             "bands": _ffi.PSI_SEG_BANDS}
+             "bands": _ffi.PSI_SEG_BANDS, "bins": _ffi.PSI_SEG_BINS}
 SEG_FORM_NAMES = {0: "none", _ffi.PSI_SEG_TILES: "tiles", _ffi.PSI_SEG_SLICES: "slices",
-                  _ffi.PSI_SEG_BANDS: "bands"}
+                  _ffi.PSI_SEG_BANDS: "bands", _ffi.PSI_SEG_BINS: "bins"}
 
 
 def _seg_form(f) -> int:
@@ -206,7 +206,8 @@ class Operator:
               raise_on_status: bool = False, band_col_log: int = 0, band_rows: int = 0):
         """psi_solve: ψ (and s) by Algorithm 2; returns (psi, info) or (psi, s, info).
         seg_form: 0 / "auto", "tiles" or "slices" (partial pass of a segmented
-        pass), or "bands" (column-blocked layout with band_col_log, band_rows)."""
+        pass), "bands" (column-blocked layout with band_col_log, band_rows) or
+        "bins" (binned two-launch pass)."""
         p = _ffi.Params()
         _check(self._lib.psi_params_default(ctypes.byref(p)))
         p.tol = tol

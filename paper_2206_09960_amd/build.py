@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpsi.so")
-SOURCES = ["psi_api.hip", "psi_build.hip", "psi_pass.hip", "psi_solve.hip", "psi_batched.hip", "psi_mpnn.hip", "psi_accel.hip", "psi_probe.hip", "psi_band.hip"]
+SOURCES = ["psi_api.hip", "psi_build.hip", "psi_pass.hip", "psi_solve.hip", "psi_batched.hip", "psi_mpnn.hip", "psi_accel.hip", "psi_probe.hip", "psi_band.hip", "psi_bins.hip"]
 ARCH = os.environ.get("PSI_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

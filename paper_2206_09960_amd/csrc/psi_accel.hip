@@ -414,7 +414,7 @@ psi_status solve_anderson(psi_operator* op, const psi_params* prm, int depth, co
   int form = 0;
   psi_status s = resolve_form(op, prm->seg_form, prm->col_segments, prec, S, 8, &form);
   if (s != PSI_OK) return s;
-  if (form == kSegBands) S = 1;
+  if (form == kSegBands || form == kSegBins) S = 1;
   {
     int wlog = 0, rows = 0;
     if (form == kSegBands) band_params(op, prec, &wlog, &rows);

@@ -1365,7 +1365,8 @@ static psi_status graph_schedule(psi_operator* op, const psi_params* prm, int pr
   PSI_REQUIRE(*S == 1 || *S == 2 || *S == 4 || *S == 8, "col_segments must be 0, 1, 2, 4 or 8");
   PSI_REQUIRE(precision != PSI_PREC_MIXED || *S <= 4,
               "a mixed-precision graph batch takes at most 4 column segments");
-  PSI_REQUIRE(prm->seg_form != PSI_SEG_BANDS, "graph batches have no band layout");
+  PSI_REQUIRE(prm->seg_form != PSI_SEG_BANDS && prm->seg_form != PSI_SEG_BINS,
+              "graph batches have no band or binned layout");
   const int req = prm->seg_form ? prm->seg_form
                 : (tuned && !prm->col_segments) ? op->tuned_graph_form[precision]
                 : (big && *S > 1 ? kSegTiles : 0);

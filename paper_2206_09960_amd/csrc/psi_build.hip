@@ -872,6 +872,32 @@ static void layout_persistent(int64_t n, int64_t m_raw, int n_graphs, uint32_t f
   // one per band for the split rows a Gauss–Seidel sweep finishes per band
   char* band_pairs = take(16 * size_t(cap_band_blocks / 4 + cap_band_blocks / 256 + 64));
   char* band_scan_tmp = take(4 * size_t((cap_band_toff + 4095) / 4096 + 8));
+  // binned layout (single-graph operators): a value, an expand-order column
+  // and a bin-order row per edge, and a run table.  Bins are planned with an
+  // edge budget of at least 2.5·R·M/N, so there are at most N/R + 5M/E + 1
+  // <= 3·ceil(N/1024) + 1 of them (R >= 1024); runs are the non-empty
+  // (column block, bin) pairs
+  const bool bins = n_graphs == 1;
+  const int64_t bins_cols = bins ? std::max<int64_t>(1, (n + kBinsCols - 1) >> kBinsLog) : 0;
+  const int64_t cap_bins_blocks = bins ? 3 * ((n + 1023) / 1024) + 8 : 0;
+  const int64_t cap_bins_runs =
+      bins ? std::min<int64_t>(cap_bins_blocks * bins_cols, std::max<int64_t>(m_raw, 1)) : 0;
+  // values (8 bytes an edge); 1 MiB more so that the count tables of small
+  // operators fit it during the build
+  const size_t bins_val_bytes = bins ? 8 * size_t(m_raw) + (size_t(1) << 20) : 0;
+  char* bins_val = take(bins_val_bytes);
+  char* bins_col = take(2 * size_t(bins ? m_raw : 0));
+  char* bins_row = take(2 * size_t(bins ? m_raw : 0));
+  char* bins_rdelta = take(4 * size_t(cap_bins_runs));
+  char* bins_cs = take(4 * size_t(bins_cols + 1));
+  char* bins_crun = take(4 * size_t(bins_cols + 1));
+  char* bins_task = take(4 * size_t(bins_cols * kBinsExpandWaves));
+  char* bins_bstart = take(4 * size_t(cap_bins_blocks + 1));
+  char* bins_order = take(4 * size_t(cap_bins_blocks));
+  char* bins_blocks = take(sizeof(BandBlock) * size_t(cap_bins_blocks + 1));
+  char* bins_split = take(16 * size_t(cap_bins_blocks));
+  char* bins_piece = take(8 * size_t(cap_bins_blocks));
+  char* bins_pairs = take(16 * size_t(cap_bins_blocks / kBinsWaves + 1));
   const int64_t mp_max_hubs = m_raw / (kMpHubEdges + 1) + 1;
   const int64_t mp_max_chunks = m_raw / kMpChunkEdges + mp_max_hubs + 1;
   char* mp[2][3];
@@ -953,6 +979,24 @@ static void layout_persistent(int64_t n, int64_t m_raw, int n_graphs, uint32_t f
   op->cap_band_toff = cap_band_toff;
   op->cap_band_cols = band_cols;
   op->band_built = false;
+  op->bins_val = bins ? static_cast<void*>(bins_val) : nullptr;
+  op->bins_col = (uint16_t*)bins_col;
+  op->bins_row = (uint16_t*)bins_row;
+  op->bins_rdelta = (uint32_t*)bins_rdelta;
+  op->bins_cs = (uint32_t*)bins_cs;
+  op->bins_crun = (uint32_t*)bins_crun;
+  op->bins_task = (int*)bins_task;
+  op->bins_bstart = (uint32_t*)bins_bstart;
+  op->bins_order = (int*)bins_order;
+  op->bins_blocks = (BandBlock*)bins_blocks;
+  op->bins_split = (int4*)bins_split;
+  op->bins_piece = (double*)bins_piece;
+  op->bins_pairs = (double*)bins_pairs;
+  op->cap_bins_blocks = cap_bins_blocks;
+  op->cap_bins_runs = cap_bins_runs;
+  op->cap_bins_cols = bins_cols;
+  op->cap_bins_val = bins_val_bytes;
+  op->bins_built = false;
   op->mp_max_hubs = mp_max_hubs;
   op->mp_max_chunks = mp_max_chunks;
   for (int o = 0; o < 2; ++o) {

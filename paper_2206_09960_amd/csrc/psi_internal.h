@@ -190,6 +190,7 @@ enum SegForm : int {
   kSegTiles = PSI_SEG_TILES,
   kSegSlices = PSI_SEG_SLICES,
   kSegBands = PSI_SEG_BANDS,  // column-blocked layout (psi_band.hip), not a segmentation
+  kSegBins = PSI_SEG_BINS,    // binned two-launch pass (psi_bins.hip), not a segmentation
 };
 
 // Column-blocked ("band") layout: row blocks of at most 1024 or 2048 rows, each
@@ -238,6 +239,41 @@ struct BandFixArgs {
   const double* pairs;
   int n_split;
   int n_pairs;
+};
+
+// Binned ("propagation-blocked") pass, psi_bins.hip.  Followers are cut into
+// column blocks of 2^kBinsLog users, whose z a workgroup holds in LDS; leaders
+// into bins (row blocks of at most kBinsRows rows, planned as the band
+// layout's).  An expand kernel streams each column block's entries, reads z
+// from LDS and writes the values in the order a bin reads them; a bin kernel
+// then streams each bin's values and adds them to its rows' sums in LDS.
+constexpr int kBinsLog = 14;
+constexpr int kBinsCols = 1 << kBinsLog;
+constexpr int kBinsMaxB = 16384;        // column blocks (LDS of the layout build)
+constexpr int kBinsRows = 1280;         // rows per bin (a wave's sums: 10 KB of LDS)
+constexpr int kBinsMinEdges = 4096;     // smallest edge budget of a bin
+constexpr int kBinsExpandWaves = 16;    // waves of an expand workgroup (one column block)
+constexpr int kBinsWaves = 4;           // waves (bins) of a bin workgroup
+constexpr uint32_t kBinsFirst = 0x8000u;  // entry flag: first entry of a (column block, bin) run
+
+// Arguments of the two launches of a binned pass.
+struct BinsArgs {
+  const uint16_t* col;      // expand order: column in block | kBinsFirst, per column block
+  const uint16_t* row;      // bin order: row in bin | kBinsFirst, per bin
+  void* val;                // values in bin order (FP64, or FP32 in FP32 passes)
+  const uint32_t* rdelta;   // per run: bin-order position − expand-order position (mod 2^32)
+  const uint32_t* cs;       // [B + 1] first expand-order entry of each column block
+  const int* task;          // [B · kBinsExpandWaves] run before each expand wave's first entry
+  const uint32_t* bstart;   // [nb + 1] first bin-order entry of each bin
+  const int* order;         // [nb] bins in launch order (most edges first)
+  const BandBlock* blocks;  // [nb + 1] the bins (row blocks)
+  double* piece;            // sums of the pieces of split rows
+  double* pairs;            // (Σ|Δ|, Σ|new|) of each bin workgroup
+  int B;                    // column blocks
+  int per_xcd;              // column blocks per XCD (expand grid = 8 · per_xcd)
+  int nb;                   // bins
+  uint32_t runs;            // runs (rdelta entries)
+  uint32_t m;               // entries
 };
 
 struct SegArgs {
@@ -510,6 +546,27 @@ struct psi_operator {
   double* band_pairs = nullptr;      // [2 * (cap_band_blocks / 4 + cap_band_blocks / 256 + 64)]
   uint32_t* band_scan_tmp = nullptr;
   int64_t cap_band_blocks = 0, cap_band_toff = 0, cap_band_cols = 0;
+  // binned layout (psi_bins.hip), built on first use
+  bool bins_built = false;
+  int bins_B = 0;                    // column blocks of 2^kBinsLog users
+  int bins_nb = 0;                   // bins
+  int bins_n_split = 0;              // rows cut into pieces
+  int64_t bins_runs = 0;             // non-empty (column block, bin) runs
+  void* bins_val = nullptr;          // [m] FP64 + 1 MiB (build scratch before the first pass)
+  uint16_t* bins_col = nullptr;      // [m]
+  uint16_t* bins_row = nullptr;      // [m]
+  uint32_t* bins_rdelta = nullptr;   // [cap_bins_runs]
+  uint32_t* bins_cs = nullptr;       // [cap_bins_cols + 1]
+  uint32_t* bins_crun = nullptr;     // [cap_bins_cols + 1]
+  int* bins_task = nullptr;          // [cap_bins_cols * kBinsExpandWaves]
+  uint32_t* bins_bstart = nullptr;   // [cap_bins_blocks + 1]
+  int* bins_order = nullptr;         // [cap_bins_blocks]
+  psi::BandBlock* bins_blocks = nullptr;  // [cap_bins_blocks + 1]
+  int4* bins_split = nullptr;        // [cap_bins_blocks]
+  double* bins_piece = nullptr;      // [cap_bins_blocks]
+  double* bins_pairs = nullptr;      // [2 * (cap_bins_blocks / kBinsWaves + 1)]
+  int64_t cap_bins_blocks = 0, cap_bins_runs = 0, cap_bins_cols = 0;
+  size_t cap_bins_val = 0;           // bytes of bins_val
 };
 
 namespace psi {
@@ -535,6 +592,11 @@ psi_status ensure_seg_slices(psi_operator* op, hipStream_t stream);
 // of at most `rows` rows (psi_band.hip), and the waves of one band launch.
 psi_status ensure_bands(psi_operator* op, int wlog, int rows, hipStream_t stream);
 int band_waves(int rows);
+// The binned layout (psi_bins.hip).
+psi_status ensure_bins(psi_operator* op, hipStream_t stream);
+// One pass in the binned form: expand, bins, then the kernel that adds the
+// pieces of split rows and ends the gap.
+psi_status launch_pass_bins(psi_operator* op, PassMode mode, const PassArgs& a, hipStream_t stream);
 // Layout of a call (requested, tuned, or from the gathered vector's size:
 // band layout, or the partial-pass form of S segments) and the schedules and
 // layouts its passes need; requested_S is the caller's col_segments.

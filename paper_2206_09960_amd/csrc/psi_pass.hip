@@ -1011,6 +1011,176 @@ __global__ __launch_bounds__(kBlock) void k_band_split(PassArgs a, BandFixArgs f
   }
 }
 
+// -------------------------------------------------------------- binned form
+// Two streaming launches per pass over the binned layout (psi_bins.hip).
+//
+// Expand: one workgroup per column block of 2^14 users.  Workgroups go to the
+// XCDs round-robin, so blockIdx mod 8 picks the XCD and each XCD takes a
+// contiguous range of column blocks in order: the runs that neighbouring
+// column blocks write into one bin lie side by side in bin order, and their
+// partial lines meet in that XCD's L2.  The block's z goes to LDS; each wave
+// streams a sixteenth of the block's entries, finds each entry's run by
+// counting run-start flags from the run before its first entry, and writes z
+// of the entry's column to slot rdelta[run] + entry.
+constexpr int kBinsUnroll = 4;  // chunks of 64 entries in flight per wave
+
+template <class XT>
+__global__ __launch_bounds__(kBinsExpandWaves * 64) void k_bins_expand(PassArgs a, BinsArgs b) {
+  __shared__ XT zl[kBinsCols];
+  // the deferred gap's reduction uses the first 2·waves doubles of zl before
+  // the block's z is loaded
+  if (a.defer_gap && blockIdx.x == 0)
+    take_deferred_n<kBinsExpandWaves>(a.ctrl, a.gap_prev, a.hist, a.count_iter, a.pass_id,
+                                      reinterpret_cast<double*>(zl));
+  if (a.respect_done && pass_cancelled(a.ctrl, a.pass_id, false)) return;
+  const int c = static_cast<int>(blockIdx.x & 7) * b.per_xcd + static_cast<int>(blockIdx.x >> 3);
+  if (c >= b.B) return;  // uniform across the workgroup
+  const int64_t col0 = static_cast<int64_t>(c) << kBinsLog;
+  const int64_t nc = min(static_cast<int64_t>(kBinsCols), static_cast<int64_t>(a.n_rows) - col0);
+  const XT* x = static_cast<const XT*>(a.x) + col0;
+  for (int j = threadIdx.x; j < kBinsCols; j += kBinsExpandWaves * 64)
+    zl[j] = j < nc ? x[j] : XT(0);
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const uint32_t lo0 = b.cs[c], ne = b.cs[c + 1] - lo0;
+  const uint32_t lo =
+      lo0 + static_cast<uint32_t>((static_cast<uint64_t>(ne) * wave) / kBinsExpandWaves);
+  const uint32_t hi =
+      lo0 + static_cast<uint32_t>((static_cast<uint64_t>(ne) * (wave + 1)) / kBinsExpandWaves);
+  int run = b.task[c * kBinsExpandWaves + wave];
+  const unsigned long long upto = ~0ull >> (63 - lane);  // lanes 0..lane
+  XT* out = static_cast<XT*>(b.val);
+  for (uint32_t k0 = lo; k0 < hi; k0 += 64 * kBinsUnroll) {
+    uint32_t w[kBinsUnroll];
+#pragma unroll
+    for (int u = 0; u < kBinsUnroll; ++u) {
+      const uint32_t k = k0 + u * 64 + lane;
+      w[u] = k < hi ? static_cast<uint32_t>(b.col[k]) : 0u;
+    }
+    uint32_t dst[kBinsUnroll];
+#pragma unroll
+    for (int u = 0; u < kBinsUnroll; ++u) {
+      const uint32_t k = k0 + u * 64 + lane;
+      const unsigned long long fl = __ballot(k < hi && (w[u] & kBinsFirst));
+      const int r = run + __popcll(fl & upto);
+      run += __popcll(fl);
+      // r and the slot are in range by construction; the clamps keep a
+      // damaged layout from writing outside the value array
+      const uint32_t rc = static_cast<uint32_t>(min(max(r, 0), static_cast<int>(b.runs) - 1));
+      dst[u] = k < hi ? min(b.rdelta[rc] + k, b.m - 1u) : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < kBinsUnroll; ++u) {
+      const uint32_t k = k0 + u * 64 + lane;
+      if (k < hi) out[dst[u]] = zl[w[u] & (kBinsCols - 1)];
+    }
+  }
+}
+
+// Bins: one wave per bin (launch order: most edges first), its rows' sums in
+// LDS, its values and rows streamed 64 entries a chunk.  A chunk holds the end
+// and start of several runs (column blocks); inside a run rows ascend, so a
+// segmented scan adds the equal rows, which are adjacent, and the last lane of
+// each row's stretch adds it to the row's sum.  One row can end a stretch in
+// two runs of a chunk, so those adds go run by run (one LDS add per run of the
+// chunk, lanes of other runs idle): no two lanes of one add share a row, and
+// every row's sum keeps the layout's order.
+__device__ inline void bins_chunk_add(double* y, uint32_t w, double v, int lane) {
+  const bool valid = w != 0xFFFFFFFFu;
+  const unsigned rl = w & (kBinsFirst - 1u);
+  const unsigned key = valid ? rl : 0x10000u + static_cast<unsigned>(lane);
+  const unsigned prev = __shfl_up(key, 1, 64);
+  const bool head = lane == 0 || key != prev;
+  const unsigned long long hm = __ballot(head);
+  const int h = 63 - __clzll(hm & (~0ull >> (63 - lane)));  // first lane of this stretch
+  unsigned long long pos = ~hm;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    if (pos == 0ull) break;
+    const double t = __shfl_up(v, off, 64);
+    if (lane - off >= h) v += t;
+    pos &= pos << off;
+  }
+  const bool tail = lane == 63 || ((hm >> (lane + 1)) & 1ull);
+  const unsigned long long fm = __ballot(valid && (w & kBinsFirst));
+  const int nruns = __popcll(fm);  // runs that start in this chunk (uniform)
+  if (tail && valid) {
+    const int mine = __popcll(fm & (~0ull >> (63 - lane)));
+    for (int r = 0; r <= nruns; ++r)
+      if (mine == r) __hip_atomic_fetch_add(y + rl, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+}
+
+template <class XT>
+__device__ inline void bins_load(const uint16_t* row, const XT* val, uint32_t e, uint32_t end,
+                                 int lane, uint32_t* w, XT* v) {
+#pragma unroll
+  for (int u = 0; u < kBinsUnroll; ++u) {
+    const uint32_t i = e + u * 64 + lane;
+    const bool ok = i < end;
+    w[u] = ok ? static_cast<uint32_t>(row[i]) : 0xFFFFFFFFu;
+    v[u] = ok ? val[i] : XT(0);
+  }
+}
+
+template <int MODE, int R, int NW>
+__global__ __launch_bounds__(NW * 64) void k_bins(PassArgs a, BinsArgs b) {
+  // the row sums; the first 2·NW doubles also serve the gap reduction after
+  // the sums are consumed
+  __shared__ double ylds[NW][R];
+  double* red = &ylds[0][0];
+  using XT = typename std::conditional<MODE == kStep32, float, double>::type;
+  if (a.respect_done && pass_cancelled(a.ctrl, a.pass_id, true)) return;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int slot = static_cast<int>(blockIdx.x) * NW + wave;
+  double g = 0.0, sn = 0.0;
+  if (slot < b.nb) {
+    const int blk = b.order[slot];
+    const BandBlock bb = b.blocks[blk];
+    double* y = ylds[wave];
+    for (int k = lane; k < bb.nrows; k += 64) y[k] = 0.0;
+    __builtin_amdgcn_wave_barrier();
+    const uint32_t e0 = b.bstart[blk], e1 = b.bstart[blk + 1];
+    const XT* val = static_cast<const XT*>(b.val);
+    uint32_t wn[kBinsUnroll];
+    XT vn[kBinsUnroll];
+    bins_load(b.row, val, e0, e1, lane, wn, vn);
+    for (uint32_t e = e0; e < e1; e += 64 * kBinsUnroll) {
+      uint32_t wc[kBinsUnroll];
+      XT vc[kBinsUnroll];
+#pragma unroll
+      for (int u = 0; u < kBinsUnroll; ++u) {
+        wc[u] = wn[u];
+        vc[u] = vn[u];
+      }
+      // the next chunks in flight while these are added
+      if (e + 64 * kBinsUnroll < e1) bins_load(b.row, val, e + 64 * kBinsUnroll, e1, lane, wn, vn);
+#pragma unroll
+      for (int u = 0; u < kBinsUnroll; ++u) {
+        if (e + u * 64 >= e1) break;  // uniform
+        bins_chunk_add(y, wc[u], static_cast<double>(vc[u]), lane);
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (bb.piece >= 0) {
+      if (lane == 0) b.piece[bb.piece] = y[0];
+    } else {
+      for (int k = lane; k < bb.nrows; k += 64) {
+        const int r = bb.row_lo + k;
+        apply_row<MODE>(a, nullptr, r, load_row<MODE>(a, r), y[k], g, sn);
+      }
+    }
+  }
+  if constexpr (MODE != kFinal64) {
+    __syncthreads();  // every wave has read its sums before red overwrites them
+    block_sum2_n<NW>(g, sn, red);
+    if (threadIdx.x == 0) {
+      b.pairs[2 * blockIdx.x] = g;
+      b.pairs[2 * blockIdx.x + 1] = sn;
+    }
+  }
+}
+
 // Co-resident workgroups of a kernel: CUs × workgroups per CU, a multiple of 8.
 template <class K>
 int resident_grid(K kernel) {
@@ -1189,6 +1359,45 @@ psi_status launch_bands_mode(psi_operator* op, const PassArgs& a, bool band_only
   }
 }
 
+// A binned pass: expand, bins, then the split rows and the gap (k_band_fix).
+template <int MODE>
+psi_status launch_bins_mode(psi_operator* op, const PassArgs& a, hipStream_t st) {
+  using XT = typename std::conditional<MODE == kStep32, float, double>::type;
+  BinsArgs b{};
+  b.col = op->bins_col;
+  b.row = op->bins_row;
+  b.val = op->bins_val;
+  b.rdelta = op->bins_rdelta;
+  b.cs = op->bins_cs;
+  b.task = op->bins_task;
+  b.bstart = op->bins_bstart;
+  b.order = op->bins_order;
+  b.blocks = op->bins_blocks;
+  b.piece = op->bins_piece;
+  b.pairs = op->bins_pairs;
+  b.B = op->bins_B;
+  b.per_xcd = (op->bins_B + 7) / 8;
+  b.nb = op->bins_nb;
+  b.runs = static_cast<uint32_t>(op->bins_runs);
+  b.m = static_cast<uint32_t>(op->m);
+  hipLaunchKernelGGL(k_bins_expand<XT>, dim3(unsigned(8 * b.per_xcd)),
+                     dim3(kBinsExpandWaves * 64), 0, st, a, b);
+  const int grid = (b.nb + kBinsWaves - 1) / kBinsWaves;
+  hipLaunchKernelGGL((k_bins<MODE, kBinsRows, kBinsWaves>), dim3(unsigned(std::max(1, grid))),
+                     dim3(kBinsWaves * 64), 0, st, a, b);
+  BandFixArgs f{};
+  f.split = op->bins_split;
+  f.piece = op->bins_piece;
+  f.pairs = op->bins_pairs;
+  f.n_split = op->bins_n_split;
+  f.n_pairs = MODE == kFinal64 ? 0 : grid;
+  const int want = std::max((f.n_split + kBlock - 1) / kBlock, (f.n_pairs + 255) / 256);
+  const int fgrid = std::max(1, std::min(kBandFixGrid, want));
+  hipLaunchKernelGGL(k_band_fix<MODE>, dim3(fgrid), dim3(kBlock), 0, st, a, f);
+  PSI_HIP_CHECK(hipGetLastError());
+  return PSI_OK;
+}
+
 // Co-resident workgroups of a kernel of `threads` threads per workgroup.
 template <class K>
 int resident_groups(K kernel, int threads, int max_per_cu = 1 << 20) {
@@ -1232,9 +1441,23 @@ psi_status launch_pass_bands(psi_operator* op, PassMode mode, const PassArgs& a,
   return PSI_EINVAL;
 }
 
+psi_status launch_pass_bins(psi_operator* op, PassMode mode, const PassArgs& a, hipStream_t st) {
+  PSI_REQUIRE(op->bins_built, "binned layout not built");
+  switch (mode) {
+    case kStep64: return launch_bins_mode<kStep64>(op, a, st);
+    case kFinal64: return launch_bins_mode<kFinal64>(op, a, st);
+    case kStep32: return launch_bins_mode<kStep32>(op, a, st);
+    default: break;
+  }
+  set_error("this pass has no binned form");
+  return PSI_EINVAL;
+}
+
 psi_status run_pass(psi_operator* op, int S, PassMode mode, const PassArgs& a, hipStream_t st) {
   if (op->seg_form == kSegBands && (mode == kStep64 || mode == kFinal64 || mode == kStep32))
     return launch_pass_bands(op, mode, a, false, st);
+  if (op->seg_form == kSegBins && (mode == kStep64 || mode == kFinal64 || mode == kStep32))
+    return launch_pass_bins(op, mode, a, st);
   if (S > 1 && mode != kStep64W) return launch_pass_seg(op, mode, a, st);
   return launch_pass(op, mode, a, st);
 }

@@ -272,10 +272,16 @@ constexpr double kBandAutoBytes = 32.0e6;
 psi_status resolve_form(const psi_operator* op, int requested, int requested_S, int precision,
                         int S, int bytes, int* form) {
   PSI_REQUIRE(requested == 0 || requested == PSI_SEG_TILES || requested == PSI_SEG_SLICES ||
-                  requested == PSI_SEG_BANDS,
-              "seg_form must be 0, PSI_SEG_TILES, PSI_SEG_SLICES or PSI_SEG_BANDS");
+                  requested == PSI_SEG_BANDS || requested == PSI_SEG_BINS,
+              "seg_form must be 0, PSI_SEG_TILES, PSI_SEG_SLICES, PSI_SEG_BANDS or PSI_SEG_BINS");
   const bool untuned = op->tuned_tile[precision] == 0;
-  if (requested == kSegBands ||
+  if (requested == kSegBins ||
+      (requested == 0 && requested_S == 0 && precision != PSI_PREC_FP64_WEIGHTED &&
+       op->n_graphs == 1 && op->tuned_form[precision] == kSegBins)) {
+    PSI_REQUIRE(op->n_graphs == 1, "the binned layout is for single-graph operators");
+    PSI_REQUIRE(precision != PSI_PREC_FP64_WEIGHTED, "the weighted pass has no binned layout");
+    *form = kSegBins;
+  } else if (requested == kSegBands ||
       (requested == 0 && requested_S == 0 && precision != PSI_PREC_FP64_WEIGHTED &&
        op->n_graphs == 1 &&
        (op->tuned_form[precision] == kSegBands ||
@@ -317,6 +323,12 @@ psi_status prepare(psi_operator* op, int tile, int S, int form, hipStream_t st, 
   psi_status s = ensure_schedule(op, tile, st);
   if (s != PSI_OK) return s;
   op->seg_form = 0;
+  if (form == kSegBins) {
+    s = ensure_bins(op, st);
+    if (s != PSI_OK) return s;
+    op->seg_form = kSegBins;
+    return PSI_OK;
+  }
   if (form == kSegBands) {
     if (!wlog) wlog = op->band_built ? op->band_wlog : kBandMaxLog;
     if (!rows) rows = op->band_built ? op->band_rows : 2048;
@@ -389,7 +401,7 @@ psi_status solve(psi_operator* op, const psi_params* prm, const double* s0, doub
   s = resolve_form(op, prm->seg_form, prm->col_segments, prm->precision, S,
                    prm->precision == PSI_PREC_FP64 ? 8 : 4, &form);
   if (s != PSI_OK) return s;
-  if (form == kSegBands) S = 1;
+  if (form == kSegBands || form == kSegBins) S = 1;
   s = prepare_for(op, prm->precision, tile, S, form, st, prm->band_col_log, prm->band_rows);
   if (s != PSI_OK) return s;
 
@@ -785,7 +797,7 @@ psi_status step(psi_operator* op, int precision, const double* s_in, double* s_o
   int form = 0;
   s = resolve_form(op, seg_form, col_segments, precision, S, 8, &form);
   if (s != PSI_OK) return s;
-  if (form == kSegBands) S = 1;
+  if (form == kSegBands || form == kSegBins) S = 1;
   s = prepare_for(op, precision, tile, S, form, st);
   if (s != PSI_OK) return s;
   PassArgs a = base_args(op);
@@ -812,7 +824,7 @@ psi_status final_psi(psi_operator* op, const double* s_vec, double* psi_out, hip
   int form = 0;
   psi_status s = resolve_form(op, 0, 0, PSI_PREC_FP64, S, 8, &form);
   if (s != PSI_OK) return s;
-  if (form == kSegBands) S = 1;
+  if (form == kSegBands || form == kSegBins) S = 1;
   s = prepare_for(op, PSI_PREC_FP64, op->sched_items ? op->sched_items : kDefaultTileItems, S,
                   form, st);
   if (s != PSI_OK) return s;
@@ -849,8 +861,8 @@ psi_status pass_time_ex(psi_operator* op, int kind, int reps, int tile_items, in
   int form = 0;
   s = resolve_form(op, seg_form, col_segments, prec, S, kind == PSI_PASS_STEP32 ? 4 : 8, &form);
   if (s != PSI_OK) return s;
-  if (form == kSegBands) S = 1;
-  PSI_REQUIRE(!part_only || S > 1 || form == kSegBands,
+  if (form == kSegBands || form == kSegBins) S = 1;
+  PSI_REQUIRE(!part_only || (S > 1 && form != kSegBins) || form == kSegBands,
               "a partial pass needs col_segments > 1 or the band layout");
   if (form == kSegBands && !wlog && !rows) band_params(op, prec, &wlog, &rows);
   s = prepare(op, tile, S, form, st, wlog, rows);
@@ -1036,6 +1048,13 @@ psi_status autotune(psi_operator* op, int precision, int reps, int* tile_items, 
       }
     }
     op->band_pace_ticks = 0;
+    // the binned layout, when its count tables fit the workspace
+    if (op->bins_val) {
+      double ms = 0.0;
+      psi_status s = time_one(tile_s1, 1, kSegBins, 0, 0, &ms);
+      if (s == PSI_OK) keep(tile_s1, 1, kSegBins, 0, 0, ms);
+      else if (s != PSI_EINVAL && s != PSI_ENOSPACE) return s;
+    }
   }
   psi_status s = prepare(op, best_tile, best_S, best_form, st, best_wlog, best_rows);
   if (s != PSI_OK) return s;
