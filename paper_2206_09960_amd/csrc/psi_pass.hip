@@ -1022,7 +1022,36 @@ __global__ __launch_bounds__(kBlock) void k_band_split(PassArgs a, BandFixArgs f
 // streams a sixteenth of the block's entries, finds each entry's run by
 // counting run-start flags from the run before its first entry, and writes z
 // of the entry's column to slot rdelta[run] + entry.
-constexpr int kBinsUnroll = 4;  // chunks of 64 entries in flight per wave
+constexpr int kBinsUnroll = 8;        // chunks of 64 entries in flight per bin wave
+constexpr int kBinsExpandUnroll = 8;  // chunks of 64 entries a group in the expand waves
+
+// Words (column in block | run-start flag) of one group of chunks from k0.
+__device__ inline void expand_words(const uint16_t* col, uint32_t k0, uint32_t hi, int lane,
+                                    uint32_t* w) {
+#pragma unroll
+  for (int u = 0; u < kBinsExpandUnroll; ++u) {
+    const uint32_t k = k0 + u * 64 + lane;
+    w[u] = k < hi ? static_cast<uint32_t>(col[k]) : 0u;
+  }
+}
+
+// Slots of one group: each entry's run from the run-start flags counted on
+// from `run`, then rdelta[run] + entry (loads issued, not waited for).  r and
+// the slot are in range by construction; the clamps keep a damaged layout
+// from writing outside the value array.
+__device__ inline void expand_slots(const BinsArgs& b, const uint32_t* w, uint32_t k0, uint32_t hi,
+                                    int lane, int& run, uint32_t* dst) {
+  const unsigned long long upto = ~0ull >> (63 - lane);  // lanes 0..lane
+#pragma unroll
+  for (int u = 0; u < kBinsExpandUnroll; ++u) {
+    const uint32_t k = k0 + u * 64 + lane;
+    const unsigned long long fl = __ballot(k < hi && (w[u] & kBinsFirst));
+    const int r = run + __popcll(fl & upto);
+    run += __popcll(fl);
+    const uint32_t rc = static_cast<uint32_t>(min(max(r, 0), static_cast<int>(b.runs) - 1));
+    dst[u] = k < hi ? min(b.rdelta[rc] + k, b.m - 1u) : 0u;
+  }
+}
 
 template <class XT>
 __global__ __launch_bounds__(kBinsExpandWaves * 64) void k_bins_expand(PassArgs a, BinsArgs b) {
@@ -1038,9 +1067,6 @@ __global__ __launch_bounds__(kBinsExpandWaves * 64) void k_bins_expand(PassArgs 
   const int64_t col0 = static_cast<int64_t>(c) << kBinsLog;
   const int64_t nc = min(static_cast<int64_t>(kBinsCols), static_cast<int64_t>(a.n_rows) - col0);
   const XT* x = static_cast<const XT*>(a.x) + col0;
-  for (int j = threadIdx.x; j < kBinsCols; j += kBinsExpandWaves * 64)
-    zl[j] = j < nc ? x[j] : XT(0);
-  __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const uint32_t lo0 = b.cs[c], ne = b.cs[c + 1] - lo0;
   const uint32_t lo =
@@ -1048,31 +1074,31 @@ __global__ __launch_bounds__(kBinsExpandWaves * 64) void k_bins_expand(PassArgs 
   const uint32_t hi =
       lo0 + static_cast<uint32_t>((static_cast<uint64_t>(ne) * (wave + 1)) / kBinsExpandWaves);
   int run = b.task[c * kBinsExpandWaves + wave];
-  const unsigned long long upto = ~0ull >> (63 - lane);  // lanes 0..lane
+  // the first groups' words and slots in flight while z is loaded
+  constexpr uint32_t G = 64 * kBinsExpandUnroll;
+  uint32_t w0[kBinsExpandUnroll], w1[kBinsExpandUnroll], d0[kBinsExpandUnroll];
+  expand_words(b.col, lo, hi, lane, w0);
+  expand_words(b.col, lo + G, hi, lane, w1);
+  for (int j = threadIdx.x; j < kBinsCols; j += kBinsExpandWaves * 64)
+    zl[j] = j < nc ? x[j] : XT(0);
+  expand_slots(b, w0, lo, hi, lane, run, d0);
+  __syncthreads();
   XT* out = static_cast<XT*>(b.val);
-  for (uint32_t k0 = lo; k0 < hi; k0 += 64 * kBinsUnroll) {
-    uint32_t w[kBinsUnroll];
+  // three stages: words two groups ahead, slots one group ahead, stores now
+  for (uint32_t k0 = lo; k0 < hi; k0 += G) {
+    uint32_t w2[kBinsExpandUnroll], d1[kBinsExpandUnroll];
+    if (k0 + 2 * G < hi) expand_words(b.col, k0 + 2 * G, hi, lane, w2);
+    if (k0 + G < hi) expand_slots(b, w1, k0 + G, hi, lane, run, d1);
 #pragma unroll
-    for (int u = 0; u < kBinsUnroll; ++u) {
+    for (int u = 0; u < kBinsExpandUnroll; ++u) {
       const uint32_t k = k0 + u * 64 + lane;
-      w[u] = k < hi ? static_cast<uint32_t>(b.col[k]) : 0u;
-    }
-    uint32_t dst[kBinsUnroll];
-#pragma unroll
-    for (int u = 0; u < kBinsUnroll; ++u) {
-      const uint32_t k = k0 + u * 64 + lane;
-      const unsigned long long fl = __ballot(k < hi && (w[u] & kBinsFirst));
-      const int r = run + __popcll(fl & upto);
-      run += __popcll(fl);
-      // r and the slot are in range by construction; the clamps keep a
-      // damaged layout from writing outside the value array
-      const uint32_t rc = static_cast<uint32_t>(min(max(r, 0), static_cast<int>(b.runs) - 1));
-      dst[u] = k < hi ? min(b.rdelta[rc] + k, b.m - 1u) : 0u;
+      if (k < hi) out[d0[u]] = zl[w0[u] & (kBinsCols - 1)];
     }
 #pragma unroll
-    for (int u = 0; u < kBinsUnroll; ++u) {
-      const uint32_t k = k0 + u * 64 + lane;
-      if (k < hi) out[dst[u]] = zl[w[u] & (kBinsCols - 1)];
+    for (int u = 0; u < kBinsExpandUnroll; ++u) {
+      w0[u] = w1[u];
+      d0[u] = d1[u];
+      w1[u] = w2[u];
     }
   }
 }
