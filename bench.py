@@ -67,12 +67,12 @@ DESCRIPTIONS = {
 def algorithmic_bytes(kind: str, n: int, m: int, segs: int = 1) -> int:
     """Compulsory HBM bytes of one pass (each array touched once): the
     per-edge and per-user figures of the scope table's roofline."""
-    if kind in ("step64", "part64", "band64"):  # col 4M; row_ptr 4, z 8, c 8, mu 8, invden 8,
-        return 4 * m + 44 * n                   # s_new 8 (the factored FP64 pass)
+    if kind in ("step64", "part64", "band64", "bins64"):  # col 4M; row_ptr 4, z 8, c 8,
+        return 4 * m + 44 * n                   # mu 8, invden 8, s_new 8 (factored FP64 pass)
     if kind == "step64_w":   # col 4M + val 8M; row_ptr 4, s 8, c 8, s_new 8
         return 12 * m + 28 * n
-    if kind in ("step32", "part32", "band32"):  # col 4M; row_ptr 4, ze 4, r 4, mu 4, invden 4,
-        return 4 * m + 32 * n                   # e_old 4, e_new 4, ze_new 4 (FP32 correction)
+    if kind in ("step32", "part32", "band32", "bins32"):  # col 4M; row_ptr 4, ze 4, r 4,
+        return 4 * m + 32 * n                   # mu 4, invden 4, e_old 4, e_new 4, ze_new 4 (FP32)
     if kind == "final64":    # col 4M; row_ptr 4, z 8, lam 8, d 8, psi 8
         return 4 * m + 36 * n
     raise ValueError(kind)
@@ -301,7 +301,16 @@ def run_single(args, name):
                for k, v in launch.items()}
     kind = "step32" if mixed else "step64"
     reps = max(3, min(50, int(2000 / max(pass_ms[kind], 0.01))))
-    if form == "bands":
+    if form == "bins":
+        # the binned pass is two streaming launches and the small closing
+        # kernel: its roofline is that of the whole pass (HIP events around
+        # the three launches on their stream)
+        dom = "bins32" if mixed else "bins64"
+        kernel = (f"k_bins_expand<{'float' if mixed else 'double'}> + "
+                  f"k_bins<{3 if mixed else 0}, 1280, 4> + k_band_fix<{3 if mixed else 0}>")
+        dom_ms = pass_ms[kind]
+        launches = 1
+    elif form == "bands":
         dom = "band32" if mixed else "band64"
         kernel = f"k_band<{3 if mixed else 0}, {bands['rows']}, 4>"
         dom_ms = op.pass_time("part32" if mixed else "part64", reps=reps, seg_form="bands")
@@ -369,7 +378,7 @@ def run_single(args, name):
         "speedup_vs_plain_fp64_by_mode": {p: round(modes["fp64_weighted"]["ms"] / v["ms"], 3)
                                           for p, v in modes.items()},
         "gteps_per_pass": {k: round(m / (v * 1e-3) / 1e9, 1) for k, v in pass_ms.items()
-                           if not k.startswith(("band", "part"))},
+                           if not k.startswith(("band", "part", "bins"))},
         "pass_us": {k: round(v * 1e3, 2) for k, v in pass_ms.items()},
         "roofline": roofline,
         "warm_start": warm,

@@ -53,9 +53,14 @@ psi_status psi_gather_probe(const double* x, int64_t n_x, int32_t col_segments,
  * combine kernel when col_segments > 1) for every supported tile_items
  * (1024, 1536, 2048, 3072, 4096) and col_segments (1, 2, 4, 8; 1 only for
  * the weighted form), and for col_segments > 1 in both partial-pass forms
- * (the sliced form once, it has no tiles), with hipEvents on `stream`, and
- * keeps the fastest in the operator: later psi_solve calls in that precision
- * whose psi_params leave tile_items / col_segments / seg_form at 0 use it.  reps = 0 picks about 20 ms
+ * (the sliced form once, it has no tiles); outside the weighted form also
+ * the band layout (both column widths at every row-block size, then each
+ * row-block size paced) and the binned layout (when its count tables fit its
+ * workspace); with hipEvents on `stream`.  It keeps the fastest in the
+ * operator: later psi_solve calls in that precision whose psi_params leave
+ * tile_items / col_segments / seg_form at 0 use it.  The fastest band layout
+ * and pacing are kept as well, for calls that ask for the band layout
+ * (psi_solve_async) whichever form won.  reps = 0 picks about 20 ms
  * of passes per candidate (at least 3).  Writes the choice and its mean pass
  * time (ms) to the host pointers, each of which may be NULL.  Overwrites the
  * operator's solve state; blocks.  Single-graph operators only. */

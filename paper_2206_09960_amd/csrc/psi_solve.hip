@@ -958,8 +958,19 @@ psi_status autotune(psi_operator* op, int precision, int reps, int* tile_items, 
     }
     return pass_time_ex(op, kind, r, tile, S, form, wlog, rows, ms, st);
   };
+  // the fastest band layout on its own: the asynchronous sweeps run in it
+  // whichever form wins the passes
+  double band_best = 0.0;
+  int band_wlog = 0, band_rows = 0;
+  unsigned long long band_pace = 0;
   auto keep = [&](int tile, int S, int form, int wlog, int rows, double ms,
                   unsigned long long pace = 0) {
+    if (form == kSegBands && (band_wlog == 0 || ms < band_best)) {
+      band_best = ms;
+      band_wlog = wlog;
+      band_rows = rows;
+      band_pace = pace;
+    }
     if (best_tile == 0 || ms < best) {
       best = ms;
       best_tile = tile;
@@ -1061,9 +1072,9 @@ psi_status autotune(psi_operator* op, int precision, int reps, int* tile_items, 
   op->tuned_tile[precision] = best_tile;
   op->tuned_S[precision] = best_S;
   op->tuned_form[precision] = best_form;
-  op->tuned_band_wlog[precision] = best_wlog;
-  op->tuned_band_rows[precision] = best_rows;
-  op->tuned_band_pace[precision] = best_pace;
+  op->tuned_band_wlog[precision] = band_wlog;
+  op->tuned_band_rows[precision] = band_rows;
+  op->tuned_band_pace[precision] = band_pace;
   op->band_pace_ticks = best_form == kSegBands ? best_pace : 0ull;
   if (tile_items) *tile_items = best_tile;
   if (col_segments) *col_segments = best_S;

@@ -25,12 +25,13 @@ def test_algorithmic_bytes_count_each_array_once():
     each) — the factored pass's 4M + 44N — or the weighted pass's 12M + 28N."""
     n, m = 1000, 20000
     assert bench.algorithmic_bytes("step64", n, m) == 4 * m + 44 * n
-    for k in ("part64", "band64"):  # the gather kernel of a pass carries the pass's bytes
+    for k in ("part64", "band64", "bins64"):  # the gather kernel(s) carry the pass's bytes
         assert bench.algorithmic_bytes(k, n, m) == bench.algorithmic_bytes("step64", n, m)
     assert bench.algorithmic_bytes("step64_w", n, m) == 12 * m + 28 * n
     assert bench.algorithmic_bytes("final64", n, m) == 4 * m + (4 + 4 * 8) * n
     assert bench.algorithmic_bytes("step32", n, m) == 4 * m + 32 * n
     assert bench.algorithmic_bytes("band32", n, m) < bench.algorithmic_bytes("band64", n, m)
+    assert bench.algorithmic_bytes("bins32", n, m) == bench.algorithmic_bytes("step32", n, m)
 
 
 def test_batched_bytes_read_the_pattern_once():

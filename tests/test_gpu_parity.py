@@ -574,8 +574,8 @@ def test_autotune_picks_a_supported_schedule_that_solves_use(gpu_lib):
         t = op.autotune(prec, reps=3)
         assert t["tile_items"] in (1024, 1536, 2048, 3072, 4096)
         assert t["col_segments"] in (1, 2, 4, 8) and t["pass_ms"] > 0
-        assert t["seg_form"] in ("none", "tiles", "slices", "bands")
-        if t["seg_form"] != "bands":
+        assert t["seg_form"] in ("none", "tiles", "slices", "bands", "bins")
+        if t["seg_form"] not in ("bands", "bins"):
             assert t["seg_form"] == ("none" if t["col_segments"] == 1 else t["seg_form"])
         psi, info = op.solve(tol=1e-10, precision=prec)
         assert info["status"] == 0
