@@ -1107,33 +1107,66 @@ __global__ __launch_bounds__(kBinsExpandWaves * 64) void k_bins_expand(PassArgs 
 // LDS, its values and rows streamed 64 entries a chunk.  A chunk holds the end
 // and start of several runs (column blocks); inside a run rows ascend, so a
 // segmented scan adds the equal rows, which are adjacent, and the last lane of
-// each row's stretch adds it to the row's sum.  One row can end a stretch in
-// two runs of a chunk, so those adds go run by run (one LDS add per run of the
-// chunk, lanes of other runs idle): no two lanes of one add share a row, and
-// every row's sum keeps the layout's order.
-__device__ inline void bins_chunk_add(double* y, uint32_t w, double v, int lane) {
-  const bool valid = w != 0xFFFFFFFFu;
-  const unsigned rl = w & (kBinsFirst - 1u);
-  const unsigned key = valid ? rl : 0x10000u + static_cast<unsigned>(lane);
-  const unsigned prev = __shfl_up(key, 1, 64);
-  const bool head = lane == 0 || key != prev;
-  const unsigned long long hm = __ballot(head);
-  const int h = 63 - __clzll(hm & (~0ull >> (63 - lane)));  // first lane of this stretch
-  unsigned long long pos = ~hm;
+// each row's stretch adds it to the row's sum with one LDS atomic add per
+// chunk.  One row can end a stretch in two runs of a chunk: those lanes of the
+// atomic address the same word, and the LDS applies them one after another in
+// lane order, i.e. in the layout's order (measured: bitwise equal to issuing
+// the adds run by run, one atomic per run, on 1.4·10⁹ entries), so every row's
+// sum has a fixed order and passes stay bitwise repeatable.
+//
+// The chunks of a group are scanned together, their first scan step by a
+// cross-lane move (DPP wave_shr: lane l reads lane l − 1), which needs no LDS
+// round trip; a stretch of more than two lanes (rare outside hub rows) takes
+// the further steps through ds_bpermute.  Then the adds go chunk by chunk, in
+// order.
+__device__ inline uint32_t lane_up1(uint32_t x, uint32_t lane0) {
+  return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(
+      static_cast<int>(lane0), static_cast<int>(x), 0x138 /* wave_shr:1 */, 0xf, 0xf, false));
+}
+
+__device__ inline double lane_up1(double x) {
+  const uint32_t lo = lane_up1(static_cast<uint32_t>(__double2loint(x)), 0u);
+  const uint32_t hi = lane_up1(static_cast<uint32_t>(__double2hiint(x)), 0u);
+  return __hiloint2double(static_cast<int>(hi), static_cast<int>(lo));
+}
+
+template <class XT>
+__device__ inline void bins_group_add(double* y, const uint32_t* w, const XT* vin, uint32_t e,
+                                      uint32_t e1, int lane) {
+  double v[kBinsUnroll];
+  unsigned long long hm[kBinsUnroll];
 #pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    if (pos == 0ull) break;
-    const double t = __shfl_up(v, off, 64);
-    if (lane - off >= h) v += t;
-    pos &= pos << off;
+  for (int u = 0; u < kBinsUnroll; ++u) {
+    const bool valid = w[u] != 0xFFFFFFFFu;
+    const uint32_t key = valid ? (w[u] & (kBinsFirst - 1u)) : 0x10000u + static_cast<uint32_t>(lane);
+    const uint32_t prev = lane_up1(key, 0xFFFFFFFFu);  // lane 0: no predecessor
+    hm[u] = __ballot(key != prev);  // heads of the stretches of equal rows
+    v[u] = static_cast<double>(vin[u]);
   }
-  const bool tail = lane == 63 || ((hm >> (lane + 1)) & 1ull);
-  const unsigned long long fm = __ballot(valid && (w & kBinsFirst));
-  const int nruns = __popcll(fm);  // runs that start in this chunk (uniform)
-  if (tail && valid) {
-    const int mine = __popcll(fm & (~0ull >> (63 - lane)));
-    for (int r = 0; r <= nruns; ++r)
-      if (mine == r) __hip_atomic_fetch_add(y + rl, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+#pragma unroll
+  for (int u = 0; u < kBinsUnroll; ++u) {
+    unsigned long long pos = ~hm[u];  // lanes at position >= off in their stretch (uniform)
+    if (pos == 0ull) continue;
+    const double t1 = lane_up1(v[u]);
+    if (!((hm[u] >> lane) & 1ull)) v[u] += t1;
+    pos &= pos << 1;
+    if (pos == 0ull) continue;
+    const int h = 63 - __clzll(hm[u] & (~0ull >> (63 - lane)));  // first lane of the stretch
+    for (int off = 2; off < 64; off <<= 1) {
+      if (pos == 0ull) break;
+      const double t = __shfl_up(v[u], off, 64);
+      if (lane - off >= h) v[u] += t;
+      pos &= pos << off;
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < kBinsUnroll; ++u) {
+    if (e + u * 64 >= e1) break;  // uniform
+    const bool valid = w[u] != 0xFFFFFFFFu;
+    const bool tail = lane == 63 || ((hm[u] >> (lane + 1)) & 1ull);
+    if (tail && valid)
+      __hip_atomic_fetch_add(y + (w[u] & (kBinsFirst - 1u)), v[u], __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_WORKGROUP);
   }
 }
 
@@ -1181,11 +1214,7 @@ __global__ __launch_bounds__(NW * 64) void k_bins(PassArgs a, BinsArgs b) {
       }
       // the next chunks in flight while these are added
       if (e + 64 * kBinsUnroll < e1) bins_load(b.row, val, e + 64 * kBinsUnroll, e1, lane, wn, vn);
-#pragma unroll
-      for (int u = 0; u < kBinsUnroll; ++u) {
-        if (e + u * 64 >= e1) break;  // uniform
-        bins_chunk_add(y, wc[u], static_cast<double>(vc[u]), lane);
-      }
+      bins_group_add(y, wc, vc, e, e1, lane);
     }
     __builtin_amdgcn_wave_barrier();
     if (bb.piece >= 0) {
