@@ -85,7 +85,7 @@ typedef enum psi_status {
  * than the caches.
  * BINS is another layout of its own for iterates larger than the caches
  * (single-graph operators; FP64 factored, FP32 and final passes): followers
- * are cut into blocks of 2^14 users and leaders into bins of at most 1280
+ * are cut into blocks of 20,480 users and leaders into bins of at most 1280
  * rows.  A pass is two streaming launches: the first reads each follower
  * block's slice of the iterate into LDS and writes one value per edge, in
  * the order the bins read them (8 bytes an edge, 4 in FP32 passes); the

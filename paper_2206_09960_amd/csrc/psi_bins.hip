@@ -5,8 +5,8 @@
 // a cache line for 8 useful bytes.  The binned pass reorders the work so that
 // every read of z comes from LDS and everything else streams (propagation
 // blocking, Beamer, Asanović and Patterson, IPDPS 2017):
-//   * followers are cut into column blocks of 2^kBinsLog users (128 KB of
-//     FP64 z, one workgroup's LDS); leaders into bins, row blocks of at most
+//   * followers are cut into column blocks of kBinsCols users (160 KB of
+//     FP64 z, a CU's whole LDS); leaders into bins, row blocks of at most
 //     kBinsRows rows and an edge budget, planned as the band layout's (a row
 //     longer than the budget becomes pieces, each its own bin, added in order
 //     afterwards);
@@ -14,7 +14,7 @@
 //     (row, column);
 //   * expand launch: one workgroup per column block loads the block's z into
 //     LDS, then streams the block's entries (its runs, bins in order; each a
-//     16-bit column within the block) and writes z of each entry to the
+//     15-bit column within the block) and writes z of each entry to the
 //     entry's slot in bin order: a run's slots are consecutive, so a run is
 //     one contiguous write;
 //   * bin launch: one wave per bin streams the bin's values and 16-bit rows
@@ -55,7 +55,7 @@ __global__ __launch_bounds__(kBlock) void k_bins_count(const int* col, const Ban
   __syncthreads();
   const int e_lo = blocks[b].e_lo, e_hi = blocks[b + 1].e_lo;
   for (int e = e_lo + static_cast<int>(threadIdx.x); e < e_hi; e += kBlock)
-    atomicAdd(&hist[col[e] >> kBinsLog], 1u);
+    atomicAdd(&hist[col[e] / kBinsCols], 1u);
   __syncthreads();
   for (int c = threadIdx.x; c < B; c += kBlock) cnt[int64_t(b) * B + c] = hist[c];
 }
@@ -175,7 +175,7 @@ __global__ __launch_bounds__(64) void k_bins_fill(const int* row_ptr, const int*
       }
       rl = lo;
     }
-    const int c = valid ? (j >> kBinsLog) : 0;
+    const int c = valid ? (j / kBinsCols) : 0;
     unsigned long long peers = __ballot(valid);
     for (int bit = 0; bit < cbits; ++bit) {
       const bool one = (c >> bit) & 1;
@@ -189,7 +189,7 @@ __global__ __launch_bounds__(64) void k_bins_fill(const int* row_ptr, const int*
       const uint16_t first = rank == 0u ? static_cast<uint16_t>(kBinsFirst) : uint16_t(0);
       rows16[p2[int64_t(b) * B + c] + rank] = static_cast<uint16_t>(rl) | first;
       cols16[p1[int64_t(c) * nb + b] + rank] =
-          static_cast<uint16_t>(j & (kBinsCols - 1)) | first;
+          static_cast<uint16_t>(j - c * kBinsCols) | first;
       if ((peers >> lane) == 1ull) cur[c] = base + static_cast<uint32_t>(__popcll(peers));
     }
     __builtin_amdgcn_wave_barrier();
@@ -239,7 +239,7 @@ psi_status ensure_bins(psi_operator* op, hipStream_t st) {
   const int64_t n = op->n;
   const int64_t m = op->m;
   PSI_REQUIRE(m < (int64_t(1) << 32) - 1, "too many edges for the binned layout");
-  const int64_t B = (n + kBinsCols - 1) >> kBinsLog;
+  const int64_t B = (n + kBinsCols - 1) / kBinsCols;
   PSI_REQUIRE(B >= 1 && B <= kBinsMaxB && B <= op->cap_bins_cols,
               "too many column blocks for the binned layout");
   std::vector<int> rp(n + 1);

@@ -878,7 +878,7 @@ static void layout_persistent(int64_t n, int64_t m_raw, int n_graphs, uint32_t f
   // <= 3·ceil(N/1024) + 1 of them (R >= 1024); runs are the non-empty
   // (column block, bin) pairs
   const bool bins = n_graphs == 1;
-  const int64_t bins_cols = bins ? std::max<int64_t>(1, (n + kBinsCols - 1) >> kBinsLog) : 0;
+  const int64_t bins_cols = bins ? std::max<int64_t>(1, (n + kBinsCols - 1) / kBinsCols) : 0;
   const int64_t cap_bins_blocks = bins ? 3 * ((n + 1023) / 1024) + 8 : 0;
   const int64_t cap_bins_runs =
       bins ? std::min<int64_t>(cap_bins_blocks * bins_cols, std::max<int64_t>(m_raw, 1)) : 0;

@@ -242,13 +242,13 @@ struct BandFixArgs {
 };
 
 // Binned ("propagation-blocked") pass, psi_bins.hip.  Followers are cut into
-// column blocks of 2^kBinsLog users, whose z a workgroup holds in LDS; leaders
+// column blocks of kBinsCols users, whose z a workgroup holds in LDS; leaders
 // into bins (row blocks of at most kBinsRows rows, planned as the band
 // layout's).  An expand kernel streams each column block's entries, reads z
 // from LDS and writes the values in the order a bin reads them; a bin kernel
 // then streams each bin's values and adds them to its rows' sums in LDS.
-constexpr int kBinsLog = 14;
-constexpr int kBinsCols = 1 << kBinsLog;
+constexpr int kBinsCols = 20480;       // 160 KB of FP64 z: a CU's whole LDS
+constexpr uint32_t kBinsColMask = 0x7FFFu;  // column in block (15 bits) of an expand word
 constexpr int kBinsMaxB = 16384;        // column blocks (LDS of the layout build)
 constexpr int kBinsRows = 1280;         // rows per bin (a wave's sums: 10 KB of LDS)
 constexpr int kBinsMinEdges = 4096;     // smallest edge budget of a bin
@@ -548,7 +548,7 @@ struct psi_operator {
   int64_t cap_band_blocks = 0, cap_band_toff = 0, cap_band_cols = 0;
   // binned layout (psi_bins.hip), built on first use
   bool bins_built = false;
-  int bins_B = 0;                    // column blocks of 2^kBinsLog users
+  int bins_B = 0;                    // column blocks of kBinsCols users
   int bins_nb = 0;                   // bins
   int bins_n_split = 0;              // rows cut into pieces
   int64_t bins_runs = 0;             // non-empty (column block, bin) runs

@@ -1014,7 +1014,7 @@ __global__ __launch_bounds__(kBlock) void k_band_split(PassArgs a, BandFixArgs f
 // -------------------------------------------------------------- binned form
 // Two streaming launches per pass over the binned layout (psi_bins.hip).
 //
-// Expand: one workgroup per column block of 2^14 users.  Workgroups go to the
+// Expand: one workgroup per column block of 20,480 users.  Workgroups go to the
 // XCDs round-robin, so blockIdx mod 8 picks the XCD and each XCD takes a
 // contiguous range of column blocks in order: the runs that neighbouring
 // column blocks write into one bin lie side by side in bin order, and their
@@ -1064,7 +1064,7 @@ __global__ __launch_bounds__(kBinsExpandWaves * 64) void k_bins_expand(PassArgs 
   if (a.respect_done && pass_cancelled(a.ctrl, a.pass_id, false)) return;
   const int c = static_cast<int>(blockIdx.x & 7) * b.per_xcd + static_cast<int>(blockIdx.x >> 3);
   if (c >= b.B) return;  // uniform across the workgroup
-  const int64_t col0 = static_cast<int64_t>(c) << kBinsLog;
+  const int64_t col0 = static_cast<int64_t>(c) * kBinsCols;
   const int64_t nc = min(static_cast<int64_t>(kBinsCols), static_cast<int64_t>(a.n_rows) - col0);
   const XT* x = static_cast<const XT*>(a.x) + col0;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -1092,7 +1092,7 @@ __global__ __launch_bounds__(kBinsExpandWaves * 64) void k_bins_expand(PassArgs 
 #pragma unroll
     for (int u = 0; u < kBinsExpandUnroll; ++u) {
       const uint32_t k = k0 + u * 64 + lane;
-      if (k < hi) out[d0[u]] = zl[w0[u] & (kBinsCols - 1)];
+      if (k < hi) out[d0[u]] = zl[w0[u] & kBinsColMask];
     }
 #pragma unroll
     for (int u = 0; u < kBinsExpandUnroll; ++u) {

@@ -3,7 +3,7 @@
 Rows of every kind the layout has to handle: a hub row cut into pieces over
 several follower blocks, rows at and one past a bin's edge budget, a row in
 the last follower block, the last user, users with no followers; one and
-many follower blocks of 2^14 users, bins whose chunks hold the same row in
+many follower blocks of 20,480 users, bins whose chunks hold the same row in
 two runs (the adds go run by run), and degenerate operators.  One pass is
 compared element by element (rtol 1e-13) and bit for bit between repeats;
 solves to the oracle's Algorithm 2 at the same tolerance (1e-9 relative L1,
@@ -36,15 +36,15 @@ def graph_with_rows(n, rows, m_background, seed):
 
 
 def special_graph():
-    # N = 300,000: 19 follower blocks; about 4 edges a user, so a bin's edge
+    # N = 300,000: 15 follower blocks; about 4 edges a user, so a bin's edge
     # budget is max(4096, 2.5 · 1280 · M/N) ≈ 11,900
     n = 300_000
     rows = [(5, 0, 150_000),          # hub over ten follower blocks: about twelve pieces
-            (9, 16_000, 11_000),      # just under the budget, across a follower-block edge
+            (9, 20_000, 11_000),      # just under the budget, across a follower-block edge
             (12, 100_000, 40_000),    # a few pieces
             (15, 290_000, 9_999),     # into the last follower block
             (n - 1, 10, 5_000),       # the last user
-            (77, 16_383, 2)]          # the two users around the first follower-block edge
+            (77, 20_479, 2)]          # the two users around the first follower-block edge
     return graph_with_rows(n, rows, 3 * n, 11)
 
 
@@ -98,7 +98,7 @@ def test_bins_solves_every_precision(gpu_lib, prec, tol, bar, elem):
 
 
 def test_bins_many_blocks_against_the_c_oracle(gpu_lib):
-    """5·10⁶ users: 306 follower blocks and thousands of bins; every user
+    """5·10⁶ users: 245 follower blocks and thousands of bins; every user
     against the C oracle, and one pass element by element."""
     api = gpu_lib
     g = synth.chung_lu(5_000_000, 4, 2.1, 16, sigma=2.0)
