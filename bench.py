@@ -370,6 +370,7 @@ def run_single(args, name):
                    "tol": tol, "headline_mode": head, "layout": form,
                    "col_segments": info["col_segments"], "tile_items": info["tile_items"],
                    "band_layout": bands if form == "bands" else None,
+                   "bins_layout": op.bins_info() if form == "bins" else None,
                    "parallelism": "single GPU"},
         "time_to_psi_ms": {p: round(v["ms"], 4) for p, v in modes.items()},
         "solves_timed": {p: (args.steps if p == head else cmp_k) for p in modes},

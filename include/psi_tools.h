@@ -112,6 +112,16 @@ psi_status psi_operator_band_info(const psi_operator* op, int32_t* col_log, int3
                                   int32_t* col_blocks, int32_t* row_blocks, int32_t* bands,
                                   int32_t* split_rows);
 
+/* The binned layout built on the operator (by a call that used PSI_SEG_BINS
+ * or by psi_autotune), for reports: *col_blocks follower blocks of
+ * *block_users users, *bins bins (row blocks) of at most *rows rows,
+ * *split_rows rows cut into pieces, *runs non-empty (follower block, bin)
+ * pairs.  All zero when no binned layout is built.  Any out pointer may be
+ * NULL. */
+psi_status psi_operator_bins_info(const psi_operator* op, int32_t* block_users, int32_t* rows,
+                                  int32_t* col_blocks, int32_t* bins, int32_t* split_rows,
+                                  int64_t* runs);
+
 /* Test hook for the recovery of a bounded wait that gives up.  The passes
  * hand partial sums between workgroups through slots that the reader waits
  * for (bounded); a wait that gives up makes the blocking call that saw it

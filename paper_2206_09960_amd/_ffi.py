@@ -78,6 +78,7 @@ SIGNATURES = [
     ("psi_final", i32, [vp, vp, vp, vp]),
     ("psi_debug_force_slot_timeout", i32, [vp, i32]),
     ("psi_operator_band_info", i32, [vp] + [ctypes.POINTER(i32)] * 6),
+    ("psi_operator_bins_info", i32, [vp] + [ctypes.POINTER(i32)] * 5 + [ctypes.POINTER(i64)]),
     ("psi_pass_time", i32, [vp, i32, i32, i32, i32, i32, ctypes.POINTER(f64), vp]),
     ("psi_autotune_batched", i32, [vp, i32, i32, vp, sz, i32, ctypes.POINTER(i32),
                                    ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(f64),

@@ -185,6 +185,13 @@ class Operator:
             out[name] = self.workspace[off:off + nbytes].view(dt)
         return out
 
+    def bins_info(self) -> dict:
+        """psi_operator_bins_info: the binned layout built on the operator."""
+        v = [ctypes.c_int32() for _ in range(5)] + [ctypes.c_int64()]
+        _check(self._lib.psi_operator_bins_info(self._h, *[ctypes.byref(x) for x in v]))
+        keys = ("block_users", "rows", "col_blocks", "bins", "split_rows", "runs")
+        return {k: x.value for k, x in zip(keys, v)}
+
     def band_info(self) -> dict:
         """psi_operator_band_info: the band layout built on the operator."""
         v = [ctypes.c_int32() for _ in range(6)]

@@ -254,6 +254,22 @@ psi_status psi_operator_band_info(const psi_operator* op, int32_t* col_log, int3
   PSI_GUARD_END
 }
 
+psi_status psi_operator_bins_info(const psi_operator* op, int32_t* block_users, int32_t* rows,
+                                  int32_t* col_blocks, int32_t* bins, int32_t* split_rows,
+                                  int64_t* runs) {
+  PSI_GUARD_BEGIN
+  PSI_REQUIRE(op, "operator must not be NULL");
+  const bool b = op->bins_built;
+  if (block_users) *block_users = b ? psi::kBinsCols : 0;
+  if (rows) *rows = b ? psi::kBinsRows : 0;
+  if (col_blocks) *col_blocks = b ? op->bins_B : 0;
+  if (bins) *bins = b ? op->bins_nb : 0;
+  if (split_rows) *split_rows = b ? op->bins_n_split : 0;
+  if (runs) *runs = b ? op->bins_runs : 0;
+  return PSI_OK;
+  PSI_GUARD_END
+}
+
 psi_status psi_debug_force_slot_timeout(psi_operator* op, int32_t on) {
   PSI_GUARD_BEGIN
   PSI_REQUIRE(op, "operator must not be NULL");

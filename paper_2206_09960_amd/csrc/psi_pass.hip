@@ -1023,13 +1023,18 @@ __global__ __launch_bounds__(kBlock) void k_band_split(PassArgs a, BandFixArgs f
 // counting run-start flags from the run before its first entry, and writes z
 // of the entry's column to slot rdelta[run] + entry.
 constexpr int kBinsUnroll = 8;        // chunks of 64 entries in flight per bin wave
-constexpr int kBinsExpandUnroll = 8;  // chunks of 64 entries a group in the expand waves
+// Chunks of 64 entries a group in the expand waves: 16 with FP64 z (one
+// workgroup of 16 waves per CU, 128 registers a lane), 8 with FP32 z (two
+// workgroups per CU, 64 registers a lane).
+template <class XT>
+constexpr int expand_unroll() { return sizeof(XT) == 8 ? 16 : 8; }
 
 // Words (column in block | run-start flag) of one group of chunks from k0.
+template <int U>
 __device__ inline void expand_words(const uint16_t* col, uint32_t k0, uint32_t hi, int lane,
                                     uint32_t* w) {
 #pragma unroll
-  for (int u = 0; u < kBinsExpandUnroll; ++u) {
+  for (int u = 0; u < U; ++u) {
     const uint32_t k = k0 + u * 64 + lane;
     w[u] = k < hi ? static_cast<uint32_t>(col[k]) : 0u;
   }
@@ -1039,11 +1044,12 @@ __device__ inline void expand_words(const uint16_t* col, uint32_t k0, uint32_t h
 // from `run`, then rdelta[run] + entry (loads issued, not waited for).  r and
 // the slot are in range by construction; the clamps keep a damaged layout
 // from writing outside the value array.
+template <int U>
 __device__ inline void expand_slots(const BinsArgs& b, const uint32_t* w, uint32_t k0, uint32_t hi,
                                     int lane, int& run, uint32_t* dst) {
   const unsigned long long upto = ~0ull >> (63 - lane);  // lanes 0..lane
 #pragma unroll
-  for (int u = 0; u < kBinsExpandUnroll; ++u) {
+  for (int u = 0; u < U; ++u) {
     const uint32_t k = k0 + u * 64 + lane;
     const unsigned long long fl = __ballot(k < hi && (w[u] & kBinsFirst));
     const int r = run + __popcll(fl & upto);
@@ -1075,27 +1081,28 @@ __global__ __launch_bounds__(kBinsExpandWaves * 64) void k_bins_expand(PassArgs 
       lo0 + static_cast<uint32_t>((static_cast<uint64_t>(ne) * (wave + 1)) / kBinsExpandWaves);
   int run = b.task[c * kBinsExpandWaves + wave];
   // the first groups' words and slots in flight while z is loaded
-  constexpr uint32_t G = 64 * kBinsExpandUnroll;
-  uint32_t w0[kBinsExpandUnroll], w1[kBinsExpandUnroll], d0[kBinsExpandUnroll];
-  expand_words(b.col, lo, hi, lane, w0);
-  expand_words(b.col, lo + G, hi, lane, w1);
+  constexpr int U = expand_unroll<XT>();
+  constexpr uint32_t G = 64 * U;
+  uint32_t w0[U], w1[U], d0[U];
+  expand_words<U>(b.col, lo, hi, lane, w0);
+  expand_words<U>(b.col, lo + G, hi, lane, w1);
   for (int j = threadIdx.x; j < kBinsCols; j += kBinsExpandWaves * 64)
     zl[j] = j < nc ? x[j] : XT(0);
-  expand_slots(b, w0, lo, hi, lane, run, d0);
+  expand_slots<U>(b, w0, lo, hi, lane, run, d0);
   __syncthreads();
   XT* out = static_cast<XT*>(b.val);
   // three stages: words two groups ahead, slots one group ahead, stores now
   for (uint32_t k0 = lo; k0 < hi; k0 += G) {
-    uint32_t w2[kBinsExpandUnroll], d1[kBinsExpandUnroll];
-    if (k0 + 2 * G < hi) expand_words(b.col, k0 + 2 * G, hi, lane, w2);
-    if (k0 + G < hi) expand_slots(b, w1, k0 + G, hi, lane, run, d1);
+    uint32_t w2[U], d1[U];
+    if (k0 + 2 * G < hi) expand_words<U>(b.col, k0 + 2 * G, hi, lane, w2);
+    if (k0 + G < hi) expand_slots<U>(b, w1, k0 + G, hi, lane, run, d1);
 #pragma unroll
-    for (int u = 0; u < kBinsExpandUnroll; ++u) {
+    for (int u = 0; u < U; ++u) {
       const uint32_t k = k0 + u * 64 + lane;
       if (k < hi) out[d0[u]] = zl[w0[u] & kBinsColMask];
     }
 #pragma unroll
-    for (int u = 0; u < kBinsExpandUnroll; ++u) {
+    for (int u = 0; u < U; ++u) {
       w0[u] = w1[u];
       d0[u] = d1[u];
       w1[u] = w2[u];

@@ -69,6 +69,10 @@ def test_bins_step_and_final_match_oracle(gpu_lib, special):
         again, gap2 = op.step(torch.tensor(s_in, device="cuda"), seg_form="bins")
         torch.cuda.synchronize()
         assert torch.equal(again, out) and torch.equal(gap2, gap)
+    bi = op.bins_info()
+    assert bi["block_users"] == 20480 and bi["rows"] == 1280, bi
+    assert bi["col_blocks"] == -(-g.n // 20480) and bi["split_rows"] >= 2, bi
+    assert bi["bins"] >= -(-g.n // 1280) and 0 < bi["runs"] <= bi["bins"] * bi["col_blocks"], bi
     r = oracle.power_psi(A, B, c, d, 1e-9)
     psi, info = op.solve(tol=1e-9, seg_form="bins")
     assert info["status"] == 0 and info["seg_form"] == api.SEG_FORMS["bins"], info
