@@ -4,9 +4,9 @@ oracle's Algorithm 2 on the same graph and activity.
 Each case draws a graph (Erdős–Rényi-style with users who follow nobody,
 repeated edges and self-loops in the input, or a small Chung–Lu graph with
 hubs) and checks the plain solve in both pass forms and segment counts, the
-mixed-precision solve, Anderson acceleration, and the scenario batch in both
-precisions, each within 1e-9 relative L1 of the oracle at the same
-tolerance.
+band and binned layouts (FP64 and mixed precision), the mixed-precision
+solve, Anderson acceleration, and the scenario batch in both precisions,
+each within 1e-9 relative L1 of the oracle at the same tolerance.
 """
 import numpy as np
 import pytest
@@ -53,6 +53,11 @@ def test_all_modes_match_the_oracle(gpu_lib, seed):
         check(psi, info, f"fp64 S={segs} {form}", exact_iters=True)
     psi, info = op.solve(tol=TOL, precision="mixed")
     check(psi, info, "mixed")
+    for form in ("bands", "bins"):
+        for prec in ("fp64", "mixed"):
+            psi, info = op.solve(tol=TOL, precision=prec, seg_form=form)
+            assert info["seg_form"] == api.SEG_FORMS[form]
+            check(psi, info, f"{prec} {form}", exact_iters=prec == "fp64")
     psi, info = op.solve_anderson(tol=TOL, depth=1 + seed % 4)
     check(psi, info, "anderson")
 
