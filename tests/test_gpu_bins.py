@@ -155,3 +155,26 @@ def test_bins_refused_where_it_does_not_apply(gpu_lib):
         op.solve(tol=1e-8, precision="fp64_weighted", seg_form="bins")
     with pytest.raises(api.PsiError):
         op.pass_time("part64", reps=1, seg_form="bins")
+
+
+def test_bins_tables_that_do_not_fit_are_refused_and_skipped(gpu_lib):
+    """10⁷ users and a few hundred edges: the layout's count tables (bins ×
+    follower blocks) outgrow the value array they are built in, so the binned
+    layout is refused with an error, and the autotuner goes on without it."""
+    api = gpu_lib
+    n = 10_000_000
+    rng = np.random.default_rng(21)
+    f = rng.integers(0, n, 300).astype(np.int32)
+    l = rng.integers(0, n, 300).astype(np.int32)
+    lam = np.full(n, 1.0)
+    mu = np.full(n, 0.5)
+    op = api.Operator(n, f, l, lam, mu)
+    with pytest.raises(api.PsiError, match="count tables"):
+        op.solve(tol=1e-8, seg_form="bins")
+    t = op.autotune("fp64", reps=2)
+    assert t["seg_form"] != "bins", t
+    psi, info = op.solve(tol=1e-8)
+    assert info["status"] == 0
+    A, B, c, d = oracle.operator(n, f, l, lam, mu)
+    r = oracle.power_psi(A, B, c, d, 1e-8)
+    assert oracle.rel_l1(r["psi"], psi.cpu().numpy()) <= 1e-9
