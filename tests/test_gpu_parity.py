@@ -347,7 +347,7 @@ def test_solve_fp64_matches_oracle(gpu_lib, name, make, tol):
     assert oracle.fixed_point_residual(A, c, s_np) <= tol * 1.5 + 1e-15 * np.abs(s_np).sum()
 
 
-@pytest.mark.parametrize("segs,form", [(1, "auto"), (4, "slices"), (1, "bands")])
+@pytest.mark.parametrize("segs,form", [(1, "auto"), (4, "slices"), (1, "bands"), (1, "bins")])
 def test_resume_from_a_checkpointed_iterate_is_bitwise_equal(gpu_lib, segs, form):
     """A solve stopped by max_iter (PSI_ENOTCONV) returns its iterate s_k;
     restarting from it (used as given) runs the remaining steps of eq.
@@ -369,7 +369,7 @@ def test_resume_from_a_checkpointed_iterate_is_bitwise_equal(gpu_lib, segs, form
     assert torch.equal(s2, s) and torch.equal(psi2, psi)
 
 
-@pytest.mark.parametrize("segs,form", [(1, "auto"), (4, "slices"), (4, "tiles")])
+@pytest.mark.parametrize("segs,form", [(1, "auto"), (4, "slices"), (4, "tiles"), (1, "bins")])
 def test_deferred_decision_stops_at_the_first_step_under_tol(gpu_lib, segs, form):
     """The solve loop decides each pass's gap in the next pass (deferred);
     single psi_step calls reduce it inside the pass.  Both run the same
@@ -402,12 +402,18 @@ def test_deferred_decision_stops_at_the_first_step_under_tol(gpu_lib, segs, form
         assert info2["iterations"] == t and torch.equal(s2, s), (check_every, info2)
 
 
-def test_star_hub_closed_form(gpu_lib):
-    """One 3M-long row: ψ_h = d_h(1 + Σ_{j≠h} c_j)/N, ψ_j = d_j/N."""
+@pytest.mark.parametrize("form", ["auto", "bins"])
+def test_star_hub_closed_form(gpu_lib, form):
+    """One 3M-long row: ψ_h = d_h(1 + Σ_{j≠h} c_j)/N, ψ_j = d_j/N (in the
+    binned layout the row is cut into hundreds of pieces over all follower
+    blocks)."""
     api = gpu_lib
     g = synth.star(3_000_001, 26)
     op = gpu_op(api, g)
-    psi, info = op.solve(tol=1e-10)
+    psi, info = op.solve(tol=1e-10, seg_form=form)
+    assert info["status"] == 0, info
+    if form == "bins":
+        assert op.bins_info()["split_rows"] == 1 and op.bins_info()["bins"] > 500
     psi = psi.cpu().numpy()
     c = g.mu / (g.lam + g.mu)
     d = g.lam / (g.lam + g.mu)
