@@ -91,8 +91,8 @@ typedef enum psi_status {
  * the order the bins read them (8 bytes an edge, 4 in FP32 passes); the
  * second adds each bin's values to its rows' sums in LDS (propagation
  * blocking).  No gather leaves LDS, at the price of writing and reading the
- * per-edge values once per pass.  Its layout costs 12 bytes per edge of the
- * operator's workspace plus a run table.
+ * per-edge values once per pass.  Its layout (12 bytes per edge and a run
+ * table) is reserved in every single-graph operator's workspace.
  * 0 = the tuned form (psi_autotune), else SLICES when N·(8 or 4 bytes)/S is
  * at most 6 MB and TILES otherwise. */
 #define PSI_SEG_TILES   1
@@ -173,7 +173,11 @@ const char* psi_last_error(void);
 
 /* Sizes of the two device workspaces an operator build needs.
  *   persistent: holds the operator and its solve state for the operator's
- *               lifetime;
+ *               lifetime, including the layouts every pass form builds on
+ *               first use (for a single-graph operator about 36 bytes per
+ *               raw edge — CSR(Aᵀ), CSR(A), the segmented and sliced copies,
+ *               the band entries, the binned layout's values, columns and
+ *               rows — and about 220 bytes per user);
  *   scratch:    used only during psi_build_operator, free afterwards.
  * n_edges counts the raw edges, before self-loops and repeats are dropped. */
 psi_status psi_operator_workspace_size(int64_t n_users, int64_t n_edges, int32_t n_graphs,
