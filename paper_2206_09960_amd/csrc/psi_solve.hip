@@ -62,7 +62,15 @@ __global__ void k_ctrl_set(Ctrl* c, double tol, int tol_mode, int max_iter, doub
 }
 
 // Inner (FP32 correction) solve: stop when ‖e_k − e_{k−1}‖₁ ≤ η‖r‖₁.
+// The correction solve e = Aᵀe + r stops at eta·‖r‖₁, or at half the outer
+// tolerance (in L1 units) when that is larger: after the correction the
+// outer residual is about the correction's last step, so solving it below
+// the outer tolerance buys nothing (the last refinement would otherwise run
+// several passes past what the outer test needs).
 __global__ void k_ctrl_inner(const Ctrl* outer, Ctrl* inner, double eta, int max_iter) {
+  double target = outer->tol;  // the outer test in L1 units
+  if (outer->tol_mode == PSI_TOL_BNORM) target = outer->bnorm > 0.0 ? outer->tol / outer->bnorm : 0.0;
+  else if (outer->tol_mode == PSI_TOL_REL_L1) target = outer->tol * outer->snorm;
   inner->ticket = 0;
   inner->done = 0;
   inner->done_pass = -1;
@@ -71,7 +79,7 @@ __global__ void k_ctrl_inner(const Ctrl* outer, Ctrl* inner, double eta, int max
   inner->status = 0;
   inner->gap = 0.0;
   inner->l1 = 0.0;
-  inner->tol = eta * outer->l1;
+  inner->tol = fmax(eta * outer->l1, 0.5 * target);
   inner->tol_mode = PSI_TOL_ABS_L1;
   inner->max_iter = max_iter;
   inner->bnorm = 1.0;
