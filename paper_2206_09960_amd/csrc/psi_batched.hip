@@ -739,7 +739,9 @@ __global__ void k_bctrl_init(BatchCtrl* bc, double tol, int max_iter) {
 }
 
 // Control block of a correction solve: scenario k runs to η·‖r^k‖₁ (its last
-// FP64 gap); scenarios already finished are frozen from the start.
+// FP64 gap), or to half its own L1 tolerance when that is larger (solving the
+// correction below what the outer test asks buys nothing); scenarios already
+// finished are frozen from the start.
 __global__ void k_bctrl_inner(BatchCtrl* in, const BatchCtrl* out, double eta, int max_iter,
                               int Kc) {
   in->c = Ctrl{};
@@ -751,7 +753,7 @@ __global__ void k_bctrl_inner(BatchCtrl* in, const BatchCtrl* out, double eta, i
     in->kiter[k] = 0;
     in->kstatus[k] = PSI_OK;
     in->kgap[k] = 0.0;
-    in->ktol[k] = eta * out->kgap[k];
+    in->ktol[k] = fmax(eta * out->kgap[k], 0.5 * out->ktol[k]);
     all &= dn;
   }
   in->c.done = all;
@@ -917,11 +919,12 @@ __global__ void k_graph_reset(int n_graphs, int* gdone, int* gskip, int* giter, 
 }
 
 // The correction solves of a mixed-precision graph batch: graph g runs to
-// eta·‖r_g‖₁ (its last FP64 gap); graphs already finished are frozen from the
-// start.
+// eta·‖r_g‖₁ (its last FP64 gap), or to half the batch's L1 tolerance when
+// that is larger; graphs already finished are frozen from the start.
 __global__ void k_graph_inner_init(int n_graphs, const int* gdone, const double* ggap, double eta,
-                                   int* gdone2, int* gskip2, int* giter2, int* gstatus2,
-                                   double* ggap2, double* gtol, Ctrl* ctrl2, int max_iter) {
+                                   double tol, int* gdone2, int* gskip2, int* giter2,
+                                   int* gstatus2, double* ggap2, double* gtol, Ctrl* ctrl2,
+                                   int max_iter) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g < n_graphs) {
     gdone2[g] = gdone[g];
@@ -929,7 +932,7 @@ __global__ void k_graph_inner_init(int n_graphs, const int* gdone, const double*
     giter2[g] = 0;
     gstatus2[g] = PSI_OK;
     ggap2[g] = 0.0;
-    gtol[g] = eta * ggap[g];
+    gtol[g] = fmax(eta * ggap[g], 0.5 * tol);
   }
   if (g == 0) {
     const unsigned err = ctrl2->err_flags;
@@ -1518,8 +1521,9 @@ static psi_status graph_solve(psi_operator* op, const psi_params* prm, double* p
       hipLaunchKernelGGL(k_graph_prep_inner, dim3(grid_for(n)), dim3(kBlock), 0, st, Y, X,
                          op->invden32, n, op->r32, op->e_a, op->ze_a);
       hipLaunchKernelGGL(k_graph_inner_init, dim3(grid_for(G)), dim3(kBlock), 0, st, G,
-                         op->gdone, op->ggap, eta, op->gdone + G, op->gskip + G, op->giter + G,
-                         op->gstatus + G, op->ggap + G, op->gtol, op->ctrl + 1, prm->max_iter);
+                         op->gdone, op->ggap, eta, prm->tol, op->gdone + G, op->gskip + G,
+                         op->giter + G, op->gstatus + G, op->ggap + G, op->gtol, op->ctrl + 1,
+                         prm->max_iter);
       PSI_HIP_CHECK(hipGetLastError());
       int enq = 0;
       s = loop(op->ctrl + 1, prm->max_iter, [&](int i) {

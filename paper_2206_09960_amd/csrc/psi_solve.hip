@@ -61,8 +61,7 @@ __global__ void k_ctrl_set(Ctrl* c, double tol, int tol_mode, int max_iter, doub
   c->bnorm = bnorm;
 }
 
-// Inner (FP32 correction) solve: stop when ‖e_k − e_{k−1}‖₁ ≤ η‖r‖₁.
-// The correction solve e = Aᵀe + r stops at eta·‖r‖₁, or at half the outer
+// The FP32 correction solve e = Aᵀe + r stops at eta·‖r‖₁, or at half the outer
 // tolerance (in L1 units) when that is larger: after the correction the
 // outer residual is about the correction's last step, so solving it below
 // the outer tolerance buys nothing (the last refinement would otherwise run
