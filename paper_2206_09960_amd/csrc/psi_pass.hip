@@ -1110,82 +1110,64 @@ __global__ __launch_bounds__(kBinsExpandWaves * 64) void k_bins_expand(PassArgs 
   }
 }
 
-// Bins: one wave per bin (launch order: most edges first), its rows' sums in
-// LDS, its values and rows streamed 64 entries a chunk.  A chunk holds the end
-// and start of several runs (column blocks); inside a run rows ascend, so a
-// segmented scan adds the equal rows, which are adjacent, and the last lane of
-// each row's stretch adds it to the row's sum with one LDS atomic add per
-// chunk.  One row can end a stretch in two runs of a chunk: those lanes of the
-// atomic address the same word, and the LDS applies them one after another in
-// lane order, i.e. in the layout's order (measured: bitwise equal to issuing
-// the adds run by run, one atomic per run, on 1.4·10⁹ entries), so every row's
-// sum has a fixed order and passes stay bitwise repeatable.
-//
-// The chunks of a group are scanned together, their first scan step by a
-// cross-lane move (DPP wave_shr: lane l reads lane l − 1), which needs no LDS
-// round trip; a stretch of more than two lanes (rare outside hub rows) takes
-// the further steps through ds_bpermute.  Then the adds go chunk by chunk, in
-// order.
-__device__ inline uint32_t lane_up1(uint32_t x, uint32_t lane0) {
-  return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(
-      static_cast<int>(lane0), static_cast<int>(x), 0x138 /* wave_shr:1 */, 0xf, 0xf, false));
-}
+// Bins: one wave per bin (launch order: most edges first), its values and rows
+// streamed 64 entries a chunk.
+// * A piece of a split row (one row): each lane sums its entries (lane l takes
+//   entries l, l + 64, ... in order) and one fixed butterfly joins the lanes.
+// * Whole rows: the rows' sums live in LDS, and every lane adds its entry to
+//   its row's sum, one atomic per chunk.  Lanes of one atomic that hit the
+//   same word are applied by the LDS one after another in lane order, i.e. in
+//   the layout's order (measured: bitwise equal to issuing the adds run by
+//   run on 1.4·10⁹ entries), and a wave's atomics in program order, so every
+//   row's sum has a fixed order and passes stay bitwise repeatable.
 
-__device__ inline double lane_up1(double x) {
-  const uint32_t lo = lane_up1(static_cast<uint32_t>(__double2loint(x)), 0u);
-  const uint32_t hi = lane_up1(static_cast<uint32_t>(__double2hiint(x)), 0u);
-  return __hiloint2double(static_cast<int>(hi), static_cast<int>(lo));
-}
-
+// Every lane adds its own entry to its row's sum.
 template <class XT>
-__device__ inline void bins_group_add(double* y, const uint32_t* w, const XT* vin, uint32_t e,
-                                      uint32_t e1, int lane) {
-  double v[kBinsUnroll];
-  unsigned long long hm[kBinsUnroll];
-#pragma unroll
-  for (int u = 0; u < kBinsUnroll; ++u) {
-    const bool valid = w[u] != 0xFFFFFFFFu;
-    const uint32_t key = valid ? (w[u] & (kBinsFirst - 1u)) : 0x10000u + static_cast<uint32_t>(lane);
-    const uint32_t prev = lane_up1(key, 0xFFFFFFFFu);  // lane 0: no predecessor
-    hm[u] = __ballot(key != prev);  // heads of the stretches of equal rows
-    v[u] = static_cast<double>(vin[u]);
-  }
-#pragma unroll
-  for (int u = 0; u < kBinsUnroll; ++u) {
-    unsigned long long pos = ~hm[u];  // lanes at position >= off in their stretch (uniform)
-    if (pos == 0ull) continue;
-    const double t1 = lane_up1(v[u]);
-    if (!((hm[u] >> lane) & 1ull)) v[u] += t1;
-    pos &= pos << 1;
-    if (pos == 0ull) continue;
-    const int h = 63 - __clzll(hm[u] & (~0ull >> (63 - lane)));  // first lane of the stretch
-    for (int off = 2; off < 64; off <<= 1) {
-      if (pos == 0ull) break;
-      const double t = __shfl_up(v[u], off, 64);
-      if (lane - off >= h) v[u] += t;
-      pos &= pos << off;
-    }
-  }
+__device__ inline void bins_lane_add(double* y, const uint32_t* w, const XT* vin, uint32_t e,
+                                     uint32_t e1, int lane) {
 #pragma unroll
   for (int u = 0; u < kBinsUnroll; ++u) {
     if (e + u * 64 >= e1) break;  // uniform
-    const bool valid = w[u] != 0xFFFFFFFFu;
-    const bool tail = lane == 63 || ((hm[u] >> (lane + 1)) & 1ull);
-    if (tail && valid)
-      __hip_atomic_fetch_add(y + (w[u] & (kBinsFirst - 1u)), v[u], __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (e + u * 64 + lane < e1)
+      __hip_atomic_fetch_add(y + (w[u] & (kBinsFirst - 1u)), static_cast<double>(vin[u]),
+                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   }
 }
 
-template <class XT>
+// Entries [e, e + 64·kBinsUnroll) of a bin whose entries end at end > e
+// (their rows only if ROWS): lanes past the end load the bin's last entry (in
+// range), which the adds drop by their index (no select here, so the loads
+// stay in flight).
+template <bool ROWS, class XT>
 __device__ inline void bins_load(const uint16_t* row, const XT* val, uint32_t e, uint32_t end,
                                  int lane, uint32_t* w, XT* v) {
 #pragma unroll
   for (int u = 0; u < kBinsUnroll; ++u) {
-    const uint32_t i = e + u * 64 + lane;
-    const bool ok = i < end;
-    w[u] = ok ? static_cast<uint32_t>(row[i]) : 0xFFFFFFFFu;
-    v[u] = ok ? val[i] : XT(0);
+    const uint32_t j = min(e + u * 64 + lane, end - 1u);
+    w[u] = ROWS ? row[j] : 0u;
+    v[u] = val[j];
+  }
+}
+
+// Streams the bin's entries [e0, e1), e0 < e1, a group of chunks at a time
+// with the next group in flight, and hands each group to add(w, v, e).
+template <bool ROWS, class XT, class Add>
+__device__ inline void bins_stream(const uint16_t* row, const XT* val, uint32_t e0, uint32_t e1,
+                                   int lane, Add add) {
+  uint32_t wn[kBinsUnroll];
+  XT vn[kBinsUnroll];
+  bins_load<ROWS>(row, val, e0, e1, lane, wn, vn);
+  for (uint32_t e = e0; e < e1; e += 64 * kBinsUnroll) {
+    uint32_t wc[kBinsUnroll];
+    XT vc[kBinsUnroll];
+#pragma unroll
+    for (int u = 0; u < kBinsUnroll; ++u) {
+      wc[u] = wn[u];
+      vc[u] = vn[u];
+    }
+    if (e + 64 * kBinsUnroll < e1)
+      bins_load<ROWS>(row, val, e + 64 * kBinsUnroll, e1, lane, wn, vn);
+    add(wc, vc, e);
   }
 }
 
@@ -1204,29 +1186,26 @@ __global__ __launch_bounds__(NW * 64) void k_bins(PassArgs a, BinsArgs b) {
     const int blk = b.order[slot];
     const BandBlock bb = b.blocks[blk];
     double* y = ylds[wave];
-    for (int k = lane; k < bb.nrows; k += 64) y[k] = 0.0;
-    __builtin_amdgcn_wave_barrier();
     const uint32_t e0 = b.bstart[blk], e1 = b.bstart[blk + 1];
     const XT* val = static_cast<const XT*>(b.val);
-    uint32_t wn[kBinsUnroll];
-    XT vn[kBinsUnroll];
-    bins_load(b.row, val, e0, e1, lane, wn, vn);
-    for (uint32_t e = e0; e < e1; e += 64 * kBinsUnroll) {
-      uint32_t wc[kBinsUnroll];
-      XT vc[kBinsUnroll];
-#pragma unroll
-      for (int u = 0; u < kBinsUnroll; ++u) {
-        wc[u] = wn[u];
-        vc[u] = vn[u];
-      }
-      // the next chunks in flight while these are added
-      if (e + 64 * kBinsUnroll < e1) bins_load(b.row, val, e + 64 * kBinsUnroll, e1, lane, wn, vn);
-      bins_group_add(y, wc, vc, e, e1, lane);
-    }
-    __builtin_amdgcn_wave_barrier();
     if (bb.piece >= 0) {
-      if (lane == 0) b.piece[bb.piece] = y[0];
+      double acc = 0.0;
+      const auto add = [&](const uint32_t*, const XT* v, uint32_t e) {
+#pragma unroll
+        for (int u = 0; u < kBinsUnroll; ++u)
+          if (e + u * 64 + lane < e1) acc += static_cast<double>(v[u]);
+      };
+      if (e0 < e1) bins_stream<false>(b.row, val, e0, e1, lane, add);
+      for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+      if (lane == 0) b.piece[bb.piece] = acc;
     } else {
+      for (int k = lane; k < bb.nrows; k += 64) y[k] = 0.0;
+      __builtin_amdgcn_wave_barrier();
+      const auto add = [&](const uint32_t* w, const XT* v, uint32_t e) {
+        bins_lane_add(y, w, v, e, e1, lane);
+      };
+      if (e0 < e1) bins_stream<true>(b.row, val, e0, e1, lane, add);
+      __builtin_amdgcn_wave_barrier();
       for (int k = lane; k < bb.nrows; k += 64) {
         const int r = bb.row_lo + k;
         apply_row<MODE>(a, nullptr, r, load_row<MODE>(a, r), y[k], g, sn);
