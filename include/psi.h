@@ -130,7 +130,9 @@ typedef struct psi_params {
                          /* of a segmented pass), PSI_SEG_BANDS, PSI_SEG_BINS;   */
                          /* 0 = tuned, else                                      */
                          /* from N and precision                                 */
-    double inner_tol;    /* PSI_PREC_MIXED: relative tol of each FP32 solve; 0 = default */
+    double inner_tol;    /* PSI_PREC_MIXED: each FP32 correction solve stops at
+                            inner_tol·‖r‖₁ (0 = 2e-6) or at half the outer tol in L1
+                            units, whichever is larger                           */
     int32_t band_col_log;/* PSI_SEG_BANDS: column blocks of 2^17 or 2^18 users;     */
                          /* 0 = tuned, else 18                                    */
     int32_t band_rows;   /* PSI_SEG_BANDS: rows per row block, 1024, 1280, 1536   */
@@ -326,9 +328,9 @@ psi_status psi_batched_workspace_size(const psi_operator* op, int32_t n_scenario
  * residual pass r = Aᵀs + c − s for every scenario (graph) — ‖r‖₁ is its
  * gap, the stopping test — then the FP32 correction solves e = Aᵀe + r of
  * all unfinished scenarios (graphs) together, each to
- * prm->inner_tol·‖r‖₁ (0 = 2e-6), and s ← s + e; when a refinement stops
- * shrinking some unfinished scenario's (graph's) gap fourfold the batch
- * finishes with FP64 steps.  infos[k].iterations counts the FP64 passes,
+ * max(prm->inner_tol·‖r‖₁, tol / 2) (inner_tol 0 = 2e-6), and s ← s + e;
+ * when a refinement stops shrinking some unfinished scenario's (graph's)
+ * gap fourfold the batch finishes with FP64 steps.  infos[k].iterations counts the FP64 passes,
  * fp32_passes the correction passes.
  * Both modes: PSI_TOL_ABS_L1 only; returns the first non-OK scenario/graph
  * status, if any.
