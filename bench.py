@@ -250,6 +250,13 @@ def run_single(args, name):
     assert info_aa["status"] == 0, info_aa
     modes["fp64_anderson"] = dict(ms=ms_aa, info=info_aa, psi=psi_aa.cpu().numpy())
     log(f"fp64_anderson: {ms_aa:.3f} ms/solve, {info_aa['spmv_passes']} passes")
+    # the same mixing in each FP32 correction solve of the mixed refinement
+    ms_am, (psi_am, info_am) = timed(lambda: op.solve_anderson(tol=tol, depth=4,
+                                                               precision="mixed"), cmp_k, cmp_w)
+    assert info_am["status"] == 0, info_am
+    modes["mixed_anderson"] = dict(ms=ms_am, info=info_am, psi=psi_am.cpu().numpy())
+    log(f"mixed_anderson: {ms_am:.3f} ms/solve, {info_am['spmv_passes']} passes "
+        f"({info_am['iterations']} FP64, {info_am['fp32_passes']} FP32)")
     # asynchronous local updates: block Gauss–Seidel sweeps over the band layout
     # (same fixed point and stopping test; reported beside, like Anderson)
     ms_gs, (psi_gs, info_gs) = timed(lambda: op.solve_async(tol=tol), cmp_k, cmp_w)
@@ -273,7 +280,8 @@ def run_single(args, name):
                                                     / psi64[top])))
         log(f"origins: 64 origins in {ms_o:.3f} ms, up to {max(po)} passes")
 
-    head = min((p for p in modes if p not in ("fp64_weighted", "fp64_anderson", "fp64_async")),
+    head = min((p for p in modes
+                if p not in ("fp64_weighted", "fp64_anderson", "mixed_anderson", "fp64_async")),
                key=lambda p: modes[p]["ms"])
     head_prec = head.replace("_warm", "")
     # the timed region of the reported value: K solves of the headline mode

@@ -348,11 +348,19 @@ psi_status psi_solve_batched(psi_operator* op, const psi_params* prm, int32_t n_
  * f = g − x, x ← g − ΔG γ.  The stopping test is the pass's own gap
  * ‖g − x‖₁ ≤ tol in prm->tol_mode units, and s = g is returned, so the
  * result is a Power-ψ step of size at most tol (eq. condition), as in
- * Algorithm 2; ψ = (Bᵀs + d)/N.  depth in [1, 8]; only PSI_PREC_FP64;
- * tile_items / col_segments as in psi_solve (autotuned values used).
- * s0 (device FP64 [N], may be NULL = c) is the start, used as given.
- * info->iterations counts passes (one per iteration), info->refinements
- * the window restarts.  workspace: device, at least
+ * Algorithm 2; ψ = (Bᵀs + d)/N.  depth in [1, 8].  PSI_PREC_FP64, or
+ * PSI_PREC_MIXED: the refinement of psi_solve's PSI_PREC_MIXED (FP64
+ * residual passes, the gap test and s = the last FP64 step as there), each
+ * FP32 correction solve e = Aᵀe + r accelerated by the same mixing (FP32
+ * window, FP64 dot products, an empty window per correction), to
+ * max(prm->inner_tol·‖r‖₁, half the tolerance in L1 units); when a
+ * refinement stops shrinking the gap fourfold, accelerated FP64 iterations
+ * finish.  tile_items / col_segments as in psi_solve (the precision's
+ * autotuned values used).  s0 (device FP64 [N], may be NULL = c) is the
+ * start, used as given.  info->iterations counts FP64 passes (one per
+ * iteration), fp32_passes the correction passes, info->refinements the
+ * window restarts (FP64) or the correction solves (MIXED).  workspace:
+ * device, at least
  * psi_anderson_workspace_size bytes (2·depth + 2 FP64 vectors of N plus
  * 130 KB).  Overwrites the operator's solve state; blocks. */
 psi_status psi_anderson_workspace_size(const psi_operator* op, int32_t depth, size_t* bytes);

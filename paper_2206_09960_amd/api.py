@@ -418,12 +418,14 @@ class Operator:
     def solve_anderson(self, tol: float = 1e-8, depth: int = 4, tol_mode: str = "abs_l1",
                        max_iter: int = 10000, s0: torch.Tensor | None = None,
                        check_every: int = 0, tile_items: int = 0, col_segments: int = 0,
-                       seg_form: str | int = 0,
+                       seg_form: str | int = 0, precision: str = "fp64",
+                       inner_tol: float = 0.0,
                        return_s: bool = False, stream=None, raise_on_status: bool = False):
-        """psi_solve_anderson: the same ψ with Anderson-accelerated passes;
-        returns (psi, info) or (psi, s, info)."""
-        p = self._params(tol, tol_mode, max_iter, "fp64", check_every, tile_items, col_segments,
-                         seg_form=seg_form)
+        """psi_solve_anderson: the same ψ with Anderson-accelerated passes
+        (precision "fp64", or "mixed": accelerated FP32 correction solves
+        between FP64 residual passes); returns (psi, info) or (psi, s, info)."""
+        p = self._params(tol, tol_mode, max_iter, precision, check_every, tile_items,
+                         col_segments, inner_tol=inner_tol, seg_form=seg_form)
         nbytes = ctypes.c_size_t()
         _check(self._lib.psi_anderson_workspace_size(self._h, depth, ctypes.byref(nbytes)))
         ws = self._accel_ws if getattr(self, "_accel_ws", None) is not None and \

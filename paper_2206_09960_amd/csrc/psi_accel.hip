@@ -24,6 +24,12 @@
 // factorisation fails or the gap grows tenfold); k_aa_mix (x_{k+1},
 // z = x/den).  Every reduction has a fixed order, so solves are bitwise
 // repeatable.
+//
+// In mixed precision the same mixing accelerates each FP32 correction solve
+// e = Aᵀe + r between the FP64 residual passes of the refinement (the
+// iteration of psi_solve's PSI_PREC_MIXED): the window's columns, f and g are
+// FP32, every dot product and the mixing sum are FP64, and the window starts
+// empty for every correction.
 #include <algorithm>
 #include <cmath>
 #include <limits>
@@ -63,6 +69,22 @@ struct AaWs {
   AaState* st;
 };
 
+// The window's vectors in the iterate's type (FP32 ones use the first half of
+// each FP64 array).
+template <class T>
+struct AaVecs {
+  T* dF;
+  T* dG;
+  T* f_prev;
+  T* g_prev;
+};
+
+template <class T>
+AaVecs<T> aa_vecs(const AaWs& w) {
+  return AaVecs<T>{reinterpret_cast<T*>(w.dF), reinterpret_cast<T*>(w.dG),
+                   reinterpret_cast<T*>(w.f_prev), reinterpret_cast<T*>(w.g_prev)};
+}
+
 size_t aa_layout(int64_t n, int m, AaWs* w, char* base) {
   size_t off = 0;
   auto take = [&](size_t bytes) -> char* {
@@ -94,11 +116,12 @@ __global__ void k_aa_init(AaState* s) {
 }
 
 // f = g − x; the new ΔF, ΔG column at ring slot `head`; f_prev, g_prev ← f, g;
-// partial dot products of every window column (the new one included) with
-// the new ΔF column and with f.
-__global__ __launch_bounds__(kBlock) void k_aa_diff(const double* g, const double* x, int64_t n,
-                                                    int m, AaWs w, Ctrl* ctrl, double* pairs,
-                                                    double* hist) {
+// partial dot products (FP64) of every window column (the new one included)
+// with the new ΔF column and with f.
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_aa_diff(const T* g, const T* x, int64_t n, int m,
+                                                    AaVecs<T> v, AaWs w, Ctrl* ctrl,
+                                                    double* pairs, double* hist) {
   __shared__ double red[2 * (kBlock / 64)];
   __shared__ int s_done;
   // the pass's gap: decided here, before k_aa_solve reads it
@@ -116,23 +139,23 @@ __global__ __launch_bounds__(kBlock) void k_aa_diff(const double* g, const doubl
   for (int j = 0; j < kMaxDepth; ++j) vv[j] = vb[j] = 0.0;
   for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n;
        i += int64_t(gridDim.x) * kBlock) {
-    const double gi = g[i], fi = gi - x[i];
+    const T gi = g[i], fi = gi - x[i];
     if (valid) {
-      const double df = fi - w.f_prev[i];
-      w.dF[int64_t(slot) * n + i] = df;
-      w.dG[int64_t(slot) * n + i] = gi - w.g_prev[i];
+      const T df = fi - v.f_prev[i];
+      v.dF[int64_t(slot) * n + i] = df;
+      v.dG[int64_t(slot) * n + i] = gi - v.g_prev[i];
 #pragma unroll
       for (int q = 0; q < kMaxDepth; ++q) {
         if (q < cnt) {  // window column q: q steps back from the new one
           const int sj = (slot - q + m) % m;
-          const double dj = q == 0 ? df : w.dF[int64_t(sj) * n + i];
-          vv[q] += dj * df;
-          vb[q] += dj * fi;
+          const double dj = static_cast<double>(q == 0 ? df : v.dF[int64_t(sj) * n + i]);
+          vv[q] += dj * static_cast<double>(df);
+          vb[q] += dj * static_cast<double>(fi);
         }
       }
     }
-    w.f_prev[i] = fi;
-    w.g_prev[i] = gi;
+    v.f_prev[i] = fi;
+    v.g_prev[i] = gi;
   }
   if (!valid) return;  // uniform: no dot products on the first iteration
   // all 2m sums at once: wave shuffles, one LDS round, waves added in order
@@ -272,9 +295,10 @@ __global__ __launch_bounds__(kAaSolveBlock) void k_aa_solve(AaWs w, int m, int n
     for (int j = 0; j < kMaxDepth; ++j) st->G[i][j] = Gs[i][j];
 }
 
-// x_{k+1} = g_k − ΔG γ and its gathered form z = x/den.
-__global__ __launch_bounds__(kBlock) void k_aa_mix(const double* g, const double* invden,
-                                                   int64_t n, int m, AaWs w, double* x, double* z,
+// x_{k+1} = g_k − ΔG γ (summed in FP64) and its gathered form z = x/den.
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_aa_mix(const T* g, const T* invden, int64_t n, int m,
+                                                   AaVecs<T> vw, AaWs w, T* x, T* z,
                                                    const Ctrl* ctrl) {
   if (ctrl->done) return;
   const int cnt = w.st->count;
@@ -283,15 +307,16 @@ __global__ __launch_bounds__(kBlock) void k_aa_mix(const double* g, const double
   for (int j = 0; j < kMaxDepth; ++j) gam[j] = j < m ? w.st->gamma[j] : 0.0;
   const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
   if (i >= n) return;
-  double v = g[i];
+  double v = static_cast<double>(g[i]);
   if (cnt > 0) {
     // slots outside the window have γ = 0 and may never have been written
 #pragma unroll
     for (int j = 0; j < kMaxDepth; ++j)
-      if (j < m && gam[j] != 0.0) v -= gam[j] * w.dG[int64_t(j) * n + i];
+      if (j < m && gam[j] != 0.0) v -= gam[j] * static_cast<double>(vw.dG[int64_t(j) * n + i]);
   }
-  x[i] = v;
-  z[i] = invden[i] * v;
+  const T xv = static_cast<T>(v);
+  x[i] = xv;
+  z[i] = invden[i] * xv;
 }
 
 __global__ void k_aa_start(const double* s0, const double* c, const double* invden, int64_t n,
@@ -385,7 +410,8 @@ psi_status solve_anderson(psi_operator* op, const psi_params* prm, int depth, co
   PSI_REQUIRE(prm->max_iter > 0, "max_iter must be > 0");
   PSI_REQUIRE(prm->tol_mode >= PSI_TOL_ABS_L1 && prm->tol_mode <= PSI_TOL_REL_L1,
               "unknown tol_mode");
-  PSI_REQUIRE(prm->precision == PSI_PREC_FP64, "Anderson solves run in PSI_PREC_FP64");
+  PSI_REQUIRE(prm->precision == PSI_PREC_FP64 || prm->precision == PSI_PREC_MIXED,
+              "Anderson solves run in PSI_PREC_FP64 or PSI_PREC_MIXED");
   PSI_REQUIRE(op->n_graphs == 1, "Anderson solves need a single-graph operator");
   const size_t need = aa_layout(op->n, depth, nullptr, nullptr);
   if (ws_bytes < need) {
@@ -395,15 +421,17 @@ psi_status solve_anderson(psi_operator* op, const psi_params* prm, int depth, co
   AaWs w{};
   aa_layout(op->n, depth, &w, static_cast<char*>(ws));
   const int64_t n = op->n;
-  const int prec = PSI_PREC_FP64;
+  const int prec = prm->precision;
+  const bool mixed = prec == PSI_PREC_MIXED;
+  const int xbytes = mixed ? 4 : 8;  // gathered element of the passes that dominate
   const int tuned_tile = op->tuned_tile[prec];
   const int tile = prm->tile_items ? prm->tile_items
                  : tuned_tile      ? tuned_tile
                  : (op->sched_items ? op->sched_items : kDefaultTileItems);
   PSI_REQUIRE(tile_items_supported(tile), "unsupported tile_items");
   int S = prm->col_segments ? prm->col_segments : op->tuned_S[prec];
-  if (S == 0) {  // the same rule as psi_solve for an FP64 gathered vector
-    const double xb = 8.0 * static_cast<double>(n);
+  if (S == 0) {  // the same rule as psi_solve for the gathered vector
+    const double xb = static_cast<double>(xbytes) * static_cast<double>(n);
     S = 1;
     if (xb > 3.0e6) {
       S = 2;
@@ -412,7 +440,7 @@ psi_status solve_anderson(psi_operator* op, const psi_params* prm, int depth, co
   }
   PSI_REQUIRE(S == 1 || S == 2 || S == 4 || S == 8, "col_segments must be 0, 1, 2, 4 or 8");
   int form = 0;
-  psi_status s = resolve_form(op, prm->seg_form, prm->col_segments, prec, S, 8, &form);
+  psi_status s = resolve_form(op, prm->seg_form, prm->col_segments, prec, S, xbytes, &form);
   if (s != PSI_OK) return s;
   if (form == kSegBands || form == kSegBins) S = 1;
   {
@@ -443,89 +471,187 @@ psi_status solve_anderson(psi_operator* op, const psi_params* prm, int depth, co
                      n, X, zX);
   hipLaunchKernelGGL(k_aa_ctrl, dim3(1), dim3(1), 0, st, op->ctrl, prm->tol, prm->tol_mode,
                      prm->max_iter, op->stats.b_norm);
-  hipLaunchKernelGGL(k_aa_init, dim3(1), dim3(1), 0, st, w.st);
   PSI_HIP_CHECK(hipGetLastError());
   const int dgrid = static_cast<int>(std::min<int64_t>(kAaGrid, (n + kBlock - 1) / kBlock));
   PassArgs base = base_args(op);
-  auto iteration = [&]() -> psi_status {
+  // One accelerated iteration: a pass g = Aᵀx + b from x (FP64 with b = c,
+  // or FP32 with b = r), then the window update, the small solve and the mix
+  // x ← g − ΔG γ, all under control block `ctrl`.
+  auto iteration = [&](bool fp32, Ctrl* ctrl) -> psi_status {
     PassArgs a = base;
-    a.x = zX;
-    a.s_old = X;
-    a.s_new = Gb;
-    a.z_new = zG;
+    if (fp32) {
+      a.x = op->ze_a;
+      a.r32 = op->r32;
+      a.e_old = op->e_a;
+      a.e_new = op->e_b;
+      a.ze_new = op->ze_b;
+    } else {
+      a.x = zX;
+      a.s_old = X;
+      a.s_new = Gb;
+      a.z_new = zG;
+    }
     a.count_iter = 1;
     a.respect_done = 1;
-    a.ctrl = op->ctrl;
+    a.ctrl = ctrl;
     a.defer_gap = 1;  // pairs in gap_part, decided by k_aa_diff
     a.gap_prev = op->gap_part + 2 * kMaxGrid;  // nothing is ever pending there
-    psi_status r = pass(kStep64, a);
+    psi_status r = pass(fp32 ? kStep32 : kStep64, a);
     if (r != PSI_OK) return r;
-    hipLaunchKernelGGL(k_aa_diff, dim3(dgrid), dim3(kBlock), 0, st, Gb, X, n, depth, w, op->ctrl,
-                       op->gap_part, op->hist);
-    hipLaunchKernelGGL(k_aa_solve, dim3(1), dim3(kAaSolveBlock), 0, st, w, depth, dgrid,
-                       op->ctrl);
-    hipLaunchKernelGGL(k_aa_mix, dim3(grid_for(n)), dim3(kBlock), 0, st, Gb, op->invden, n, depth,
-                       w, X, zX, op->ctrl);
+    if (fp32) {
+      const AaVecs<float> v = aa_vecs<float>(w);
+      hipLaunchKernelGGL(k_aa_diff<float>, dim3(dgrid), dim3(kBlock), 0, st, op->e_b, op->e_a, n,
+                         depth, v, w, ctrl, op->gap_part, op->hist);
+      hipLaunchKernelGGL(k_aa_solve, dim3(1), dim3(kAaSolveBlock), 0, st, w, depth, dgrid, ctrl);
+      hipLaunchKernelGGL(k_aa_mix<float>, dim3(grid_for(n)), dim3(kBlock), 0, st, op->e_b,
+                         op->invden32, n, depth, v, w, op->e_a, op->ze_a, ctrl);
+    } else {
+      const AaVecs<double> v = aa_vecs<double>(w);
+      hipLaunchKernelGGL(k_aa_diff<double>, dim3(dgrid), dim3(kBlock), 0, st, Gb, X, n, depth, v,
+                         w, ctrl, op->gap_part, op->hist);
+      hipLaunchKernelGGL(k_aa_solve, dim3(1), dim3(kAaSolveBlock), 0, st, w, depth, dgrid, ctrl);
+      hipLaunchKernelGGL(k_aa_mix<double>, dim3(grid_for(n)), dim3(kBlock), 0, st, Gb,
+                         op->invden, n, depth, v, w, X, zX, ctrl);
+    }
     PSI_HIP_CHECK(hipGetLastError());
     return PSI_OK;
   };
-  // enqueue blocks of iterations; iterations after the gap met tol exit at once
-  int enq = 0, k = prm->check_every > 0 ? prm->check_every : 4;
+  // Runs accelerated iterations from a fresh window until the gap of control
+  // block ctrl_idx meets its tolerance (iterations after that exit at once),
+  // max_iter is reached or the gap stagnates; blocks of iterations are
+  // enqueued between host checks.
+  auto accelerate = [&](bool fp32, int ctrl_idx, int max_iter, int* status) -> psi_status {
+    Ctrl* ctrl = op->ctrl + ctrl_idx;
+    Ctrl* h = op->host_ctrl + ctrl_idx;
+    hipLaunchKernelGGL(k_aa_init, dim3(1), dim3(1), 0, st, w.st);
+    PSI_HIP_CHECK(hipGetLastError());
+    int enq = 0, k = prm->check_every > 0 ? prm->check_every : 4;
+    double best = std::numeric_limits<double>::infinity();
+    int best_iter = 0;
+    *status = PSI_OK;
+    while (true) {
+      const int cnt = std::min(k, max_iter - enq);
+      for (int i = 0; i < cnt; ++i) {
+        psi_status r = iteration(fp32, ctrl);
+        if (r != PSI_OK) return r;
+      }
+      enq += cnt;
+      PSI_HIP_CHECK(hipMemcpyAsync(h, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+      PSI_HIP_CHECK(hipStreamSynchronize(st));
+      if (h->err_flags & kErrSlotTimeout) return check_waits(op, st);
+      if (h->done) {
+        *status = h->status;
+        break;
+      }
+      if (enq >= max_iter) {
+        *status = PSI_ENOTCONV;
+        break;
+      }
+      if (h->gap < best * (1.0 - 1e-3)) {
+        best = h->gap;
+        best_iter = h->iter;
+      } else if (h->iter - best_iter >= 25) {
+        *status = PSI_ESTAGNATED;
+        break;
+      }
+      if (prm->check_every == 0) k = std::min(2 * k, 16);
+    }
+    return PSI_OK;
+  };
+  psi_info inf{};
   int status = PSI_OK;
-  double best = std::numeric_limits<double>::infinity();
-  int best_iter = 0;
-  Ctrl* h = op->host_ctrl;
-  while (true) {
-    const int cnt = std::min(k, prm->max_iter - enq);
-    for (int i = 0; i < cnt; ++i) {
-      s = iteration();
-      if (s != PSI_OK) return s;
-    }
-    enq += cnt;
-    PSI_HIP_CHECK(hipMemcpyAsync(h, op->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+  const double* z_fin = zG;
+  const double* s_fin = Gb;
+  int restarts = 0;
+  if (!mixed) {
+    s = accelerate(false, 0, prm->max_iter, &status);
+    if (s != PSI_OK) return s;
+    inf.iterations = op->host_ctrl->iter;
+    AaState hs{};
+    PSI_HIP_CHECK(hipMemcpyAsync(&hs, w.st, sizeof(AaState), hipMemcpyDeviceToHost, st));
     PSI_HIP_CHECK(hipStreamSynchronize(st));
-    if (h->err_flags & kErrSlotTimeout) return check_waits(op, st);
-    if (h->done) {
-      status = h->status;
-      break;
+    restarts = hs.restarts;
+    inf.refinements = restarts;  // window restarts
+  } else {
+    // FP64 residual passes X → Gb around accelerated FP32 corrections, as
+    // psi_solve's PSI_PREC_MIXED; when a refinement stops shrinking the gap
+    // fourfold, accelerated FP64 iterations finish from Gb.
+    const double eta = prm->inner_tol > 0.0 ? prm->inner_tol : 2e-6;
+    double prev_gap = std::numeric_limits<double>::infinity();
+    int fp64_passes = 0;
+    Ctrl* h = op->host_ctrl;
+    while (true) {
+      PassArgs a = base;
+      a.x = zX;
+      a.s_old = X;
+      a.s_new = Gb;
+      a.z_new = zG;
+      a.count_iter = 1;
+      a.respect_done = 0;
+      a.ctrl = op->ctrl;
+      s = pass(kStep64, a);
+      if (s != PSI_OK) return s;
+      ++fp64_passes;
+      s = check_waits(op, st);  // copies both control blocks to the host
+      if (s != PSI_OK) return s;
+      if (h->done) {
+        status = h->status;
+        break;
+      }
+      if (fp64_passes >= prm->max_iter) {
+        status = PSI_ENOTCONV;
+        break;
+      }
+      if (!(h->gap < 0.25 * prev_gap)) {
+        // refinement no longer gains: accelerated FP64 iterations from Gb
+        hipLaunchKernelGGL(k_aa_start, dim3(grid_for(n)), dim3(kBlock), 0, st, Gb, op->c,
+                           op->invden, n, X, zX);
+        hipLaunchKernelGGL(k_aa_ctrl, dim3(1), dim3(1), 0, st, op->ctrl, prm->tol, prm->tol_mode,
+                           prm->max_iter - fp64_passes, op->stats.b_norm);
+        PSI_HIP_CHECK(hipGetLastError());
+        s = accelerate(false, 0, prm->max_iter - fp64_passes, &status);
+        if (s != PSI_OK) return s;
+        fp64_passes += h->iter;
+        break;
+      }
+      prev_gap = h->gap;
+      s = mixed_inner_begin(op, Gb, X, eta, prm->max_iter, st);
+      if (s != PSI_OK) return s;
+      int inner_status = PSI_OK;
+      s = accelerate(true, 1, prm->max_iter, &inner_status);
+      if (s != PSI_OK) return s;
+      inf.fp32_passes += op->host_ctrl[1].iter;
+      if (inner_status == PSI_ENUMERIC) {
+        status = PSI_ENUMERIC;
+        break;
+      }
+      // e = g of the correction's last pass
+      s = mixed_update(op, X, op->e_b, zX, st);
+      if (s != PSI_OK) return s;
+      inf.refinements += 1;
     }
-    if (enq >= prm->max_iter) {
-      status = PSI_ENOTCONV;
-      break;
-    }
-    if (h->gap < best * (1.0 - 1e-3)) {
-      best = h->gap;
-      best_iter = h->iter;
-    } else if (h->iter - best_iter >= 25) {
-      status = PSI_ESTAGNATED;
-      break;
-    }
-    if (prm->check_every == 0) k = std::min(2 * k, 16);
+    inf.iterations = fp64_passes;
   }
-  // ψ = (Bᵀs + d)/N from s = g of the last pass (the last line of Algorithm 2)
+  // ψ = (Bᵀs + d)/N from s = g of the last FP64 pass (the last line of Algorithm 2)
   {
     PassArgs a = base;
-    a.x = zG;
+    a.x = z_fin;
     a.s_new = psi_out;
     a.count_iter = 0;
     a.respect_done = 0;
     s = pass(kFinal64, a);
     if (s != PSI_OK) return s;
   }
-  if (s_out) PSI_HIP_CHECK(hipMemcpyAsync(s_out, Gb, 8 * size_t(n), hipMemcpyDeviceToDevice, st));
-  AaState hs{};
-  PSI_HIP_CHECK(hipMemcpyAsync(&hs, w.st, sizeof(AaState), hipMemcpyDeviceToHost, st));
+  if (s_out) PSI_HIP_CHECK(hipMemcpyAsync(s_out, s_fin, 8 * size_t(n), hipMemcpyDeviceToDevice, st));
   PSI_HIP_CHECK(hipEventRecord(ev1, st));
   PSI_HIP_CHECK(hipEventSynchronize(ev1));
   float ms = 0.f;
   PSI_HIP_CHECK(hipEventElapsedTime(&ms, ev0, ev1));
   s = check_waits(op, st);
   if (s != PSI_OK) return s;
-  psi_info inf{};
+  const Ctrl* h = op->host_ctrl;
   inf.status = status;
-  inf.iterations = h->iter;
-  inf.spmv_passes = h->iter + 1;
-  inf.refinements = hs.restarts;  // window restarts
+  inf.spmv_passes = inf.iterations + inf.fp32_passes + 1;
   inf.used_s0 = s0 ? 1 : 0;
   inf.col_segments = S;
   inf.tile_items = tile;

@@ -602,6 +602,14 @@ psi_status launch_pass_bins(psi_operator* op, PassMode mode, const PassArgs& a, 
 // layouts its passes need; requested_S is the caller's col_segments.
 psi_status resolve_form(const psi_operator* op, int requested, int requested_S, int precision,
                         int S, int bytes, int* form);
+// Start of an FP32 correction solve of mixed precision from the FP64 step
+// X → Y: r = Y − X rounded to FP32, e_0 = r (e_a, ze_a = e_0/den), and the
+// inner control block (ctrl + 1) from the outer one's residual.
+psi_status mixed_inner_begin(psi_operator* op, const double* Y, const double* X, double eta,
+                             int max_iter, hipStream_t stream);
+// X ← X + e and zX = X/den after a correction solve.
+psi_status mixed_update(psi_operator* op, double* X, const float* e, double* zX,
+                        hipStream_t stream);
 psi_status prepare(psi_operator* op, int tile, int S, int form, hipStream_t stream);
 // The same with the band layout's parameters (0: those built, else defaults).
 psi_status prepare(psi_operator* op, int tile, int S, int form, hipStream_t stream, int wlog,

@@ -235,6 +235,24 @@ psi_status iterate(psi_operator* op, int S, int ctrl_idx, PassMode mode, Make ma
 
 }  // namespace
 
+psi_status mixed_inner_begin(psi_operator* op, const double* Y, const double* X, double eta,
+                             int max_iter, hipStream_t st) {
+  const int64_t n = op->n;
+  hipLaunchKernelGGL(k_prep_inner, dim3(grid_for(n)), dim3(kBlock), 0, st, Y, X, op->invden32, n,
+                     op->r32, op->e_a, op->ze_a);
+  hipLaunchKernelGGL(k_ctrl_inner, dim3(1), dim3(1), 0, st, op->ctrl, op->ctrl + 1, eta,
+                     max_iter);
+  PSI_HIP_CHECK(hipGetLastError());
+  return PSI_OK;
+}
+
+psi_status mixed_update(psi_operator* op, double* X, const float* e, double* zX, hipStream_t st) {
+  const int64_t n = op->n;
+  hipLaunchKernelGGL(k_update, dim3(grid_for(n)), dim3(kBlock), 0, st, X, e, op->invden, n, zX);
+  PSI_HIP_CHECK(hipGetLastError());
+  return PSI_OK;
+}
+
 psi_status check_waits(psi_operator* op, hipStream_t st) {
   Ctrl* h = op->host_ctrl;
   PSI_HIP_CHECK(hipMemcpyAsync(h, op->ctrl, 2 * sizeof(Ctrl), hipMemcpyDeviceToHost, st));
@@ -626,10 +644,8 @@ psi_status solve(psi_operator* op, const psi_params* prm, const double* s0, doub
       }
       prev_gap = h->gap;
       // FP32 correction solve e = Aᵀe + r
-      hipLaunchKernelGGL(k_prep_inner, dim3(grid_for(n)), dim3(kBlock), 0, st, Y, X,
-                         op->invden32, n, op->r32, op->e_a, op->ze_a);
-      hipLaunchKernelGGL(k_ctrl_inner, dim3(1), dim3(1), 0, st, op->ctrl, op->ctrl + 1, eta,
-                         prm->max_iter);
+      s = mixed_inner_begin(op, Y, X, eta, prm->max_iter, st);
+      if (s != PSI_OK) return s;
       auto make = [&](int i) {
         PassArgs b = base;
         const bool even = (i & 1) == 0;
@@ -652,8 +668,8 @@ psi_status solve(psi_operator* op, const psi_params* prm, const double* s0, doub
         break;
       }
       const float* e_fin = (res.iters & 1) ? op->e_b : op->e_a;
-      hipLaunchKernelGGL(k_update, dim3(grid_for(n)), dim3(kBlock), 0, st, X, e_fin, op->invden,
-                         n, zX);
+      s = mixed_update(op, X, e_fin, zX, st);
+      if (s != PSI_OK) return s;
       inf.refinements += 1;
       if (fp64_passes >= prm->max_iter) {
         status = PSI_ENOTCONV;

@@ -695,12 +695,41 @@ def test_anderson_matches_oracle_in_fewer_passes(gpu_lib, n, deg, gamma, sigma, 
     assert oracle.rel_l1(r["psi"], psi2.cpu().numpy()) <= 1e-9
 
 
+@pytest.mark.parametrize("seg_form", [0, "bins"])
+def test_anderson_mixed_matches_oracle_in_fewer_passes(gpu_lib, seg_form):
+    """Accelerated FP32 corrections between FP64 residual passes: the oracle's
+    ψ at the same tolerance, s a Power-ψ step of size <= tol, and fewer passes
+    than the plain mixed refinement."""
+    api = gpu_lib
+    tol = 1e-9
+    g = synth.chung_lu(300_000, 20, 2.1, 15, sigma=2.0)
+    A, B, c, d = oracle.operator(g.n, g.follower, g.leader, g.lam, g.mu)
+    r = oracle.power_psi(A, B, c, d, tol)
+    op = api.Operator(g.n, g.follower, g.leader, g.lam, g.mu)
+    psi, s, info = op.solve_anderson(tol=tol, depth=4, precision="mixed", seg_form=seg_form,
+                                     return_s=True)
+    assert info["status"] == 0, info
+    assert info["refinements"] >= 1 and info["fp32_passes"] > 0, info
+    got = psi.cpu().numpy()
+    assert oracle.rel_l1(r["psi"], got) <= 1e-9
+    assert oracle.max_rel(r["psi"], got) <= 1e-6
+    res = oracle.fixed_point_residual(A, c, s.cpu().numpy())
+    assert res <= 1.5 * tol + 1e-15 * np.abs(r["s"]).sum(), res
+    _, plain = op.solve(tol=tol, precision="mixed", seg_form=seg_form)
+    assert info["spmv_passes"] < plain["spmv_passes"], (info["spmv_passes"],
+                                                        plain["spmv_passes"])
+    again, _ = op.solve_anderson(tol=tol, depth=4, precision="mixed", seg_form=seg_form)
+    assert torch.equal(again, psi)
+
+
 def test_anderson_invalid(gpu_lib):
     api = gpu_lib
     g = synth.chung_lu(2000, 5, 2.2, 92)
     op = api.Operator(g.n, g.follower, g.leader, g.lam, g.mu)
     with pytest.raises(api.PsiError, match="depth"):
         op.solve_anderson(depth=9)
+    with pytest.raises(api.PsiError, match="PSI_PREC_FP64 or PSI_PREC_MIXED"):
+        op.solve_anderson(precision="fp32")
     psi, info = op.solve_anderson(tol=1e-14, max_iter=3)
     assert info["status_name"] == "PSI_ENOTCONV" and info["iterations"] == 3
 

@@ -5,7 +5,8 @@ Each case draws a graph (Erdős–Rényi-style with users who follow nobody,
 repeated edges and self-loops in the input, or a small Chung–Lu graph with
 hubs) and checks the plain solve in both pass forms and segment counts, the
 band and binned layouts (FP64 and mixed precision), the mixed-precision
-solve, Anderson acceleration, and the scenario batch in both precisions,
+solve, Anderson acceleration (FP64 and mixed precision), and the scenario
+batch in both precisions,
 each within 1e-9 relative L1 of the oracle at the same tolerance.
 """
 import numpy as np
@@ -60,6 +61,9 @@ def test_all_modes_match_the_oracle(gpu_lib, seed):
             check(psi, info, f"{prec} {form}", exact_iters=prec == "fp64")
     psi, info = op.solve_anderson(tol=TOL, depth=1 + seed % 4)
     check(psi, info, "anderson")
+    psi, info = op.solve_anderson(tol=TOL, depth=1 + seed % 4, precision="mixed",
+                                  seg_form=("bins", 0)[seed % 2])
+    check(psi, info, "mixed anderson")
 
     # three scenarios: the operator's own activity and two more draws
     k = 3
