@@ -452,12 +452,13 @@ class Operator:
     def solve_anderson_noalloc(self, tol: float = 1e-8, depth: int = 4, tol_mode: str = "abs_l1",
                                max_iter: int = 10000, s0: torch.Tensor | None = None,
                                check_every: int = 0, tile_items: int = 0, col_segments: int = 0,
-                               seg_form: str | int = 0, return_s: bool = False, stream=None,
+                               seg_form: str | int = 0, precision: str = "fp64",
+                               inner_tol: float = 0.0, return_s: bool = False, stream=None,
                                raise_on_status: bool = False):
         """psi_solve_anderson_noalloc: psi_solve_anderson with its scratch in the
         library's fixed device array (no workspace, no device allocation)."""
-        p = self._params(tol, tol_mode, max_iter, "fp64", check_every, tile_items, col_segments,
-                         seg_form=seg_form)
+        p = self._params(tol, tol_mode, max_iter, precision, check_every, tile_items,
+                         col_segments, inner_tol=inner_tol, seg_form=seg_form)
         psi = torch.empty(self.n, dtype=torch.float64, device=self.device)
         s = torch.empty(self.n, dtype=torch.float64, device=self.device) if return_s else None
         if s0 is not None:

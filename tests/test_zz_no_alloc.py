@@ -1,8 +1,9 @@
 """The entry point for callers that cannot allocate device memory
 (psi_solve_anderson_noalloc, through the C ABI) against the workspace entry
 point it mirrors (psi_solve_anderson): the same kernels on the same inputs,
-so the same bits; two calls in a row, the second on a smaller graph (the
-fixed scratch keeps the first call's contents), and the size limit."""
+so the same bits, in FP64 and in mixed precision; two calls in a row, the
+second on a smaller graph (the fixed scratch keeps the first call's
+contents), and the size limit."""
 import numpy as np
 import pytest
 import torch
@@ -26,6 +27,14 @@ def test_no_alloc_anderson_equals_the_workspace_entry_point(gpu_lib):
         A, B, c, d = oracle.operator(g.n, g.follower, g.leader, g.lam, g.mu)
         r = oracle.power_psi(A, B, c, d, 1e-10)
         assert oracle.rel_l1(r["psi"], psi_na.cpu().numpy()) <= 1e-9
+        # mixed precision: the FP32 window in the same scratch, after the FP64 call
+        psi_wm, info_wm = op.solve_anderson(tol=1e-10, depth=4, precision="mixed")
+        psi_nm, info_nm = op.solve_anderson_noalloc(tol=1e-10, depth=4, precision="mixed")
+        assert info_nm["status"] == 0, info_nm
+        assert torch.equal(psi_nm, psi_wm)
+        assert (info_nm["iterations"], info_nm["fp32_passes"]) == (info_wm["iterations"],
+                                                                   info_wm["fp32_passes"])
+        assert oracle.rel_l1(r["psi"], psi_nm.cpu().numpy()) <= 1e-9
 
 
 def test_no_alloc_anderson_refuses_more_than_its_scratch(gpu_lib):
